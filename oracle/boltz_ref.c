@@ -1,0 +1,853 @@
+/*
+ * boltz_ref.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see the
+ * header).  Every loop below follows the paper's statement of the method in
+ * the order the paper gives it; nothing is blocked, fused or reordered.
+ *
+ * Sections of the paper followed here:
+ *   Sec. 2  Eqs. definition, MaxwellDist, devIntColl   deviational form
+ *   Sec. 2  Eqs. densita..sforzi                       moments (re-derived in V0 units)
+ *   Sec. 2  Eq. bcMax and the zero-net-flux condition  diffuse walls
+ *   Sec. 3  Eq. streaming2D                            first-order upwind streaming
+ *   Sec. 3  Eqs. coll8Dim, monteCarloInt               MC collision integral
+ *   Sec. 3  Eq. collision_step                         explicit (Jacobi) update
+ *   Sec. 3  Eqs. rinorm_a, correzione                  conservation correction
+ *   Sec. 5.1                                           units, driven cavity, CFL
+ * The readings taken where the paper is silent or garbled are listed in the
+ * repository's design notes; the ones that shape a formula are repeated at
+ * the formula.
+ */
+#include "boltz_ref.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define INV_SQRT_PI 0.56418958354775628694807945156077
+#define PI_OVER_4 0.78539816339744830961566084581988
+#define TWO_PI 6.28318530717958647692528676655901
+
+enum { WALL_LEFT = 0, WALL_RIGHT = 1, WALL_BOTTOM = 2, WALL_TOP = 3 };
+
+struct boltz_ref_ctx {
+  boltz_ref_problem p;
+  int n[3];
+  double a[3];
+  int nv, ncells;
+  double dvel[3];
+  double inv_cell[3]; /* n / (2 a): maps x + a to a cell coordinate */
+  double* v[3];
+  double* om[3];
+  double Om[3];
+  uint64_t* T[3]; /* T[k][i] = T_i for i in [1, n); T[k][0] = 0 */
+  double dx, dy, dt, K, W, qfac;
+  char err[256];
+};
+
+static char g_create_err[256];
+
+static void set_err(char* buf, const char* msg) {
+  strncpy(buf, msg, 255);
+  buf[255] = 0;
+}
+
+void boltz_ref_set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+int boltz_ref_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+const char* boltz_ref_last_error(const boltz_ref_ctx* ctx) {
+  return ctx ? ctx->err : g_create_err;
+}
+
+/* ---------------------------------------------------------------- setup -- */
+
+void boltz_ref_destroy(boltz_ref_ctx* c) {
+  if (!c) return;
+  for (int k = 0; k < 3; ++k) {
+    free(c->v[k]);
+    free(c->om[k]);
+    free(c->T[k]);
+  }
+  free(c);
+}
+
+int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
+  if (!p || !out) {
+    set_err(g_create_err, "null argument");
+    return BOLTZ_REF_EINVAL;
+  }
+  *out = NULL;
+  int min_cells = (p->bc == BOLTZ_REF_BC_CAVITY) ? 2 : 1;
+  if (p->nx < min_cells || p->ny < min_cells || p->nx > 100000 || p->ny > 100000) {
+    set_err(g_create_err, "nx, ny out of range (cavity needs >= 2)");
+    return BOLTZ_REF_EINVAL;
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (p->nv[k] < 1 || p->nv[k] > 255 || !(p->vmax[k] > 0.0)) {
+      set_err(g_create_err, "velocity grid out of range (1 <= nv <= 255, vmax > 0)");
+      return BOLTZ_REF_EINVAL;
+    }
+  }
+  if (!(p->delta > 0.0) || !(p->eps > 0.0) || (p->order != 1 && p->order != 2) ||
+      (p->bc != BOLTZ_REF_BC_CAVITY && p->bc != BOLTZ_REF_BC_PERIODIC) || p->n_pairs < 0 ||
+      p->n_pairs >= (int64_t)1 << 31 || p->sample_group < 0 ||
+      (!(p->dt > 0.0) && !(p->cfl > 0.0))) {
+    set_err(g_create_err, "invalid scalar parameter");
+    return BOLTZ_REF_EINVAL;
+  }
+  boltz_ref_ctx* c = (boltz_ref_ctx*)calloc(1, sizeof(*c));
+  if (!c) {
+    set_err(g_create_err, "out of memory");
+    return BOLTZ_REF_ENOMEM;
+  }
+  c->p = *p;
+  c->nv = 1;
+  for (int k = 0; k < 3; ++k) {
+    int n = p->nv[k];
+    double a = p->vmax[k];
+    c->n[k] = n;
+    c->a[k] = a;
+    c->nv *= n;
+    c->v[k] = (double*)malloc(sizeof(double) * n);
+    c->om[k] = (double*)malloc(sizeof(double) * n);
+    c->T[k] = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    if (!c->v[k] || !c->om[k] || !c->T[k]) {
+      boltz_ref_destroy(c);
+      set_err(g_create_err, "out of memory");
+      return BOLTZ_REF_ENOMEM;
+    }
+    /* Sec. 3: h is constant in each velocity cell with the node at the cell
+     * centre; uniform cells on [-a, a].  The node formula is exactly
+     * antisymmetric in floating point. */
+    c->dvel[k] = (2.0 * a) / n;
+    c->inv_cell[k] = (double)n / (2.0 * a);
+    double om_sum = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double vi = ((double)(2 * i + 1 - n) * a) / n;
+      c->v[k][i] = vi;
+      /* per-axis midpoint weight of Phi0: omega = dv exp(-v^2)/sqrt(pi) */
+      c->om[k][i] = (c->dvel[k] * exp(-(vi * vi))) * INV_SQRT_PI;
+      om_sum += c->om[k][i];
+    }
+    c->Om[k] = om_sum;
+    /* cumulative thresholds of the per-axis node law (quantised to 2^-32) */
+    double s = 0.0;
+    c->T[k][0] = 0;
+    for (int i = 0; i < n; ++i) {
+      if (i > 0) c->T[k][i] = (uint64_t)nearbyint(ldexp(s / om_sum, 32));
+      s += c->om[k][i];
+    }
+  }
+  c->ncells = p->nx * p->ny;
+  c->dx = 1.0 / p->nx;
+  c->dy = 1.0 / p->ny;
+  double vmx = fabs(c->v[0][0]), vmy = fabs(c->v[1][0]);
+  if (p->dt > 0.0) {
+    c->dt = p->dt;
+  } else {
+    /* Sec. 5.1: the largest Courant number over nodes and axes equals cfl */
+    double rx = vmx / c->dx, ry = vmy / c->dy;
+    c->dt = p->cfl / (rx > ry ? rx : ry);
+  }
+  double cx = vmx * c->dt / c->dx, cy = vmy * c->dt / c->dy;
+  int stable = (p->order == 1) ? (cx + cy <= 1.0 + 1e-12) : (cx <= 1.0 + 1e-12 && cy <= 1.0 + 1e-12);
+  if (!stable && !(p->flags & BOLTZ_REF_ALLOW_UNSTABLE)) {
+    boltz_ref_destroy(c);
+    set_err(g_create_err, "time step violates the Courant limit of the streaming scheme");
+    return BOLTZ_REF_EINVAL;
+  }
+  /* Collision constant K = pi n0 sigma^2 from lambda0 = mu0/p0 sqrt(2 R T0)
+   * with the hard-sphere viscosity (Chapman-Cowling, 1.016034 correction):
+   * K = (5/16) sqrt(2 pi) 1.016034 delta. */
+  c->K = 0.3125 * sqrt(TWO_PI) * 1.016034 * p->delta;
+  c->W = (c->Om[0] * c->Om[1]) * c->Om[2];
+  c->qfac = (p->n_pairs > 0) ? (((c->dt * c->K) * c->W) * c->W) / (double)p->n_pairs : 0.0;
+  *out = c;
+  return BOLTZ_REF_OK;
+}
+
+int boltz_ref_info(const boltz_ref_ctx* c, double* out) {
+  if (!c || !out) return BOLTZ_REF_EINVAL;
+  out[BOLTZ_REF_INFO_DT] = c->dt;
+  out[BOLTZ_REF_INFO_K] = c->K;
+  out[BOLTZ_REF_INFO_W] = c->W;
+  out[BOLTZ_REF_INFO_QFAC] = c->qfac;
+  out[BOLTZ_REF_INFO_DX] = c->dx;
+  out[BOLTZ_REF_INFO_DY] = c->dy;
+  out[BOLTZ_REF_INFO_NCELLS] = c->ncells;
+  out[BOLTZ_REF_INFO_NV] = c->nv;
+  return BOLTZ_REF_OK;
+}
+
+int boltz_ref_axis(const boltz_ref_ctx* c, int axis, double* v, double* omega, uint64_t* thr) {
+  if (!c || axis < 0 || axis > 2) return BOLTZ_REF_EINVAL;
+  for (int i = 0; i < c->n[axis]; ++i) {
+    if (v) v[i] = c->v[axis][i];
+    if (omega) omega[i] = c->om[axis][i];
+    if (thr && i > 0) thr[i - 1] = c->T[axis][i];
+  }
+  return BOLTZ_REF_OK;
+}
+
+/* -------------------------------------------------------- node helpers -- */
+
+static void node_idx(const boltz_ref_ctx* c, int j, int* jx, int* jy, int* jz) {
+  *jz = j % c->n[2];
+  *jy = (j / c->n[2]) % c->n[1];
+  *jx = j / (c->n[2] * c->n[1]);
+}
+
+static int node_of(const boltz_ref_ctx* c, int jx, int jy, int jz) {
+  return (jx * c->n[1] + jy) * c->n[2] + jz;
+}
+
+static double node_w(const boltz_ref_ctx* c, int jx, int jy, int jz) {
+  return (c->om[0][jx] * c->om[1][jy]) * c->om[2][jz];
+}
+
+/* ------------------------------------------------------------- Philox -- */
+
+/* Philox4x32-10 as published by Salmon, Moraes, Dror and Shaw (SC'11):
+ * ten rounds of two 32x32->64 multiplies with a Weyl-sequence key schedule. */
+void boltz_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+/* ------------------------------------------------------- direction map -- */
+
+/* cos and sin of 2 pi u for u in (0, 1): reduce to an octant exactly
+ * (8u is exact for u = (r + 1/2) 2^-32), fold to [0, pi/4], then Taylor
+ * polynomials in z^2 (truncation below 1e-18 on [0, pi/4]). */
+void boltz_ref_cos_sin_2pi(double u, double* cs, double* sn) {
+  double t = u * 8.0;
+  double o = floor(t);
+  double f = t - o;
+  int oct = ((int)o) & 7;
+  double z = ((oct & 1) ? (1.0 - f) : f) * PI_OVER_4;
+  double z2 = z * z;
+  double ps = 1.0 / 355687428096000.0;
+  ps = -1.0 / 1307674368000.0 + z2 * ps;
+  ps = 1.0 / 6227020800.0 + z2 * ps;
+  ps = -1.0 / 39916800.0 + z2 * ps;
+  ps = 1.0 / 362880.0 + z2 * ps;
+  ps = -1.0 / 5040.0 + z2 * ps;
+  ps = 1.0 / 120.0 + z2 * ps;
+  ps = -1.0 / 6.0 + z2 * ps;
+  ps = 1.0 + z2 * ps;
+  double S = z * ps;
+  double pc = 1.0 / 20922789888000.0;
+  pc = -1.0 / 87178291200.0 + z2 * pc;
+  pc = 1.0 / 479001600.0 + z2 * pc;
+  pc = -1.0 / 3628800.0 + z2 * pc;
+  pc = 1.0 / 40320.0 + z2 * pc;
+  pc = -1.0 / 720.0 + z2 * pc;
+  pc = 1.0 / 24.0 + z2 * pc;
+  pc = -1.0 / 2.0 + z2 * pc;
+  double C = 1.0 + z2 * pc;
+  switch (oct) {
+    case 0: *cs = C; *sn = S; break;
+    case 1: *cs = S; *sn = C; break;
+    case 2: *cs = -S; *sn = C; break;
+    case 3: *cs = -C; *sn = S; break;
+    case 4: *cs = -C; *sn = -S; break;
+    case 5: *cs = -S; *sn = -C; break;
+    case 6: *cs = S; *sn = -C; break;
+    default: *cs = C; *sn = -S; break;
+  }
+}
+
+/* --------------------------------------------------------- pair sample -- */
+
+typedef struct {
+  int kept;
+  int a, b, as, bs;
+  double q;
+  uint32_t r[8];
+  double vel[12]; /* v_a, v_b, v*, v1* (continuous) */
+} pair_t;
+
+/* Inverse CDF of the per-axis node law: the number of thresholds <= r. */
+static int axis_draw(const boltz_ref_ctx* c, int k, uint32_t r) {
+  int idx = 0;
+  for (int i = 1; i < c->n[k]; ++i)
+    if ((uint64_t)r >= c->T[k][i]) idx++;
+  return idx;
+}
+
+int boltz_ref_axis_draw(const boltz_ref_ctx* c, int axis, uint32_t r) {
+  if (!c || axis < 0 || axis > 2) return -1;
+  return axis_draw(c, axis, r);
+}
+
+/* Cell of a velocity component, or -1 outside the box. */
+static int axis_cell(const boltz_ref_ctx* c, int k, double x) {
+  double t = floor((x + c->a[k]) * c->inv_cell[k]);
+  if (!(t >= 0.0 && t < (double)c->n[k])) return -1;
+  return (int)t;
+}
+
+/* One Monte Carlo collision sample (Sec. 3, Eqs. coll8Dim / monteCarloInt):
+ * pre-collision nodes a, b drawn from the discrete Maxwellian weights, a
+ * direction k uniform on the unit sphere, post-collision velocities
+ * v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a (the sign
+ * of the sampling-kernel listing; it conserves energy), and the weight
+ * q = dt K W^2 |v_r.k| / N_t.  Pairs whose post-collision velocity leaves the
+ * box are discarded (they still count in N_t). */
+static void sample_pair(const boltz_ref_ctx* c, uint32_t group, uint32_t step, uint32_t m,
+                        pair_t* out) {
+  const uint32_t key[2] = {(uint32_t)c->p.seed, (uint32_t)(c->p.seed >> 32)};
+  const uint32_t c0[4] = {2u * m, group, step, c->p.cavity_id};
+  const uint32_t c1[4] = {2u * m + 1u, group, step, c->p.cavity_id};
+  uint32_t* r = out->r;
+  boltz_ref_philox4x32_10(c0, key, r);
+  boltz_ref_philox4x32_10(c1, key, r + 4);
+  int iax = axis_draw(c, 0, r[0]), iay = axis_draw(c, 1, r[1]), iaz = axis_draw(c, 2, r[2]);
+  int ibx = axis_draw(c, 0, r[3]), iby = axis_draw(c, 1, r[4]), ibz = axis_draw(c, 2, r[5]);
+  double u6 = ((double)r[6] + 0.5) * 0x1p-32;
+  double u7 = ((double)r[7] + 0.5) * 0x1p-32;
+  double kz = 2.0 * u6 - 1.0;
+  double s = sqrt((1.0 - kz) * (1.0 + kz));
+  double cp, sp;
+  boltz_ref_cos_sin_2pi(u7, &cp, &sp);
+  double kx = s * cp, ky = s * sp;
+  double vax = c->v[0][iax], vay = c->v[1][iay], vaz = c->v[2][iaz];
+  double vbx = c->v[0][ibx], vby = c->v[1][iby], vbz = c->v[2][ibz];
+  double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
+  double alpha = (vrx * kx + vry * ky) + vrz * kz;
+  double ddx = alpha * kx, ddy = alpha * ky, ddz = alpha * kz;
+  int sx = axis_cell(c, 0, vax + ddx), sy = axis_cell(c, 1, vay + ddy), sz = axis_cell(c, 2, vaz + ddz);
+  int tx = axis_cell(c, 0, vbx - ddx), ty = axis_cell(c, 1, vby - ddy), tz = axis_cell(c, 2, vbz - ddz);
+  out->a = node_of(c, iax, iay, iaz);
+  out->b = node_of(c, ibx, iby, ibz);
+  const double vel[12] = {vax, vay, vaz, vbx, vby, vbz, vax + ddx, vay + ddy, vaz + ddz,
+                          vbx - ddx, vby - ddy, vbz - ddz};
+  memcpy(out->vel, vel, sizeof(vel));
+  out->kept = (sx >= 0 && sy >= 0 && sz >= 0 && tx >= 0 && ty >= 0 && tz >= 0);
+  if (out->kept) {
+    out->as = node_of(c, sx, sy, sz);
+    out->bs = node_of(c, tx, ty, tz);
+    out->q = c->qfac * fabs(alpha);
+  } else {
+    out->as = -1;
+    out->bs = -1;
+    out->q = 0.0;
+  }
+}
+
+static uint32_t group_of(const boltz_ref_ctx* c, int64_t cell) {
+  return (c->p.sample_group == 0) ? 0u : (uint32_t)(cell / c->p.sample_group);
+}
+
+int boltz_ref_debug_pairs(const boltz_ref_ctx* c, int64_t cell, int64_t step, int64_t m0,
+                          int64_t count, int32_t* idx4, double* q, uint32_t* words, double* vel) {
+  if (!c || cell < 0 || cell >= c->ncells || m0 < 0 || count < 0 ||
+      m0 + count > ((int64_t)1 << 31) || !idx4 || !q)
+    return BOLTZ_REF_EINVAL;
+  uint32_t g = group_of(c, cell);
+  for (int64_t i = 0; i < count; ++i) {
+    pair_t pr;
+    sample_pair(c, g, (uint32_t)step, (uint32_t)(m0 + i), &pr);
+    idx4[4 * i + 0] = pr.a;
+    idx4[4 * i + 1] = pr.b;
+    idx4[4 * i + 2] = pr.as;
+    idx4[4 * i + 3] = pr.bs;
+    q[i] = pr.q;
+    if (words) memcpy(words + 8 * i, pr.r, 8 * sizeof(uint32_t));
+    if (vel) memcpy(vel + 12 * i, pr.vel, 12 * sizeof(double));
+  }
+  return BOLTZ_REF_OK;
+}
+
+/* --------------------------------------------------------------- walls -- */
+
+static double wall_tau(const boltz_ref_walls* w, int wall) {
+  switch (wall) {
+    case WALL_LEFT: return w->tau_left;
+    case WALL_RIGHT: return w->tau_right;
+    case WALL_BOTTOM: return w->tau_bottom;
+    default: return w->tau_top;
+  }
+}
+
+/* Phi_w(v) / Phi0(v) for a wall Maxwellian of velocity (U, 0, 0) and
+ * temperature ratio tau (Eq. bcMax with the wall Maxwellian). */
+static double wall_ratio(double vx, double vy, double vz, double U, double tau) {
+  double v2 = (vx * vx + vy * vy) + vz * vz;
+  double ux = vx - U;
+  double c2 = (ux * ux + vy * vy) + vz * vz;
+  return pow(tau, -1.5) * exp(v2 - c2 / tau);
+}
+
+/* Wall density n_w of one boundary face from the zero-net-mass-flux
+ * condition of Sec. 2, written with discrete sums over the velocity nodes so
+ * that the streaming step passes zero net mass through the face:
+ *   n_w = sum_{out} |v_n| w_j (1 + eps hhat_j) / sum_{in} |v_n| w_j R_j,
+ * R = Phi_w / Phi0.  hhat is the scheme's own gas-side face value (adjacent
+ * cell for order 1; the Beam-Warming face value h_a + (1-C)(h_a - h_a')/2 for
+ * order 2).  The incoming sum runs over the mirror images of the outgoing
+ * nodes in the same order, so a wall at rest facing h = 0 gives n_w = 1
+ * exactly. */
+static double face_density(const boltz_ref_ctx* c, const double* src, int wall, int pos,
+                           const boltz_ref_walls* walls, int order) {
+  const int nx = c->p.nx, ny = c->p.ny;
+  int nax = (wall == WALL_LEFT || wall == WALL_RIGHT) ? 0 : 1;
+  int sgn = (wall == WALL_LEFT || wall == WALL_BOTTOM) ? 1 : -1;
+  int ca, cb;
+  switch (wall) {
+    case WALL_LEFT: ca = pos * nx + 0; cb = pos * nx + 1; break;
+    case WALL_RIGHT: ca = pos * nx + nx - 1; cb = pos * nx + nx - 2; break;
+    case WALL_BOTTOM: ca = 0 * nx + pos; cb = 1 * nx + pos; break;
+    default: ca = (ny - 1) * nx + pos; cb = (ny - 2) * nx + pos; break;
+  }
+  double dl = (nax == 0) ? c->dx : c->dy;
+  double U = (wall == WALL_TOP) ? walls->lid_u : 0.0;
+  double tau = wall_tau(walls, wall);
+  double phi_out = 0.0, dens = 0.0;
+  for (int j = 0; j < c->nv; ++j) {
+    int jx, jy, jz;
+    node_idx(c, j, &jx, &jy, &jz);
+    double vn = (nax == 0) ? c->v[0][jx] : c->v[1][jy];
+    if (!(sgn * vn < 0.0)) continue; /* outgoing nodes only */
+    double an = fabs(vn);
+    double hh = src[(size_t)ca * c->nv + j];
+    if (order == 2) {
+      double C = an * c->dt / dl;
+      hh = hh + 0.5 * (1.0 - C) * (hh - src[(size_t)cb * c->nv + j]);
+    }
+    double w = node_w(c, jx, jy, jz);
+    phi_out += (an * w) * (1.0 + c->p.eps * hh);
+    int mx = jx, my = jy;
+    if (nax == 0) mx = c->n[0] - 1 - jx; else my = c->n[1] - 1 - jy;
+    double R = wall_ratio(c->v[0][mx], c->v[1][my], c->v[2][jz], U, tau);
+    dens += (an * node_w(c, mx, my, jz)) * R;
+  }
+  return phi_out / dens;
+}
+
+/* Re-emitted deviation h_w = (n_w Phi_w/Phi0 - 1)/eps (Eq. bcMax). */
+static double ghost_value(const boltz_ref_ctx* c, int wall, double nw, int j,
+                          const boltz_ref_walls* walls) {
+  int jx, jy, jz;
+  node_idx(c, j, &jx, &jy, &jz);
+  double U = (wall == WALL_TOP) ? walls->lid_u : 0.0;
+  double R = wall_ratio(c->v[0][jx], c->v[1][jy], c->v[2][jz], U, wall_tau(walls, wall));
+  return (nw * R - 1.0) / c->p.eps;
+}
+
+/* ----------------------------------------------------------- streaming -- */
+
+static int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+/* Beam-Warming update of one node along one axis (second-order upwind, flux
+ * form with face value h_i + (1-C)(h_i - h_{i-s})/2). */
+static double bw_update(double h0, double h1, double h2, double C) {
+  return h0 - C * (h0 - h1) - 0.5 * C * (1.0 - C) * ((h0 - 2.0 * h1) + h2);
+}
+
+/* x-sweep of order 2 over all rows: hx = BW_x(h), ghosts from the x walls. */
+static void sweep_x(const boltz_ref_ctx* c, const double* h, double* hx, const double* nw_left,
+                    const double* nw_right, const boltz_ref_walls* walls) {
+  const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
+  const int periodic = (c->p.bc == BOLTZ_REF_BC_PERIODIC);
+#pragma omp parallel for schedule(static)
+  for (int cell = 0; cell < nx * ny; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx];
+      double h0 = h[(size_t)cell * nv + j];
+      if (vx == 0.0) {
+        hx[(size_t)cell * nv + j] = h0;
+        continue;
+      }
+      int s = vx > 0.0 ? 1 : -1;
+      double C = fabs(vx) * c->dt / c->dx;
+      double hn[2];
+      for (int d = 1; d <= 2; ++d) {
+        int i = ix - d * s;
+        if (i >= 0 && i < nx) hn[d - 1] = h[((size_t)iy * nx + i) * nv + j];
+        else if (periodic) hn[d - 1] = h[((size_t)iy * nx + wrap(i, nx)) * nv + j];
+        else if (i < 0) hn[d - 1] = ghost_value(c, WALL_LEFT, nw_left[iy], j, walls);
+        else hn[d - 1] = ghost_value(c, WALL_RIGHT, nw_right[iy], j, walls);
+      }
+      hx[(size_t)cell * nv + j] = bw_update(h0, hn[0], hn[1], C);
+    }
+  }
+}
+
+/* y-sweep of order 2: hs = BW_y(hx), ghosts from the y walls. */
+static void sweep_y(const boltz_ref_ctx* c, const double* hx, double* hs, const double* nw_bottom,
+                    const double* nw_top, const boltz_ref_walls* walls) {
+  const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
+  const int periodic = (c->p.bc == BOLTZ_REF_BC_PERIODIC);
+#pragma omp parallel for schedule(static)
+  for (int cell = 0; cell < nx * ny; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vy = c->v[1][jy];
+      double h0 = hx[(size_t)cell * nv + j];
+      if (vy == 0.0) {
+        hs[(size_t)cell * nv + j] = h0;
+        continue;
+      }
+      int s = vy > 0.0 ? 1 : -1;
+      double C = fabs(vy) * c->dt / c->dy;
+      double hn[2];
+      for (int d = 1; d <= 2; ++d) {
+        int i = iy - d * s;
+        if (i >= 0 && i < ny) hn[d - 1] = hx[((size_t)i * nx + ix) * nv + j];
+        else if (periodic) hn[d - 1] = hx[((size_t)wrap(i, ny) * nx + ix) * nv + j];
+        else if (i < 0) hn[d - 1] = ghost_value(c, WALL_BOTTOM, nw_bottom[ix], j, walls);
+        else hn[d - 1] = ghost_value(c, WALL_TOP, nw_top[ix], j, walls);
+      }
+      hs[(size_t)cell * nv + j] = bw_update(h0, hn[0], hn[1], C);
+    }
+  }
+}
+
+/* First-order unsplit upwind step, Eq. streaming2D with the upwind side
+ * chosen by the sign of each velocity component. */
+static void stream_order1(const boltz_ref_ctx* c, const double* h, double* hs, const double* nw,
+                          const boltz_ref_walls* walls) {
+  const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
+  const int periodic = (c->p.bc == BOLTZ_REF_BC_PERIODIC);
+  const double* nwl = nw;
+  const double* nwr = nw + ny;
+  const double* nwb = nw + 2 * ny;
+  const double* nwt = nw + 2 * ny + nx;
+#pragma omp parallel for schedule(static)
+  for (int cell = 0; cell < nx * ny; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx], vy = c->v[1][jy];
+      double h0 = h[(size_t)cell * nv + j];
+      double Cx = fabs(vx) * c->dt / c->dx, Cy = fabs(vy) * c->dt / c->dy;
+      double hxn = h0, hyn = h0;
+      if (vx != 0.0) {
+        int i = ix - (vx > 0.0 ? 1 : -1);
+        if (i >= 0 && i < nx) hxn = h[((size_t)iy * nx + i) * nv + j];
+        else if (periodic) hxn = h[((size_t)iy * nx + wrap(i, nx)) * nv + j];
+        else if (i < 0) hxn = ghost_value(c, WALL_LEFT, nwl[iy], j, walls);
+        else hxn = ghost_value(c, WALL_RIGHT, nwr[iy], j, walls);
+      }
+      if (vy != 0.0) {
+        int i = iy - (vy > 0.0 ? 1 : -1);
+        if (i >= 0 && i < ny) hyn = h[((size_t)i * nx + ix) * nv + j];
+        else if (periodic) hyn = h[((size_t)wrap(i, ny) * nx + ix) * nv + j];
+        else if (i < 0) hyn = ghost_value(c, WALL_BOTTOM, nwb[ix], j, walls);
+        else hyn = ghost_value(c, WALL_TOP, nwt[ix], j, walls);
+      }
+      hs[(size_t)cell * nv + j] = ((1.0 - Cx) - Cy) * h0 + Cx * hxn + Cy * hyn;
+    }
+  }
+}
+
+/* n_w of every face exactly as the streaming step uses them; for order 2 the
+ * y-wall faces are computed from the x-swept state (passed as hx). */
+static void all_wall_densities(const boltz_ref_ctx* c, const double* h, const double* hx,
+                               const boltz_ref_walls* walls, double* nw, int which) {
+  const int nx = c->p.nx, ny = c->p.ny, order = c->p.order;
+  /* which: 1 = x walls, 2 = y walls, 3 = both */
+  if (which & 1)
+    for (int iy = 0; iy < ny; ++iy) {
+      nw[iy] = face_density(c, h, WALL_LEFT, iy, walls, order);
+      nw[ny + iy] = face_density(c, h, WALL_RIGHT, iy, walls, order);
+    }
+  if (which & 2) {
+    const double* src = (order == 2) ? hx : h;
+    for (int ix = 0; ix < nx; ++ix) {
+      nw[2 * ny + ix] = face_density(c, src, WALL_BOTTOM, ix, walls, order);
+      nw[2 * ny + nx + ix] = face_density(c, src, WALL_TOP, ix, walls, order);
+    }
+  }
+}
+
+int boltz_ref_wall_density(const boltz_ref_ctx* c, const double* h, const boltz_ref_walls* walls,
+                           double* nw) {
+  if (!c || !h || !walls || !nw || c->p.bc != BOLTZ_REF_BC_CAVITY) return BOLTZ_REF_EINVAL;
+  const int nx = c->p.nx, ny = c->p.ny;
+  all_wall_densities(c, h, NULL, walls, nw, 1);
+  if (c->p.order == 2) {
+    double* hx = (double*)malloc(sizeof(double) * (size_t)c->ncells * c->nv);
+    if (!hx) return BOLTZ_REF_ENOMEM;
+    sweep_x(c, h, hx, nw, nw + ny, walls);
+    all_wall_densities(c, h, hx, walls, nw, 2);
+    free(hx);
+  } else {
+    all_wall_densities(c, h, NULL, walls, nw, 2);
+  }
+  (void)nx;
+  return BOLTZ_REF_OK;
+}
+
+int boltz_ref_stream(const boltz_ref_ctx* c, const double* h_in, double* h_out,
+                     const boltz_ref_walls* walls) {
+  if (!c || !h_in || !h_out || h_in == h_out) return BOLTZ_REF_EINVAL;
+  const int cavity = (c->p.bc == BOLTZ_REF_BC_CAVITY);
+  if (cavity && !walls) return BOLTZ_REF_EINVAL;
+  const int nx = c->p.nx, ny = c->p.ny;
+  double* nw = (double*)calloc((size_t)2 * (nx + ny), sizeof(double));
+  if (!nw) return BOLTZ_REF_ENOMEM;
+  if (c->p.order == 1) {
+    if (cavity) all_wall_densities(c, h_in, NULL, walls, nw, 3);
+    stream_order1(c, h_in, h_out, nw, walls);
+  } else {
+    double* hx = (double*)malloc(sizeof(double) * (size_t)c->ncells * c->nv);
+    if (!hx) {
+      free(nw);
+      return BOLTZ_REF_ENOMEM;
+    }
+    if (cavity) all_wall_densities(c, h_in, NULL, walls, nw, 1);
+    sweep_x(c, h_in, hx, nw, nw + ny, walls);
+    if (cavity) all_wall_densities(c, h_in, hx, walls, nw, 2);
+    sweep_y(c, hx, h_out, nw + 2 * ny, nw + 2 * ny + nx, walls);
+    free(hx);
+  }
+  free(nw);
+  return BOLTZ_REF_OK;
+}
+
+/* ----------------------------------------------------------- collision -- */
+
+/* Cholesky solve of the 5x5 symmetric positive definite system M x = r. */
+static int solve5(double M[5][5], const double r[5], double x[5]) {
+  double L[5][5] = {{0}};
+  for (int i = 0; i < 5; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double s = M[i][j];
+      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+      if (i == j) {
+        if (!(s > 0.0)) return -1;
+        L[i][i] = sqrt(s);
+      } else {
+        L[i][j] = s / L[j][j];
+      }
+    }
+  }
+  double y[5];
+  for (int i = 0; i < 5; ++i) {
+    double s = r[i];
+    for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+    y[i] = s / L[i][i];
+  }
+  for (int i = 4; i >= 0; --i) {
+    double s = y[i];
+    for (int k = i + 1; k < 5; ++k) s -= L[k][i] * x[k];
+    x[i] = s / L[i][i];
+  }
+  return 0;
+}
+
+int boltz_ref_collide(const boltz_ref_ctx* c, const double* h_s, double* h_out, int64_t step,
+                      uint32_t flags, double* dN_out, double* defect) {
+  if (!c || !h_s || !h_out) return BOLTZ_REF_EINVAL;
+  const int nv = c->nv;
+  const double eps = c->p.eps;
+  const int64_t nt = c->p.n_pairs;
+  int status = BOLTZ_REF_OK;
+#pragma omp parallel
+  {
+    double* hs = (double*)malloc(sizeof(double) * nv);
+    double* dn = (double*)malloc(sizeof(double) * nv);
+    double* hc = (double*)malloc(sizeof(double) * nv);
+#pragma omp for schedule(dynamic, 1)
+    for (int cell = 0; cell < c->ncells; ++cell) {
+      memcpy(hs, h_s + (size_t)cell * nv, sizeof(double) * nv);
+      memset(dn, 0, sizeof(double) * nv);
+      uint32_t g = group_of(c, cell);
+      /* Eq. monteCarloInt evaluated at the post-stream h (Eq. collision_step):
+       * every sample reads the same h (Jacobi form). */
+      for (int64_t m = 0; m < nt; ++m) {
+        pair_t pr;
+        sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
+        if (!pr.kept) continue;
+        double ha = hs[pr.a], hb = hs[pr.b];
+        double gg = (ha + hb) + (eps * ha) * hb;
+        double qg = pr.q * gg;
+        dn[pr.as] += qg;
+        dn[pr.bs] += qg;
+        dn[pr.a] -= qg;
+        dn[pr.b] -= qg;
+      }
+      /* Eq. collision_step: h^c_j = h^s_j + Delta N_j / (dV_j Phi0_j) */
+      for (int j = 0; j < nv; ++j) {
+        int jx, jy, jz;
+        node_idx(c, j, &jx, &jy, &jz);
+        hc[j] = hs[j] + dn[j] / node_w(c, jx, jy, jz);
+      }
+      double* ho = h_out + (size_t)cell * nv;
+      if (flags & BOLTZ_REF_NO_CORRECTION) {
+        memcpy(ho, hc, sizeof(double) * nv);
+      } else {
+        /* Eqs. rinorm_a / correzione: F^{n+1} = F^c (1 + A + B.v + C v^2)
+         * with the moments of psi = (1, v, v^2) of F^{n+1} equal to those of
+         * the post-stream F^s.  Linear system M x = r,
+         *   M_kl = sum_j w_j F^c_j psi_k psi_l,
+         *   r_k  = sum_j w_j psi_k (F^s_j - F^c_j) = -eps sum_j psi_k dN_j. */
+        double M[5][5] = {{0}}, rr[5] = {0}, x[5];
+        for (int j = 0; j < nv; ++j) {
+          int jx, jy, jz;
+          node_idx(c, j, &jx, &jy, &jz);
+          double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+          double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
+          double wF = node_w(c, jx, jy, jz) * (1.0 + eps * hc[j]);
+          for (int k = 0; k < 5; ++k) {
+            for (int l = 0; l < 5; ++l) M[k][l] += wF * psi[k] * psi[l];
+            rr[k] += -eps * psi[k] * dn[j];
+          }
+        }
+        if (solve5(M, rr, x) != 0) {
+#pragma omp atomic write
+          status = BOLTZ_REF_ENUMERIC;
+          for (int k = 0; k < 5; ++k) x[k] = 0.0;
+        }
+        for (int j = 0; j < nv; ++j) {
+          int jx, jy, jz;
+          node_idx(c, j, &jx, &jy, &jz);
+          double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+          double xpsi = x[0] + x[1] * vx + x[2] * vy + x[3] * vz + x[4] * ((vx * vx + vy * vy) + vz * vz);
+          ho[j] = hc[j] + (1.0 + eps * hc[j]) * xpsi / eps;
+        }
+      }
+      if (dN_out) memcpy(dN_out + (size_t)cell * nv, dn, sizeof(double) * nv);
+      if (defect) {
+        double d[5] = {0};
+        for (int j = 0; j < nv; ++j) {
+          int jx, jy, jz;
+          node_idx(c, j, &jx, &jy, &jz);
+          double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+          double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
+          double diff = eps * (ho[j] - hs[j]) * node_w(c, jx, jy, jz);
+          for (int k = 0; k < 5; ++k) d[k] += psi[k] * diff;
+        }
+        memcpy(defect + (size_t)cell * 5, d, sizeof(d));
+      }
+    }
+    free(hs);
+    free(dn);
+    free(hc);
+  }
+  return status;
+}
+
+/* ------------------------------------------------------------- moments -- */
+
+int boltz_ref_moments(const boltz_ref_ctx* c, const double* h, const boltz_ref_walls* walls,
+                      double* mom, double* lid_shear) {
+  if (!c || !h || !mom) return BOLTZ_REF_EINVAL;
+  const int nv = c->nv;
+  const double eps = c->p.eps;
+#pragma omp parallel for schedule(static)
+  for (int cell = 0; cell < c->ncells; ++cell) {
+    /* midpoint sums of Eqs. densita..sforzi */
+    double rho = 0, U[3] = {0, 0, 0}, E = 0, P[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double v[3] = {c->v[0][jx], c->v[1][jy], c->v[2][jz]};
+      double wh = node_w(c, jx, jy, jz) * h[(size_t)cell * nv + j];
+      rho += wh;
+      for (int k = 0; k < 3; ++k) U[k] += wh * v[k];
+      E += wh * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+      P[0] += wh * v[0] * v[0];
+      P[1] += wh * v[0] * v[1];
+      P[2] += wh * v[0] * v[2];
+      P[3] += wh * v[1] * v[1];
+      P[4] += wh * v[1] * v[2];
+      P[5] += wh * v[2] * v[2];
+    }
+    /* In units of V0 = sqrt(2 R T0): n/n0 = 1 + eps rho, u = U/(1 + eps rho),
+     * theta = ((2/3) E - rho)/(1 + eps rho) - (2/3) eps |u|^2,
+     * Pi_ij = 2 P_ij - 2 eps (1 + eps rho) u_i u_j. */
+    double n = 1.0 + eps * rho;
+    double u[3] = {U[0] / n, U[1] / n, U[2] / n};
+    double uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    double* o = mom + (size_t)cell * 11;
+    o[0] = rho;
+    o[1] = u[0];
+    o[2] = u[1];
+    o[3] = u[2];
+    o[4] = ((2.0 / 3.0) * E - rho) / n - (2.0 / 3.0) * eps * uu;
+    const int pi_k[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    for (int k = 0; k < 6; ++k) o[5 + k] = 2.0 * P[k] - 2.0 * eps * n * u[pi_k[k][0]] * u[pi_k[k][1]];
+  }
+  if (lid_shear) {
+    if (c->p.bc != BOLTZ_REF_BC_CAVITY || !walls) return BOLTZ_REF_EINVAL;
+    /* Lid shear D: the x-y stress on the lid face, built from the gas-side
+     * values of the top cells (v_y > 0) and the wall emission (v_y < 0, with
+     * n_w from the first-order face values); D = -(1/nx) sum Pi_xy so that
+     * D > 0 for a lid moving in +x. */
+    const int nx = c->p.nx, ny = c->p.ny;
+    double total = 0.0;
+    for (int ix = 0; ix < nx; ++ix) {
+      int cell = (ny - 1) * nx + ix;
+      double nw = face_density(c, h, WALL_TOP, ix, walls, 1);
+      double pxy = 0.0;
+      for (int j = 0; j < nv; ++j) {
+        int jx, jy, jz;
+        node_idx(c, j, &jx, &jy, &jz);
+        double vx = c->v[0][jx], vy = c->v[1][jy];
+        double hh = (vy > 0.0) ? h[(size_t)cell * nv + j]
+                               : (vy < 0.0 ? ghost_value(c, WALL_TOP, nw, j, walls) : 0.0);
+        pxy += node_w(c, jx, jy, jz) * vx * vy * hh;
+      }
+      total += 2.0 * pxy;
+    }
+    *lid_shear = -total / nx;
+  }
+  return BOLTZ_REF_OK;
+}
+
+/* ---------------------------------------------------------------- step -- */
+
+int boltz_ref_step(const boltz_ref_ctx* c, const double* h_in, double* h_out,
+                   const boltz_ref_walls* walls, int64_t step) {
+  if (!c || !h_in || !h_out || h_in == h_out) return BOLTZ_REF_EINVAL;
+  int rc = boltz_ref_stream(c, h_in, h_out, walls);
+  if (rc != BOLTZ_REF_OK) return rc;
+  return boltz_ref_collide(c, h_out, h_out, step, 0u, NULL, NULL);
+}
