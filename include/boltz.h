@@ -1,0 +1,185 @@
+/*
+ * boltz.h -- C ABI of the MI355X (gfx950) implementation of one time-split
+ * step of the semi-regular Boltzmann solver of Frezzotti, Ghiroldi and
+ * Gibelli, "Solving the Boltzmann Equation on GPUs" (arXiv:1005.5405).
+ *
+ * One step advances the deviational distribution h of f = Phi0 (1 + eps h)
+ * (Sec. 2, Eq. definition) on a 2D spatial x 3D velocity grid:
+ *   S1  diffuse Maxwell walls with zero net mass flux   (Sec. 2, Eq. bcMax)
+ *   S2  free streaming, first-order upwind (Sec. 3, Eq. streaming2D) or its
+ *       second-order Beam-Warming counterpart (dimension split x then y)
+ *   S3  Monte Carlo sampling of velocity-node pairs and directions
+ *       (Sec. 3, Eqs. coll8Dim, monteCarloInt)
+ *   S4  gain/loss scatter and the explicit update (Sec. 3, Eq. collision_step)
+ *   S5  conservation correction (Sec. 3, Eqs. rinorm_a, correzione)
+ *   S6  macroscopic moments (Sec. 2, Eqs. densita..sforzi) and lid shear
+ *
+ * Units (Sec. 5.1): n0 = 1, V0 = sqrt(2 R T0) = 1, cavity = unit square,
+ * lid at y = 1 moving in +x, time unit L/V0, delta = L/lambda0.
+ *
+ * Layout of every distribution buffer: FP32, cell-major,
+ *   h[cell * nv + j],  cell = iy * nx + ix,  j = (jx * nv_y + jy) * nv_z + jz,
+ * velocity node of axis k: v_i = (2 i + 1 - nv_k) * vmax_k / nv_k.
+ *
+ * Conventions of every call below:
+ *   - Buffers named h*, mom, defect, lid_shear are DEVICE pointers owned by
+ *     the caller; the library never frees them.  The context owns its own
+ *     constant tables and scratch (allocated in boltz_create); the compute
+ *     calls allocate nothing.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Compute calls
+ *     only enqueue work and return without synchronising; errors detected on
+ *     the device (a non-SPD correction matrix, a non-finite value) set bits
+ *     of a status word read with boltz_read_status.
+ *   - Return value: BOLTZ_OK or a negative boltz_status; the message of the
+ *     last failure is returned by boltz_last_error.  No C++ exception
+ *     crosses this interface.
+ *   - Calls on one context must not overlap on different streams (they
+ *     share the context scratch).
+ */
+#ifndef BOLTZ_H
+#define BOLTZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum boltz_status {
+  BOLTZ_OK = 0,
+  BOLTZ_EINVAL = -1,       /* invalid argument or problem                    */
+  BOLTZ_ENOMEM = -2,       /* device allocation failed                       */
+  BOLTZ_EHIP = -3,         /* a HIP runtime call failed                      */
+  BOLTZ_ENUMERIC = -4,     /* numerical failure reported by the device       */
+  BOLTZ_EUNSUPPORTED = -5  /* valid request this build does not implement   */
+} boltz_status;
+
+enum { BOLTZ_BC_CAVITY = 0, BOLTZ_BC_PERIODIC = 1 };
+
+/* boltz_problem.flags */
+enum { BOLTZ_ALLOW_UNSTABLE = 1u };  /* accept a dt above the Courant limit  */
+/* boltz_collide flags */
+enum { BOLTZ_NO_CORRECTION = 1u };   /* skip S5 (raw Monte Carlo update)     */
+/* device status bits (boltz_read_status) */
+enum { BOLTZ_STATUS_NOT_SPD = 1u, BOLTZ_STATUS_NONFINITE = 2u };
+
+/* Problem statement (Sec. 3 discretisation, Sec. 5.1 driven cavity). */
+typedef struct boltz_problem {
+  int32_t nx, ny;        /* spatial cells on the unit square (cavity: >= 2)  */
+  int32_t nv[3];         /* velocity cells per axis, 1..255                  */
+  double vmax[3];        /* half width of the velocity box per axis, in V0   */
+  double delta;          /* rarefaction parameter L / lambda0 (= 1/Kn)       */
+  double eps;            /* deviation scale eps > 0 of Eq. definition        */
+  double cfl;            /* largest Courant number when dt <= 0 (Sec. 5.1)   */
+  double dt;             /* explicit time step; <= 0: dt from cfl            */
+  int32_t order;         /* streaming order: 1 or 2                          */
+  int32_t bc;            /* BOLTZ_BC_CAVITY or BOLTZ_BC_PERIODIC             */
+  int64_t n_pairs;       /* N_t of Eq. monteCarloInt, pairs per cell per step*/
+  int64_t sample_group;  /* G: cells cell/G share a pair stream; 0 = all     */
+  uint64_t seed;         /* Philox4x32-10 key (low word, high word)          */
+  uint32_t cavity_id;    /* fourth Philox counter word                       */
+  uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE                             */
+  uint32_t mix16;        /* uniform share beta = mix16/16 of the node-pair   */
+                         /* law (0..16; 0 = the paper's sampling from Phi0)  */
+} boltz_problem;
+
+/* Wall state for one call (Sec. 2, Eq. bcMax; Sec. 5.1). */
+typedef struct boltz_walls {
+  double lid_u;          /* x velocity of the top wall y = 1, in V0          */
+  double tau_left, tau_right, tau_bottom, tau_top;  /* T_w / T0, > 0         */
+} boltz_walls;
+
+typedef struct boltz_info {
+  int64_t ncells;        /* nx * ny                                          */
+  int64_t nv;            /* nv[0] * nv[1] * nv[2]                            */
+  double dt;             /* time step in use                                 */
+  double K;              /* pi n0 sigma^2 = (5/16) sqrt(2 pi) 1.016034 delta */
+  double W;              /* discrete mass of Phi0 on the velocity grid       */
+  double qfac;           /* dt K / N_t                                       */
+  int64_t device_bytes;  /* device memory held by the context                */
+} boltz_info;
+
+typedef struct boltz_ctx boltz_ctx;
+
+/* Validate the problem, build the velocity-grid tables (Sec. 3) and the
+ * per-axis sampling thresholds, and allocate the context on the current HIP
+ * device.  EINVAL: out-of-range sizes, a dt above the Courant limit of the
+ * streaming scheme (unless BOLTZ_ALLOW_UNSTABLE), n_pairs >= 2^31.
+ * EUNSUPPORTED: a velocity grid whose two per-cell FP32 tiles exceed the
+ * 160 KB local data share.  ENOMEM / EHIP: device allocation failed. */
+int boltz_create(const boltz_problem* problem, boltz_ctx** out);
+
+void boltz_destroy(boltz_ctx* ctx);
+
+int boltz_query(const boltz_ctx* ctx, boltz_info* out);
+
+/* Message of the last failure on ctx (ctx = NULL: of the last failed
+ * boltz_create on this thread).  Valid until the next call on ctx. */
+const char* boltz_last_error(const boltz_ctx* ctx);
+
+/* S1 + S2: one free-streaming step h_in -> h_out (Sec. 3, Eq. freestreaming
+ * discretised by Eq. streaming2D for order 1, Beam-Warming x then y for
+ * order 2), with the diffuse-wall emission of Eq. bcMax whose density n_w
+ * makes the discrete mass flux through every boundary face vanish.  h_in and
+ * h_out: ncells*nv FP32, must not overlap.  walls: host pointer, required for
+ * cavities, ignored (may be NULL) for periodic problems. */
+int boltz_stream(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_walls* walls,
+                 void* stream);
+
+/* S3 + S4 + S5: one collision step at fixed position (Sec. 3, Eq. homrel),
+ * h_s -> h_out.  N_t pairs per cell: nodes a, b drawn from the mixture
+ * (1 - beta) Maxwellian node law + beta uniform node law, a direction
+ * uniform on the sphere, by Philox4x32-10 with counter
+ * (2m + {0,1}, group, step, cavity_id) and key seed; each pair carries the
+ * importance weight dt K |v_r . k| (w_a/p_a)(w_b/p_b) / N_t of Eq. coll8Dim
+ * (w = midpoint weight of Phi0, p = probability of the draw); the Monte Carlo
+ * increments of Eq. monteCarloInt are applied in Jacobi form
+ * (Eq. collision_step), then the correction of Eq. rinorm_a restores the
+ * post-stream mass, momentum and energy (FP64 sums and 5x5 solve).
+ * h_s may equal h_out (in place); otherwise they must not overlap.
+ * flags: BOLTZ_NO_CORRECTION.  defect: NULL or ncells*5 FP64 device buffer
+ * receiving sum_j w_j psi_k (F_out - F_s) of the stored FP32 values. */
+int boltz_collide(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, uint32_t flags,
+                  double* defect, void* stream);
+
+/* S6: per-cell moments (Sec. 2, Eqs. densita..sforzi, re-derived in units
+ * of V0): mom[cell*11 + k] = rho, u_x, u_y, u_z, theta, Pi_xx, Pi_xy, Pi_xz,
+ * Pi_yy, Pi_yz, Pi_zz (FP64 device buffer).  lid_shear: NULL or one FP64
+ * device value D = -(1/nx) sum over lid faces of Pi_xy, built from the
+ * gas-side values of the top cells and the wall emission (Sec. 5.2 defines
+ * D as the mean shear stress on the moving wall); cavity only. */
+int boltz_moments(boltz_ctx* ctx, const float* h, const boltz_walls* walls, double* mom,
+                  double* lid_shear, void* stream);
+
+/* One full time-split step h_in -> h_out: boltz_stream then boltz_collide
+ * in place on h_out (Sec. 3).  h_in and h_out must not overlap. */
+int boltz_step(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_walls* walls,
+               int64_t step, void* stream);
+
+/* Adjoint of boltz_step for fixed Philox streams (gradient of a functional
+ * of h_out with respect to h_in and to the wall parameters).  Declared for
+ * interface stability; this build returns BOLTZ_EUNSUPPORTED. */
+int boltz_step_adjoint(boltz_ctx* ctx, const float* h_in, const double* lam_out, double* lam_in,
+                       double* grad_walls, const boltz_walls* walls, int64_t step, void* stream);
+
+/* Test hook: the pairs the collision kernel draws for (cell, step) and pair
+ * indices m0 .. m0+count-1, computed on the device by the kernel's own
+ * sampler.  idx4 (host, count*4): a, b, a*, b* (a* = b* = -1 for a discarded
+ * pair); q (host, count): weight dt K |v_r . k| (w_a/p_a)(w_b/p_b) / N_t (0 if
+ * discarded);
+ * words (host, count*8 or NULL): the eight Philox words.  Synchronous. */
+int boltz_debug_pairs(boltz_ctx* ctx, int64_t cell, int64_t step, int64_t m0, int64_t count,
+                      int32_t* idx4, double* q, uint32_t* words);
+
+/* Test hook: thresholds T_1..T_{n-1} of the node law of one axis (host
+ * buffer of nv[axis]-1 uint64 values, each in [0, 2^32]). */
+int boltz_axis_thresholds(const boltz_ctx* ctx, int axis, uint64_t* out);
+
+/* Read (and optionally clear) the device status word after synchronising
+ * `stream`.  *out: OR of BOLTZ_STATUS_* bits raised since the last clear. */
+int boltz_read_status(boltz_ctx* ctx, uint32_t* out, int clear, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -46,7 +46,8 @@ class _Problem(ctypes.Structure):
                 ("vmax", ctypes.c_double * 3), ("delta", ctypes.c_double), ("eps", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("dt", ctypes.c_double), ("order", ctypes.c_int32),
                 ("bc", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("sample_group", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("cavity_id", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("seed", ctypes.c_uint64), ("cavity_id", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("mix16", ctypes.c_uint32)]
 
 
 class _Walls(ctypes.Structure):
@@ -80,6 +81,7 @@ def _load():
         L.boltz_ref_wall_density.argtypes = [P, V, ctypes.POINTER(_Walls), V]
         L.boltz_ref_stream.argtypes = [P, V, V, ctypes.POINTER(_Walls)]
         L.boltz_ref_collide.argtypes = [P, V, V, I64, U32, V, V]
+        L.boltz_ref_collide_cells.argtypes = [P, V, V, I64, U32, V, I64]
         L.boltz_ref_moments.argtypes = [P, V, ctypes.POINTER(_Walls), V, V]
         L.boltz_ref_step.argtypes = [P, V, V, ctypes.POINTER(_Walls), I64]
         _lib = L
@@ -131,13 +133,13 @@ class Oracle:
     """One problem set-up of the oracle (FP64, host memory)."""
 
     def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2,
-                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0):
+                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=0):
         L = _load()
         nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
         vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
         p = _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax),
                      float(delta), float(eps), float(cfl), float(dt), int(order), int(bc),
-                     int(n_pairs), int(sample_group), int(seed), int(cavity_id), int(flags))
+                     int(n_pairs), int(sample_group), int(seed), int(cavity_id), int(flags), int(mix16))
         ctx = ctypes.c_void_p()
         rc = L.boltz_ref_create(ctypes.byref(p), ctypes.byref(ctx))
         if rc != 0:
@@ -209,6 +211,17 @@ class Oracle:
                                            defect.ctypes.data if want_defect else None), "collide")
         if want_dN or want_defect:
             return out, dN, defect
+        return out
+
+    def collide_cells(self, h_cells, step, cells, correction=True):
+        """Collision of the listed cells only: h_cells (count, nv) holds their
+        post-stream values; returns their outputs (count, nv)."""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        h = _f64(h_cells, (len(cells), self.nv))
+        out = np.zeros((len(cells), self.nv))
+        flags = 0 if correction else NO_CORRECTION
+        self._check(_lib.boltz_ref_collide_cells(self._ctx, h.ctypes.data, out.ctypes.data, int(step), flags,
+                                                 cells.ctypes.data, len(cells)), "collide_cells")
         return out
 
     def moments(self, h, walls: Walls | None = None, lid_shear=False):

@@ -43,6 +43,9 @@ struct boltz_ref_ctx {
   double* om[3];
   double Om[3];
   uint64_t* T[3]; /* T[k][i] = T_i for i in [1, n); T[k][0] = 0 */
+  double* pphi[3];  /* realised per-axis Maxwellian law (T_{i+1} - T_i) 2^-32 */
+  double* punif[3]; /* realised per-axis uniform law of floor(r n / 2^32)     */
+  double beta;      /* weight of the uniform component, mix16 / 16           */
   double dx, dy, dt, K, W, qfac;
   char err[256];
 };
@@ -82,6 +85,8 @@ void boltz_ref_destroy(boltz_ref_ctx* c) {
     free(c->v[k]);
     free(c->om[k]);
     free(c->T[k]);
+    free(c->pphi[k]);
+    free(c->punif[k]);
   }
   free(c);
 }
@@ -105,7 +110,7 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
   }
   if (!(p->delta > 0.0) || !(p->eps > 0.0) || (p->order != 1 && p->order != 2) ||
       (p->bc != BOLTZ_REF_BC_CAVITY && p->bc != BOLTZ_REF_BC_PERIODIC) || p->n_pairs < 0 ||
-      p->n_pairs >= (int64_t)1 << 31 || p->sample_group < 0 ||
+      p->n_pairs >= (int64_t)1 << 31 || p->sample_group < 0 || p->mix16 > 16 ||
       (!(p->dt > 0.0) && !(p->cfl > 0.0))) {
     set_err(g_create_err, "invalid scalar parameter");
     return BOLTZ_REF_EINVAL;
@@ -126,7 +131,9 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
     c->v[k] = (double*)malloc(sizeof(double) * n);
     c->om[k] = (double*)malloc(sizeof(double) * n);
     c->T[k] = (uint64_t*)malloc(sizeof(uint64_t) * n);
-    if (!c->v[k] || !c->om[k] || !c->T[k]) {
+    c->pphi[k] = (double*)malloc(sizeof(double) * n);
+    c->punif[k] = (double*)malloc(sizeof(double) * n);
+    if (!c->v[k] || !c->om[k] || !c->T[k] || !c->pphi[k] || !c->punif[k]) {
       boltz_ref_destroy(c);
       set_err(g_create_err, "out of memory");
       return BOLTZ_REF_ENOMEM;
@@ -152,7 +159,18 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
       if (i > 0) c->T[k][i] = (uint64_t)nearbyint(ldexp(s / om_sum, 32));
       s += c->om[k][i];
     }
+    /* realised probabilities of the two per-axis laws: node i of the
+     * Maxwellian law for r in [T_i, T_{i+1}); node i of the uniform law for
+     * r with floor(r n / 2^32) = i, i.e. r in [ceil(i 2^32/n), ceil((i+1) 2^32/n)) */
+    for (int i = 0; i < n; ++i) {
+      uint64_t hi = (i + 1 < n) ? c->T[k][i + 1] : ((uint64_t)1 << 32);
+      c->pphi[k][i] = ldexp((double)(hi - c->T[k][i]), -32);
+      uint64_t lo_u = (((uint64_t)i << 32) + (uint64_t)n - 1) / (uint64_t)n;
+      uint64_t hi_u = (((uint64_t)(i + 1) << 32) + (uint64_t)n - 1) / (uint64_t)n;
+      c->punif[k][i] = ldexp((double)(hi_u - lo_u), -32);
+    }
   }
+  c->beta = p->mix16 / 16.0;
   c->ncells = p->nx * p->ny;
   c->dx = 1.0 / p->nx;
   c->dy = 1.0 / p->ny;
@@ -176,7 +194,7 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
    * K = (5/16) sqrt(2 pi) 1.016034 delta. */
   c->K = 0.3125 * sqrt(TWO_PI) * 1.016034 * p->delta;
   c->W = (c->Om[0] * c->Om[1]) * c->Om[2];
-  c->qfac = (p->n_pairs > 0) ? (((c->dt * c->K) * c->W) * c->W) / (double)p->n_pairs : 0.0;
+  c->qfac = (p->n_pairs > 0) ? (c->dt * c->K) / (double)p->n_pairs : 0.0;
   *out = c;
   return BOLTZ_REF_OK;
 }
@@ -322,13 +340,25 @@ static int axis_cell(const boltz_ref_ctx* c, int k, double x) {
   return (int)t;
 }
 
+/* w_a / p~_a for node (i, j, k): the midpoint weight of Phi0 over the
+ * probability of drawing the node from the mixture (1 - beta) p_Phi0 + beta
+ * p_uniform (Eq. coll8Dim as an importance-sampling estimate). */
+static double node_ratio(const boltz_ref_ctx* c, int i, int j, int k) {
+  double w = (c->om[0][i] * c->om[1][j]) * c->om[2][k];
+  double pm = (c->pphi[0][i] * c->pphi[1][j]) * c->pphi[2][k];
+  double pu = (c->punif[0][i] * c->punif[1][j]) * c->punif[2][k];
+  return w / ((1.0 - c->beta) * pm + c->beta * pu);
+}
+
 /* One Monte Carlo collision sample (Sec. 3, Eqs. coll8Dim / monteCarloInt):
- * pre-collision nodes a, b drawn from the discrete Maxwellian weights, a
- * direction k uniform on the unit sphere, post-collision velocities
+ * pre-collision nodes a, b drawn from the mixture of the discrete
+ * Maxwellian law (weight 1 - beta) and the uniform node law (weight beta),
+ * a direction k uniform on the unit sphere, post-collision velocities
  * v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a (the sign
  * of the sampling-kernel listing; it conserves energy), and the weight
- * q = dt K W^2 |v_r.k| / N_t.  Pairs whose post-collision velocity leaves the
- * box are discarded (they still count in N_t). */
+ * q = dt K |v_r.k| (w_a/p~_a) (w_b/p~_b) / N_t.  beta = 0 is the paper's
+ * sampling from Phi0.  Pairs whose post-collision velocity leaves the box
+ * are discarded (they still count in N_t). */
 static void sample_pair(const boltz_ref_ctx* c, uint32_t group, uint32_t step, uint32_t m,
                         pair_t* out) {
   const uint32_t key[2] = {(uint32_t)c->p.seed, (uint32_t)(c->p.seed >> 32)};
@@ -337,24 +367,30 @@ static void sample_pair(const boltz_ref_ctx* c, uint32_t group, uint32_t step, u
   uint32_t* r = out->r;
   boltz_ref_philox4x32_10(c0, key, r);
   boltz_ref_philox4x32_10(c1, key, r + 4);
-  int iax = axis_draw(c, 0, r[0]), iay = axis_draw(c, 1, r[1]), iaz = axis_draw(c, 2, r[2]);
-  int ibx = axis_draw(c, 0, r[3]), iby = axis_draw(c, 1, r[4]), ibz = axis_draw(c, 2, r[5]);
+  /* component choice from the low byte of r7: 4 bits for a, 4 for b */
+  const int unif_a = (int)(r[7] & 15u) < (int)c->p.mix16;
+  const int unif_b = (int)((r[7] >> 4) & 15u) < (int)c->p.mix16;
+  int ia[3], ib[3];
+  for (int k = 0; k < 3; ++k) {
+    ia[k] = unif_a ? (int)(((uint64_t)r[k] * (uint64_t)c->n[k]) >> 32) : axis_draw(c, k, r[k]);
+    ib[k] = unif_b ? (int)(((uint64_t)r[3 + k] * (uint64_t)c->n[k]) >> 32) : axis_draw(c, k, r[3 + k]);
+  }
   double u6 = ((double)r[6] + 0.5) * 0x1p-32;
-  double u7 = ((double)r[7] + 0.5) * 0x1p-32;
+  double u7 = ((double)(r[7] >> 8) + 0.5) * 0x1p-24;
   double kz = 2.0 * u6 - 1.0;
   double s = sqrt((1.0 - kz) * (1.0 + kz));
   double cp, sp;
   boltz_ref_cos_sin_2pi(u7, &cp, &sp);
   double kx = s * cp, ky = s * sp;
-  double vax = c->v[0][iax], vay = c->v[1][iay], vaz = c->v[2][iaz];
-  double vbx = c->v[0][ibx], vby = c->v[1][iby], vbz = c->v[2][ibz];
+  double vax = c->v[0][ia[0]], vay = c->v[1][ia[1]], vaz = c->v[2][ia[2]];
+  double vbx = c->v[0][ib[0]], vby = c->v[1][ib[1]], vbz = c->v[2][ib[2]];
   double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
   double alpha = (vrx * kx + vry * ky) + vrz * kz;
   double ddx = alpha * kx, ddy = alpha * ky, ddz = alpha * kz;
   int sx = axis_cell(c, 0, vax + ddx), sy = axis_cell(c, 1, vay + ddy), sz = axis_cell(c, 2, vaz + ddz);
   int tx = axis_cell(c, 0, vbx - ddx), ty = axis_cell(c, 1, vby - ddy), tz = axis_cell(c, 2, vbz - ddz);
-  out->a = node_of(c, iax, iay, iaz);
-  out->b = node_of(c, ibx, iby, ibz);
+  out->a = node_of(c, ia[0], ia[1], ia[2]);
+  out->b = node_of(c, ib[0], ib[1], ib[2]);
   const double vel[12] = {vax, vay, vaz, vbx, vby, vbz, vax + ddx, vay + ddy, vaz + ddz,
                           vbx - ddx, vby - ddy, vbz - ddz};
   memcpy(out->vel, vel, sizeof(vel));
@@ -362,7 +398,8 @@ static void sample_pair(const boltz_ref_ctx* c, uint32_t group, uint32_t step, u
   if (out->kept) {
     out->as = node_of(c, sx, sy, sz);
     out->bs = node_of(c, tx, ty, tz);
-    out->q = c->qfac * fabs(alpha);
+    out->q = ((c->qfac * fabs(alpha)) * node_ratio(c, ia[0], ia[1], ia[2])) *
+             node_ratio(c, ib[0], ib[1], ib[2]);
   } else {
     out->as = -1;
     out->bs = -1;
@@ -682,12 +719,91 @@ static int solve5(double M[5][5], const double r[5], double x[5]) {
   return 0;
 }
 
-int boltz_ref_collide(const boltz_ref_ctx* c, const double* h_s, double* h_out, int64_t step,
-                      uint32_t flags, double* dN_out, double* defect) {
-  if (!c || !h_s || !h_out) return BOLTZ_REF_EINVAL;
+/* Collision of one cell: hs (copy of the cell's post-stream h), work
+ * arrays dn, hc of nv doubles; writes the cell's output to ho. */
+static int collide_cell(const boltz_ref_ctx* c, int64_t cell, int64_t step, uint32_t flags,
+                        const double* hs, double* dn, double* hc, double* ho, double* dN_out,
+                        double* defect) {
   const int nv = c->nv;
   const double eps = c->p.eps;
   const int64_t nt = c->p.n_pairs;
+  int status = BOLTZ_REF_OK;
+  memset(dn, 0, sizeof(double) * nv);
+  uint32_t g = group_of(c, cell);
+  /* Eq. monteCarloInt evaluated at the post-stream h (Eq. collision_step):
+   * every sample reads the same h (Jacobi form). */
+  for (int64_t m = 0; m < nt; ++m) {
+    pair_t pr;
+    sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
+    if (!pr.kept) continue;
+    double ha = hs[pr.a], hb = hs[pr.b];
+    double gg = (ha + hb) + (eps * ha) * hb;
+    double qg = pr.q * gg;
+    dn[pr.as] += qg;
+    dn[pr.bs] += qg;
+    dn[pr.a] -= qg;
+    dn[pr.b] -= qg;
+  }
+  /* Eq. collision_step: h^c_j = h^s_j + Delta N_j / (dV_j Phi0_j) */
+  for (int j = 0; j < nv; ++j) {
+    int jx, jy, jz;
+    node_idx(c, j, &jx, &jy, &jz);
+    hc[j] = hs[j] + dn[j] / node_w(c, jx, jy, jz);
+  }
+  if (flags & BOLTZ_REF_NO_CORRECTION) {
+    memcpy(ho, hc, sizeof(double) * nv);
+  } else {
+    /* Eqs. rinorm_a / correzione: F^{n+1} = F^c (1 + A + B.v + C v^2)
+     * with the moments of psi = (1, v, v^2) of F^{n+1} equal to those of
+     * the post-stream F^s.  Linear system M x = r,
+     *   M_kl = sum_j w_j F^c_j psi_k psi_l,
+     *   r_k  = sum_j w_j psi_k (F^s_j - F^c_j) = -eps sum_j psi_k dN_j. */
+    double M[5][5] = {{0}}, rr[5] = {0}, x[5];
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+      double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
+      double wF = node_w(c, jx, jy, jz) * (1.0 + eps * hc[j]);
+      for (int k = 0; k < 5; ++k) {
+        for (int l = 0; l < 5; ++l) M[k][l] += wF * psi[k] * psi[l];
+        rr[k] += -eps * psi[k] * dn[j];
+      }
+    }
+    if (solve5(M, rr, x) != 0) {
+      status = BOLTZ_REF_ENUMERIC;
+      for (int k = 0; k < 5; ++k) x[k] = 0.0;
+    }
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+      double xpsi = x[0] + x[1] * vx + x[2] * vy + x[3] * vz + x[4] * ((vx * vx + vy * vy) + vz * vz);
+      ho[j] = hc[j] + (1.0 + eps * hc[j]) * xpsi / eps;
+    }
+  }
+  if (dN_out) memcpy(dN_out, dn, sizeof(double) * nv);
+  if (defect) {
+    double d[5] = {0};
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+      double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
+      double diff = eps * (ho[j] - hs[j]) * node_w(c, jx, jy, jz);
+      for (int k = 0; k < 5; ++k) d[k] += psi[k] * diff;
+    }
+    memcpy(defect, d, sizeof(d));
+  }
+  return status;
+}
+
+/* cells == NULL: all cells of full arrays; otherwise the listed cells, with
+ * h_s / h_out holding only those cells (count * nv, compact). */
+static int collide_list(const boltz_ref_ctx* c, const double* h_s, double* h_out, int64_t step,
+                        uint32_t flags, const int64_t* cells, int64_t count, double* dN_out,
+                        double* defect) {
+  const int nv = c->nv;
   int status = BOLTZ_REF_OK;
 #pragma omp parallel
   {
@@ -695,76 +811,15 @@ int boltz_ref_collide(const boltz_ref_ctx* c, const double* h_s, double* h_out, 
     double* dn = (double*)malloc(sizeof(double) * nv);
     double* hc = (double*)malloc(sizeof(double) * nv);
 #pragma omp for schedule(dynamic, 1)
-    for (int cell = 0; cell < c->ncells; ++cell) {
-      memcpy(hs, h_s + (size_t)cell * nv, sizeof(double) * nv);
-      memset(dn, 0, sizeof(double) * nv);
-      uint32_t g = group_of(c, cell);
-      /* Eq. monteCarloInt evaluated at the post-stream h (Eq. collision_step):
-       * every sample reads the same h (Jacobi form). */
-      for (int64_t m = 0; m < nt; ++m) {
-        pair_t pr;
-        sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
-        if (!pr.kept) continue;
-        double ha = hs[pr.a], hb = hs[pr.b];
-        double gg = (ha + hb) + (eps * ha) * hb;
-        double qg = pr.q * gg;
-        dn[pr.as] += qg;
-        dn[pr.bs] += qg;
-        dn[pr.a] -= qg;
-        dn[pr.b] -= qg;
-      }
-      /* Eq. collision_step: h^c_j = h^s_j + Delta N_j / (dV_j Phi0_j) */
-      for (int j = 0; j < nv; ++j) {
-        int jx, jy, jz;
-        node_idx(c, j, &jx, &jy, &jz);
-        hc[j] = hs[j] + dn[j] / node_w(c, jx, jy, jz);
-      }
-      double* ho = h_out + (size_t)cell * nv;
-      if (flags & BOLTZ_REF_NO_CORRECTION) {
-        memcpy(ho, hc, sizeof(double) * nv);
-      } else {
-        /* Eqs. rinorm_a / correzione: F^{n+1} = F^c (1 + A + B.v + C v^2)
-         * with the moments of psi = (1, v, v^2) of F^{n+1} equal to those of
-         * the post-stream F^s.  Linear system M x = r,
-         *   M_kl = sum_j w_j F^c_j psi_k psi_l,
-         *   r_k  = sum_j w_j psi_k (F^s_j - F^c_j) = -eps sum_j psi_k dN_j. */
-        double M[5][5] = {{0}}, rr[5] = {0}, x[5];
-        for (int j = 0; j < nv; ++j) {
-          int jx, jy, jz;
-          node_idx(c, j, &jx, &jy, &jz);
-          double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
-          double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
-          double wF = node_w(c, jx, jy, jz) * (1.0 + eps * hc[j]);
-          for (int k = 0; k < 5; ++k) {
-            for (int l = 0; l < 5; ++l) M[k][l] += wF * psi[k] * psi[l];
-            rr[k] += -eps * psi[k] * dn[j];
-          }
-        }
-        if (solve5(M, rr, x) != 0) {
+    for (int64_t i = 0; i < count; ++i) {
+      int64_t cell = cells ? cells[i] : i;
+      memcpy(hs, h_s + (size_t)i * nv, sizeof(double) * nv);
+      int st = collide_cell(c, cell, step, flags, hs, dn, hc, h_out + (size_t)i * nv,
+                            dN_out ? dN_out + (size_t)cell * nv : NULL,
+                            defect ? defect + (size_t)cell * 5 : NULL);
+      if (st != BOLTZ_REF_OK) {
 #pragma omp atomic write
-          status = BOLTZ_REF_ENUMERIC;
-          for (int k = 0; k < 5; ++k) x[k] = 0.0;
-        }
-        for (int j = 0; j < nv; ++j) {
-          int jx, jy, jz;
-          node_idx(c, j, &jx, &jy, &jz);
-          double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
-          double xpsi = x[0] + x[1] * vx + x[2] * vy + x[3] * vz + x[4] * ((vx * vx + vy * vy) + vz * vz);
-          ho[j] = hc[j] + (1.0 + eps * hc[j]) * xpsi / eps;
-        }
-      }
-      if (dN_out) memcpy(dN_out + (size_t)cell * nv, dn, sizeof(double) * nv);
-      if (defect) {
-        double d[5] = {0};
-        for (int j = 0; j < nv; ++j) {
-          int jx, jy, jz;
-          node_idx(c, j, &jx, &jy, &jz);
-          double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
-          double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
-          double diff = eps * (ho[j] - hs[j]) * node_w(c, jx, jy, jz);
-          for (int k = 0; k < 5; ++k) d[k] += psi[k] * diff;
-        }
-        memcpy(defect + (size_t)cell * 5, d, sizeof(d));
+        status = st;
       }
     }
     free(hs);
@@ -772,6 +827,20 @@ int boltz_ref_collide(const boltz_ref_ctx* c, const double* h_s, double* h_out, 
     free(hc);
   }
   return status;
+}
+
+int boltz_ref_collide(const boltz_ref_ctx* c, const double* h_s, double* h_out, int64_t step,
+                      uint32_t flags, double* dN_out, double* defect) {
+  if (!c || !h_s || !h_out) return BOLTZ_REF_EINVAL;
+  return collide_list(c, h_s, h_out, step, flags, NULL, c->ncells, dN_out, defect);
+}
+
+int boltz_ref_collide_cells(const boltz_ref_ctx* c, const double* h_s, double* h_out, int64_t step,
+                            uint32_t flags, const int64_t* cells, int64_t count) {
+  if (!c || !h_s || !h_out || !cells || count < 0) return BOLTZ_REF_EINVAL;
+  for (int64_t i = 0; i < count; ++i)
+    if (cells[i] < 0 || cells[i] >= c->ncells) return BOLTZ_REF_EINVAL;
+  return collide_list(c, h_s, h_out, step, flags, cells, count, NULL, NULL);
 }
 
 /* ------------------------------------------------------------- moments -- */

@@ -56,6 +56,7 @@ typedef struct boltz_ref_problem {
   uint64_t seed;         /* Philox key                                      */
   uint32_t cavity_id;    /* fourth Philox counter word                      */
   uint32_t flags;        /* BOLTZ_REF_ALLOW_UNSTABLE                        */
+  uint32_t mix16;        /* uniform share of the pair law, in 1/16 (0..16)  */
 } boltz_ref_problem;
 
 typedef struct boltz_ref_walls {
@@ -118,6 +119,11 @@ int boltz_ref_stream(const boltz_ref_ctx* ctx, const double* h_in, double* h_out
  * Delta N; defect (ncells*5, optional) receives sum_j w_j psi_k (F^out - F^s). */
 int boltz_ref_collide(const boltz_ref_ctx* ctx, const double* h_s, double* h_out,
                       int64_t step, uint32_t flags, double* dN, double* defect);
+
+/* The same collision for the listed cells only; h_s and h_out hold just
+ * those cells (count * nv values, in list order). */
+int boltz_ref_collide_cells(const boltz_ref_ctx* ctx, const double* h_s, double* h_out,
+                            int64_t step, uint32_t flags, const int64_t* cells, int64_t count);
 
 /* Per-cell moments rho, u_x, u_y, u_z, theta, Pi_xx, Pi_xy, Pi_xz, Pi_yy,
  * Pi_yz, Pi_zz (11 per cell) and the lid shear D (cavity only, optional). */

@@ -1,0 +1,245 @@
+"""ctypes binding of libboltz (include/boltz.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of libboltz.so; this module
+checks tensor shapes, dtypes and devices, passes raw device pointers and the
+current HIP stream, and turns negative status codes into exceptions.  PyTorch
+is used for device memory and streams only.  There is no fallback: if the
+library is missing or was not built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libboltz.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BC_CAVITY, BC_PERIODIC = 0, 1
+ALLOW_UNSTABLE = 1
+NO_CORRECTION = 1
+STATUS_NOT_SPD, STATUS_NONFINITE = 1, 2
+
+
+class BoltzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (status %d)" % (msg, code))
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nv", ctypes.c_int32 * 3),
+                ("vmax", ctypes.c_double * 3), ("delta", ctypes.c_double), ("eps", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("dt", ctypes.c_double), ("order", ctypes.c_int32),
+                ("bc", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("sample_group", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("cavity_id", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("mix16", ctypes.c_uint32)]
+
+
+class _Walls(ctypes.Structure):
+    _fields_ = [("lid_u", ctypes.c_double), ("tau_left", ctypes.c_double), ("tau_right", ctypes.c_double),
+                ("tau_bottom", ctypes.c_double), ("tau_top", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("ncells", ctypes.c_int64), ("nv", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("K", ctypes.c_double), ("W", ctypes.c_double), ("qfac", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+
+EXPORTS = ("boltz_create", "boltz_destroy", "boltz_query", "boltz_last_error", "boltz_stream",
+           "boltz_collide", "boltz_moments", "boltz_step", "boltz_step_adjoint", "boltz_debug_pairs",
+           "boltz_axis_thresholds", "boltz_read_status")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libboltz.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch ships its own HIP runtime (same soname as the system one); load it
+    # first so that libboltz binds to the runtime that owns torch's device
+    # memory and streams instead of mapping a second runtime.
+    import torch  # noqa: F401
+
+    if not os.path.exists(path):
+        raise RuntimeError("libboltz.so not found at %s: build it with __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950)" % path)
+    L = ctypes.CDLL(path)
+    P, V, I64, U32 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32
+    W = ctypes.POINTER(_Walls)
+    L.boltz_create.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(P)]
+    L.boltz_destroy.argtypes = [P]
+    L.boltz_query.argtypes = [P, ctypes.POINTER(_Info)]
+    L.boltz_last_error.argtypes = [P]
+    L.boltz_last_error.restype = ctypes.c_char_p
+    L.boltz_stream.argtypes = [P, V, V, W, V]
+    L.boltz_collide.argtypes = [P, V, V, I64, U32, V, V]
+    L.boltz_moments.argtypes = [P, V, W, V, V, V]
+    L.boltz_step.argtypes = [P, V, V, W, I64, V]
+    L.boltz_step_adjoint.argtypes = [P, V, V, V, V, W, I64, V]
+    L.boltz_debug_pairs.argtypes = [P, I64, I64, I64, I64, V, V, V]
+    L.boltz_axis_thresholds.argtypes = [P, ctypes.c_int, V]
+    L.boltz_read_status.argtypes = [P, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, V]
+    for name in EXPORTS:
+        if name not in ("boltz_last_error", "boltz_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    L.boltz_destroy.restype = None
+    _lib = L
+    return L
+
+
+@dataclass
+class Walls:
+    """Wall state of one call: lid x velocity and wall temperatures T_w/T0."""
+    lid_u: float = 0.0
+    tau_left: float = 1.0
+    tau_right: float = 1.0
+    tau_bottom: float = 1.0
+    tau_top: float = 1.0
+
+    def _c(self) -> _Walls:
+        return _Walls(self.lid_u, self.tau_left, self.tau_right, self.tau_bottom, self.tau_top)
+
+
+def _ptr(t, numel, dtype, what, allow_none=False):
+    import torch
+
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError("%s: tensor required" % what)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s: expected a CUDA (HIP) tensor" % what)
+    if t.dtype != dtype:
+        raise ValueError("%s: expected dtype %s, got %s" % (what, dtype, t.dtype))
+    if not t.is_contiguous() or t.numel() != numel:
+        raise ValueError("%s: expected a contiguous tensor of %d elements" % (what, numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Boltz:
+    """One problem on the current HIP device (a boltz_ctx)."""
+
+    def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2, bc=BC_CAVITY,
+                 sample_group=1, seed=1, cavity_id=0, flags=0, mix16=0):
+        L = load_library()
+        nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
+        vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
+        p = _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax), float(delta),
+                     float(eps), float(cfl), float(dt), int(order), int(bc), int(n_pairs), int(sample_group),
+                     int(seed), int(cavity_id), int(flags), int(mix16))
+        ctx = ctypes.c_void_p()
+        rc = L.boltz_create(ctypes.byref(p), ctypes.byref(ctx))
+        if rc != OK:
+            raise BoltzError(rc, "boltz_create: " + L.boltz_last_error(None).decode())
+        self._ctx = ctx
+        info = _Info()
+        L.boltz_query(ctx, ctypes.byref(info))
+        self.nx, self.ny, self.nv3 = int(nx), int(ny), nv
+        self.ncells, self.nv = int(info.ncells), int(info.nv)
+        self.numel = self.ncells * self.nv
+        self.shape = (self.ny, self.nx, self.nv)
+        self.dt, self.K, self.W, self.qfac = info.dt, info.K, info.W, info.qfac
+        self.device_bytes = int(info.device_bytes)
+        self.n_pairs, self.order, self.bc, self.eps = int(n_pairs), int(order), int(bc), float(eps)
+        self.mix16 = int(mix16)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and _lib is not None:
+            _lib.boltz_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise BoltzError(rc, "%s: %s" % (what, _lib.boltz_last_error(self._ctx).decode()))
+
+    def _walls(self, walls):
+        if walls is None:
+            return None
+        return ctypes.byref(walls._c())
+
+    def empty(self, fill=None):
+        import torch
+
+        t = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+        if fill is not None:
+            t.fill_(fill)
+        return t
+
+    # ---- hot path
+    def stream(self, h_in, h_out, walls=None, stream=None):
+        import torch
+
+        self._check(_lib.boltz_stream(self._ctx, _ptr(h_in, self.numel, torch.float32, "h_in"),
+                                      _ptr(h_out, self.numel, torch.float32, "h_out"), self._walls(walls),
+                                      _stream(stream)), "boltz_stream")
+
+    def collide(self, h_s, h_out, step, correction=True, defect=None, stream=None):
+        import torch
+
+        flags = 0 if correction else NO_CORRECTION
+        self._check(_lib.boltz_collide(self._ctx, _ptr(h_s, self.numel, torch.float32, "h_s"),
+                                       _ptr(h_out, self.numel, torch.float32, "h_out"), int(step), flags,
+                                       _ptr(defect, self.ncells * 5, torch.float64, "defect", True),
+                                       _stream(stream)), "boltz_collide")
+
+    def moments(self, h, mom, walls=None, lid_shear=None, stream=None):
+        import torch
+
+        self._check(_lib.boltz_moments(self._ctx, _ptr(h, self.numel, torch.float32, "h"), self._walls(walls),
+                                       _ptr(mom, self.ncells * 11, torch.float64, "mom"),
+                                       _ptr(lid_shear, 1, torch.float64, "lid_shear", True), _stream(stream)),
+                    "boltz_moments")
+
+    def step(self, h_in, h_out, walls, step, stream=None):
+        import torch
+
+        self._check(_lib.boltz_step(self._ctx, _ptr(h_in, self.numel, torch.float32, "h_in"),
+                                    _ptr(h_out, self.numel, torch.float32, "h_out"), self._walls(walls), int(step),
+                                    _stream(stream)), "boltz_step")
+
+    def step_adjoint(self, h_in, lam_out, lam_in, grad_walls, walls, step, stream=None):
+        import torch
+
+        self._check(_lib.boltz_step_adjoint(self._ctx, _ptr(h_in, self.numel, torch.float32, "h_in"),
+                                            _ptr(lam_out, self.numel, torch.float64, "lam_out"),
+                                            _ptr(lam_in, self.numel, torch.float64, "lam_in"),
+                                            _ptr(grad_walls, grad_walls.numel() if grad_walls is not None else 0,
+                                                 torch.float64, "grad_walls", True),
+                                            self._walls(walls), int(step), _stream(stream)), "boltz_step_adjoint")
+
+    # ---- test hooks
+    def debug_pairs(self, cell, step, m0, count, words=False):
+        idx = np.zeros((count, 4), dtype=np.int32)
+        q = np.zeros(count)
+        wd = np.zeros((count, 8), dtype=np.uint32) if words else None
+        self._check(_lib.boltz_debug_pairs(self._ctx, int(cell), int(step), int(m0), int(count), idx.ctypes.data,
+                                           q.ctypes.data, wd.ctypes.data if words else None), "boltz_debug_pairs")
+        return (idx, q, wd) if words else (idx, q)
+
+    def axis_thresholds(self, axis):
+        out = np.zeros(max(self.nv3[axis] - 1, 1), dtype=np.uint64)
+        self._check(_lib.boltz_axis_thresholds(self._ctx, int(axis), out.ctypes.data), "boltz_axis_thresholds")
+        return out[: self.nv3[axis] - 1]
+
+    def read_status(self, clear=True, stream=None):
+        v = ctypes.c_uint32(0)
+        self._check(_lib.boltz_read_status(self._ctx, ctypes.byref(v), 1 if clear else 0, _stream(stream)),
+                    "boltz_read_status")
+        return int(v.value)

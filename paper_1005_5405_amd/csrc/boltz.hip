@@ -1,0 +1,477 @@
+// boltz.hip -- host side of libboltz: problem validation, velocity-grid and
+// sampling tables, context memory, and the C ABI declared in include/boltz.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "boltz.h"
+#include "kernels.hpp"
+
+using namespace boltz;
+
+namespace {
+
+constexpr double kInvSqrtPi = 0.56418958354775628694807945156077;
+constexpr double kTwoPi = 6.28318530717958647692528676655901;
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct boltz_ctx {
+  boltz_problem p{};
+  int n[3]{};
+  double a[3]{}, dvel[3]{}, inv_cell[3]{};
+  std::vector<double> v[3], om[3];
+  std::vector<uint64_t> T[3];
+  std::vector<double> pphi[3], punif[3];
+  double dx = 0, dy = 0, dt = 0, K = 0, W = 0, qfac = 0;
+  int nv = 0;
+  int64_t ncells = 0;
+  int device = 0;
+  // device memory (one allocation)
+  void* dmem = nullptr;
+  size_t dbytes = 0;
+  Params P{};
+  size_t collide_lds = 0;
+  int collide_block = 256;
+  std::string err;
+};
+
+namespace {
+
+int fail(boltz_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return code;
+}
+
+int hip_fail(boltz_ctx* c, hipError_t e, const char* what) {
+  return fail(c, BOLTZ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WallArgs make_walls(const boltz_walls* w) {
+  WallArgs a{};
+  a.lid_u = w ? w->lid_u : 0.0;
+  const double t[4] = {w ? w->tau_left : 1.0, w ? w->tau_right : 1.0, w ? w->tau_bottom : 1.0,
+                       w ? w->tau_top : 1.0};
+  for (int k = 0; k < 4; ++k) {
+    a.tau[k] = t[k];
+    a.tfac[k] = std::pow(t[k], -1.5);
+  }
+  return a;
+}
+
+bool walls_ok(const boltz_walls* w) {
+  return w && w->tau_left > 0 && w->tau_right > 0 && w->tau_bottom > 0 && w->tau_top > 0 &&
+         std::isfinite(w->lid_u);
+}
+
+int block_for_collide(int nv) {
+  if (nv <= 2048) return 256;
+  if (nv <= 10648) return 512;  // up to 22^3: two workgroups per CU
+  return 1024;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* boltz_last_error(const boltz_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+void boltz_destroy(boltz_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->dmem) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->dmem);
+    (void)hipSetDevice(cur);
+  }
+  delete ctx;
+}
+
+int boltz_create(const boltz_problem* p, boltz_ctx** out) {
+  if (!p || !out) return fail(nullptr, BOLTZ_EINVAL, "boltz_create: null argument");
+  *out = nullptr;
+  const int min_cells = (p->bc == BOLTZ_BC_CAVITY) ? 2 : 1;
+  if (p->nx < min_cells || p->ny < min_cells || p->nx > 100000 || p->ny > 100000)
+    return fail(nullptr, BOLTZ_EINVAL, "boltz_create: nx, ny out of range (cavity needs >= 2 per axis)");
+  for (int k = 0; k < 3; ++k)
+    if (p->nv[k] < 1 || p->nv[k] > kMaxAxis || !(p->vmax[k] > 0.0) || !std::isfinite(p->vmax[k]))
+      return fail(nullptr, BOLTZ_EINVAL, "boltz_create: velocity grid out of range (1 <= nv <= 255, vmax > 0)");
+  if (!(p->delta > 0.0) || !(p->eps > 0.0) || (p->order != 1 && p->order != 2) ||
+      (p->bc != BOLTZ_BC_CAVITY && p->bc != BOLTZ_BC_PERIODIC) || p->n_pairs < 0 ||
+      p->n_pairs >= ((int64_t)1 << 31) || p->sample_group < 0 || p->mix16 > 16 ||
+      (!(p->dt > 0.0) && !(p->cfl > 0.0)))
+    return fail(nullptr, BOLTZ_EINVAL, "boltz_create: invalid scalar parameter");
+  const int64_t nvt = (int64_t)p->nv[0] * p->nv[1] * p->nv[2];
+  const int nsum = p->nv[0] + p->nv[1] + p->nv[2];
+  const size_t lds = CollideLDS::bytes((int)nvt, nsum);
+  if (lds + 20 * 16 * sizeof(double) + 64 > 160 * 1024)
+    return fail(nullptr, BOLTZ_EUNSUPPORTED,
+                "boltz_create: the per-cell h and Delta N tiles of this velocity grid exceed the 160 KB LDS");
+  if ((int64_t)p->nx * p->ny * nvt >= ((int64_t)1 << 40))
+    return fail(nullptr, BOLTZ_EINVAL, "boltz_create: phase-space grid too large");
+
+  boltz_ctx* c = new (std::nothrow) boltz_ctx;
+  if (!c) return fail(nullptr, BOLTZ_ENOMEM, "boltz_create: out of host memory");
+  c->p = *p;
+  c->nv = (int)nvt;
+  c->ncells = (int64_t)p->nx * p->ny;
+  // Sec. 3: uniform velocity cells on [-a, a], node at the cell centre;
+  // omega = dv exp(-v^2)/sqrt(pi) is the per-axis midpoint weight of Phi0.
+  for (int k = 0; k < 3; ++k) {
+    const int n = p->nv[k];
+    const double a = p->vmax[k];
+    c->n[k] = n;
+    c->a[k] = a;
+    c->dvel[k] = (2.0 * a) / n;
+    c->inv_cell[k] = (double)n / (2.0 * a);
+    c->v[k].resize(n);
+    c->om[k].resize(n);
+    c->T[k].assign(n, 0);
+    double osum = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double vi = ((double)(2 * i + 1 - n) * a) / n;
+      c->v[k][i] = vi;
+      c->om[k][i] = (c->dvel[k] * std::exp(-(vi * vi))) * kInvSqrtPi;
+      osum += c->om[k][i];
+    }
+    // node law of one axis: node i for a 32-bit word r in [T_i, T_{i+1}),
+    // T_i = round(2^32 sum_{l<i} omega_l / sum omega)
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (i > 0) c->T[k][i] = (uint64_t)std::nearbyint(std::ldexp(s / osum, 32));
+      s += c->om[k][i];
+    }
+    // realised probabilities: Maxwellian law (T_{i+1} - T_i) 2^-32; uniform
+    // law of floor(r n / 2^32): #{r : floor(r n 2^-32) = i} 2^-32
+    c->pphi[k].resize(n);
+    c->punif[k].resize(n);
+    for (int i = 0; i < n; ++i) {
+      const uint64_t hi = (i + 1 < n) ? c->T[k][i + 1] : ((uint64_t)1 << 32);
+      c->pphi[k][i] = std::ldexp((double)(hi - c->T[k][i]), -32);
+      const uint64_t lo_u = (((uint64_t)i << 32) + (uint64_t)n - 1) / (uint64_t)n;
+      const uint64_t hi_u = (((uint64_t)(i + 1) << 32) + (uint64_t)n - 1) / (uint64_t)n;
+      c->punif[k][i] = std::ldexp((double)(hi_u - lo_u), -32);
+    }
+  }
+  {
+    // W = (Om_x Om_y) Om_z, the discrete mass of Phi0
+    double Om[3];
+    for (int k = 0; k < 3; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < c->n[k]; ++i) s += c->om[k][i];
+      Om[k] = s;
+    }
+    c->W = (Om[0] * Om[1]) * Om[2];
+  }
+  c->dx = 1.0 / p->nx;
+  c->dy = 1.0 / p->ny;
+  const double vmx = std::fabs(c->v[0][0]), vmy = std::fabs(c->v[1][0]);
+  if (p->dt > 0.0) {
+    c->dt = p->dt;
+  } else {
+    const double rx = vmx / c->dx, ry = vmy / c->dy;
+    c->dt = p->cfl / (rx > ry ? rx : ry);
+  }
+  const double cx = vmx * c->dt / c->dx, cy = vmy * c->dt / c->dy;
+  const bool stable = (p->order == 1) ? (cx + cy <= 1.0 + 1e-12) : (cx <= 1.0 + 1e-12 && cy <= 1.0 + 1e-12);
+  if (!stable && !(p->flags & BOLTZ_ALLOW_UNSTABLE)) {
+    delete c;
+    return fail(nullptr, BOLTZ_EINVAL, "boltz_create: time step violates the Courant limit of the streaming scheme");
+  }
+  // K = pi n0 sigma^2 from lambda0 = mu0/p0 sqrt(2RT0) and the hard-sphere
+  // viscosity with the Chapman-Cowling factor 1.016034 (Sec. 5.1 scales).
+  c->K = 0.3125 * std::sqrt(kTwoPi) * 1.016034 * p->delta;
+  c->qfac = (p->n_pairs > 0) ? (c->dt * c->K) / (double)p->n_pairs : 0.0;
+
+  // ---- host images of the device tables
+  std::vector<double> vtab(3 * kMaxAxis, 0.0), omtab(3 * kMaxAxis, 0.0), pphi(3 * kMaxAxis, 0.0),
+      punif(3 * kMaxAxis, 0.0);
+  std::vector<uint32_t> tm1(3 * kMaxAxis, 0u);
+  std::vector<uint8_t> guide(3 * kGuideSize, 0);
+  std::vector<float> cour(2 * kMaxAxis, 0.f), cour2(2 * kMaxAxis, 0.f);
+  for (int k = 0; k < 3; ++k) {
+    const int n = c->n[k];
+    for (int i = 0; i < n; ++i) {
+      vtab[k * kMaxAxis + i] = c->v[k][i];
+      omtab[k * kMaxAxis + i] = c->om[k][i];
+      pphi[k * kMaxAxis + i] = c->pphi[k][i];
+      punif[k * kMaxAxis + i] = c->punif[k][i];
+      if (i > 0 && c->T[k][i] >= 1) tm1[k * kMaxAxis + i] = (uint32_t)(c->T[k][i] - 1);
+    }
+    for (int b = 0; b < kGuideSize; ++b) {
+      const uint64_t start = (uint64_t)b << (32 - kGuideBits);
+      int cnt = 0;
+      for (int i = 1; i < n; ++i)
+        if (c->T[k][i] <= start) ++cnt;
+      guide[k * kGuideSize + b] = (uint8_t)cnt;
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    const double dl = k == 0 ? c->dx : c->dy;
+    for (int i = 0; i < c->n[k]; ++i) {
+      const double C = std::fabs(c->v[k][i]) * c->dt / dl;
+      cour[k * kMaxAxis + i] = (float)C;
+      cour2[k * kMaxAxis + i] = (float)(0.5 * C * (1.0 - C));
+    }
+  }
+  // ---- device memory: tables + scratch in one allocation
+  const int nfaces = 2 * (p->nx + p->ny);
+  size_t off = 0;
+  const size_t o_v = off; off = align256(off + vtab.size() * 8);
+  const size_t o_om = off; off = align256(off + omtab.size() * 8);
+  const size_t o_pphi = off; off = align256(off + pphi.size() * 8);
+  const size_t o_punif = off; off = align256(off + punif.size() * 8);
+  const size_t o_tm1 = off; off = align256(off + tm1.size() * 4);
+  const size_t o_guide = off; off = align256(off + guide.size());
+  const size_t o_cour = off; off = align256(off + cour.size() * 4);
+  const size_t o_cour2 = off; off = align256(off + cour2.size() * 4);
+  const size_t o_nw = off; off = align256(off + (size_t)nfaces * 8);
+  const size_t o_ratio = off; off = align256(off + (size_t)4 * c->nv * 8);
+  const size_t o_dpart = off; off = align256(off + (size_t)p->nx * 8);
+  const size_t o_status = off; off = align256(off + 4);
+  (void)hipGetDevice(&c->device);
+  hipError_t e = hipMalloc(&c->dmem, off);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, BOLTZ_ENOMEM, std::string("boltz_create: hipMalloc: ") + hipGetErrorString(e));
+  }
+  c->dbytes = off;
+  unsigned char* base = static_cast<unsigned char*>(c->dmem);
+  struct Cp { size_t o; const void* src; size_t n; } cps[] = {
+      {o_v, vtab.data(), vtab.size() * 8}, {o_om, omtab.data(), omtab.size() * 8},
+      {o_pphi, pphi.data(), pphi.size() * 8}, {o_punif, punif.data(), punif.size() * 8},
+      {o_tm1, tm1.data(), tm1.size() * 4}, {o_guide, guide.data(), guide.size()},
+      {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4}};
+  for (const Cp& cp : cps) {
+    e = hipMemcpy(base + cp.o, cp.src, cp.n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      boltz_destroy(c);
+      return fail(nullptr, BOLTZ_EHIP, std::string("boltz_create: hipMemcpy: ") + hipGetErrorString(e));
+    }
+  }
+  e = hipMemset(base + o_nw, 0, o_status + 4 - o_nw);
+  if (e != hipSuccess) {
+    boltz_destroy(c);
+    return fail(nullptr, BOLTZ_EHIP, std::string("boltz_create: hipMemset: ") + hipGetErrorString(e));
+  }
+  Params& P = c->P;
+  P.nx = p->nx;
+  P.ny = p->ny;
+  P.nv = c->nv;
+  for (int k = 0; k < 3; ++k) {
+    P.n[k] = c->n[k];
+    P.a[k] = c->a[k];
+    P.inv_cell[k] = c->inv_cell[k];
+  }
+  P.order = p->order;
+  P.bc = p->bc;
+  P.n_pairs = p->n_pairs;
+  P.sample_group = p->sample_group;
+  P.key0 = (uint32_t)p->seed;
+  P.key1 = (uint32_t)(p->seed >> 32);
+  P.cavity = p->cavity_id;
+  P.mix16 = p->mix16;
+  P.beta = p->mix16 / 16.0;
+  P.dt = c->dt;
+  P.dx = c->dx;
+  P.dy = c->dy;
+  P.eps = p->eps;
+  P.inv_eps = 1.0 / p->eps;
+  P.qfac = c->qfac;
+  P.vtab = reinterpret_cast<const double*>(base + o_v);
+  P.omtab = reinterpret_cast<const double*>(base + o_om);
+  P.pphi = reinterpret_cast<const double*>(base + o_pphi);
+  P.punif = reinterpret_cast<const double*>(base + o_punif);
+  P.tm1 = reinterpret_cast<const uint32_t*>(base + o_tm1);
+  P.guide = reinterpret_cast<const uint8_t*>(base + o_guide);
+  P.cour = reinterpret_cast<const float*>(base + o_cour);
+  P.cour2 = reinterpret_cast<const float*>(base + o_cour2);
+  P.nw = reinterpret_cast<double*>(base + o_nw);
+  P.ratio = reinterpret_cast<double*>(base + o_ratio);
+  P.dpart = reinterpret_cast<double*>(base + o_dpart);
+  P.status = reinterpret_cast<uint32_t*>(base + o_status);
+  c->collide_lds = lds;
+  c->collide_block = block_for_collide(c->nv);
+  hipError_t ea = hipSuccess;
+  switch (c->collide_block) {
+    case 256: ea = hipFuncSetAttribute((const void*)collide_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+    case 512: ea = hipFuncSetAttribute((const void*)collide_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+    default: ea = hipFuncSetAttribute((const void*)collide_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+  }
+  if (ea != hipSuccess) {
+    boltz_destroy(c);
+    return fail(nullptr, BOLTZ_EHIP, std::string("boltz_create: hipFuncSetAttribute: ") + hipGetErrorString(ea));
+  }
+  *out = c;
+  return BOLTZ_OK;
+}
+
+int boltz_query(const boltz_ctx* c, boltz_info* out) {
+  if (!c || !out) return BOLTZ_EINVAL;
+  out->ncells = c->ncells;
+  out->nv = c->nv;
+  out->dt = c->dt;
+  out->K = c->K;
+  out->W = c->W;
+  out->qfac = c->qfac;
+  out->device_bytes = (int64_t)c->dbytes;
+  return BOLTZ_OK;
+}
+
+int boltz_axis_thresholds(const boltz_ctx* c, int axis, uint64_t* out) {
+  if (!c || !out || axis < 0 || axis > 2) return BOLTZ_EINVAL;
+  for (int i = 1; i < c->n[axis]; ++i) out[i - 1] = c->T[axis][i];
+  return BOLTZ_OK;
+}
+
+static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, hipStream_t st) {
+  const int nfaces = 2 * (c->p.nx + c->p.ny);
+  hipLaunchKernelGGL(wall_kernel, dim3(nfaces), dim3(256), 0, st, c->P, W, h);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "wall_kernel launch");
+}
+
+static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_t st) {
+  const int tiles_x = (c->p.nx + kTX - 1) / kTX, tiles_y = (c->p.ny + kTY - 1) / kTY;
+  const int nchunks = (c->nv + kJ - 1) / kJ;
+  const long long total = (long long)tiles_x * tiles_y * nchunks;
+  const int per_xcd = (int)((total + 7) / 8);
+  const dim3 grid((unsigned)(8 * (long long)per_xcd));
+  if (c->p.order == 2)
+    hipLaunchKernelGGL(stream_kernel<2>, grid, dim3(kStreamBlock), 0, st, c->P, hin, hout, tiles_x, tiles_y,
+                       nchunks, per_xcd);
+  else
+    hipLaunchKernelGGL(stream_kernel<1>, grid, dim3(kStreamBlock), 0, st, c->P, hin, hout, tiles_x, tiles_y,
+                       nchunks, per_xcd);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream_kernel launch");
+}
+
+static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
+                          double* defect, hipStream_t st) {
+  const dim3 grid((unsigned)c->ncells);
+  const uint32_t s32 = (uint32_t)step;
+  switch (c->collide_block) {
+    case 256:
+      hipLaunchKernelGGL(collide_kernel<256>, grid, dim3(256), c->collide_lds, st, c->P, hs, hout, s32, flags, defect);
+      break;
+    case 512:
+      hipLaunchKernelGGL(collide_kernel<512>, grid, dim3(512), c->collide_lds, st, c->P, hs, hout, s32, flags, defect);
+      break;
+    default:
+      hipLaunchKernelGGL(collide_kernel<1024>, grid, dim3(1024), c->collide_lds, st, c->P, hs, hout, s32, flags, defect);
+      break;
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "collide_kernel launch");
+}
+
+static bool overlap(const void* a, const void* b, size_t n) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + n && y < x + n;
+}
+
+int boltz_stream(boltz_ctx* c, const float* h_in, float* h_out, const boltz_walls* walls, void* stream) {
+  if (!c) return BOLTZ_EINVAL;
+  if (!h_in || !h_out) return fail(c, BOLTZ_EINVAL, "boltz_stream: null buffer");
+  const size_t bytes = (size_t)c->ncells * c->nv * sizeof(float);
+  if (overlap(h_in, h_out, bytes)) return fail(c, BOLTZ_EINVAL, "boltz_stream: h_in and h_out overlap");
+  const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
+  if (cavity && !walls_ok(walls)) return fail(c, BOLTZ_EINVAL, "boltz_stream: cavity needs valid walls");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = BOLTZ_OK;
+  if (cavity) rc = launch_walls(c, h_in, make_walls(walls), st);
+  if (rc == BOLTZ_OK) rc = launch_stream(c, h_in, h_out, st);
+  return rc;
+}
+
+int boltz_collide(boltz_ctx* c, const float* h_s, float* h_out, int64_t step, uint32_t flags, double* defect,
+                  void* stream) {
+  if (!c) return BOLTZ_EINVAL;
+  if (!h_s || !h_out) return fail(c, BOLTZ_EINVAL, "boltz_collide: null buffer");
+  const size_t bytes = (size_t)c->ncells * c->nv * sizeof(float);
+  if (h_s != h_out && overlap(h_s, h_out, bytes))
+    return fail(c, BOLTZ_EINVAL, "boltz_collide: h_s and h_out partially overlap");
+  if (flags & ~(uint32_t)BOLTZ_NO_CORRECTION) return fail(c, BOLTZ_EINVAL, "boltz_collide: unknown flag");
+  return launch_collide(c, h_s, h_out, step, flags, defect, static_cast<hipStream_t>(stream));
+}
+
+int boltz_step(boltz_ctx* c, const float* h_in, float* h_out, const boltz_walls* walls, int64_t step,
+               void* stream) {
+  const int rc = boltz_stream(c, h_in, h_out, walls, stream);
+  if (rc != BOLTZ_OK) return rc;
+  return launch_collide(c, h_out, h_out, step, 0u, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int boltz_moments(boltz_ctx* c, const float* h, const boltz_walls* walls, double* mom, double* lid_shear,
+                  void* stream) {
+  if (!c) return BOLTZ_EINVAL;
+  if (!h || !mom) return fail(c, BOLTZ_EINVAL, "boltz_moments: null buffer");
+  if (lid_shear && (c->p.bc != BOLTZ_BC_CAVITY || !walls_ok(walls)))
+    return fail(c, BOLTZ_EINVAL, "boltz_moments: lid shear needs a cavity and valid walls");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const WallArgs W = make_walls(walls);
+  hipLaunchKernelGGL(moments_kernel, dim3((unsigned)c->ncells), dim3(256), 0, st, c->P, W, h, mom,
+                     lid_shear ? 1 : 0);
+  if (lid_shear) hipLaunchKernelGGL(lid_reduce_kernel, dim3(1), dim3(64), 0, st, c->P, lid_shear);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "moments_kernel launch");
+}
+
+int boltz_step_adjoint(boltz_ctx* c, const float*, const double*, double*, double*, const boltz_walls*, int64_t,
+                       void*) {
+  if (!c) return BOLTZ_EINVAL;
+  return fail(c, BOLTZ_EUNSUPPORTED, "boltz_step_adjoint: not implemented in this build");
+}
+
+int boltz_debug_pairs(boltz_ctx* c, int64_t cell, int64_t step, int64_t m0, int64_t count, int32_t* idx4,
+                      double* q, uint32_t* words) {
+  if (!c) return BOLTZ_EINVAL;
+  if (cell < 0 || cell >= c->ncells || m0 < 0 || count < 0 || m0 + count > ((int64_t)1 << 31) || !idx4 || !q)
+    return fail(c, BOLTZ_EINVAL, "boltz_debug_pairs: invalid argument");
+  if (count == 0) return BOLTZ_OK;
+  const size_t bi = (size_t)count * 4 * sizeof(int32_t), bq = (size_t)count * sizeof(double),
+               bw = words ? (size_t)count * 8 * sizeof(uint32_t) : 0;
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, bi + bq + bw + 64);
+  if (e != hipSuccess) return hip_fail(c, e, "boltz_debug_pairs: hipMalloc");
+  unsigned char* b = static_cast<unsigned char*>(d);
+  int32_t* d_idx = reinterpret_cast<int32_t*>(b);
+  double* d_q = reinterpret_cast<double*>(b + ((bi + 7) & ~(size_t)7));
+  uint32_t* d_w = words ? reinterpret_cast<uint32_t*>(b + ((bi + 7) & ~(size_t)7) + bq) : nullptr;
+  const int nsum = c->n[0] + c->n[1] + c->n[2];
+  const size_t lds = CollideLDS::tables_bytes(nsum);
+  const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(debug_pairs_kernel, dim3(blocks), dim3(256), lds, 0, c->P, cell, (uint32_t)step, m0, count,
+                     d_idx, d_q, d_w);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(idx4, d_idx, bi, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(q, d_q, bq, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && words) e = hipMemcpy(words, d_w, bw, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "boltz_debug_pairs");
+}
+
+int boltz_read_status(boltz_ctx* c, uint32_t* out, int clear, void* stream) {
+  if (!c || !out) return BOLTZ_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipMemcpy(out, c->P.status, 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && clear) e = hipMemset(c->P.status, 0, 4);
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "boltz_read_status");
+}
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars (the benchmark spec tolerances): node indices and Philox words bit-exact; h
+within a relative 1e-5 per step and 1e-4 after 100 steps, measured as
+max|h_gpu - h_ref| / max|h_ref|; the same bar on the Maxwellian-weighted
+error max_j w_j |dh_j| / max_j w_j |h_ref,j|, which is not dominated by the
+rarely visited tail nodes.  Moments are FP64 sums of the same FP32 data on
+both sides.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1005_5405_amd as pkg
+
+    pkg.load_library()
+    return pkg
+
+
+def _pair(lib, oracle_mod, **kw):
+    return lib.Boltz(**kw), oracle_mod.Oracle(**kw)
+
+
+def _dev(torch_mod, a):
+    return torch_mod.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _errs(o, got, ref):
+    d = np.abs(got - ref)
+    rel = d.max() / max(np.abs(ref).max(), 1e-300)
+    w = o.node_weights()
+    wrel = (d * w).max() / max((np.abs(ref) * w).max(), 1e-300)
+    return rel, wrel
+
+
+WALLS = dict(lid_u=0.1, tau_left=1.05, tau_right=0.97, tau_bottom=1.02, tau_top=1.0)
+
+
+def test_thresholds_bitwise(lib, oracle_mod, torch_mod):
+    for nv, a in [((12, 12, 12), 4.5), ((20, 20, 20), 5.0), ((24, 24, 24), 5.0), ((7, 5, 9), (3.0, 2.5, 3.5))]:
+        _say("thresholds", nv, a)
+        g, o = _pair(lib, oracle_mod, nx=2, ny=2, nv=nv, vmax=a, delta=1.0, eps=0.1, n_pairs=10)
+        for k in range(3):
+            np.testing.assert_array_equal(g.axis_thresholds(k), o.thresholds[k])
+        assert g.dt == o.dt and g.K == o.K and g.W == o.W and g.qfac == o.qfac
+
+
+@pytest.mark.parametrize("grid", [((12, 12, 12), 4.5), ((20, 20, 20), 5.0), ((24, 24, 24), 5.0),
+                                  ((7, 5, 9), (3.0, 2.5, 3.5)), ((6, 6, 6), 3.0)])
+@pytest.mark.parametrize("G,mix16", [(1, 0), (1, 4), (0, 4), (5, 16)])
+def test_pairs_bit_exact(lib, oracle_mod, torch_mod, grid, G, mix16):
+    nv, a = grid
+    g, o = _pair(lib, oracle_mod, nx=7, ny=6, nv=nv, vmax=a, delta=3.0, eps=0.1, n_pairs=50000,
+                 sample_group=G, seed=0x1234567890ABCDEF, cavity_id=3, mix16=mix16)
+    for cell, step, m0, count in [(0, 0, 0, 40000), (41, 123456789, 7, 20000), (17, 5, 2**31 - 5000, 5000)]:
+        _say("pairs", nv, "G", G, "mix16", mix16, "cell", cell, "step", step, "m0", m0)
+        gi, gq, gw = g.debug_pairs(cell, step, m0, count, words=True)
+        oi, oq, ow = o.debug_pairs(cell, step, m0, count, words=True)
+        np.testing.assert_array_equal(gw, ow)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_array_equal(gq, oq)
+
+
+STREAM_CASES = [
+    dict(order=2, bc=0, nx=16, ny=16, nv=(12, 12, 12), vmax=4.5),
+    dict(order=1, bc=0, nx=16, ny=16, nv=(12, 12, 12), vmax=4.5),
+    dict(order=2, bc=0, nx=13, ny=11, nv=(8, 6, 5), vmax=(3.5, 3.0, 2.5)),   # ragged tiles, nv % 32 != 0
+    dict(order=1, bc=0, nx=9, ny=3, nv=(5, 7, 3), vmax=(3.0, 3.5, 2.0)),     # odd grids, v = 0 nodes
+    dict(order=2, bc=1, nx=10, ny=9, nv=(6, 6, 6), vmax=3.0),
+    dict(order=1, bc=1, nx=5, ny=12, nv=(6, 4, 4), vmax=3.0),
+    dict(order=2, bc=0, nx=2, ny=2, nv=(4, 4, 4), vmax=2.5),                 # smallest cavity
+]
+
+
+@pytest.mark.parametrize("case", range(len(STREAM_CASES)))
+def test_stream_parity(lib, oracle_mod, torch_mod, case):
+    from paper_1005_5405_amd import inputs
+
+    kw = dict(STREAM_CASES[case], delta=5.0, eps=0.1, n_pairs=100)
+    _say("stream", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    h = inputs.random_field(o.shape, seed=10 + case, scale=0.5).astype(np.float32).astype(np.float64)
+    walls_o = oracle_mod.Walls(**WALLS) if kw["bc"] == 0 else None
+    walls_g = lib.Walls(**WALLS) if kw["bc"] == 0 else None
+    ref = o.stream(h, walls_o)
+    hin, hout = _dev(torch_mod, h), g.empty()
+    g.stream(hin, hout, walls_g)
+    torch_mod.cuda.synchronize()
+    rel, wrel = _errs(o, _host(hout), ref)
+    assert rel <= 1e-5 and wrel <= 1e-5, (rel, wrel)
+    # a uniform state and h = 0 with walls at rest are reproduced exactly
+    for c in (0.0, 0.25):
+        hu = np.full(o.shape, c)
+        g.stream(_dev(torch_mod, hu), hout, lib.Walls() if kw["bc"] == 0 else None)
+        torch_mod.cuda.synchronize()
+        assert np.abs(_host(hout) - c).max() <= (0.0 if c == 0.0 else 2e-6)
+
+
+COLLIDE_CASES = [
+    dict(nx=5, ny=4, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=2000),
+    dict(nx=3, ny=3, nv=(20, 20, 20), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, mix16=4),
+    dict(nx=2, ny=2, nv=(24, 24, 24), vmax=5.0, delta=100.0, eps=0.05, n_pairs=50000, mix16=4),
+    dict(nx=3, ny=2, nv=(5, 7, 3), vmax=(3.0, 3.5, 2.0), delta=2.0, eps=0.3, n_pairs=3000),  # nv % 4 != 0
+    dict(nx=2, ny=2, nv=(26, 26, 26), vmax=5.0, delta=1.0, eps=0.1, n_pairs=5000, mix16=16),  # largest LDS tile
+    dict(nx=4, ny=4, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=2000, sample_group=0),
+    dict(nx=4, ny=4, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(COLLIDE_CASES)))
+@pytest.mark.parametrize("correction", [True, False])
+def test_collide_parity(lib, oracle_mod, torch_mod, case, correction):
+    from paper_1005_5405_amd import inputs
+
+    kw = dict(COLLIDE_CASES[case], bc=1)
+    _say("collide", kw, "correction", correction)
+    g, o = _pair(lib, oracle_mod, **kw)
+    V = o.node_velocities()
+    h = np.stack([inputs.velocity_polynomial(V, seed=100 + c) for c in range(o.nx * o.ny)]).reshape(o.shape)
+    h = (h + inputs.random_field(o.shape, seed=7, scale=0.05)).astype(np.float32).astype(np.float64)
+    ref = o.collide(h, 42, correction=correction)
+    hs, hout = _dev(torch_mod, h), g.empty()
+    defect = torch_mod.zeros(o.nx * o.ny * 5, dtype=torch_mod.float64, device="cuda")
+    g.collide(hs, hout, 42, correction=correction, defect=defect)
+    torch_mod.cuda.synchronize()
+    got = _host(hout)
+    rel, wrel = _errs(o, got, ref)
+    assert rel <= 1e-5 and wrel <= 1e-5, (rel, wrel)
+    if kw["n_pairs"] == 0:
+        np.testing.assert_array_equal(got, h)
+    # in-place call gives the same result
+    g.collide(hs, hs, 42, correction=correction)
+    torch_mod.cuda.synchronize()
+    assert np.abs(_host(hs) - got).max() <= 1e-6 * np.abs(got).max()
+    # the device-reported defect is that of the stored FP32 values
+    w = o.node_weights()
+    psi = np.stack([np.ones(len(w)), V[:, 0], V[:, 1], V[:, 2], (V**2).sum(1)], 1)
+    d_host = o.eps * np.einsum("j,jk,ycj->yck", w, psi, got - h).reshape(-1, 5)
+    d_dev = defect.cpu().numpy().reshape(-1, 5)
+    scale = o.eps * np.einsum("j,jk,ycj->yck", w, np.abs(psi), np.abs(got) + np.abs(h)).reshape(-1, 5)
+    assert np.all(np.abs(d_dev - d_host) <= 1e-12 * scale)
+    if correction:
+        # conservation up to FP32 storage of h
+        assert np.all(np.abs(d_dev) <= 1e-6 * scale)
+    assert g.read_status() == 0
+
+
+def test_equilibrium_is_bitwise_fixed_point(lib, oracle_mod, torch_mod):
+    _say("equilibrium")
+    g = lib.Boltz(nx=16, ny=16, nv=12, vmax=4.5, delta=10.0, eps=0.1, n_pairs=2000)
+    h0, h1 = g.empty(0.0), g.empty(1.0)
+    for n in range(3):
+        g.step(h0, h1, lib.Walls(), n)
+        h0, h1 = h1, h0
+    torch_mod.cuda.synchronize()
+    assert torch_mod.count_nonzero(h0).item() == 0
+
+
+def test_non_spd_correction_is_reported(lib, oracle_mod, torch_mod):
+    _say("non-spd")
+    g = lib.Boltz(nx=2, ny=2, nv=6, vmax=3.0, delta=1.0, eps=0.1, n_pairs=100, bc=1)
+    h = g.empty(-50.0)  # F = 1 + eps h = -4 < 0: the correction matrix is negative definite
+    out = g.empty()
+    g.read_status(clear=True)
+    g.collide(h, out, 0)
+    assert g.read_status(clear=True) & 1
+    ref = g.empty()
+    g.collide(h, ref, 0, correction=False)
+    torch_mod.cuda.synchronize()
+    # the failed correction leaves the raw update (LDS atomics add in any order)
+    assert torch_mod.allclose(out, ref, rtol=1e-6, atol=0)
+    assert g.read_status() == 0
+
+
+@pytest.mark.parametrize("order", [2, 1])
+def test_moments_and_lid_shear_parity(lib, oracle_mod, torch_mod, order):
+    from paper_1005_5405_amd import inputs
+
+    _say("moments", order)
+    g, o = _pair(lib, oracle_mod, nx=12, ny=10, nv=12, vmax=4.5, delta=10.0, eps=0.1, n_pairs=100, order=order)
+    h = inputs.random_field(o.shape, seed=3, scale=0.5).astype(np.float32).astype(np.float64)
+    mom_ref, D_ref = o.moments(h, oracle_mod.Walls(**WALLS), lid_shear=True)
+    mom = torch_mod.zeros(o.nx * o.ny * 11, dtype=torch_mod.float64, device="cuda")
+    D = torch_mod.zeros(1, dtype=torch_mod.float64, device="cuda")
+    g.moments(_dev(torch_mod, h), mom, lib.Walls(**WALLS), D)
+    got = mom.cpu().numpy().reshape(mom_ref.shape)
+    scale = np.abs(mom_ref).reshape(-1, 11).max(0)
+    assert np.all(np.abs(got - mom_ref).reshape(-1, 11) <= 1e-10 * scale)
+    assert abs(D.item() - D_ref) <= 1e-10 * max(abs(D_ref), 1e-3)
+
+
+def test_cavity_step_parity_1_and_100_steps(lib, oracle_mod, torch_mod):
+    from paper_1005_5405_amd import CAVITY_16, inputs
+
+    pre = CAVITY_16
+    kw = pre.problem()
+    g, o = _pair(lib, oracle_mod, **kw)
+    walls_o, walls_g = oracle_mod.Walls(lid_u=pre.lid_u), lib.Walls(lid_u=pre.lid_u)
+    # one step from a random state
+    _say("step 1", kw)
+    h = inputs.random_field(o.shape, seed=5, scale=0.3).astype(np.float32).astype(np.float64)
+    ref = o.step(h, walls_o, 7)
+    hin, hout = _dev(torch_mod, h), g.empty()
+    g.step(hin, hout, walls_g, 7)
+    torch_mod.cuda.synchronize()
+    rel, wrel = _errs(o, _host(hout), ref)
+    assert rel <= 1e-5 and wrel <= 1e-5, (rel, wrel)
+    # 100 steps of the driven cavity from rest, run independently on both sides
+    _say("step 100", kw)
+    href = np.zeros(o.shape)
+    a, b = g.empty(0.0), g.empty()
+    for n in range(100):
+        href = o.step(href, walls_o, n)
+        g.step(a, b, walls_g, n)
+        a, b = b, a
+    torch_mod.cuda.synchronize()
+    rel, wrel = _errs(o, _host(a), href)
+    assert rel <= 1e-4 and wrel <= 1e-4, (rel, wrel)
+    mom_ref, D_ref = o.moments(href, walls_o, lid_shear=True)
+    mom = torch_mod.zeros(o.nx * o.ny * 11, dtype=torch_mod.float64, device="cuda")
+    D = torch_mod.zeros(1, dtype=torch_mod.float64, device="cuda")
+    g.moments(a, mom, walls_g, D)
+    got = mom.cpu().numpy().reshape(mom_ref.shape)
+    scale = np.abs(mom_ref).reshape(-1, 11).max(0)
+    assert np.all(np.abs(got - mom_ref).reshape(-1, 11) <= 1e-4 * scale)
+    assert abs(D.item() - D_ref) <= 1e-4 * abs(D_ref)
+    assert g.read_status() == 0
+
+
+@pytest.mark.parametrize("which", ["cavity64", "cavity200"])
+def test_full_size_sampled_parity(lib, oracle_mod, torch_mod, which):
+    """Full-size grids in the launch configuration the benchmark times:
+    streaming checked on every node for the 64x64 cavity, collision on sampled
+    cells that the oracle computes one by one (both sizes)."""
+    from paper_1005_5405_amd import PRESETS, inputs
+
+    pre = PRESETS[which]
+    kw = pre.problem()
+    _say("full size", which)
+    g, o = _pair(lib, oracle_mod, **kw)
+    walls_o, walls_g = oracle_mod.Walls(lid_u=0.1), lib.Walls(lid_u=0.1)
+    rng = np.random.default_rng(1)
+    # input: smooth in space times a velocity polynomial, built on the device
+    h32 = inputs.random_field((o.ny, o.nx, 1), seed=2, scale=0.3).astype(np.float32)
+    prof = inputs.velocity_polynomial(o.node_velocities(), seed=3, scale=0.1).astype(np.float32)
+    hin = (torch_mod.from_numpy(h32).cuda() * torch_mod.from_numpy(prof).cuda().view(1, 1, -1)).contiguous()
+    hs = g.empty()
+    g.stream(hin, hs, walls_g)
+    hout = g.empty()
+    g.collide(hs, hout, 9)
+    torch_mod.cuda.synchronize()
+    if which == "cavity64":
+        ref_s = o.stream(hin.cpu().numpy().astype(np.float64), walls_o)
+        rel, wrel = _errs(o, _host(hs), ref_s)
+        assert rel <= 1e-5 and wrel <= 1e-5, (rel, wrel)
+        del ref_s
+    cells = np.unique(np.concatenate([[0, o.nx - 1, (o.ny - 1) * o.nx, o.nx * o.ny - 1],
+                                      rng.integers(0, o.nx * o.ny, 6)]))
+    idx = torch_mod.from_numpy(cells).cuda()
+    hs_c = hs.view(-1, o.nv)[idx].cpu().numpy().astype(np.float64)
+    got_c = hout.view(-1, o.nv)[idx].cpu().numpy().astype(np.float64)
+    ref_c = o.collide_cells(hs_c, 9, cells)
+    w = o.node_weights()
+    for k in range(len(cells)):
+        d = np.abs(got_c[k] - ref_c[k])
+        assert d.max() <= 1e-5 * np.abs(ref_c[k]).max(), (which, cells[k])
+        assert (d * w).max() <= 1e-5 * (np.abs(ref_c[k]) * w).max(), (which, cells[k])
+    assert g.read_status() == 0

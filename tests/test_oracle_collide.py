@@ -79,8 +79,8 @@ def _enumerate_mean_dN(n, a, h, eps, dt, delta, M):
     return dt * K * W * W * E
 
 
-def _mc_dN(oracle_mod, n, a, h, eps, delta, nt, nsteps):
-    o = oracle_mod.Oracle(1, 1, n, a, delta, eps, nt, bc=oracle_mod.BC_PERIODIC)
+def _mc_dN(oracle_mod, n, a, h, eps, delta, nt, nsteps, mix16=0):
+    o = oracle_mod.Oracle(1, 1, n, a, delta, eps, nt, bc=oracle_mod.BC_PERIODIC, mix16=mix16)
     samples = []
     for st in range(nsteps):
         _, dN, _ = o.collide(h.reshape(1, 1, -1), st, correction=False, want_dN=True)
@@ -99,11 +99,13 @@ def _h_test(n, a, kind, eps):
     return (F - 1) / eps
 
 
-@pytest.mark.parametrize("kind", ["nonequilibrium", "maxwellian"])
-def test_mc_mean_matches_enumeration_6cubed(oracle_mod, kind):
+@pytest.mark.parametrize("kind,mix16", [("nonequilibrium", 0), ("maxwellian", 0), ("nonequilibrium", 4)])
+def test_mc_mean_matches_enumeration_6cubed(oracle_mod, kind, mix16):
+    # the mixture of the Maxwellian and uniform node laws (mix16 > 0) is an
+    # importance-sampling estimate of the same integral: same expectation
     n, a, eps, delta = 6, 3.0, 0.5, 1.0
     h = _h_test(n, a, kind, eps)
-    o, S = _mc_dN(oracle_mod, n, a, h, eps, delta, nt=20000, nsteps=100)
+    o, S = _mc_dN(oracle_mod, n, a, h, eps, delta, nt=20000, nsteps=100, mix16=mix16)
     mean = S.mean(0)
     se = S.std(0, ddof=1) / np.sqrt(S.shape[0])
     E = _enumerate_mean_dN(n, a, h, eps, o.dt, delta, M=256)

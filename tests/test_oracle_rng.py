@@ -140,6 +140,53 @@ def test_sampled_nodes_follow_law(oracle_mod):
     assert ((tab[m] - e[m]) ** 2 / e[m]).sum() / m.sum() < 2.0
 
 
+def _laws(o, k):
+    n = o.nv3[k]
+    T = np.concatenate([[0], o.thresholds[k].astype(np.float64), [2.0**32]])
+    pm = np.diff(T) / 2.0**32
+    edges = np.array([-(-(i << 32) // n) for i in range(n + 1)], dtype=np.float64)
+    pu = np.diff(edges) / 2.0**32
+    return pm, pu
+
+
+@pytest.mark.parametrize("mix16", [4, 8, 16])
+def test_mixture_law_marginals(oracle_mod, mix16):
+    n = 10
+    o = oracle_mod.Oracle(2, 2, n, 4.0, 1.0, 0.1, 1, bc=oracle_mod.BC_PERIODIC, mix16=mix16)
+    N = 200000
+    idx, _, wd = o.debug_pairs(1, 9, 0, N, words=True)
+    beta = mix16 / 16.0
+    # the component choices are the low nibbles of the eighth word
+    assert abs((wd[:, 7] & 15 < mix16).mean() - beta) < 4 * np.sqrt(beta * (1 - beta) / N) + 1e-12
+    for col in (0, 1):
+        j = idx[:, col]
+        for k, c in enumerate([j // (n * n), (j // n) % n, j % n]):
+            pm, pu = _laws(o, k)
+            e = N * ((1 - beta) * pm + beta * pu)
+            cnt = np.bincount(c, minlength=n)
+            m = e > 5
+            assert ((cnt[m] - e[m]) ** 2 / e[m]).sum() / m.sum() < 3.0
+
+
+def test_mixture_weight_is_w_over_p(oracle_mod):
+    o = oracle_mod.Oracle(2, 2, (9, 8, 7), (4.0, 3.5, 3.0), 2.0, 0.1, 50, bc=oracle_mod.BC_PERIODIC, mix16=4)
+    idx, q, vel = o.debug_pairs(2, 4, 0, 20000, velocities=True)
+    kept = idx[:, 2] >= 0
+    n = o.nv3
+    laws = [_laws(o, k) for k in range(3)]
+
+    def ratio(j):
+        i3 = [j // (n[1] * n[2]), (j // n[2]) % n[1], j % n[2]]
+        w = np.prod([o.omega[k][i3[k]] for k in range(3)], axis=0)
+        pm = np.prod([laws[k][0][i3[k]] for k in range(3)], axis=0)
+        pu = np.prod([laws[k][1][i3[k]] for k in range(3)], axis=0)
+        return w / (0.75 * pm + 0.25 * pu)
+
+    alpha = np.sqrt(((vel[:, 2] - vel[:, 0]) ** 2).sum(1))
+    expect = o.dt * o.K * alpha / 50 * ratio(idx[:, 0]) * ratio(idx[:, 1])
+    np.testing.assert_allclose(q[kept], expect[kept], rtol=1e-12, atol=1e-13 * q.max())
+
+
 def test_pair_kinematics_conserve_momentum_energy(oracle_mod):
     o = oracle_mod.Oracle(3, 2, (12, 10, 8), (4.5, 4.0, 3.5), 1.0, 0.1, 100, bc=oracle_mod.BC_PERIODIC)
     idx, q, vel = o.debug_pairs(4, 7, 1000, 20000, velocities=True)
@@ -168,10 +215,13 @@ def test_pair_kinematics_conserve_momentum_energy(oracle_mod):
     if out.any():
         outside = (np.abs(vs[out]) > -lo).any(1) | (np.abs(v1s[out]) > -lo).any(1)
         assert outside.all()
-    # weight q = dt K W^2 |v_r . k| / N_t with |v_r . k| = |v* - v_a|
+    # weight q = dt K |v_r . k| (w_a/p_a)(w_b/p_b) / N_t with |v_r . k| = |v* - v_a|;
+    # for the Maxwellian law w/p = W up to the 2^-32 quantisation of p
     K = (5.0 / 16.0) * np.sqrt(2 * np.pi) * 1.016034 * 1.0
     np.testing.assert_allclose(o.K, K, rtol=1e-15)
     alpha = np.sqrt(((vs - va) ** 2).sum(1))
-    np.testing.assert_allclose(q[kept], o.dt * K * o.W**2 * alpha[kept] / 100, rtol=1e-13,
-                               atol=1e-13 * q.max())
+    live = kept & (alpha > 1e-3)  # a = b gives v_r = 0 and q = 0
+    ratio = q[live] / (o.dt * K * alpha[live] / 100)
+    bulk = (np.abs(va[live]).max(1) < 2.5) & (np.abs(vb[live]).max(1) < 2.5)
+    np.testing.assert_allclose(ratio[bulk], o.W**2, rtol=1e-6)
     assert np.all(q[~kept] == 0)
