@@ -75,7 +75,9 @@ typedef struct boltz_problem {
   int32_t order;         /* streaming order: 1 or 2                          */
   int32_t bc;            /* BOLTZ_BC_CAVITY or BOLTZ_BC_PERIODIC             */
   int64_t n_pairs;       /* N_t of Eq. monteCarloInt, pairs per cell per step*/
-  int64_t sample_group;  /* G: cells cell/G share a pair stream; 0 = all     */
+  int64_t sample_group;  /* G: cells cell/G share a pair stream; 0 = all.    */
+                         /* G != 1: the pairs of every group are drawn once */
+                         /* per step into a context table (16 B per pair)   */
   uint64_t seed;         /* Philox4x32-10 key (low word, high word)          */
   uint32_t cavity_id;    /* fourth Philox counter word                       */
   uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE                             */
@@ -105,8 +107,10 @@ typedef struct boltz_ctx boltz_ctx;
  * per-axis sampling thresholds, and allocate the context on the current HIP
  * device.  EINVAL: out-of-range sizes, a dt above the Courant limit of the
  * streaming scheme (unless BOLTZ_ALLOW_UNSTABLE), n_pairs >= 2^31.
- * EUNSUPPORTED: a velocity grid whose two per-cell FP32 tiles exceed the
- * 160 KB local data share.  ENOMEM / EHIP: device allocation failed. */
+ * EINVAL also for shared samples (G != 1) with more than 65535 groups or
+ * velocity nodes.  EUNSUPPORTED: a velocity grid whose two per-cell FP32
+ * tiles exceed the 160 KB local data share.  ENOMEM / EHIP: device
+ * allocation failed. */
 int boltz_create(const boltz_problem* problem, boltz_ctx** out);
 
 void boltz_destroy(boltz_ctx* ctx);
@@ -129,8 +133,8 @@ int boltz_stream(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_wa
 /* S3 + S4 + S5: one collision step at fixed position (Sec. 3, Eq. homrel),
  * h_s -> h_out.  N_t pairs per cell: nodes a, b drawn from the mixture
  * (1 - beta) Maxwellian node law + beta uniform node law, a direction
- * uniform on the sphere, by Philox4x32-10 with counter
- * (2m + {0,1}, group, step, cavity_id) and key seed; each pair carries the
+ * uniform on the sphere, from one Philox4x32-10 block with counter
+ * (m, group, step, cavity_id) and key seed; each pair carries the
  * importance weight dt K |v_r . k| (w_a/p_a)(w_b/p_b) / N_t of Eq. coll8Dim
  * (w = midpoint weight of Phi0, p = probability of the draw); the Monte Carlo
  * increments of Eq. monteCarloInt are applied in Jacobi form
@@ -167,12 +171,12 @@ int boltz_step_adjoint(boltz_ctx* ctx, const float* h_in, const double* lam_out,
  * sampler.  idx4 (host, count*4): a, b, a*, b* (a* = b* = -1 for a discarded
  * pair); q (host, count): weight dt K |v_r . k| (w_a/p_a)(w_b/p_b) / N_t (0 if
  * discarded);
- * words (host, count*8 or NULL): the eight Philox words.  Synchronous. */
+ * words (host, count*4 or NULL): the Philox4x32-10 block.  Synchronous. */
 int boltz_debug_pairs(boltz_ctx* ctx, int64_t cell, int64_t step, int64_t m0, int64_t count,
                       int32_t* idx4, double* q, uint32_t* words);
 
-/* Test hook: thresholds T_1..T_{n-1} of the node law of one axis (host
- * buffer of nv[axis]-1 uint64 values, each in [0, 2^32]). */
+/* Test hook: thresholds T_1..T_{n-1} of the Maxwellian node law of one axis
+ * on 12-bit fields (host buffer of nv[axis]-1 uint64 values in [0, 4096]). */
 int boltz_axis_thresholds(const boltz_ctx* ctx, int axis, uint64_t* out);
 
 /* Read (and optionally clear) the device status word after synchronising

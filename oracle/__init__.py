@@ -243,10 +243,10 @@ class Oracle:
     def debug_pairs(self, cell, step, m0, count, words=False, velocities=False):
         """Pairs m0..m0+count-1 of (cell, step): idx (count, 4) = a, b, a*, b*
         (-1 for a discarded pair), q (count,), optionally the Philox words
-        (count, 8) and the continuous velocities (count, 4, 3)."""
+        (count, 4) and the continuous velocities (count, 4, 3)."""
         idx = np.zeros((count, 4), dtype=np.int32)
         q = np.zeros(count)
-        wd = np.zeros((count, 8), dtype=np.uint32) if words else None
+        wd = np.zeros((count, 4), dtype=np.uint32) if words else None
         vel = np.zeros((count, 4, 3)) if velocities else None
         self._check(_lib.boltz_ref_debug_pairs(self._ctx, int(cell), int(step), int(m0), int(count),
                                                idx.ctypes.data, q.ctypes.data,

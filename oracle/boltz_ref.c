@@ -29,6 +29,7 @@
 #define INV_SQRT_PI 0.56418958354775628694807945156077
 #define PI_OVER_4 0.78539816339744830961566084581988
 #define TWO_PI 6.28318530717958647692528676655901
+#define FIELD_BITS 12 /* bits of a Philox word that select one node index */
 
 enum { WALL_LEFT = 0, WALL_RIGHT = 1, WALL_BOTTOM = 2, WALL_TOP = 3 };
 
@@ -152,22 +153,23 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
       om_sum += c->om[k][i];
     }
     c->Om[k] = om_sum;
-    /* cumulative thresholds of the per-axis node law (quantised to 2^-32) */
+    /* cumulative thresholds of the per-axis node law, on 12-bit fields */
     double s = 0.0;
     c->T[k][0] = 0;
     for (int i = 0; i < n; ++i) {
-      if (i > 0) c->T[k][i] = (uint64_t)nearbyint(ldexp(s / om_sum, 32));
+      if (i > 0) c->T[k][i] = (uint64_t)nearbyint(ldexp(s / om_sum, FIELD_BITS));
       s += c->om[k][i];
     }
-    /* realised probabilities of the two per-axis laws: node i of the
-     * Maxwellian law for r in [T_i, T_{i+1}); node i of the uniform law for
-     * r with floor(r n / 2^32) = i, i.e. r in [ceil(i 2^32/n), ceil((i+1) 2^32/n)) */
+    /* realised probabilities of the two per-axis laws on a field f in
+     * [0, 2^12): node i of the Maxwellian law for f in [T_i, T_{i+1}); node i
+     * of the uniform law for floor(f n / 2^12) = i, i.e.
+     * f in [ceil(i 2^12/n), ceil((i+1) 2^12/n)) */
     for (int i = 0; i < n; ++i) {
-      uint64_t hi = (i + 1 < n) ? c->T[k][i + 1] : ((uint64_t)1 << 32);
-      c->pphi[k][i] = ldexp((double)(hi - c->T[k][i]), -32);
-      uint64_t lo_u = (((uint64_t)i << 32) + (uint64_t)n - 1) / (uint64_t)n;
-      uint64_t hi_u = (((uint64_t)(i + 1) << 32) + (uint64_t)n - 1) / (uint64_t)n;
-      c->punif[k][i] = ldexp((double)(hi_u - lo_u), -32);
+      uint64_t hi = (i + 1 < n) ? c->T[k][i + 1] : ((uint64_t)1 << FIELD_BITS);
+      c->pphi[k][i] = ldexp((double)(hi - c->T[k][i]), -FIELD_BITS);
+      uint64_t lo_u = (((uint64_t)i << FIELD_BITS) + (uint64_t)n - 1) / (uint64_t)n;
+      uint64_t hi_u = (((uint64_t)(i + 1) << FIELD_BITS) + (uint64_t)n - 1) / (uint64_t)n;
+      c->punif[k][i] = ldexp((double)(hi_u - lo_u), -FIELD_BITS);
     }
   }
   c->beta = p->mix16 / 16.0;
@@ -270,8 +272,9 @@ void boltz_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint3
 /* ------------------------------------------------------- direction map -- */
 
 /* cos and sin of 2 pi u for u in (0, 1): reduce to an octant exactly
- * (8u is exact for u = (r + 1/2) 2^-32), fold to [0, pi/4], then Taylor
- * polynomials in z^2 (truncation below 1e-18 on [0, pi/4]). */
+ * (8u is exact for u = (r + 1/2) 2^-16), fold to [0, pi/4], then Taylor
+ * polynomials in z^2 of degree 13 (sin) and 12 (cos): truncation below
+ * 4e-13 on [0, pi/4]. */
 void boltz_ref_cos_sin_2pi(double u, double* cs, double* sn) {
   double t = u * 8.0;
   double o = floor(t);
@@ -279,9 +282,7 @@ void boltz_ref_cos_sin_2pi(double u, double* cs, double* sn) {
   int oct = ((int)o) & 7;
   double z = ((oct & 1) ? (1.0 - f) : f) * PI_OVER_4;
   double z2 = z * z;
-  double ps = 1.0 / 355687428096000.0;
-  ps = -1.0 / 1307674368000.0 + z2 * ps;
-  ps = 1.0 / 6227020800.0 + z2 * ps;
+  double ps = 1.0 / 6227020800.0;
   ps = -1.0 / 39916800.0 + z2 * ps;
   ps = 1.0 / 362880.0 + z2 * ps;
   ps = -1.0 / 5040.0 + z2 * ps;
@@ -289,9 +290,7 @@ void boltz_ref_cos_sin_2pi(double u, double* cs, double* sn) {
   ps = -1.0 / 6.0 + z2 * ps;
   ps = 1.0 + z2 * ps;
   double S = z * ps;
-  double pc = 1.0 / 20922789888000.0;
-  pc = -1.0 / 87178291200.0 + z2 * pc;
-  pc = 1.0 / 479001600.0 + z2 * pc;
+  double pc = 1.0 / 479001600.0;
   pc = -1.0 / 3628800.0 + z2 * pc;
   pc = 1.0 / 40320.0 + z2 * pc;
   pc = -1.0 / 720.0 + z2 * pc;
@@ -316,21 +315,27 @@ typedef struct {
   int kept;
   int a, b, as, bs;
   double q;
-  uint32_t r[8];
+  uint32_t r[4];
   double vel[12]; /* v_a, v_b, v*, v1* (continuous) */
 } pair_t;
 
-/* Inverse CDF of the per-axis node law: the number of thresholds <= r. */
-static int axis_draw(const boltz_ref_ctx* c, int k, uint32_t r) {
+/* Inverse CDF of the per-axis node law on a 12-bit field f: the number of
+ * thresholds <= f. */
+static int axis_draw(const boltz_ref_ctx* c, int k, uint32_t f) {
   int idx = 0;
   for (int i = 1; i < c->n[k]; ++i)
-    if ((uint64_t)r >= c->T[k][i]) idx++;
+    if ((uint64_t)f >= c->T[k][i]) idx++;
   return idx;
 }
 
-int boltz_ref_axis_draw(const boltz_ref_ctx* c, int axis, uint32_t r) {
-  if (!c || axis < 0 || axis > 2) return -1;
-  return axis_draw(c, axis, r);
+/* Uniform node law on a 12-bit field: floor(f n / 2^12). */
+static int axis_uniform(const boltz_ref_ctx* c, int k, uint32_t f) {
+  return (int)(((uint64_t)f * (uint64_t)c->n[k]) >> FIELD_BITS);
+}
+
+int boltz_ref_axis_draw(const boltz_ref_ctx* c, int axis, uint32_t f) {
+  if (!c || axis < 0 || axis > 2 || f >= (1u << FIELD_BITS)) return -1;
+  return axis_draw(c, axis, f);
 }
 
 /* Cell of a velocity component, or -1 outside the box. */
@@ -350,33 +355,38 @@ static double node_ratio(const boltz_ref_ctx* c, int i, int j, int k) {
   return w / ((1.0 - c->beta) * pm + c->beta * pu);
 }
 
-/* One Monte Carlo collision sample (Sec. 3, Eqs. coll8Dim / monteCarloInt):
- * pre-collision nodes a, b drawn from the mixture of the discrete
- * Maxwellian law (weight 1 - beta) and the uniform node law (weight beta),
- * a direction k uniform on the unit sphere, post-collision velocities
- * v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a (the sign
- * of the sampling-kernel listing; it conserves energy), and the weight
- * q = dt K |v_r.k| (w_a/p~_a) (w_b/p~_b) / N_t.  beta = 0 is the paper's
- * sampling from Phi0.  Pairs whose post-collision velocity leaves the box
- * are discarded (they still count in N_t). */
+/* One Monte Carlo collision sample (Sec. 3, Eqs. coll8Dim / monteCarloInt)
+ * from one Philox4x32-10 block r0..r3 with counter (m, group, step, cavity):
+ *   r0 = [a_x:12][a_y:12][choice_a:4][choice_b:4]
+ *   r1 = [a_z:12][b_x:12][phi_hi:8]    r2 = [b_y:12][b_z:12][phi_lo:8]
+ *   r3 = u for k_z.
+ * Each node comes from the discrete Maxwellian law (choice >= mix16) or the
+ * uniform law (choice < mix16) of its 12-bit fields; k is uniform on the unit
+ * sphere, k_z = 2 u - 1 with u = (r3 + 1/2) 2^-32, azimuth 2 pi (phi + 1/2)
+ * 2^-16; post-collision velocities v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k
+ * with v_r = v_b - v_a (the sign of the sampling-kernel listing, which
+ * conserves energy); weight q = dt K |v_r.k| (w_a/p~_a)(w_b/p~_b) / N_t, the
+ * importance-sampling estimate of Eq. coll8Dim for the mixture density
+ * p~ = (1 - beta) p_Maxwell + beta p_uniform.  Pairs whose post-collision
+ * velocity leaves the box are discarded (they still count in N_t). */
 static void sample_pair(const boltz_ref_ctx* c, uint32_t group, uint32_t step, uint32_t m,
                         pair_t* out) {
   const uint32_t key[2] = {(uint32_t)c->p.seed, (uint32_t)(c->p.seed >> 32)};
-  const uint32_t c0[4] = {2u * m, group, step, c->p.cavity_id};
-  const uint32_t c1[4] = {2u * m + 1u, group, step, c->p.cavity_id};
+  const uint32_t ctr[4] = {m, group, step, c->p.cavity_id};
   uint32_t* r = out->r;
-  boltz_ref_philox4x32_10(c0, key, r);
-  boltz_ref_philox4x32_10(c1, key, r + 4);
-  /* component choice from the low byte of r7: 4 bits for a, 4 for b */
-  const int unif_a = (int)(r[7] & 15u) < (int)c->p.mix16;
-  const int unif_b = (int)((r[7] >> 4) & 15u) < (int)c->p.mix16;
+  boltz_ref_philox4x32_10(ctr, key, r);
+  const uint32_t fa[3] = {r[0] >> 20, (r[0] >> 8) & 0xFFFu, r[1] >> 20};
+  const uint32_t fb[3] = {(r[1] >> 8) & 0xFFFu, r[2] >> 20, (r[2] >> 8) & 0xFFFu};
+  const int unif_a = (int)((r[0] >> 4) & 15u) < (int)c->p.mix16;
+  const int unif_b = (int)(r[0] & 15u) < (int)c->p.mix16;
   int ia[3], ib[3];
   for (int k = 0; k < 3; ++k) {
-    ia[k] = unif_a ? (int)(((uint64_t)r[k] * (uint64_t)c->n[k]) >> 32) : axis_draw(c, k, r[k]);
-    ib[k] = unif_b ? (int)(((uint64_t)r[3 + k] * (uint64_t)c->n[k]) >> 32) : axis_draw(c, k, r[3 + k]);
+    ia[k] = unif_a ? axis_uniform(c, k, fa[k]) : axis_draw(c, k, fa[k]);
+    ib[k] = unif_b ? axis_uniform(c, k, fb[k]) : axis_draw(c, k, fb[k]);
   }
-  double u6 = ((double)r[6] + 0.5) * 0x1p-32;
-  double u7 = ((double)(r[7] >> 8) + 0.5) * 0x1p-24;
+  const uint32_t phi = ((r[1] & 0xFFu) << 8) | (r[2] & 0xFFu);
+  double u6 = ((double)r[3] + 0.5) * 0x1p-32;
+  double u7 = ((double)phi + 0.5) * 0x1p-16;
   double kz = 2.0 * u6 - 1.0;
   double s = sqrt((1.0 - kz) * (1.0 + kz));
   double cp, sp;
@@ -425,7 +435,7 @@ int boltz_ref_debug_pairs(const boltz_ref_ctx* c, int64_t cell, int64_t step, in
     idx4[4 * i + 2] = pr.as;
     idx4[4 * i + 3] = pr.bs;
     q[i] = pr.q;
-    if (words) memcpy(words + 8 * i, pr.r, 8 * sizeof(uint32_t));
+    if (words) memcpy(words + 4 * i, pr.r, 4 * sizeof(uint32_t));
     if (vel) memcpy(vel + 12 * i, pr.vel, 12 * sizeof(double));
   }
   return BOLTZ_REF_OK;

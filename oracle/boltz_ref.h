@@ -81,12 +81,13 @@ void boltz_ref_set_threads(int nthreads);
 int boltz_ref_get_threads(void);
 
 /* Velocity grid of one axis: node values, weights omega, cumulative
- * thresholds T_1..T_{n-1} (uint64, T in [0, 2^32]). */
+ * thresholds T_1..T_{n-1} of the node law on 12-bit fields (T in [0, 4096]). */
 int boltz_ref_axis(const boltz_ref_ctx* ctx, int axis, double* v, double* omega,
                    uint64_t* thresholds /* n-1 entries */);
 
-/* Inverse CDF of the per-axis node law: #{i in [1, n) : r >= T_i}. */
-int boltz_ref_axis_draw(const boltz_ref_ctx* ctx, int axis, uint32_t r);
+/* Inverse CDF of the per-axis node law on a 12-bit field f:
+ * #{i in [1, n) : f >= T_i} (-1 for f >= 4096). */
+int boltz_ref_axis_draw(const boltz_ref_ctx* ctx, int axis, uint32_t f);
 
 /* Philox4x32-10 (Salmon et al., SC'11).  Pinned by published known-answer
  * vectors and by the Philox4x64 instance of the same round structure. */
@@ -98,11 +99,11 @@ void boltz_ref_cos_sin_2pi(double u, double* c, double* s);
 
 /* Pair sampler for (cell, step, m0 .. m0+count-1): node indices
  * (a, b, a*, b*) with -1 for a*, b* when the pair is discarded, the weight q
- * (0 when discarded), optionally the eight Philox words per pair and the
+ * (0 when discarded), optionally the four Philox words per pair and the
  * continuous velocities v_a, v_b, v*, v1* (12 doubles per pair). */
 int boltz_ref_debug_pairs(const boltz_ref_ctx* ctx, int64_t cell, int64_t step,
                           int64_t m0, int64_t count, int32_t* idx4, double* q,
-                          uint32_t* words /* count*8 or NULL */,
+                          uint32_t* words /* count*4 or NULL */,
                           double* vel /* count*12 or NULL */);
 
 /* Wall densities n_w per boundary face, in the order

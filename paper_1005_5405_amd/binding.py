@@ -228,7 +228,7 @@ class Boltz:
     def debug_pairs(self, cell, step, m0, count, words=False):
         idx = np.zeros((count, 4), dtype=np.int32)
         q = np.zeros(count)
-        wd = np.zeros((count, 8), dtype=np.uint32) if words else None
+        wd = np.zeros((count, 4), dtype=np.uint32) if words else None
         self._check(_lib.boltz_debug_pairs(self._ctx, int(cell), int(step), int(m0), int(count), idx.ctypes.data,
                                            q.ctypes.data, wd.ctypes.data if words else None), "boltz_debug_pairs")
         return (idx, q, wd) if words else (idx, q)

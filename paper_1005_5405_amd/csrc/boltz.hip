@@ -40,6 +40,8 @@ struct boltz_ctx {
   Params P{};
   size_t collide_lds = 0;
   int collide_block = 256;
+  int64_t ngroups = 0;          // sample groups (shared-sample mode)
+  uint4* table = nullptr;       // ngroups * n_pairs pair records (G != 1)
   std::string err;
 };
 
@@ -121,6 +123,12 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
                 "boltz_create: the per-cell h and Delta N tiles of this velocity grid exceed the 160 KB LDS");
   if ((int64_t)p->nx * p->ny * nvt >= ((int64_t)1 << 40))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: phase-space grid too large");
+  const int64_t ncells_ = (int64_t)p->nx * p->ny;
+  const int64_t ngroups = (p->sample_group == 1) ? 0
+                          : (p->sample_group == 0 ? 1 : (ncells_ + p->sample_group - 1) / p->sample_group);
+  if (ngroups > 65535 || nvt > 65535)
+    return fail(nullptr, BOLTZ_EINVAL,
+                "boltz_create: shared-sample mode needs at most 65535 groups and 65535 velocity nodes");
 
   boltz_ctx* c = new (std::nothrow) boltz_ctx;
   if (!c) return fail(nullptr, BOLTZ_ENOMEM, "boltz_create: out of host memory");
@@ -146,23 +154,23 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       c->om[k][i] = (c->dvel[k] * std::exp(-(vi * vi))) * kInvSqrtPi;
       osum += c->om[k][i];
     }
-    // node law of one axis: node i for a 32-bit word r in [T_i, T_{i+1}),
-    // T_i = round(2^32 sum_{l<i} omega_l / sum omega)
+    // node law of one axis on a 12-bit field f: node i for f in
+    // [T_i, T_{i+1}), T_i = round(2^12 sum_{l<i} omega_l / sum omega)
     double s = 0.0;
     for (int i = 0; i < n; ++i) {
-      if (i > 0) c->T[k][i] = (uint64_t)std::nearbyint(std::ldexp(s / osum, 32));
+      if (i > 0) c->T[k][i] = (uint64_t)std::nearbyint(std::ldexp(s / osum, kFieldBits));
       s += c->om[k][i];
     }
-    // realised probabilities: Maxwellian law (T_{i+1} - T_i) 2^-32; uniform
-    // law of floor(r n / 2^32): #{r : floor(r n 2^-32) = i} 2^-32
+    // realised probabilities: Maxwellian law (T_{i+1} - T_i) 2^-12; uniform
+    // law floor(f n / 2^12): #{f : floor(f n 2^-12) = i} 2^-12
     c->pphi[k].resize(n);
     c->punif[k].resize(n);
     for (int i = 0; i < n; ++i) {
-      const uint64_t hi = (i + 1 < n) ? c->T[k][i + 1] : ((uint64_t)1 << 32);
-      c->pphi[k][i] = std::ldexp((double)(hi - c->T[k][i]), -32);
-      const uint64_t lo_u = (((uint64_t)i << 32) + (uint64_t)n - 1) / (uint64_t)n;
-      const uint64_t hi_u = (((uint64_t)(i + 1) << 32) + (uint64_t)n - 1) / (uint64_t)n;
-      c->punif[k][i] = std::ldexp((double)(hi_u - lo_u), -32);
+      const uint64_t hi = (i + 1 < n) ? c->T[k][i + 1] : ((uint64_t)1 << kFieldBits);
+      c->pphi[k][i] = std::ldexp((double)(hi - c->T[k][i]), -kFieldBits);
+      const uint64_t lo_u = (((uint64_t)i << kFieldBits) + (uint64_t)n - 1) / (uint64_t)n;
+      const uint64_t hi_u = (((uint64_t)(i + 1) << kFieldBits) + (uint64_t)n - 1) / (uint64_t)n;
+      c->punif[k][i] = std::ldexp((double)(hi_u - lo_u), -kFieldBits);
     }
   }
   {
@@ -196,26 +204,24 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->qfac = (p->n_pairs > 0) ? (c->dt * c->K) / (double)p->n_pairs : 0.0;
 
   // ---- host images of the device tables
-  std::vector<double> vtab(3 * kMaxAxis, 0.0), omtab(3 * kMaxAxis, 0.0), pphi(3 * kMaxAxis, 0.0),
-      punif(3 * kMaxAxis, 0.0);
-  std::vector<uint32_t> tm1(3 * kMaxAxis, 0u);
-  std::vector<uint8_t> guide(3 * kGuideSize, 0);
+  std::vector<double> vtab(3 * kMaxAxis, 0.0), omtab(3 * kMaxAxis, 0.0);
+  std::vector<float> omf(3 * kMaxAxis, 0.f), pphi(3 * kMaxAxis, 0.f), punif(3 * kMaxAxis, 0.f);
+  std::vector<uint8_t> icdf(3 * kFieldSize, 0);
   std::vector<float> cour(2 * kMaxAxis, 0.f), cour2(2 * kMaxAxis, 0.f);
   for (int k = 0; k < 3; ++k) {
     const int n = c->n[k];
     for (int i = 0; i < n; ++i) {
       vtab[k * kMaxAxis + i] = c->v[k][i];
       omtab[k * kMaxAxis + i] = c->om[k][i];
-      pphi[k * kMaxAxis + i] = c->pphi[k][i];
-      punif[k * kMaxAxis + i] = c->punif[k][i];
-      if (i > 0 && c->T[k][i] >= 1) tm1[k * kMaxAxis + i] = (uint32_t)(c->T[k][i] - 1);
+      omf[k * kMaxAxis + i] = (float)c->om[k][i];
+      pphi[k * kMaxAxis + i] = (float)c->pphi[k][i];
+      punif[k * kMaxAxis + i] = (float)c->punif[k][i];
     }
-    for (int b = 0; b < kGuideSize; ++b) {
-      const uint64_t start = (uint64_t)b << (32 - kGuideBits);
-      int cnt = 0;
-      for (int i = 1; i < n; ++i)
-        if (c->T[k][i] <= start) ++cnt;
-      guide[k * kGuideSize + b] = (uint8_t)cnt;
+    // direct inverse CDF of the Maxwellian law: icdf[f] = #{i >= 1 : T_i <= f}
+    int idx = 0;
+    for (int f = 0; f < kFieldSize; ++f) {
+      while (idx + 1 < n && c->T[k][idx + 1] <= (uint64_t)f) ++idx;
+      icdf[k * kFieldSize + f] = (uint8_t)idx;
     }
   }
   for (int k = 0; k < 2; ++k) {
@@ -231,16 +237,17 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   size_t off = 0;
   const size_t o_v = off; off = align256(off + vtab.size() * 8);
   const size_t o_om = off; off = align256(off + omtab.size() * 8);
-  const size_t o_pphi = off; off = align256(off + pphi.size() * 8);
-  const size_t o_punif = off; off = align256(off + punif.size() * 8);
-  const size_t o_tm1 = off; off = align256(off + tm1.size() * 4);
-  const size_t o_guide = off; off = align256(off + guide.size());
+  const size_t o_omf = off; off = align256(off + omf.size() * 4);
+  const size_t o_pphi = off; off = align256(off + pphi.size() * 4);
+  const size_t o_punif = off; off = align256(off + punif.size() * 4);
+  const size_t o_icdf = off; off = align256(off + icdf.size());
   const size_t o_cour = off; off = align256(off + cour.size() * 4);
   const size_t o_cour2 = off; off = align256(off + cour2.size() * 4);
   const size_t o_nw = off; off = align256(off + (size_t)nfaces * 8);
   const size_t o_ratio = off; off = align256(off + (size_t)4 * c->nv * 8);
   const size_t o_dpart = off; off = align256(off + (size_t)p->nx * 8);
   const size_t o_status = off; off = align256(off + 4);
+  const size_t o_table = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(uint4));
   (void)hipGetDevice(&c->device);
   hipError_t e = hipMalloc(&c->dmem, off);
   if (e != hipSuccess) {
@@ -251,8 +258,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   unsigned char* base = static_cast<unsigned char*>(c->dmem);
   struct Cp { size_t o; const void* src; size_t n; } cps[] = {
       {o_v, vtab.data(), vtab.size() * 8}, {o_om, omtab.data(), omtab.size() * 8},
-      {o_pphi, pphi.data(), pphi.size() * 8}, {o_punif, punif.data(), punif.size() * 8},
-      {o_tm1, tm1.data(), tm1.size() * 4}, {o_guide, guide.data(), guide.size()},
+      {o_omf, omf.data(), omf.size() * 4}, {o_pphi, pphi.data(), pphi.size() * 4},
+      {o_punif, punif.data(), punif.size() * 4}, {o_icdf, icdf.data(), icdf.size()},
       {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4}};
   for (const Cp& cp : cps) {
     e = hipMemcpy(base + cp.o, cp.src, cp.n, hipMemcpyHostToDevice);
@@ -292,24 +299,29 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.qfac = c->qfac;
   P.vtab = reinterpret_cast<const double*>(base + o_v);
   P.omtab = reinterpret_cast<const double*>(base + o_om);
-  P.pphi = reinterpret_cast<const double*>(base + o_pphi);
-  P.punif = reinterpret_cast<const double*>(base + o_punif);
-  P.tm1 = reinterpret_cast<const uint32_t*>(base + o_tm1);
-  P.guide = reinterpret_cast<const uint8_t*>(base + o_guide);
+  P.omf = reinterpret_cast<const float*>(base + o_omf);
+  P.pphi = reinterpret_cast<const float*>(base + o_pphi);
+  P.punif = reinterpret_cast<const float*>(base + o_punif);
+  P.icdf = reinterpret_cast<const uint8_t*>(base + o_icdf);
   P.cour = reinterpret_cast<const float*>(base + o_cour);
   P.cour2 = reinterpret_cast<const float*>(base + o_cour2);
   P.nw = reinterpret_cast<double*>(base + o_nw);
   P.ratio = reinterpret_cast<double*>(base + o_ratio);
   P.dpart = reinterpret_cast<double*>(base + o_dpart);
   P.status = reinterpret_cast<uint32_t*>(base + o_status);
+  c->ngroups = ngroups;
+  c->table = ngroups ? reinterpret_cast<uint4*>(base + o_table) : nullptr;
   c->collide_lds = lds;
   c->collide_block = block_for_collide(c->nv);
   hipError_t ea = hipSuccess;
+  const void* kfn[2] = {nullptr, nullptr};
   switch (c->collide_block) {
-    case 256: ea = hipFuncSetAttribute((const void*)collide_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
-    case 512: ea = hipFuncSetAttribute((const void*)collide_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
-    default: ea = hipFuncSetAttribute((const void*)collide_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+    case 256: kfn[0] = (const void*)collide_kernel<256, false>; kfn[1] = (const void*)collide_kernel<256, true>; break;
+    case 512: kfn[0] = (const void*)collide_kernel<512, false>; kfn[1] = (const void*)collide_kernel<512, true>; break;
+    default: kfn[0] = (const void*)collide_kernel<1024, false>; kfn[1] = (const void*)collide_kernel<1024, true>; break;
   }
+  for (int t = 0; t < 2 && ea == hipSuccess; ++t)
+    ea = hipFuncSetAttribute(kfn[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (ea != hipSuccess) {
     boltz_destroy(c);
     return fail(nullptr, BOLTZ_EHIP, std::string("boltz_create: hipFuncSetAttribute: ") + hipGetErrorString(ea));
@@ -337,8 +349,13 @@ int boltz_axis_thresholds(const boltz_ctx* c, int axis, uint64_t* out) {
 }
 
 static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, hipStream_t st) {
-  const int nfaces = 2 * (c->p.nx + c->p.ny);
-  hipLaunchKernelGGL(wall_kernel, dim3(nfaces), dim3(256), 0, st, c->P, W, h);
+  if (c->p.order == 2) {
+    // x faces first; the y faces read their densities for the x-swept rows
+    hipLaunchKernelGGL(wall_kernel<0>, dim3(2 * c->p.ny), dim3(kWallBlock), 0, st, c->P, W, h);
+    hipLaunchKernelGGL(wall_kernel<1>, dim3(2 * c->p.nx), dim3(kWallBlock), 0, st, c->P, W, h);
+  } else {
+    hipLaunchKernelGGL(wall_kernel<0>, dim3(2 * (c->p.nx + c->p.ny)), dim3(kWallBlock), 0, st, c->P, W, h);
+  }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "wall_kernel launch");
 }
@@ -359,20 +376,38 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream_kernel launch");
 }
 
-static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
-                          double* defect, hipStream_t st) {
+extern "C++" template <bool TABLE>
+static void launch_collide_t(boltz_ctx* c, const float* hs, float* hout, uint32_t s32, uint32_t flags,
+                             double* defect, hipStream_t st) {
   const dim3 grid((unsigned)c->ncells);
-  const uint32_t s32 = (uint32_t)step;
   switch (c->collide_block) {
     case 256:
-      hipLaunchKernelGGL(collide_kernel<256>, grid, dim3(256), c->collide_lds, st, c->P, hs, hout, s32, flags, defect);
+      hipLaunchKernelGGL((collide_kernel<256, TABLE>), grid, dim3(256), c->collide_lds, st, c->P, hs, hout, s32,
+                         flags, defect, c->table);
       break;
     case 512:
-      hipLaunchKernelGGL(collide_kernel<512>, grid, dim3(512), c->collide_lds, st, c->P, hs, hout, s32, flags, defect);
+      hipLaunchKernelGGL((collide_kernel<512, TABLE>), grid, dim3(512), c->collide_lds, st, c->P, hs, hout, s32,
+                         flags, defect, c->table);
       break;
     default:
-      hipLaunchKernelGGL(collide_kernel<1024>, grid, dim3(1024), c->collide_lds, st, c->P, hs, hout, s32, flags, defect);
+      hipLaunchKernelGGL((collide_kernel<1024, TABLE>), grid, dim3(1024), c->collide_lds, st, c->P, hs, hout, s32,
+                         flags, defect, c->table);
       break;
+  }
+}
+
+static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
+                          double* defect, hipStream_t st) {
+  const uint32_t s32 = (uint32_t)step;
+  if (c->ngroups > 0) {
+    if (c->p.n_pairs > 0) {
+      const int nsum = c->n[0] + c->n[1] + c->n[2];
+      const dim3 grid((unsigned)((c->p.n_pairs + 255) / 256), (unsigned)c->ngroups);
+      hipLaunchKernelGGL(sample_kernel, grid, dim3(256), CollideLDS::tables_bytes(nsum), st, c->P, s32, c->table);
+    }
+    launch_collide_t<true>(c, hs, hout, s32, flags, defect, st);
+  } else {
+    launch_collide_t<false>(c, hs, hout, s32, flags, defect, st);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "collide_kernel launch");
@@ -444,7 +479,7 @@ int boltz_debug_pairs(boltz_ctx* c, int64_t cell, int64_t step, int64_t m0, int6
     return fail(c, BOLTZ_EINVAL, "boltz_debug_pairs: invalid argument");
   if (count == 0) return BOLTZ_OK;
   const size_t bi = (size_t)count * 4 * sizeof(int32_t), bq = (size_t)count * sizeof(double),
-               bw = words ? (size_t)count * 8 * sizeof(uint32_t) : 0;
+               bw = words ? (size_t)count * 4 * sizeof(uint32_t) : 0;
   void* d = nullptr;
   hipError_t e = hipMalloc(&d, bi + bq + bw + 64);
   if (e != hipSuccess) return hip_fail(c, e, "boltz_debug_pairs: hipMalloc");

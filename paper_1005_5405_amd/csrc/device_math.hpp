@@ -14,8 +14,8 @@
 namespace boltz {
 
 constexpr int kMaxAxis = 255;          // velocity cells per axis
-constexpr int kGuideBits = 10;         // top bits of a Philox word indexing the guide
-constexpr int kGuideSize = 1 << kGuideBits;
+constexpr int kFieldBits = 12;         // bits of a Philox word selecting one node index
+constexpr int kFieldSize = 1 << kFieldBits;
 constexpr double kPiOver4 = 0.78539816339744830961566084581988;
 
 // ---------------------------------------------------------------- Philox --
@@ -46,7 +46,8 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
 
 // ------------------------------------------------------- direction map --
 // (cos 2 pi u, sin 2 pi u) for u in (0,1): exact octant reduction of 8u, fold
-// to z in [0, pi/4], Taylor polynomials in z^2 evaluated in a fixed order.
+// to z in [0, pi/4], Taylor polynomials in z^2 of degree 13 (sin) and 12
+// (cos) evaluated in a fixed order (truncation below 4e-13).
 __device__ __forceinline__ void cos_sin_2pi(double u, double& cs, double& sn) {
   const double t = u * 8.0;
   const double o = floor(t);
@@ -54,9 +55,7 @@ __device__ __forceinline__ void cos_sin_2pi(double u, double& cs, double& sn) {
   const int oct = ((int)o) & 7;
   const double z = ((oct & 1) ? (1.0 - f) : f) * kPiOver4;
   const double z2 = z * z;
-  double ps = 1.0 / 355687428096000.0;
-  ps = -1.0 / 1307674368000.0 + z2 * ps;
-  ps = 1.0 / 6227020800.0 + z2 * ps;
+  double ps = 1.0 / 6227020800.0;
   ps = -1.0 / 39916800.0 + z2 * ps;
   ps = 1.0 / 362880.0 + z2 * ps;
   ps = -1.0 / 5040.0 + z2 * ps;
@@ -64,9 +63,7 @@ __device__ __forceinline__ void cos_sin_2pi(double u, double& cs, double& sn) {
   ps = -1.0 / 6.0 + z2 * ps;
   ps = 1.0 + z2 * ps;
   const double S = z * ps;
-  double pc = 1.0 / 20922789888000.0;
-  pc = -1.0 / 87178291200.0 + z2 * pc;
-  pc = 1.0 / 479001600.0 + z2 * pc;
+  double pc = 1.0 / 479001600.0;
   pc = -1.0 / 3628800.0 + z2 * pc;
   pc = 1.0 / 40320.0 + z2 * pc;
   pc = -1.0 / 720.0 + z2 * pc;
@@ -81,15 +78,11 @@ __device__ __forceinline__ void cos_sin_2pi(double u, double& cs, double& sn) {
 }
 
 // ------------------------------------------------------------ node law --
-// Per-axis inverse CDF: node i is drawn for r in [T_i, T_{i+1}).  The guide
-// table gives #{i >= 1 : T_i <= b 2^(32-kGuideBits)} for the bucket b of r;
-// the remaining thresholds of the bucket are scanned.  Every threshold
-// examined satisfies T >= 1, so "r >= T" is evaluated as "r > T - 1" on the
-// stored u32 values tm1 = T - 1.
-__device__ __forceinline__ int axis_draw(uint32_t r, const uint8_t* guide, const uint32_t* tm1, int n) {
-  int k = guide[r >> (32 - kGuideBits)];
-  while (k + 1 < n && r > tm1[k + 1]) ++k;
-  return k;
+// A node index comes from a 12-bit field f of a Philox word: the Maxwellian
+// law is a direct inverse-CDF table icdf[f] = #{i >= 1 : T_i <= f}; the
+// uniform law is floor(f n / 2^12) (a 24-bit product).
+__device__ __forceinline__ int uniform_draw(uint32_t f, int n) {
+  return (int)((f * (uint32_t)n) >> kFieldBits);
 }
 
 // ------------------------------------------------------------ streaming --
@@ -99,6 +92,47 @@ __device__ __forceinline__ int axis_draw(uint32_t r, const uint8_t* guide, const
 __device__ __forceinline__ float bw_update(float h0, float h1, float h2, float C, float c2) {
   return h0 - C * (h0 - h1) - c2 * ((h0 - 2.0f * h1) + h2);
 }
+
+// ------------------------------------------------------- LDS float add --
+// Float accumulation into LDS as a read plus a 32-bit compare-and-swap,
+// retried when another lane changed the word.  On gfx950 the native LDS
+// float atomic add completes about one lane every three clocks per CU
+// whatever the address pattern, while integer LDS atomics run ~28x faster;
+// the compare-and-swap form keeps exact FP32 addition semantics.
+__device__ __forceinline__ void lds_add(float* p, float v) {
+  unsigned* u = reinterpret_cast<unsigned*>(p);
+  unsigned old = *u;
+  while (true) {
+    const unsigned nw = __float_as_uint(__uint_as_float(old) + v);
+    const unsigned prev = atomicCAS(u, old, nw);
+    if (prev == old) break;
+    old = prev;
+  }
+}
+
+// Per-thread walk over j = j0, j0 + step, ... of the velocity index with the
+// components (jx, jy, jz) updated by carries instead of integer divisions
+// (step < n1 * n2 * n0 arbitrary; each carry is at most one).
+struct NodeWalk {
+  int jx, jy, jz, dx, dy, dz, n1, n2;
+  __device__ NodeWalk(int j0, int step, int n1_, int n2_) : n1(n1_), n2(n2_) {
+    jz = j0 % n2;
+    jy = (j0 / n2) % n1;
+    jx = j0 / (n2 * n1);
+    dz = step % n2;
+    dy = (step / n2) % n1;
+    dx = step / (n2 * n1);
+  }
+  __device__ __forceinline__ void next() {
+    jz += dz;
+    int cy = 0;
+    if (jz >= n2) { jz -= n2; cy = 1; }
+    jy += dy + cy;
+    int cx = 0;
+    if (jy >= n1) { jy -= n1; cx = 1; }
+    jx += dx + cx;
+  }
+};
 
 // ---------------------------------------------------------- reductions --
 __device__ __forceinline__ double wave_sum(double v) {

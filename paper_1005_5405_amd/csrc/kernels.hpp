@@ -34,10 +34,10 @@ struct Params {
   double a[3], inv_cell[3];
   const double* vtab;     // [3][kMaxAxis] node velocities
   const double* omtab;    // [3][kMaxAxis] per-axis weights omega
-  const double* pphi;     // [3][kMaxAxis] realised per-axis Maxwellian law
-  const double* punif;    // [3][kMaxAxis] realised per-axis uniform law
-  const uint32_t* tm1;    // [3][kMaxAxis] T_i - 1 (i >= 1)
-  const uint8_t* guide;   // [3][kGuideSize]
+  const float* omf;      // [3][kMaxAxis] omega in FP32 (importance weights)
+  const float* pphi;      // [3][kMaxAxis] realised per-axis Maxwellian law
+  const float* punif;     // [3][kMaxAxis] realised per-axis uniform law
+  const uint8_t* icdf;    // [3][kFieldSize] Maxwellian inverse CDF on 12-bit fields
   const float* cour;      // [2][kMaxAxis] Courant number |v| dt / d{x,y}
   const float* cour2;     // [2][kMaxAxis] C (1 - C) / 2
   double* nw;             // [2 ny + 2 nx] face densities: left, right, bottom, top
@@ -123,45 +123,62 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
   const double Uw = (wall == WALL_TOP) ? W.lid_u : 0.0;
   const bool ysw = (order == 2) && (nax == 1);
   double s[3] = {0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
-    int jx, jy, jz;
-    node_decode(j, n1, n2, jx, jy, jz);
-    const double vn = nax ? P.vtab[kMaxAxis + jy] : P.vtab[jx];
-    if (!(sgn * vn < 0.0)) continue;
-    const double an = fabs(vn);
-    const double w = (P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz];
-    int mx = jx, my = jy;
-    if (nax == 0) mx = P.n[0] - 1 - jx; else my = n1 - 1 - jy;
-    const double R = wall_ratio(P.vtab[mx], P.vtab[kMaxAxis + my], P.vtab[2 * kMaxAxis + jz], Uw,
-                                W.tau[wall], W.tfac[wall]);
-    double ha, hb = 0.0;
-    if (ysw) {
-      ha = xswept_value(P, W, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
-      hb = xswept_value(P, W, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
-    } else {
-      ha = h[cell_off(P, ax_, ay_) + j];
-      if (order == 2) hb = h[cell_off(P, bx_, by_) + j];
+  // four nodes per thread and pass, so that their loads are in flight together
+  constexpr int U = 4;
+  const int step = blockDim.x;
+  NodeWalk walk(threadIdx.x, step, n1, n2);
+  for (int j0 = threadIdx.x; j0 < nv; j0 += U * step) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * step;
+      const int jx = walk.jx, jy = walk.jy, jz = walk.jz;
+      walk.next();
+      if (j >= nv) continue;
+      const double vn = nax ? P.vtab[kMaxAxis + jy] : P.vtab[jx];
+      if (!(sgn * vn < 0.0)) continue;
+      const double an = fabs(vn);
+      const double w = (P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz];
+      int mx = jx, my = jy;
+      if (nax == 0) mx = P.n[0] - 1 - jx; else my = n1 - 1 - jy;
+      const double R = wall_ratio(P.vtab[mx], P.vtab[kMaxAxis + my], P.vtab[2 * kMaxAxis + jz], Uw,
+                                  W.tau[wall], W.tfac[wall]);
+      double ha, hb = 0.0;
+      if (ysw) {
+        ha = xswept_value(P, W, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
+        hb = xswept_value(P, W, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
+      } else {
+        ha = h[cell_off(P, ax_, ay_) + j];
+        if (order == 2) hb = h[cell_off(P, bx_, by_) + j];
+      }
+      double hh = ha;
+      if (order == 2) {
+        const double C = an * P.dt / dl;
+        hh = ha + 0.5 * (1.0 - C) * (ha - hb);
+      }
+      const double aw = an * w;
+      s[0] += aw;
+      s[1] += aw * R;
+      s[2] += aw * hh;
     }
-    double hh = ha;
-    if (order == 2) {
-      const double C = an * P.dt / dl;
-      hh = ha + 0.5 * (1.0 - C) * (ha - hb);
-    }
-    const double aw = an * w;
-    s[0] += aw;
-    s[1] += aw * R;
-    s[2] += aw * hh;
   }
   block_sum<3>(s, red);
   return (s[0] + P.eps * s[2]) / s[1];
 }
 
-// One workgroup per boundary face (left[ny], right[ny], bottom[nx], top[nx]).
-// Face 0 of every wall also fills that wall's ratio table for the stream
-// kernel.  Launched only for cavity problems.
-__global__ __launch_bounds__(256) void wall_kernel(Params P, WallArgs W, const float* __restrict__ h) {
-  __shared__ double red[3 * 4];
-  const int f = blockIdx.x;
+constexpr int kWallBlock = 512;
+
+// One workgroup per boundary face, faces numbered left[ny], right[ny],
+// bottom[nx], top[nx].  PHASE 0 handles the x faces (and, for order 1, the y
+// faces too); PHASE 1 the y faces of order 2, whose face values come from
+// the x-swept boundary rows and therefore need the x-face densities of the
+// previous launch.  The first face of every wall also fills that wall's
+// ratio table Phi_w / Phi0 for the stream kernel.  Cavity problems only.
+template <int PHASE>
+__global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, const float* __restrict__ h) {
+  __shared__ double red[3 * (kWallBlock / 64)];
+  const bool ysplit = (P.order == 2);
+  int f = blockIdx.x;
+  if (PHASE == 1) f += 2 * P.ny;  // y faces only
   int wall, pos;
   if (f < P.ny) { wall = WALL_LEFT; pos = f; }
   else if (f < 2 * P.ny) { wall = WALL_RIGHT; pos = f - P.ny; }
@@ -169,29 +186,25 @@ __global__ __launch_bounds__(256) void wall_kernel(Params P, WallArgs W, const f
   else { wall = WALL_TOP; pos = f - 2 * P.ny - P.nx; }
   if (pos == 0) {
     const double Uw = (wall == WALL_TOP) ? W.lid_u : 0.0;
-    for (int j = threadIdx.x; j < P.nv; j += blockDim.x) {
-      int jx, jy, jz;
-      node_decode(j, P.n[1], P.n[2], jx, jy, jz);
-      P.ratio[(int64_t)wall * P.nv + j] = wall_ratio(P.vtab[jx], P.vtab[kMaxAxis + jy],
-                                                     P.vtab[2 * kMaxAxis + jz], Uw, W.tau[wall],
+    NodeWalk walk(threadIdx.x, blockDim.x, P.n[1], P.n[2]);
+    for (int j = threadIdx.x; j < P.nv; j += blockDim.x, walk.next()) {
+      P.ratio[(int64_t)wall * P.nv + j] = wall_ratio(P.vtab[walk.jx], P.vtab[kMaxAxis + walk.jy],
+                                                     P.vtab[2 * kMaxAxis + walk.jz], Uw, W.tau[wall],
                                                      W.tfac[wall]);
     }
   }
   double nwl0 = 0.0, nwl1 = 0.0, nwr0 = 0.0, nwr1 = 0.0;
-  if (P.order == 2 && wall >= WALL_BOTTOM) {
-    // the x-swept boundary rows of a corner column need the x-wall densities
+  if (PHASE == 1) {
+    // x-wall densities of the two boundary rows next to this y face
     const int ra = (wall == WALL_BOTTOM) ? 0 : P.ny - 1;
     const int rb = (wall == WALL_BOTTOM) ? 1 : P.ny - 2;
-    if (pos < 2) {
-      nwl0 = face_density(P, W, h, WALL_LEFT, ra, 2, 0, 0, 0, 0, red);
-      nwl1 = face_density(P, W, h, WALL_LEFT, rb, 2, 0, 0, 0, 0, red);
-    }
-    if (pos >= P.nx - 2) {
-      nwr0 = face_density(P, W, h, WALL_RIGHT, ra, 2, 0, 0, 0, 0, red);
-      nwr1 = face_density(P, W, h, WALL_RIGHT, rb, 2, 0, 0, 0, 0, red);
-    }
+    nwl0 = P.nw[ra];
+    nwl1 = P.nw[rb];
+    nwr0 = P.nw[P.ny + ra];
+    nwr1 = P.nw[P.ny + rb];
   }
   const double nwv = face_density(P, W, h, wall, pos, P.order, nwl0, nwl1, nwr0, nwr1, red);
+  (void)ysplit;
   if (threadIdx.x == 0) P.nw[f] = nwv;
 }
 
@@ -203,17 +216,23 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-// Value of the order-1 / x-direction ghost or in-domain cell for the LDS
-// tile.  Cells outside the cavity in x take the re-emitted value of that
-// x wall; outside in y (order 1 only) that of the y wall.
+// One workgroup: an 8x8 tile of cells and a chunk of 32 consecutive
+// velocities.  The (8 + 2H)^2 x 32 block (H = order) is staged in LDS with
+// 16-byte loads, but only on the upwind sides that the chunk's velocities
+// need (jx, and within one jx also jy, increase with j, so the extreme nodes
+// of the chunk decide).  Cells outside the cavity take the re-emitted value
+// of the wall they lie beyond.  Order 2: the x sweep of every tile row
+// (y-halo rows included) goes to a second LDS buffer, then the y sweep.
 template <int ORDER>
 __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const float* __restrict__ hin,
                                                               float* __restrict__ hout, int tiles_x,
                                                               int tiles_y, int nchunks, int per_xcd) {
   constexpr int H = ORDER;
   constexpr int AX = kTX + 2 * H, AY = kTY + 2 * H;
-  __shared__ float A[AY * AX * kJ];
+  constexpr int Q = kJ / 4;  // float4 per cell and chunk
+  __shared__ float4 A4[AY * AX * Q];
   __shared__ float B[(ORDER == 2) ? AY * kTX * kJ : 1];
+  float* A = reinterpret_cast<float*>(A4);
   // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give
   // each XCD a contiguous range of (chunk, tile) units so that neighbouring
   // tiles (which share halos) run on the same L2.
@@ -225,46 +244,72 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
   const int ix0 = (tile % tiles_x) * kTX, iy0 = (tile / tiles_x) * kTY;
   const int j0 = chunk * kJ;
   const int nx = P.nx, ny = P.ny, nv = P.nv;
+  const int n1 = P.n[1], n2 = P.n[2];
   const bool periodic = (P.bc == 1);
+  // upwind sides needed by this chunk
+  const int jlast = min(j0 + kJ, nv) - 1;
+  int fx, fy, fz, lx, ly, lz;
+  node_decode(j0, n1, n2, fx, fy, fz);
+  node_decode(jlast, n1, n2, lx, ly, lz);
+  const bool needL = P.vtab[lx] > 0.0, needR = P.vtab[fx] < 0.0;
+  const bool oneX = (fx == lx);
+  const bool needB = !oneX || P.vtab[kMaxAxis + ly] > 0.0;  // v_y > 0 reads cells below
+  const bool needT = !oneX || P.vtab[kMaxAxis + fy] < 0.0;
+  const int c_lo = needL ? 0 : H, c_hi = needR ? AX : AX - H;
+  const int r_lo = needB ? 0 : H, r_hi = needT ? AY : AY - H;
+  // ---- stage the block (16-byte loads; ghosts per component)
+  const bool vec = (nv & 3) == 0;
+  {
+    const int q = threadIdx.x % Q;
+    const int jq = j0 + 4 * q;
+    for (int cidx = threadIdx.x / Q; cidx < AY * AX; cidx += kStreamBlock / Q) {
+      const int r = cidx / AX, c = cidx % AX;
+      if (r < r_lo || r >= r_hi || c < c_lo || c >= c_hi) continue;
+      const int iy = iy0 - H + r, ix = ix0 - H + c;
+      const bool inY = iy >= 0 && iy < ny, inX = ix >= 0 && ix < nx;
+      float v4[4] = {0.f, 0.f, 0.f, 0.f};
+      if (periodic || (inX && inY)) {
+        const int64_t base = cell_off(P, periodic ? wrapi(ix, nx) : ix, periodic ? wrapi(iy, ny) : iy);
+        if (vec && jq + 3 < nv) {
+          const float4 t = *reinterpret_cast<const float4*>(hin + base + jq);
+          v4[0] = t.x; v4[1] = t.y; v4[2] = t.z; v4[3] = t.w;
+        } else {
+          for (int e = 0; e < 4; ++e)
+            if (jq + e < nv) v4[e] = hin[base + jq + e];
+        }
+      } else if (inY || (ORDER == 1 && inX)) {
+        int wall;
+        double nwv;
+        if (inY) {
+          wall = ix < 0 ? WALL_LEFT : WALL_RIGHT;
+          nwv = P.nw[(wall == WALL_LEFT ? 0 : ny) + iy];
+        } else {
+          wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
+          nwv = P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix];
+        }
+        for (int e = 0; e < 4; ++e)
+          if (jq + e < nv) v4[e] = ghost_value(nwv, P.ratio[(int64_t)wall * nv + jq + e], P.inv_eps);
+      }
+      A4[cidx * Q + q] = make_float4(v4[0], v4[1], v4[2], v4[3]);
+    }
+  }
   const int jj = threadIdx.x & (kJ - 1);
   const int j = j0 + jj;
   const bool jok = j < nv;
   int jx = 0, jy = 0, jz = 0;
-  if (jok) node_decode(j, P.n[1], P.n[2], jx, jy, jz);
+  if (jok) node_decode(j, n1, n2, jx, jy, jz);
   const double vx = P.vtab[jx], vy = P.vtab[kMaxAxis + jy];
   const int sx = vx > 0.0 ? 1 : (vx < 0.0 ? -1 : 0);
   const int sy = vy > 0.0 ? 1 : (vy < 0.0 ? -1 : 0);
   const float Cx = P.cour[jx], Cx2 = P.cour2[jx];
   const float Cy = P.cour[kMaxAxis + jy], Cy2 = P.cour2[kMaxAxis + jy];
   const int rstep = kStreamBlock / kJ;  // 8 tile cells per pass
-  // ---- load the (AY x AX) x 32 block
-  for (int cidx = threadIdx.x / kJ; cidx < AY * AX; cidx += rstep) {
-    const int r = cidx / AX, c = cidx % AX;
-    int iy = iy0 - H + r, ix = ix0 - H + c;
-    const bool inY = iy >= 0 && iy < ny, inX = ix >= 0 && ix < nx;
-    float val = 0.0f;
-    if (jok) {
-      if (periodic) {
-        val = hin[cell_off(P, wrapi(ix, nx), wrapi(iy, ny)) + j];
-      } else if (inX && inY) {
-        val = hin[cell_off(P, ix, iy) + j];
-      } else if (inY) {
-        const int wall = ix < 0 ? WALL_LEFT : WALL_RIGHT;
-        val = ghost_value(P.nw[(wall == WALL_LEFT ? 0 : ny) + iy], P.ratio[(int64_t)wall * nv + j],
-                          P.inv_eps);
-      } else if (ORDER == 1 && inX) {
-        const int wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
-        val = ghost_value(P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix],
-                          P.ratio[(int64_t)wall * nv + j], P.inv_eps);
-      }
-    }
-    A[cidx * kJ + jj] = val;
-  }
   __syncthreads();
   if (ORDER == 2) {
-    // ---- x sweep of every tile row, halo rows included
+    // ---- x sweep of the tile rows that the y sweep reads
     for (int cidx = threadIdx.x / kJ; cidx < AY * kTX; cidx += rstep) {
       const int r = cidx / kTX, c = cidx % kTX;
+      if (r < r_lo || r >= r_hi) continue;
       const int iy = iy0 - 2 + r, ix = ix0 + c;
       float val = 0.0f;
       if (jok && ix < nx) {
@@ -308,68 +353,65 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
 // --------------------------------------------------------------- S3, S4 --
 // LDS copies of the per-axis tables used by the pair sampler.
 struct SamplerLDS {
-  double* v;        // [n0 + n1 + n2]
-  double* om;       // [n0 + n1 + n2]
-  double* pphi;     // [n0 + n1 + n2]
-  double* punif;    // [n0 + n1 + n2]
-  uint32_t* tm1;    // [n0 + n1 + n2]
-  uint8_t* guide;   // [3 * kGuideSize]
+  double* v;        // [n0 + n1 + n2] node velocities
+  double* om;       // [n0 + n1 + n2] omega (FP64, moment sums)
+  float* omf;       // [n0 + n1 + n2] omega (FP32, weights)
+  float* pphi;      // [n0 + n1 + n2]
+  float* punif;     // [n0 + n1 + n2]
+  uint8_t* icdf;    // [3 * kFieldSize]
 };
 
-// w_a / p~_a: midpoint weight of Phi0 over the probability of drawing node
-// (i, j, k) from (1 - beta) Maxwellian law + beta uniform law.
-__device__ __forceinline__ double node_ratio(const SamplerLDS& T, double beta, int i, int j, int k, int n0,
-                                             int n1) {
-  const double w = (T.om[i] * T.om[n0 + j]) * T.om[n0 + n1 + k];
-  const double pm = (T.pphi[i] * T.pphi[n0 + j]) * T.pphi[n0 + n1 + k];
-  const double pu = (T.punif[i] * T.punif[n0 + j]) * T.punif[n0 + n1 + k];
-  return w / ((1.0 - beta) * pm + beta * pu);
-}
-
-__device__ __forceinline__ int uniform_draw(uint32_t r, int n) {
-  return (int)(((uint64_t)r * (uint64_t)n) >> 32);
+// w_a / p~_a in FP32: midpoint weight of Phi0 over the probability of drawing
+// node (i, j, k) from (1 - beta) Maxwellian law + beta uniform law.
+__device__ __forceinline__ float node_ratio(const SamplerLDS& T, float beta, int i, int j, int k, int n0,
+                                            int n1) {
+  const float w = (T.omf[i] * T.omf[n0 + j]) * T.omf[n0 + n1 + k];
+  const float pm = (T.pphi[i] * T.pphi[n0 + j]) * T.pphi[n0 + n1 + k];
+  const float pu = (T.punif[i] * T.punif[n0 + j]) * T.punif[n0 + n1 + k];
+  return w / ((1.0f - beta) * pm + beta * pu);
 }
 
 struct Pair {
   int a, b, as, bs;  // node indices; as = bs = -1 when discarded
-  double q;
+  float q;
 };
 
-// One Monte Carlo collision sample: Philox words -> nodes a, b, each from
-// the Maxwellian node law or (low byte of the eighth word below mix16) the
-// uniform node law, direction k uniform on the sphere,
-// v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a,
-// post-collision cells by floor((x + a) n / 2a) (discard outside the box),
-// q = qfac |v_r . k| (w_a/p~_a)(w_b/p~_b) with qfac = dt K / N_t.
+// One Monte Carlo collision sample from one Philox4x32-10 block with counter
+// (m, group, step, cavity):
+//   r0 = [a_x:12][a_y:12][choice_a:4][choice_b:4]
+//   r1 = [a_z:12][b_x:12][phi_hi:8]   r2 = [b_y:12][b_z:12][phi_lo:8]   r3 = u
+// nodes from the Maxwellian law, or the uniform law when the choice nibble
+// is below mix16; k_z = 2 (r3 + 1/2) 2^-32 - 1, azimuth 2 pi (phi + 1/2) 2^-16;
+// v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a;
+// post-collision cells floor((x + a) n / 2a), discard outside the box;
+// q = qfac |v_r.k| (w_a/p~_a)(w_b/p~_b), qfac = dt K / N_t.
 __device__ __forceinline__ Pair sample_pair(const Params& P, const SamplerLDS& T, uint32_t group,
                                             uint32_t step, uint32_t m, u32x4* words) {
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
-  u32x4 c0 = {2u * m, group, step, P.cavity};
-  u32x4 c1 = {2u * m + 1u, group, step, P.cavity};
-  const u32x4 r0 = philox4x32_10(c0, P.key0, P.key1);
-  const u32x4 r1 = philox4x32_10(c1, P.key0, P.key1);
-  if (words) {
-    words[0] = r0;
-    words[1] = r1;
-  }
-  const double* vx = T.v;
-  const double* vy = T.v + n0;
-  const double* vz = T.v + n0 + n1;
-  const bool ua = (r1.w & 15u) < P.mix16;
-  const bool ub = ((r1.w >> 4) & 15u) < P.mix16;
-  const int iax = ua ? uniform_draw(r0.x, n0) : axis_draw(r0.x, T.guide, T.tm1, n0);
-  const int iay = ua ? uniform_draw(r0.y, n1) : axis_draw(r0.y, T.guide + kGuideSize, T.tm1 + n0, n1);
-  const int iaz = ua ? uniform_draw(r0.z, n2) : axis_draw(r0.z, T.guide + 2 * kGuideSize, T.tm1 + n0 + n1, n2);
-  const int ibx = ub ? uniform_draw(r0.w, n0) : axis_draw(r0.w, T.guide, T.tm1, n0);
-  const int iby = ub ? uniform_draw(r1.x, n1) : axis_draw(r1.x, T.guide + kGuideSize, T.tm1 + n0, n1);
-  const int ibz = ub ? uniform_draw(r1.y, n2) : axis_draw(r1.y, T.guide + 2 * kGuideSize, T.tm1 + n0 + n1, n2);
-  const double u6 = ((double)r1.z + 0.5) * 0x1p-32;
-  const double u7 = ((double)(r1.w >> 8) + 0.5) * 0x1p-24;
+  const u32x4 c = {m, group, step, P.cavity};
+  const u32x4 r = philox4x32_10(c, P.key0, P.key1);
+  if (words) words[0] = r;
+  const bool ua = ((r.x >> 4) & 15u) < P.mix16;
+  const bool ub = (r.x & 15u) < P.mix16;
+  const uint32_t fax = r.x >> 20, fay = (r.x >> 8) & 0xFFFu, faz = r.y >> 20;
+  const uint32_t fbx = (r.y >> 8) & 0xFFFu, fby = r.z >> 20, fbz = (r.z >> 8) & 0xFFFu;
+  const int iax = ua ? uniform_draw(fax, n0) : (int)T.icdf[fax];
+  const int iay = ua ? uniform_draw(fay, n1) : (int)T.icdf[kFieldSize + fay];
+  const int iaz = ua ? uniform_draw(faz, n2) : (int)T.icdf[2 * kFieldSize + faz];
+  const int ibx = ub ? uniform_draw(fbx, n0) : (int)T.icdf[fbx];
+  const int iby = ub ? uniform_draw(fby, n1) : (int)T.icdf[kFieldSize + fby];
+  const int ibz = ub ? uniform_draw(fbz, n2) : (int)T.icdf[2 * kFieldSize + fbz];
+  const uint32_t phi = ((r.y & 0xFFu) << 8) | (r.z & 0xFFu);
+  const double u6 = ((double)r.w + 0.5) * 0x1p-32;
+  const double u7 = ((double)phi + 0.5) * 0x1p-16;
   const double kz = 2.0 * u6 - 1.0;
   const double s = sqrt((1.0 - kz) * (1.0 + kz));
   double cp, sp;
   cos_sin_2pi(u7, cp, sp);
   const double kx = s * cp, ky = s * sp;
+  const double* vx = T.v;
+  const double* vy = T.v + n0;
+  const double* vz = T.v + n0 + n1;
   const double vax = vx[iax], vay = vy[iay], vaz = vz[iaz];
   const double vbx = vx[ibx], vby = vy[iby], vbz = vz[ibz];
   const double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
@@ -390,20 +432,22 @@ __device__ __forceinline__ Pair sample_pair(const Params& P, const SamplerLDS& T
   if (kept) {
     p.as = ((int)tsx * n1 + (int)tsy) * n2 + (int)tsz;
     p.bs = ((int)ttx * n1 + (int)tty) * n2 + (int)ttz;
-    p.q = ((P.qfac * fabs(alpha)) * node_ratio(T, P.beta, iax, iay, iaz, n0, n1)) *
-          node_ratio(T, P.beta, ibx, iby, ibz, n0, n1);
+    const float beta = (float)P.beta;
+    p.q = ((float)(P.qfac * fabs(alpha)) * node_ratio(T, beta, iax, iay, iaz, n0, n1)) *
+          node_ratio(T, beta, ibx, iby, ibz, n0, n1);
   } else {
     p.as = -1;
     p.bs = -1;
-    p.q = 0.0;
+    p.q = 0.0f;
   }
   return p;
 }
 
-// Layout of the dynamic LDS of the collide kernel.
+// Layout of the dynamic LDS of the collide kernel: h^s and Delta N tiles,
+// then the sampler tables.
 struct CollideLDS {
   static __host__ __device__ size_t tables_bytes(int nsum) {
-    return 4 * (size_t)nsum * sizeof(double) + (size_t)nsum * sizeof(uint32_t) + 3 * kGuideSize;
+    return 2 * (size_t)nsum * sizeof(double) + 3 * (size_t)nsum * sizeof(float) + 3 * kFieldSize;
   }
   static __host__ __device__ size_t bytes(int nv, int nsum) {
     size_t b = 2 * (size_t)nv * sizeof(float);
@@ -416,20 +460,22 @@ __device__ __forceinline__ void load_sampler_tables(const Params& P, unsigned ch
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2], ns = n0 + n1 + n2;
   T.v = reinterpret_cast<double*>(base);
   T.om = T.v + ns;
-  T.pphi = T.om + ns;
+  T.omf = reinterpret_cast<float*>(T.om + ns);
+  T.pphi = T.omf + ns;
   T.punif = T.pphi + ns;
-  T.tm1 = reinterpret_cast<uint32_t*>(T.punif + ns);
-  T.guide = reinterpret_cast<uint8_t*>(T.tm1 + ns);
+  T.icdf = reinterpret_cast<uint8_t*>(T.punif + ns);
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
     const int k = i < n0 ? 0 : (i < n0 + n1 ? 1 : 2);
     const int o = i - (k == 0 ? 0 : (k == 1 ? n0 : n0 + n1));
     T.v[i] = P.vtab[k * kMaxAxis + o];
     T.om[i] = P.omtab[k * kMaxAxis + o];
+    T.omf[i] = P.omf[k * kMaxAxis + o];
     T.pphi[i] = P.pphi[k * kMaxAxis + o];
     T.punif[i] = P.punif[k * kMaxAxis + o];
-    T.tm1[i] = P.tm1[k * kMaxAxis + o];
   }
-  for (int i = threadIdx.x; i < 3 * kGuideSize; i += blockDim.x) T.guide[i] = P.guide[i];
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(P.icdf);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(T.icdf);
+  for (int i = threadIdx.x; i < 3 * kFieldSize / 4; i += blockDim.x) dst[i] = src[i];
 }
 
 // Test hook kernel: the pairs of (cell, step, m0 + i) from the same sampler.
@@ -442,18 +488,41 @@ __global__ __launch_bounds__(256) void debug_pairs_kernel(Params P, int64_t cell
   __syncthreads();
   const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-    u32x4 w[2];
-    const Pair p = sample_pair(P, T, group, step, (uint32_t)(m0 + i), w);
+    u32x4 w;
+    const Pair p = sample_pair(P, T, group, step, (uint32_t)(m0 + i), &w);
     idx4[4 * i + 0] = p.a;
     idx4[4 * i + 1] = p.b;
     idx4[4 * i + 2] = p.as;
     idx4[4 * i + 3] = p.bs;
-    q[i] = p.q;
+    q[i] = (double)p.q;
     if (words) {
-      const uint32_t ww[8] = {w[0].x, w[0].y, w[0].z, w[0].w, w[1].x, w[1].y, w[1].z, w[1].w};
-      for (int k = 0; k < 8; ++k) words[8 * i + k] = ww[k];
+      words[4 * i + 0] = w.x;
+      words[4 * i + 1] = w.y;
+      words[4 * i + 2] = w.z;
+      words[4 * i + 3] = w.w;
     }
   }
+}
+
+// Shared-sample mode (G != 1): one pass draws the N_t pairs of every sample
+// group once per step into 16-byte records {a | b << 16, a* | b* << 16,
+// q bits, 0}; a discarded pair is stored with a* = a, b* = b and q = 0.
+__global__ __launch_bounds__(256) void sample_kernel(Params P, uint32_t step, uint4* __restrict__ table) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  SamplerLDS T;
+  load_sampler_tables(P, dsm, T);
+  __syncthreads();
+  const int64_t nt = P.n_pairs;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t group = blockIdx.y;
+  if (i >= nt) return;
+  const Pair p = sample_pair(P, T, group, step, (uint32_t)i, nullptr);
+  uint4 rec;
+  rec.x = (uint32_t)p.a | ((uint32_t)p.b << 16);
+  rec.y = p.as >= 0 ? ((uint32_t)p.as | ((uint32_t)p.bs << 16)) : rec.x;
+  rec.z = __float_as_uint(p.q);
+  rec.w = 0u;
+  table[(int64_t)group * nt + i] = rec;
 }
 
 // ------------------------------------------------------------------- S5 --
@@ -496,11 +565,14 @@ __device__ bool solve5(const double* S, const double* r, double* x) {
   return true;
 }
 
-// One workgroup per spatial cell (blockIdx.x = cell).
-template <int BLOCK>
+// One workgroup per spatial cell (blockIdx.x = cell).  TABLE: the pairs come
+// from the records of sample_kernel (cells of one group share them) instead
+// of being drawn by the workgroup itself.
+template <int BLOCK, bool TABLE>
 __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* __restrict__ hs_g,
                                                         float* __restrict__ hout_g, uint32_t step,
-                                                        uint32_t flags, double* __restrict__ defect) {
+                                                        uint32_t flags, double* __restrict__ defect,
+                                                        const uint4* __restrict__ table) {
   extern __shared__ __align__(16) unsigned char dsm[];
   __shared__ double red[20 * (BLOCK / 64)];
   __shared__ double xs[5];
@@ -532,16 +604,32 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* _
   const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
   const float epsf = (float)P.eps;
   const uint32_t nt = (uint32_t)P.n_pairs;
-  for (uint32_t m = threadIdx.x; m < nt; m += BLOCK) {
-    const Pair p = sample_pair(P, T, group, step, m, nullptr);
-    if (p.as >= 0) {
-      const float ha = hs[p.a], hb = hs[p.b];
+  if (TABLE) {
+    const uint4* rec = table + (int64_t)group * nt;
+    for (uint32_t m = threadIdx.x; m < nt; m += BLOCK) {
+      const uint4 r = rec[m];
+      const int a = (int)(r.x & 0xFFFFu), b = (int)(r.x >> 16);
+      const int as = (int)(r.y & 0xFFFFu), bs = (int)(r.y >> 16);
+      const float ha = hs[a], hb = hs[b];
       const float g = (ha + hb) + (epsf * ha) * hb;
-      const float qg = (float)p.q * g;
-      __hip_atomic_fetch_add(&dN[p.as], qg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_add(&dN[p.bs], qg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_add(&dN[p.a], -qg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_add(&dN[p.b], -qg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const float qg = __uint_as_float(r.z) * g;
+      lds_add(&dN[as], qg);
+      lds_add(&dN[bs], qg);
+      lds_add(&dN[a], -qg);
+      lds_add(&dN[b], -qg);
+    }
+  } else {
+    for (uint32_t m = threadIdx.x; m < nt; m += BLOCK) {
+      const Pair p = sample_pair(P, T, group, step, m, nullptr);
+      if (p.as >= 0) {
+        const float ha = hs[p.a], hb = hs[p.b];
+        const float g = (ha + hb) + (epsf * ha) * hb;
+        const float qg = p.q * g;
+        lds_add(&dN[p.as], qg);
+        lds_add(&dN[p.bs], qg);
+        lds_add(&dN[p.a], -qg);
+        lds_add(&dN[p.b], -qg);
+      }
     }
   }
   __syncthreads();
@@ -558,25 +646,30 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* _
   double acc[20];
 #pragma unroll
   for (int i = 0; i < 20; ++i) acc[i] = 0.0;
-  for (int j = threadIdx.x; j < nv; j += BLOCK) {
-    int jx, jy, jz;
-    node_decode(j, n1, n2, jx, jy, jz);
-    const double w = (omx[jx] * omy[jy]) * omz[jz];
-    const double dn = (double)dN[j];
-    const float hc = (float)((double)hs[j] + dn / w);
-    dN[j] = hc;
-    if (correct) {
-      const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-      const double vv = (v1 * v1 + v2 * v2) + v3 * v3;
-      const double wF = w * (1.0 + eps * (double)hc);
-      const double psi[5] = {1.0, v1, v2, v3, vv};
-      int t = 0;
+  {
+    NodeWalk nw(threadIdx.x, BLOCK, n1, n2);
+    for (int j = threadIdx.x; j < nv; j += BLOCK, nw.next()) {
+      const int jx = nw.jx, jy = nw.jy, jz = nw.jz;
+      const double w = (omx[jx] * omy[jy]) * omz[jz];
+      const double dn = (double)dN[j];
+      const float hc = (float)((double)hs[j] + dn / w);
+      dN[j] = hc;
+      if (correct) {
+        const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+        const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
+        const double wF = w * fma(eps, (double)hc, 1.0);
+        const double psi[5] = {1.0, v1, v2, v3, vv};
+        int t = 0;
 #pragma unroll
-      for (int k = 0; k < 5; ++k)
+        for (int k = 0; k < 5; ++k) {
+          const double wk = wF * psi[k];
 #pragma unroll
-        for (int l = k; l < 5; ++l) acc[t++] += wF * psi[k] * psi[l];
+          for (int l = k; l < 5; ++l) acc[t] = fma(wk, psi[l], acc[t]), ++t;
+        }
+        const double edn = -eps * dn;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) acc[15 + k] += -eps * psi[k] * dn;
+        for (int k = 0; k < 5; ++k) acc[15 + k] = fma(edn, psi[k], acc[15 + k]);
+      }
     }
   }
   if (correct) {
@@ -600,16 +693,16 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* _
   double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   bool finite = true;
   float* dst = hout_g + cell * nv;
-  for (int j = threadIdx.x; j < nv; j += BLOCK) {
-    int jx, jy, jz;
-    node_decode(j, n1, n2, jx, jy, jz);
+  NodeWalk nw2(threadIdx.x, BLOCK, n1, n2);
+  for (int j = threadIdx.x; j < nv; j += BLOCK, nw2.next()) {
+    const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
     const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-    const double vv = (v1 * v1 + v2 * v2) + v3 * v3;
+    const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
     const double hc = (double)dN[j];
     float out = (float)hc;
     if (correct) {
-      const double xpsi = x[0] + x[1] * v1 + x[2] * v2 + x[3] * v3 + x[4] * vv;
-      out = (float)(hc + (1.0 + eps * hc) * xpsi * P.inv_eps);
+      const double xpsi = fma(x[4], vv, fma(x[3], v3, fma(x[2], v2, fma(x[1], v1, x[0]))));
+      out = (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc);
     }
     finite = finite && isfinite(out);
     dst[j] = out;
