@@ -7,14 +7,19 @@ step, CFL 0.5, second-order streaming, FP32 h with FP64 moment/correction sums.
 The state starts at rest (h = 0) and evolves through the warm-up steps, so the
 timed steps act on a developing cavity flow; all data stay resident in HBM.
 
-One step = boltz_stream (wall densities + streaming kernels) followed by
-boltz_collide in place (sampling, gain/loss, correction in one kernel):
-exactly what boltz_step enqueues, with HIP events recorded between the two
-calls on the launch stream to time each kernel group.
+Sample sharing: the headline run draws one set of N_t pairs per step that
+every cell evaluates with its own h (sample group G = 0, the sharing of the
+paper's Sec. 3); the variant with an independent Philox stream per cell
+(G = 1) is timed in the same process and reported beside it.
 
-Prints one JSON line: node-updates/s (value), pairs/s, the roofline of the
-dominant kernel, and the FP64 CPU oracle's throughput on a bounded sample of
-the same workload (a baseline only).
+One step = boltz_stream (wall densities + streaming kernels) followed by
+boltz_collide in place (pair table + collision kernel): exactly what
+boltz_step enqueues, with HIP events recorded between the two calls on the
+launch stream to time each kernel group.
+
+Prints one JSON line: node-updates/s (value), pairs/s, the HBM roofline of the
+dominant kernel group, and the FP64 CPU oracle's throughput on a bounded
+sample of the same workload (a baseline only).
 """
 from __future__ import annotations
 
@@ -28,18 +33,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "phase-space node-updates/s (stream+collide), collision pairs/s, % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# One vector operation per lane per clock on every SIMD: 256 CUs x 4 SIMD x
-# 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s (no FMA doubling).
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic operations of one Monte Carlo sample (two Philox4x32-10 calls,
-# six inverse-CDF searches, direction map, kinematics, cell lookup, weight and
-# the gain/loss update) and of one node of the update + correction; the count
-# is itemised in the design notes.
-OPS_PER_PAIR = 319
-OPS_PER_NODE = 60
-# Algorithmic HBM bytes per phase-space node: FP32 read + FP32 write.
+# Algorithmic HBM bytes per phase-space node and kernel group: one FP32 read
+# and one FP32 write of h.  A whole step (stream + collide) moves 16 B/node.
 BYTES_PER_NODE_KERNEL = 8
+# LDS operations of one pair in one cell in the collision kernel: gathers of
+# h_a and h_b and four 64-bit integer atomic adds (Eq. monteCarloInt).
+LDS_READS_PER_PAIR, LDS_ATOMICS_PER_PAIR = 2, 4
+N_CU, CLOCK_HZ = 256, 2.4e9
 
 
 def _json_line(d):
@@ -68,19 +70,63 @@ def cpu_baseline(preset, seconds_budget: float):
     dt = time.perf_counter() - t0
     ncells, nv = o.nx * o.ny, o.nv
     return {"value": ncells * nv * steps / dt, "unit": "node-updates/s", "cores": used, "kind": "oracle",
-            "sample": "%d full step(s) of the same %dx%d-cell, %d-node, %d-pair workload from rest, "
-                      "FP64, OpenMP over cells, %.1f s" % (steps, o.nx, o.ny, nv, kw["n_pairs"], dt),
+            "sample": "%d full step(s) of the same %dx%d-cell, %d-node, %d-pair, G=%d workload from rest, "
+                      "FP64, OpenMP over cells, %.1f s" % (steps, o.nx, o.ny, nv, kw["n_pairs"],
+                                                           kw["sample_group"], dt),
             "pairs_per_s": ncells * kw["n_pairs"] * steps / dt}
+
+
+def run(pkg, torch, preset, steps: int, warmup: int):
+    """Warm up, then time `steps` steps; per-step HIP events around the two
+    kernel groups on the launch stream."""
+    kw = preset.problem()
+    g = pkg.Boltz(**kw)
+    stream = torch.cuda.current_stream()
+    a, b = g.empty(0.0), g.empty()
+    walls = pkg.Walls(lid_u=preset.lid(0.0))
+    n = 0
+    for _ in range(warmup):
+        walls.lid_u = preset.lid(n * g.dt)
+        g.stream(a, b, walls)
+        g.collide(b, b, n)
+        a, b = b, a
+        n += 1
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        walls.lid_u = preset.lid(n * g.dt)
+        ev[k][0].record(stream)
+        g.stream(a, b, walls)
+        ev[k][1].record(stream)
+        g.collide(b, b, n)
+        ev[k][2].record(stream)
+        a, b = b, a
+        n += 1
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    status = g.read_status()
+    if status:
+        print("[bench] device status %d (numerical failure)" % status, file=sys.stderr, flush=True)
+        sys.exit(3)
+    t_stream = sum(e[0].elapsed_time(e[1]) for e in ev) / steps * 1e-3
+    t_collide = sum(e[1].elapsed_time(e[2]) for e in ev) / steps * 1e-3
+    nodes = g.ncells * g.nv
+    return dict(g=g, kw=kw, wall_s=wall_s, t_stream=t_stream, t_collide=t_collide, nodes=nodes,
+                value=nodes * steps / wall_s, pairs_per_s=g.ncells * g.n_pairs * steps / wall_s,
+                ms_per_step=wall_s / steps * 1e3)
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="cavity64")
-    ap.add_argument("--sample-group", type=int, default=None, help="cells sharing a pair stream (0 = all)")
+    ap.add_argument("--sample-group", type=int, default=0, help="cells sharing a pair stream (0 = all)")
     ap.add_argument("--order", type=int, default=None)
+    ap.add_argument("--variant", choices=["auto", "skip"], default="auto",
+                    help="also time the per-cell sample streams (G = 1)")
     ap.add_argument("--cpu-baseline", choices=["auto", "skip"], default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -94,77 +140,50 @@ def main():
 
     import paper_1005_5405_amd as pkg
 
-    preset = pkg.PRESETS[args.config]
-    over = {}
-    if args.sample_group is not None:
-        over["sample_group"] = args.sample_group
+    over = {"sample_group": args.sample_group}
     if args.order is not None:
         over["order"] = args.order
-    preset = preset.with_(**over) if over else preset
-    kw = preset.problem()
-    g = pkg.Boltz(**kw)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    a, b = g.empty(0.0), g.empty()
-    walls = pkg.Walls(lid_u=preset.lid(0.0))
-    n = 0
-    print("[bench] %s: %d cells x %d nodes, %d pairs/cell, G=%d, order %d; warm-up %d steps" %
-          (args.config, g.ncells, g.nv, g.n_pairs, kw["sample_group"], g.order, args.warmup), flush=True)
-    for _ in range(args.warmup):
-        walls.lid_u = preset.lid(n * g.dt)
-        g.stream(a, b, walls)
-        g.collide(b, b, n)
-        a, b = b, a
-        n += 1
-    torch.cuda.synchronize()
+    preset = pkg.PRESETS[args.config].with_(**over)
+    print("[bench] %s: G=%d, warm-up %d + %d timed steps" % (args.config, args.sample_group, args.warmup,
+                                                           args.steps), flush=True)
+    r = run(pkg, torch, preset, args.steps, args.warmup)
+    g, kw, nodes = r["g"], r["kw"], r["nodes"]
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
-    t0 = time.perf_counter()
-    for k in range(K):
-        walls.lid_u = preset.lid(n * g.dt)
-        ev[k][0].record(stream)
-        g.stream(a, b, walls)
-        ev[k][1].record(stream)
-        g.collide(b, b, n)
-        ev[k][2].record(stream)
-        a, b = b, a
-        n += 1
-    torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t0
-    t_stream = sum(e[0].elapsed_time(e[1]) for e in ev) / K * 1e-3
-    t_collide = sum(e[1].elapsed_time(e[2]) for e in ev) / K * 1e-3
-    t_events = ev[0][0].elapsed_time(ev[-1][2]) * 1e-3
-    status = g.read_status()
-    if status:
-        print("[bench] device status %d (numerical failure)" % status, file=sys.stderr, flush=True)
-        sys.exit(3)
-    ms_per_step = wall_s / K * 1e3
-    nodes = g.ncells * g.nv
-    value = nodes * K / wall_s
-    pairs_per_s = g.ncells * g.n_pairs * K / wall_s
-    hbm_step = 2 * BYTES_PER_NODE_KERNEL * nodes / (wall_s / K) / 1e9
-    # dominant kernel: the collision (sampling + gain/loss + correction)
-    ops = g.ncells * (g.n_pairs * OPS_PER_PAIR + g.nv * OPS_PER_NODE)
-    coll_bytes = BYTES_PER_NODE_KERNEL * nodes
-    roof = {"kernel": "collide_kernel", "bound": "alu", "achieved": ops / t_collide / 1e12,
-            "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": ops / t_collide / 1e12 / ALU_PEAK_TOPS,
-            "traffic": None, "avg_ms": t_collide * 1e3,
-            "hbm_algorithmic_GBs": coll_bytes / t_collide / 1e9,
-            "note": "lane operations per launch (OPS_PER_PAIR x pairs + OPS_PER_NODE x nodes) over the "
-                    "HIP-event average of the launch; peak = one vector op per lane per clock"}
-    stream_k = {"kernel": "wall_kernel + stream_kernel", "bound": "hbm", "avg_ms": t_stream * 1e3,
-                "achieved": BYTES_PER_NODE_KERNEL * nodes / t_stream / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": BYTES_PER_NODE_KERNEL * nodes / t_stream / 1e9 / HBM_PEAK_GBS}
-    line = {"metric": "phase-space node-updates/s (stream+collide), collision pairs/s, % HBM peak",
-            "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
-            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32", "data": "synthetic",
+    hbm_step = 2 * BYTES_PER_NODE_KERNEL * nodes / (r["wall_s"] / K) / 1e9
+    # dominant kernel group: the collision (pair table + collision kernel)
+    t_c = r["t_collide"]
+    coll_gbs = BYTES_PER_NODE_KERNEL * nodes / t_c / 1e9
+    pair_cells = g.ncells * g.n_pairs
+    atom_rate = LDS_ATOMICS_PER_PAIR * pair_cells / t_c / (N_CU * CLOCK_HZ)
+    roof = {"kernel": "collide_kernel + sample_kernel" if kw["sample_group"] != 1 else "collide_kernel",
+            "bound": "hbm", "achieved": coll_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": coll_gbs / HBM_PEAK_GBS, "traffic": None, "avg_ms": t_c * 1e3,
+            "algorithmic_bytes_per_launch": BYTES_PER_NODE_KERNEL * nodes,
+            "lds_atomic_lane_ops_per_clk_per_cu": atom_rate,
+            "note": "8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision "
+                    "launch group; the pair loop is bound by LDS integer atomics (4 per pair and cell), "
+                    "whose measured gfx950 rate is ~5.4 lane-ops/clk/CU"}
+    stream_gbs = BYTES_PER_NODE_KERNEL * nodes / r["t_stream"] / 1e9
+    stream_k = {"kernel": "ratio_kernel (when the walls change) + wall_kernel + stream4_kernel", "bound": "hbm",
+                "avg_ms": r["t_stream"] * 1e3, "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": stream_gbs / HBM_PEAK_GBS}
+    line = {"metric": METRIC, "value": r["value"], "unit": "node-updates/s", "n_gpus": 1, "steps": K,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": preset.name, "cells": [g.nx, g.ny], "velocity_grid": list(g.nv3),
                        "pairs_per_cell": g.n_pairs, "sample_group": kw["sample_group"], "order": g.order,
-                       "kn": preset.kn, "lid_u": preset.lid_u, "cfl": preset.cfl, "parallelism": "single GPU"},
-            "pairs_per_s": pairs_per_s, "hbm_frac_step": hbm_step / HBM_PEAK_GBS,
-            "event_ms_per_step": t_events / K * 1e3,
+                       "kn": preset.kn, "lid_u": preset.lid_u, "cfl": preset.cfl, "mix16": kw["mix16"],
+                       "parallelism": "single GPU"},
+            "pairs_per_s": r["pairs_per_s"], "hbm_frac_step": hbm_step / HBM_PEAK_GBS,
+            "event_ms_per_step": (r["t_stream"] + r["t_collide"]) * 1e3,
             "roofline": roof, "kernels": {"stream": stream_k}}
+    if args.variant == "auto" and kw["sample_group"] != 1:
+        print("[bench] variant: per-cell sample streams (G=1)", flush=True)
+        v = run(pkg, torch, preset.with_(sample_group=1), max(10, K // 4), max(3, args.warmup // 4))
+        line["variants"] = {"per_cell_samples_G1": {
+            "value": v["value"], "ms_per_step": v["ms_per_step"], "pairs_per_s": v["pairs_per_s"],
+            "collide_ms": v["t_collide"] * 1e3, "stream_ms": v["t_stream"] * 1e3,
+            "steps": max(10, K // 4)}}
     if args.cpu_baseline == "auto":
         print("[bench] CPU oracle baseline ...", flush=True)
         line["cpu_baseline"] = cpu_baseline(preset, args.cpu_seconds)

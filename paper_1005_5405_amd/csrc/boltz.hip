@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -38,10 +39,18 @@ struct boltz_ctx {
   void* dmem = nullptr;
   size_t dbytes = 0;
   Params P{};
-  size_t collide_lds = 0;
+  // collide launch: block size, accumulator kind, dynamic LDS and persistent
+  // grid of the fused-sampler [0] and shared-table [1] variants
   int collide_block = 256;
+  bool collide_fixed = true;
+  size_t collide_lds[2] = {0, 0};
+  int64_t collide_grid[2] = {0, 0};
   int64_t ngroups = 0;          // sample groups (shared-sample mode)
-  uint4* table = nullptr;       // ngroups * n_pairs pair records (G != 1)
+  // wall state the ratio tables Phi_w / Phi0 were last built for
+  WallArgs ratio_walls{};
+  bool ratio_valid = false;
+  uint2* tidx = nullptr;        // ngroups * n_pairs pair indices (G != 1)
+  float4* tcoef = nullptr;      // ngroups * n_pairs pair coefficients
   std::string err;
 };
 
@@ -75,10 +84,39 @@ bool walls_ok(const boltz_walls* w) {
          std::isfinite(w->lid_u);
 }
 
-int block_for_collide(int nv) {
-  if (nv <= 2048) return 256;
-  if (nv <= 10648) return 512;  // up to 22^3: two workgroups per CU
-  return 1024;
+constexpr size_t kLdsBytes = 160 * 1024;
+
+// static LDS of the collide kernel (block reduction scratch) per block size
+size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof(double) + 64; }
+
+// Accumulator kind and block size of the collide kernel: 64-bit fixed-point
+// accumulators when they fit next to the h tile and tables, else FP32; the
+// block size gives about 1024 resident threads per CU.
+bool pick_collide(int nv, int ns, bool& fixed, int& block) {
+  fixed = CollideLDS::bytes(nv, ns, true, true) + collide_static_lds(1024) <= kLdsBytes;
+  const size_t dyn = CollideLDS::bytes(nv, ns, fixed, true);
+  if (dyn + collide_static_lds(1024) > kLdsBytes) return false;
+  if (4 * (dyn + collide_static_lds(256)) <= kLdsBytes) block = 256;
+  else if (2 * (dyn + collide_static_lds(512)) <= kLdsBytes) block = 512;
+  else block = 1024;
+  // tuning override: BOLTZ_COLLIDE_BLOCK = 256 | 512 | 1024
+  if (const char* e = std::getenv("BOLTZ_COLLIDE_BLOCK")) {
+    const int b = std::atoi(e);
+    if ((b == 256 || b == 512 || b == 1024) && dyn + collide_static_lds(b) <= kLdsBytes) block = b;
+  }
+  return true;
+}
+
+const void* collide_fn(int block, bool table, bool fixed) {
+#define BOLTZ_COLLIDE_FN(B)                                                                      \
+  if (block == B)                                                                              \
+    return table ? (fixed ? (const void*)collide_kernel<B, true, true> : (const void*)collide_kernel<B, true, false>) \
+                 : (fixed ? (const void*)collide_kernel<B, false, true> : (const void*)collide_kernel<B, false, false>);
+  BOLTZ_COLLIDE_FN(256)
+  BOLTZ_COLLIDE_FN(512)
+  BOLTZ_COLLIDE_FN(1024)
+#undef BOLTZ_COLLIDE_FN
+  return nullptr;
 }
 
 }  // namespace
@@ -117,10 +155,11 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: invalid scalar parameter");
   const int64_t nvt = (int64_t)p->nv[0] * p->nv[1] * p->nv[2];
   const int nsum = p->nv[0] + p->nv[1] + p->nv[2];
-  const size_t lds = CollideLDS::bytes((int)nvt, nsum);
-  if (lds + 20 * 16 * sizeof(double) + 64 > 160 * 1024)
+  bool cfixed = true;
+  int cblock = 256;
+  if (nvt > (1 << 20) || !pick_collide((int)nvt, nsum, cfixed, cblock))
     return fail(nullptr, BOLTZ_EUNSUPPORTED,
-                "boltz_create: the per-cell h and Delta N tiles of this velocity grid exceed the 160 KB LDS");
+                "boltz_create: the per-cell h and increment tiles of this velocity grid exceed the 160 KB LDS");
   if ((int64_t)p->nx * p->ny * nvt >= ((int64_t)1 << 40))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: phase-space grid too large");
   const int64_t ncells_ = (int64_t)p->nx * p->ny;
@@ -204,8 +243,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->qfac = (p->n_pairs > 0) ? (c->dt * c->K) / (double)p->n_pairs : 0.0;
 
   // ---- host images of the device tables
-  std::vector<double> vtab(3 * kMaxAxis, 0.0), omtab(3 * kMaxAxis, 0.0);
-  std::vector<float> omf(3 * kMaxAxis, 0.f), pphi(3 * kMaxAxis, 0.f), punif(3 * kMaxAxis, 0.f);
+  std::vector<double> vtab(3 * kMaxAxis, 0.0), omtab(3 * kMaxAxis, 0.0), rwtab(3 * kMaxAxis, 0.0);
+  std::vector<float4> nqtab(3 * kMaxAxis, make_float4(0.f, 0.f, 0.f, 0.f));
   std::vector<uint8_t> icdf(3 * kFieldSize, 0);
   std::vector<float> cour(2 * kMaxAxis, 0.f), cour2(2 * kMaxAxis, 0.f);
   for (int k = 0; k < 3; ++k) {
@@ -213,9 +252,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     for (int i = 0; i < n; ++i) {
       vtab[k * kMaxAxis + i] = c->v[k][i];
       omtab[k * kMaxAxis + i] = c->om[k][i];
-      omf[k * kMaxAxis + i] = (float)c->om[k][i];
-      pphi[k * kMaxAxis + i] = (float)c->pphi[k][i];
-      punif[k * kMaxAxis + i] = (float)c->punif[k][i];
+      rwtab[k * kMaxAxis + i] = 1.0 / c->om[k][i];
+      nqtab[k * kMaxAxis + i] =
+          make_float4((float)c->om[k][i], (float)c->pphi[k][i], (float)c->punif[k][i], 0.f);
     }
     // direct inverse CDF of the Maxwellian law: icdf[f] = #{i >= 1 : T_i <= f}
     int idx = 0;
@@ -237,9 +276,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   size_t off = 0;
   const size_t o_v = off; off = align256(off + vtab.size() * 8);
   const size_t o_om = off; off = align256(off + omtab.size() * 8);
-  const size_t o_omf = off; off = align256(off + omf.size() * 4);
-  const size_t o_pphi = off; off = align256(off + pphi.size() * 4);
-  const size_t o_punif = off; off = align256(off + punif.size() * 4);
+  const size_t o_rw = off; off = align256(off + rwtab.size() * 8);
+  const size_t o_nq = off; off = align256(off + nqtab.size() * 16);
   const size_t o_icdf = off; off = align256(off + icdf.size());
   const size_t o_cour = off; off = align256(off + cour.size() * 4);
   const size_t o_cour2 = off; off = align256(off + cour2.size() * 4);
@@ -247,7 +285,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t o_ratio = off; off = align256(off + (size_t)4 * c->nv * 8);
   const size_t o_dpart = off; off = align256(off + (size_t)p->nx * 8);
   const size_t o_status = off; off = align256(off + 4);
-  const size_t o_table = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(uint4));
+  const size_t o_tidx = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(uint2));
+  const size_t o_tcoef = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(float4));
   (void)hipGetDevice(&c->device);
   hipError_t e = hipMalloc(&c->dmem, off);
   if (e != hipSuccess) {
@@ -258,8 +297,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   unsigned char* base = static_cast<unsigned char*>(c->dmem);
   struct Cp { size_t o; const void* src; size_t n; } cps[] = {
       {o_v, vtab.data(), vtab.size() * 8}, {o_om, omtab.data(), omtab.size() * 8},
-      {o_omf, omf.data(), omf.size() * 4}, {o_pphi, pphi.data(), pphi.size() * 4},
-      {o_punif, punif.data(), punif.size() * 4}, {o_icdf, icdf.data(), icdf.size()},
+      {o_rw, rwtab.data(), rwtab.size() * 8}, {o_nq, nqtab.data(), nqtab.size() * 16},
+      {o_icdf, icdf.data(), icdf.size()},
       {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4}};
   for (const Cp& cp : cps) {
     e = hipMemcpy(base + cp.o, cp.src, cp.n, hipMemcpyHostToDevice);
@@ -299,9 +338,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.qfac = c->qfac;
   P.vtab = reinterpret_cast<const double*>(base + o_v);
   P.omtab = reinterpret_cast<const double*>(base + o_om);
-  P.omf = reinterpret_cast<const float*>(base + o_omf);
-  P.pphi = reinterpret_cast<const float*>(base + o_pphi);
-  P.punif = reinterpret_cast<const float*>(base + o_punif);
+  P.rwtab = reinterpret_cast<const double*>(base + o_rw);
+  P.nqtab = reinterpret_cast<const float4*>(base + o_nq);
   P.icdf = reinterpret_cast<const uint8_t*>(base + o_icdf);
   P.cour = reinterpret_cast<const float*>(base + o_cour);
   P.cour2 = reinterpret_cast<const float*>(base + o_cour2);
@@ -310,21 +348,26 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.dpart = reinterpret_cast<double*>(base + o_dpart);
   P.status = reinterpret_cast<uint32_t*>(base + o_status);
   c->ngroups = ngroups;
-  c->table = ngroups ? reinterpret_cast<uint4*>(base + o_table) : nullptr;
-  c->collide_lds = lds;
-  c->collide_block = block_for_collide(c->nv);
-  hipError_t ea = hipSuccess;
-  const void* kfn[2] = {nullptr, nullptr};
-  switch (c->collide_block) {
-    case 256: kfn[0] = (const void*)collide_kernel<256, false>; kfn[1] = (const void*)collide_kernel<256, true>; break;
-    case 512: kfn[0] = (const void*)collide_kernel<512, false>; kfn[1] = (const void*)collide_kernel<512, true>; break;
-    default: kfn[0] = (const void*)collide_kernel<1024, false>; kfn[1] = (const void*)collide_kernel<1024, true>; break;
+  c->tidx = ngroups ? reinterpret_cast<uint2*>(base + o_tidx) : nullptr;
+  c->tcoef = ngroups ? reinterpret_cast<float4*>(base + o_tcoef) : nullptr;
+  c->collide_block = cblock;
+  c->collide_fixed = cfixed;
+  int ncu = 0;
+  hipError_t ea = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
+    const void* fn = collide_fn(cblock, t == 1, cfixed);
+    c->collide_lds[t] = CollideLDS::bytes(c->nv, nsum, cfixed, t == 0);
+    ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->collide_lds[t]);
+    int per_cu = 0;
+    if (ea == hipSuccess)
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cblock, c->collide_lds[t]);
+    if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
+    const int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
+    c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
   }
-  for (int t = 0; t < 2 && ea == hipSuccess; ++t)
-    ea = hipFuncSetAttribute(kfn[t], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (ea != hipSuccess) {
     boltz_destroy(c);
-    return fail(nullptr, BOLTZ_EHIP, std::string("boltz_create: hipFuncSetAttribute: ") + hipGetErrorString(ea));
+    return fail(nullptr, BOLTZ_EHIP, std::string("boltz_create: collide kernel set-up: ") + hipGetErrorString(ea));
   }
   *out = c;
   return BOLTZ_OK;
@@ -348,7 +391,16 @@ int boltz_axis_thresholds(const boltz_ctx* c, int axis, uint64_t* out) {
   return BOLTZ_OK;
 }
 
+static void ensure_ratio(boltz_ctx* c, const WallArgs& W, hipStream_t st) {
+  if (c->ratio_valid && std::memcmp(&c->ratio_walls, &W, sizeof(WallArgs)) == 0) return;
+  const int64_t n = 4 * (int64_t)c->nv;
+  hipLaunchKernelGGL(ratio_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c->P, W);
+  c->ratio_walls = W;
+  c->ratio_valid = true;
+}
+
 static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, hipStream_t st) {
+  ensure_ratio(c, W, st);
   if (c->p.order == 2) {
     // x faces first; the y faces read their densities for the x-swept rows
     hipLaunchKernelGGL(wall_kernel<0>, dim3(2 * c->p.ny), dim3(kWallBlock), 0, st, c->P, W, h);
@@ -361,53 +413,73 @@ static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, hipStre
 }
 
 static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_t st) {
-  const int tiles_x = (c->p.nx + kTX - 1) / kTX, tiles_y = (c->p.ny + kTY - 1) / kTY;
-  const int nchunks = (c->nv + kJ - 1) / kJ;
-  const long long total = (long long)tiles_x * tiles_y * nchunks;
-  const int per_xcd = (int)((total + 7) / 8);
-  const dim3 grid((unsigned)(8 * (long long)per_xcd));
-  if (c->p.order == 2)
-    hipLaunchKernelGGL(stream_kernel<2>, grid, dim3(kStreamBlock), 0, st, c->P, hin, hout, tiles_x, tiles_y,
-                       nchunks, per_xcd);
-  else
-    hipLaunchKernelGGL(stream_kernel<1>, grid, dim3(kStreamBlock), 0, st, c->P, hin, hout, tiles_x, tiles_y,
-                       nchunks, per_xcd);
+  if (c->n[2] % 4 == 0) {
+    // velocity groups of four share (jx, jy): vector kernel
+    const int tiles_x = (c->p.nx + kTX4 - 1) / kTX4, tiles_y = (c->p.ny + kTY4 - 1) / kTY4;
+    const int nchunks = (c->nv + kJ4 - 1) / kJ4;
+    const long long total = (long long)tiles_x * tiles_y * nchunks;
+    const int per_xcd = (int)((total + 7) / 8);
+    const dim3 grid((unsigned)(8 * (long long)per_xcd));
+    if (c->p.order == 2)
+      hipLaunchKernelGGL(stream4_kernel<2>, grid, dim3(kStream4Block), 0, st, c->P, hin, hout, tiles_x, tiles_y,
+                         nchunks, per_xcd);
+    else
+      hipLaunchKernelGGL(stream4_kernel<1>, grid, dim3(kStream4Block), 0, st, c->P, hin, hout, tiles_x, tiles_y,
+                         nchunks, per_xcd);
+  } else {
+    const int tiles_x = (c->p.nx + kTX - 1) / kTX, tiles_y = (c->p.ny + kTY - 1) / kTY;
+    const int nchunks = (c->nv + kJ - 1) / kJ;
+    const long long total = (long long)tiles_x * tiles_y * nchunks;
+    const int per_xcd = (int)((total + 7) / 8);
+    const dim3 grid((unsigned)(8 * (long long)per_xcd));
+    if (c->p.order == 2)
+      hipLaunchKernelGGL(stream_kernel<2>, grid, dim3(kStreamBlock), 0, st, c->P, hin, hout, tiles_x, tiles_y,
+                         nchunks, per_xcd);
+    else
+      hipLaunchKernelGGL(stream_kernel<1>, grid, dim3(kStreamBlock), 0, st, c->P, hin, hout, tiles_x, tiles_y,
+                         nchunks, per_xcd);
+  }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream_kernel launch");
 }
 
-extern "C++" template <bool TABLE>
-static void launch_collide_t(boltz_ctx* c, const float* hs, float* hout, uint32_t s32, uint32_t flags,
+extern "C++" template <int B>
+static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
                              double* defect, hipStream_t st) {
-  const dim3 grid((unsigned)c->ncells);
-  switch (c->collide_block) {
-    case 256:
-      hipLaunchKernelGGL((collide_kernel<256, TABLE>), grid, dim3(256), c->collide_lds, st, c->P, hs, hout, s32,
-                         flags, defect, c->table);
-      break;
-    case 512:
-      hipLaunchKernelGGL((collide_kernel<512, TABLE>), grid, dim3(512), c->collide_lds, st, c->P, hs, hout, s32,
-                         flags, defect, c->table);
-      break;
-    default:
-      hipLaunchKernelGGL((collide_kernel<1024, TABLE>), grid, dim3(1024), c->collide_lds, st, c->P, hs, hout, s32,
-                         flags, defect, c->table);
-      break;
+  const int t = table ? 1 : 0;
+  const dim3 grid((unsigned)c->collide_grid[t]);
+  const size_t lds = c->collide_lds[t];
+  if (table) {
+    if (c->collide_fixed)
+      hipLaunchKernelGGL((collide_kernel<B, true, true>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
+                         c->tidx, c->tcoef);
+    else
+      hipLaunchKernelGGL((collide_kernel<B, true, false>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
+                         c->tidx, c->tcoef);
+  } else {
+    if (c->collide_fixed)
+      hipLaunchKernelGGL((collide_kernel<B, false, true>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags,
+                         defect, c->tidx, c->tcoef);
+    else
+      hipLaunchKernelGGL((collide_kernel<B, false, false>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags,
+                         defect, c->tidx, c->tcoef);
   }
 }
 
 static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
                           double* defect, hipStream_t st) {
   const uint32_t s32 = (uint32_t)step;
-  if (c->ngroups > 0) {
-    if (c->p.n_pairs > 0) {
-      const int nsum = c->n[0] + c->n[1] + c->n[2];
-      const dim3 grid((unsigned)((c->p.n_pairs + 255) / 256), (unsigned)c->ngroups);
-      hipLaunchKernelGGL(sample_kernel, grid, dim3(256), CollideLDS::tables_bytes(nsum), st, c->P, s32, c->table);
-    }
-    launch_collide_t<true>(c, hs, hout, s32, flags, defect, st);
-  } else {
-    launch_collide_t<false>(c, hs, hout, s32, flags, defect, st);
+  const bool table = c->ngroups > 0;
+  if (table && c->p.n_pairs > 0) {
+    const int nsum = c->n[0] + c->n[1] + c->n[2];
+    const dim3 grid((unsigned)((c->p.n_pairs + 255) / 256), (unsigned)c->ngroups);
+    hipLaunchKernelGGL(sample_kernel, grid, dim3(256), TablesLDS::bytes(nsum, true), st, c->P, s32, c->tidx,
+                       c->tcoef);
+  }
+  switch (c->collide_block) {
+    case 256: launch_collide_b<256>(c, table, hs, hout, s32, flags, defect, st); break;
+    case 512: launch_collide_b<512>(c, table, hs, hout, s32, flags, defect, st); break;
+    default: launch_collide_b<1024>(c, table, hs, hout, s32, flags, defect, st); break;
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "collide_kernel launch");
@@ -459,6 +531,7 @@ int boltz_moments(boltz_ctx* c, const float* h, const boltz_walls* walls, double
     return fail(c, BOLTZ_EINVAL, "boltz_moments: lid shear needs a cavity and valid walls");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const WallArgs W = make_walls(walls);
+  if (lid_shear) ensure_ratio(c, W, st);
   hipLaunchKernelGGL(moments_kernel, dim3((unsigned)c->ncells), dim3(256), 0, st, c->P, W, h, mom,
                      lid_shear ? 1 : 0);
   if (lid_shear) hipLaunchKernelGGL(lid_reduce_kernel, dim3(1), dim3(64), 0, st, c->P, lid_shear);
@@ -488,7 +561,7 @@ int boltz_debug_pairs(boltz_ctx* c, int64_t cell, int64_t step, int64_t m0, int6
   double* d_q = reinterpret_cast<double*>(b + ((bi + 7) & ~(size_t)7));
   uint32_t* d_w = words ? reinterpret_cast<uint32_t*>(b + ((bi + 7) & ~(size_t)7) + bq) : nullptr;
   const int nsum = c->n[0] + c->n[1] + c->n[2];
-  const size_t lds = CollideLDS::tables_bytes(nsum);
+  const size_t lds = TablesLDS::bytes(nsum, true);
   const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 1024);
   hipLaunchKernelGGL(debug_pairs_kernel, dim3(blocks), dim3(256), lds, 0, c->P, cell, (uint32_t)step, m0, count,
                      d_idx, d_q, d_w);

@@ -1,0 +1,493 @@
+// collide.hpp -- S3-S5 of one step on gfx950: the Monte Carlo pair sampler
+// (Sec. 3, Eqs. coll8Dim, monteCarloInt), the shared-sample table pass, and
+// the collision kernel with its conservation correction (Eqs.
+// collision_step, rinorm_a, correzione).  Included by kernels.hpp.
+#pragma once
+
+#include "device_math.hpp"
+
+namespace boltz {
+
+// ---------------------------------------------------------------- tables --
+// LDS copies of the per-axis tables, ns = n0 + n1 + n2 entries each:
+//   v, om            always (moment sums and the correction)
+//   nq, rw, icdf     only where pairs are drawn
+struct TablesLDS {
+  double* v;      // node velocities
+  double* om;     // omega, FP64
+  float4* nq;     // {omega, p_phi, p_unif, 0}, FP32
+  double* rw;     // 1 / omega, FP64
+  uint8_t* icdf;  // [3 * kFieldSize] Maxwellian inverse CDF on 12-bit fields
+
+  static __host__ __device__ size_t bytes(int ns, bool sampler) {
+    size_t b = 16 * (size_t)ns;
+    if (sampler) b += 24 * (size_t)ns + 3 * (size_t)kFieldSize;
+    return b;
+  }
+};
+
+// base: 16-byte aligned LDS.  The caller synchronises before use.
+__device__ __forceinline__ void load_tables(const Params& P, unsigned char* base, bool sampler, TablesLDS& T) {
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2], ns = n0 + n1 + n2;
+  T.v = reinterpret_cast<double*>(base);
+  T.om = T.v + ns;
+  T.nq = reinterpret_cast<float4*>(T.om + ns);
+  T.rw = reinterpret_cast<double*>(T.nq + ns);
+  T.icdf = reinterpret_cast<uint8_t*>(T.rw + ns);
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int k = i < n0 ? 0 : (i < n0 + n1 ? 1 : 2);
+    const int o = k * kMaxAxis + i - (k == 0 ? 0 : (k == 1 ? n0 : n0 + n1));
+    T.v[i] = P.vtab[o];
+    T.om[i] = P.omtab[o];
+    if (sampler) {
+      T.nq[i] = P.nqtab[o];
+      T.rw[i] = P.rwtab[o];
+    }
+  }
+  if (sampler) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(P.icdf);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(T.icdf);
+    for (int i = threadIdx.x; i < 3 * kFieldSize / 4; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
+// ----------------------------------------------------------------- S3 --
+// Importance weights of a drawn node (i, j, k): r = w / p~ and s = 1 / p~,
+// with w the midpoint weight of Phi0 and p~ = (1 - beta) p_phi + beta p_unif
+// the probability of drawing it from the mixture law.  FP32.
+struct NodeWeight {
+  float r, s;
+};
+
+__device__ __forceinline__ NodeWeight node_weight(const TablesLDS& T, float beta, float obeta, int i, int j, int k,
+                                                  int n0, int n1) {
+  const float4 x = T.nq[i], y = T.nq[n0 + j], z = T.nq[n0 + n1 + k];
+  const float w = (x.x * y.x) * z.x;
+  const float pm = (x.y * y.y) * z.y;
+  const float pu = (x.z * y.z) * z.z;
+  const float s = 1.0f / (obeta * pm + beta * pu);
+  NodeWeight o;
+  o.r = w * s;
+  o.s = s;
+  return o;
+}
+
+// One Monte Carlo collision sample.  The four coefficients are the weight q
+// of Eq. coll8Dim divided by the midpoint weight of the node it lands on, so
+// that the sample changes h by +k g at a*, b* and by -k g at a, b with
+// g = h_a + h_b + eps h_a h_b (Eqs. monteCarloInt, collision_step).
+struct Pair {
+  int a, b, as, bs;   // node indices; as = bs = -1 when discarded
+  double q;           // dt K |v_r . k| (w_a / p~_a)(w_b / p~_b) / N_t
+  double kas, kbs;    // q / w_{a*}, q / w_{b*}
+  double ka, kb;      // q / w_a, q / w_b
+};
+
+// One Philox4x32-10 block with counter (m, group, step, cavity) per sample:
+//   r0 = [a_x:12][a_y:12][choice_a:4][choice_b:4]
+//   r1 = [a_z:12][b_x:12][phi_hi:8]   r2 = [b_y:12][b_z:12][phi_lo:8]   r3 = u
+// nodes from the Maxwellian law, or the uniform law when the choice nibble
+// is below mix16; k_z = 2 (r3 + 1/2) 2^-32 - 1, azimuth 2 pi (phi + 1/2) 2^-16;
+// v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a;
+// post-collision cells floor((x + a) n / 2a), discard outside the box.
+__device__ __forceinline__ Pair sample_pair(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
+                                            uint32_t m, u32x4* words) {
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const u32x4 c = {m, group, step, P.cavity};
+  uint32_t k0 = P.key0, k1 = P.key1;
+  // an empty statement that keeps the key words opaque, so the round keys
+  // are rebuilt by scalar adds inside the caller's loop instead of being
+  // hoisted into twenty scalar registers
+  asm volatile("" : "+s"(k0), "+s"(k1));
+  const u32x4 r = philox4x32_10(c, k0, k1);
+  if (words) words[0] = r;
+  const bool ua = ((r.x >> 4) & 15u) < P.mix16;
+  const bool ub = (r.x & 15u) < P.mix16;
+  const uint32_t fax = r.x >> 20, fay = (r.x >> 8) & 0xFFFu, faz = r.y >> 20;
+  const uint32_t fbx = (r.y >> 8) & 0xFFFu, fby = r.z >> 20, fbz = (r.z >> 8) & 0xFFFu;
+  // both laws evaluated, then selected (no divergent branch)
+  const int max_ = (int)T.icdf[fax], may = (int)T.icdf[kFieldSize + fay], maz = (int)T.icdf[2 * kFieldSize + faz];
+  const int mbx = (int)T.icdf[fbx], mby = (int)T.icdf[kFieldSize + fby], mbz = (int)T.icdf[2 * kFieldSize + fbz];
+  const int iax = ua ? uniform_draw(fax, n0) : max_;
+  const int iay = ua ? uniform_draw(fay, n1) : may;
+  const int iaz = ua ? uniform_draw(faz, n2) : maz;
+  const int ibx = ub ? uniform_draw(fbx, n0) : mbx;
+  const int iby = ub ? uniform_draw(fby, n1) : mby;
+  const int ibz = ub ? uniform_draw(fbz, n2) : mbz;
+  const uint32_t phi = ((r.y & 0xFFu) << 8) | (r.z & 0xFFu);
+  const double u6 = ((double)r.w + 0.5) * 0x1p-32;
+  const double u7 = ((double)phi + 0.5) * 0x1p-16;
+  const double kz = 2.0 * u6 - 1.0;
+  const double s = sqrt((1.0 - kz) * (1.0 + kz));
+  double cp, sp;
+  cos_sin_2pi(u7, cp, sp);
+  const double kx = s * cp, ky = s * sp;
+  const double* vx = T.v;
+  const double* vy = T.v + n0;
+  const double* vz = T.v + n0 + n1;
+  const double vax = vx[iax], vay = vy[iay], vaz = vz[iaz];
+  const double vbx = vx[ibx], vby = vy[iby], vbz = vz[ibz];
+  const double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
+  const double alpha = (vrx * kx + vry * ky) + vrz * kz;
+  const double ddx = alpha * kx, ddy = alpha * ky, ddz = alpha * kz;
+  const double tsx = floor((vax + ddx + P.a[0]) * P.inv_cell[0]);
+  const double tsy = floor((vay + ddy + P.a[1]) * P.inv_cell[1]);
+  const double tsz = floor((vaz + ddz + P.a[2]) * P.inv_cell[2]);
+  const double ttx = floor((vbx - ddx + P.a[0]) * P.inv_cell[0]);
+  const double tty = floor((vby - ddy + P.a[1]) * P.inv_cell[1]);
+  const double ttz = floor((vbz - ddz + P.a[2]) * P.inv_cell[2]);
+  // inside the box iff 0 <= floor < n per component (the integer conversion
+  // saturates, so far-out values fail the unsigned test as well)
+  const int sx = (int)tsx, sy = (int)tsy, sz = (int)tsz, tx = (int)ttx, ty = (int)tty, tz = (int)ttz;
+  const bool kept = ((unsigned)sx < (unsigned)n0) & ((unsigned)sy < (unsigned)n1) & ((unsigned)sz < (unsigned)n2) &
+                    ((unsigned)tx < (unsigned)n0) & ((unsigned)ty < (unsigned)n1) & ((unsigned)tz < (unsigned)n2);
+  Pair p;
+  p.a = (iax * n1 + iay) * n2 + iaz;
+  p.b = (ibx * n1 + iby) * n2 + ibz;
+  if (kept) {
+    p.as = (sx * n1 + sy) * n2 + sz;
+    p.bs = (tx * n1 + ty) * n2 + tz;
+    const float beta = (float)P.beta;
+    const NodeWeight wa = node_weight(T, beta, 1.0f - beta, iax, iay, iaz, n0, n1);
+    const NodeWeight wb = node_weight(T, beta, 1.0f - beta, ibx, iby, ibz, n0, n1);
+    const double qa = P.qfac * fabs(alpha);
+    const double ra = (double)wa.r, rb = (double)wb.r;
+    p.q = (qa * ra) * rb;
+    p.ka = (qa * (double)wa.s) * rb;
+    p.kb = (qa * ra) * (double)wb.s;
+    p.kas = p.q * ((T.rw[sx] * T.rw[n0 + sy]) * T.rw[n0 + n1 + sz]);
+    p.kbs = p.q * ((T.rw[tx] * T.rw[n0 + ty]) * T.rw[n0 + n1 + tz]);
+  } else {
+    p.as = -1;
+    p.bs = -1;
+    p.q = 0.0;
+    p.kas = p.kbs = p.ka = p.kb = 0.0;
+  }
+  return p;
+}
+
+// Test hook kernel: the pairs of (cell, step, m0 + i) from the same sampler.
+__global__ __launch_bounds__(256) void debug_pairs_kernel(Params P, int64_t cell, uint32_t step, int64_t m0,
+                                                          int64_t count, int32_t* idx4, double* q,
+                                                          uint32_t* words) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  TablesLDS T;
+  load_tables(P, dsm, true, T);
+  __syncthreads();
+  const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    u32x4 w;
+    const Pair p = sample_pair(P, T, group, step, (uint32_t)(m0 + i), &w);
+    idx4[4 * i + 0] = p.a;
+    idx4[4 * i + 1] = p.b;
+    idx4[4 * i + 2] = p.as;
+    idx4[4 * i + 3] = p.bs;
+    q[i] = p.q;
+    if (words) {
+      words[4 * i + 0] = w.x;
+      words[4 * i + 1] = w.y;
+      words[4 * i + 2] = w.z;
+      words[4 * i + 3] = w.w;
+    }
+  }
+}
+
+// Shared-sample mode (G != 1): the N_t pairs of every sample group are drawn
+// once per step into two arrays, idx = {a | b << 16, a* | b* << 16} and
+// coef = {q/w_a*, q/w_b*, q/w_a, q/w_b} in FP32; a discarded pair is stored
+// with a* = a, b* = b and zero coefficients.
+__global__ __launch_bounds__(256) void sample_kernel(Params P, uint32_t step, uint2* __restrict__ tidx,
+                                                     float4* __restrict__ tcoef) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  TablesLDS T;
+  load_tables(P, dsm, true, T);
+  __syncthreads();
+  const int64_t nt = P.n_pairs;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t group = blockIdx.y;
+  if (i >= nt) return;
+  const Pair p = sample_pair(P, T, group, step, (uint32_t)i, nullptr);
+  uint2 id;
+  id.x = (uint32_t)p.a | ((uint32_t)p.b << 16);
+  id.y = p.as >= 0 ? ((uint32_t)p.as | ((uint32_t)p.bs << 16)) : id.x;
+  tidx[(int64_t)group * nt + i] = id;
+  tcoef[(int64_t)group * nt + i] = make_float4((float)p.kas, (float)p.kbs, (float)p.ka, (float)p.kb);
+}
+
+// ------------------------------------------------------------------- S5 --
+// Solve of the 5x5 SPD system M x = r, M given by the packed upper triangle
+// of its 15 sums (row k, columns l >= k), by the LDL^T factorisation (unit
+// lower L, diagonal D): five reciprocals of the pivots, no square roots.
+//   E_ij = L_ij D_j = M_ij - sum_{k<j} L_ik E_jk,  L_ij = E_ij / D_j,
+//   D_i = M_ii - sum_{k<i} L_ik E_ik;  L y = r, x = L^-T (D^-1 y).
+// false when a pivot is not positive (M not positive definite).
+__device__ __forceinline__ bool solve5(const double* S, const double* r, double* x) {
+  double A[5][5];
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int l = k; l < 5; ++l) A[l][k] = S[t++];
+  double L[5][5], E[5][5], rd[5];
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double d = A[i][i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      double e = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) e -= L[i][k] * E[j][k];
+      E[i][j] = e;
+      L[i][j] = e * rd[j];
+      d -= L[i][j] * e;
+    }
+    ok = ok && (d > 0.0);
+    rd[i] = 1.0 / (d > 0.0 ? d : 1.0);
+  }
+  double y[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double v = r[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+    y[i] = v;
+  }
+#pragma unroll
+  for (int i = 4; i >= 0; --i) {
+    double v = y[i] * rd[i];
+#pragma unroll
+    for (int k = i + 1; k < 5; ++k) v -= L[k][i] * x[k];
+    x[i] = v;
+  }
+  return ok;
+}
+
+// ------------------------------------------------------------ collision --
+// Dynamic LDS of the collide kernel: the h^s tile (FP32), the increment
+// accumulators (64-bit fixed point plus an FP32 array for large values, or
+// FP32 alone when those do not fit), then the tables.  The FP32 array comes
+// first and holds h^c after the pair loop.
+struct CollideLDS {
+  static __host__ __device__ size_t tile(int nv) { return ((size_t)nv * 4 + 15) & ~(size_t)15; }
+  static __host__ __device__ size_t acc(int nv, bool fixed) {
+    return tile(nv) + (fixed ? (((size_t)nv * 8 + 15) & ~(size_t)15) : 0);
+  }
+  static __host__ __device__ size_t bytes(int nv, int ns, bool fixed, bool sampler) {
+    return tile(nv) + acc(nv, fixed) + TablesLDS::bytes(ns, sampler);
+  }
+};
+
+// float4 registers per thread holding the next cell's h^s tile
+constexpr int kPrefetch = 4;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct Prefetch {
+  f32x4 r0, r1, r2, r3;
+  // every lane loads (indices clamped into the tile) so the registers are
+  // always defined and the loads stay in flight until the next tile store
+  __device__ __forceinline__ void load(const float* src, int i, int stride, int n) {
+    const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
+    r0 = s4[min(i, n - 1)];
+    r1 = s4[min(i + stride, n - 1)];
+    r2 = s4[min(i + 2 * stride, n - 1)];
+    r3 = s4[min(i + 3 * stride, n - 1)];
+  }
+  __device__ __forceinline__ void store(float* dst, int i, int stride, int n) const {
+    f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+    if (i < n) d4[i] = r0;
+    if (i + stride < n) d4[i + stride] = r1;
+    if (i + 2 * stride < n) d4[i + 2 * stride] = r2;
+    if (i + 3 * stride < n) d4[i + 3 * stride] = r3;
+  }
+};
+
+// Scatter of one sample: +k_as g at a*, +k_bs g at b*, -k_a g at a, -k_b g
+// at b, in units of h (the increment Delta N / w of Eq. collision_step).
+template <bool FIXED>
+__device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, int a, int b, int as, int bs,
+                                        double kas, double kbs, double ka, double kb, float g) {
+  if (FIXED) {
+    const double gd = (double)g;
+    lds_add_hybrid(acc64, accf, as, kas, gd);
+    lds_add_hybrid(acc64, accf, bs, kbs, gd);
+    lds_add_hybrid(acc64, accf, a, -ka, gd);
+    lds_add_hybrid(acc64, accf, b, -kb, gd);
+  } else {
+    float* acc = accf;
+    lds_add(&acc[as], (float)kas * g);
+    lds_add(&acc[bs], (float)kbs * g);
+    lds_add(&acc[a], -((float)ka * g));
+    lds_add(&acc[b], -((float)kb * g));
+  }
+}
+
+// Persistent workgroups: workgroup b collides cells b, b + gridDim.x, ...;
+// the h^s tile of the next cell is loaded into registers while the pairs of
+// the current one are processed.  TABLE: the pairs come from the records of
+// sample_kernel (cells of one group share them).  FIXED: 64-bit fixed-point
+// accumulation (else FP32 compare-and-swap).  h_s may equal h_out.
+template <int BLOCK, bool TABLE, bool FIXED>
+__global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* hs_g, float* hout_g, uint32_t step,
+                                                        uint32_t flags, double* __restrict__ defect,
+                                                        const uint2* __restrict__ tidx,
+                                                        const float4* __restrict__ tcoef) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  __shared__ double red[20 * (BLOCK / 64)];
+  __shared__ double tot[20];
+  const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const int64_t ncells = (int64_t)P.nx * P.ny;
+  const int tid = threadIdx.x;
+  float* hs = reinterpret_cast<float*>(dsm);
+  float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
+  unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(dsm + 2 * CollideLDS::tile(nv));
+  TablesLDS T;
+  load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, FIXED), !TABLE, T);
+  const double* vx = T.v;
+  const double* vy = T.v + n0;
+  const double* vz = T.v + n0 + n1;
+  const double* omx = T.om;
+  const double* omy = T.om + n0;
+  const double* omz = T.om + n0 + n1;
+  const bool correct = !(flags & 1u);
+  const double eps = P.eps;
+  const float epsf = (float)P.eps;
+  const uint32_t nt = (uint32_t)P.n_pairs;
+  const int nv4 = nv >> 2;
+  const bool vec = ((nv & 3) == 0) && nv4 <= kPrefetch * BLOCK;
+  Prefetch pre;
+  int64_t cell = blockIdx.x;
+  if (vec && cell < ncells) pre.load(hs_g + cell * nv, tid, BLOCK, nv4);
+  for (; cell < ncells; cell += gridDim.x) {
+    // ---- h^s tile in, accumulators cleared
+    if (vec) {
+      pre.store(hs, tid, BLOCK, nv4);
+    } else {
+      const float* src = hs_g + cell * nv;
+      for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
+    }
+    {
+      uint4* z = reinterpret_cast<uint4*>(accf);
+      const int nz = (int)(CollideLDS::acc(nv, FIXED) / 16);
+      for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+    const int64_t next = cell + gridDim.x;
+    if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
+    // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
+    const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
+    if (TABLE) {
+      const uint2* ri = tidx + (int64_t)group * nt;
+      const float4* rk = tcoef + (int64_t)group * nt;
+      uint32_t m = tid;
+      for (; m + BLOCK < nt; m += 2 * BLOCK) {
+        const uint2 i0 = ri[m], i1 = ri[m + BLOCK];
+        const float4 k0 = rk[m], k1 = rk[m + BLOCK];
+        const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
+        const int a1 = (int)(i1.x & 0xFFFFu), b1 = (int)(i1.x >> 16);
+        const float ha0 = hs[a0], hb0 = hs[b0], ha1 = hs[a1], hb1 = hs[b1];
+        const float g0 = (ha0 + hb0) + (epsf * ha0) * hb0;
+        const float g1 = (ha1 + hb1) + (epsf * ha1) * hb1;
+        scatter<FIXED>(accf, acc64, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w, g0);
+        scatter<FIXED>(accf, acc64, a1, b1, (int)(i1.y & 0xFFFFu), (int)(i1.y >> 16), k1.x, k1.y, k1.z, k1.w, g1);
+      }
+      if (m < nt) {
+        const uint2 i0 = ri[m];
+        const float4 k0 = rk[m];
+        const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
+        const float ha0 = hs[a0], hb0 = hs[b0];
+        const float g0 = (ha0 + hb0) + (epsf * ha0) * hb0;
+        scatter<FIXED>(accf, acc64, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w, g0);
+      }
+    } else {
+      for (uint32_t m = tid; m < nt; m += BLOCK) {
+        const Pair p = sample_pair(P, T, group, step, m, nullptr);
+        if (p.as >= 0) {
+          const float ha = hs[p.a], hb = hs[p.b];
+          const float g = (ha + hb) + (epsf * ha) * hb;
+          scatter<FIXED>(accf, acc64, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+        }
+      }
+    }
+    __syncthreads();
+    // ---- S5: h^c = h^s + increment (stored over the accumulator), FP64
+    // sums M_kl = sum w F^c psi_k psi_l and r_k = -eps sum w psi_k (h^c - h^s)
+    double acc[20];
+#pragma unroll
+    for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+    {
+      NodeWalk nw(tid, BLOCK, n1, n2);
+      for (int j = tid; j < nv; j += BLOCK, nw.next()) {
+        const int jx = nw.jx, jy = nw.jy, jz = nw.jz;
+        const float hsj = hs[j];
+        double dh = (double)accf[j];
+        if (FIXED) dh += from_fixed(acc64[j]);
+        const float hc = (float)((double)hsj + dh);
+        accf[j] = hc;
+        if (correct) {
+          const double w = (omx[jx] * omy[jy]) * omz[jz];
+          const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+          const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
+          const double wF = w * fma(eps, (double)hc, 1.0);
+          const double psi[5] = {1.0, v1, v2, v3, vv};
+          int t = 0;
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            const double wk = wF * psi[k];
+#pragma unroll
+            for (int l = k; l < 5; ++l) acc[t] = fma(wk, psi[l], acc[t]), ++t;
+          }
+          const double edn = -eps * (w * ((double)hc - (double)hsj));
+#pragma unroll
+          for (int k = 0; k < 5; ++k) acc[15 + k] = fma(edn, psi[k], acc[15 + k]);
+        }
+      }
+    }
+    double x[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (correct) {
+      // every thread solves the same system from the totals in LDS
+      block_sum20_lds(acc, red, tot);
+      if (!solve5(tot, tot + 15, x)) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[k] = 0.0;
+        if (tid == 0) atomicOr(P.status, 1u);
+      }
+    }
+    // ---- h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
+    double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    bool finite = true;
+    float* dst = hout_g + cell * nv;
+    NodeWalk nw2(tid, BLOCK, n1, n2);
+    for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
+      const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
+      const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+      const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
+      const double hc = (double)accf[j];
+      float out = (float)hc;
+      if (correct) {
+        const double xpsi = fma(x[4], vv, fma(x[3], v3, fma(x[2], v2, fma(x[1], v1, x[0]))));
+        out = (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc);
+      }
+      finite = finite && isfinite(out);
+      dst[j] = out;
+      if (defect) {
+        const double w = (omx[jx] * omy[jy]) * omz[jz];
+        const double diff = eps * ((double)out - (double)hs[j]) * w;
+        dsum[0] += diff;
+        dsum[1] += v1 * diff;
+        dsum[2] += v2 * diff;
+        dsum[3] += v3 * diff;
+        dsum[4] += vv * diff;
+      }
+    }
+    if (!finite) atomicOr(P.status, 2u);
+    if (defect) {
+      block_sum<5>(dsum, red);
+      if (tid < 5) defect[cell * 5 + tid] = dsum[tid];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace boltz

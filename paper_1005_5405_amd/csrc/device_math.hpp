@@ -93,12 +93,32 @@ __device__ __forceinline__ float bw_update(float h0, float h1, float h2, float C
   return h0 - C * (h0 - h1) - c2 * ((h0 - 2.0f * h1) + h2);
 }
 
+// ------------------------------------------------ fixed-point LDS sums --
+// Increments of h are accumulated as signed 64-bit integers in units of
+// 2^-32 with the integer LDS atomic add, which on gfx950 runs an order of
+// magnitude faster than any float accumulation in LDS and is associative,
+// so the sums do not depend on the order of the lanes.  A value c with
+// |c| < 2^18 is rounded to the 2^-32 grid by adding 1.5 * 2^20 (whose FP64
+// ulp is 2^-32, round to nearest even); the difference of the two bit
+// patterns is then round(c 2^32) (the low word of 1.5 * 2^20 is zero).  Larger contributions (deviations in the
+// far tail of the velocity grid, where Phi0 is tiny and |h| can grow by many
+// orders of magnitude) and non-finite ones go to an FP32 accumulator
+// instead, so no value is clipped.
+constexpr double kFixMagic = 1572864.0;               // 1.5 * 2^20
+constexpr double kFixLimit = 262144.0;                // 2^18
+constexpr double kFixScale = 2.3283064365386963e-10;  // 2^-32
+
+__device__ __forceinline__ double from_fixed(unsigned long long v) {
+  return (double)(long long)v * kFixScale;
+}
+
 // ------------------------------------------------------- LDS float add --
 // Float accumulation into LDS as a read plus a 32-bit compare-and-swap,
 // retried when another lane changed the word.  On gfx950 the native LDS
 // float atomic add completes about one lane every three clocks per CU
 // whatever the address pattern, while integer LDS atomics run ~28x faster;
-// the compare-and-swap form keeps exact FP32 addition semantics.
+// the compare-and-swap form keeps exact FP32 addition semantics.  Used when
+// the 64-bit accumulators of a large velocity grid do not fit in LDS.
 __device__ __forceinline__ void lds_add(float* p, float v) {
   unsigned* u = reinterpret_cast<unsigned*>(p);
   unsigned old = *u;
@@ -107,6 +127,22 @@ __device__ __forceinline__ void lds_add(float* p, float v) {
     const unsigned prev = atomicCAS(u, old, nw);
     if (prev == old) break;
     old = prev;
+  }
+}
+
+// One contribution k g to node j: 64-bit fixed point when |k g| < 2^18,
+// else the FP32 accumulator ovf[j].  fma(k, g, 1.5 * 2^20) rounds the exact
+// product once onto the 2^-32 grid; the high word of the bit difference
+// then lies in [-2^18, 2^18) exactly for the values kept in fixed point
+// (the bit patterns of positive doubles are ordered like their values;
+// negative, infinite and NaN sums fall outside that window).
+__device__ __forceinline__ void lds_add_hybrid(unsigned long long* acc, float* ovf, int j, double k, double g) {
+  const long long d = __double_as_longlong(fma(k, g, kFixMagic)) - __double_as_longlong(kFixMagic);
+  const int hi = (int)(d >> 32);
+  if ((unsigned)(hi + (1 << 18)) < (1u << 19)) {
+    __hip_atomic_fetch_add(&acc[j], (unsigned long long)d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    lds_add(&ovf[j], (float)(k * g));
   }
 }
 
@@ -159,6 +195,53 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += red[i * nw + w];
     v[i] = s;
+  }
+  __syncthreads();
+}
+
+// Halving step of a multi-value wavefront reduction: v[0..N) becomes
+// v[0..H), H = (N + 1) / 2, where lanes with (lane & OFF) == 0 keep the sums
+// of the lower half (v[i] + partner's v[i]) and the others those of the upper
+// half (v[H + i], zero-padded when N is odd).
+template <int N, int OFF>
+__device__ __forceinline__ void fold_half(double* v, bool upper) {
+  constexpr int H = (N + 1) / 2;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double lo = v[i];
+    const double hi = (H + i < N) ? v[H + i] : 0.0;
+    const double send = upper ? lo : hi;
+    const double keep = upper ? hi : lo;
+    v[i] = keep + __shfl_xor(send, OFF, 64);
+  }
+}
+
+// Sum of 20 values per thread over the whole block into tot[0..20) in LDS
+// (blockDim.x a multiple of 64).  Within a wavefront the values are halved
+// at every exchange (offsets 32, 16, 8, 4, 2, then a plain pairwise sum),
+// 22 exchanges instead of 120; lane l then holds value
+// 10 b5 + 5 b4 + 3 b3 + 2 b2 + b1 of its bits b_k (or a zero pad).  The
+// wavefront sums are added in wavefront order.  Deterministic order.
+// red: LDS scratch of 20 * (blockDim.x / 64) doubles.  v is consumed.
+__device__ __forceinline__ void block_sum20_lds(double (&v)[20], double* red, double* tot) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  fold_half<20, 32>(v, lane & 32);
+  fold_half<10, 16>(v, lane & 16);
+  fold_half<5, 8>(v, lane & 8);
+  fold_half<3, 4>(v, lane & 4);
+  fold_half<2, 2>(v, lane & 2);
+  const double s = v[0] + __shfl_xor(v[0], 1, 64);
+  const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1,
+            b1 = (lane >> 1) & 1;
+  // positions within the last group of five: b3 b2 b1 -> 0,1,2,pad,3,4,pad,pad
+  const int pos = 3 * b3 + 2 * b2 + b1;
+  const bool valid = ((lane & 1) == 0) && (b3 ? (b2 == 0) : (pos < 3));
+  if (valid) red[(10 * b5 + 5 * b4 + pos) * nw + wid] = s;
+  __syncthreads();
+  if (threadIdx.x < 20) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[threadIdx.x * nw + w];
+    tot[threadIdx.x] = t;
   }
   __syncthreads();
 }

@@ -6,12 +6,14 @@
 //   stream_kernel    S2  one HBM pass: (8x8 cells + halo) x 32 velocities per
 //                        workgroup staged in LDS; order 1 = Eq. streaming2D,
 //                        order 2 = Beam-Warming x sweep then y sweep
-//   collide_kernel   S3-S5  one workgroup per spatial cell: the cell's h and
-//                        Delta N tiles live in LDS, lanes draw Philox pairs,
-//                        gather h_a, h_b and scatter gain/loss with LDS
-//                        atomics (Eqs. monteCarloInt, collision_step), then
-//                        FP64 moment sums, a 5x5 Cholesky solve and the
-//                        correction of Eq. rinorm_a, one coalesced store
+//   collide_kernel   S3-S5  (collide.hpp) persistent workgroups walking the
+//                        spatial cells: the cell's h tile and its increment
+//                        accumulators live in LDS, lanes draw Philox pairs
+//                        (or read the shared-sample table), gather h_a, h_b
+//                        and scatter gain/loss with LDS atomics (Eqs.
+//                        monteCarloInt, collision_step), then FP64 moment
+//                        sums, a 5x5 Cholesky solve and the correction of
+//                        Eq. rinorm_a, one coalesced store
 //   moments_kernel   S6  FP64 moments per cell (Eqs. densita..sforzi) and the
 //                        lid-face shear partial sums
 #pragma once
@@ -34,9 +36,9 @@ struct Params {
   double a[3], inv_cell[3];
   const double* vtab;     // [3][kMaxAxis] node velocities
   const double* omtab;    // [3][kMaxAxis] per-axis weights omega
-  const float* omf;      // [3][kMaxAxis] omega in FP32 (importance weights)
-  const float* pphi;      // [3][kMaxAxis] realised per-axis Maxwellian law
-  const float* punif;     // [3][kMaxAxis] realised per-axis uniform law
+  const double* rwtab;    // [3][kMaxAxis] 1 / omega
+  const float4* nqtab;    // [3][kMaxAxis] {omega, p_phi, p_unif, 0} in FP32: weight
+                          // and realised Maxwellian / uniform laws of one axis
   const uint8_t* icdf;    // [3][kFieldSize] Maxwellian inverse CDF on 12-bit fields
   const float* cour;      // [2][kMaxAxis] Courant number |v| dt / d{x,y}
   const float* cour2;     // [2][kMaxAxis] C (1 - C) / 2
@@ -93,9 +95,7 @@ __device__ float xswept_value(const Params& P, const WallArgs& W, const float* h
       hn[d - 1] = h[cell_off(P, i, iy) + j];
     } else {
       const int wall = (i < 0) ? WALL_LEFT : WALL_RIGHT;
-      const double R = wall_ratio(vx, P.vtab[kMaxAxis + jy], P.vtab[2 * kMaxAxis + jz], 0.0,
-                                  W.tau[wall], W.tfac[wall]);
-      hn[d - 1] = ghost_value(i < 0 ? nwl : nwr, R, P.inv_eps);
+      hn[d - 1] = ghost_value(i < 0 ? nwl : nwr, P.ratio[(int64_t)wall * P.nv + j], P.inv_eps);
     }
   }
   return bw_update(h0, hn[0], hn[1], P.cour[jx], P.cour2[jx]);
@@ -120,7 +120,6 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
     default: ax_ = pos; ay_ = ny - 1; bx_ = pos; by_ = ny - 2; break;
   }
   const double dl = nax ? P.dy : P.dx;
-  const double Uw = (wall == WALL_TOP) ? W.lid_u : 0.0;
   const bool ysw = (order == 2) && (nax == 1);
   double s[3] = {0.0, 0.0, 0.0};
   // four nodes per thread and pass, so that their loads are in flight together
@@ -140,8 +139,7 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
       const double w = (P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz];
       int mx = jx, my = jy;
       if (nax == 0) mx = P.n[0] - 1 - jx; else my = n1 - 1 - jy;
-      const double R = wall_ratio(P.vtab[mx], P.vtab[kMaxAxis + my], P.vtab[2 * kMaxAxis + jz], Uw,
-                                  W.tau[wall], W.tfac[wall]);
+      const double R = P.ratio[(int64_t)wall * nv + (mx * n1 + my) * n2 + jz];
       double ha, hb = 0.0;
       if (ysw) {
         ha = xswept_value(P, W, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
@@ -167,12 +165,25 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
 
 constexpr int kWallBlock = 512;
 
+// Phi_w / Phi0 of every wall and node: ratio[wall * nv + j] (FP64).  Only the
+// lid moves (velocity lid_u along x); every wall has its own temperature.
+__global__ __launch_bounds__(256) void ratio_kernel(Params P, WallArgs W) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 4 * (int64_t)P.nv) return;
+  const int wall = (int)(i / P.nv), j = (int)(i - (int64_t)wall * P.nv);
+  int jx, jy, jz;
+  node_decode(j, P.n[1], P.n[2], jx, jy, jz);
+  const double Uw = (wall == WALL_TOP) ? W.lid_u : 0.0;
+  P.ratio[i] = wall_ratio(P.vtab[jx], P.vtab[kMaxAxis + jy], P.vtab[2 * kMaxAxis + jz], Uw, W.tau[wall],
+                          W.tfac[wall]);
+}
+
 // One workgroup per boundary face, faces numbered left[ny], right[ny],
 // bottom[nx], top[nx].  PHASE 0 handles the x faces (and, for order 1, the y
 // faces too); PHASE 1 the y faces of order 2, whose face values come from
 // the x-swept boundary rows and therefore need the x-face densities of the
-// previous launch.  The first face of every wall also fills that wall's
-// ratio table Phi_w / Phi0 for the stream kernel.  Cavity problems only.
+// previous launch.  The ratio tables Phi_w / Phi0 come from ratio_kernel.
+// Cavity problems only.
 template <int PHASE>
 __global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, const float* __restrict__ h) {
   __shared__ double red[3 * (kWallBlock / 64)];
@@ -184,15 +195,6 @@ __global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, 
   else if (f < 2 * P.ny) { wall = WALL_RIGHT; pos = f - P.ny; }
   else if (f < 2 * P.ny + P.nx) { wall = WALL_BOTTOM; pos = f - 2 * P.ny; }
   else { wall = WALL_TOP; pos = f - 2 * P.ny - P.nx; }
-  if (pos == 0) {
-    const double Uw = (wall == WALL_TOP) ? W.lid_u : 0.0;
-    NodeWalk walk(threadIdx.x, blockDim.x, P.n[1], P.n[2]);
-    for (int j = threadIdx.x; j < P.nv; j += blockDim.x, walk.next()) {
-      P.ratio[(int64_t)wall * P.nv + j] = wall_ratio(P.vtab[walk.jx], P.vtab[kMaxAxis + walk.jy],
-                                                     P.vtab[2 * kMaxAxis + walk.jz], Uw, W.tau[wall],
-                                                     W.tfac[wall]);
-    }
-  }
   double nwl0 = 0.0, nwl1 = 0.0, nwr0 = 0.0, nwr1 = 0.0;
   if (PHASE == 1) {
     // x-wall densities of the two boundary rows next to this y face
@@ -350,378 +352,150 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
   }
 }
 
-// --------------------------------------------------------------- S3, S4 --
-// LDS copies of the per-axis tables used by the pair sampler.
-struct SamplerLDS {
-  double* v;        // [n0 + n1 + n2] node velocities
-  double* om;       // [n0 + n1 + n2] omega (FP64, moment sums)
-  float* omf;       // [n0 + n1 + n2] omega (FP32, weights)
-  float* pphi;      // [n0 + n1 + n2]
-  float* punif;     // [n0 + n1 + n2]
-  uint8_t* icdf;    // [3 * kFieldSize]
-};
+// Vector form of the stream kernel for velocity grids with n_z % 4 == 0
+// (then every aligned group of four consecutive velocities shares (jx, jy):
+// one sign and one Courant number per axis).  One workgroup: 16 x 8 cells
+// and 32 velocities; thread (column c, group q) owns four velocities of one
+// column.  The raw block with its upwind halo is staged in LDS; each thread
+// then x-sweeps the rows of its column into registers and applies the y
+// sweep from that register window (order 2), or the unsplit first-order
+// stencil (order 1).  Same arithmetic per element as stream_kernel.
+constexpr int kTX4 = 16, kTY4 = 8, kJ4 = 32, kStream4Block = kTX4 * (kJ4 / 4);
 
-// w_a / p~_a in FP32: midpoint weight of Phi0 over the probability of drawing
-// node (i, j, k) from (1 - beta) Maxwellian law + beta uniform law.
-__device__ __forceinline__ float node_ratio(const SamplerLDS& T, float beta, int i, int j, int k, int n0,
-                                            int n1) {
-  const float w = (T.omf[i] * T.omf[n0 + j]) * T.omf[n0 + n1 + k];
-  const float pm = (T.pphi[i] * T.pphi[n0 + j]) * T.pphi[n0 + n1 + k];
-  const float pu = (T.punif[i] * T.punif[n0 + j]) * T.punif[n0 + n1 + k];
-  return w / ((1.0f - beta) * pm + beta * pu);
+__device__ __forceinline__ float4 ghost4(double nwv, const double* R, double inv_eps) {
+  return make_float4(ghost_value(nwv, R[0], inv_eps), ghost_value(nwv, R[1], inv_eps),
+                     ghost_value(nwv, R[2], inv_eps), ghost_value(nwv, R[3], inv_eps));
 }
 
-struct Pair {
-  int a, b, as, bs;  // node indices; as = bs = -1 when discarded
-  float q;
-};
-
-// One Monte Carlo collision sample from one Philox4x32-10 block with counter
-// (m, group, step, cavity):
-//   r0 = [a_x:12][a_y:12][choice_a:4][choice_b:4]
-//   r1 = [a_z:12][b_x:12][phi_hi:8]   r2 = [b_y:12][b_z:12][phi_lo:8]   r3 = u
-// nodes from the Maxwellian law, or the uniform law when the choice nibble
-// is below mix16; k_z = 2 (r3 + 1/2) 2^-32 - 1, azimuth 2 pi (phi + 1/2) 2^-16;
-// v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a;
-// post-collision cells floor((x + a) n / 2a), discard outside the box;
-// q = qfac |v_r.k| (w_a/p~_a)(w_b/p~_b), qfac = dt K / N_t.
-__device__ __forceinline__ Pair sample_pair(const Params& P, const SamplerLDS& T, uint32_t group,
-                                            uint32_t step, uint32_t m, u32x4* words) {
-  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
-  const u32x4 c = {m, group, step, P.cavity};
-  const u32x4 r = philox4x32_10(c, P.key0, P.key1);
-  if (words) words[0] = r;
-  const bool ua = ((r.x >> 4) & 15u) < P.mix16;
-  const bool ub = (r.x & 15u) < P.mix16;
-  const uint32_t fax = r.x >> 20, fay = (r.x >> 8) & 0xFFFu, faz = r.y >> 20;
-  const uint32_t fbx = (r.y >> 8) & 0xFFFu, fby = r.z >> 20, fbz = (r.z >> 8) & 0xFFFu;
-  const int iax = ua ? uniform_draw(fax, n0) : (int)T.icdf[fax];
-  const int iay = ua ? uniform_draw(fay, n1) : (int)T.icdf[kFieldSize + fay];
-  const int iaz = ua ? uniform_draw(faz, n2) : (int)T.icdf[2 * kFieldSize + faz];
-  const int ibx = ub ? uniform_draw(fbx, n0) : (int)T.icdf[fbx];
-  const int iby = ub ? uniform_draw(fby, n1) : (int)T.icdf[kFieldSize + fby];
-  const int ibz = ub ? uniform_draw(fbz, n2) : (int)T.icdf[2 * kFieldSize + fbz];
-  const uint32_t phi = ((r.y & 0xFFu) << 8) | (r.z & 0xFFu);
-  const double u6 = ((double)r.w + 0.5) * 0x1p-32;
-  const double u7 = ((double)phi + 0.5) * 0x1p-16;
-  const double kz = 2.0 * u6 - 1.0;
-  const double s = sqrt((1.0 - kz) * (1.0 + kz));
-  double cp, sp;
-  cos_sin_2pi(u7, cp, sp);
-  const double kx = s * cp, ky = s * sp;
-  const double* vx = T.v;
-  const double* vy = T.v + n0;
-  const double* vz = T.v + n0 + n1;
-  const double vax = vx[iax], vay = vy[iay], vaz = vz[iaz];
-  const double vbx = vx[ibx], vby = vy[iby], vbz = vz[ibz];
-  const double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
-  const double alpha = (vrx * kx + vry * ky) + vrz * kz;
-  const double ddx = alpha * kx, ddy = alpha * ky, ddz = alpha * kz;
-  const double tsx = floor((vax + ddx + P.a[0]) * P.inv_cell[0]);
-  const double tsy = floor((vay + ddy + P.a[1]) * P.inv_cell[1]);
-  const double tsz = floor((vaz + ddz + P.a[2]) * P.inv_cell[2]);
-  const double ttx = floor((vbx - ddx + P.a[0]) * P.inv_cell[0]);
-  const double tty = floor((vby - ddy + P.a[1]) * P.inv_cell[1]);
-  const double ttz = floor((vbz - ddz + P.a[2]) * P.inv_cell[2]);
-  const bool kept = tsx >= 0.0 && tsx < (double)n0 && tsy >= 0.0 && tsy < (double)n1 && tsz >= 0.0 &&
-                    tsz < (double)n2 && ttx >= 0.0 && ttx < (double)n0 && tty >= 0.0 &&
-                    tty < (double)n1 && ttz >= 0.0 && ttz < (double)n2;
-  Pair p;
-  p.a = (iax * n1 + iay) * n2 + iaz;
-  p.b = (ibx * n1 + iby) * n2 + ibz;
-  if (kept) {
-    p.as = ((int)tsx * n1 + (int)tsy) * n2 + (int)tsz;
-    p.bs = ((int)ttx * n1 + (int)tty) * n2 + (int)ttz;
-    const float beta = (float)P.beta;
-    p.q = ((float)(P.qfac * fabs(alpha)) * node_ratio(T, beta, iax, iay, iaz, n0, n1)) *
-          node_ratio(T, beta, ibx, iby, ibz, n0, n1);
-  } else {
-    p.as = -1;
-    p.bs = -1;
-    p.q = 0.0f;
-  }
-  return p;
+__device__ __forceinline__ float4 bw4(float4 h0, float4 h1, float4 h2, float C, float c2) {
+  return make_float4(bw_update(h0.x, h1.x, h2.x, C, c2), bw_update(h0.y, h1.y, h2.y, C, c2),
+                     bw_update(h0.z, h1.z, h2.z, C, c2), bw_update(h0.w, h1.w, h2.w, C, c2));
 }
 
-// Layout of the dynamic LDS of the collide kernel: h^s and Delta N tiles,
-// then the sampler tables.
-struct CollideLDS {
-  static __host__ __device__ size_t tables_bytes(int nsum) {
-    return 2 * (size_t)nsum * sizeof(double) + 3 * (size_t)nsum * sizeof(float) + 3 * kFieldSize;
-  }
-  static __host__ __device__ size_t bytes(int nv, int nsum) {
-    size_t b = 2 * (size_t)nv * sizeof(float);
-    b = (b + 7) & ~(size_t)7;
-    return b + tables_bytes(nsum);
-  }
-};
-
-__device__ __forceinline__ void load_sampler_tables(const Params& P, unsigned char* base, SamplerLDS& T) {
-  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2], ns = n0 + n1 + n2;
-  T.v = reinterpret_cast<double*>(base);
-  T.om = T.v + ns;
-  T.omf = reinterpret_cast<float*>(T.om + ns);
-  T.pphi = T.omf + ns;
-  T.punif = T.pphi + ns;
-  T.icdf = reinterpret_cast<uint8_t*>(T.punif + ns);
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    const int k = i < n0 ? 0 : (i < n0 + n1 ? 1 : 2);
-    const int o = i - (k == 0 ? 0 : (k == 1 ? n0 : n0 + n1));
-    T.v[i] = P.vtab[k * kMaxAxis + o];
-    T.om[i] = P.omtab[k * kMaxAxis + o];
-    T.omf[i] = P.omf[k * kMaxAxis + o];
-    T.pphi[i] = P.pphi[k * kMaxAxis + o];
-    T.punif[i] = P.punif[k * kMaxAxis + o];
-  }
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(P.icdf);
-  uint32_t* dst = reinterpret_cast<uint32_t*>(T.icdf);
-  for (int i = threadIdx.x; i < 3 * kFieldSize / 4; i += blockDim.x) dst[i] = src[i];
-}
-
-// Test hook kernel: the pairs of (cell, step, m0 + i) from the same sampler.
-__global__ __launch_bounds__(256) void debug_pairs_kernel(Params P, int64_t cell, uint32_t step, int64_t m0,
-                                                          int64_t count, int32_t* idx4, double* q,
-                                                          uint32_t* words) {
-  extern __shared__ __align__(16) unsigned char dsm[];
-  SamplerLDS T;
-  load_sampler_tables(P, dsm, T);
-  __syncthreads();
-  const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-    u32x4 w;
-    const Pair p = sample_pair(P, T, group, step, (uint32_t)(m0 + i), &w);
-    idx4[4 * i + 0] = p.a;
-    idx4[4 * i + 1] = p.b;
-    idx4[4 * i + 2] = p.as;
-    idx4[4 * i + 3] = p.bs;
-    q[i] = (double)p.q;
-    if (words) {
-      words[4 * i + 0] = w.x;
-      words[4 * i + 1] = w.y;
-      words[4 * i + 2] = w.z;
-      words[4 * i + 3] = w.w;
-    }
-  }
-}
-
-// Shared-sample mode (G != 1): one pass draws the N_t pairs of every sample
-// group once per step into 16-byte records {a | b << 16, a* | b* << 16,
-// q bits, 0}; a discarded pair is stored with a* = a, b* = b and q = 0.
-__global__ __launch_bounds__(256) void sample_kernel(Params P, uint32_t step, uint4* __restrict__ table) {
-  extern __shared__ __align__(16) unsigned char dsm[];
-  SamplerLDS T;
-  load_sampler_tables(P, dsm, T);
-  __syncthreads();
-  const int64_t nt = P.n_pairs;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t group = blockIdx.y;
-  if (i >= nt) return;
-  const Pair p = sample_pair(P, T, group, step, (uint32_t)i, nullptr);
-  uint4 rec;
-  rec.x = (uint32_t)p.a | ((uint32_t)p.b << 16);
-  rec.y = p.as >= 0 ? ((uint32_t)p.as | ((uint32_t)p.bs << 16)) : rec.x;
-  rec.z = __float_as_uint(p.q);
-  rec.w = 0u;
-  table[(int64_t)group * nt + i] = rec;
-}
-
-// ------------------------------------------------------------------- S5 --
-// Cholesky solve of the 5x5 SPD system (packed upper triangle of 15 sums).
-__device__ bool solve5(const double* S, const double* r, double* x) {
-  double M[5][5];
-  int t = 0;
-  for (int k = 0; k < 5; ++k)
-    for (int l = k; l < 5; ++l) {
-      M[k][l] = S[t];
-      M[l][k] = S[t];
-      ++t;
-    }
-  double L[5][5];
-  for (int i = 0; i < 5; ++i)
-    for (int j = 0; j < 5; ++j) L[i][j] = 0.0;
-  for (int i = 0; i < 5; ++i) {
-    for (int j = 0; j <= i; ++j) {
-      double s = M[i][j];
-      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-      if (i == j) {
-        if (!(s > 0.0)) return false;
-        L[i][i] = sqrt(s);
-      } else {
-        L[i][j] = s / L[j][j];
-      }
-    }
-  }
-  double y[5];
-  for (int i = 0; i < 5; ++i) {
-    double s = r[i];
-    for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
-    y[i] = s / L[i][i];
-  }
-  for (int i = 4; i >= 0; --i) {
-    double s = y[i];
-    for (int k = i + 1; k < 5; ++k) s -= L[k][i] * x[k];
-    x[i] = s / L[i][i];
-  }
-  return true;
-}
-
-// One workgroup per spatial cell (blockIdx.x = cell).  TABLE: the pairs come
-// from the records of sample_kernel (cells of one group share them) instead
-// of being drawn by the workgroup itself.
-template <int BLOCK, bool TABLE>
-__global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* __restrict__ hs_g,
-                                                        float* __restrict__ hout_g, uint32_t step,
-                                                        uint32_t flags, double* __restrict__ defect,
-                                                        const uint4* __restrict__ table) {
-  extern __shared__ __align__(16) unsigned char dsm[];
-  __shared__ double red[20 * (BLOCK / 64)];
-  __shared__ double xs[5];
-  const int nv = P.nv, n1 = P.n[1], n2 = P.n[2], n0 = P.n[0];
-  const int64_t cell = blockIdx.x;
-  float* hs = reinterpret_cast<float*>(dsm);
-  float* dN = hs + nv;
-  size_t off = (2 * (size_t)nv * sizeof(float) + 7) & ~(size_t)7;
-  SamplerLDS T;
-  load_sampler_tables(P, dsm + off, T);
-  const double* om = T.om;
-  const float* src = hs_g + cell * nv;
-  if ((nv & 3) == 0) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
-    float4* h4 = reinterpret_cast<float4*>(hs);
-    float4* d4 = reinterpret_cast<float4*>(dN);
-    for (int i = threadIdx.x; i < (nv >> 2); i += BLOCK) {
-      h4[i] = s4[i];
-      d4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-  } else {
-    for (int i = threadIdx.x; i < nv; i += BLOCK) {
-      hs[i] = src[i];
-      dN[i] = 0.0f;
-    }
-  }
-  __syncthreads();
-  // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
-  const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
-  const float epsf = (float)P.eps;
-  const uint32_t nt = (uint32_t)P.n_pairs;
-  if (TABLE) {
-    const uint4* rec = table + (int64_t)group * nt;
-    for (uint32_t m = threadIdx.x; m < nt; m += BLOCK) {
-      const uint4 r = rec[m];
-      const int a = (int)(r.x & 0xFFFFu), b = (int)(r.x >> 16);
-      const int as = (int)(r.y & 0xFFFFu), bs = (int)(r.y >> 16);
-      const float ha = hs[a], hb = hs[b];
-      const float g = (ha + hb) + (epsf * ha) * hb;
-      const float qg = __uint_as_float(r.z) * g;
-      lds_add(&dN[as], qg);
-      lds_add(&dN[bs], qg);
-      lds_add(&dN[a], -qg);
-      lds_add(&dN[b], -qg);
-    }
-  } else {
-    for (uint32_t m = threadIdx.x; m < nt; m += BLOCK) {
-      const Pair p = sample_pair(P, T, group, step, m, nullptr);
-      if (p.as >= 0) {
-        const float ha = hs[p.a], hb = hs[p.b];
-        const float g = (ha + hb) + (epsf * ha) * hb;
-        const float qg = p.q * g;
-        lds_add(&dN[p.as], qg);
-        lds_add(&dN[p.bs], qg);
-        lds_add(&dN[p.a], -qg);
-        lds_add(&dN[p.b], -qg);
-      }
-    }
-  }
-  __syncthreads();
-  const double* vx = T.v;
-  const double* vy = T.v + n0;
-  const double* vz = T.v + n0 + n1;
-  const double* omx = om;
-  const double* omy = om + n0;
-  const double* omz = om + n0 + n1;
-  const bool correct = !(flags & 1u);
-  const double eps = P.eps;
-  // ---- S5: h^c = h^s + dN / w, FP64 sums M_kl = sum w F^c psi_k psi_l and
-  // r_k = -eps sum psi_k dN; h^c replaces dN in LDS.
-  double acc[20];
-#pragma unroll
-  for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+template <int ORDER>
+__global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const float* __restrict__ hin,
+                                                                float* __restrict__ hout, int tiles_x,
+                                                                int tiles_y, int nchunks, int per_xcd) {
+  constexpr int H = ORDER;
+  constexpr int AX = kTX4 + 2 * H, AY = kTY4 + 2 * H;
+  constexpr int Q = kJ4 / 4;
+  __shared__ float4 A4[AY * AX * Q];
+  const int ntiles = tiles_x * tiles_y;
+  const int total = ntiles * nchunks;
+  const int unit = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (unit >= total) return;
+  const int chunk = unit / ntiles, tile = unit % ntiles;
+  const int ix0 = (tile % tiles_x) * kTX4, iy0 = (tile / tiles_x) * kTY4;
+  const int j0 = chunk * kJ4;
+  const int nx = P.nx, ny = P.ny, nv = P.nv;
+  const int n1 = P.n[1], n2 = P.n[2];
+  const bool periodic = (P.bc == 1);
+  const int jlast = min(j0 + kJ4, nv) - 1;
+  int fx, fy, fz, lx, ly, lz;
+  node_decode(j0, n1, n2, fx, fy, fz);
+  node_decode(jlast, n1, n2, lx, ly, lz);
+  const bool needL = P.vtab[lx] > 0.0, needR = P.vtab[fx] < 0.0;
+  const bool oneX = (fx == lx);
+  const bool needB = !oneX || P.vtab[kMaxAxis + ly] > 0.0;
+  const bool needT = !oneX || P.vtab[kMaxAxis + fy] < 0.0;
+  const int c_lo = needL ? 0 : H, c_hi = needR ? AX : AX - H;
+  const int r_lo = needB ? 0 : H, r_hi = needT ? AY : AY - H;
+  // ---- stage the block; outside the cavity: the wall's re-emitted values
   {
-    NodeWalk nw(threadIdx.x, BLOCK, n1, n2);
-    for (int j = threadIdx.x; j < nv; j += BLOCK, nw.next()) {
-      const int jx = nw.jx, jy = nw.jy, jz = nw.jz;
-      const double w = (omx[jx] * omy[jy]) * omz[jz];
-      const double dn = (double)dN[j];
-      const float hc = (float)((double)hs[j] + dn / w);
-      dN[j] = hc;
-      if (correct) {
-        const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-        const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
-        const double wF = w * fma(eps, (double)hc, 1.0);
-        const double psi[5] = {1.0, v1, v2, v3, vv};
-        int t = 0;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          const double wk = wF * psi[k];
-#pragma unroll
-          for (int l = k; l < 5; ++l) acc[t] = fma(wk, psi[l], acc[t]), ++t;
+    const int q = threadIdx.x % Q;
+    const int jq = j0 + 4 * q;
+    for (int cidx = threadIdx.x / Q; cidx < AY * AX; cidx += kStream4Block / Q) {
+      const int r = cidx / AX, c = cidx - (cidx / AX) * AX;
+      if (r < r_lo || r >= r_hi || c < c_lo || c >= c_hi || jq >= nv) continue;
+      const int iy = iy0 - H + r, ix = ix0 - H + c;
+      const bool inY = iy >= 0 && iy < ny, inX = ix >= 0 && ix < nx;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (periodic || (inX && inY)) {
+        const int64_t base = cell_off(P, periodic ? wrapi(ix, nx) : ix, periodic ? wrapi(iy, ny) : iy);
+        v = *reinterpret_cast<const float4*>(hin + base + jq);
+      } else if (inY || (ORDER == 1 && inX)) {
+        int wall;
+        double nwv;
+        if (inY) {
+          wall = ix < 0 ? WALL_LEFT : WALL_RIGHT;
+          nwv = P.nw[(wall == WALL_LEFT ? 0 : ny) + iy];
+        } else {
+          wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
+          nwv = P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix];
         }
-        const double edn = -eps * dn;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) acc[15 + k] = fma(edn, psi[k], acc[15 + k]);
+        v = ghost4(nwv, P.ratio + (int64_t)wall * nv + jq, P.inv_eps);
       }
+      A4[cidx * Q + q] = v;
     }
   }
-  if (correct) {
-    block_sum<20>(acc, red);
-    if (threadIdx.x == 0) {
-      double x[5];
-      if (!solve5(acc, acc + 15, x)) {
-        for (int k = 0; k < 5; ++k) x[k] = 0.0;
-        atomicOr(P.status, 1u);
-      }
-      for (int k = 0; k < 5; ++k) xs[k] = x[k];
-    }
-  }
+  const int q = threadIdx.x % Q, c = threadIdx.x / Q;
+  const int jq = j0 + 4 * q;
+  const int ix = ix0 + c;
+  const bool ok = jq < nv && ix < nx;
+  int jx = 0, jy = 0, jz = 0;
+  if (jq < nv) node_decode(jq, n1, n2, jx, jy, jz);
+  const double vx = P.vtab[jx], vy = P.vtab[kMaxAxis + jy];
+  const int sx = vx > 0.0 ? 1 : (vx < 0.0 ? -1 : 0);
+  const int sy = vy > 0.0 ? 1 : (vy < 0.0 ? -1 : 0);
+  const float Cx = P.cour[jx], Cx2 = P.cour2[jx];
+  const float Cy = P.cour[kMaxAxis + jy], Cy2 = P.cour2[kMaxAxis + jy];
   __syncthreads();
-  double x[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (correct) {
+  if (!ok) return;
+  if (ORDER == 2) {
+    // x-swept rows iy0 - 2 .. iy0 + kTY4 + 1 of this column (only the rows
+    // on the upwind side in y are formed)
+    float4 hx[AY];
+    const int xc = c + 2;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) x[k] = xs[k];
-  }
-  // ---- h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
-  double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  bool finite = true;
-  float* dst = hout_g + cell * nv;
-  NodeWalk nw2(threadIdx.x, BLOCK, n1, n2);
-  for (int j = threadIdx.x; j < nv; j += BLOCK, nw2.next()) {
-    const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
-    const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-    const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
-    const double hc = (double)dN[j];
-    float out = (float)hc;
-    if (correct) {
-      const double xpsi = fma(x[4], vv, fma(x[3], v3, fma(x[2], v2, fma(x[1], v1, x[0]))));
-      out = (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc);
+    for (int r = 0; r < AY; ++r) {
+      hx[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < r_lo || r >= r_hi) continue;
+      const int iy = iy0 - 2 + r;
+      if (!periodic && (iy < 0 || iy >= ny)) {
+        const int wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
+        hx[r] = ghost4(P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix], P.ratio + (int64_t)wall * nv + jq,
+                       P.inv_eps);
+      } else {
+        const float4* row = &A4[(r * AX + xc) * Q + q];
+        const float4 h0 = row[0];
+        hx[r] = (sx == 0) ? h0 : bw4(h0, row[-sx * Q], row[-2 * sx * Q], Cx, Cx2);
+      }
     }
-    finite = finite && isfinite(out);
-    dst[j] = out;
-    if (defect) {
-      const double w = (omx[jx] * omy[jy]) * omz[jz];
-      const double diff = eps * ((double)out - (double)hs[j]) * w;
-      dsum[0] += diff;
-      dsum[1] += v1 * diff;
-      dsum[2] += v2 * diff;
-      dsum[3] += v3 * diff;
-      dsum[4] += vv * diff;
+    float* dst = hout + jq;
+#pragma unroll
+    for (int r = 0; r < kTY4; ++r) {
+      const int iy = iy0 + r;
+      if (iy >= ny) break;
+      const float4 h0 = hx[r + 2];
+      const float4 out = (sy == 0) ? h0
+                         : (sy > 0 ? bw4(h0, hx[r + 1], hx[r], Cy, Cy2) : bw4(h0, hx[r + 3], hx[r + 4], Cy, Cy2));
+      *reinterpret_cast<float4*>(dst + cell_off(P, ix, iy)) = out;
     }
-  }
-  if (!finite) atomicOr(P.status, 2u);
-  if (defect) {
-    block_sum<5>(dsum, red);
-    if (threadIdx.x < 5) defect[cell * 5 + threadIdx.x] = dsum[threadIdx.x];
+  } else {
+    float* dst = hout + jq;
+#pragma unroll
+    for (int r = 0; r < kTY4; ++r) {
+      const int iy = iy0 + r;
+      if (iy >= ny) break;
+      const float4* ctr = &A4[((r + 1) * AX + c + 1) * Q + q];
+      const float4 h0 = ctr[0];
+      const float4 hxn = (sx == 0) ? h0 : ctr[-sx * Q];
+      const float4 hyn = (sy == 0) ? h0 : ctr[-sy * AX * Q];
+      float4 out;
+      out.x = h0.x + Cx * (hxn.x - h0.x) + Cy * (hyn.x - h0.x);
+      out.y = h0.y + Cx * (hxn.y - h0.y) + Cy * (hyn.y - h0.y);
+      out.z = h0.z + Cx * (hxn.z - h0.z) + Cy * (hyn.z - h0.z);
+      out.w = h0.w + Cx * (hxn.w - h0.w) + Cy * (hyn.w - h0.w);
+      *reinterpret_cast<float4*>(dst + cell_off(P, ix, iy)) = out;
+    }
   }
 }
+
+}  // namespace boltz
+
+#include "collide.hpp"
+
+namespace boltz {
 
 // ------------------------------------------------------------------- S6 --
 __global__ __launch_bounds__(256) void moments_kernel(Params P, WallArgs W, const float* __restrict__ h,

@@ -95,6 +95,9 @@ STREAM_CASES = [
     dict(order=2, bc=1, nx=10, ny=9, nv=(6, 6, 6), vmax=3.0),
     dict(order=1, bc=1, nx=5, ny=12, nv=(6, 4, 4), vmax=3.0),
     dict(order=2, bc=0, nx=2, ny=2, nv=(4, 4, 4), vmax=2.5),                 # smallest cavity
+    dict(order=2, bc=0, nx=13, ny=11, nv=(6, 4, 8), vmax=(3.0, 2.5, 3.5)),   # vector kernel, ragged tiles
+    dict(order=2, bc=1, nx=10, ny=9, nv=(4, 6, 4), vmax=3.0),                # vector kernel, periodic
+    dict(order=1, bc=0, nx=17, ny=9, nv=(5, 3, 4), vmax=(3.0, 2.0, 2.5)),    # vector kernel, v_x = 0 nodes
 ]
 
 
