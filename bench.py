@@ -42,6 +42,32 @@ BYTES_PER_NODE_KERNEL = 8
 # h_a and h_b and four 64-bit integer atomic adds (Eq. monteCarloInt).
 LDS_READS_PER_PAIR, LDS_ATOMICS_PER_PAIR = 2, 4
 N_CU, CLOCK_HZ = 256, 2.4e9
+# HBM traffic of the collision launch group measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, summed over the group's
+# kernels), each scaled by what the counter reads for a device copy of the
+# 131 MB state (bench.py --calibrate); valid only for the kernel sources whose
+# SHA-256 is recorded (profiles/collide_counters_cavity64.md).
+TRAFFIC = {"sha256": "7af7bb4025722018fef92cb8590f34cda8dadbeb134ddfd2854ac5f6c1a6319e",
+           "fetch_kib": 66350.4 + 98.5, "write_kib": 128000.0 + 468.8,
+           "fetch_scale": 128000.0 / 64018.1, "write_scale": 1.0}
+KERNEL_SOURCES = ("boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1005_5405_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    t = TRAFFIC
+    if not t["sha256"] or t["sha256"] != kernel_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def _json_line(d):
@@ -65,7 +91,7 @@ def cpu_baseline(preset, seconds_budget: float):
     while True:
         h = o.step(h, walls, steps)
         steps += 1
-        if time.perf_counter() - t0 >= seconds_budget or steps >= 3:
+        if time.perf_counter() - t0 >= seconds_budget or steps >= 200:
             break
     dt = time.perf_counter() - t0
     ncells, nv = o.nx * o.ny, o.nv
@@ -129,7 +155,13 @@ def main():
                     help="also time the per-cell sample streams (G = 1)")
     ap.add_argument("--cpu-baseline", choices=["auto", "skip"], default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first copy the state once on the device (scale of the traffic counters)")
+    ap.add_argument("--print-sha", action="store_true", help="print the kernel-source SHA-256 and exit")
     args = ap.parse_args()
+    if args.print_sha:
+        print(kernel_sources_sha256())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -146,6 +178,13 @@ def main():
     preset = pkg.PRESETS[args.config].with_(**over)
     print("[bench] %s: G=%d, warm-up %d + %d timed steps" % (args.config, args.sample_group, args.warmup,
                                                            args.steps), flush=True)
+    if args.calibrate:
+        n0 = preset.nx * preset.ny * preset.nv ** 3
+        src = torch.zeros(n0, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: %d bytes" % (4 * n0), flush=True)
     r = run(pkg, torch, preset, args.steps, args.warmup)
     g, kw, nodes = r["g"], r["kw"], r["nodes"]
     K = args.steps
@@ -157,14 +196,14 @@ def main():
     atom_rate = LDS_ATOMICS_PER_PAIR * pair_cells / t_c / (N_CU * CLOCK_HZ)
     roof = {"kernel": "collide_kernel + sample_kernel" if kw["sample_group"] != 1 else "collide_kernel",
             "bound": "hbm", "achieved": coll_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": coll_gbs / HBM_PEAK_GBS, "traffic": None, "avg_ms": t_c * 1e3,
+            "frac": coll_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(), "avg_ms": t_c * 1e3,
             "algorithmic_bytes_per_launch": BYTES_PER_NODE_KERNEL * nodes,
             "lds_atomic_lane_ops_per_clk_per_cu": atom_rate,
             "note": "8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision "
                     "launch group; the pair loop is bound by LDS integer atomics (4 per pair and cell), "
                     "whose measured gfx950 rate is ~5.4 lane-ops/clk/CU"}
     stream_gbs = BYTES_PER_NODE_KERNEL * nodes / r["t_stream"] / 1e9
-    stream_k = {"kernel": "ratio_kernel (when the walls change) + wall_kernel + stream4_kernel", "bound": "hbm",
+    stream_k = {"kernel": "wallconst_kernel (when the walls change) + wall_kernel x2 + stream4_kernel", "bound": "hbm",
                 "avg_ms": r["t_stream"] * 1e3, "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": stream_gbs / HBM_PEAK_GBS}
     line = {"metric": METRIC, "value": r["value"], "unit": "node-updates/s", "n_gpus": 1, "steps": K,

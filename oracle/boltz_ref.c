@@ -44,8 +44,8 @@ struct boltz_ref_ctx {
   double* om[3];
   double Om[3];
   uint64_t* T[3]; /* T[k][i] = T_i for i in [1, n); T[k][0] = 0 */
-  double* pphi[3];  /* realised per-axis Maxwellian law (T_{i+1} - T_i) 2^-32 */
-  double* punif[3]; /* realised per-axis uniform law of floor(r n / 2^32)     */
+  double* pphi[3];  /* realised per-axis Maxwellian law (T_{i+1} - T_i) 2^-12 */
+  double* punif[3]; /* realised per-axis uniform law of floor(f n / 2^12)     */
   double beta;      /* weight of the uniform component, mix16 / 16           */
   double dx, dy, dt, K, W, qfac;
   char err[256];

@@ -41,7 +41,7 @@ struct boltz_ctx {
   Params P{};
   // collide launch: block size, accumulator kind, dynamic LDS and persistent
   // grid of the fused-sampler [0] and shared-table [1] variants
-  int collide_block = 256;
+  int collide_block[2] = {256, 256};
   bool collide_fixed = true;
   size_t collide_lds[2] = {0, 0};
   int64_t collide_grid[2] = {0, 0};
@@ -89,20 +89,26 @@ constexpr size_t kLdsBytes = 160 * 1024;
 // static LDS of the collide kernel (block reduction scratch) per block size
 size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof(double) + 64; }
 
-// Accumulator kind and block size of the collide kernel: 64-bit fixed-point
+// Accumulator kind and block sizes of the collide kernel: 64-bit fixed-point
 // accumulators when they fit next to the h tile and tables, else FP32; the
-// block size gives about 1024 resident threads per CU.
-bool pick_collide(int nv, int ns, bool& fixed, int& block) {
+// block size gives about 1024 resident threads per CU.  block[0]: pairs drawn
+// in the kernel; block[1]: pairs read from the shared table, which runs
+// faster with 512 threads (and unrolled node loops) than with 1024 when only
+// one workgroup fits per CU.
+bool pick_collide(int nv, int ns, bool& fixed, int (&blocks)[2]) {
+  int block = 256;
   fixed = CollideLDS::bytes(nv, ns, true, true) + collide_static_lds(1024) <= kLdsBytes;
   const size_t dyn = CollideLDS::bytes(nv, ns, fixed, true);
   if (dyn + collide_static_lds(1024) > kLdsBytes) return false;
   if (4 * (dyn + collide_static_lds(256)) <= kLdsBytes) block = 256;
   else if (2 * (dyn + collide_static_lds(512)) <= kLdsBytes) block = 512;
   else block = 1024;
-  // tuning override: BOLTZ_COLLIDE_BLOCK = 256 | 512 | 1024
+  blocks[0] = block;
+  blocks[1] = block == 1024 ? 512 : block;
+  // tuning override: BOLTZ_COLLIDE_BLOCK = 256 | 512 | 1024 (both variants)
   if (const char* e = std::getenv("BOLTZ_COLLIDE_BLOCK")) {
     const int b = std::atoi(e);
-    if ((b == 256 || b == 512 || b == 1024) && dyn + collide_static_lds(b) <= kLdsBytes) block = b;
+    if ((b == 256 || b == 512 || b == 1024) && dyn + collide_static_lds(b) <= kLdsBytes) blocks[0] = blocks[1] = b;
   }
   return true;
 }
@@ -156,7 +162,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const int64_t nvt = (int64_t)p->nv[0] * p->nv[1] * p->nv[2];
   const int nsum = p->nv[0] + p->nv[1] + p->nv[2];
   bool cfixed = true;
-  int cblock = 256;
+  int cblock[2] = {256, 256};
   if (nvt > (1 << 20) || !pick_collide((int)nvt, nsum, cfixed, cblock))
     return fail(nullptr, BOLTZ_EUNSUPPORTED,
                 "boltz_create: the per-cell h and increment tiles of this velocity grid exceed the 160 KB LDS");
@@ -263,6 +269,18 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       icdf[k * kFieldSize + f] = (uint8_t)idx;
     }
   }
+  // M0 = sum_j w_j psi_k psi_l, psi = (1, v_x, v_y, v_z, |v|^2), packed k <= l
+  std::vector<double> m0(16, 0.0);
+  for (int ix = 0; ix < c->n[0]; ++ix)
+    for (int iy = 0; iy < c->n[1]; ++iy)
+      for (int iz = 0; iz < c->n[2]; ++iz) {
+        const double vx = c->v[0][ix], vy = c->v[1][iy], vz = c->v[2][iz];
+        const double w = (c->om[0][ix] * c->om[1][iy]) * c->om[2][iz];
+        const double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
+        int t = 0;
+        for (int k = 0; k < 5; ++k)
+          for (int l = k; l < 5; ++l) m0[t++] += w * psi[k] * psi[l];
+      }
   for (int k = 0; k < 2; ++k) {
     const double dl = k == 0 ? c->dx : c->dy;
     for (int i = 0; i < c->n[k]; ++i) {
@@ -279,11 +297,13 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t o_rw = off; off = align256(off + rwtab.size() * 8);
   const size_t o_nq = off; off = align256(off + nqtab.size() * 16);
   const size_t o_icdf = off; off = align256(off + icdf.size());
+  const size_t o_m0 = off; off = align256(off + m0.size() * 8);
   const size_t o_cour = off; off = align256(off + cour.size() * 4);
   const size_t o_cour2 = off; off = align256(off + cour2.size() * 4);
   const size_t o_nw = off; off = align256(off + (size_t)nfaces * 8);
   const size_t o_ratio = off; off = align256(off + (size_t)4 * c->nv * 8);
   const size_t o_dpart = off; off = align256(off + (size_t)p->nx * 8);
+  const size_t o_wconst = off; off = align256(off + 8 * 8);
   const size_t o_status = off; off = align256(off + 4);
   const size_t o_tidx = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(uint2));
   const size_t o_tcoef = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(float4));
@@ -298,7 +318,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   struct Cp { size_t o; const void* src; size_t n; } cps[] = {
       {o_v, vtab.data(), vtab.size() * 8}, {o_om, omtab.data(), omtab.size() * 8},
       {o_rw, rwtab.data(), rwtab.size() * 8}, {o_nq, nqtab.data(), nqtab.size() * 16},
-      {o_icdf, icdf.data(), icdf.size()},
+      {o_icdf, icdf.data(), icdf.size()}, {o_m0, m0.data(), m0.size() * 8},
       {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4}};
   for (const Cp& cp : cps) {
     e = hipMemcpy(base + cp.o, cp.src, cp.n, hipMemcpyHostToDevice);
@@ -336,31 +356,35 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.eps = p->eps;
   P.inv_eps = 1.0 / p->eps;
   P.qfac = c->qfac;
+
   P.vtab = reinterpret_cast<const double*>(base + o_v);
   P.omtab = reinterpret_cast<const double*>(base + o_om);
   P.rwtab = reinterpret_cast<const double*>(base + o_rw);
   P.nqtab = reinterpret_cast<const float4*>(base + o_nq);
   P.icdf = reinterpret_cast<const uint8_t*>(base + o_icdf);
+  P.m0 = reinterpret_cast<const double*>(base + o_m0);
   P.cour = reinterpret_cast<const float*>(base + o_cour);
   P.cour2 = reinterpret_cast<const float*>(base + o_cour2);
   P.nw = reinterpret_cast<double*>(base + o_nw);
   P.ratio = reinterpret_cast<double*>(base + o_ratio);
   P.dpart = reinterpret_cast<double*>(base + o_dpart);
+  P.wconst = reinterpret_cast<double*>(base + o_wconst);
   P.status = reinterpret_cast<uint32_t*>(base + o_status);
   c->ngroups = ngroups;
   c->tidx = ngroups ? reinterpret_cast<uint2*>(base + o_tidx) : nullptr;
   c->tcoef = ngroups ? reinterpret_cast<float4*>(base + o_tcoef) : nullptr;
-  c->collide_block = cblock;
+  c->collide_block[0] = cblock[0];
+  c->collide_block[1] = cblock[1];
   c->collide_fixed = cfixed;
   int ncu = 0;
   hipError_t ea = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
-    const void* fn = collide_fn(cblock, t == 1, cfixed);
+    const void* fn = collide_fn(cblock[t], t == 1, cfixed);
     c->collide_lds[t] = CollideLDS::bytes(c->nv, nsum, cfixed, t == 0);
     ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->collide_lds[t]);
     int per_cu = 0;
     if (ea == hipSuccess)
-      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cblock, c->collide_lds[t]);
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cblock[t], c->collide_lds[t]);
     if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
     const int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
@@ -393,20 +417,23 @@ int boltz_axis_thresholds(const boltz_ctx* c, int axis, uint64_t* out) {
 
 static void ensure_ratio(boltz_ctx* c, const WallArgs& W, hipStream_t st) {
   if (c->ratio_valid && std::memcmp(&c->ratio_walls, &W, sizeof(WallArgs)) == 0) return;
-  const int64_t n = 4 * (int64_t)c->nv;
-  hipLaunchKernelGGL(ratio_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c->P, W);
+  hipLaunchKernelGGL(wallconst_kernel, dim3(4), dim3(kWallConstBlock), 0, st, c->P, W);
   c->ratio_walls = W;
   c->ratio_valid = true;
 }
 
 static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, hipStream_t st) {
   ensure_ratio(c, W, st);
+  auto launch = [&](auto kern, int nface) {
+    const int per_xcd = (nface + 7) / 8;
+    hipLaunchKernelGGL(kern, dim3(8 * per_xcd), dim3(kWallBlock), 0, st, c->P, W, h, nface, per_xcd);
+  };
   if (c->p.order == 2) {
     // x faces first; the y faces read their densities for the x-swept rows
-    hipLaunchKernelGGL(wall_kernel<0>, dim3(2 * c->p.ny), dim3(kWallBlock), 0, st, c->P, W, h);
-    hipLaunchKernelGGL(wall_kernel<1>, dim3(2 * c->p.nx), dim3(kWallBlock), 0, st, c->P, W, h);
+    launch(wall_kernel<0>, 2 * c->p.ny);
+    launch(wall_kernel<1>, 2 * c->p.nx);
   } else {
-    hipLaunchKernelGGL(wall_kernel<0>, dim3(2 * (c->p.nx + c->p.ny)), dim3(kWallBlock), 0, st, c->P, W, h);
+    launch(wall_kernel<0>, 2 * (c->p.nx + c->p.ny));
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "wall_kernel launch");
@@ -476,7 +503,7 @@ static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t st
     hipLaunchKernelGGL(sample_kernel, grid, dim3(256), TablesLDS::bytes(nsum, true), st, c->P, s32, c->tidx,
                        c->tcoef);
   }
-  switch (c->collide_block) {
+  switch (c->collide_block[table ? 1 : 0]) {
     case 256: launch_collide_b<256>(c, table, hs, hout, s32, flags, defect, st); break;
     case 512: launch_collide_b<512>(c, table, hs, hout, s32, flags, defect, st); break;
     default: launch_collide_b<1024>(c, table, hs, hout, s32, flags, defect, st); break;

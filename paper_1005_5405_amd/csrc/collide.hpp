@@ -10,17 +10,19 @@ namespace boltz {
 
 // ---------------------------------------------------------------- tables --
 // LDS copies of the per-axis tables, ns = n0 + n1 + n2 entries each:
-//   v, om            always (moment sums and the correction)
+//   v, om, xt        always (moment sums and the correction)
 //   nq, rw, icdf     only where pairs are drawn
 struct TablesLDS {
   double* v;      // node velocities
   double* om;     // omega, FP64
+  double* xt;     // per-axis parts of x . psi of the correction (per cell)
+  double* m0;     // [16] sum_j w_j psi_k psi_l (packed k <= l), constant
   float4* nq;     // {omega, p_phi, p_unif, 0}, FP32
   double* rw;     // 1 / omega, FP64
   uint8_t* icdf;  // [3 * kFieldSize] Maxwellian inverse CDF on 12-bit fields
 
   static __host__ __device__ size_t bytes(int ns, bool sampler) {
-    size_t b = 16 * (size_t)ns;
+    size_t b = 24 * (size_t)ns + 16 * sizeof(double);
     if (sampler) b += 24 * (size_t)ns + 3 * (size_t)kFieldSize;
     return b;
   }
@@ -31,7 +33,9 @@ __device__ __forceinline__ void load_tables(const Params& P, unsigned char* base
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2], ns = n0 + n1 + n2;
   T.v = reinterpret_cast<double*>(base);
   T.om = T.v + ns;
-  T.nq = reinterpret_cast<float4*>(T.om + ns);
+  T.xt = T.om + ns;
+  T.m0 = T.xt + ns;
+  T.nq = reinterpret_cast<float4*>(T.m0 + 16);
   T.rw = reinterpret_cast<double*>(T.nq + ns);
   T.icdf = reinterpret_cast<uint8_t*>(T.rw + ns);
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
@@ -44,6 +48,7 @@ __device__ __forceinline__ void load_tables(const Params& P, unsigned char* base
       T.rw[i] = P.rwtab[o];
     }
   }
+  if (threadIdx.x < 15) T.m0[threadIdx.x] = P.m0[threadIdx.x];
   if (sampler) {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(P.icdf);
     uint32_t* dst = reinterpret_cast<uint32_t*>(T.icdf);
@@ -324,8 +329,8 @@ __device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, 
 }
 
 // Persistent workgroups: workgroup b collides cells b, b + gridDim.x, ...;
-// the h^s tile of the next cell is loaded into registers while the pairs of
-// the current one are processed.  TABLE: the pairs come from the records of
+// the h^s tile of the next cell is loaded into registers while the node
+// phases of the current one run.  TABLE: the pairs come from the records of
 // sample_kernel (cells of one group share them).  FIXED: 64-bit fixed-point
 // accumulation (else FP32 compare-and-swap).  h_s may equal h_out.
 template <int BLOCK, bool TABLE, bool FIXED>
@@ -350,6 +355,9 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   const double* omx = T.om;
   const double* omy = T.om + n0;
   const double* omz = T.om + n0 + n1;
+  // node loops are unrolled where the register budget allows it (at most
+  // 256 VGPRs below 1024 threads per workgroup, 128 at 1024)
+  constexpr int NU = BLOCK <= 512 ? 4 : 1;
   const bool correct = !(flags & 1u);
   const double eps = P.eps;
   const float epsf = (float)P.eps;
@@ -373,26 +381,37 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
       for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
-    const int64_t next = cell + gridDim.x;
-    if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
     // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
     const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
     if (TABLE) {
+      // four records per thread and pass: their loads and gathers are in
+      // flight together
+      constexpr int PU = 4;
       const uint2* ri = tidx + (int64_t)group * nt;
       const float4* rk = tcoef + (int64_t)group * nt;
       uint32_t m = tid;
-      for (; m + BLOCK < nt; m += 2 * BLOCK) {
-        const uint2 i0 = ri[m], i1 = ri[m + BLOCK];
-        const float4 k0 = rk[m], k1 = rk[m + BLOCK];
-        const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
-        const int a1 = (int)(i1.x & 0xFFFFu), b1 = (int)(i1.x >> 16);
-        const float ha0 = hs[a0], hb0 = hs[b0], ha1 = hs[a1], hb1 = hs[b1];
-        const float g0 = (ha0 + hb0) + (epsf * ha0) * hb0;
-        const float g1 = (ha1 + hb1) + (epsf * ha1) * hb1;
-        scatter<FIXED>(accf, acc64, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w, g0);
-        scatter<FIXED>(accf, acc64, a1, b1, (int)(i1.y & 0xFFFFu), (int)(i1.y >> 16), k1.x, k1.y, k1.z, k1.w, g1);
+      for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) {
+        uint2 id[PU];
+        float4 kk[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+          id[u] = ri[m + u * BLOCK];
+          kk[u] = rk[m + u * BLOCK];
+        }
+        float ha[PU], hb[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+          ha[u] = hs[id[u].x & 0xFFFFu];
+          hb[u] = hs[id[u].x >> 16];
+        }
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+          const float g = (ha[u] + hb[u]) + (epsf * ha[u]) * hb[u];
+          scatter<FIXED>(accf, acc64, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
+                         (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
+        }
       }
-      if (m < nt) {
+      for (; m < nt; m += BLOCK) {
         const uint2 i0 = ri[m];
         const float4 k0 = rk[m];
         const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
@@ -411,67 +430,122 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
       }
     }
     __syncthreads();
-    // ---- S5: h^c = h^s + increment (stored over the accumulator), FP64
-    // sums M_kl = sum w F^c psi_k psi_l and r_k = -eps sum w psi_k (h^c - h^s)
-    double acc[20];
-#pragma unroll
-    for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+    // The next cell's tile is requested only now: vector-memory waits retire
+    // in issue order, so loads issued before the pair loop would stall its
+    // first record loads; the node phases below wait on no vector load.
     {
-      NodeWalk nw(tid, BLOCK, n1, n2);
-      for (int j = tid; j < nv; j += BLOCK, nw.next()) {
-        const int jx = nw.jx, jy = nw.jy, jz = nw.jz;
-        const float hsj = hs[j];
-        double dh = (double)accf[j];
-        if (FIXED) dh += from_fixed(acc64[j]);
-        const float hc = (float)((double)hsj + dh);
-        accf[j] = hc;
-        if (correct) {
-          const double w = (omx[jx] * omy[jy]) * omz[jz];
-          const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-          const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
-          const double wF = w * fma(eps, (double)hc, 1.0);
-          const double psi[5] = {1.0, v1, v2, v3, vv};
-          int t = 0;
+      const int64_t next = cell + gridDim.x;
+      if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
+    }
+    // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator
+#pragma unroll NU
+    for (int j = tid; j < nv; j += BLOCK) {
+      const float hsj = hs[j];
+      double dh = (double)accf[j];
+      if (FIXED) dh += from_fixed(acc64[j]);
+      accf[j] = (float)((double)hsj + dh);
+    }
+    if (correct) {
+      __syncthreads();
+      // (2) FP64 sums, one velocity row (jx, jy) per thread:
+      //   M = M0 + eps sum_j w_j h^c_j psi_j psi_j^T  (M0 = sum w psi psi^T),
+      //   r = -eps sum_j w_j psi_j (h^c_j - h^s_j),  psi = (1, v, |v|^2),
+      // from the z moments S_p = sum_z omega_z h^c v_z^p (p <= 4) and
+      // R_p = sum_z omega_z (h^c - h^s) v_z^p (p <= 2) of the row.
+      double acc[20];
 #pragma unroll
-          for (int k = 0; k < 5; ++k) {
-            const double wk = wF * psi[k];
+      for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+      for (int row = tid; row < n0 * n1; row += BLOCK) {
+        const int jx = row / n1, jy = row - (row / n1) * n1;
+        const float* hcr = accf + row * n2;
+        const float* hsr = hs + row * n2;
+        double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
+#pragma unroll NU
+        for (int jz = 0; jz < n2; ++jz) {
+          const double hc = (double)hcr[jz], oz = omz[jz], z = vz[jz];
+          double u = oz * hc;
+          S0 += u;
+          u *= z;
+          S1 += u;
+          u *= z;
+          S2 += u;
+          u *= z;
+          S3 += u;
+          u *= z;
+          S4 += u;
+          double d = oz * (hc - (double)hsr[jz]);
+          R0 += d;
+          d *= z;
+          R1 += d;
+          d *= z;
+          R2 += d;
+        }
+        const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
+        const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
+        const double E0 = c2 * T0 + T2;  // sum w h^c |v|^2
+        acc[0] += T0;
+        acc[1] += a * T0;
+        acc[2] += b * T0;
+        acc[3] += T1;
+        acc[4] += E0;
+        acc[5] += (a * a) * T0;
+        acc[6] += (a * b) * T0;
+        acc[7] += a * T1;
+        acc[8] += a * E0;
+        acc[9] += (b * b) * T0;
+        acc[10] += b * T1;
+        acc[11] += b * E0;
+        acc[12] += T2;
+        acc[13] += c2 * T1 + T3;
+        acc[14] += (c2 * c2) * T0 + 2.0 * c2 * T2 + T4;
+        const double Q0 = W * R0, Q1 = W * R1, Q2 = W * R2;
+        acc[15] += Q0;
+        acc[16] += a * Q0;
+        acc[17] += b * Q0;
+        acc[18] += Q1;
+        acc[19] += c2 * Q0 + Q2;
+      }
+      block_sum20_lds(acc, red, tot);
+      if (tid < 64) {
+        // wavefront 0 solves M x = r and tabulates x . psi per axis:
+        // x1 v_x + x4 v_x^2, x2 v_y + x4 v_y^2, x0 + x3 v_z + x4 v_z^2
+        double M[15], r[5], x[5];
 #pragma unroll
-            for (int l = k; l < 5; ++l) acc[t] = fma(wk, psi[l], acc[t]), ++t;
-          }
-          const double edn = -eps * (w * ((double)hc - (double)hsj));
+        for (int k = 0; k < 15; ++k) M[k] = T.m0[k] + eps * tot[k];
 #pragma unroll
-          for (int k = 0; k < 5; ++k) acc[15 + k] = fma(edn, psi[k], acc[15 + k]);
+        for (int k = 0; k < 5; ++k) r[k] = -eps * tot[15 + k];
+        if (!solve5(M, r, x)) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) x[k] = 0.0;
+          if (tid == 0) atomicOr(P.status, 1u);
+        }
+        for (int i = tid; i < n0 + n1 + n2; i += 64) {
+          const double v = T.v[i];
+          T.xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
+                           : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
         }
       }
+      __syncthreads();
     }
-    double x[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (correct) {
-      // every thread solves the same system from the totals in LDS
-      block_sum20_lds(acc, red, tot);
-      if (!solve5(tot, tot + 15, x)) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) x[k] = 0.0;
-        if (tid == 0) atomicOr(P.status, 1u);
-      }
-    }
-    // ---- h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
+    // ---- (3) h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
     double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     bool finite = true;
     float* dst = hout_g + cell * nv;
     NodeWalk nw2(tid, BLOCK, n1, n2);
+#pragma unroll NU
     for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
       const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
-      const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-      const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
       const double hc = (double)accf[j];
       float out = (float)hc;
       if (correct) {
-        const double xpsi = fma(x[4], vv, fma(x[3], v3, fma(x[2], v2, fma(x[1], v1, x[0]))));
+        const double xpsi = (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz];
         out = (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc);
       }
       finite = finite && isfinite(out);
       dst[j] = out;
       if (defect) {
+        const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+        const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
         const double w = (omx[jx] * omy[jy]) * omz[jz];
         const double diff = eps * ((double)out - (double)hs[j]) * w;
         dsum[0] += diff;

@@ -1,18 +1,22 @@
 // kernels.hpp -- HIP kernels of one time-split step (CDNA4 / gfx950).
 //
-//   wall_kernel      S1  per boundary face: discrete zero-net-flux density n_w
-//                        (Sec. 2, Eq. bcMax) and the per-wall ratio table
-//                        Phi_w / Phi0 used for the re-emitted values
-//   stream_kernel    S2  one HBM pass: (8x8 cells + halo) x 32 velocities per
-//                        workgroup staged in LDS; order 1 = Eq. streaming2D,
+//   wallconst_kernel S1  per wall: table Phi_w / Phi0 of the re-emitted
+//                        Maxwellian and the flux sums A_w, D_w (rebuilt only
+//                        when the walls change)
+//   wall_kernel      S1  per boundary face: the discrete zero-net-flux
+//                        density n_w (Sec. 2, Eq. bcMax)
+//   stream4_kernel   S2  one HBM pass: (16x8 cells + upwind halo) x 32
+//                        velocities per workgroup staged in LDS, four
+//                        velocities per thread; order 1 = Eq. streaming2D,
 //                        order 2 = Beam-Warming x sweep then y sweep
+//   stream_kernel    S2  scalar form for velocity grids with n_z % 4 != 0
 //   collide_kernel   S3-S5  (collide.hpp) persistent workgroups walking the
 //                        spatial cells: the cell's h tile and its increment
 //                        accumulators live in LDS, lanes draw Philox pairs
 //                        (or read the shared-sample table), gather h_a, h_b
 //                        and scatter gain/loss with LDS atomics (Eqs.
 //                        monteCarloInt, collision_step), then FP64 moment
-//                        sums, a 5x5 Cholesky solve and the correction of
+//                        sums, a 5x5 LDL^T solve and the correction of
 //                        Eq. rinorm_a, one coalesced store
 //   moments_kernel   S6  FP64 moments per cell (Eqs. densita..sforzi) and the
 //                        lid-face shear partial sums
@@ -44,7 +48,9 @@ struct Params {
   const float* cour2;     // [2][kMaxAxis] C (1 - C) / 2
   double* nw;             // [2 ny + 2 nx] face densities: left, right, bottom, top
   double* ratio;          // [4][nv] Phi_w / Phi0 per wall and node
+  const double* m0;       // [15] sum_j w_j psi_k psi_l, psi = (1, v, |v|^2), packed k <= l
   double* dpart;          // [nx] lid shear partial sums
+  double* wconst;         // [4][2] per wall: A_w, D_w of the face densities
   uint32_t* status;       // device status bits
 };
 
@@ -163,33 +169,137 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
   return (s[0] + P.eps * s[2]) / s[1];
 }
 
-constexpr int kWallBlock = 512;
+// Per wall (one workgroup each): the table Phi_w / Phi0 of every node,
+// ratio[wall * nv + j] (FP64; only the lid moves, with velocity lid_u along
+// x), then A_w = sum_out |v_n| w_j and D_w = sum over the mirror images of
+// the outgoing nodes of |v_n| w R, reduced in one pass with the same tree so
+// that a wall at rest (R = 1) gives D_w = A_w bitwise: wconst[2 wall + {0,1}].
+// Launched only when the wall state changes.
+constexpr int kWallConstBlock = 1024;
 
-// Phi_w / Phi0 of every wall and node: ratio[wall * nv + j] (FP64).  Only the
-// lid moves (velocity lid_u along x); every wall has its own temperature.
-__global__ __launch_bounds__(256) void ratio_kernel(Params P, WallArgs W) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 4 * (int64_t)P.nv) return;
-  const int wall = (int)(i / P.nv), j = (int)(i - (int64_t)wall * P.nv);
-  int jx, jy, jz;
-  node_decode(j, P.n[1], P.n[2], jx, jy, jz);
+__global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, WallArgs W) {
+  __shared__ double red[2 * (kWallConstBlock / 64)];
+  const int wall = blockIdx.x;
+  const int nv = P.nv, n1 = P.n[1], n2 = P.n[2];
   const double Uw = (wall == WALL_TOP) ? W.lid_u : 0.0;
-  P.ratio[i] = wall_ratio(P.vtab[jx], P.vtab[kMaxAxis + jy], P.vtab[2 * kMaxAxis + jz], Uw, W.tau[wall],
-                          W.tfac[wall]);
+  double* R = P.ratio + (int64_t)wall * nv;
+  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+    int jx, jy, jz;
+    node_decode(j, n1, n2, jx, jy, jz);
+    R[j] = wall_ratio(P.vtab[jx], P.vtab[kMaxAxis + jy], P.vtab[2 * kMaxAxis + jz], Uw, W.tau[wall], W.tfac[wall]);
+  }
+  __syncthreads();
+  const int nax = (wall <= WALL_RIGHT) ? 0 : 1;
+  const int sgn = (wall == WALL_LEFT || wall == WALL_BOTTOM) ? 1 : -1;
+  double s[2] = {0.0, 0.0};
+  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+    int jx, jy, jz;
+    node_decode(j, n1, n2, jx, jy, jz);
+    const double vn = nax ? P.vtab[kMaxAxis + jy] : P.vtab[jx];
+    if (!(sgn * vn < 0.0)) continue;
+    const double aw = fabs(vn) * ((P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz]);
+    int mx = jx, my = jy;
+    if (nax == 0) mx = P.n[0] - 1 - jx; else my = n1 - 1 - jy;
+    s[0] += aw;
+    s[1] += aw * R[(mx * n1 + my) * n2 + jz];
+  }
+  block_sum<2>(s, red);
+  if (threadIdx.x == 0) {
+    P.wconst[2 * wall] = s[0];
+    P.wconst[2 * wall + 1] = s[1];
+  }
 }
 
-// One workgroup per boundary face, faces numbered left[ny], right[ny],
-// bottom[nx], top[nx].  PHASE 0 handles the x faces (and, for order 1, the y
-// faces too); PHASE 1 the y faces of order 2, whose face values come from
-// the x-swept boundary rows and therefore need the x-face densities of the
-// previous launch.  The ratio tables Phi_w / Phi0 come from ratio_kernel.
-// Cavity problems only.
+// B of one face: sum over the outgoing nodes of |v_n| w_j hhat_j (hhat as in
+// face_density), over j = j0, j0 + step, ... below nv, U nodes per pass
+// with every load of a pass issued before it is used.  A y face of order 2
+// away from the corner columns reads the three cells of each x sweep
+// directly (no ghost value is needed there).
+template <int U>
+__device__ double face_b(const Params& P, const WallArgs& W, const float* h, int wall, int pos, int order,
+                         double nwl0, double nwl1, double nwr0, double nwr1, int j0, int step) {
+  const int nx = P.nx, ny = P.ny, nv = P.nv, n1 = P.n[1], n2 = P.n[2];
+  const int nax = (wall <= WALL_RIGHT) ? 0 : 1;
+  const int sgn = (wall == WALL_LEFT || wall == WALL_BOTTOM) ? 1 : -1;
+  int ax_, ay_, bx_, by_;
+  switch (wall) {
+    case WALL_LEFT: ax_ = 0; ay_ = pos; bx_ = 1; by_ = pos; break;
+    case WALL_RIGHT: ax_ = nx - 1; ay_ = pos; bx_ = nx - 2; by_ = pos; break;
+    case WALL_BOTTOM: ax_ = pos; ay_ = 0; bx_ = pos; by_ = 1; break;
+    default: ax_ = pos; ay_ = ny - 1; bx_ = pos; by_ = ny - 2; break;
+  }
+  const double dl = nax ? P.dy : P.dx;
+  const bool ysw = (order == 2) && (nax == 1);
+  const bool corner = ysw && (pos < 2 || pos >= nx - 2);
+  const float* ca = h + cell_off(P, ax_, ay_);
+  const float* cb = h + cell_off(P, bx_, by_);
+  double b = 0.0;
+  NodeWalk walk(j0, step, n1, n2);
+  for (int jb = j0; jb < nv; jb += U * step) {
+    int jxs[U], jys[U], jzs[U];
+    float a0[U], a1[U], a2[U], b0[U], b1[U], b2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      jxs[u] = walk.jx; jys[u] = walk.jy; jzs[u] = walk.jz;
+      walk.next();
+      const int j = (jb + u * step < nv) ? jb + u * step : j0;
+      a0[u] = ca[j];
+      b0[u] = (order == 2) ? cb[j] : 0.0f;
+      a1[u] = a2[u] = b1[u] = b2[u] = 0.0f;
+      if (ysw && !corner) {
+        const double vx = P.vtab[jxs[u]];
+        const int sx = vx > 0.0 ? 1 : (vx < 0.0 ? -1 : 0);
+        const int64_t o1 = -(int64_t)sx * nv;
+        a1[u] = ca[j + o1]; a2[u] = ca[j + 2 * o1];
+        b1[u] = cb[j + o1]; b2[u] = cb[j + 2 * o1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = jb + u * step;
+      if (j >= nv) continue;
+      const int jx = jxs[u], jy = jys[u], jz = jzs[u];
+      const double vn = nax ? P.vtab[kMaxAxis + jy] : P.vtab[jx];
+      if (!(sgn * vn < 0.0)) continue;
+      const double an = fabs(vn);
+      const double aw = an * ((P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz]);
+      double ha = a0[u], hb = b0[u];
+      if (ysw) {
+        if (corner) {
+          ha = xswept_value(P, W, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
+          hb = xswept_value(P, W, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
+        } else if (P.vtab[jx] != 0.0) {
+          const float Cx = P.cour[jx], Cx2 = P.cour2[jx];
+          ha = bw_update(a0[u], a1[u], a2[u], Cx, Cx2);
+          hb = bw_update(b0[u], b1[u], b2[u], Cx, Cx2);
+        }
+      }
+      double hh = ha;
+      if (order == 2) {
+        const double C = an * P.dt / dl;
+        hh = ha + 0.5 * (1.0 - C) * (ha - hb);
+      }
+      b += aw * hh;
+    }
+  }
+  return b;
+}
+
+// Face densities n_w = (A_w + eps B) / D_w, one workgroup per face, faces
+// numbered left[ny], right[ny], bottom[nx], top[nx].  PHASE 0 handles the x
+// faces (and, for order 1, the y faces too); PHASE 1 the y faces of order
+// 2, whose face values come from the x-swept boundary rows and therefore
+// need the x-face densities of the previous launch.  Cavity problems only.
+constexpr int kWallBlock = 1024;
+
 template <int PHASE>
-__global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, const float* __restrict__ h) {
-  __shared__ double red[3 * (kWallBlock / 64)];
-  const bool ysplit = (P.order == 2);
-  int f = blockIdx.x;
-  if (PHASE == 1) f += 2 * P.ny;  // y faces only
+__global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, const float* __restrict__ h,
+                                                          int nface, int per_xcd) {
+  __shared__ double red[kWallBlock / 64];
+  // neighbouring faces (which read overlapping cells) on the same XCD
+  int f = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (f >= nface) return;
+  if (PHASE == 1) f += 2 * P.ny;
   int wall, pos;
   if (f < P.ny) { wall = WALL_LEFT; pos = f; }
   else if (f < 2 * P.ny) { wall = WALL_RIGHT; pos = f - P.ny; }
@@ -197,7 +307,6 @@ __global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, 
   else { wall = WALL_TOP; pos = f - 2 * P.ny - P.nx; }
   double nwl0 = 0.0, nwl1 = 0.0, nwr0 = 0.0, nwr1 = 0.0;
   if (PHASE == 1) {
-    // x-wall densities of the two boundary rows next to this y face
     const int ra = (wall == WALL_BOTTOM) ? 0 : P.ny - 1;
     const int rb = (wall == WALL_BOTTOM) ? 1 : P.ny - 2;
     nwl0 = P.nw[ra];
@@ -205,9 +314,9 @@ __global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, 
     nwr0 = P.nw[P.ny + ra];
     nwr1 = P.nw[P.ny + rb];
   }
-  const double nwv = face_density(P, W, h, wall, pos, P.order, nwl0, nwl1, nwr0, nwr1, red);
-  (void)ysplit;
-  if (threadIdx.x == 0) P.nw[f] = nwv;
+  double s[1] = {face_b<8>(P, W, h, wall, pos, P.order, nwl0, nwl1, nwr0, nwr1, (int)threadIdx.x, kWallBlock)};
+  block_sum<1>(s, red);
+  if (threadIdx.x == 0) P.nw[f] = (P.wconst[2 * wall] + P.eps * s[0]) / P.wconst[2 * wall + 1];
 }
 
 // ------------------------------------------------------------------- S2 --
@@ -400,19 +509,27 @@ __global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const 
   const bool needT = !oneX || P.vtab[kMaxAxis + fy] < 0.0;
   const int c_lo = needL ? 0 : H, c_hi = needR ? AX : AX - H;
   const int r_lo = needB ? 0 : H, r_hi = needT ? AY : AY - H;
-  // ---- stage the block; outside the cavity: the wall's re-emitted values
+  // ---- stage the block; outside the cavity: the wall's re-emitted values.
+  // All loads of a thread are issued before its LDS stores (fixed trip
+  // count), so their latencies overlap.
   {
+    constexpr int kRows = kStream4Block / Q;                 // cells per pass
+    constexpr int kIter = (AY * AX + kRows - 1) / kRows;     // passes
     const int q = threadIdx.x % Q;
     const int jq = j0 + 4 * q;
-    for (int cidx = threadIdx.x / Q; cidx < AY * AX; cidx += kStream4Block / Q) {
-      const int r = cidx / AX, c = cidx - (cidx / AX) * AX;
+    float4 v[kIter];
+#pragma unroll
+    for (int it = 0; it < kIter; ++it) {
+      const int cidx = threadIdx.x / Q + it * kRows;
+      v[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (cidx >= AY * AX) continue;
+      const int r = cidx / AX, c = cidx - r * AX;
       if (r < r_lo || r >= r_hi || c < c_lo || c >= c_hi || jq >= nv) continue;
       const int iy = iy0 - H + r, ix = ix0 - H + c;
       const bool inY = iy >= 0 && iy < ny, inX = ix >= 0 && ix < nx;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (periodic || (inX && inY)) {
         const int64_t base = cell_off(P, periodic ? wrapi(ix, nx) : ix, periodic ? wrapi(iy, ny) : iy);
-        v = *reinterpret_cast<const float4*>(hin + base + jq);
+        v[it] = *reinterpret_cast<const float4*>(hin + base + jq);
       } else if (inY || (ORDER == 1 && inX)) {
         int wall;
         double nwv;
@@ -423,9 +540,13 @@ __global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const 
           wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
           nwv = P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix];
         }
-        v = ghost4(nwv, P.ratio + (int64_t)wall * nv + jq, P.inv_eps);
+        v[it] = ghost4(nwv, P.ratio + (int64_t)wall * nv + jq, P.inv_eps);
       }
-      A4[cidx * Q + q] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < kIter; ++it) {
+      const int cidx = threadIdx.x / Q + it * kRows;
+      if (cidx < AY * AX) A4[cidx * Q + q] = v[it];
     }
   }
   const int q = threadIdx.x % Q, c = threadIdx.x / Q;
