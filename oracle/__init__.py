@@ -53,7 +53,7 @@ class _Problem(ctypes.Structure):
 class _Walls(ctypes.Structure):
     _fields_ = [("lid_u", ctypes.c_double), ("tau_left", ctypes.c_double),
                 ("tau_right", ctypes.c_double), ("tau_bottom", ctypes.c_double),
-                ("tau_top", ctypes.c_double)]
+                ("tau_top", ctypes.c_double), ("tau_bottom_x", ctypes.c_void_p)]
 
 
 _lib = None
@@ -84,6 +84,10 @@ def _load():
         L.boltz_ref_collide_cells.argtypes = [P, V, V, I64, U32, V, I64]
         L.boltz_ref_moments.argtypes = [P, V, ctypes.POINTER(_Walls), V, V]
         L.boltz_ref_step.argtypes = [P, V, V, ctypes.POINTER(_Walls), I64]
+        L.boltz_ref_stream_adjoint.argtypes = [P, V, V, V, V, ctypes.POINTER(_Walls)]
+        L.boltz_ref_collide_adjoint.argtypes = [P, V, V, V, I64, U32]
+        L.boltz_ref_step_adjoint.argtypes = [P, V, V, V, V, ctypes.POINTER(_Walls), I64]
+        L.boltz_ref_lid_shear_adjoint.argtypes = [P, V, ctypes.POINTER(_Walls), D, V, V]
         _lib = L
     return _lib
 
@@ -117,9 +121,18 @@ class Walls:
     tau_right: float = 1.0
     tau_bottom: float = 1.0
     tau_top: float = 1.0
+    tau_bottom_x: object = None   # None, or nx per-face temperatures of the bottom wall
 
     def _c(self) -> _Walls:
-        return _Walls(self.lid_u, self.tau_left, self.tau_right, self.tau_bottom, self.tau_top)
+        ptr = None
+        if self.tau_bottom_x is not None:
+            self._tbx = np.ascontiguousarray(self.tau_bottom_x, dtype=np.float64)
+            ptr = self._tbx.ctypes.data
+        return _Walls(self.lid_u, self.tau_left, self.tau_right, self.tau_bottom, self.tau_top, ptr)
+
+
+# entries of the wall-parameter gradient (then one per bottom face)
+GRAD_NAMES = ("lid_u", "tau_left", "tau_right", "tau_top")
 
 
 def _f64(a, shape):
@@ -239,6 +252,51 @@ class Oracle:
         w = ctypes.byref(walls._c()) if walls is not None else None
         self._check(_lib.boltz_ref_step(self._ctx, h.ctypes.data, out.ctypes.data, w, int(step)), "step")
         return out
+
+    # --- adjoint (reverse-mode derivatives of the functions above) ---
+    def grad_size(self) -> int:
+        return 4 + self.nx
+
+    def stream_adjoint(self, h, lam_out, walls: Walls | None = None):
+        """(lam_in, grad): the adjoint of stream at h applied to lam_out."""
+        h = _f64(h, self.shape)
+        lo = _f64(lam_out, self.shape)
+        lam = np.empty(self.shape)
+        grad = np.zeros(self.grad_size())
+        w = ctypes.byref(walls._c()) if walls is not None else None
+        self._check(_lib.boltz_ref_stream_adjoint(self._ctx, h.ctypes.data, lo.ctypes.data, lam.ctypes.data,
+                                                  grad.ctypes.data, w), "stream_adjoint")
+        return lam, grad
+
+    def collide_adjoint(self, h_s, lam_out, step, correction=True):
+        h = _f64(h_s, self.shape)
+        lo = _f64(lam_out, self.shape)
+        lam = np.empty(self.shape)
+        flags = 0 if correction else NO_CORRECTION
+        self._check(_lib.boltz_ref_collide_adjoint(self._ctx, h.ctypes.data, lo.ctypes.data, lam.ctypes.data,
+                                                   int(step), flags), "collide_adjoint")
+        return lam
+
+    def step_adjoint(self, h, lam_out, walls: Walls | None, step: int):
+        """(lam_in, grad) of one full step at h (forward recomputed)."""
+        h = _f64(h, self.shape)
+        lo = _f64(lam_out, self.shape)
+        lam = np.empty(self.shape)
+        grad = np.zeros(self.grad_size())
+        w = ctypes.byref(walls._c()) if walls is not None else None
+        self._check(_lib.boltz_ref_step_adjoint(self._ctx, h.ctypes.data, lo.ctypes.data, lam.ctypes.data,
+                                                grad.ctypes.data, w, int(step)), "step_adjoint")
+        return lam, grad
+
+    def lid_shear_adjoint(self, h, walls: Walls, weight=1.0):
+        """(dD/dh * weight, dD/dtheta * weight) of the lid shear D."""
+        h = _f64(h, self.shape)
+        lam = np.zeros(self.shape)
+        grad = np.zeros(self.grad_size())
+        self._check(_lib.boltz_ref_lid_shear_adjoint(self._ctx, h.ctypes.data, ctypes.byref(walls._c()),
+                                                     float(weight), lam.ctypes.data, grad.ctypes.data),
+                    "lid_shear_adjoint")
+        return lam, grad
 
     def debug_pairs(self, cell, step, m0, count, words=False, velocities=False):
         """Pairs m0..m0+count-1 of (cell, step): idx (count, 4) = a, b, a*, b*

@@ -443,11 +443,13 @@ int boltz_ref_debug_pairs(const boltz_ref_ctx* c, int64_t cell, int64_t step, in
 
 /* --------------------------------------------------------------- walls -- */
 
-static double wall_tau(const boltz_ref_walls* w, int wall) {
+/* Temperature ratio of the face `pos` of a wall (the bottom wall may carry
+ * a per-face profile). */
+static double wall_tau(const boltz_ref_walls* w, int wall, int pos) {
   switch (wall) {
     case WALL_LEFT: return w->tau_left;
     case WALL_RIGHT: return w->tau_right;
-    case WALL_BOTTOM: return w->tau_bottom;
+    case WALL_BOTTOM: return w->tau_bottom_x ? w->tau_bottom_x[pos] : w->tau_bottom;
     default: return w->tau_top;
   }
 }
@@ -484,7 +486,7 @@ static double face_density(const boltz_ref_ctx* c, const double* src, int wall, 
   }
   double dl = (nax == 0) ? c->dx : c->dy;
   double U = (wall == WALL_TOP) ? walls->lid_u : 0.0;
-  double tau = wall_tau(walls, wall);
+  double tau = wall_tau(walls, wall, pos);
   double phi_out = 0.0, dens = 0.0;
   for (int j = 0; j < c->nv; ++j) {
     int jx, jy, jz;
@@ -507,13 +509,14 @@ static double face_density(const boltz_ref_ctx* c, const double* src, int wall, 
   return phi_out / dens;
 }
 
-/* Re-emitted deviation h_w = (n_w Phi_w/Phi0 - 1)/eps (Eq. bcMax). */
-static double ghost_value(const boltz_ref_ctx* c, int wall, double nw, int j,
+/* Re-emitted deviation h_w = (n_w Phi_w/Phi0 - 1)/eps (Eq. bcMax) of face
+ * `pos` of a wall. */
+static double ghost_value(const boltz_ref_ctx* c, int wall, int pos, double nw, int j,
                           const boltz_ref_walls* walls) {
   int jx, jy, jz;
   node_idx(c, j, &jx, &jy, &jz);
   double U = (wall == WALL_TOP) ? walls->lid_u : 0.0;
-  double R = wall_ratio(c->v[0][jx], c->v[1][jy], c->v[2][jz], U, wall_tau(walls, wall));
+  double R = wall_ratio(c->v[0][jx], c->v[1][jy], c->v[2][jz], U, wall_tau(walls, wall, pos));
   return (nw * R - 1.0) / c->p.eps;
 }
 
@@ -554,8 +557,8 @@ static void sweep_x(const boltz_ref_ctx* c, const double* h, double* hx, const d
         int i = ix - d * s;
         if (i >= 0 && i < nx) hn[d - 1] = h[((size_t)iy * nx + i) * nv + j];
         else if (periodic) hn[d - 1] = h[((size_t)iy * nx + wrap(i, nx)) * nv + j];
-        else if (i < 0) hn[d - 1] = ghost_value(c, WALL_LEFT, nw_left[iy], j, walls);
-        else hn[d - 1] = ghost_value(c, WALL_RIGHT, nw_right[iy], j, walls);
+        else if (i < 0) hn[d - 1] = ghost_value(c, WALL_LEFT, iy, nw_left[iy], j, walls);
+        else hn[d - 1] = ghost_value(c, WALL_RIGHT, iy, nw_right[iy], j, walls);
       }
       hx[(size_t)cell * nv + j] = bw_update(h0, hn[0], hn[1], C);
     }
@@ -586,8 +589,8 @@ static void sweep_y(const boltz_ref_ctx* c, const double* hx, double* hs, const 
         int i = iy - d * s;
         if (i >= 0 && i < ny) hn[d - 1] = hx[((size_t)i * nx + ix) * nv + j];
         else if (periodic) hn[d - 1] = hx[((size_t)wrap(i, ny) * nx + ix) * nv + j];
-        else if (i < 0) hn[d - 1] = ghost_value(c, WALL_BOTTOM, nw_bottom[ix], j, walls);
-        else hn[d - 1] = ghost_value(c, WALL_TOP, nw_top[ix], j, walls);
+        else if (i < 0) hn[d - 1] = ghost_value(c, WALL_BOTTOM, ix, nw_bottom[ix], j, walls);
+        else hn[d - 1] = ghost_value(c, WALL_TOP, ix, nw_top[ix], j, walls);
       }
       hs[(size_t)cell * nv + j] = bw_update(h0, hn[0], hn[1], C);
     }
@@ -618,15 +621,15 @@ static void stream_order1(const boltz_ref_ctx* c, const double* h, double* hs, c
         int i = ix - (vx > 0.0 ? 1 : -1);
         if (i >= 0 && i < nx) hxn = h[((size_t)iy * nx + i) * nv + j];
         else if (periodic) hxn = h[((size_t)iy * nx + wrap(i, nx)) * nv + j];
-        else if (i < 0) hxn = ghost_value(c, WALL_LEFT, nwl[iy], j, walls);
-        else hxn = ghost_value(c, WALL_RIGHT, nwr[iy], j, walls);
+        else if (i < 0) hxn = ghost_value(c, WALL_LEFT, iy, nwl[iy], j, walls);
+        else hxn = ghost_value(c, WALL_RIGHT, iy, nwr[iy], j, walls);
       }
       if (vy != 0.0) {
         int i = iy - (vy > 0.0 ? 1 : -1);
         if (i >= 0 && i < ny) hyn = h[((size_t)i * nx + ix) * nv + j];
         else if (periodic) hyn = h[((size_t)wrap(i, ny) * nx + ix) * nv + j];
-        else if (i < 0) hyn = ghost_value(c, WALL_BOTTOM, nwb[ix], j, walls);
-        else hyn = ghost_value(c, WALL_TOP, nwt[ix], j, walls);
+        else if (i < 0) hyn = ghost_value(c, WALL_BOTTOM, ix, nwb[ix], j, walls);
+        else hyn = ghost_value(c, WALL_TOP, ix, nwt[ix], j, walls);
       }
       hs[(size_t)cell * nv + j] = ((1.0 - Cx) - Cy) * h0 + Cx * hxn + Cy * hyn;
     }
@@ -911,12 +914,429 @@ int boltz_ref_moments(const boltz_ref_ctx* c, const double* h, const boltz_ref_w
         node_idx(c, j, &jx, &jy, &jz);
         double vx = c->v[0][jx], vy = c->v[1][jy];
         double hh = (vy > 0.0) ? h[(size_t)cell * nv + j]
-                               : (vy < 0.0 ? ghost_value(c, WALL_TOP, nw, j, walls) : 0.0);
+                               : (vy < 0.0 ? ghost_value(c, WALL_TOP, ix, nw, j, walls) : 0.0);
         pxy += node_w(c, jx, jy, jz) * vx * vy * hh;
       }
       total += 2.0 * pxy;
     }
     *lid_shear = -total / nx;
+  }
+  return BOLTZ_REF_OK;
+}
+
+/* ------------------------------------------------------------- adjoint -- */
+/* Reverse-mode derivatives of the discrete step above (the paper has no
+ * adjoint: every function below is the transpose of the linearisation of
+ * the forward function it names, taken piece by piece).  Wall parameters
+ * theta are indexed in grad[] as
+ *   0 lid_u, 1 tau_left, 2 tau_right, 3 tau_top, 4 + ix: tau of bottom face ix
+ * (for a uniform bottom wall the sum of the last nx entries is the
+ * derivative with respect to tau_bottom).  Pinned against centred finite
+ * differences of the forward functions (tests/test_oracle_adjoint.py). */
+
+enum { GRAD_LID_U = 0, GRAD_TAU_LEFT = 1, GRAD_TAU_RIGHT = 2, GRAD_TAU_TOP = 3, GRAD_TAU_BOTTOM0 = 4 };
+
+static int tau_index(int wall, int pos) {
+  switch (wall) {
+    case WALL_LEFT: return GRAD_TAU_LEFT;
+    case WALL_RIGHT: return GRAD_TAU_RIGHT;
+    case WALL_BOTTOM: return GRAD_TAU_BOTTOM0 + pos;
+    default: return GRAD_TAU_TOP;
+  }
+}
+
+/* dR/dU and dR/dtau of R = tau^-3/2 exp(|v|^2 - |v - U e_x|^2 / tau). */
+static void wall_ratio_grad(double vx, double vy, double vz, double U, double tau, double* dU,
+                            double* dtau) {
+  double R = wall_ratio(vx, vy, vz, U, tau);
+  double ux = vx - U;
+  double c2 = (ux * ux + vy * vy) + vz * vz;
+  *dU = R * 2.0 * ux / tau;
+  *dtau = R * (c2 / (tau * tau) - 1.5 / tau);
+}
+
+/* Adjoint of ghost_value: lam is the adjoint of h_w = (n_w R_j - 1)/eps of
+ * node j at face (wall, pos).  Adds the wall-parameter part to grad and
+ * returns the adjoint of n_w. */
+static double ghost_value_adj(const boltz_ref_ctx* c, int wall, int pos, double nw, int j,
+                              const boltz_ref_walls* walls, double lam, double* grad) {
+  int jx, jy, jz;
+  node_idx(c, j, &jx, &jy, &jz);
+  double U = (wall == WALL_TOP) ? walls->lid_u : 0.0;
+  double tau = wall_tau(walls, wall, pos);
+  double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+  double R = wall_ratio(vx, vy, vz, U, tau);
+  double dU, dtau;
+  wall_ratio_grad(vx, vy, vz, U, tau, &dU, &dtau);
+  if (grad) {
+    if (wall == WALL_TOP) grad[GRAD_LID_U] += lam * nw * dU / c->p.eps;
+    grad[tau_index(wall, pos)] += lam * nw * dtau / c->p.eps;
+  }
+  return lam * R / c->p.eps;
+}
+
+/* Adjoint of face_density: lam_nw is the adjoint of n_w of face (wall, pos)
+ * computed from src; adds the adjoint of src to lam_src and the
+ * wall-parameter part to grad. */
+static void face_density_adj(const boltz_ref_ctx* c, const double* src, int wall, int pos,
+                             const boltz_ref_walls* walls, int order, double lam_nw, double* lam_src,
+                             double* grad) {
+  const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
+  int nax = (wall == WALL_LEFT || wall == WALL_RIGHT) ? 0 : 1;
+  int sgn = (wall == WALL_LEFT || wall == WALL_BOTTOM) ? 1 : -1;
+  int ca, cb;
+  switch (wall) {
+    case WALL_LEFT: ca = pos * nx + 0; cb = pos * nx + 1; break;
+    case WALL_RIGHT: ca = pos * nx + nx - 1; cb = pos * nx + nx - 2; break;
+    case WALL_BOTTOM: ca = 0 * nx + pos; cb = 1 * nx + pos; break;
+    default: ca = (ny - 1) * nx + pos; cb = (ny - 2) * nx + pos; break;
+  }
+  double dl = (nax == 0) ? c->dx : c->dy;
+  double U = (wall == WALL_TOP) ? walls->lid_u : 0.0;
+  double tau = wall_tau(walls, wall, pos);
+  /* forward sums: n_w = phi_out / dens */
+  double phi_out = 0.0, dens = 0.0;
+  for (int j = 0; j < nv; ++j) {
+    int jx, jy, jz;
+    node_idx(c, j, &jx, &jy, &jz);
+    double vn = (nax == 0) ? c->v[0][jx] : c->v[1][jy];
+    if (!(sgn * vn < 0.0)) continue;
+    double an = fabs(vn);
+    double hh = src[(size_t)ca * nv + j];
+    if (order == 2) {
+      double C = an * c->dt / dl;
+      hh = hh + 0.5 * (1.0 - C) * (hh - src[(size_t)cb * nv + j]);
+    }
+    phi_out += (an * node_w(c, jx, jy, jz)) * (1.0 + c->p.eps * hh);
+    int mx = jx, my = jy;
+    if (nax == 0) mx = c->n[0] - 1 - jx; else my = c->n[1] - 1 - jy;
+    dens += (an * node_w(c, mx, my, jz)) * wall_ratio(c->v[0][mx], c->v[1][my], c->v[2][jz], U, tau);
+  }
+  double nw = phi_out / dens;
+  for (int j = 0; j < nv; ++j) {
+    int jx, jy, jz;
+    node_idx(c, j, &jx, &jy, &jz);
+    double vn = (nax == 0) ? c->v[0][jx] : c->v[1][jy];
+    if (!(sgn * vn < 0.0)) continue;
+    double an = fabs(vn);
+    /* d n_w / d hhat_j = eps |v_n| w_j / dens */
+    double lam_hh = lam_nw * c->p.eps * an * node_w(c, jx, jy, jz) / dens;
+    if (order == 2) {
+      double C = an * c->dt / dl;
+      lam_src[(size_t)ca * nv + j] += lam_hh * (1.0 + 0.5 * (1.0 - C));
+      lam_src[(size_t)cb * nv + j] -= lam_hh * 0.5 * (1.0 - C);
+    } else {
+      lam_src[(size_t)ca * nv + j] += lam_hh;
+    }
+    if (grad) {
+      /* d n_w / d R_m = -n_w |v_n| w_m / dens at the mirror node m */
+      int mx = jx, my = jy;
+      if (nax == 0) mx = c->n[0] - 1 - jx; else my = c->n[1] - 1 - jy;
+      double lam_R = -lam_nw * nw * an * node_w(c, mx, my, jz) / dens;
+      double dU, dtau;
+      wall_ratio_grad(c->v[0][mx], c->v[1][my], c->v[2][jz], U, tau, &dU, &dtau);
+      if (wall == WALL_TOP) grad[GRAD_LID_U] += lam_R * dU;
+      grad[tau_index(wall, pos)] += lam_R * dtau;
+    }
+  }
+}
+
+/* Coefficients of the Beam-Warming update: bw_update(h0, h1, h2, C) =
+ * a0 h0 + a1 h1 + a2 h2. */
+static void bw_coefs(double C, double* a) {
+  double c2 = 0.5 * C * (1.0 - C);
+  a[0] = (1.0 - C) - c2;
+  a[1] = C + 2.0 * c2;
+  a[2] = -c2;
+}
+
+/* Adjoint of one order-2 sweep along axis `ax` (0: x, 1: y): lam_out is the
+ * adjoint of out = BW_ax(in); adds the adjoint of `in` to lam_in and that of
+ * the face densities of the walls crossed to lam_nw (face order of
+ * boltz_ref_wall_density); wall-parameter parts go to grad. */
+static void sweep_adj(const boltz_ref_ctx* c, int ax, const double* lam_out, double* lam_in,
+                      const double* nw, double* lam_nw, const boltz_ref_walls* walls, double* grad) {
+  const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
+  const int periodic = (c->p.bc == BOLTZ_REF_BC_PERIODIC);
+  for (int cell = 0; cell < nx * ny; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double v = (ax == 0) ? c->v[0][jx] : c->v[1][jy];
+      double lam = lam_out[(size_t)cell * nv + j];
+      if (v == 0.0) {
+        lam_in[(size_t)cell * nv + j] += lam;
+        continue;
+      }
+      int s = v > 0.0 ? 1 : -1;
+      double a[3];
+      bw_coefs(fabs(v) * c->dt / ((ax == 0) ? c->dx : c->dy), a);
+      lam_in[(size_t)cell * nv + j] += a[0] * lam;
+      for (int d = 1; d <= 2; ++d) {
+        int i = ((ax == 0) ? ix : iy) - d * s, n = (ax == 0) ? nx : ny;
+        double l = a[d] * lam;
+        if (i >= 0 && i < n) {
+          int nb = (ax == 0) ? iy * nx + i : i * nx + ix;
+          lam_in[(size_t)nb * nv + j] += l;
+        } else if (periodic) {
+          int nb = (ax == 0) ? iy * nx + wrap(i, nx) : wrap(i, ny) * nx + ix;
+          lam_in[(size_t)nb * nv + j] += l;
+        } else {
+          int wall, pos, f;
+          if (ax == 0) {
+            wall = i < 0 ? WALL_LEFT : WALL_RIGHT;
+            pos = iy;
+            f = (wall == WALL_LEFT ? 0 : ny) + iy;
+          } else {
+            wall = i < 0 ? WALL_BOTTOM : WALL_TOP;
+            pos = ix;
+            f = 2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix;
+          }
+          lam_nw[f] += ghost_value_adj(c, wall, pos, nw[f], j, walls, l, grad);
+        }
+      }
+    }
+  }
+}
+
+/* Adjoint of the first-order unsplit step (stream_order1). */
+static void order1_adj(const boltz_ref_ctx* c, const double* lam_out, double* lam_in, const double* nw,
+                       double* lam_nw, const boltz_ref_walls* walls, double* grad) {
+  const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
+  const int periodic = (c->p.bc == BOLTZ_REF_BC_PERIODIC);
+  for (int cell = 0; cell < nx * ny; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx], vy = c->v[1][jy];
+      double Cx = fabs(vx) * c->dt / c->dx, Cy = fabs(vy) * c->dt / c->dy;
+      double lam = lam_out[(size_t)cell * nv + j];
+      lam_in[(size_t)cell * nv + j] += ((1.0 - Cx) - Cy) * lam;
+      for (int ax = 0; ax < 2; ++ax) {
+        double v = ax == 0 ? vx : vy;
+        if (v == 0.0) continue;
+        double l = (ax == 0 ? Cx : Cy) * lam;
+        int n = ax == 0 ? nx : ny;
+        int i = (ax == 0 ? ix : iy) - (v > 0.0 ? 1 : -1);
+        if (i >= 0 && i < n) {
+          int nb = ax == 0 ? iy * nx + i : i * nx + ix;
+          lam_in[(size_t)nb * nv + j] += l;
+        } else if (periodic) {
+          int nb = ax == 0 ? iy * nx + wrap(i, nx) : wrap(i, ny) * nx + ix;
+          lam_in[(size_t)nb * nv + j] += l;
+        } else {
+          int wall, pos, f;
+          if (ax == 0) {
+            wall = i < 0 ? WALL_LEFT : WALL_RIGHT;
+            pos = iy;
+            f = (wall == WALL_LEFT ? 0 : ny) + iy;
+          } else {
+            wall = i < 0 ? WALL_BOTTOM : WALL_TOP;
+            pos = ix;
+            f = 2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix;
+          }
+          lam_nw[f] += ghost_value_adj(c, wall, pos, nw[f], j, walls, l, grad);
+        }
+      }
+    }
+  }
+}
+
+int boltz_ref_stream_adjoint(const boltz_ref_ctx* c, const double* h_in, const double* lam_out,
+                             double* lam_in, double* grad, const boltz_ref_walls* walls) {
+  if (!c || !h_in || !lam_out || !lam_in) return BOLTZ_REF_EINVAL;
+  const int cavity = (c->p.bc == BOLTZ_REF_BC_CAVITY);
+  if (cavity && !walls) return BOLTZ_REF_EINVAL;
+  const int nx = c->p.nx, ny = c->p.ny;
+  const size_t n = (size_t)c->ncells * c->nv;
+  const int nf = 2 * (nx + ny);
+  double* nw = (double*)calloc((size_t)nf, sizeof(double));
+  double* lam_nw = (double*)calloc((size_t)nf, sizeof(double));
+  double* hx = (double*)malloc(sizeof(double) * n);
+  double* lam_hx = (double*)calloc(n, sizeof(double));
+  if (!nw || !lam_nw || !hx || !lam_hx) {
+    free(nw); free(lam_nw); free(hx); free(lam_hx);
+    return BOLTZ_REF_ENOMEM;
+  }
+  memset(lam_in, 0, sizeof(double) * n);
+  if (c->p.order == 1) {
+    if (cavity) all_wall_densities(c, h_in, NULL, walls, nw, 3);
+    order1_adj(c, lam_out, lam_in, nw, lam_nw, walls, grad);
+    if (cavity) {
+      for (int iy = 0; iy < ny; ++iy) {
+        face_density_adj(c, h_in, WALL_LEFT, iy, walls, 1, lam_nw[iy], lam_in, grad);
+        face_density_adj(c, h_in, WALL_RIGHT, iy, walls, 1, lam_nw[ny + iy], lam_in, grad);
+      }
+      for (int ix = 0; ix < nx; ++ix) {
+        face_density_adj(c, h_in, WALL_BOTTOM, ix, walls, 1, lam_nw[2 * ny + ix], lam_in, grad);
+        face_density_adj(c, h_in, WALL_TOP, ix, walls, 1, lam_nw[2 * ny + nx + ix], lam_in, grad);
+      }
+    }
+  } else {
+    /* forward intermediates: x faces from h, the x-swept state, y faces */
+    if (cavity) all_wall_densities(c, h_in, NULL, walls, nw, 1);
+    sweep_x(c, h_in, hx, nw, nw + ny, walls);
+    if (cavity) all_wall_densities(c, h_in, hx, walls, nw, 2);
+    /* y sweep, then the y faces (which read the x-swept state) */
+    sweep_adj(c, 1, lam_out, lam_hx, nw, lam_nw, walls, grad);
+    if (cavity)
+      for (int ix = 0; ix < nx; ++ix) {
+        face_density_adj(c, hx, WALL_BOTTOM, ix, walls, 2, lam_nw[2 * ny + ix], lam_hx, grad);
+        face_density_adj(c, hx, WALL_TOP, ix, walls, 2, lam_nw[2 * ny + nx + ix], lam_hx, grad);
+      }
+    /* x sweep, then the x faces */
+    sweep_adj(c, 0, lam_hx, lam_in, nw, lam_nw, walls, grad);
+    if (cavity)
+      for (int iy = 0; iy < ny; ++iy) {
+        face_density_adj(c, h_in, WALL_LEFT, iy, walls, 2, lam_nw[iy], lam_in, grad);
+        face_density_adj(c, h_in, WALL_RIGHT, iy, walls, 2, lam_nw[ny + iy], lam_in, grad);
+      }
+  }
+  free(nw); free(lam_nw); free(hx); free(lam_hx);
+  return BOLTZ_REF_OK;
+}
+
+/* Adjoint of the collision of one cell (see collide_cell): lam_o is the
+ * adjoint of the cell's output, lam_hs receives that of its post-stream h. */
+static void collide_cell_adj(const boltz_ref_ctx* c, int64_t cell, int64_t step, uint32_t flags,
+                             const double* hs, const double* lam_o, double* lam_hs, double* dn,
+                             double* hc, double* lam_dn) {
+  const int nv = c->nv;
+  const double eps = c->p.eps;
+  const int64_t nt = c->p.n_pairs;
+  uint32_t g = group_of(c, cell);
+  /* forward: Monte Carlo increments and h^c */
+  memset(dn, 0, sizeof(double) * nv);
+  for (int64_t m = 0; m < nt; ++m) {
+    pair_t pr;
+    sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
+    if (!pr.kept) continue;
+    double ha = hs[pr.a], hb = hs[pr.b];
+    double qg = pr.q * ((ha + hb) + (eps * ha) * hb);
+    dn[pr.as] += qg;
+    dn[pr.bs] += qg;
+    dn[pr.a] -= qg;
+    dn[pr.b] -= qg;
+  }
+  for (int j = 0; j < nv; ++j) {
+    int jx, jy, jz;
+    node_idx(c, j, &jx, &jy, &jz);
+    hc[j] = hs[j] + dn[j] / node_w(c, jx, jy, jz);
+  }
+  /* forward correction: M x = r; adjoint: y = M^-1 z with z = dJ/dx */
+  double x[5] = {0, 0, 0, 0, 0}, y[5] = {0, 0, 0, 0, 0};
+  int corrected = 0;
+  if (!(flags & BOLTZ_REF_NO_CORRECTION)) {
+    double M[5][5] = {{0}}, rr[5] = {0}, z[5] = {0};
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+      double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
+      double wF = node_w(c, jx, jy, jz) * (1.0 + eps * hc[j]);
+      for (int k = 0; k < 5; ++k) {
+        for (int l = 0; l < 5; ++l) M[k][l] += wF * psi[k] * psi[l];
+        rr[k] += -eps * psi[k] * dn[j];
+        /* h_out = h^c + (1 + eps h^c)(x . psi)/eps: dJ/dx_k */
+        z[k] += lam_o[j] * (1.0 + eps * hc[j]) * psi[k] / eps;
+      }
+    }
+    if (solve5(M, rr, x) == 0 && solve5(M, z, y) == 0) corrected = 1;
+    else for (int k = 0; k < 5; ++k) x[k] = y[k] = 0.0;
+  }
+  for (int j = 0; j < nv; ++j) {
+    int jx, jy, jz;
+    node_idx(c, j, &jx, &jy, &jz);
+    double w = node_w(c, jx, jy, jz);
+    double lam_hc = lam_o[j];
+    lam_dn[j] = 0.0;
+    if (corrected) {
+      double vx = c->v[0][jx], vy = c->v[1][jy], vz = c->v[2][jz];
+      double psi[5] = {1.0, vx, vy, vz, (vx * vx + vy * vy) + vz * vz};
+      double xpsi = 0.0, ypsi = 0.0;
+      for (int k = 0; k < 5; ++k) {
+        xpsi += x[k] * psi[k];
+        ypsi += y[k] * psi[k];
+      }
+      /* direct term, and M_kl = sum w (1 + eps h^c) psi_k psi_l (dJ/dM = -y x^T) */
+      lam_hc = lam_o[j] * (1.0 + xpsi) - eps * w * ypsi * xpsi;
+      /* r_k = -eps sum psi_k dN_j */
+      lam_dn[j] = -eps * ypsi;
+    }
+    /* h^c = h^s + dN / w */
+    lam_hs[j] = lam_hc;
+    lam_dn[j] += lam_hc / w;
+  }
+  /* Monte Carlo increments: dN_t += +-q g(h_a, h_b) */
+  for (int64_t m = 0; m < nt; ++m) {
+    pair_t pr;
+    sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
+    if (!pr.kept) continue;
+    double G = pr.q * ((lam_dn[pr.as] + lam_dn[pr.bs]) - (lam_dn[pr.a] + lam_dn[pr.b]));
+    lam_hs[pr.a] += G * (1.0 + eps * hs[pr.b]);
+    lam_hs[pr.b] += G * (1.0 + eps * hs[pr.a]);
+  }
+}
+
+int boltz_ref_collide_adjoint(const boltz_ref_ctx* c, const double* h_s, const double* lam_out,
+                              double* lam_s, int64_t step, uint32_t flags) {
+  if (!c || !h_s || !lam_out || !lam_s) return BOLTZ_REF_EINVAL;
+  const int nv = c->nv;
+#pragma omp parallel
+  {
+    double* dn = (double*)malloc(sizeof(double) * nv);
+    double* hc = (double*)malloc(sizeof(double) * nv);
+    double* ld = (double*)malloc(sizeof(double) * nv);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t cell = 0; cell < c->ncells; ++cell)
+      collide_cell_adj(c, cell, step, flags, h_s + (size_t)cell * nv, lam_out + (size_t)cell * nv,
+                       lam_s + (size_t)cell * nv, dn, hc, ld);
+    free(dn);
+    free(hc);
+    free(ld);
+  }
+  return BOLTZ_REF_OK;
+}
+
+int boltz_ref_step_adjoint(const boltz_ref_ctx* c, const double* h_in, const double* lam_out,
+                           double* lam_in, double* grad, const boltz_ref_walls* walls, int64_t step) {
+  if (!c || !h_in || !lam_out || !lam_in || lam_out == lam_in) return BOLTZ_REF_EINVAL;
+  const size_t n = (size_t)c->ncells * c->nv;
+  double* hs = (double*)malloc(sizeof(double) * n);
+  double* lam_s = (double*)malloc(sizeof(double) * n);
+  if (!hs || !lam_s) {
+    free(hs);
+    free(lam_s);
+    return BOLTZ_REF_ENOMEM;
+  }
+  int rc = boltz_ref_stream(c, h_in, hs, walls);
+  if (rc == BOLTZ_REF_OK) rc = boltz_ref_collide_adjoint(c, hs, lam_out, lam_s, step, 0u);
+  if (rc == BOLTZ_REF_OK) rc = boltz_ref_stream_adjoint(c, h_in, lam_s, lam_in, grad, walls);
+  free(hs);
+  free(lam_s);
+  return rc;
+}
+
+int boltz_ref_lid_shear_adjoint(const boltz_ref_ctx* c, const double* h, const boltz_ref_walls* walls,
+                                double weight, double* lam, double* grad) {
+  if (!c || !h || !walls || !lam || c->p.bc != BOLTZ_REF_BC_CAVITY) return BOLTZ_REF_EINVAL;
+  const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
+  /* D = -(1/nx) sum_ix 2 sum_j w_j v_x v_y hhat_j (see boltz_ref_moments) */
+  for (int ix = 0; ix < nx; ++ix) {
+    int cell = (ny - 1) * nx + ix;
+    double nw = face_density(c, h, WALL_TOP, ix, walls, 1);
+    double lam_nw = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      int jx, jy, jz;
+      node_idx(c, j, &jx, &jy, &jz);
+      double vx = c->v[0][jx], vy = c->v[1][jy];
+      double coef = weight * (-2.0 / nx) * node_w(c, jx, jy, jz) * vx * vy;
+      if (vy > 0.0) lam[(size_t)cell * nv + j] += coef;
+      else if (vy < 0.0) lam_nw += ghost_value_adj(c, WALL_TOP, ix, nw, j, walls, coef, grad);
+    }
+    face_density_adj(c, h, WALL_TOP, ix, walls, 1, lam_nw, lam, grad);
   }
   return BOLTZ_REF_OK;
 }

@@ -62,6 +62,8 @@ typedef struct boltz_ref_problem {
 typedef struct boltz_ref_walls {
   double lid_u;          /* x velocity of the top wall (y = 1)              */
   double tau_left, tau_right, tau_bottom, tau_top;  /* T_w / T0            */
+  const double* tau_bottom_x;  /* NULL, or nx per-face T_w / T0 of the     */
+                               /* bottom wall (replaces tau_bottom)         */
 } boltz_ref_walls;
 
 typedef struct boltz_ref_ctx boltz_ref_ctx;
@@ -133,6 +135,31 @@ int boltz_ref_moments(const boltz_ref_ctx* ctx, const double* h,
 
 int boltz_ref_step(const boltz_ref_ctx* ctx, const double* h_in, double* h_out,
                    const boltz_ref_walls* walls, int64_t step);
+
+/* ------------------------------------------------------------ adjoint --
+ * Reverse-mode derivatives of the functions above (their transposed
+ * linearisations), FP64.  Wall parameters in grad[] (cavity problems,
+ * 4 + nx entries, accumulated): lid_u, tau_left, tau_right, tau_top, then
+ * the temperature of every bottom face.  Pinned against centred finite
+ * differences of the forward functions. */
+
+/* lam_in = (d stream / d h_in)^T lam_out; grad += (d stream / d theta)^T lam_out. */
+int boltz_ref_stream_adjoint(const boltz_ref_ctx* ctx, const double* h_in, const double* lam_out,
+                             double* lam_in, double* grad, const boltz_ref_walls* walls);
+
+/* lam_s = (d collide / d h_s)^T lam_out for fixed samples (flags as in
+ * boltz_ref_collide). */
+int boltz_ref_collide_adjoint(const boltz_ref_ctx* ctx, const double* h_s, const double* lam_out,
+                              double* lam_s, int64_t step, uint32_t flags);
+
+/* Adjoint of boltz_ref_step (forward recomputed from h_in). */
+int boltz_ref_step_adjoint(const boltz_ref_ctx* ctx, const double* h_in, const double* lam_out,
+                           double* lam_in, double* grad, const boltz_ref_walls* walls, int64_t step);
+
+/* lam += weight dD/dh and grad += weight dD/dtheta for the lid shear D of
+ * boltz_ref_moments. */
+int boltz_ref_lid_shear_adjoint(const boltz_ref_ctx* ctx, const double* h, const boltz_ref_walls* walls,
+                                double weight, double* lam, double* grad);
 
 #ifdef __cplusplus
 }
