@@ -57,7 +57,9 @@ typedef enum boltz_status {
 enum { BOLTZ_BC_CAVITY = 0, BOLTZ_BC_PERIODIC = 1 };
 
 /* boltz_problem.flags */
-enum { BOLTZ_ALLOW_UNSTABLE = 1u };  /* accept a dt above the Courant limit  */
+enum { BOLTZ_ALLOW_UNSTABLE = 1u,    /* accept a dt above the Courant limit  */
+       BOLTZ_WITH_ADJOINT = 2u };    /* also allocate the scratch of         */
+                                     /* boltz_step_adjoint                   */
 /* boltz_collide flags */
 enum { BOLTZ_NO_CORRECTION = 1u };   /* skip S5 (raw Monte Carlo update)     */
 /* device status bits (boltz_read_status) */
@@ -80,7 +82,7 @@ typedef struct boltz_problem {
                          /* per step into a context table (16 B per pair)   */
   uint64_t seed;         /* Philox4x32-10 key (low word, high word)          */
   uint32_t cavity_id;    /* fourth Philox counter word                       */
-  uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE                             */
+  uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT        */
   uint32_t mix16;        /* uniform share beta = mix16/16 of the node-pair   */
                          /* law (0..16; 0 = the paper's sampling from Phi0)  */
 } boltz_problem;
@@ -89,6 +91,9 @@ typedef struct boltz_problem {
 typedef struct boltz_walls {
   double lid_u;          /* x velocity of the top wall y = 1, in V0          */
   double tau_left, tau_right, tau_bottom, tau_top;  /* T_w / T0, > 0         */
+  const double* tau_bottom_x;  /* NULL, or a HOST array of nx values T_w/T0  */
+                               /* of the bottom faces (replaces tau_bottom;  */
+                               /* read during the call only)                 */
 } boltz_walls;
 
 typedef struct boltz_info {
@@ -160,11 +165,48 @@ int boltz_moments(boltz_ctx* ctx, const float* h, const boltz_walls* walls, doub
 int boltz_step(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_walls* walls,
                int64_t step, void* stream);
 
-/* Adjoint of boltz_step for fixed Philox streams (gradient of a functional
- * of h_out with respect to h_in and to the wall parameters).  Declared for
- * interface stability; this build returns BOLTZ_EUNSUPPORTED. */
+/* ---- Reverse mode (the paper has no adjoint; these are the transposes of
+ * the linearised calls above for fixed Philox samples, used to differentiate
+ * a functional of the flow with respect to the initial state and the wall
+ * parameters).  Adjoints are FP64 device buffers of ncells*nv values in the
+ * layout of h.  grad_walls: NULL or a device FP64 array of 4 + nx entries to
+ * which the call ADDS the wall-parameter gradient, in the order
+ *   lid_u, tau_left, tau_right, tau_top, tau of bottom face 0 .. nx-1
+ * (a uniform bottom wall: the sum of the last nx entries is the derivative
+ * with respect to tau_bottom); periodic problems add nothing.  The context
+ * scratch used by these calls (BOLTZ_WITH_ADJOINT at boltz_create): 12 bytes
+ * per phase-space node.  EUNSUPPORTED: a velocity grid whose h tile, FP32
+ * and 64-bit arrays and tables exceed the 160 KB local data share. */
+
+/* Adjoint of boltz_stream (Sec. 3, Eq. streaming2D / the Beam-Warming
+ * sweeps, with the wall emission of Eq. bcMax): lam_in = (dh_out/dh_in)^T
+ * lam_out, where h_out = boltz_stream(h_in).  h_in: the FP32 state that was
+ * streamed.  lam_in must not overlap lam_out.  Order 2 needs the
+ * BOLTZ_WITH_ADJOINT scratch. */
+int boltz_stream_adjoint(boltz_ctx* ctx, const float* h_in, const double* lam_out, double* lam_in,
+                         double* grad_walls, const boltz_walls* walls, void* stream);
+
+/* Adjoint of boltz_collide (Sec. 3, Eqs. monteCarloInt, collision_step,
+ * rinorm_a, correzione) at the post-stream state h_s: lam_s =
+ * (dh_out/dh_s)^T lam_out.  The collision is recomputed per cell from h_s;
+ * the correction's 5x5 system is solved a second time for the transposed
+ * right-hand side.  lam_s may equal lam_out (in place).  flags:
+ * BOLTZ_NO_CORRECTION. */
+int boltz_collide_adjoint(boltz_ctx* ctx, const float* h_s, const double* lam_out, double* lam_s, int64_t step,
+                          uint32_t flags, void* stream);
+
+/* Adjoint of boltz_step (h_in -> h_out at `step`): lam_in = (dh_out/dh_in)^T
+ * lam_out, and the wall-parameter gradient added to grad_walls.  The
+ * post-stream state is recomputed from h_in.  lam_in may equal lam_out (in
+ * place); needs the BOLTZ_WITH_ADJOINT scratch (EINVAL otherwise). */
 int boltz_step_adjoint(boltz_ctx* ctx, const float* h_in, const double* lam_out, double* lam_in,
                        double* grad_walls, const boltz_walls* walls, int64_t step, void* stream);
+
+/* Adjoint of weight * D, D the lid shear of boltz_moments (Sec. 5.2): ADDS
+ * weight * dD/dh to lam (only the top row of cells changes) and
+ * weight * dD/dtheta to grad_walls (NULL: not formed).  Cavity only. */
+int boltz_lid_shear_adjoint(boltz_ctx* ctx, const float* h, const boltz_walls* walls, double weight, double* lam,
+                            double* grad_walls, void* stream);
 
 /* Test hook: the pairs the collision kernel draws for (cell, step) and pair
  * indices m0 .. m0+count-1, computed on the device by the kernel's own

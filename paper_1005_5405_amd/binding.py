@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libboltz.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BC_CAVITY, BC_PERIODIC = 0, 1
-ALLOW_UNSTABLE = 1
+ALLOW_UNSTABLE, WITH_ADJOINT = 1, 2
 NO_CORRECTION = 1
 STATUS_NOT_SPD, STATUS_NONFINITE = 1, 2
 
@@ -41,7 +41,7 @@ class _Problem(ctypes.Structure):
 
 class _Walls(ctypes.Structure):
     _fields_ = [("lid_u", ctypes.c_double), ("tau_left", ctypes.c_double), ("tau_right", ctypes.c_double),
-                ("tau_bottom", ctypes.c_double), ("tau_top", ctypes.c_double)]
+                ("tau_bottom", ctypes.c_double), ("tau_top", ctypes.c_double), ("tau_bottom_x", ctypes.c_void_p)]
 
 
 class _Info(ctypes.Structure):
@@ -51,8 +51,9 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ("boltz_create", "boltz_destroy", "boltz_query", "boltz_last_error", "boltz_stream",
-           "boltz_collide", "boltz_moments", "boltz_step", "boltz_step_adjoint", "boltz_debug_pairs",
-           "boltz_axis_thresholds", "boltz_read_status")
+           "boltz_collide", "boltz_moments", "boltz_step", "boltz_stream_adjoint", "boltz_collide_adjoint",
+           "boltz_step_adjoint", "boltz_lid_shear_adjoint", "boltz_debug_pairs", "boltz_axis_thresholds",
+           "boltz_read_status")
 
 _lib = None
 
@@ -82,7 +83,10 @@ def load_library(path: str = LIB_PATH):
     L.boltz_collide.argtypes = [P, V, V, I64, U32, V, V]
     L.boltz_moments.argtypes = [P, V, W, V, V, V]
     L.boltz_step.argtypes = [P, V, V, W, I64, V]
+    L.boltz_stream_adjoint.argtypes = [P, V, V, V, V, W, V]
+    L.boltz_collide_adjoint.argtypes = [P, V, V, V, I64, U32, V]
     L.boltz_step_adjoint.argtypes = [P, V, V, V, V, W, I64, V]
+    L.boltz_lid_shear_adjoint.argtypes = [P, V, W, ctypes.c_double, V, V, V]
     L.boltz_debug_pairs.argtypes = [P, I64, I64, I64, I64, V, V, V]
     L.boltz_axis_thresholds.argtypes = [P, ctypes.c_int, V]
     L.boltz_read_status.argtypes = [P, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, V]
@@ -96,15 +100,25 @@ def load_library(path: str = LIB_PATH):
 
 @dataclass
 class Walls:
-    """Wall state of one call: lid x velocity and wall temperatures T_w/T0."""
+    """Wall state of one call: lid x velocity and wall temperatures T_w/T0;
+    tau_bottom_x (None or nx values) gives every bottom face its own."""
     lid_u: float = 0.0
     tau_left: float = 1.0
     tau_right: float = 1.0
     tau_bottom: float = 1.0
     tau_top: float = 1.0
+    tau_bottom_x: object = None
 
     def _c(self) -> _Walls:
-        return _Walls(self.lid_u, self.tau_left, self.tau_right, self.tau_bottom, self.tau_top)
+        ptr = None
+        if self.tau_bottom_x is not None:
+            self._tbx = np.ascontiguousarray(self.tau_bottom_x, dtype=np.float64)
+            ptr = self._tbx.ctypes.data
+        return _Walls(self.lid_u, self.tau_left, self.tau_right, self.tau_bottom, self.tau_top, ptr)
+
+
+# wall-parameter gradient entries (then one per bottom face)
+GRAD_NAMES = ("lid_u", "tau_left", "tau_right", "tau_top")
 
 
 def _ptr(t, numel, dtype, what, allow_none=False):
@@ -214,15 +228,59 @@ class Boltz:
                                     _ptr(h_out, self.numel, torch.float32, "h_out"), self._walls(walls), int(step),
                                     _stream(stream)), "boltz_step")
 
+    # ---- reverse mode (adjoints FP64; grad_walls: None or 4 + nx FP64 values
+    # that the calls add to, see GRAD_NAMES)
+    def grad_size(self):
+        return 4 + self.nx
+
+    def empty_adjoint(self, fill=None):
+        import torch
+
+        t = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        if fill is not None:
+            t.fill_(fill)
+        return t
+
+    def _grad(self, g):
+        import torch
+
+        return _ptr(g, self.grad_size(), torch.float64, "grad_walls", True)
+
+    def stream_adjoint(self, h_in, lam_out, lam_in, grad_walls=None, walls=None, stream=None):
+        import torch
+
+        self._check(_lib.boltz_stream_adjoint(self._ctx, _ptr(h_in, self.numel, torch.float32, "h_in"),
+                                              _ptr(lam_out, self.numel, torch.float64, "lam_out"),
+                                              _ptr(lam_in, self.numel, torch.float64, "lam_in"),
+                                              self._grad(grad_walls), self._walls(walls), _stream(stream)),
+                    "boltz_stream_adjoint")
+
+    def collide_adjoint(self, h_s, lam_out, lam_s, step, correction=True, stream=None):
+        import torch
+
+        flags = 0 if correction else NO_CORRECTION
+        self._check(_lib.boltz_collide_adjoint(self._ctx, _ptr(h_s, self.numel, torch.float32, "h_s"),
+                                               _ptr(lam_out, self.numel, torch.float64, "lam_out"),
+                                               _ptr(lam_s, self.numel, torch.float64, "lam_s"), int(step), flags,
+                                               _stream(stream)), "boltz_collide_adjoint")
+
     def step_adjoint(self, h_in, lam_out, lam_in, grad_walls, walls, step, stream=None):
         import torch
 
         self._check(_lib.boltz_step_adjoint(self._ctx, _ptr(h_in, self.numel, torch.float32, "h_in"),
                                             _ptr(lam_out, self.numel, torch.float64, "lam_out"),
                                             _ptr(lam_in, self.numel, torch.float64, "lam_in"),
-                                            _ptr(grad_walls, grad_walls.numel() if grad_walls is not None else 0,
-                                                 torch.float64, "grad_walls", True),
-                                            self._walls(walls), int(step), _stream(stream)), "boltz_step_adjoint")
+                                            self._grad(grad_walls), self._walls(walls), int(step), _stream(stream)),
+                    "boltz_step_adjoint")
+
+    def lid_shear_adjoint(self, h, walls, weight, lam, grad_walls=None, stream=None):
+        import torch
+
+        self._check(_lib.boltz_lid_shear_adjoint(self._ctx, _ptr(h, self.numel, torch.float32, "h"),
+                                                 self._walls(walls), float(weight),
+                                                 _ptr(lam, self.numel, torch.float64, "lam"),
+                                                 self._grad(grad_walls), _stream(stream)),
+                    "boltz_lid_shear_adjoint")
 
     # ---- test hooks
     def debug_pairs(self, cell, step, m0, count, words=False):

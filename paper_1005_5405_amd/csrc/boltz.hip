@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "boltz.h"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace boltz;
@@ -48,7 +49,18 @@ struct boltz_ctx {
   int64_t ngroups = 0;          // sample groups (shared-sample mode)
   // wall state the ratio tables Phi_w / Phi0 were last built for
   WallArgs ratio_walls{};
+  std::vector<double> ratio_taub;   // bottom-face temperatures of that state
   bool ratio_valid = false;
+  // adjoint: collide-adjoint launch (block, dynamic LDS, grid) of the two
+  // variants, and the scratch of BOLTZ_WITH_ADJOINT
+  bool adj_supported = false;
+  int adj_block = 256;
+  size_t adj_lds[2] = {0, 0};
+  int64_t adj_grid[2] = {0, 0};
+  float* adj_hs = nullptr;      // post-stream state recomputed by boltz_step_adjoint
+  double* adj_lam = nullptr;    // FP64 adjoint of an intermediate state
+  double* lnw = nullptr;        // adjoint of every face density
+  double* gpart = nullptr;      // per-face wall-parameter partials [nfaces][2]
   uint2* tidx = nullptr;        // ngroups * n_pairs pair indices (G != 1)
   float4* tcoef = nullptr;      // ngroups * n_pairs pair coefficients
   std::string err;
@@ -79,9 +91,23 @@ WallArgs make_walls(const boltz_walls* w) {
   return a;
 }
 
-bool walls_ok(const boltz_walls* w) {
-  return w && w->tau_left > 0 && w->tau_right > 0 && w->tau_bottom > 0 && w->tau_top > 0 &&
-         std::isfinite(w->lid_u);
+bool walls_ok(const boltz_walls* w, int nx) {
+  if (!(w && w->tau_left > 0 && w->tau_right > 0 && w->tau_bottom > 0 && w->tau_top > 0 &&
+        std::isfinite(w->lid_u) && std::isfinite(w->tau_left) && std::isfinite(w->tau_right) &&
+        std::isfinite(w->tau_bottom) && std::isfinite(w->tau_top)))
+    return false;
+  if (w->tau_bottom_x)
+    for (int i = 0; i < nx; ++i)
+      if (!(w->tau_bottom_x[i] > 0) || !std::isfinite(w->tau_bottom_x[i])) return false;
+  return true;
+}
+
+// temperatures of the bottom faces of a wall state
+std::vector<double> bottom_taus(const boltz_walls* w, int nx) {
+  std::vector<double> t(nx, w ? w->tau_bottom : 1.0);
+  if (w && w->tau_bottom_x)
+    for (int i = 0; i < nx; ++i) t[i] = w->tau_bottom_x[i];
+  return t;
 }
 
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -111,6 +137,21 @@ bool pick_collide(int nv, int ns, bool& fixed, int (&blocks)[2]) {
     if ((b == 256 || b == 512 || b == 1024) && dyn + collide_static_lds(b) <= kLdsBytes) blocks[0] = blocks[1] = b;
   }
   return true;
+}
+
+// Block size of the collide adjoint (the fixed-point layout plus a y . psi
+// table must fit in LDS): 256 threads when four workgroups fit per CU, else
+// 512.  false when the layout does not fit.
+bool pick_adjoint(int nv, int ns, int& block) {
+  const size_t dyn = collide_adj_lds(nv, ns, true);
+  if (dyn + collide_static_lds(512) > kLdsBytes) return false;
+  block = (4 * (dyn + collide_static_lds(256)) <= kLdsBytes) ? 256 : 512;
+  return true;
+}
+
+const void* collide_adj_fn(int block, bool table) {
+  if (block == 256) return table ? (const void*)collide_adj_kernel<256, true> : (const void*)collide_adj_kernel<256, false>;
+  return table ? (const void*)collide_adj_kernel<512, true> : (const void*)collide_adj_kernel<512, false>;
 }
 
 const void* collide_fn(int block, bool table, bool fixed) {
@@ -157,7 +198,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   if (!(p->delta > 0.0) || !(p->eps > 0.0) || (p->order != 1 && p->order != 2) ||
       (p->bc != BOLTZ_BC_CAVITY && p->bc != BOLTZ_BC_PERIODIC) || p->n_pairs < 0 ||
       p->n_pairs >= ((int64_t)1 << 31) || p->sample_group < 0 || p->mix16 > 16 ||
-      (!(p->dt > 0.0) && !(p->cfl > 0.0)))
+      (!(p->dt > 0.0) && !(p->cfl > 0.0)) ||
+      (p->flags & ~(uint32_t)(BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT)))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: invalid scalar parameter");
   const int64_t nvt = (int64_t)p->nv[0] * p->nv[1] * p->nv[2];
   const int nsum = p->nv[0] + p->nv[1] + p->nv[2];
@@ -302,11 +344,20 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t o_cour2 = off; off = align256(off + cour2.size() * 4);
   const size_t o_nw = off; off = align256(off + (size_t)nfaces * 8);
   const size_t o_ratio = off; off = align256(off + (size_t)4 * c->nv * 8);
+  const size_t o_ratio_b = off; off = align256(off + (size_t)p->nx * c->nv * 8);
+  const size_t o_tau_b = off; off = align256(off + (size_t)p->nx * 8);
+  const size_t o_wconst_b = off; off = align256(off + (size_t)p->nx * 2 * 8);
   const size_t o_dpart = off; off = align256(off + (size_t)p->nx * 8);
   const size_t o_wconst = off; off = align256(off + 8 * 8);
   const size_t o_status = off; off = align256(off + 4);
+  const size_t o_lnw = off; off = align256(off + (size_t)nfaces * 8);
+  const size_t o_gpart = off; off = align256(off + (size_t)nfaces * 2 * 8);
   const size_t o_tidx = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(uint2));
   const size_t o_tcoef = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(float4));
+  const bool with_adj = (p->flags & BOLTZ_WITH_ADJOINT) != 0;
+  const size_t nodes = (size_t)c->ncells * (size_t)c->nv;
+  const size_t o_adj_hs = off; off = align256(off + (with_adj ? nodes * 4 : 0));
+  const size_t o_adj_lam = off; off = align256(off + (with_adj ? nodes * 8 : 0));
   (void)hipGetDevice(&c->device);
   hipError_t e = hipMalloc(&c->dmem, off);
   if (e != hipSuccess) {
@@ -367,12 +418,19 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.cour2 = reinterpret_cast<const float*>(base + o_cour2);
   P.nw = reinterpret_cast<double*>(base + o_nw);
   P.ratio = reinterpret_cast<double*>(base + o_ratio);
+  P.ratio_b = reinterpret_cast<double*>(base + o_ratio_b);
+  P.tau_b = reinterpret_cast<const double*>(base + o_tau_b);
+  P.wconst_b = reinterpret_cast<double*>(base + o_wconst_b);
   P.dpart = reinterpret_cast<double*>(base + o_dpart);
   P.wconst = reinterpret_cast<double*>(base + o_wconst);
   P.status = reinterpret_cast<uint32_t*>(base + o_status);
   c->ngroups = ngroups;
   c->tidx = ngroups ? reinterpret_cast<uint2*>(base + o_tidx) : nullptr;
   c->tcoef = ngroups ? reinterpret_cast<float4*>(base + o_tcoef) : nullptr;
+  c->lnw = reinterpret_cast<double*>(base + o_lnw);
+  c->gpart = reinterpret_cast<double*>(base + o_gpart);
+  c->adj_hs = with_adj ? reinterpret_cast<float*>(base + o_adj_hs) : nullptr;
+  c->adj_lam = with_adj ? reinterpret_cast<double*>(base + o_adj_lam) : nullptr;
   c->collide_block[0] = cblock[0];
   c->collide_block[1] = cblock[1];
   c->collide_fixed = cfixed;
@@ -388,6 +446,18 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
     const int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
+  }
+  c->adj_supported = pick_adjoint(c->nv, nsum, c->adj_block);
+  for (int t = 0; t < 2 && ea == hipSuccess && c->adj_supported; ++t) {
+    const void* fn = collide_adj_fn(c->adj_block, t == 1);
+    c->adj_lds[t] = collide_adj_lds(c->nv, nsum, t == 0);
+    ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->adj_lds[t]);
+    int per_cu = 0;
+    if (ea == hipSuccess)
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, c->adj_block, c->adj_lds[t]);
+    if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
+    const int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
+    c->adj_grid[t] = c->ncells < cap ? c->ncells : cap;
   }
   if (ea != hipSuccess) {
     boltz_destroy(c);
@@ -415,15 +485,27 @@ int boltz_axis_thresholds(const boltz_ctx* c, int axis, uint64_t* out) {
   return BOLTZ_OK;
 }
 
-static void ensure_ratio(boltz_ctx* c, const WallArgs& W, hipStream_t st) {
-  if (c->ratio_valid && std::memcmp(&c->ratio_walls, &W, sizeof(WallArgs)) == 0) return;
-  hipLaunchKernelGGL(wallconst_kernel, dim3(4), dim3(kWallConstBlock), 0, st, c->P, W);
+// Rebuild the wall tables (Phi_w / Phi0 and the flux constants A, D) when the
+// wall state differs from the one they were built for.
+static int ensure_ratio(boltz_ctx* c, const WallArgs& W, const boltz_walls* walls, hipStream_t st) {
+  std::vector<double> taub = bottom_taus(walls, c->p.nx);
+  if (c->ratio_valid && std::memcmp(&c->ratio_walls, &W, sizeof(WallArgs)) == 0 && taub == c->ratio_taub)
+    return BOLTZ_OK;
+  // from pageable host memory: staged before the call returns
+  hipError_t e = hipMemcpyAsync(const_cast<double*>(c->P.tau_b), taub.data(), taub.size() * sizeof(double),
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(c, e, "wall temperatures");
+  hipLaunchKernelGGL(wallconst_kernel, dim3(3 + c->p.nx), dim3(kWallConstBlock), 0, st, c->P, W);
   c->ratio_walls = W;
+  c->ratio_taub = taub;
   c->ratio_valid = true;
+  return BOLTZ_OK;
 }
 
-static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, hipStream_t st) {
-  ensure_ratio(c, W, st);
+static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const boltz_walls* walls,
+                        hipStream_t st) {
+  const int rc = ensure_ratio(c, W, walls, st);
+  if (rc != BOLTZ_OK) return rc;
   auto launch = [&](auto kern, int nface) {
     const int per_xcd = (nface + 7) / 8;
     hipLaunchKernelGGL(kern, dim3(8 * per_xcd), dim3(kWallBlock), 0, st, c->P, W, h, nface, per_xcd);
@@ -493,16 +575,21 @@ static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* h
   }
 }
 
-static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
-                          double* defect, hipStream_t st) {
-  const uint32_t s32 = (uint32_t)step;
-  const bool table = c->ngroups > 0;
-  if (table && c->p.n_pairs > 0) {
+// Shared-sample mode: the pair records of every group for this step.
+static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st) {
+  if (c->ngroups > 0 && c->p.n_pairs > 0) {
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     const dim3 grid((unsigned)((c->p.n_pairs + 255) / 256), (unsigned)c->ngroups);
     hipLaunchKernelGGL(sample_kernel, grid, dim3(256), TablesLDS::bytes(nsum, true), st, c->P, s32, c->tidx,
                        c->tcoef);
   }
+}
+
+static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
+                          double* defect, hipStream_t st) {
+  const uint32_t s32 = (uint32_t)step;
+  const bool table = c->ngroups > 0;
+  launch_samples(c, s32, st);
   switch (c->collide_block[table ? 1 : 0]) {
     case 256: launch_collide_b<256>(c, table, hs, hout, s32, flags, defect, st); break;
     case 512: launch_collide_b<512>(c, table, hs, hout, s32, flags, defect, st); break;
@@ -524,10 +611,10 @@ int boltz_stream(boltz_ctx* c, const float* h_in, float* h_out, const boltz_wall
   const size_t bytes = (size_t)c->ncells * c->nv * sizeof(float);
   if (overlap(h_in, h_out, bytes)) return fail(c, BOLTZ_EINVAL, "boltz_stream: h_in and h_out overlap");
   const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
-  if (cavity && !walls_ok(walls)) return fail(c, BOLTZ_EINVAL, "boltz_stream: cavity needs valid walls");
+  if (cavity && !walls_ok(walls, c->p.nx)) return fail(c, BOLTZ_EINVAL, "boltz_stream: cavity needs valid walls");
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = BOLTZ_OK;
-  if (cavity) rc = launch_walls(c, h_in, make_walls(walls), st);
+  if (cavity) rc = launch_walls(c, h_in, make_walls(walls), walls, st);
   if (rc == BOLTZ_OK) rc = launch_stream(c, h_in, h_out, st);
   return rc;
 }
@@ -554,11 +641,14 @@ int boltz_moments(boltz_ctx* c, const float* h, const boltz_walls* walls, double
                   void* stream) {
   if (!c) return BOLTZ_EINVAL;
   if (!h || !mom) return fail(c, BOLTZ_EINVAL, "boltz_moments: null buffer");
-  if (lid_shear && (c->p.bc != BOLTZ_BC_CAVITY || !walls_ok(walls)))
+  if (lid_shear && (c->p.bc != BOLTZ_BC_CAVITY || !walls_ok(walls, c->p.nx)))
     return fail(c, BOLTZ_EINVAL, "boltz_moments: lid shear needs a cavity and valid walls");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const WallArgs W = make_walls(walls);
-  if (lid_shear) ensure_ratio(c, W, st);
+  if (lid_shear) {
+    const int rc = ensure_ratio(c, W, walls, st);
+    if (rc != BOLTZ_OK) return rc;
+  }
   hipLaunchKernelGGL(moments_kernel, dim3((unsigned)c->ncells), dim3(256), 0, st, c->P, W, h, mom,
                      lid_shear ? 1 : 0);
   if (lid_shear) hipLaunchKernelGGL(lid_reduce_kernel, dim3(1), dim3(64), 0, st, c->P, lid_shear);
@@ -566,10 +656,152 @@ int boltz_moments(boltz_ctx* c, const float* h, const boltz_walls* walls, double
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "moments_kernel launch");
 }
 
-int boltz_step_adjoint(boltz_ctx* c, const float*, const double*, double*, double*, const boltz_walls*, int64_t,
-                       void*) {
+}  // extern "C"
+
+// ------------------------------------------------------------- adjoint --
+// Reverse mode of the streaming step whose face densities P.nw are current:
+// lo (adjoint of the streamed state) -> li.  Order 2: y sweep transposed
+// into tmp, then x sweep into li (li may equal lo); order 1: li != lo.
+// Wall-parameter partials go to grad (when not NULL).
+static int launch_stream_adj(boltz_ctx* c, const WallArgs& W, const double* lo, double* li, double* tmp,
+                             double* grad, hipStream_t st) {
+  const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
+  const int nx = c->p.nx, ny = c->p.ny;
+  const int nchunks = (c->nv + kSweepAdjBlock - 1) / kSweepAdjBlock;
+  auto walls_adj = [&](const double* lam, int f0, int nface) {
+    const int per_xcd = (nface + 7) / 8;
+    hipLaunchKernelGGL(wall_adj_kernel, dim3(8 * per_xcd), dim3(kWallAdjBlock), 0, st, c->P, W, lam, c->lnw,
+                       c->gpart, f0, nface, per_xcd);
+  };
+  auto sweep = [&](auto kern, const double* in, double* out, int nlines) {
+    const long long units = (long long)nlines * nchunks;
+    const int per_xcd = (int)((units + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(8 * (long long)per_xcd)), dim3(kSweepAdjBlock), 0, st, c->P, in, out,
+                       c->lnw, nchunks, per_xcd);
+  };
+  if (c->p.order == 2) {
+    // y faces and the y sweep read the adjoint of the y-sweep output; the x
+    // faces and the x sweep that of the x-swept state
+    if (cavity) walls_adj(lo, 2 * ny, 2 * nx);
+    sweep(sweep_adj_kernel<1>, lo, tmp, nx);
+    if (cavity) walls_adj(tmp, 0, 2 * ny);
+    sweep(sweep_adj_kernel<0>, tmp, li, ny);
+  } else {
+    if (cavity) walls_adj(lo, 0, 2 * (nx + ny));
+    const int nc = (c->nv + kOrder1AdjBlock - 1) / kOrder1AdjBlock;
+    hipLaunchKernelGGL(order1_adj_kernel, dim3((unsigned)(c->ncells * nc)), dim3(kOrder1AdjBlock), 0, st, c->P, lo,
+                       li, c->lnw, nc);
+  }
+  if (cavity && grad) hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(256), 0, st, c->P, c->gpart, grad, 3);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream adjoint launch");
+}
+
+extern "C++" template <int B>
+static void launch_collide_adj_b(boltz_ctx* c, bool table, const float* hs, const double* lo, double* ls,
+                                 uint32_t s32, uint32_t flags, hipStream_t st) {
+  const int t = table ? 1 : 0;
+  const dim3 grid((unsigned)c->adj_grid[t]);
+  if (table)
+    hipLaunchKernelGGL((collide_adj_kernel<B, true>), grid, dim3(B), c->adj_lds[t], st, c->P, hs, lo, ls, s32, flags,
+                       c->tidx, c->tcoef);
+  else
+    hipLaunchKernelGGL((collide_adj_kernel<B, false>), grid, dim3(B), c->adj_lds[t], st, c->P, hs, lo, ls, s32,
+                       flags, c->tidx, c->tcoef);
+}
+
+static int launch_collide_adj(boltz_ctx* c, const float* hs, const double* lo, double* ls, int64_t step,
+                              uint32_t flags, hipStream_t st) {
+  const uint32_t s32 = (uint32_t)step;
+  const bool table = c->ngroups > 0;
+  launch_samples(c, s32, st);
+  if (c->adj_block == 256) launch_collide_adj_b<256>(c, table, hs, lo, ls, s32, flags, st);
+  else launch_collide_adj_b<512>(c, table, hs, lo, ls, s32, flags, st);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "collide adjoint launch");
+}
+
+extern "C" {
+
+int boltz_stream_adjoint(boltz_ctx* c, const float* h_in, const double* lam_out, double* lam_in, double* grad_walls,
+                         const boltz_walls* walls, void* stream) {
   if (!c) return BOLTZ_EINVAL;
-  return fail(c, BOLTZ_EUNSUPPORTED, "boltz_step_adjoint: not implemented in this build");
+  if (!h_in || !lam_out || !lam_in) return fail(c, BOLTZ_EINVAL, "boltz_stream_adjoint: null buffer");
+  const size_t bytes = (size_t)c->ncells * c->nv * sizeof(double);
+  if (overlap(lam_out, lam_in, bytes)) return fail(c, BOLTZ_EINVAL, "boltz_stream_adjoint: lam_out and lam_in overlap");
+  const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
+  if (cavity && !walls_ok(walls, c->p.nx))
+    return fail(c, BOLTZ_EINVAL, "boltz_stream_adjoint: cavity needs valid walls");
+  if (c->p.order == 2 && !c->adj_lam)
+    return fail(c, BOLTZ_EINVAL, "boltz_stream_adjoint: order 2 needs a context created with BOLTZ_WITH_ADJOINT");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const WallArgs W = make_walls(walls);
+  int rc = BOLTZ_OK;
+  if (cavity) rc = launch_walls(c, h_in, W, walls, st);
+  if (rc == BOLTZ_OK) rc = launch_stream_adj(c, W, lam_out, lam_in, c->adj_lam, grad_walls, st);
+  return rc;
+}
+
+int boltz_collide_adjoint(boltz_ctx* c, const float* h_s, const double* lam_out, double* lam_s, int64_t step,
+                          uint32_t flags, void* stream) {
+  if (!c) return BOLTZ_EINVAL;
+  if (!h_s || !lam_out || !lam_s) return fail(c, BOLTZ_EINVAL, "boltz_collide_adjoint: null buffer");
+  const size_t bytes = (size_t)c->ncells * c->nv * sizeof(double);
+  if (lam_out != lam_s && overlap(lam_out, lam_s, bytes))
+    return fail(c, BOLTZ_EINVAL, "boltz_collide_adjoint: lam_out and lam_s partially overlap");
+  if (flags & ~(uint32_t)BOLTZ_NO_CORRECTION) return fail(c, BOLTZ_EINVAL, "boltz_collide_adjoint: unknown flag");
+  if (!c->adj_supported)
+    return fail(c, BOLTZ_EUNSUPPORTED, "boltz_collide_adjoint: velocity grid too large for the adjoint's LDS layout");
+  return launch_collide_adj(c, h_s, lam_out, lam_s, step, flags, static_cast<hipStream_t>(stream));
+}
+
+int boltz_step_adjoint(boltz_ctx* c, const float* h_in, const double* lam_out, double* lam_in, double* grad_walls,
+                       const boltz_walls* walls, int64_t step, void* stream) {
+  if (!c) return BOLTZ_EINVAL;
+  if (!h_in || !lam_out || !lam_in) return fail(c, BOLTZ_EINVAL, "boltz_step_adjoint: null buffer");
+  const size_t bytes = (size_t)c->ncells * c->nv * sizeof(double);
+  if (lam_out != lam_in && overlap(lam_out, lam_in, bytes))
+    return fail(c, BOLTZ_EINVAL, "boltz_step_adjoint: lam_out and lam_in partially overlap");
+  if (!c->adj_hs || !c->adj_lam)
+    return fail(c, BOLTZ_EINVAL, "boltz_step_adjoint: context not created with BOLTZ_WITH_ADJOINT");
+  if (!c->adj_supported)
+    return fail(c, BOLTZ_EUNSUPPORTED, "boltz_step_adjoint: velocity grid too large for the adjoint's LDS layout");
+  const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
+  if (cavity && !walls_ok(walls, c->p.nx))
+    return fail(c, BOLTZ_EINVAL, "boltz_step_adjoint: cavity needs valid walls");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const WallArgs W = make_walls(walls);
+  // forward streaming again (also leaves the face densities of h_in in P.nw)
+  int rc = BOLTZ_OK;
+  if (cavity) rc = launch_walls(c, h_in, W, walls, st);
+  if (rc == BOLTZ_OK) rc = launch_stream(c, h_in, c->adj_hs, st);
+  if (rc != BOLTZ_OK) return rc;
+  if (c->p.order == 2) {
+    // collision adjoint into lam_in (in place when it is lam_out), then the
+    // sweeps through the scratch back into lam_in
+    rc = launch_collide_adj(c, c->adj_hs, lam_out, lam_in, step, 0u, st);
+    if (rc == BOLTZ_OK) rc = launch_stream_adj(c, W, lam_in, lam_in, c->adj_lam, grad_walls, st);
+  } else {
+    rc = launch_collide_adj(c, c->adj_hs, lam_out, c->adj_lam, step, 0u, st);
+    if (rc == BOLTZ_OK) rc = launch_stream_adj(c, W, c->adj_lam, lam_in, nullptr, grad_walls, st);
+  }
+  return rc;
+}
+
+int boltz_lid_shear_adjoint(boltz_ctx* c, const float* h, const boltz_walls* walls, double weight, double* lam,
+                            double* grad_walls, void* stream) {
+  if (!c) return BOLTZ_EINVAL;
+  if (!h || !lam) return fail(c, BOLTZ_EINVAL, "boltz_lid_shear_adjoint: null buffer");
+  if (c->p.bc != BOLTZ_BC_CAVITY || !walls_ok(walls, c->p.nx) || !std::isfinite(weight))
+    return fail(c, BOLTZ_EINVAL, "boltz_lid_shear_adjoint: needs a cavity, valid walls and a finite weight");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const WallArgs W = make_walls(walls);
+  const int rc = ensure_ratio(c, W, walls, st);
+  if (rc != BOLTZ_OK) return rc;
+  hipLaunchKernelGGL(lid_adj_kernel, dim3((unsigned)c->p.nx), dim3(256), 0, st, c->P, W, h, weight, lam, c->gpart);
+  if (grad_walls) hipLaunchKernelGGL(lid_grad_kernel, dim3(1), dim3(64), 0, st, c->P, c->gpart, grad_walls);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "lid shear adjoint launch");
 }
 
 int boltz_debug_pairs(boltz_ctx* c, int64_t cell, int64_t step, int64_t m0, int64_t count, int32_t* idx4,

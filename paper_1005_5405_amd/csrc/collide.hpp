@@ -328,6 +328,135 @@ __device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, 
   }
 }
 
+// S3 + S4 for one cell (Eqs. monteCarloInt, collision_step in Jacobi form):
+// every sample reads the post-stream tile hs and adds its gain and loss to
+// the accumulators.  TABLE: the pairs are the records of sample_kernel for
+// the cell's group, four per thread and pass so that their loads and
+// gathers are in flight together; else they are drawn here.
+template <int BLOCK, bool TABLE, bool FIXED>
+__device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, const float* hs, float* accf,
+                                          unsigned long long* acc64, uint32_t group, uint32_t step,
+                                          const uint2* __restrict__ tidx, const float4* __restrict__ tcoef) {
+  const int tid = threadIdx.x;
+  const float epsf = (float)P.eps;
+  const uint32_t nt = (uint32_t)P.n_pairs;
+  if (TABLE) {
+    constexpr int PU = 4;
+    const uint2* ri = tidx + (int64_t)group * nt;
+    const float4* rk = tcoef + (int64_t)group * nt;
+    uint32_t m = tid;
+    for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) {
+      uint2 id[PU];
+      float4 kk[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        id[u] = ri[m + u * BLOCK];
+        kk[u] = rk[m + u * BLOCK];
+      }
+      float ha[PU], hb[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        ha[u] = hs[id[u].x & 0xFFFFu];
+        hb[u] = hs[id[u].x >> 16];
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const float g = (ha[u] + hb[u]) + (epsf * ha[u]) * hb[u];
+        scatter<FIXED>(accf, acc64, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
+                       (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
+      }
+    }
+    for (; m < nt; m += BLOCK) {
+      const uint2 i0 = ri[m];
+      const float4 k0 = rk[m];
+      const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
+      const float ha0 = hs[a0], hb0 = hs[b0];
+      const float g0 = (ha0 + hb0) + (epsf * ha0) * hb0;
+      scatter<FIXED>(accf, acc64, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w, g0);
+    }
+  } else {
+    for (uint32_t m = tid; m < nt; m += BLOCK) {
+      const Pair p = sample_pair(P, T, group, step, m, nullptr);
+      if (p.as >= 0) {
+        const float ha = hs[p.a], hb = hs[p.b];
+        const float g = (ha + hb) + (epsf * ha) * hb;
+        scatter<FIXED>(accf, acc64, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+      }
+    }
+  }
+}
+
+// FP64 sums of the correction (Eqs. rinorm_a, correzione), one velocity row
+// (jx, jy) per thread:
+//   M = M0 + eps sum_j w_j h^c_j psi_j psi_j^T  (M0 = sum w psi psi^T),
+//   r = -eps sum_j w_j psi_j (h^c_j - h^s_j),  psi = (1, v, |v|^2),
+// from the z moments S_p = sum_z omega_z h^c v_z^p (p <= 4) and
+// R_p = sum_z omega_z (h^c - h^s) v_z^p (p <= 2) of the row.  acc[0..15)
+// are the sums of h^c psi_k psi_l (packed k <= l), acc[15..20) those of
+// (h^c - h^s) psi_k, per thread.
+template <int BLOCK, int NU>
+__device__ __forceinline__ void correction_sums(const TablesLDS& T, const float* hs, const float* hc_t, int n0,
+                                                int n1, int n2, double (&acc)[20]) {
+  const double* vx = T.v;
+  const double* vy = T.v + n0;
+  const double* vz = T.v + n0 + n1;
+  const double* omx = T.om;
+  const double* omy = T.om + n0;
+  const double* omz = T.om + n0 + n1;
+#pragma unroll
+  for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+  for (int row = threadIdx.x; row < n0 * n1; row += BLOCK) {
+    const int jx = row / n1, jy = row - (row / n1) * n1;
+    const float* hcr = hc_t + row * n2;
+    const float* hsr = hs + row * n2;
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
+#pragma unroll NU
+    for (int jz = 0; jz < n2; ++jz) {
+      const double hc = (double)hcr[jz], oz = omz[jz], z = vz[jz];
+      double u = oz * hc;
+      S0 += u;
+      u *= z;
+      S1 += u;
+      u *= z;
+      S2 += u;
+      u *= z;
+      S3 += u;
+      u *= z;
+      S4 += u;
+      double d = oz * (hc - (double)hsr[jz]);
+      R0 += d;
+      d *= z;
+      R1 += d;
+      d *= z;
+      R2 += d;
+    }
+    const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
+    const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
+    const double E0 = c2 * T0 + T2;  // sum w h^c |v|^2
+    acc[0] += T0;
+    acc[1] += a * T0;
+    acc[2] += b * T0;
+    acc[3] += T1;
+    acc[4] += E0;
+    acc[5] += (a * a) * T0;
+    acc[6] += (a * b) * T0;
+    acc[7] += a * T1;
+    acc[8] += a * E0;
+    acc[9] += (b * b) * T0;
+    acc[10] += b * T1;
+    acc[11] += b * E0;
+    acc[12] += T2;
+    acc[13] += c2 * T1 + T3;
+    acc[14] += (c2 * c2) * T0 + 2.0 * c2 * T2 + T4;
+    const double Q0 = W * R0, Q1 = W * R1, Q2 = W * R2;
+    acc[15] += Q0;
+    acc[16] += a * Q0;
+    acc[17] += b * Q0;
+    acc[18] += Q1;
+    acc[19] += c2 * Q0 + Q2;
+  }
+}
+
 // Persistent workgroups: workgroup b collides cells b, b + gridDim.x, ...;
 // the h^s tile of the next cell is loaded into registers while the node
 // phases of the current one run.  TABLE: the pairs come from the records of
@@ -360,8 +489,6 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   constexpr int NU = BLOCK <= 512 ? 4 : 1;
   const bool correct = !(flags & 1u);
   const double eps = P.eps;
-  const float epsf = (float)P.eps;
-  const uint32_t nt = (uint32_t)P.n_pairs;
   const int nv4 = nv >> 2;
   const bool vec = ((nv & 3) == 0) && nv4 <= kPrefetch * BLOCK;
   Prefetch pre;
@@ -383,52 +510,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
     __syncthreads();
     // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
     const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
-    if (TABLE) {
-      // four records per thread and pass: their loads and gathers are in
-      // flight together
-      constexpr int PU = 4;
-      const uint2* ri = tidx + (int64_t)group * nt;
-      const float4* rk = tcoef + (int64_t)group * nt;
-      uint32_t m = tid;
-      for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) {
-        uint2 id[PU];
-        float4 kk[PU];
-#pragma unroll
-        for (int u = 0; u < PU; ++u) {
-          id[u] = ri[m + u * BLOCK];
-          kk[u] = rk[m + u * BLOCK];
-        }
-        float ha[PU], hb[PU];
-#pragma unroll
-        for (int u = 0; u < PU; ++u) {
-          ha[u] = hs[id[u].x & 0xFFFFu];
-          hb[u] = hs[id[u].x >> 16];
-        }
-#pragma unroll
-        for (int u = 0; u < PU; ++u) {
-          const float g = (ha[u] + hb[u]) + (epsf * ha[u]) * hb[u];
-          scatter<FIXED>(accf, acc64, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
-                         (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
-        }
-      }
-      for (; m < nt; m += BLOCK) {
-        const uint2 i0 = ri[m];
-        const float4 k0 = rk[m];
-        const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
-        const float ha0 = hs[a0], hb0 = hs[b0];
-        const float g0 = (ha0 + hb0) + (epsf * ha0) * hb0;
-        scatter<FIXED>(accf, acc64, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w, g0);
-      }
-    } else {
-      for (uint32_t m = tid; m < nt; m += BLOCK) {
-        const Pair p = sample_pair(P, T, group, step, m, nullptr);
-        if (p.as >= 0) {
-          const float ha = hs[p.a], hb = hs[p.b];
-          const float g = (ha + hb) + (epsf * ha) * hb;
-          scatter<FIXED>(accf, acc64, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
-        }
-      }
-    }
+    gain_loss<BLOCK, TABLE, FIXED>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
     __syncthreads();
     // The next cell's tile is requested only now: vector-memory waits retire
     // in issue order, so loads issued before the pair loop would stall its
@@ -447,64 +529,9 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
     }
     if (correct) {
       __syncthreads();
-      // (2) FP64 sums, one velocity row (jx, jy) per thread:
-      //   M = M0 + eps sum_j w_j h^c_j psi_j psi_j^T  (M0 = sum w psi psi^T),
-      //   r = -eps sum_j w_j psi_j (h^c_j - h^s_j),  psi = (1, v, |v|^2),
-      // from the z moments S_p = sum_z omega_z h^c v_z^p (p <= 4) and
-      // R_p = sum_z omega_z (h^c - h^s) v_z^p (p <= 2) of the row.
+      // (2) FP64 sums of M and r, block-reduced
       double acc[20];
-#pragma unroll
-      for (int i = 0; i < 20; ++i) acc[i] = 0.0;
-      for (int row = tid; row < n0 * n1; row += BLOCK) {
-        const int jx = row / n1, jy = row - (row / n1) * n1;
-        const float* hcr = accf + row * n2;
-        const float* hsr = hs + row * n2;
-        double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
-#pragma unroll NU
-        for (int jz = 0; jz < n2; ++jz) {
-          const double hc = (double)hcr[jz], oz = omz[jz], z = vz[jz];
-          double u = oz * hc;
-          S0 += u;
-          u *= z;
-          S1 += u;
-          u *= z;
-          S2 += u;
-          u *= z;
-          S3 += u;
-          u *= z;
-          S4 += u;
-          double d = oz * (hc - (double)hsr[jz]);
-          R0 += d;
-          d *= z;
-          R1 += d;
-          d *= z;
-          R2 += d;
-        }
-        const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
-        const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
-        const double E0 = c2 * T0 + T2;  // sum w h^c |v|^2
-        acc[0] += T0;
-        acc[1] += a * T0;
-        acc[2] += b * T0;
-        acc[3] += T1;
-        acc[4] += E0;
-        acc[5] += (a * a) * T0;
-        acc[6] += (a * b) * T0;
-        acc[7] += a * T1;
-        acc[8] += a * E0;
-        acc[9] += (b * b) * T0;
-        acc[10] += b * T1;
-        acc[11] += b * E0;
-        acc[12] += T2;
-        acc[13] += c2 * T1 + T3;
-        acc[14] += (c2 * c2) * T0 + 2.0 * c2 * T2 + T4;
-        const double Q0 = W * R0, Q1 = W * R1, Q2 = W * R2;
-        acc[15] += Q0;
-        acc[16] += a * Q0;
-        acc[17] += b * Q0;
-        acc[18] += Q1;
-        acc[19] += c2 * Q0 + Q2;
-      }
+      correction_sums<BLOCK, NU>(T, hs, accf, n0, n1, n2, acc);
       block_sum20_lds(acc, red, tot);
       if (tid < 64) {
         // wavefront 0 solves M x = r and tabulates x . psi per axis:

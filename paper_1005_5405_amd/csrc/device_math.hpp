@@ -130,6 +130,19 @@ __device__ __forceinline__ void lds_add(float* p, float v) {
   }
 }
 
+// FP64 accumulation into LDS as a read plus a 64-bit compare-and-swap (the
+// adjoint sums, whose scale is not known in advance).
+__device__ __forceinline__ void lds_add_f64(double* p, double v) {
+  unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+  unsigned long long old = *u;
+  while (true) {
+    const unsigned long long nw = (unsigned long long)__double_as_longlong(__longlong_as_double((long long)old) + v);
+    const unsigned long long prev = atomicCAS(u, old, nw);
+    if (prev == old) break;
+    old = prev;
+  }
+}
+
 // One contribution k g to node j: 64-bit fixed point when |k g| < 2^18,
 // else the FP32 accumulator ovf[j].  fma(k, g, 1.5 * 2^20) rounds the exact
 // product once onto the 2^-32 grid; the high word of the bit difference

@@ -47,10 +47,13 @@ struct Params {
   const float* cour;      // [2][kMaxAxis] Courant number |v| dt / d{x,y}
   const float* cour2;     // [2][kMaxAxis] C (1 - C) / 2
   double* nw;             // [2 ny + 2 nx] face densities: left, right, bottom, top
-  double* ratio;          // [4][nv] Phi_w / Phi0 per wall and node
+  double* ratio;          // [4][nv] Phi_w / Phi0 per wall and node (bottom slot unused)
+  double* ratio_b;        // [nx][nv] Phi_w / Phi0 of every bottom face
+  const double* tau_b;    // [nx] T_w / T0 of every bottom face
   const double* m0;       // [15] sum_j w_j psi_k psi_l, psi = (1, v, |v|^2), packed k <= l
   double* dpart;          // [nx] lid shear partial sums
   double* wconst;         // [4][2] per wall: A_w, D_w of the face densities
+  double* wconst_b;       // [nx][2] A, D of every bottom face
   uint32_t* status;       // device status bits
 };
 
@@ -83,6 +86,17 @@ __device__ __forceinline__ float ghost_value(double nw, double R, double inv_eps
 
 __device__ __forceinline__ int64_t cell_off(const Params& P, int ix, int iy) {
   return ((int64_t)iy * P.nx + ix) * P.nv;
+}
+
+// Phi_w / Phi0 of all nodes for face `pos` of a wall (the bottom wall has one
+// table per face: it may carry a temperature profile).
+__device__ __forceinline__ const double* ratio_row(const Params& P, int wall, int pos) {
+  return wall == WALL_BOTTOM ? P.ratio_b + (int64_t)pos * P.nv : P.ratio + (int64_t)wall * P.nv;
+}
+
+// A and D of the face densities of face `pos` of a wall.
+__device__ __forceinline__ const double* wall_consts(const Params& P, int wall, int pos) {
+  return wall == WALL_BOTTOM ? P.wconst_b + 2 * pos : P.wconst + 2 * wall;
 }
 
 // ------------------------------------------------------------------- S1 --
@@ -145,7 +159,7 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
       const double w = (P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz];
       int mx = jx, my = jy;
       if (nax == 0) mx = P.n[0] - 1 - jx; else my = n1 - 1 - jy;
-      const double R = P.ratio[(int64_t)wall * nv + (mx * n1 + my) * n2 + jz];
+      const double R = ratio_row(P, wall, pos)[(mx * n1 + my) * n2 + jz];
       double ha, hb = 0.0;
       if (ysw) {
         ha = xswept_value(P, W, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
@@ -169,24 +183,28 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
   return (s[0] + P.eps * s[2]) / s[1];
 }
 
-// Per wall (one workgroup each): the table Phi_w / Phi0 of every node,
-// ratio[wall * nv + j] (FP64; only the lid moves, with velocity lid_u along
-// x), then A_w = sum_out |v_n| w_j and D_w = sum over the mirror images of
+// One workgroup per wall (left, right, top) and per bottom face: the table
+// Phi_w / Phi0 of every node (FP64; only the lid moves, with velocity lid_u
+// along x), then A = sum_out |v_n| w_j and D = sum over the mirror images of
 // the outgoing nodes of |v_n| w R, reduced in one pass with the same tree so
-// that a wall at rest (R = 1) gives D_w = A_w bitwise: wconst[2 wall + {0,1}].
-// Launched only when the wall state changes.
+// that a wall at rest (R = 1) gives D = A bitwise.  Launched only when the
+// wall state changes.
 constexpr int kWallConstBlock = 1024;
 
 __global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, WallArgs W) {
   __shared__ double red[2 * (kWallConstBlock / 64)];
-  const int wall = blockIdx.x;
+  const int b = blockIdx.x;
+  const int wall = b == 0 ? WALL_LEFT : (b == 1 ? WALL_RIGHT : (b == 2 ? WALL_TOP : WALL_BOTTOM));
+  const int pos = b < 3 ? 0 : b - 3;
   const int nv = P.nv, n1 = P.n[1], n2 = P.n[2];
   const double Uw = (wall == WALL_TOP) ? W.lid_u : 0.0;
-  double* R = P.ratio + (int64_t)wall * nv;
+  const double tau = wall == WALL_BOTTOM ? P.tau_b[pos] : W.tau[wall];
+  const double tfac = wall == WALL_BOTTOM ? pow(tau, -1.5) : W.tfac[wall];
+  double* R = const_cast<double*>(ratio_row(P, wall, pos));
   for (int j = threadIdx.x; j < nv; j += blockDim.x) {
     int jx, jy, jz;
     node_decode(j, n1, n2, jx, jy, jz);
-    R[j] = wall_ratio(P.vtab[jx], P.vtab[kMaxAxis + jy], P.vtab[2 * kMaxAxis + jz], Uw, W.tau[wall], W.tfac[wall]);
+    R[j] = wall_ratio(P.vtab[jx], P.vtab[kMaxAxis + jy], P.vtab[2 * kMaxAxis + jz], Uw, tau, tfac);
   }
   __syncthreads();
   const int nax = (wall <= WALL_RIGHT) ? 0 : 1;
@@ -205,8 +223,9 @@ __global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, Wa
   }
   block_sum<2>(s, red);
   if (threadIdx.x == 0) {
-    P.wconst[2 * wall] = s[0];
-    P.wconst[2 * wall + 1] = s[1];
+    double* k = const_cast<double*>(wall_consts(P, wall, pos));
+    k[0] = s[0];
+    k[1] = s[1];
   }
 }
 
@@ -316,7 +335,10 @@ __global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, 
   }
   double s[1] = {face_b<8>(P, W, h, wall, pos, P.order, nwl0, nwl1, nwr0, nwr1, (int)threadIdx.x, kWallBlock)};
   block_sum<1>(s, red);
-  if (threadIdx.x == 0) P.nw[f] = (P.wconst[2 * wall] + P.eps * s[0]) / P.wconst[2 * wall + 1];
+  if (threadIdx.x == 0) {
+    const double* k = wall_consts(P, wall, pos);
+    P.nw[f] = (k[0] + P.eps * s[0]) / k[1];
+  }
 }
 
 // ------------------------------------------------------------------- S2 --
@@ -399,7 +421,7 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
           nwv = P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix];
         }
         for (int e = 0; e < 4; ++e)
-          if (jq + e < nv) v4[e] = ghost_value(nwv, P.ratio[(int64_t)wall * nv + jq + e], P.inv_eps);
+          if (jq + e < nv) v4[e] = ghost_value(nwv, ratio_row(P, wall, inY ? iy : ix)[jq + e], P.inv_eps);
       }
       A4[cidx * Q + q] = make_float4(v4[0], v4[1], v4[2], v4[3]);
     }
@@ -426,8 +448,8 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
       if (jok && ix < nx) {
         if (!periodic && (iy < 0 || iy >= ny)) {
           const int wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
-          val = ghost_value(P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix],
-                            P.ratio[(int64_t)wall * nv + j], P.inv_eps);
+          val = ghost_value(P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix], ratio_row(P, wall, ix)[j],
+                            P.inv_eps);
         } else {
           const float* row = &A[(r * AX + c + 2) * kJ + jj];
           const float h0 = row[0];
@@ -540,7 +562,7 @@ __global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const 
           wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
           nwv = P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix];
         }
-        v[it] = ghost4(nwv, P.ratio + (int64_t)wall * nv + jq, P.inv_eps);
+        v[it] = ghost4(nwv, ratio_row(P, wall, inY ? iy : ix) + jq, P.inv_eps);
       }
     }
 #pragma unroll
@@ -574,7 +596,7 @@ __global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const 
       const int iy = iy0 - 2 + r;
       if (!periodic && (iy < 0 || iy >= ny)) {
         const int wall = iy < 0 ? WALL_BOTTOM : WALL_TOP;
-        hx[r] = ghost4(P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix], P.ratio + (int64_t)wall * nv + jq,
+        hx[r] = ghost4(P.nw[2 * ny + (wall == WALL_BOTTOM ? 0 : nx) + ix], ratio_row(P, wall, ix) + jq,
                        P.inv_eps);
       } else {
         const float4* row = &A4[(r * AX + xc) * Q + q];

@@ -1,0 +1,368 @@
+"""GPU parity of the reverse mode and of the per-face bottom temperature:
+the HIP library (through its C ABI) against the FP64 oracle, plus same-seed
+central finite differences of the GPU forward map.
+
+Bars.  Forward with a bottom-temperature profile: the forward bars (relative
+1e-5 per step).  Adjoints (FP64 on both sides): the GPU forms its face
+densities from the FP32 state (the order-2 y faces from the FP32 x sweep),
+stores h^s, h^c and the adjoint of the increment in FP32 and reads FP32
+table coefficients, so every term it sums carries a relative error of a few
+FP32 ulps against the oracle and the totals show no cancellation beyond the
+step's O(nu dt) collision share: relative 1e-5 of max|lam| per step, 1e-5 of
+max|grad| for the wall gradient, 1e-4 over a multi-step window.  Finite
+differences: the step is quadratic in h apart from the correction's 5x5
+solve, so a centred difference with t = 1e-2 carries only the FP32 rounding
+of the outputs (~1e-7 |J| / t) and O(t^2) terms: relative 2e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1005_5405_amd as pkg
+
+    pkg.load_library()
+    return pkg
+
+
+def _profile(nx):
+    return 1.0 + 0.05 * np.sin(2 * np.pi * (np.arange(nx) + 0.5) / nx)
+
+
+WALLS = dict(lid_u=0.12, tau_left=1.04, tau_right=0.97, tau_bottom=1.01, tau_top=1.02)
+
+
+def _walls(lib, oracle_mod, nx, profile=True):
+    tbx = _profile(nx) if profile else None
+    return lib.Walls(**WALLS, tau_bottom_x=tbx), oracle_mod.Walls(**WALLS, tau_bottom_x=tbx)
+
+
+def _pair(lib, oracle_mod, **kw):
+    flags = kw.pop("flags", 0)
+    return lib.Boltz(flags=flags | lib.WITH_ADJOINT, **kw), oracle_mod.Oracle(**kw)
+
+
+def _dev32(torch_mod, a):
+    return torch_mod.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _dev64(torch_mod, a):
+    return torch_mod.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(got, ref):
+    return np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def _state(o, seed, scale=0.3):
+    from paper_1005_5405_amd import inputs
+
+    return inputs.random_field(o.shape, seed=seed, scale=scale).astype(np.float32).astype(np.float64)
+
+
+def _adjoint_input(o, seed):
+    """lam = w (smooth polynomial in v + noise): the form the adjoint of a
+    moment functional takes (lam = w phi(v))."""
+    from paper_1005_5405_amd import inputs
+
+    V = o.node_velocities()
+    w = o.node_weights()
+    poly = np.stack([inputs.velocity_polynomial(V, seed=seed + c) for c in range(o.nx * o.ny)]).reshape(o.shape)
+    noise = inputs.random_field(o.shape, seed=seed + 7, scale=0.2)
+    return w * (1.0 + poly + noise)
+
+
+# ------------------------------------------------ forward with a profile --
+PROFILE_CASES = [
+    dict(order=2, nx=12, ny=9, nv=(6, 6, 8), vmax=3.0),         # vector stream kernel
+    dict(order=2, nx=11, ny=7, nv=(5, 7, 3), vmax=(3.0, 3.5, 2.5)),   # scalar kernel, ragged
+    dict(order=1, nx=9, ny=10, nv=(6, 4, 4), vmax=3.0),
+    dict(order=1, nx=7, ny=5, nv=(5, 3, 5), vmax=(3.0, 2.0, 2.5)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(PROFILE_CASES)))
+def test_bottom_profile_forward_parity(lib, oracle_mod, torch_mod, case):
+    kw = dict(PROFILE_CASES[case], delta=5.0, eps=0.1, n_pairs=500, bc=0)
+    _say("profile forward", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    wg, wo = _walls(lib, oracle_mod, o.nx)
+    h = _state(o, 20 + case)
+    ref = o.stream(h, wo)
+    out = g.empty()
+    g.stream(_dev32(torch_mod, h), out, wg)
+    torch_mod.cuda.synchronize()
+    assert _rel(_host(out), ref) <= 1e-5
+    ref = o.step(h, wo, 3)
+    g.step(_dev32(torch_mod, h), out, wg, 3)
+    torch_mod.cuda.synchronize()
+    assert _rel(_host(out), ref) <= 1e-5
+    # a uniform profile equals the scalar bottom temperature
+    wu = lib.Walls(**dict(WALLS, tau_bottom=1.03), tau_bottom_x=np.full(o.nx, 1.03))
+    ws = lib.Walls(**dict(WALLS, tau_bottom=1.03))
+    a, b = g.empty(), g.empty()
+    g.stream(_dev32(torch_mod, h), a, wu)
+    g.stream(_dev32(torch_mod, h), b, ws)
+    torch_mod.cuda.synchronize()
+    assert torch_mod.equal(a, b)
+    assert g.read_status() == 0
+
+
+# ------------------------------------------------------ stream adjoint --
+ADJ_STREAM_CASES = [
+    dict(order=2, bc=0, nx=12, ny=9, nv=(6, 6, 8), vmax=3.0),
+    dict(order=2, bc=0, nx=11, ny=7, nv=(5, 7, 3), vmax=(3.0, 3.5, 2.5)),
+    dict(order=2, bc=0, nx=2, ny=2, nv=(4, 4, 4), vmax=2.5),
+    dict(order=1, bc=0, nx=9, ny=10, nv=(6, 4, 4), vmax=3.0),
+    dict(order=1, bc=0, nx=7, ny=5, nv=(5, 3, 5), vmax=(3.0, 2.0, 2.5)),
+    dict(order=2, bc=1, nx=10, ny=9, nv=(6, 6, 6), vmax=3.0),
+    dict(order=1, bc=1, nx=5, ny=12, nv=(6, 4, 4), vmax=3.0),
+    dict(order=2, bc=1, nx=1, ny=2, nv=(4, 4, 4), vmax=2.5),
+]
+
+
+@pytest.mark.parametrize("case", range(len(ADJ_STREAM_CASES)))
+def test_stream_adjoint_parity(lib, oracle_mod, torch_mod, case):
+    kw = dict(ADJ_STREAM_CASES[case], delta=5.0, eps=0.1, n_pairs=100)
+    _say("stream adjoint", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    cavity = kw["bc"] == 0
+    wg, wo = _walls(lib, oracle_mod, o.nx) if cavity else (None, None)
+    h = _state(o, 30 + case)
+    lo = np.random.default_rng(case).standard_normal(o.shape)
+    ref, gref = o.stream_adjoint(h, lo, wo)
+    li = g.empty_adjoint()
+    grad = torch_mod.zeros(g.grad_size(), dtype=torch_mod.float64, device="cuda")
+    g.stream_adjoint(_dev32(torch_mod, h), _dev64(torch_mod, lo), li, grad, wg)
+    torch_mod.cuda.synchronize()
+    rel = _rel(_host(li), ref)
+    assert rel <= 1e-5, rel
+    gg = grad.cpu().numpy()
+    if cavity:
+        assert np.abs(gg - gref).max() <= 1e-5 * np.abs(gref).max(), (gg, gref)
+    else:
+        assert np.all(gg == 0.0)
+    # the grad buffer accumulates
+    g.stream_adjoint(_dev32(torch_mod, h), _dev64(torch_mod, lo), li, grad, wg)
+    torch_mod.cuda.synchronize()
+    assert np.allclose(grad.cpu().numpy(), 2 * gg, rtol=1e-12, atol=0)
+
+
+# ----------------------------------------------------- collide adjoint --
+ADJ_COLLIDE_CASES = [
+    dict(nx=3, ny=2, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=2000),
+    dict(nx=2, ny=2, nv=(20, 20, 20), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, mix16=4),
+    dict(nx=3, ny=2, nv=(5, 7, 3), vmax=(3.0, 3.5, 2.0), delta=2.0, eps=0.3, n_pairs=3000),
+    dict(nx=4, ny=3, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=2000, sample_group=0),
+    dict(nx=4, ny=2, nv=(20, 20, 20), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, sample_group=0, mix16=4),
+    dict(nx=5, ny=2, nv=(8, 8, 8), vmax=3.5, delta=10.0, eps=0.1, n_pairs=3000, sample_group=3),
+    dict(nx=2, ny=2, nv=(8, 8, 8), vmax=3.5, delta=10.0, eps=0.1, n_pairs=0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(ADJ_COLLIDE_CASES)))
+@pytest.mark.parametrize("correction", [True, False])
+def test_collide_adjoint_parity(lib, oracle_mod, torch_mod, case, correction):
+    kw = dict(ADJ_COLLIDE_CASES[case], bc=1)
+    _say("collide adjoint", kw, "correction", correction)
+    g, o = _pair(lib, oracle_mod, **kw)
+    h = _state(o, 40 + case)
+    lo = _adjoint_input(o, 50 + case)
+    ref = o.collide_adjoint(h, lo, 11, correction=correction)
+    ls = g.empty_adjoint()
+    lo_d = _dev64(torch_mod, lo)
+    g.collide_adjoint(_dev32(torch_mod, h), lo_d, ls, 11, correction=correction)
+    torch_mod.cuda.synchronize()
+    got = _host(ls)
+    rel = _rel(got, ref)
+    assert rel <= 1e-5, rel
+    # per cell as well (cells differ in scale)
+    for c in range(o.nx * o.ny):
+        r = got.reshape(-1, o.nv)[c]
+        e = ref.reshape(-1, o.nv)[c]
+        assert np.abs(r - e).max() <= 1e-5 * np.abs(e).max(), c
+    if kw["n_pairs"] == 0:
+        np.testing.assert_allclose(got, lo, rtol=1e-12, atol=0)
+    # in place gives the same result
+    g.collide_adjoint(_dev32(torch_mod, h), lo_d, lo_d, 11, correction=correction)
+    torch_mod.cuda.synchronize()
+    assert np.abs(_host(lo_d) - got).max() <= 1e-12 * np.abs(got).max()
+    assert g.read_status() == 0
+
+
+# -------------------------------------------------------- step adjoint --
+ADJ_STEP_CASES = [
+    dict(order=2, bc=0, nx=6, ny=5, nv=(8, 8, 8), vmax=3.5, n_pairs=1500, sample_group=0),
+    dict(order=2, bc=0, nx=5, ny=4, nv=(8, 8, 8), vmax=3.5, n_pairs=1500, sample_group=1, mix16=4),
+    dict(order=1, bc=0, nx=5, ny=6, nv=(6, 6, 6), vmax=3.0, n_pairs=800, sample_group=0),
+    dict(order=2, bc=1, nx=4, ny=5, nv=(6, 6, 6), vmax=3.0, n_pairs=800, sample_group=1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(ADJ_STEP_CASES)))
+def test_step_adjoint_parity(lib, oracle_mod, torch_mod, case):
+    kw = dict(ADJ_STEP_CASES[case], delta=10.0, eps=0.1)
+    _say("step adjoint", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    cavity = kw["bc"] == 0
+    wg, wo = _walls(lib, oracle_mod, o.nx) if cavity else (None, None)
+    h = _state(o, 60 + case)
+    lo = _adjoint_input(o, 70 + case)
+    ref, gref = o.step_adjoint(h, lo, wo, 5)
+    li = g.empty_adjoint()
+    grad = torch_mod.zeros(g.grad_size(), dtype=torch_mod.float64, device="cuda")
+    g.step_adjoint(_dev32(torch_mod, h), _dev64(torch_mod, lo), li, grad, wg, 5)
+    torch_mod.cuda.synchronize()
+    rel = _rel(_host(li), ref)
+    assert rel <= 1e-5, rel
+    gg = grad.cpu().numpy()
+    if cavity:
+        assert np.abs(gg - gref).max() <= 1e-5 * np.abs(gref).max(), (gg, gref)
+    # in place (lam_in = lam_out) gives the same result
+    lio = _dev64(torch_mod, lo)
+    g.step_adjoint(_dev32(torch_mod, h), lio, lio, None, wg, 5)
+    torch_mod.cuda.synchronize()
+    assert np.abs(_host(lio) - _host(li)).max() <= 1e-12 * np.abs(_host(li)).max()
+    assert g.read_status() == 0
+
+
+def test_step_adjoint_matches_gpu_finite_differences(lib, oracle_mod, torch_mod):
+    """<lam_out, step(h + t d)> - <lam_out, step(h - t d)> over 2t from the GPU
+    forward map (same seed) against <lam_in, d>; and the wall parameters."""
+    kw = dict(order=2, bc=0, nx=8, ny=8, nv=(8, 8, 8), vmax=3.5, delta=10.0, eps=0.1, n_pairs=2000,
+              sample_group=0)
+    _say("step adjoint FD", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    wg, _ = _walls(lib, oracle_mod, o.nx)
+    h = _state(o, 80)
+    lo = _adjoint_input(o, 81)
+    d = np.random.default_rng(5).standard_normal(o.shape)
+    lo_d = _dev64(torch_mod, lo)
+    out = g.empty()
+
+    def J(x, w=wg):
+        g.step(_dev32(torch_mod, x), out, w, 2)
+        torch_mod.cuda.synchronize()
+        return float(np.vdot(lo, _host(out)))
+
+    li = g.empty_adjoint()
+    grad = torch_mod.zeros(g.grad_size(), dtype=torch_mod.float64, device="cuda")
+    g.step_adjoint(_dev32(torch_mod, h), lo_d, li, grad, wg, 2)
+    torch_mod.cuda.synchronize()
+    t = 1e-2
+    fd = (J(h + t * d) - J(h - t * d)) / (2 * t)
+    an = float(np.vdot(_host(li), d))
+    assert abs(fd - an) <= 2e-3 * abs(an), (fd, an)
+    gg = grad.cpu().numpy()
+    for k in [0, 1, 3, 4 + o.nx // 2]:
+        import copy
+
+        def shifted(sign):
+            w = copy.deepcopy(wg)
+            tt = 2e-3
+            if k == 0:
+                w.lid_u += sign * tt
+            elif k == 1:
+                w.tau_left += sign * tt
+            elif k == 3:
+                w.tau_top += sign * tt
+            else:
+                tb = np.array(w.tau_bottom_x, dtype=float)
+                tb[k - 4] += sign * tt
+                w.tau_bottom_x = tb
+            return J(h, w)
+
+        fdk = (shifted(+1) - shifted(-1)) / 4e-3
+        assert abs(fdk - gg[k]) <= 5e-3 * max(abs(gg[k]), 1e-3 * np.abs(gg).max()), (k, fdk, gg[k])
+
+
+# ---------------------------------------------------------- lid shear --
+def test_lid_shear_adjoint_parity(lib, oracle_mod, torch_mod):
+    kw = dict(order=2, bc=0, nx=9, ny=7, nv=(8, 8, 8), vmax=3.5, delta=10.0, eps=0.1, n_pairs=100)
+    _say("lid shear adjoint", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    wg, wo = _walls(lib, oracle_mod, o.nx)
+    h = _state(o, 90)
+    lam0 = np.random.default_rng(2).standard_normal(o.shape)
+    ref, gref = o.lid_shear_adjoint(h, wo, weight=2.5)
+    lam = _dev64(torch_mod, lam0)
+    grad = torch_mod.zeros(g.grad_size(), dtype=torch_mod.float64, device="cuda")
+    g.lid_shear_adjoint(_dev32(torch_mod, h), wg, 2.5, lam, grad)
+    torch_mod.cuda.synchronize()
+    got = _host(lam) - lam0
+    assert np.all(got[:-1] == 0.0)
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+    gg = grad.cpu().numpy()
+    assert np.abs(gg - gref).max() <= 1e-6 * np.abs(gref).max(), (gg, gref)
+    assert gg[1] == gg[2] == 0.0 and np.all(gg[4:] == 0.0)
+
+
+# ---------------------------------------------------- windowed gradient --
+def test_window_gradient_matches_oracle_chain(lib, oracle_mod, torch_mod):
+    """J = (1/N) sum D(h^n) from rest through the autograd function
+    (checkpoints every 3 steps, so segments are recomputed) against the same
+    chain of oracle adjoints, and against GPU finite differences."""
+    from paper_1005_5405_amd.window import lid_shear_window
+
+    kw = dict(order=2, bc=0, nx=8, ny=8, nv=(8, 8, 8), vmax=3.5, delta=10.0, eps=0.1, n_pairs=1500,
+              sample_group=0)
+    _say("window gradient", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    N = 7
+    theta0 = np.concatenate([[0.12, 1.04, 0.97, 1.02], _profile(o.nx)])
+    theta = torch_mod.tensor(theta0, dtype=torch_mod.float64, requires_grad=True)
+    h0 = torch_mod.zeros(o.shape, dtype=torch_mod.float32, device="cuda", requires_grad=True)
+    J = lid_shear_window(g, h0, theta, N, step0=0, every=3)
+    J.backward()
+    gt = theta.grad.numpy()
+    gh = _host(h0.grad)
+    # oracle chain
+    wo = oracle_mod.Walls(lid_u=theta0[0], tau_left=theta0[1], tau_right=theta0[2], tau_bottom=1.0,
+                          tau_top=theta0[3], tau_bottom_x=theta0[4:])
+    states = [np.zeros(o.shape)]
+    for n in range(N):
+        states.append(o.step(states[-1], wo, n))
+    Jref = np.mean([o.moments(states[n], wo, lid_shear=True)[1] for n in range(1, N + 1)])
+    assert abs(J.item() - Jref) <= 1e-4 * abs(Jref)
+    lam = np.zeros(o.shape)
+    grad = np.zeros(o.grad_size())
+    for n in range(N, 0, -1):
+        lD, gD = o.lid_shear_adjoint(states[n], wo, weight=1.0 / N)
+        lam = lam + lD
+        grad += gD
+        lam, gs = o.step_adjoint(states[n - 1], lam, wo, n - 1)
+        grad += gs
+    assert np.abs(gt - grad).max() <= 1e-4 * np.abs(grad).max(), (gt, grad)
+    assert np.abs(gh - lam).max() <= 1e-4 * np.abs(lam).max()
+    # GPU finite differences of J in two parameters
+    for k in [0, 4 + 3]:
+        def Jk(sign):
+            th = theta0.copy()
+            th[k] += sign * 1e-3
+            with torch_mod.no_grad():
+                return lid_shear_window(g, h0.detach(), torch_mod.tensor(th), N, step0=0, every=3).item()
+
+        fd = (Jk(+1) - Jk(-1)) / 2e-3
+        assert abs(fd - gt[k]) <= 5e-3 * max(abs(gt[k]), 1e-2 * np.abs(gt).max()), (k, fd, gt[k])

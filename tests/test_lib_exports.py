@@ -27,7 +27,8 @@ def _lib():
 def test_header_declares_the_hot_path():
     names = _declared()
     for fn in ("boltz_stream", "boltz_collide", "boltz_moments", "boltz_step", "boltz_step_adjoint",
-               "boltz_create", "boltz_destroy"):
+               "boltz_stream_adjoint", "boltz_collide_adjoint", "boltz_lid_shear_adjoint", "boltz_create",
+               "boltz_destroy"):
         assert fn in names
 
 
@@ -45,7 +46,7 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
     assert "null" in L.boltz_last_error(None).decode()
     bad = [dict(nx=1), dict(nv=(0, 4, 4)), dict(nv=(256, 4, 4)), dict(eps=0.0), dict(order=3),
            dict(n_pairs=2**31), dict(dt=1.0), dict(vmax=(0.0, 1.0, 1.0)), dict(sample_group=-1),
-           dict(mix16=17)]
+           dict(mix16=17), dict(flags=4)]
     base = dict(nx=8, ny=8, nv=(8, 8, 8), vmax=(3.0, 3.0, 3.0), delta=1.0, eps=0.1, cfl=0.5, dt=0.0, order=2,
                 bc=0, n_pairs=100, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=0)
     for over in bad:
@@ -68,3 +69,6 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
     assert L.boltz_moments(None, None, None, None, None, None) == binding.EINVAL
     assert L.boltz_step(None, None, None, None, 0, None) == binding.EINVAL
     assert L.boltz_step_adjoint(None, None, None, None, None, None, 0, None) == binding.EINVAL
+    assert L.boltz_stream_adjoint(None, None, None, None, None, None, None) == binding.EINVAL
+    assert L.boltz_collide_adjoint(None, None, None, None, 0, 0, None) == binding.EINVAL
+    assert L.boltz_lid_shear_adjoint(None, None, None, 1.0, None, None, None) == binding.EINVAL
