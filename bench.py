@@ -50,7 +50,7 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 TRAFFIC = {"sha256": "7af7bb4025722018fef92cb8590f34cda8dadbeb134ddfd2854ac5f6c1a6319e",
            "fetch_kib": 66350.4 + 98.5, "write_kib": 128000.0 + 468.8,
            "fetch_scale": 128000.0 / 64018.1, "write_scale": 1.0}
-KERNEL_SOURCES = ("boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
+KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
 
 
 def kernel_sources_sha256() -> str:
@@ -143,6 +143,88 @@ def run(pkg, torch, preset, steps: int, warmup: int):
                 ms_per_step=wall_s / steps * 1e3)
 
 
+def run_adjoint(pkg, torch, preset, steps: int, warmup: int, window: int, every: int):
+    """Reverse mode on the same workload with the bottom-wall profile
+    T_w(x_i)/T0 = 1 + 0.05 sin(2 pi x_i): boltz_step_adjoint per step (forward
+    streaming recomputed, collision adjoint, stream adjoint), its kernel groups
+    timed through the separate calls it is made of, and one gradient of the
+    time-averaged lid shear over `window` steps from rest with checkpoints
+    every `every` steps (forward, segment recomputation, reverse sweep)."""
+    import numpy as np
+
+    from paper_1005_5405_amd.window import lid_shear_window
+
+    kw = preset.problem()
+    g = pkg.Boltz(**dict(kw, flags=pkg.WITH_ADJOINT))
+    stream = torch.cuda.current_stream()
+    x = (np.arange(g.nx) + 0.5) / g.nx
+    prof = 1.0 + 0.05 * np.sin(2 * np.pi * x)
+    walls = pkg.Walls(lid_u=preset.lid(0.0), tau_bottom_x=prof)
+    a, b = g.empty(0.0), g.empty()
+    for n in range(warmup):
+        g.step(a, b, walls, n)
+        a, b = b, a
+    lam = g.empty_adjoint(0.0)
+    lam2 = g.empty_adjoint(0.0)
+    grad = torch.zeros(g.grad_size(), dtype=torch.float64, device="cuda")
+    mom = torch.empty(g.ncells * 11, dtype=torch.float64, device="cuda")
+    g.lid_shear_adjoint(a, walls, 1.0, lam, grad)
+    # whole adjoint steps
+    for n in range(2):
+        g.step_adjoint(a, lam, lam, grad, walls, warmup + n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for n in range(steps):
+        g.step_adjoint(a, lam, lam, grad, walls, warmup + n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_step = e0.elapsed_time(e1) * 1e-3 / steps
+    # kernel groups of one adjoint step, through the calls it is made of
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record(stream)
+        g.stream(a, b, walls)
+        ev[k][1].record(stream)
+        g.collide_adjoint(b, lam, lam, warmup + k)
+        ev[k][2].record(stream)
+        g.stream_adjoint(a, lam, lam2, grad, walls)
+        ev[k][3].record(stream)
+        lam, lam2 = lam2, lam
+    torch.cuda.synchronize()
+    t_fw = sum(e[0].elapsed_time(e[1]) for e in ev) / steps * 1e-3
+    t_ca = sum(e[1].elapsed_time(e[2]) for e in ev) / steps * 1e-3
+    t_sa = sum(e[2].elapsed_time(e[3]) for e in ev) / steps * 1e-3
+    status = g.read_status()
+    finite = bool(torch.isfinite(lam).all().item())
+    del a, b, lam, lam2, mom
+    # windowed gradient
+    theta = torch.tensor(np.concatenate([[preset.lid(0.0), 1.0, 1.0, 1.0], prof]), dtype=torch.float64,
+                         requires_grad=True)
+    h0 = torch.zeros(g.shape, dtype=torch.float32, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = lid_shear_window(g, h0, theta, window, step0=0, every=every)
+    J.backward()
+    torch.cuda.synchronize()
+    t_win = time.perf_counter() - t0
+    nodes = g.ncells * g.nv
+    return {"workload": preset.name + " with bottom profile 1 + 0.05 sin(2 pi x)", "steps": steps,
+            "ms_per_adjoint_step": t_step * 1e3, "value": nodes / t_step, "unit": "node-updates/s",
+            "status": status, "finite": finite,
+            "kernels": {
+                "forward_stream_ms": t_fw * 1e3,
+                "collide_adjoint": {"kernel": "collide_adj_kernel + sample_kernel", "avg_ms": t_ca * 1e3,
+                                    "bound": "lds", "hbm_bytes_per_node": 20,
+                                    "hbm_frac": 20 * nodes / t_ca / 1e9 / HBM_PEAK_GBS},
+                "stream_adjoint": {"kernel": "wall_kernel x2 + wall_adj_kernel x2 + sweep_adj_kernel x2 + "
+                                             "grad_reduce_kernel", "avg_ms": t_sa * 1e3, "bound": "hbm",
+                                   "hbm_bytes_per_node": 32,
+                                   "hbm_frac": 32 * nodes / t_sa / 1e9 / HBM_PEAK_GBS}},
+            "window": {"steps": window, "checkpoint_every": every, "seconds": t_win, "J": J.item(),
+                       "dJ_dlid_u": float(theta.grad[0]), "dJ_dtau_top": float(theta.grad[3])}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +235,9 @@ def main():
     ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--variant", choices=["auto", "skip"], default="auto",
                     help="also time the per-cell sample streams (G = 1)")
+    ap.add_argument("--adjoint", choices=["auto", "skip"], default="auto",
+                    help="also time the reverse mode (step adjoint, windowed lid-shear gradient)")
+    ap.add_argument("--window", type=int, default=200, help="steps of the windowed gradient")
     ap.add_argument("--cpu-baseline", choices=["auto", "skip"], default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate", action="store_true",
@@ -223,6 +308,10 @@ def main():
             "value": v["value"], "ms_per_step": v["ms_per_step"], "pairs_per_s": v["pairs_per_s"],
             "collide_ms": v["t_collide"] * 1e3, "stream_ms": v["t_stream"] * 1e3,
             "steps": max(10, K // 4)}}
+    if args.adjoint == "auto":
+        print("[bench] variant: reverse mode (%d-step window)" % args.window, flush=True)
+        line.setdefault("variants", {})["adjoint"] = run_adjoint(
+            pkg, torch, preset, max(10, K // 4), max(3, args.warmup // 4), args.window, 20)
     if args.cpu_baseline == "auto":
         print("[bench] CPU oracle baseline ...", flush=True)
         line["cpu_baseline"] = cpu_baseline(preset, args.cpu_seconds)

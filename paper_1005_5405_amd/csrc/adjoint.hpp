@@ -19,13 +19,25 @@ namespace boltz {
 
 // -------------------------------------------------------- collision --
 // Adjoint of the gain/loss pass: lI is the adjoint of the increment of h
-// (FP32 tile), ls accumulates the adjoint of h^s (FP64 in LDS).  A sample
-// adds dJ/dg (1 + eps h_b) to ls_a and dJ/dg (1 + eps h_a) to ls_b, with
-// dJ/dg = k_a* lI_a* + k_b* lI_b* - k_a lI_a - k_b lI_b and the sample's
-// own coefficients k (FP32 table records or the FP64 values of the draw).
-template <int BLOCK, bool TABLE>
+// (FP32 tile).  A sample adds dJ/dg (1 + eps h_b) to the adjoint of h_a and
+// dJ/dg (1 + eps h_a) to that of h_b, with
+// dJ/dg = k_a* lI_a* + k_b* lI_b* - k_a lI_a - k_b lI_b and the sample's own
+// coefficients k (FP32 table records or the FP64 values of the draw).
+// FIXED: the terms, divided by the cell's power-of-two scale S (inv_s =
+// 1/S), go to the 64-bit fixed-point accumulators acc (large ones to the
+// FP32 array ovf) as in the forward pass; else they are added in FP64 to ls
+// by compare-and-swap.
+template <bool FIXED>
+__device__ __forceinline__ void adj_add(double* ls, unsigned long long* acc, float* ovf, int j, double lg,
+                                        double inv_s, double f) {
+  if (FIXED) lds_add_hybrid(acc, ovf, j, lg * inv_s, f);
+  else lds_add_f64(&ls[j], lg * f);
+}
+
+template <int BLOCK, bool TABLE, bool FIXED>
 __device__ __forceinline__ void gain_loss_adj(const Params& P, const TablesLDS& T, const float* hs,
-                                              const float* lI, double* ls, uint32_t group, uint32_t step,
+                                              const float* lI, double* ls, unsigned long long* acc, float* ovf,
+                                              double inv_s, uint32_t group, uint32_t step,
                                               const uint2* __restrict__ tidx,
                                               const float4* __restrict__ tcoef) {
   const int tid = threadIdx.x;
@@ -53,8 +65,8 @@ __device__ __forceinline__ void gain_loss_adj(const Params& P, const TablesLDS& 
                           fma((double)kk[u].z, (double)lI[a], (double)kk[u].w * (double)lI[b]);
         if (lg != 0.0) {
           const double ha = (double)hs[a], hb = (double)hs[b];
-          lds_add_f64(&ls[a], lg * fma(eps, hb, 1.0));
-          lds_add_f64(&ls[b], lg * fma(eps, ha, 1.0));
+          adj_add<FIXED>(ls, acc, ovf, a, lg, inv_s, fma(eps, hb, 1.0));
+          adj_add<FIXED>(ls, acc, ovf, b, lg, inv_s, fma(eps, ha, 1.0));
         }
       }
     }
@@ -65,18 +77,25 @@ __device__ __forceinline__ void gain_loss_adj(const Params& P, const TablesLDS& 
         const double lg = fma(p.kas, (double)lI[p.as], p.kbs * (double)lI[p.bs]) -
                           fma(p.ka, (double)lI[p.a], p.kb * (double)lI[p.b]);
         const double ha = (double)hs[p.a], hb = (double)hs[p.b];
-        lds_add_f64(&ls[p.a], lg * fma(eps, hb, 1.0));
-        lds_add_f64(&ls[p.b], lg * fma(eps, ha, 1.0));
+        adj_add<FIXED>(ls, acc, ovf, p.a, lg, inv_s, fma(eps, hb, 1.0));
+        adj_add<FIXED>(ls, acc, ovf, p.b, lg, inv_s, fma(eps, ha, 1.0));
       }
     }
   }
 }
 
 // Dynamic LDS of the collide adjoint: the collide kernel's fixed-point layout
-// (h^s tile, FP32 array, 64-bit accumulators, tables) plus the per-axis
+// (h^s tile, FP32 array, 64-bit accumulators), with FIXED a second FP32
+// array (large terms of the adjoint sums), then the tables and the per-axis
 // table of y . psi.
-__host__ __device__ inline size_t collide_adj_lds(int nv, int ns, bool sampler) {
-  return CollideLDS::bytes(nv, ns, true, sampler) + 8 * (size_t)ns;
+__host__ __device__ inline size_t collide_adj_lds(int nv, int ns, bool sampler, bool fixed) {
+  return CollideLDS::tile(nv) + CollideLDS::acc(nv, true) + (fixed ? CollideLDS::tile(nv) : 0) +
+         TablesLDS::bytes(ns, sampler) + 8 * (size_t)ns;
+}
+
+// static LDS of the collide adjoint (reduction scratch)
+__host__ __device__ inline size_t collide_adj_static_lds(int block) {
+  return (20 * (size_t)(block / 64) + 20) * sizeof(double);
 }
 
 // Reverse mode of collide_kernel: lo = adjoint of h^{n+1}, ls = adjoint of
@@ -88,8 +107,10 @@ __host__ __device__ inline size_t collide_adj_lds(int nv, int ns, bool sampler) 
 // and ls = lhc plus the sample terms of gain_loss_adj.  Without the
 // correction, or when M is not positive definite (status bit 1, as in the
 // forward pass), x = y = 0.  LDS reuse: h^c is overwritten by lI (FP32), the
-// fixed-point accumulators by ls (FP64).
-template <int BLOCK, bool TABLE>
+// forward's fixed-point accumulators by the adjoint sums: FIXED, 64-bit fixed
+// point in units of S 2^-32 with S the power of two above the cell's
+// max |lhc| (terms of 2^18 S or more in a second FP32 array); else FP64.
+template <int BLOCK, bool TABLE, bool FIXED>
 __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const float* __restrict__ hs_g,
                                                             const double* lo_g, double* ls_g, uint32_t step,
                                                             uint32_t flags, const uint2* __restrict__ tidx,
@@ -104,7 +125,9 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
   float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
   unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(dsm + 2 * CollideLDS::tile(nv));
   double* lsh = reinterpret_cast<double*>(acc64);
-  unsigned char* tb = dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, true);
+  unsigned char* after = dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, true);
+  float* ovf = FIXED ? reinterpret_cast<float*>(after) : nullptr;
+  unsigned char* tb = after + (FIXED ? CollideLDS::tile(nv) : 0);
   TablesLDS T;
   load_tables(P, tb, !TABLE, T);
   double* yt = reinterpret_cast<double*>(tb + TablesLDS::bytes(ns, !TABLE));
@@ -116,6 +139,19 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
   const double* omz = T.om + n0 + n1;
   const bool correct = !(flags & 1u);
   const double eps = P.eps;
+  // adjoint of h^c at node j = (jx, jy, jz)
+  auto lam_hc = [&](double l, int jx, int jy, int jz, double& lI) -> double {
+    if (!correct) {
+      lI = l;
+      return l;
+    }
+    const double xpsi = (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz];
+    const double ypsi = (yt[jx] + yt[n0 + jy]) + yt[n0 + n1 + jz];
+    const double ewy = eps * ((omx[jx] * omy[jy]) * omz[jz]) * ypsi;
+    const double lhc = fma(l, xpsi, l) - ewy * xpsi;
+    lI = lhc - ewy;
+    return lhc;
+  };
   for (int64_t cell = blockIdx.x; cell < ncells; cell += gridDim.x) {
     const float* src = hs_g + cell * nv;
     const double* lo = lo_g + cell * nv;
@@ -177,32 +213,56 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
       __syncthreads();
     }
     // ---- adjoints of h^c and of the increment (each thread its own nodes)
+    double scale = 1.0, inv_scale = 1.0;
     {
+      double mx = 0.0;
       NodeWalk walk(tid, BLOCK, n1, n2);
       for (int j = tid; j < nv; j += BLOCK, walk.next()) {
-        const double l = lo[j];
-        double lhc = l, lI = l;
-        if (correct) {
-          const int jx = walk.jx, jy = walk.jy, jz = walk.jz;
-          const double xpsi = (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz];
-          const double ypsi = (yt[jx] + yt[n0 + jy]) + yt[n0 + n1 + jz];
-          const double ewy = eps * ((omx[jx] * omy[jy]) * omz[jz]) * ypsi;
-          lhc = fma(l, xpsi, l) - ewy * xpsi;
-          lI = lhc - ewy;
-        }
+        double lI;
+        const double lhc = lam_hc(lo[j], walk.jx, walk.jy, walk.jz, lI);
         accf[j] = (float)lI;
-        lsh[j] = lhc;
+        if (FIXED) {
+          acc64[j] = 0ull;
+          ovf[j] = 0.0f;
+          mx = fmax(mx, fabs(lhc));
+        } else {
+          lsh[j] = lhc;
+        }
+      }
+      if (FIXED) {
+        // S = 2^e > max |lhc| of the cell (1 for an all-zero or non-finite cell)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if ((tid & 63) == 0) red[tid >> 6] = mx;
       }
     }
     __syncthreads();
-    gain_loss_adj<BLOCK, TABLE>(P, T, hs, accf, lsh, group, step, tidx, tcoef);
+    if (FIXED) {
+      double mx = 0.0;
+      for (int w = 0; w < BLOCK / 64; ++w) mx = fmax(mx, red[w]);
+      if (mx > 0.0 && isfinite(mx)) {
+        const int e = ilogb(mx) + 1;
+        scale = ldexp(1.0, e);
+        inv_scale = ldexp(1.0, -e);
+      }
+    }
+    gain_loss_adj<BLOCK, TABLE, FIXED>(P, T, hs, accf, lsh, acc64, ovf, inv_scale, group, step, tidx, tcoef);
     __syncthreads();
     bool finite = true;
     double* dst = ls_g + cell * nv;
-    for (int j = tid; j < nv; j += BLOCK) {
-      const double v = lsh[j];
-      finite = finite && isfinite(v);
-      dst[j] = v;
+    {
+      NodeWalk walk(tid, BLOCK, n1, n2);
+      for (int j = tid; j < nv; j += BLOCK, walk.next()) {
+        double v;
+        if (FIXED) {
+          double lI;
+          v = lam_hc(lo[j], walk.jx, walk.jy, walk.jz, lI) + scale * (from_fixed(acc64[j]) + (double)ovf[j]);
+        } else {
+          v = lsh[j];
+        }
+        finite = finite && isfinite(v);
+        dst[j] = v;
+      }
     }
     if (!finite) atomicOr(P.status, 2u);
     __syncthreads();

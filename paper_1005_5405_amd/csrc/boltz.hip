@@ -55,6 +55,7 @@ struct boltz_ctx {
   // variants, and the scratch of BOLTZ_WITH_ADJOINT
   bool adj_supported = false;
   int adj_block = 256;
+  bool adj_fixed[2] = {false, false};
   size_t adj_lds[2] = {0, 0};
   int64_t adj_grid[2] = {0, 0};
   float* adj_hs = nullptr;      // post-stream state recomputed by boltz_step_adjoint
@@ -139,19 +140,29 @@ bool pick_collide(int nv, int ns, bool& fixed, int (&blocks)[2]) {
   return true;
 }
 
-// Block size of the collide adjoint (the fixed-point layout plus a y . psi
-// table must fit in LDS): 256 threads when four workgroups fit per CU, else
-// 512.  false when the layout does not fit.
-bool pick_adjoint(int nv, int ns, int& block) {
-  const size_t dyn = collide_adj_lds(nv, ns, true);
-  if (dyn + collide_static_lds(512) > kLdsBytes) return false;
-  block = (4 * (dyn + collide_static_lds(256)) <= kLdsBytes) ? 256 : 512;
+// Block size of the collide adjoint (at least the FP64-sum layout, the
+// forward's fixed-point layout plus a y . psi table, must fit in LDS): 256
+// threads when four workgroups fit per CU, else 512.  fixed[t]: the
+// fixed-point adjoint sums (one more FP32 array) fit as well, for the
+// drawn-pair [0] and shared-table [1] variants.  false when nothing fits.
+bool pick_adjoint(int nv, int ns, int& block, bool (&fixed)[2]) {
+  const size_t dyn = collide_adj_lds(nv, ns, true, false);
+  if (dyn + collide_adj_static_lds(512) > kLdsBytes) return false;
+  block = (4 * (dyn + collide_adj_static_lds(256)) <= kLdsBytes) ? 256 : 512;
+  for (int t = 0; t < 2; ++t)
+    fixed[t] = collide_adj_lds(nv, ns, t == 0, true) + collide_adj_static_lds(block) <= kLdsBytes;
   return true;
 }
 
-const void* collide_adj_fn(int block, bool table) {
-  if (block == 256) return table ? (const void*)collide_adj_kernel<256, true> : (const void*)collide_adj_kernel<256, false>;
-  return table ? (const void*)collide_adj_kernel<512, true> : (const void*)collide_adj_kernel<512, false>;
+const void* collide_adj_fn(int block, bool table, bool fixed) {
+#define BOLTZ_ADJ_FN(B)                                                                                   \
+  if (block == B)                                                                                         \
+    return table ? (fixed ? (const void*)collide_adj_kernel<B, true, true> : (const void*)collide_adj_kernel<B, true, false>) \
+                 : (fixed ? (const void*)collide_adj_kernel<B, false, true> : (const void*)collide_adj_kernel<B, false, false>);
+  BOLTZ_ADJ_FN(256)
+  BOLTZ_ADJ_FN(512)
+#undef BOLTZ_ADJ_FN
+  return nullptr;
 }
 
 const void* collide_fn(int block, bool table, bool fixed) {
@@ -447,17 +458,26 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     const int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
   }
-  c->adj_supported = pick_adjoint(c->nv, nsum, c->adj_block);
+  c->adj_supported = ea == hipSuccess && pick_adjoint(c->nv, nsum, c->adj_block, c->adj_fixed);
   for (int t = 0; t < 2 && ea == hipSuccess && c->adj_supported; ++t) {
-    const void* fn = collide_adj_fn(c->adj_block, t == 1);
-    c->adj_lds[t] = collide_adj_lds(c->nv, nsum, t == 0);
-    ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->adj_lds[t]);
-    int per_cu = 0;
-    if (ea == hipSuccess)
-      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, c->adj_block, c->adj_lds[t]);
-    if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
-    const int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
-    c->adj_grid[t] = c->ncells < cap ? c->ncells : cap;
+    // the fixed-point layout when the runtime accepts its LDS size, else FP64 sums
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      const void* fn = collide_adj_fn(c->adj_block, t == 1, c->adj_fixed[t]);
+      c->adj_lds[t] = collide_adj_lds(c->nv, nsum, t == 0, c->adj_fixed[t]);
+      ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->adj_lds[t]);
+      int per_cu = 0;
+      if (ea == hipSuccess)
+        ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, c->adj_block, c->adj_lds[t]);
+      if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
+      if (ea == hipSuccess) {
+        const int64_t cap = (int64_t)per_cu * (ncu < 1 ? 1 : ncu);
+        c->adj_grid[t] = c->ncells < cap ? c->ncells : cap;
+        break;
+      }
+      if (!c->adj_fixed[t]) break;
+      (void)hipGetLastError();
+      c->adj_fixed[t] = false;
+    }
   }
   if (ea != hipSuccess) {
     boltz_destroy(c);
@@ -697,17 +717,25 @@ static int launch_stream_adj(boltz_ctx* c, const WallArgs& W, const double* lo, 
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream adjoint launch");
 }
 
+extern "C++" template <int B, bool TABLE, bool FIXED>
+static void launch_collide_adj_v(boltz_ctx* c, const float* hs, const double* lo, double* ls, uint32_t s32,
+                                 uint32_t flags, hipStream_t st) {
+  const int t = TABLE ? 1 : 0;
+  hipLaunchKernelGGL((collide_adj_kernel<B, TABLE, FIXED>), dim3((unsigned)c->adj_grid[t]), dim3(B), c->adj_lds[t],
+                     st, c->P, hs, lo, ls, s32, flags, c->tidx, c->tcoef);
+}
+
 extern "C++" template <int B>
 static void launch_collide_adj_b(boltz_ctx* c, bool table, const float* hs, const double* lo, double* ls,
                                  uint32_t s32, uint32_t flags, hipStream_t st) {
-  const int t = table ? 1 : 0;
-  const dim3 grid((unsigned)c->adj_grid[t]);
-  if (table)
-    hipLaunchKernelGGL((collide_adj_kernel<B, true>), grid, dim3(B), c->adj_lds[t], st, c->P, hs, lo, ls, s32, flags,
-                       c->tidx, c->tcoef);
-  else
-    hipLaunchKernelGGL((collide_adj_kernel<B, false>), grid, dim3(B), c->adj_lds[t], st, c->P, hs, lo, ls, s32,
-                       flags, c->tidx, c->tcoef);
+  const bool fixed = c->adj_fixed[table ? 1 : 0];
+  if (table) {
+    if (fixed) launch_collide_adj_v<B, true, true>(c, hs, lo, ls, s32, flags, st);
+    else launch_collide_adj_v<B, true, false>(c, hs, lo, ls, s32, flags, st);
+  } else {
+    if (fixed) launch_collide_adj_v<B, false, true>(c, hs, lo, ls, s32, flags, st);
+    else launch_collide_adj_v<B, false, false>(c, hs, lo, ls, s32, flags, st);
+  }
 }
 
 static int launch_collide_adj(boltz_ctx* c, const float* hs, const double* lo, double* ls, int64_t step,
