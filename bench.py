@@ -47,9 +47,9 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 # kernels), each scaled by what the counter reads for a device copy of the
 # 131 MB state (bench.py --calibrate); valid only for the kernel sources whose
 # SHA-256 is recorded (profiles/collide_counters_cavity64.md).
-TRAFFIC = {"sha256": "7af7bb4025722018fef92cb8590f34cda8dadbeb134ddfd2854ac5f6c1a6319e",
-           "fetch_kib": 66350.4 + 98.5, "write_kib": 128000.0 + 468.8,
-           "fetch_scale": 128000.0 / 64018.1, "write_scale": 1.0}
+TRAFFIC = {"sha256": "9b714637a9438bcde388005a20e0a5cb89ad2939778ba557bd867e29a3d31d9f",
+           "fetch_kib": 66538.2 + 106.0, "write_kib": 128000.0 + 468.8,
+           "fetch_scale": 128000.0 / 64018.6, "write_scale": 1.0}
 KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
 
 
@@ -208,6 +208,16 @@ def run_adjoint(pkg, torch, preset, steps: int, warmup: int, window: int, every:
     J.backward()
     torch.cuda.synchronize()
     t_win = time.perf_counter() - t0
+    # same-seed central differences of the forward map, h = 1e-3
+    fd = {}
+    for k, name in ((0, "lid_u"), (3, "tau_top"), (4 + g.nx // 4, "tau_bottom_%d" % (g.nx // 4))):
+        vals = []
+        for sgn in (1.0, -1.0):
+            th = theta.detach().clone()
+            th[k] += sgn * 1e-3
+            with torch.no_grad():
+                vals.append(lid_shear_window(g, h0.detach(), th, window, step0=0, every=every).item())
+        fd[name] = {"adjoint": float(theta.grad[k]), "fd": (vals[0] - vals[1]) / 2e-3}
     nodes = g.ncells * g.nv
     return {"workload": preset.name + " with bottom profile 1 + 0.05 sin(2 pi x)", "steps": steps,
             "ms_per_adjoint_step": t_step * 1e3, "value": nodes / t_step, "unit": "node-updates/s",
@@ -222,7 +232,7 @@ def run_adjoint(pkg, torch, preset, steps: int, warmup: int, window: int, every:
                                    "hbm_bytes_per_node": 32,
                                    "hbm_frac": 32 * nodes / t_sa / 1e9 / HBM_PEAK_GBS}},
             "window": {"steps": window, "checkpoint_every": every, "seconds": t_win, "J": J.item(),
-                       "dJ_dlid_u": float(theta.grad[0]), "dJ_dtau_top": float(theta.grad[3])}}
+                       "gradient_vs_central_differences": fd}}
 
 
 def main():

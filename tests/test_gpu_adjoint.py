@@ -380,3 +380,83 @@ def test_window_gradient_matches_oracle_chain(lib, oracle_mod, torch_mod):
 
         fd = (Jk(+1) - Jk(-1)) / 2e-3
         assert abs(fd - gt[k]) <= 5e-3 * max(abs(gt[k]), 1e-2 * np.abs(gt).max()), (k, fd, gt[k])
+
+
+# ------------------------------------------------------------ full size --
+def _c3(lib, oracle_mod=None):
+    from paper_1005_5405_amd import CAVITY_64
+
+    kw = CAVITY_64.problem()
+    g = lib.Boltz(**dict(kw, flags=lib.WITH_ADJOINT))
+    o = oracle_mod.Oracle(**kw) if oracle_mod is not None else None
+    theta0 = np.concatenate([[CAVITY_64.lid_u, 1.0, 1.0, 1.0], _profile(g.nx)])
+    return g, o, theta0
+
+
+def test_full_size_window_gradient_matches_oracle_chain(lib, oracle_mod, torch_mod):
+    """The 64x64 cavity, 20^3 velocities, 20000 pairs per cell, G = 0, bottom
+    profile 1 + 0.05 sin(2 pi x): a 2-step window from a developed state
+    through the autograd function (the launch configuration the benchmark
+    times) against the oracle's chain of adjoints."""
+    from paper_1005_5405_amd import inputs
+    from paper_1005_5405_amd.window import lid_shear_window
+
+    g, o, theta0 = _c3(lib, oracle_mod)
+    _say("full-size window gradient", g.shape)
+    N = 2
+    h0 = inputs.random_field(o.shape, seed=3, scale=0.2).astype(np.float32)
+    theta = torch_mod.tensor(theta0, dtype=torch_mod.float64, requires_grad=True)
+    hd = torch_mod.from_numpy(h0).cuda().requires_grad_(True)
+    J = lid_shear_window(g, hd, theta, N, step0=40, every=20)
+    J.backward()
+    gt = theta.grad.numpy()
+    gh = _host(hd.grad)
+    wo = oracle_mod.Walls(lid_u=theta0[0], tau_left=1.0, tau_right=1.0, tau_bottom=1.0, tau_top=1.0,
+                          tau_bottom_x=theta0[4:])
+    states = [h0.astype(np.float64)]
+    for n in range(N):
+        states.append(o.step(states[-1], wo, 40 + n))
+    Jref = np.mean([o.moments(states[n], wo, lid_shear=True)[1] for n in range(1, N + 1)])
+    assert abs(J.item() - Jref) <= 1e-4 * abs(Jref), (J.item(), Jref)
+    lam = np.zeros(o.shape)
+    grad = np.zeros(o.grad_size())
+    for n in range(N, 0, -1):
+        lD, gD = o.lid_shear_adjoint(states[n], wo, weight=1.0 / N)
+        lam = lam + lD
+        grad += gD
+        lam, gs = o.step_adjoint(states[n - 1], lam, wo, 40 + n - 1)
+        grad += gs
+    assert np.abs(gt - grad).max() <= 1e-4 * np.abs(grad).max(), (gt[:6], grad[:6])
+    assert np.abs(gh - lam).max() <= 1e-4 * np.abs(lam).max()
+
+
+def test_full_size_window_gradient_matches_finite_differences(lib, torch_mod):
+    """The differentiation workload itself: a 200-step window from rest on the
+    64x64 / 20^3 / 20000-pair cavity with checkpoints every 20 steps; the
+    gradient of the time-averaged lid shear against same-seed central
+    differences of the GPU forward map with h = 1e-3."""
+    from paper_1005_5405_amd.window import lid_shear_window
+
+    g, _, theta0 = _c3(lib)
+    _say("full-size window FD", g.shape)
+    N = 200
+    h0 = torch_mod.zeros(g.shape, dtype=torch_mod.float32, device="cuda")
+    theta = torch_mod.tensor(theta0, dtype=torch_mod.float64, requires_grad=True)
+    J = lid_shear_window(g, h0, theta, N, step0=0, every=20)
+    J.backward()
+    gt = theta.grad.numpy()
+    assert np.all(np.isfinite(gt)) and g.read_status() == 0
+
+    def Jat(th):
+        with torch_mod.no_grad():
+            return lid_shear_window(g, h0, torch_mod.tensor(th), N, step0=0, every=20).item()
+
+    h = 1e-3
+    for k in [0, 3, 4 + 16, 4 + 47]:
+        tp, tm = theta0.copy(), theta0.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (Jat(tp) - Jat(tm)) / (2 * h)
+        _say("k", k, "adjoint", gt[k], "fd", fd)
+        # FP32 states: |J| 2^-24 noise over 2h, plus O(h^2)
+        assert abs(fd - gt[k]) <= 1e-3 * abs(gt[k]) + 1e-4 * abs(J.item()), (k, fd, gt[k])
