@@ -208,6 +208,69 @@ int boltz_step_adjoint(boltz_ctx* ctx, const float* h_in, const double* lam_out,
 int boltz_lid_shear_adjoint(boltz_ctx* ctx, const float* h, const boltz_walls* walls, double weight, double* lam,
                             double* grad_walls, void* stream);
 
+/* ---- Batches: many independent problems (cavities of different size,
+ * velocity grid, Knudsen number, lid velocity and pair count) advanced by
+ * one step with one launch per phase: the face densities of every cavity,
+ * the streaming of every problem, the shared-sample records of every
+ * problem, and one persistent collision launch over a work list of
+ * (problem, cell) items sorted by decreasing cost.  Every problem's result
+ * is bitwise that of boltz_step on the problem alone.  The step number is a
+ * device counter (boltz_batch_set_step; boltz_batch_step advances it), so a
+ * captured HIP graph of boltz_batch_step calls replays successive steps.
+ * All problems must share the streaming order and have nv[2] % 4 == 0. */
+typedef struct boltz_batch boltz_batch;
+
+typedef struct boltz_batch_info {
+  int32_t count;         /* problems                                         */
+  int32_t collide_block; /* threads per workgroup of the batched collision   */
+  int64_t nodes;         /* phase-space nodes of the whole batch             */
+  int64_t pair_cells;    /* sum over problems of cells * n_pairs             */
+  int64_t device_bytes;  /* device memory held by the batch                  */
+} boltz_batch_info;
+
+/* Create a batch of `count` (1..4096) problems on the current device; each
+ * problem is validated as by boltz_create (its error message names it).
+ * EINVAL also for mixed streaming orders or nv[2] % 4 != 0. */
+int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** out);
+
+void boltz_batch_destroy(boltz_batch* batch);
+
+int boltz_batch_query(const boltz_batch* batch, boltz_batch_info* out);
+
+const char* boltz_batch_last_error(const boltz_batch* batch);
+
+/* offsets (host, count values): first element of each problem's state in
+ * the batch's h buffers (ncells * nv FP32 values each, contiguous). */
+int boltz_batch_offsets(const boltz_batch* batch, int64_t* offsets);
+
+/* The context of problem `index` (owned by the batch, valid until
+ * boltz_batch_destroy): every single-problem call (moments, adjoints, ...)
+ * works on its slice of the batch state.  NULL for an invalid index. */
+boltz_ctx* boltz_batch_problem(boltz_batch* batch, int index);
+
+/* Set the device step counter (enqueued on `stream`). */
+int boltz_batch_set_step(boltz_batch* batch, int64_t step, void* stream);
+
+/* One step of every problem: h_in -> h_out (device, batch layout, must not
+ * overlap) at the device step counter, which is then advanced.  walls: host
+ * array of `count` wall states (entries of periodic problems ignored; NULL
+ * if there is no cavity).  Enqueues only kernels; while the wall states do
+ * not change it can be captured into a HIP graph. */
+int boltz_batch_step(boltz_batch* batch, const float* h_in, float* h_out, const boltz_walls* walls,
+                     void* stream);
+
+/* Tuning: time `steps` steps (h_a <-> h_b, both overwritten; the step
+ * counter advances) for every collision block size that fits the batch's
+ * LDS (256, 512, 1024 threads), keep the fastest; ms_out (host, 3 values or
+ * NULL) receives each size's milliseconds per step (untouched if it does
+ * not fit).  Synchronises `stream`. */
+int boltz_batch_tune(boltz_batch* batch, float* h_a, float* h_b, const boltz_walls* walls, int steps,
+                     void* stream, double* ms_out);
+
+/* Use a given collision block size (256, 512 or 1024; EINVAL if its LDS does
+ * not fit). */
+int boltz_batch_set_block(boltz_batch* batch, int block);
+
 /* Test hook: the pairs the collision kernel draws for (cell, step) and pair
  * indices m0 .. m0+count-1, computed on the device by the kernel's own
  * sampler.  idx4 (host, count*4): a, b, a*, b* (a* = b* = -1 for a discarded

@@ -44,6 +44,11 @@ class _Walls(ctypes.Structure):
                 ("tau_bottom", ctypes.c_double), ("tau_top", ctypes.c_double), ("tau_bottom_x", ctypes.c_void_p)]
 
 
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("collide_block", ctypes.c_int32), ("nodes", ctypes.c_int64),
+                ("pair_cells", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("ncells", ctypes.c_int64), ("nv", ctypes.c_int64), ("dt", ctypes.c_double),
                 ("K", ctypes.c_double), ("W", ctypes.c_double), ("qfac", ctypes.c_double),
@@ -53,7 +58,9 @@ class _Info(ctypes.Structure):
 EXPORTS = ("boltz_create", "boltz_destroy", "boltz_query", "boltz_last_error", "boltz_stream",
            "boltz_collide", "boltz_moments", "boltz_step", "boltz_stream_adjoint", "boltz_collide_adjoint",
            "boltz_step_adjoint", "boltz_lid_shear_adjoint", "boltz_debug_pairs", "boltz_axis_thresholds",
-           "boltz_read_status")
+           "boltz_read_status", "boltz_batch_create", "boltz_batch_destroy", "boltz_batch_query",
+           "boltz_batch_last_error", "boltz_batch_offsets", "boltz_batch_problem", "boltz_batch_set_step",
+           "boltz_batch_step", "boltz_batch_tune", "boltz_batch_set_block")
 
 _lib = None
 
@@ -90,10 +97,24 @@ def load_library(path: str = LIB_PATH):
     L.boltz_debug_pairs.argtypes = [P, I64, I64, I64, I64, V, V, V]
     L.boltz_axis_thresholds.argtypes = [P, ctypes.c_int, V]
     L.boltz_read_status.argtypes = [P, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, V]
+    L.boltz_batch_create.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(P)]
+    L.boltz_batch_destroy.argtypes = [P]
+    L.boltz_batch_query.argtypes = [P, ctypes.POINTER(_BatchInfo)]
+    L.boltz_batch_last_error.argtypes = [P]
+    L.boltz_batch_last_error.restype = ctypes.c_char_p
+    L.boltz_batch_offsets.argtypes = [P, V]
+    L.boltz_batch_problem.argtypes = [P, ctypes.c_int]
+    L.boltz_batch_set_step.argtypes = [P, I64, V]
+    L.boltz_batch_step.argtypes = [P, V, V, W, V]
+    L.boltz_batch_tune.argtypes = [P, V, V, W, ctypes.c_int, V, V]
+    L.boltz_batch_set_block.argtypes = [P, ctypes.c_int]
     for name in EXPORTS:
-        if name not in ("boltz_last_error", "boltz_destroy"):
+        if name not in ("boltz_last_error", "boltz_destroy", "boltz_batch_last_error", "boltz_batch_destroy",
+                        "boltz_batch_problem"):
             getattr(L, name).restype = ctypes.c_int
     L.boltz_destroy.restype = None
+    L.boltz_batch_destroy.restype = None
+    L.boltz_batch_problem.restype = ctypes.c_void_p
     _lib = L
     return L
 
@@ -144,24 +165,36 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _problem(nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2, bc=BC_CAVITY, sample_group=1,
+             seed=1, cavity_id=0, flags=0, mix16=0) -> _Problem:
+    nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
+    vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
+    return _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax), float(delta),
+                    float(eps), float(cfl), float(dt), int(order), int(bc), int(n_pairs), int(sample_group),
+                    int(seed), int(cavity_id), int(flags), int(mix16))
+
+
 class Boltz:
     """One problem on the current HIP device (a boltz_ctx)."""
 
     def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2, bc=BC_CAVITY,
-                 sample_group=1, seed=1, cavity_id=0, flags=0, mix16=0):
+                 sample_group=1, seed=1, cavity_id=0, flags=0, mix16=0, _borrowed=None):
         L = load_library()
-        nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
-        vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
-        p = _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax), float(delta),
-                     float(eps), float(cfl), float(dt), int(order), int(bc), int(n_pairs), int(sample_group),
-                     int(seed), int(cavity_id), int(flags), int(mix16))
-        ctx = ctypes.c_void_p()
-        rc = L.boltz_create(ctypes.byref(p), ctypes.byref(ctx))
-        if rc != OK:
-            raise BoltzError(rc, "boltz_create: " + L.boltz_last_error(None).decode())
+        if _borrowed is None:
+            p = _problem(nx, ny, nv, vmax, delta, eps, n_pairs, cfl, dt, order, bc, sample_group, seed, cavity_id,
+                         flags, mix16)
+            ctx = ctypes.c_void_p()
+            rc = L.boltz_create(ctypes.byref(p), ctypes.byref(ctx))
+            if rc != OK:
+                raise BoltzError(rc, "boltz_create: " + L.boltz_last_error(None).decode())
+            self._owned = True
+        else:
+            ctx = ctypes.c_void_p(_borrowed)
+            self._owned = False
         self._ctx = ctx
         info = _Info()
         L.boltz_query(ctx, ctypes.byref(info))
+        nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
         self.nx, self.ny, self.nv3 = int(nx), int(ny), nv
         self.ncells, self.nv = int(info.ncells), int(info.nv)
         self.numel = self.ncells * self.nv
@@ -172,9 +205,9 @@ class Boltz:
         self.mix16 = int(mix16)
 
     def close(self):
-        if getattr(self, "_ctx", None) is not None and _lib is not None:
+        if getattr(self, "_ctx", None) is not None and _lib is not None and getattr(self, "_owned", True):
             _lib.boltz_destroy(self._ctx)
-            self._ctx = None
+        self._ctx = None
 
     def __del__(self):
         self.close()
@@ -301,3 +334,94 @@ class Boltz:
         self._check(_lib.boltz_read_status(self._ctx, ctypes.byref(v), 1 if clear else 0, _stream(stream)),
                     "boltz_read_status")
         return int(v.value)
+
+
+class Batch:
+    """Many problems advanced together (a boltz_batch): one launch per phase
+    for the whole batch.  problems: list of keyword dicts as for Boltz.  The
+    state of the batch is one FP32 tensor of ``nodes`` values; problem i
+    occupies ``view(h, i)``."""
+
+    def __init__(self, problems):
+        L = load_library()
+        n = len(problems)
+        arr = (_Problem * n)(*[_problem(**p) for p in problems])
+        b = ctypes.c_void_p()
+        rc = L.boltz_batch_create(arr, n, ctypes.byref(b))
+        if rc != OK:
+            raise BoltzError(rc, "boltz_batch_create: " + L.boltz_batch_last_error(None).decode())
+        self._b = b
+        self.count = n
+        self.offsets = np.zeros(n, dtype=np.int64)
+        L.boltz_batch_offsets(b, self.offsets.ctypes.data)
+        self.problems = [Boltz(**p, _borrowed=L.boltz_batch_problem(b, i)) for i, p in enumerate(problems)]
+        self._refresh()
+
+    def _refresh(self):
+        info = _BatchInfo()
+        _lib.boltz_batch_query(self._b, ctypes.byref(info))
+        self.nodes, self.pair_cells = int(info.nodes), int(info.pair_cells)
+        self.collide_block, self.device_bytes = int(info.collide_block), int(info.device_bytes)
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and _lib is not None:
+            for p in self.problems:
+                p._ctx = None
+            _lib.boltz_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise BoltzError(rc, "%s: %s" % (what, _lib.boltz_batch_last_error(self._b).decode()))
+
+    def empty(self, fill=None):
+        import torch
+
+        t = torch.empty(self.nodes, dtype=torch.float32, device="cuda")
+        if fill is not None:
+            t.fill_(fill)
+        return t
+
+    def view(self, h, i):
+        p = self.problems[i]
+        o = int(self.offsets[i])
+        return h[o:o + p.numel].view(p.shape)
+
+    def _walls(self, walls):
+        if walls is None:
+            return None
+        if len(walls) != self.count:
+            raise ValueError("Batch: one wall state per problem")
+        arr = (_Walls * self.count)(*[(w if w is not None else Walls())._c() for w in walls])
+        self._walls_keep = (walls, arr)
+        return arr
+
+    def set_step(self, step, stream=None):
+        self._check(_lib.boltz_batch_set_step(self._b, int(step), _stream(stream)), "boltz_batch_set_step")
+
+    def step(self, h_in, h_out, walls=None, stream=None):
+        import torch
+
+        self._check(_lib.boltz_batch_step(self._b, _ptr(h_in, self.nodes, torch.float32, "h_in"),
+                                          _ptr(h_out, self.nodes, torch.float32, "h_out"), self._walls(walls),
+                                          _stream(stream)), "boltz_batch_step")
+
+    def tune(self, h_a, h_b, walls=None, steps=2, stream=None):
+        """Time every collision block size that fits and keep the fastest;
+        returns {block: ms per step}.  Overwrites h_a, h_b and advances the
+        step counter."""
+        import torch
+
+        ms = np.zeros(3)
+        self._check(_lib.boltz_batch_tune(self._b, _ptr(h_a, self.nodes, torch.float32, "h_a"),
+                                          _ptr(h_b, self.nodes, torch.float32, "h_b"), self._walls(walls),
+                                          int(steps), _stream(stream), ms.ctypes.data), "boltz_batch_tune")
+        self._refresh()
+        return {b: float(m) for b, m in zip((256, 512, 1024), ms) if m > 0}
+
+    def set_block(self, block):
+        self._check(_lib.boltz_batch_set_block(self._b, int(block)), "boltz_batch_set_block")
+        self._refresh()

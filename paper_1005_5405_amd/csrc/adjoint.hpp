@@ -279,15 +279,6 @@ __device__ __forceinline__ void wall_ratio_grad(double R, double vx, double vy, 
   dtau = R * (c2 / (tau * tau) - 1.5 / tau);
 }
 
-// Wall (and face position) of face f, faces numbered left[ny], right[ny],
-// bottom[nx], top[nx].
-__device__ __forceinline__ void face_of(const Params& P, int f, int& wall, int& pos) {
-  if (f < P.ny) { wall = WALL_LEFT; pos = f; }
-  else if (f < 2 * P.ny) { wall = WALL_RIGHT; pos = f - P.ny; }
-  else if (f < 2 * P.ny + P.nx) { wall = WALL_BOTTOM; pos = f - 2 * P.ny; }
-  else { wall = WALL_TOP; pos = f - 2 * P.ny - P.nx; }
-}
-
 __device__ __forceinline__ double face_tau(const Params& P, const WallArgs& W, int wall, int pos) {
   return wall == WALL_BOTTOM ? P.tau_b[pos] : W.tau[wall];
 }
@@ -528,7 +519,7 @@ __global__ __launch_bounds__(256) void lid_adj_kernel(Params P, WallArgs W, cons
   __shared__ double red[5 * 4];
   const int ix = blockIdx.x;
   const int nv = P.nv, n1 = P.n[1], n2 = P.n[2];
-  const double nwt = face_density(P, W, h, WALL_TOP, ix, 1, 0, 0, 0, 0, red);
+  const double nwt = face_density(P, h, WALL_TOP, ix, 1, 0, 0, 0, 0, red);
   const double* R = ratio_row(P, WALL_TOP, ix);
   const double U = W.lid_u, tau = W.tau[WALL_TOP];
   const double c0 = weight * (-2.0 / P.nx);

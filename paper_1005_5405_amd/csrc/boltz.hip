@@ -2,6 +2,7 @@
 // sampling tables, context memory, and the C ABI declared in include/boltz.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -528,7 +529,7 @@ static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const b
   if (rc != BOLTZ_OK) return rc;
   auto launch = [&](auto kern, int nface) {
     const int per_xcd = (nface + 7) / 8;
-    hipLaunchKernelGGL(kern, dim3(8 * per_xcd), dim3(kWallBlock), 0, st, c->P, W, h, nface, per_xcd);
+    hipLaunchKernelGGL(kern, dim3(8 * per_xcd), dim3(kWallBlock), 0, st, c->P, h, nface, per_xcd);
   };
   if (c->p.order == 2) {
     // x faces first; the y faces read their densities for the x-swept rows
@@ -867,6 +868,359 @@ int boltz_read_status(boltz_ctx* c, uint32_t* out, int clear, void* stream) {
   if (e == hipSuccess) e = hipMemcpy(out, c->P.status, 4, hipMemcpyDeviceToHost);
   if (e == hipSuccess && clear) e = hipMemset(c->P.status, 0, 4);
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "boltz_read_status");
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------- batches --
+namespace {
+
+__global__ void set_step_kernel(uint32_t* step, uint32_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step = v;
+}
+
+__global__ void advance_step_kernel(uint32_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1u;
+}
+
+const void* collide_batch_fn(int block) {
+  if (block == 256) return (const void*)collide_batch_kernel<256>;
+  if (block == 512) return (const void*)collide_batch_kernel<512>;
+  return (const void*)collide_batch_kernel<1024>;
+}
+
+}  // namespace
+
+struct boltz_batch {
+  std::vector<boltz_ctx*> ctx;
+  std::vector<int64_t> hoff;
+  int count = 0;
+  int order = 2;
+  bool any_cavity = false;
+  int device = 0;
+  void* dmem = nullptr;
+  size_t dbytes = 0;
+  BatchCav* cavs = nullptr;
+  int* start[4] = {nullptr, nullptr, nullptr, nullptr};  // x faces (all faces, order 1), y faces, stream units, sample blocks
+  int total[4] = {0, 0, 0, 0};
+  int2* items = nullptr;
+  int nitems = 0;
+  uint32_t* step_dev = nullptr;
+  int64_t nodes = 0;
+  int64_t pair_cells = 0;
+  size_t collide_lds = 0;
+  size_t sample_lds = 0;
+  int block = 512;                // collide block size in use
+  bool block_ok[3] = {false, false, false};  // 256, 512, 1024 fit
+  int64_t grid[3] = {0, 0, 0};
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+int bfail(boltz_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg; else g_batch_error = msg;
+  return code;
+}
+
+int block_index(int block) { return block == 256 ? 0 : (block == 512 ? 1 : 2); }
+
+}  // namespace
+
+extern "C" {
+
+const char* boltz_batch_last_error(const boltz_batch* b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+void boltz_batch_destroy(boltz_batch* b) {
+  if (!b) return;
+  for (boltz_ctx* c : b->ctx) boltz_destroy(c);
+  if (b->dmem) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(b->device);
+    (void)hipFree(b->dmem);
+    (void)hipSetDevice(cur);
+  }
+  delete b;
+}
+
+int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** out) {
+  if (!problems || !out || count < 1 || count > 4096)
+    return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: need 1..4096 problems and an output pointer");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    if (problems[i].order != problems[0].order)
+      return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: all problems need the same streaming order");
+    if (problems[i].nv[2] % 4 != 0)
+      return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batched streaming needs nv[2] % 4 == 0");
+    if ((int64_t)problems[i].nx * problems[i].ny >= ((int64_t)1 << 31))
+      return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: too many cells in one problem");
+  }
+  boltz_batch* b = new (std::nothrow) boltz_batch;
+  if (!b) return bfail(nullptr, BOLTZ_ENOMEM, "boltz_batch_create: out of host memory");
+  b->count = count;
+  b->order = problems[0].order;
+  (void)hipGetDevice(&b->device);
+  for (int i = 0; i < count; ++i) {
+    boltz_ctx* c = nullptr;
+    const int rc = boltz_create(&problems[i], &c);
+    if (rc != BOLTZ_OK) {
+      const std::string msg = "boltz_batch_create: problem " + std::to_string(i) + ": " + g_create_error;
+      boltz_batch_destroy(b);
+      return bfail(nullptr, rc, msg);
+    }
+    b->ctx.push_back(c);
+  }
+  // ---- descriptors, launch ranges, work items
+  std::vector<BatchCav> cavs(count);
+  std::vector<int> st[4];
+  for (int k = 0; k < 4; ++k) st[k].assign(count + 1, 0);
+  std::vector<double> cost(count);
+  int64_t off = 0;
+  size_t lds_max = 0, slds_max = 0;
+  for (int i = 0; i < count; ++i) {
+    const boltz_ctx* c = b->ctx[i];
+    BatchCav& C = cavs[i];
+    std::memset(&C, 0, sizeof(C));
+    C.P = c->P;
+    C.hoff = off;
+    C.tidx = c->tidx;
+    C.tcoef = c->tcoef;
+    C.fixed = c->collide_fixed ? 1 : 0;
+    b->hoff.push_back(off);
+    off += c->ncells * (int64_t)c->nv;
+    const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
+    b->any_cavity = b->any_cavity || cavity;
+    const int nx = c->p.nx, ny = c->p.ny;
+    const int nf0 = !cavity ? 0 : (b->order == 2 ? 2 * ny : 2 * (nx + ny));
+    const int nf1 = (cavity && b->order == 2) ? 2 * nx : 0;
+    const int64_t units = (int64_t)((nx + kTX4 - 1) / kTX4) * ((ny + kTY4 - 1) / kTY4) * ((c->nv + kJ4 - 1) / kJ4);
+    const int64_t sblocks = (c->ngroups > 0 && c->p.n_pairs > 0) ? c->ngroups * ((c->p.n_pairs + 255) / 256) : 0;
+    const int64_t nxt[4] = {(int64_t)st[0][i] + nf0, (int64_t)st[1][i] + nf1, (int64_t)st[2][i] + units,
+                            (int64_t)st[3][i] + sblocks};
+    for (int k = 0; k < 4; ++k) {
+      if (nxt[k] >= ((int64_t)1 << 31) / 8) {
+        boltz_batch_destroy(b);
+        return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batch too large for one launch per phase");
+      }
+      st[k][i + 1] = (int)nxt[k];
+    }
+    const int nsum = c->n[0] + c->n[1] + c->n[2];
+    const bool table = c->ngroups > 0;
+    lds_max = std::max(lds_max, CollideLDS::bytes(c->nv, nsum, c->collide_fixed, !table));
+    if (table) slds_max = std::max(slds_max, TablesLDS::bytes(nsum, true));
+    // relative cost of one cell: pair loop (drawn pairs cost more) plus the node phases
+    cost[i] = (double)c->p.n_pairs * (table ? 1.0 : 3.0) * (c->collide_fixed ? 1.0 : 4.0) + 40.0 * c->nv;
+    b->pair_cells += c->ncells * c->p.n_pairs;
+  }
+  b->nodes = off;
+  for (int k = 0; k < 4; ++k) b->total[k] = st[k][count];
+  std::vector<int2> items;
+  for (int i = 0; i < count; ++i)
+    for (int64_t cell = 0; cell < b->ctx[i]->ncells; ++cell) items.push_back(make_int2(i, (int)cell));
+  std::stable_sort(items.begin(), items.end(), [&](const int2& x, const int2& y) { return cost[x.x] > cost[y.x]; });
+  b->nitems = (int)items.size();
+  b->collide_lds = lds_max;
+  b->sample_lds = slds_max;
+  // ---- one device allocation
+  size_t o = 0;
+  const size_t o_cavs = o; o = align256(o + sizeof(BatchCav) * count);
+  size_t o_st[4];
+  for (int k = 0; k < 4; ++k) { o_st[k] = o; o = align256(o + sizeof(int) * (count + 1)); }
+  const size_t o_items = o; o = align256(o + sizeof(int2) * items.size());
+  const size_t o_step = o; o = align256(o + 4);
+  hipError_t e = hipMalloc(&b->dmem, o);
+  if (e != hipSuccess) {
+    boltz_batch_destroy(b);
+    return bfail(nullptr, BOLTZ_ENOMEM, std::string("boltz_batch_create: hipMalloc: ") + hipGetErrorString(e));
+  }
+  b->dbytes = o;
+  unsigned char* base = static_cast<unsigned char*>(b->dmem);
+  b->cavs = reinterpret_cast<BatchCav*>(base + o_cavs);
+  for (int k = 0; k < 4; ++k) b->start[k] = reinterpret_cast<int*>(base + o_st[k]);
+  b->items = reinterpret_cast<int2*>(base + o_items);
+  b->step_dev = reinterpret_cast<uint32_t*>(base + o_step);
+  e = hipMemcpy(b->cavs, cavs.data(), sizeof(BatchCav) * count, hipMemcpyHostToDevice);
+  for (int k = 0; k < 4 && e == hipSuccess; ++k)
+    e = hipMemcpy(b->start[k], st[k].data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(b->step_dev, 0, 4);
+  // ---- collide launch set-up for each block size whose LDS fits
+  int ncu = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e == hipSuccess && slds_max > 0)
+    e = hipFuncSetAttribute((const void*)sample_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)slds_max);
+  const int blocks[3] = {256, 512, 1024};
+  for (int t = 0; t < 3 && e == hipSuccess; ++t) {
+    if (lds_max + collide_static_lds(blocks[t]) > kLdsBytes) continue;
+    const void* fn = collide_batch_fn(blocks[t]);
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    int per_cu = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, blocks[t], lds_max);
+    if (e != hipSuccess || per_cu < 1) {
+      (void)hipGetLastError();
+      e = hipSuccess;
+      continue;
+    }
+    b->block_ok[t] = true;
+    const int64_t cap = (int64_t)per_cu * (ncu < 1 ? 1 : ncu);
+    b->grid[t] = b->nitems < cap ? b->nitems : cap;
+  }
+  if (e != hipSuccess) {
+    boltz_batch_destroy(b);
+    return bfail(nullptr, BOLTZ_EHIP, std::string("boltz_batch_create: ") + hipGetErrorString(e));
+  }
+  b->block = b->block_ok[1] ? 512 : (b->block_ok[0] ? 256 : 1024);
+  if (!b->block_ok[block_index(b->block)]) {
+    boltz_batch_destroy(b);
+    return bfail(nullptr, BOLTZ_EUNSUPPORTED, "boltz_batch_create: no collide block size fits the batch's LDS");
+  }
+  *out = b;
+  return BOLTZ_OK;
+}
+
+int boltz_batch_query(const boltz_batch* b, boltz_batch_info* out) {
+  if (!b || !out) return BOLTZ_EINVAL;
+  out->count = b->count;
+  out->nodes = b->nodes;
+  out->pair_cells = b->pair_cells;
+  out->collide_block = b->block;
+  int64_t bytes = (int64_t)b->dbytes;
+  for (const boltz_ctx* c : b->ctx) bytes += (int64_t)c->dbytes;
+  out->device_bytes = bytes;
+  return BOLTZ_OK;
+}
+
+int boltz_batch_offsets(const boltz_batch* b, int64_t* offsets) {
+  if (!b || !offsets) return BOLTZ_EINVAL;
+  for (int i = 0; i < b->count; ++i) offsets[i] = b->hoff[i];
+  return BOLTZ_OK;
+}
+
+boltz_ctx* boltz_batch_problem(boltz_batch* b, int index) {
+  if (!b || index < 0 || index >= b->count) return nullptr;
+  return b->ctx[index];
+}
+
+int boltz_batch_set_step(boltz_batch* b, int64_t step, void* stream) {
+  if (!b) return BOLTZ_EINVAL;
+  hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), b->step_dev,
+                     (uint32_t)step);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : bfail(b, BOLTZ_EHIP, std::string("boltz_batch_set_step: ") + hipGetErrorString(e));
+}
+
+int boltz_batch_step(boltz_batch* b, const float* h_in, float* h_out, const boltz_walls* walls, void* stream) {
+  if (!b) return BOLTZ_EINVAL;
+  if (!h_in || !h_out) return bfail(b, BOLTZ_EINVAL, "boltz_batch_step: null buffer");
+  if (overlap(h_in, h_out, (size_t)b->nodes * sizeof(float)))
+    return bfail(b, BOLTZ_EINVAL, "boltz_batch_step: h_in and h_out overlap");
+  if (b->any_cavity && !walls) return bfail(b, BOLTZ_EINVAL, "boltz_batch_step: cavities need walls");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // wall tables of every cavity (rebuilt only where the walls changed)
+  for (int i = 0; i < b->count; ++i) {
+    boltz_ctx* c = b->ctx[i];
+    if (c->p.bc != BOLTZ_BC_CAVITY) continue;
+    if (!walls_ok(&walls[i], c->p.nx))
+      return bfail(b, BOLTZ_EINVAL, "boltz_batch_step: invalid walls of problem " + std::to_string(i));
+    const int rc = ensure_ratio(c, make_walls(&walls[i]), &walls[i], st);
+    if (rc != BOLTZ_OK) return bfail(b, rc, "boltz_batch_step: " + c->err);
+  }
+  auto ranged = [](int total) { return (total + 7) / 8; };
+  if (b->total[0] > 0) {
+    const int px = ranged(b->total[0]);
+    hipLaunchKernelGGL(wall_batch_kernel<0>, dim3(8 * px), dim3(kWallBlock), 0, st, b->cavs, b->start[0], b->count,
+                       h_in, px);
+  }
+  if (b->total[1] > 0) {
+    const int px = ranged(b->total[1]);
+    hipLaunchKernelGGL(wall_batch_kernel<1>, dim3(8 * px), dim3(kWallBlock), 0, st, b->cavs, b->start[1], b->count,
+                       h_in, px);
+  }
+  {
+    const int px = ranged(b->total[2]);
+    if (b->order == 2)
+      hipLaunchKernelGGL(stream4_batch_kernel<2>, dim3(8 * px), dim3(kStream4Block), 0, st, b->cavs, b->start[2],
+                         b->count, h_in, h_out, px);
+    else
+      hipLaunchKernelGGL(stream4_batch_kernel<1>, dim3(8 * px), dim3(kStream4Block), 0, st, b->cavs, b->start[2],
+                         b->count, h_in, h_out, px);
+  }
+  if (b->total[3] > 0)
+    hipLaunchKernelGGL(sample_batch_kernel, dim3(b->total[3]), dim3(256), b->sample_lds, st, b->cavs, b->start[3],
+                       b->count, b->step_dev);
+  const int t = block_index(b->block);
+  const dim3 grid((unsigned)b->grid[t]);
+  switch (b->block) {
+    case 256:
+      hipLaunchKernelGGL(collide_batch_kernel<256>, grid, dim3(256), b->collide_lds, st, b->cavs, b->items, b->nitems,
+                         h_out, h_out, b->step_dev);
+      break;
+    case 512:
+      hipLaunchKernelGGL(collide_batch_kernel<512>, grid, dim3(512), b->collide_lds, st, b->cavs, b->items, b->nitems,
+                         h_out, h_out, b->step_dev);
+      break;
+    default:
+      hipLaunchKernelGGL(collide_batch_kernel<1024>, grid, dim3(1024), b->collide_lds, st, b->cavs, b->items,
+                         b->nitems, h_out, h_out, b->step_dev);
+      break;
+  }
+  hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, b->step_dev);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : bfail(b, BOLTZ_EHIP, std::string("boltz_batch_step: ") + hipGetErrorString(e));
+}
+
+int boltz_batch_set_block(boltz_batch* b, int block) {
+  if (!b) return BOLTZ_EINVAL;
+  if ((block != 256 && block != 512 && block != 1024) || !b->block_ok[block_index(block)])
+    return bfail(b, BOLTZ_EINVAL, "boltz_batch_set_block: block size not available for this batch");
+  b->block = block;
+  return BOLTZ_OK;
+}
+
+int boltz_batch_tune(boltz_batch* b, float* h_a, float* h_b, const boltz_walls* walls, int steps, void* stream,
+                     double* ms_out) {
+  if (!b) return BOLTZ_EINVAL;
+  if (!h_a || !h_b || steps < 1) return bfail(b, BOLTZ_EINVAL, "boltz_batch_tune: need two buffers and steps >= 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) return bfail(b, BOLTZ_EHIP, std::string("boltz_batch_tune: ") + hipGetErrorString(he));
+  const int blocks[3] = {256, 512, 1024};
+  int best = b->block;
+  float best_ms = 0.f;
+  int rc = BOLTZ_OK;
+  for (int t = 0; t < 3 && rc == BOLTZ_OK; ++t) {
+    if (!b->block_ok[t]) continue;
+    b->block = blocks[t];
+    rc = boltz_batch_step(b, h_a, h_b, walls, stream);  // warm-up
+    if (rc != BOLTZ_OK) break;
+    (void)hipEventRecord(e0, st);
+    for (int k = 0; k < steps && rc == BOLTZ_OK; ++k)
+      rc = boltz_batch_step(b, (k & 1) ? h_a : h_b, (k & 1) ? h_b : h_a, walls, stream);
+    (void)hipEventRecord(e1, st);
+    he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      rc = bfail(b, BOLTZ_EHIP, std::string("boltz_batch_tune: ") + hipGetErrorString(he));
+      break;
+    }
+    ms /= steps;
+    if (ms_out) ms_out[t] = ms;
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = blocks[t];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->block = best;
+  return rc;
 }
 
 }  // extern "C"

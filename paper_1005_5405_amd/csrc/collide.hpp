@@ -201,22 +201,49 @@ __global__ __launch_bounds__(256) void debug_pairs_kernel(Params P, int64_t cell
 // once per step into two arrays, idx = {a | b << 16, a* | b* << 16} and
 // coef = {q/w_a*, q/w_b*, q/w_a, q/w_b} in FP32; a discarded pair is stored
 // with a* = a, b* = b and zero coefficients.
-__global__ __launch_bounds__(256) void sample_kernel(Params P, uint32_t step, uint2* __restrict__ tidx,
-                                                     float4* __restrict__ tcoef) {
-  extern __shared__ __align__(16) unsigned char dsm[];
-  TablesLDS T;
-  load_tables(P, dsm, true, T);
-  __syncthreads();
+__device__ __forceinline__ void sample_record(const Params& P, const TablesLDS& T, uint32_t step, uint32_t group,
+                                              int64_t i, uint2* __restrict__ tidx, float4* __restrict__ tcoef) {
   const int64_t nt = P.n_pairs;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t group = blockIdx.y;
-  if (i >= nt) return;
   const Pair p = sample_pair(P, T, group, step, (uint32_t)i, nullptr);
   uint2 id;
   id.x = (uint32_t)p.a | ((uint32_t)p.b << 16);
   id.y = p.as >= 0 ? ((uint32_t)p.as | ((uint32_t)p.bs << 16)) : id.x;
   tidx[(int64_t)group * nt + i] = id;
   tcoef[(int64_t)group * nt + i] = make_float4((float)p.kas, (float)p.kbs, (float)p.ka, (float)p.kb);
+}
+
+__global__ __launch_bounds__(256) void sample_kernel(Params P, uint32_t step, uint2* __restrict__ tidx,
+                                                     float4* __restrict__ tcoef) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  TablesLDS T;
+  load_tables(P, dsm, true, T);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n_pairs) return;
+  sample_record(P, T, step, blockIdx.y, i, tidx, tcoef);
+}
+
+// The records of every shared-sample problem of a batch in one launch:
+// start[c] = first block of problem c, which has ceil(N_t / 256) blocks per
+// group; the step number is read from the device.
+__global__ __launch_bounds__(256) void sample_batch_kernel(const BatchCav* __restrict__ cavs,
+                                                           const int* __restrict__ start, int count,
+                                                           const uint32_t* __restrict__ step_dev) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int u = blockIdx.x;
+  if (u >= start[count]) return;
+  const int c = find_cav(start, count, u);
+  const BatchCav& C = cavs[c];
+  const Params& P = C.P;
+  const int nb = (int)((P.n_pairs + 255) / 256);
+  const int local = u - start[c];
+  const uint32_t group = (uint32_t)(local / nb);
+  TablesLDS T;
+  load_tables(P, dsm, true, T);
+  __syncthreads();
+  const int64_t i = (int64_t)(local - (int)group * nb) * 256 + threadIdx.x;
+  if (i >= P.n_pairs) return;
+  sample_record(P, T, *step_dev, group, i, C.tidx, C.tcoef);
 }
 
 // ------------------------------------------------------------------- S5 --
@@ -457,6 +484,105 @@ __device__ __forceinline__ void correction_sums(const TablesLDS& T, const float*
   }
 }
 
+// One cell after its h^s tile is in LDS and the accumulators are cleared
+// (and a barrier passed): S3 + S4 pair pass, h^c, S5 correction, one
+// coalesced store of h^{n+1} to dst.  next() is called once the pair pass is
+// over (the persistent kernel requests the next tile there); defect: the
+// cell's five values or null.  Ends with a barrier, so the LDS can be
+// refilled.
+template <int BLOCK, bool TABLE, bool FIXED, class Next>
+__device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T, float* hs, float* accf,
+                                             unsigned long long* acc64, double* red, double* tot, uint32_t group,
+                                             uint32_t step, uint32_t flags, float* dst, double* defect,
+                                             const uint2* __restrict__ tidx, const float4* __restrict__ tcoef,
+                                             Next&& next) {
+  const int tid = threadIdx.x;
+  const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const double* vx = T.v;
+  const double* vy = T.v + n0;
+  const double* vz = T.v + n0 + n1;
+  const double* omx = T.om;
+  const double* omy = T.om + n0;
+  const double* omz = T.om + n0 + n1;
+  // node loops are unrolled where the register budget allows it (at most
+  // 256 VGPRs below 1024 threads per workgroup, 128 at 1024)
+  constexpr int NU = BLOCK <= 512 ? 4 : 1;
+  const bool correct = !(flags & 1u);
+  const double eps = P.eps;
+  // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
+  gain_loss<BLOCK, TABLE, FIXED>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
+  __syncthreads();
+  next();
+  // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator
+#pragma unroll NU
+  for (int j = tid; j < nv; j += BLOCK) {
+    const float hsj = hs[j];
+    double dh = (double)accf[j];
+    if (FIXED) dh += from_fixed(acc64[j]);
+    accf[j] = (float)((double)hsj + dh);
+  }
+  if (correct) {
+    __syncthreads();
+    // (2) FP64 sums of M and r, block-reduced
+    double acc[20];
+    correction_sums<BLOCK, NU>(T, hs, accf, n0, n1, n2, acc);
+    block_sum20_lds(acc, red, tot);
+    if (tid < 64) {
+      // wavefront 0 solves M x = r and tabulates x . psi per axis:
+      // x1 v_x + x4 v_x^2, x2 v_y + x4 v_y^2, x0 + x3 v_z + x4 v_z^2
+      double M[15], r[5], x[5];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) M[k] = T.m0[k] + eps * tot[k];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) r[k] = -eps * tot[15 + k];
+      if (!solve5(M, r, x)) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[k] = 0.0;
+        if (tid == 0) atomicOr(P.status, 1u);
+      }
+      for (int i = tid; i < n0 + n1 + n2; i += 64) {
+        const double v = T.v[i];
+        T.xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
+                         : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
+      }
+    }
+    __syncthreads();
+  }
+  // ---- (3) h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
+  double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  bool finite = true;
+  NodeWalk nw2(tid, BLOCK, n1, n2);
+#pragma unroll NU
+  for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
+    const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
+    const double hc = (double)accf[j];
+    float out = (float)hc;
+    if (correct) {
+      const double xpsi = (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz];
+      out = (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc);
+    }
+    finite = finite && isfinite(out);
+    dst[j] = out;
+    if (defect) {
+      const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+      const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
+      const double w = (omx[jx] * omy[jy]) * omz[jz];
+      const double diff = eps * ((double)out - (double)hs[j]) * w;
+      dsum[0] += diff;
+      dsum[1] += v1 * diff;
+      dsum[2] += v2 * diff;
+      dsum[3] += v3 * diff;
+      dsum[4] += vv * diff;
+    }
+  }
+  if (!finite) atomicOr(P.status, 2u);
+  if (defect) {
+    block_sum<5>(dsum, red);
+    if (tid < 5) defect[tid] = dsum[tid];
+  }
+  __syncthreads();
+}
+
 // Persistent workgroups: workgroup b collides cells b, b + gridDim.x, ...;
 // the h^s tile of the next cell is loaded into registers while the node
 // phases of the current one run.  TABLE: the pairs come from the records of
@@ -470,7 +596,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   extern __shared__ __align__(16) unsigned char dsm[];
   __shared__ double red[20 * (BLOCK / 64)];
   __shared__ double tot[20];
-  const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const int nv = P.nv;
   const int64_t ncells = (int64_t)P.nx * P.ny;
   const int tid = threadIdx.x;
   float* hs = reinterpret_cast<float*>(dsm);
@@ -478,17 +604,6 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(dsm + 2 * CollideLDS::tile(nv));
   TablesLDS T;
   load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, FIXED), !TABLE, T);
-  const double* vx = T.v;
-  const double* vy = T.v + n0;
-  const double* vz = T.v + n0 + n1;
-  const double* omx = T.om;
-  const double* omy = T.om + n0;
-  const double* omz = T.om + n0 + n1;
-  // node loops are unrolled where the register budget allows it (at most
-  // 256 VGPRs below 1024 threads per workgroup, 128 at 1024)
-  constexpr int NU = BLOCK <= 512 ? 4 : 1;
-  const bool correct = !(flags & 1u);
-  const double eps = P.eps;
   const int nv4 = nv >> 2;
   const bool vec = ((nv & 3) == 0) && nv4 <= kPrefetch * BLOCK;
   Prefetch pre;
@@ -508,86 +623,85 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
       for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
-    // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
     const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
-    gain_loss<BLOCK, TABLE, FIXED>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
-    __syncthreads();
-    // The next cell's tile is requested only now: vector-memory waits retire
-    // in issue order, so loads issued before the pair loop would stall its
-    // first record loads; the node phases below wait on no vector load.
+    // The next cell's tile is requested once the pair pass is over:
+    // vector-memory waits retire in issue order, so loads issued before the
+    // pair loop would stall its first record loads; the node phases wait on
+    // no vector load.
+    collide_body<BLOCK, TABLE, FIXED>(P, T, hs, accf, acc64, red, tot, group, step, flags, hout_g + cell * nv,
+                                      defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
+                                        const int64_t next = cell + gridDim.x;
+                                        if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
+                                      });
+  }
+}
+
+// ------------------------------------------------------------ batches --
+// One work item of the batched collision: (problem, cell).  Workgroup b
+// takes items b, b + gridDim.x, ... of a list sorted by decreasing cost, so
+// every workgroup receives about the same number of pair-cells; the
+// problem's tables are reloaded into LDS when it changes from one item to
+// the next.  The dynamic LDS is that of the largest problem; each problem
+// uses its own layout (fixed-point or FP32 accumulators, drawn or shared
+// samples).  The step number is read from the device (graph replays).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __restrict__ cavs,
+                                                              const int2* __restrict__ items, int nitems,
+                                                              const float* hin, float* hout,
+                                                              const uint32_t* __restrict__ step_dev) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  __shared__ double red[20 * (BLOCK / 64)];
+  __shared__ double tot[20];
+  const int tid = threadIdx.x;
+  const uint32_t step = *step_dev;
+  int prev = -1;
+  TablesLDS T;
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int2 it = items[i];
+    const BatchCav& C = cavs[it.x];
+    const Params& P = C.P;
+    const int nv = P.nv;
+    const bool fixed = C.fixed != 0, table = P.sample_group != 1;
+    float* hs = reinterpret_cast<float*>(dsm);
+    float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
+    unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(dsm + 2 * CollideLDS::tile(nv));
+    if (it.x != prev) {
+      load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, fixed), !table, T);
+      prev = it.x;
+    }
+    const int64_t cell = it.y;
+    const float* src = hin + C.hoff + cell * nv;
+    if ((nv & 3) == 0) {
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      float4* d4 = reinterpret_cast<float4*>(hs);
+      for (int j = tid; j < (nv >> 2); j += BLOCK) d4[j] = s4[j];
+    } else {
+      for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
+    }
     {
-      const int64_t next = cell + gridDim.x;
-      if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
-    }
-    // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator
-#pragma unroll NU
-    for (int j = tid; j < nv; j += BLOCK) {
-      const float hsj = hs[j];
-      double dh = (double)accf[j];
-      if (FIXED) dh += from_fixed(acc64[j]);
-      accf[j] = (float)((double)hsj + dh);
-    }
-    if (correct) {
-      __syncthreads();
-      // (2) FP64 sums of M and r, block-reduced
-      double acc[20];
-      correction_sums<BLOCK, NU>(T, hs, accf, n0, n1, n2, acc);
-      block_sum20_lds(acc, red, tot);
-      if (tid < 64) {
-        // wavefront 0 solves M x = r and tabulates x . psi per axis:
-        // x1 v_x + x4 v_x^2, x2 v_y + x4 v_y^2, x0 + x3 v_z + x4 v_z^2
-        double M[15], r[5], x[5];
-#pragma unroll
-        for (int k = 0; k < 15; ++k) M[k] = T.m0[k] + eps * tot[k];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) r[k] = -eps * tot[15 + k];
-        if (!solve5(M, r, x)) {
-#pragma unroll
-          for (int k = 0; k < 5; ++k) x[k] = 0.0;
-          if (tid == 0) atomicOr(P.status, 1u);
-        }
-        for (int i = tid; i < n0 + n1 + n2; i += 64) {
-          const double v = T.v[i];
-          T.xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
-                           : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
-        }
-      }
-      __syncthreads();
-    }
-    // ---- (3) h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
-    double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    bool finite = true;
-    float* dst = hout_g + cell * nv;
-    NodeWalk nw2(tid, BLOCK, n1, n2);
-#pragma unroll NU
-    for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
-      const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
-      const double hc = (double)accf[j];
-      float out = (float)hc;
-      if (correct) {
-        const double xpsi = (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz];
-        out = (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc);
-      }
-      finite = finite && isfinite(out);
-      dst[j] = out;
-      if (defect) {
-        const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-        const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
-        const double w = (omx[jx] * omy[jy]) * omz[jz];
-        const double diff = eps * ((double)out - (double)hs[j]) * w;
-        dsum[0] += diff;
-        dsum[1] += v1 * diff;
-        dsum[2] += v2 * diff;
-        dsum[3] += v3 * diff;
-        dsum[4] += vv * diff;
-      }
-    }
-    if (!finite) atomicOr(P.status, 2u);
-    if (defect) {
-      block_sum<5>(dsum, red);
-      if (tid < 5) defect[cell * 5 + tid] = dsum[tid];
+      uint4* z = reinterpret_cast<uint4*>(accf);
+      const int nz = (int)(CollideLDS::acc(nv, fixed) / 16);
+      for (int k = tid; k < nz; k += BLOCK) z[k] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
+    const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
+    float* dst = hout + C.hoff + cell * nv;
+    auto none = []() {};
+    if (table) {
+      if (fixed)
+        collide_body<BLOCK, true, true>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
+                                        C.tcoef, none);
+      else
+        collide_body<BLOCK, true, false>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
+                                         C.tcoef, none);
+    } else {
+      if (fixed)
+        collide_body<BLOCK, false, true>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
+                                         C.tcoef, none);
+      else
+        collide_body<BLOCK, false, false>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
+                                          C.tcoef, none);
+    }
   }
 }
 

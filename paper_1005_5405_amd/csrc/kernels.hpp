@@ -57,6 +57,29 @@ struct Params {
   uint32_t* status;       // device status bits
 };
 
+// One problem of a batch: its constants and tables, the offset of its state
+// in the batch's h buffers and its shared-sample records.
+struct BatchCav {
+  Params P;
+  int64_t hoff;    // first element of the problem's h in the batch buffers
+  uint2* tidx;     // shared-sample records (G != 1), else null
+  float4* tcoef;
+  int fixed;       // 64-bit fixed-point collide accumulators
+  int pad;
+};
+
+// Problem of work unit u of a batched launch: the largest c with
+// start[c] <= u, start[0] = 0 (start has count + 1 entries).
+__device__ __forceinline__ int find_cav(const int* __restrict__ start, int count, int u) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 struct WallArgs {
   double lid_u;
   double tau[4];   // left, right, bottom, top
@@ -102,7 +125,7 @@ __device__ __forceinline__ const double* wall_consts(const Params& P, int wall, 
 // ------------------------------------------------------------------- S1 --
 // x-swept value (order 2) of node j at (ix, iy), read straight from global
 // memory; the same FP32 arithmetic as the stream kernel's x sweep.
-__device__ float xswept_value(const Params& P, const WallArgs& W, const float* h, int ix, int iy,
+__device__ float xswept_value(const Params& P, const float* h, int ix, int iy,
                               int j, int jx, int jy, int jz, double nwl, double nwr) {
   const double vx = P.vtab[jx];
   const float h0 = h[cell_off(P, ix, iy) + j];
@@ -126,7 +149,7 @@ __device__ float xswept_value(const Params& P, const WallArgs& W, const float* h
 // rest facing h = 0 gives n_w = 1 exactly), B = sum_out |v_n| w_j hhat_j;
 // n_w = (A + eps B) / D.  `order` selects the face value: 1 = adjacent cell,
 // 2 = Beam-Warming face value, from the x-swept state for y faces.
-__device__ double face_density(const Params& P, const WallArgs& W, const float* h, int wall, int pos,
+__device__ double face_density(const Params& P, const float* h, int wall, int pos,
                                int order, double nwl0, double nwl1, double nwr0, double nwr1,
                                double* red) {
   const int nx = P.nx, ny = P.ny, nv = P.nv, n1 = P.n[1], n2 = P.n[2];
@@ -162,8 +185,8 @@ __device__ double face_density(const Params& P, const WallArgs& W, const float* 
       const double R = ratio_row(P, wall, pos)[(mx * n1 + my) * n2 + jz];
       double ha, hb = 0.0;
       if (ysw) {
-        ha = xswept_value(P, W, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
-        hb = xswept_value(P, W, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
+        ha = xswept_value(P, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
+        hb = xswept_value(P, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
       } else {
         ha = h[cell_off(P, ax_, ay_) + j];
         if (order == 2) hb = h[cell_off(P, bx_, by_) + j];
@@ -235,7 +258,7 @@ __global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, Wa
 // away from the corner columns reads the three cells of each x sweep
 // directly (no ghost value is needed there).
 template <int U>
-__device__ double face_b(const Params& P, const WallArgs& W, const float* h, int wall, int pos, int order,
+__device__ double face_b(const Params& P, const float* h, int wall, int pos, int order,
                          double nwl0, double nwl1, double nwr0, double nwr1, int j0, int step) {
   const int nx = P.nx, ny = P.ny, nv = P.nv, n1 = P.n[1], n2 = P.n[2];
   const int nax = (wall <= WALL_RIGHT) ? 0 : 1;
@@ -285,8 +308,8 @@ __device__ double face_b(const Params& P, const WallArgs& W, const float* h, int
       double ha = a0[u], hb = b0[u];
       if (ysw) {
         if (corner) {
-          ha = xswept_value(P, W, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
-          hb = xswept_value(P, W, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
+          ha = xswept_value(P, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
+          hb = xswept_value(P, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
         } else if (P.vtab[jx] != 0.0) {
           const float Cx = P.cour[jx], Cx2 = P.cour2[jx];
           ha = bw_update(a0[u], a1[u], a2[u], Cx, Cx2);
@@ -311,19 +334,19 @@ __device__ double face_b(const Params& P, const WallArgs& W, const float* h, int
 // need the x-face densities of the previous launch.  Cavity problems only.
 constexpr int kWallBlock = 1024;
 
-template <int PHASE>
-__global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, const float* __restrict__ h,
-                                                          int nface, int per_xcd) {
-  __shared__ double red[kWallBlock / 64];
-  // neighbouring faces (which read overlapping cells) on the same XCD
-  int f = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (f >= nface) return;
-  if (PHASE == 1) f += 2 * P.ny;
-  int wall, pos;
+// Wall (and face position) of face f, faces numbered left[ny], right[ny],
+// bottom[nx], top[nx].
+__device__ __forceinline__ void face_of(const Params& P, int f, int& wall, int& pos) {
   if (f < P.ny) { wall = WALL_LEFT; pos = f; }
   else if (f < 2 * P.ny) { wall = WALL_RIGHT; pos = f - P.ny; }
   else if (f < 2 * P.ny + P.nx) { wall = WALL_BOTTOM; pos = f - 2 * P.ny; }
   else { wall = WALL_TOP; pos = f - 2 * P.ny - P.nx; }
+}
+
+template <int PHASE>
+__device__ __forceinline__ void wall_face(const Params& P, const float* __restrict__ h, int f, double* red) {
+  int wall, pos;
+  face_of(P, f, wall, pos);
   double nwl0 = 0.0, nwl1 = 0.0, nwr0 = 0.0, nwr1 = 0.0;
   if (PHASE == 1) {
     const int ra = (wall == WALL_BOTTOM) ? 0 : P.ny - 1;
@@ -333,12 +356,39 @@ __global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, WallArgs W, 
     nwr0 = P.nw[P.ny + ra];
     nwr1 = P.nw[P.ny + rb];
   }
-  double s[1] = {face_b<8>(P, W, h, wall, pos, P.order, nwl0, nwl1, nwr0, nwr1, (int)threadIdx.x, kWallBlock)};
+  double s[1] = {face_b<8>(P, h, wall, pos, P.order, nwl0, nwl1, nwr0, nwr1, (int)threadIdx.x, kWallBlock)};
   block_sum<1>(s, red);
   if (threadIdx.x == 0) {
     const double* k = wall_consts(P, wall, pos);
     P.nw[f] = (k[0] + P.eps * s[0]) / k[1];
   }
+}
+
+template <int PHASE>
+__global__ __launch_bounds__(kWallBlock) void wall_kernel(Params P, const float* __restrict__ h, int nface,
+                                                          int per_xcd) {
+  __shared__ double red[kWallBlock / 64];
+  // neighbouring faces (which read overlapping cells) on the same XCD
+  int f = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (f >= nface) return;
+  if (PHASE == 1) f += 2 * P.ny;
+  wall_face<PHASE>(P, h, f, red);
+}
+
+// The faces of every problem of a batch in one launch (start: first face of
+// each problem in this launch; PHASE 1 numbers a problem's y faces from 0).
+template <int PHASE>
+__global__ __launch_bounds__(kWallBlock) void wall_batch_kernel(const BatchCav* __restrict__ cavs,
+                                                                const int* __restrict__ start, int count,
+                                                                const float* __restrict__ h, int per_xcd) {
+  __shared__ double red[kWallBlock / 64];
+  const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (u >= start[count]) return;
+  const int c = find_cav(start, count, u);
+  const Params& P = cavs[c].P;
+  int f = u - start[c];
+  if (PHASE == 1) f += 2 * P.ny;
+  wall_face<PHASE>(P, h + cavs[c].hoff, f, red);
 }
 
 // ------------------------------------------------------------------- S2 --
@@ -504,17 +554,20 @@ __device__ __forceinline__ float4 bw4(float4 h0, float4 h1, float4 h2, float C, 
 }
 
 template <int ORDER>
-__global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const float* __restrict__ hin,
-                                                                float* __restrict__ hout, int tiles_x,
-                                                                int tiles_y, int nchunks, int per_xcd) {
+struct Stream4LDS {
+  static constexpr int AX = kTX4 + 2 * ORDER, AY = kTY4 + 2 * ORDER, Q = kJ4 / 4;
+  float4 a[AY * AX * Q];
+};
+
+// Work unit `unit` (a chunk of 32 velocities of one 16 x 8 tile of cells)
+// of one problem; tiles_x = ceil(nx / 16), tiles_y = ceil(ny / 8).
+template <int ORDER>
+__device__ __forceinline__ void stream4_unit(const Params& P, const float* __restrict__ hin, float* __restrict__ hout,
+                                             int tiles_x, int tiles_y, int unit, float4* A4) {
   constexpr int H = ORDER;
   constexpr int AX = kTX4 + 2 * H, AY = kTY4 + 2 * H;
   constexpr int Q = kJ4 / 4;
-  __shared__ float4 A4[AY * AX * Q];
   const int ntiles = tiles_x * tiles_y;
-  const int total = ntiles * nchunks;
-  const int unit = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (unit >= total) return;
   const int chunk = unit / ntiles, tile = unit % ntiles;
   const int ix0 = (tile % tiles_x) * kTX4, iy0 = (tile / tiles_x) * kTY4;
   const int j0 = chunk * kJ4;
@@ -634,6 +687,33 @@ __global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const 
   }
 }
 
+template <int ORDER>
+__global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const float* __restrict__ hin,
+                                                                float* __restrict__ hout, int tiles_x,
+                                                                int tiles_y, int nchunks, int per_xcd) {
+  __shared__ Stream4LDS<ORDER> L;
+  // XCD-aware order: contiguous (chunk, tile) ranges per XCD
+  const int unit = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (unit >= tiles_x * tiles_y * nchunks) return;
+  stream4_unit<ORDER>(P, hin, hout, tiles_x, tiles_y, unit, L.a);
+}
+
+// Every problem of a batch in one launch (start: first unit of each problem;
+// all problems have n_z % 4 == 0 and the same order).
+template <int ORDER>
+__global__ __launch_bounds__(kStream4Block) void stream4_batch_kernel(const BatchCav* __restrict__ cavs,
+                                                                      const int* __restrict__ start, int count,
+                                                                      const float* __restrict__ hin,
+                                                                      float* __restrict__ hout, int per_xcd) {
+  __shared__ Stream4LDS<ORDER> L;
+  const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (u >= start[count]) return;
+  const int c = find_cav(start, count, u);
+  const Params& P = cavs[c].P;
+  const int tiles_x = (P.nx + kTX4 - 1) / kTX4, tiles_y = (P.ny + kTY4 - 1) / kTY4;
+  stream4_unit<ORDER>(P, hin + cavs[c].hoff, hout + cavs[c].hoff, tiles_x, tiles_y, u - start[c], L.a);
+}
+
 }  // namespace boltz
 
 #include "collide.hpp"
@@ -689,7 +769,7 @@ __global__ __launch_bounds__(256) void moments_kernel(Params P, WallArgs W, cons
   if (want_lid && iy == P.ny - 1) {
     // lid face: gas-side values of this top cell for v_y > 0, wall emission
     // with the first-order face density for v_y < 0
-    const double nwt = face_density(P, W, h, WALL_TOP, ix, 1, 0, 0, 0, 0, red);
+    const double nwt = face_density(P, h, WALL_TOP, ix, 1, 0, 0, 0, 0, red);
     double pxy[1] = {0.0};
     for (int j = threadIdx.x; j < nv; j += blockDim.x) {
       int jx, jy, jz;

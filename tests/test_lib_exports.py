@@ -72,3 +72,20 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
     assert L.boltz_stream_adjoint(None, None, None, None, None, None, None) == binding.EINVAL
     assert L.boltz_collide_adjoint(None, None, None, None, 0, 0, None) == binding.EINVAL
     assert L.boltz_lid_shear_adjoint(None, None, None, 1.0, None, None, None) == binding.EINVAL
+
+
+def test_batch_arguments_are_rejected_before_any_device_call():
+    L, binding = _lib()
+    b = ctypes.c_void_p()
+    p = binding._problem(nx=8, ny=8, nv=8, vmax=3.0, delta=1.0, eps=0.1, n_pairs=10)
+    q = binding._problem(nx=8, ny=8, nv=8, vmax=3.0, delta=1.0, eps=0.1, n_pairs=10, order=1)
+    r = binding._problem(nx=8, ny=8, nv=(8, 8, 6), vmax=3.0, delta=1.0, eps=0.1, n_pairs=10)
+    assert L.boltz_batch_create(None, 1, ctypes.byref(b)) == binding.EINVAL
+    assert L.boltz_batch_create((binding._Problem * 1)(p), 0, ctypes.byref(b)) == binding.EINVAL
+    assert L.boltz_batch_create((binding._Problem * 2)(p, q), 2, ctypes.byref(b)) == binding.EINVAL
+    assert "order" in L.boltz_batch_last_error(None).decode()
+    assert L.boltz_batch_create((binding._Problem * 2)(p, r), 2, ctypes.byref(b)) == binding.EINVAL
+    assert "nv[2]" in L.boltz_batch_last_error(None).decode()
+    assert L.boltz_batch_step(None, None, None, None, None) == binding.EINVAL
+    assert L.boltz_batch_query(None, None) == binding.EINVAL
+    assert L.boltz_batch_problem(None, 0) is None
