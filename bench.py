@@ -235,6 +235,99 @@ def run_adjoint(pkg, torch, preset, steps: int, warmup: int, window: int, every:
                        "gradient_vs_central_differences": fd}}
 
 
+def batch_problems(count: int, seed: int = 0):
+    """Cavities of the batching workload drawn with numpy's default_rng(seed):
+    N x N cells with N uniform in 32..128, 16^3, 20^3 or 24^3 velocities on
+    [-5, 5], Kn log-uniform in [0.01, 1], lid velocity uniform in [0.05, 0.3]
+    (eps = lid velocity), 5000..30000 pairs per cell; shared samples (G = 0),
+    mixture share 1/4, order 2, CFL 0.5, one Philox stream per cavity."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    probs, lids = [], []
+    for i in range(count):
+        n = int(rng.integers(32, 129))
+        nv = int(rng.choice([16, 20, 24]))
+        kn = float(10.0 ** rng.uniform(-2.0, 0.0))
+        lid = float(rng.uniform(0.05, 0.3))
+        nt = int(rng.integers(5000, 30001))
+        probs.append(dict(nx=n, ny=n, nv=nv, vmax=5.0, delta=1.0 / kn, eps=lid, n_pairs=nt, cfl=0.5, order=2,
+                          bc=0, sample_group=0, seed=1, cavity_id=i, mix16=4))
+        lids.append(lid)
+    return probs, lids
+
+
+def run_batch(pkg, torch, count: int, steps: int, warmup: int):
+    """The batching workload: `count` cavities advanced by boltz_batch_step
+    (one launch per phase), first eagerly, then as replays of a captured
+    two-step HIP graph."""
+    import numpy as np
+
+    probs, lids = batch_problems(count)
+    t0 = time.perf_counter()
+    b = pkg.Batch(probs)
+    t_create = time.perf_counter() - t0
+    walls = [pkg.Walls(lid_u=u) for u in lids]
+    stream = torch.cuda.current_stream()
+    h_a, h_b = b.empty(0.0), b.empty(0.0)
+    tune_ms = b.tune(h_a, h_b, walls, steps=2)
+    h_a.zero_()
+    b.set_step(0)
+    for _ in range(warmup):
+        b.step(h_a, h_b, walls)
+        h_a, h_b = h_b, h_a
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        b.step(h_a, h_b, walls)
+        h_a, h_b = h_b, h_a
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_eager = time.perf_counter() - t0
+    ms_eager = e0.elapsed_time(e1) / steps
+    # captured graph of two steps (a -> b -> a)
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            b.step(h_a, h_b, walls)
+            b.step(h_b, h_a, walls)
+    stream.wait_stream(side)
+    reps = max(1, steps // 2)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t0
+    ms_graph = e0.elapsed_time(e1) / (2 * reps)
+    status = [p.read_status() for p in b.problems]
+    finite = bool(torch.isfinite(h_a).all().item())
+    classes = {}
+    for p in probs:
+        classes[str(p["nv"]) + "^3"] = classes.get(str(p["nv"]) + "^3", 0) + 1
+    out = {"workload": "%d cavities, N in 32..128, 16^3/20^3/24^3 velocities, Kn log-uniform [0.01, 1], lid "
+                       "U[0.05, 0.3], 5000..30000 pairs/cell, G = 0 (numpy default_rng(0))" % count,
+           "cavities": count, "velocity_grids": classes, "nodes": b.nodes, "pair_cells": b.pair_cells,
+           "state_bytes": 4 * b.nodes, "create_s": t_create, "collide_block": b.collide_block,
+           "tune_ms_per_step": {str(k): v for k, v in tune_ms.items()},
+           "eager": {"steps": steps, "ms_per_step": ms_eager, "value": b.nodes / (ms_eager * 1e-3),
+                     "pairs_per_s": b.pair_cells / (ms_eager * 1e-3), "wall_s": wall_eager},
+           "graph": {"steps": 2 * reps, "ms_per_step": ms_graph, "value": b.nodes / (ms_graph * 1e-3),
+                     "pairs_per_s": b.pair_cells / (ms_graph * 1e-3), "wall_s": wall_graph},
+           "unit": "node-updates/s", "hbm_frac_step": 16 * b.nodes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "status_nonzero": int(np.count_nonzero(status)), "finite": finite}
+    del g, h_a, h_b, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +341,9 @@ def main():
     ap.add_argument("--adjoint", choices=["auto", "skip"], default="auto",
                     help="also time the reverse mode (step adjoint, windowed lid-shear gradient)")
     ap.add_argument("--window", type=int, default=200, help="steps of the windowed gradient")
+    ap.add_argument("--batch", choices=["auto", "skip"], default="auto",
+                    help="also time the batching workload (many uneven cavities per step)")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--cpu-baseline", choices=["auto", "skip"], default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate", action="store_true",
@@ -322,6 +418,10 @@ def main():
         print("[bench] variant: reverse mode (%d-step window)" % args.window, flush=True)
         line.setdefault("variants", {})["adjoint"] = run_adjoint(
             pkg, torch, preset, max(10, K // 4), max(3, args.warmup // 4), args.window, 20)
+    if args.batch == "auto":
+        print("[bench] variant: batch of %d cavities" % args.batch_count, flush=True)
+        line.setdefault("variants", {})["batch"] = run_batch(pkg, torch, args.batch_count, max(4, K // 10),
+                                                             max(1, args.warmup // 10))
     if args.cpu_baseline == "auto":
         print("[bench] CPU oracle baseline ...", flush=True)
         line["cpu_baseline"] = cpu_baseline(preset, args.cpu_seconds)
