@@ -89,7 +89,7 @@ __device__ __forceinline__ void gain_loss_adj(const Params& P, const TablesLDS& 
 // array (large terms of the adjoint sums), then the tables and the per-axis
 // table of y . psi.
 __host__ __device__ inline size_t collide_adj_lds(int nv, int ns, bool sampler, bool fixed) {
-  return CollideLDS::tile(nv) + CollideLDS::acc(nv, true) + (fixed ? CollideLDS::tile(nv) : 0) +
+  return CollideLDS::tile(nv) + CollideLDS::acc(nv, ACC_FIXED) + (fixed ? CollideLDS::tile(nv) : 0) +
          TablesLDS::bytes(ns, sampler) + 8 * (size_t)ns;
 }
 
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
   float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
   unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(dsm + 2 * CollideLDS::tile(nv));
   double* lsh = reinterpret_cast<double*>(acc64);
-  unsigned char* after = dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, true);
+  unsigned char* after = dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, ACC_FIXED);
   float* ovf = FIXED ? reinterpret_cast<float*>(after) : nullptr;
   unsigned char* tb = after + (FIXED ? CollideLDS::tile(nv) : 0);
   TablesLDS T;
@@ -158,13 +158,13 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
     for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
     {
       uint4* z = reinterpret_cast<uint4*>(accf);
-      const int nz = (int)(CollideLDS::acc(nv, true) / 16);
+      const int nz = (int)(CollideLDS::acc(nv, ACC_FIXED) / 16);
       for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
     // ---- forward: increments and h^c
     const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
-    gain_loss<BLOCK, TABLE, true>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
+    gain_loss<BLOCK, TABLE, ACC_FIXED>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
     __syncthreads();
     for (int j = tid; j < nv; j += BLOCK) {
       const double dh = (double)accf[j] + from_fixed(acc64[j]);

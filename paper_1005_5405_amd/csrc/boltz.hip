@@ -44,7 +44,7 @@ struct boltz_ctx {
   // collide launch: block size, accumulator kind, dynamic LDS and persistent
   // grid of the fused-sampler [0] and shared-table [1] variants
   int collide_block[2] = {256, 256};
-  bool collide_fixed = true;
+  int collide_mode = ACC_FIXED;  // accumulation of the increments (ACC_*)
   size_t collide_lds[2] = {0, 0};
   int64_t collide_grid[2] = {0, 0};
   int64_t ngroups = 0;          // sample groups (shared-sample mode)
@@ -117,19 +117,25 @@ constexpr size_t kLdsBytes = 160 * 1024;
 // static LDS of the collide kernel (block reduction scratch) per block size
 size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof(double) + 64; }
 
-// Accumulator kind and block sizes of the collide kernel: 64-bit fixed-point
-// accumulators when they fit next to the h tile and tables, else FP32; the
-// block size gives about 1024 resident threads per CU.  block[0]: pairs drawn
-// in the kernel; block[1]: pairs read from the shared table, which runs
-// faster with 512 threads (and unrolled node loops) than with 1024 when only
-// one workgroup fits per CU.
-bool pick_collide(int nv, int ns, bool& fixed, int (&blocks)[2]) {
+// Accumulation mode and block sizes of the collide kernel: 64-bit
+// fixed-point accumulators for every node when they fit next to the h tile
+// and tables, else for half of the nodes per pass, else FP32; the block size
+// gives about 1024 resident threads per CU.  block[0]: pairs drawn in the
+// kernel; block[1]: pairs read from the shared table, which runs faster with
+// 512 threads (and unrolled node loops) than with 1024 when only one
+// workgroup fits per CU.  The split mode keeps 8192 / block nodes per thread
+// in registers between its passes, and uses 512 threads.
+bool pick_collide(int nv, int ns, int& mode, int (&blocks)[2]) {
   int block = 256;
-  fixed = CollideLDS::bytes(nv, ns, true, true) + collide_static_lds(1024) <= kLdsBytes;
-  const size_t dyn = CollideLDS::bytes(nv, ns, fixed, true);
-  if (dyn + collide_static_lds(1024) > kLdsBytes) return false;
+  if (CollideLDS::bytes(nv, ns, ACC_FIXED, true) + collide_static_lds(1024) <= kLdsBytes) mode = ACC_FIXED;
+  else if (CollideLDS::bytes(nv, ns, ACC_SPLIT, true) + collide_static_lds(512) <= kLdsBytes &&
+           CollideLDS::half(nv) <= 8192)
+    mode = ACC_SPLIT;
+  else mode = ACC_CAS;
+  const size_t dyn = CollideLDS::bytes(nv, ns, mode, true);
+  if (dyn + collide_static_lds(1024) > kLdsBytes && mode != ACC_SPLIT) return false;
   if (4 * (dyn + collide_static_lds(256)) <= kLdsBytes) block = 256;
-  else if (2 * (dyn + collide_static_lds(512)) <= kLdsBytes) block = 512;
+  else if (2 * (dyn + collide_static_lds(512)) <= kLdsBytes || mode == ACC_SPLIT) block = 512;
   else block = 1024;
   blocks[0] = block;
   blocks[1] = block == 1024 ? 512 : block;
@@ -166,14 +172,19 @@ const void* collide_adj_fn(int block, bool table, bool fixed) {
   return nullptr;
 }
 
-const void* collide_fn(int block, bool table, bool fixed) {
-#define BOLTZ_COLLIDE_FN(B)                                                                      \
-  if (block == B)                                                                              \
-    return table ? (fixed ? (const void*)collide_kernel<B, true, true> : (const void*)collide_kernel<B, true, false>) \
-                 : (fixed ? (const void*)collide_kernel<B, false, true> : (const void*)collide_kernel<B, false, false>);
-  BOLTZ_COLLIDE_FN(256)
-  BOLTZ_COLLIDE_FN(512)
-  BOLTZ_COLLIDE_FN(1024)
+const void* collide_fn(int block, bool table, int mode) {
+#define BOLTZ_COLLIDE_FN(B, M)                                                                                 \
+  if (block == B && mode == M)                                                                                 \
+    return table ? (const void*)collide_kernel<B, true, M> : (const void*)collide_kernel<B, false, M>;
+  BOLTZ_COLLIDE_FN(256, ACC_FIXED)
+  BOLTZ_COLLIDE_FN(512, ACC_FIXED)
+  BOLTZ_COLLIDE_FN(1024, ACC_FIXED)
+  BOLTZ_COLLIDE_FN(256, ACC_SPLIT)
+  BOLTZ_COLLIDE_FN(512, ACC_SPLIT)
+  BOLTZ_COLLIDE_FN(1024, ACC_SPLIT)
+  BOLTZ_COLLIDE_FN(256, ACC_CAS)
+  BOLTZ_COLLIDE_FN(512, ACC_CAS)
+  BOLTZ_COLLIDE_FN(1024, ACC_CAS)
 #undef BOLTZ_COLLIDE_FN
   return nullptr;
 }
@@ -215,9 +226,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: invalid scalar parameter");
   const int64_t nvt = (int64_t)p->nv[0] * p->nv[1] * p->nv[2];
   const int nsum = p->nv[0] + p->nv[1] + p->nv[2];
-  bool cfixed = true;
+  int cmode = ACC_FIXED;
   int cblock[2] = {256, 256};
-  if (nvt > (1 << 20) || !pick_collide((int)nvt, nsum, cfixed, cblock))
+  if (nvt > (1 << 20) || !pick_collide((int)nvt, nsum, cmode, cblock))
     return fail(nullptr, BOLTZ_EUNSUPPORTED,
                 "boltz_create: the per-cell h and increment tiles of this velocity grid exceed the 160 KB LDS");
   if ((int64_t)p->nx * p->ny * nvt >= ((int64_t)1 << 40))
@@ -445,12 +456,12 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->adj_lam = with_adj ? reinterpret_cast<double*>(base + o_adj_lam) : nullptr;
   c->collide_block[0] = cblock[0];
   c->collide_block[1] = cblock[1];
-  c->collide_fixed = cfixed;
+  c->collide_mode = cmode;
   int ncu = 0;
   hipError_t ea = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
-    const void* fn = collide_fn(cblock[t], t == 1, cfixed);
-    c->collide_lds[t] = CollideLDS::bytes(c->nv, nsum, cfixed, t == 0);
+    const void* fn = collide_fn(cblock[t], t == 1, cmode);
+    c->collide_lds[t] = CollideLDS::bytes(c->nv, nsum, cmode, t == 0);
     ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->collide_lds[t]);
     int per_cu = 0;
     if (ea == hipSuccess)
@@ -573,26 +584,27 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream_kernel launch");
 }
 
-extern "C++" template <int B>
-static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
+extern "C++" template <int B, int M>
+static void launch_collide_m(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
                              double* defect, hipStream_t st) {
   const int t = table ? 1 : 0;
   const dim3 grid((unsigned)c->collide_grid[t]);
   const size_t lds = c->collide_lds[t];
-  if (table) {
-    if (c->collide_fixed)
-      hipLaunchKernelGGL((collide_kernel<B, true, true>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
-                         c->tidx, c->tcoef);
-    else
-      hipLaunchKernelGGL((collide_kernel<B, true, false>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
-                         c->tidx, c->tcoef);
-  } else {
-    if (c->collide_fixed)
-      hipLaunchKernelGGL((collide_kernel<B, false, true>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags,
-                         defect, c->tidx, c->tcoef);
-    else
-      hipLaunchKernelGGL((collide_kernel<B, false, false>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags,
-                         defect, c->tidx, c->tcoef);
+  if (table)
+    hipLaunchKernelGGL((collide_kernel<B, true, M>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
+                       c->tidx, c->tcoef);
+  else
+    hipLaunchKernelGGL((collide_kernel<B, false, M>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
+                       c->tidx, c->tcoef);
+}
+
+extern "C++" template <int B>
+static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
+                             double* defect, hipStream_t st) {
+  switch (c->collide_mode) {
+    case ACC_FIXED: launch_collide_m<B, ACC_FIXED>(c, table, hs, hout, s32, flags, defect, st); break;
+    case ACC_SPLIT: launch_collide_m<B, ACC_SPLIT>(c, table, hs, hout, s32, flags, defect, st); break;
+    default: launch_collide_m<B, ACC_CAS>(c, table, hs, hout, s32, flags, defect, st); break;
   }
 }
 
@@ -988,7 +1000,7 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     C.hoff = off;
     C.tidx = c->tidx;
     C.tcoef = c->tcoef;
-    C.fixed = c->collide_fixed ? 1 : 0;
+    C.mode = c->collide_mode;
     b->hoff.push_back(off);
     off += c->ncells * (int64_t)c->nv;
     const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
@@ -1009,10 +1021,12 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     }
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     const bool table = c->ngroups > 0;
-    lds_max = std::max(lds_max, CollideLDS::bytes(c->nv, nsum, c->collide_fixed, !table));
+    lds_max = std::max(lds_max, CollideLDS::bytes(c->nv, nsum, c->collide_mode, !table));
     if (table) slds_max = std::max(slds_max, TablesLDS::bytes(nsum, true));
     // relative cost of one cell: pair loop (drawn pairs cost more) plus the node phases
-    cost[i] = (double)c->p.n_pairs * (table ? 1.0 : 3.0) * (c->collide_fixed ? 1.0 : 4.0) + 40.0 * c->nv;
+    cost[i] = (double)c->p.n_pairs * (table ? 1.0 : 3.0) *
+                  (c->collide_mode == ACC_FIXED ? 1.0 : (c->collide_mode == ACC_SPLIT ? 1.3 : 4.0)) +
+              40.0 * c->nv;
     b->pair_cells += c->ncells * c->p.n_pairs;
   }
   b->nodes = off;

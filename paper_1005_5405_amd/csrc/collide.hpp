@@ -296,19 +296,35 @@ __device__ __forceinline__ bool solve5(const double* S, const double* r, double*
 }
 
 // ------------------------------------------------------------ collision --
-// Dynamic LDS of the collide kernel: the h^s tile (FP32), the increment
-// accumulators (64-bit fixed point plus an FP32 array for large values, or
-// FP32 alone when those do not fit), then the tables.  The FP32 array comes
-// first and holds h^c after the pair loop.
+// Accumulation of the increments of h in LDS:
+//   ACC_FIXED  64-bit fixed point for every node plus an FP32 array for large
+//              values (16 B/node with the h^s tile)
+//   ACC_SPLIT  the same for half of the nodes at a time: the pairs are read
+//              twice, each pass keeping the increments of one half of the
+//              velocity index (10 B/node; grids too large for ACC_FIXED)
+//   ACC_CAS    FP32 compare-and-swap for every node (8 B/node)
+enum : int { ACC_CAS = 0, ACC_FIXED = 1, ACC_SPLIT = 2 };
+
+// Dynamic LDS of the collide kernel: the h^s tile (FP32), the accumulators,
+// then the tables.  The region after the tile holds h^c after the pair pass
+// (ACC_CAS, ACC_FIXED: the FP32 array, which comes first).
 struct CollideLDS {
   static __host__ __device__ size_t tile(int nv) { return ((size_t)nv * 4 + 15) & ~(size_t)15; }
-  static __host__ __device__ size_t acc(int nv, bool fixed) {
-    return tile(nv) + (fixed ? (((size_t)nv * 8 + 15) & ~(size_t)15) : 0);
+  static __host__ __device__ int half(int nv) { return (nv + 1) / 2; }
+  // 64-bit accumulators of ACC_SPLIT (then its FP32 array)
+  static __host__ __device__ size_t split64(int nv) { return ((size_t)half(nv) * 8 + 15) & ~(size_t)15; }
+  static __host__ __device__ size_t acc(int nv, int mode) {
+    if (mode == ACC_SPLIT) return split64(nv) + (((size_t)half(nv) * 4 + 15) & ~(size_t)15);
+    return tile(nv) + (mode == ACC_FIXED ? (((size_t)nv * 8 + 15) & ~(size_t)15) : 0);
   }
-  static __host__ __device__ size_t bytes(int nv, int ns, bool fixed, bool sampler) {
-    return tile(nv) + acc(nv, fixed) + TablesLDS::bytes(ns, sampler);
+  static __host__ __device__ size_t bytes(int nv, int ns, int mode, bool sampler) {
+    return tile(nv) + acc(nv, mode) + TablesLDS::bytes(ns, sampler);
   }
 };
+
+// nodes per thread of one ACC_SPLIT half kept in registers between passes
+template <int BLOCK>
+constexpr int split_regs() { return 8192 / BLOCK; }
 
 // float4 registers per thread holding the next cell's h^s tile
 constexpr int kPrefetch = 4;
@@ -337,10 +353,18 @@ struct Prefetch {
 
 // Scatter of one sample: +k_as g at a*, +k_bs g at b*, -k_a g at a, -k_b g
 // at b, in units of h (the increment Delta N / w of Eq. collision_step).
-template <bool FIXED>
-__device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, int a, int b, int as, int bs,
-                                        double kas, double kbs, double ka, double kb, float g) {
-  if (FIXED) {
+// accf: the FP32 accumulators (ACC_CAS) or the FP32 array of large values.
+// ACC_SPLIT: only the nodes lo .. lo + n - 1, at index node - lo.
+template <int MODE>
+__device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, int lo, unsigned n, int a, int b,
+                                        int as, int bs, double kas, double kbs, double ka, double kb, float g) {
+  if (MODE == ACC_SPLIT) {
+    const double gd = (double)g;
+    if ((unsigned)(as - lo) < n) lds_add_hybrid(acc64, accf, as - lo, kas, gd);
+    if ((unsigned)(bs - lo) < n) lds_add_hybrid(acc64, accf, bs - lo, kbs, gd);
+    if ((unsigned)(a - lo) < n) lds_add_hybrid(acc64, accf, a - lo, -ka, gd);
+    if ((unsigned)(b - lo) < n) lds_add_hybrid(acc64, accf, b - lo, -kb, gd);
+  } else if (MODE == ACC_FIXED) {
     const double gd = (double)g;
     lds_add_hybrid(acc64, accf, as, kas, gd);
     lds_add_hybrid(acc64, accf, bs, kbs, gd);
@@ -360,10 +384,11 @@ __device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, 
 // the accumulators.  TABLE: the pairs are the records of sample_kernel for
 // the cell's group, four per thread and pass so that their loads and
 // gathers are in flight together; else they are drawn here.
-template <int BLOCK, bool TABLE, bool FIXED>
+template <int BLOCK, bool TABLE, int MODE>
 __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, const float* hs, float* accf,
                                           unsigned long long* acc64, uint32_t group, uint32_t step,
-                                          const uint2* __restrict__ tidx, const float4* __restrict__ tcoef) {
+                                          const uint2* __restrict__ tidx, const float4* __restrict__ tcoef,
+                                          int lo = 0, unsigned n = 0) {
   const int tid = threadIdx.x;
   const float epsf = (float)P.eps;
   const uint32_t nt = (uint32_t)P.n_pairs;
@@ -389,7 +414,7 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
         const float g = (ha[u] + hb[u]) + (epsf * ha[u]) * hb[u];
-        scatter<FIXED>(accf, acc64, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
+        scatter<MODE>(accf, acc64, lo, n, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
                        (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
       }
     }
@@ -399,7 +424,8 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
       const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
       const float ha0 = hs[a0], hb0 = hs[b0];
       const float g0 = (ha0 + hb0) + (epsf * ha0) * hb0;
-      scatter<FIXED>(accf, acc64, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w, g0);
+      scatter<MODE>(accf, acc64, lo, n, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w,
+                    g0);
     }
   } else {
     for (uint32_t m = tid; m < nt; m += BLOCK) {
@@ -407,7 +433,7 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
       if (p.as >= 0) {
         const float ha = hs[p.a], hb = hs[p.b];
         const float g = (ha + hb) + (epsf * ha) * hb;
-        scatter<FIXED>(accf, acc64, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+        scatter<MODE>(accf, acc64, lo, n, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
       }
     }
   }
@@ -490,7 +516,7 @@ __device__ __forceinline__ void correction_sums(const TablesLDS& T, const float*
 // over (the persistent kernel requests the next tile there); defect: the
 // cell's five values or null.  Ends with a barrier, so the LDS can be
 // refilled.
-template <int BLOCK, bool TABLE, bool FIXED, class Next>
+template <int BLOCK, bool TABLE, int MODE, class Next>
 __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T, float* hs, float* accf,
                                              unsigned long long* acc64, double* red, double* tot, uint32_t group,
                                              uint32_t step, uint32_t flags, float* dst, double* defect,
@@ -510,16 +536,54 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
   const bool correct = !(flags & 1u);
   const double eps = P.eps;
   // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
-  gain_loss<BLOCK, TABLE, FIXED>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
-  __syncthreads();
-  next();
-  // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator
+  if (MODE == ACC_SPLIT) {
+    // two passes over the samples, one half of the nodes each; h^c of the
+    // halves waits in registers, then goes over the accumulators
+    constexpr int R = split_regs<BLOCK>();
+    const int h2 = CollideLDS::half(nv);
+    float* ovf = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(acc64) + CollideLDS::split64(nv));
+    float hc0[R], hc1[R];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int lo = p * h2, n = min(nv - lo, h2);
+      if (p == 1) {
+        uint4* z = reinterpret_cast<uint4*>(acc64);
+        const int nz = (int)(CollideLDS::acc(nv, ACC_SPLIT) / 16);
+        for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
+        __syncthreads();
+      }
+      gain_loss<BLOCK, TABLE, ACC_SPLIT>(P, T, hs, ovf, acc64, group, step, tidx, tcoef, lo, (unsigned)n);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int i = tid + k * BLOCK;
+        float v = 0.0f;
+        if (i < n) v = (float)((double)hs[lo + i] + ((double)ovf[i] + from_fixed(acc64[i])));
+        if (p == 0) hc0[k] = v;
+        else hc1[k] = v;
+      }
+      __syncthreads();
+    }
+    next();
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int i = tid + k * BLOCK;
+      if (i < h2) accf[i] = hc0[k];
+      if (i < nv - h2) accf[h2 + i] = hc1[k];
+    }
+    __syncthreads();
+  } else {
+    gain_loss<BLOCK, TABLE, MODE>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
+    __syncthreads();
+    next();
+    // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator
 #pragma unroll NU
-  for (int j = tid; j < nv; j += BLOCK) {
-    const float hsj = hs[j];
-    double dh = (double)accf[j];
-    if (FIXED) dh += from_fixed(acc64[j]);
-    accf[j] = (float)((double)hsj + dh);
+    for (int j = tid; j < nv; j += BLOCK) {
+      const float hsj = hs[j];
+      double dh = (double)accf[j];
+      if (MODE == ACC_FIXED) dh += from_fixed(acc64[j]);
+      accf[j] = (float)((double)hsj + dh);
+    }
   }
   if (correct) {
     __syncthreads();
@@ -586,9 +650,9 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
 // Persistent workgroups: workgroup b collides cells b, b + gridDim.x, ...;
 // the h^s tile of the next cell is loaded into registers while the node
 // phases of the current one run.  TABLE: the pairs come from the records of
-// sample_kernel (cells of one group share them).  FIXED: 64-bit fixed-point
-// accumulation (else FP32 compare-and-swap).  h_s may equal h_out.
-template <int BLOCK, bool TABLE, bool FIXED>
+// sample_kernel (cells of one group share them).  MODE: accumulation of the
+// increments (ACC_FIXED, ACC_SPLIT, ACC_CAS).  h_s may equal h_out.
+template <int BLOCK, bool TABLE, int MODE>
 __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* hs_g, float* hout_g, uint32_t step,
                                                         uint32_t flags, double* __restrict__ defect,
                                                         const uint2* __restrict__ tidx,
@@ -601,9 +665,10 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   const int tid = threadIdx.x;
   float* hs = reinterpret_cast<float*>(dsm);
   float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
-  unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(dsm + 2 * CollideLDS::tile(nv));
+  unsigned long long* acc64 =
+      reinterpret_cast<unsigned long long*>(dsm + (MODE == ACC_SPLIT ? 1 : 2) * CollideLDS::tile(nv));
   TablesLDS T;
-  load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, FIXED), !TABLE, T);
+  load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, MODE), !TABLE, T);
   const int nv4 = nv >> 2;
   const bool vec = ((nv & 3) == 0) && nv4 <= kPrefetch * BLOCK;
   Prefetch pre;
@@ -619,7 +684,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
     }
     {
       uint4* z = reinterpret_cast<uint4*>(accf);
-      const int nz = (int)(CollideLDS::acc(nv, FIXED) / 16);
+      const int nz = (int)(CollideLDS::acc(nv, MODE) / 16);
       for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
@@ -628,7 +693,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
     // vector-memory waits retire in issue order, so loads issued before the
     // pair loop would stall its first record loads; the node phases wait on
     // no vector load.
-    collide_body<BLOCK, TABLE, FIXED>(P, T, hs, accf, acc64, red, tot, group, step, flags, hout_g + cell * nv,
+    collide_body<BLOCK, TABLE, MODE>(P, T, hs, accf, acc64, red, tot, group, step, flags, hout_g + cell * nv,
                                       defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
                                         const int64_t next = cell + gridDim.x;
                                         if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
@@ -642,7 +707,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
 // every workgroup receives about the same number of pair-cells; the
 // problem's tables are reloaded into LDS when it changes from one item to
 // the next.  The dynamic LDS is that of the largest problem; each problem
-// uses its own layout (fixed-point or FP32 accumulators, drawn or shared
+// uses its own layout (accumulation mode, drawn or shared
 // samples).  The step number is read from the device (graph replays).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __restrict__ cavs,
@@ -661,12 +726,14 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
     const BatchCav& C = cavs[it.x];
     const Params& P = C.P;
     const int nv = P.nv;
-    const bool fixed = C.fixed != 0, table = P.sample_group != 1;
+    const int mode = C.mode;
+    const bool table = P.sample_group != 1;
     float* hs = reinterpret_cast<float*>(dsm);
     float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
-    unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(dsm + 2 * CollideLDS::tile(nv));
+    unsigned long long* acc64 =
+        reinterpret_cast<unsigned long long*>(dsm + (mode == ACC_SPLIT ? 1 : 2) * CollideLDS::tile(nv));
     if (it.x != prev) {
-      load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, fixed), !table, T);
+      load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, mode), !table, T);
       prev = it.x;
     }
     const int64_t cell = it.y;
@@ -680,28 +747,25 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
     }
     {
       uint4* z = reinterpret_cast<uint4*>(accf);
-      const int nz = (int)(CollideLDS::acc(nv, fixed) / 16);
+      const int nz = (int)(CollideLDS::acc(nv, mode) / 16);
       for (int k = tid; k < nz; k += BLOCK) z[k] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
     const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
     float* dst = hout + C.hoff + cell * nv;
     auto none = []() {};
+#define BOLTZ_BODY(TB, MD)                                                                                      \
+  collide_body<BLOCK, TB, MD>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx, C.tcoef, none)
     if (table) {
-      if (fixed)
-        collide_body<BLOCK, true, true>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
-                                        C.tcoef, none);
-      else
-        collide_body<BLOCK, true, false>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
-                                         C.tcoef, none);
+      if (mode == ACC_FIXED) BOLTZ_BODY(true, ACC_FIXED);
+      else if (mode == ACC_SPLIT) BOLTZ_BODY(true, ACC_SPLIT);
+      else BOLTZ_BODY(true, ACC_CAS);
     } else {
-      if (fixed)
-        collide_body<BLOCK, false, true>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
-                                         C.tcoef, none);
-      else
-        collide_body<BLOCK, false, false>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx,
-                                          C.tcoef, none);
+      if (mode == ACC_FIXED) BOLTZ_BODY(false, ACC_FIXED);
+      else if (mode == ACC_SPLIT) BOLTZ_BODY(false, ACC_SPLIT);
+      else BOLTZ_BODY(false, ACC_CAS);
     }
+#undef BOLTZ_BODY
   }
 }
 

@@ -64,7 +64,7 @@ struct BatchCav {
   int64_t hoff;    // first element of the problem's h in the batch buffers
   uint2* tidx;     // shared-sample records (G != 1), else null
   float4* tcoef;
-  int fixed;       // 64-bit fixed-point collide accumulators
+  int mode;        // accumulation of the collide increments (ACC_*)
   int pad;
 };
 
