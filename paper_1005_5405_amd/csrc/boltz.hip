@@ -556,16 +556,15 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
   if (c->n[2] % 4 == 0) {
     // velocity groups of four share (jx, jy): vector kernel
     const int tiles_x = (c->p.nx + kTX4 - 1) / kTX4, tiles_y = (c->p.ny + kTY4 - 1) / kTY4;
-    const int nchunks = (c->nv + kJ4 - 1) / kJ4;
-    const long long total = (long long)tiles_x * tiles_y * nchunks;
+    const long long total = stream4_units(c->p.nx, c->p.ny, c->nv);
     const int per_xcd = (int)((total + 7) / 8);
     const dim3 grid((unsigned)(8 * (long long)per_xcd));
     if (c->p.order == 2)
       hipLaunchKernelGGL(stream4_kernel<2>, grid, dim3(kStream4Block), 0, st, c->P, hin, hout, tiles_x, tiles_y,
-                         nchunks, per_xcd);
+                         (int)total, per_xcd);
     else
       hipLaunchKernelGGL(stream4_kernel<1>, grid, dim3(kStream4Block), 0, st, c->P, hin, hout, tiles_x, tiles_y,
-                         nchunks, per_xcd);
+                         (int)total, per_xcd);
   } else {
     const int tiles_x = (c->p.nx + kTX - 1) / kTX, tiles_y = (c->p.ny + kTY - 1) / kTY;
     const int nchunks = (c->nv + kJ - 1) / kJ;
@@ -1007,7 +1006,7 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     const int nx = c->p.nx, ny = c->p.ny;
     const int nf0 = !cavity ? 0 : (b->order == 2 ? 2 * ny : 2 * (nx + ny));
     const int nf1 = (cavity && b->order == 2) ? 2 * nx : 0;
-    const int64_t units = (int64_t)((nx + kTX4 - 1) / kTX4) * ((ny + kTY4 - 1) / kTY4) * ((c->nv + kJ4 - 1) / kJ4);
+    const int64_t units = stream4_units(nx, ny, c->nv);
     const int64_t sblocks = (c->ngroups > 0 && c->p.n_pairs > 0) ? c->ngroups * ((c->p.n_pairs + 255) / 256) : 0;
     const int64_t nxt[4] = {(int64_t)st[0][i] + nf0, (int64_t)st[1][i] + nf1, (int64_t)st[2][i] + units,
                             (int64_t)st[3][i] + sblocks};

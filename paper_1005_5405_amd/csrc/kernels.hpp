@@ -542,6 +542,25 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
 // sweep from that register window (order 2), or the unsplit first-order
 // stencil (order 1).  Same arithmetic per element as stream_kernel.
 constexpr int kTX4 = 16, kTY4 = 8, kJ4 = 32, kStream4Block = kTX4 * (kJ4 / 4);
+// Consecutive velocity chunks of one tile that are adjacent work units (at
+// most kChunkGroup, at most the problem's chunk count): each cell is then
+// read in runs of up to 2 KB rather than 128 B, about 10% faster on the
+// 64x64 cavity than one chunk per group.
+constexpr int kChunkGroup = 16;
+
+__host__ __device__ inline int stream4_group(int nv) {
+  const int nchunks = (nv + kJ4 - 1) / kJ4;
+  return nchunks < kChunkGroup ? nchunks : kChunkGroup;
+}
+
+// work units of one problem: tiles x velocity chunks, rounded up to whole
+// chunk groups
+__host__ __device__ inline int64_t stream4_units(int nx, int ny, int nv) {
+  const int64_t tiles = (int64_t)((nx + kTX4 - 1) / kTX4) * ((ny + kTY4 - 1) / kTY4);
+  const int cg = stream4_group(nv);
+  const int64_t groups = ((nv + kJ4 - 1) / kJ4 + cg - 1) / cg;
+  return tiles * groups * cg;
+}
 
 __device__ __forceinline__ float4 ghost4(double nwv, const double* R, double inv_eps) {
   return make_float4(ghost_value(nwv, R[0], inv_eps), ghost_value(nwv, R[1], inv_eps),
@@ -560,7 +579,10 @@ struct Stream4LDS {
 };
 
 // Work unit `unit` (a chunk of 32 velocities of one 16 x 8 tile of cells)
-// of one problem; tiles_x = ceil(nx / 16), tiles_y = ceil(ny / 8).
+// of one problem; tiles_x = ceil(nx / 16), tiles_y = ceil(ny / 8).  Units
+// run chunk-group-major over the tiles, so that neighbouring tiles (which
+// share halos) follow each other; within a group, stream4_group(nv)
+// consecutive chunks of one tile.
 template <int ORDER>
 __device__ __forceinline__ void stream4_unit(const Params& P, const float* __restrict__ hin, float* __restrict__ hout,
                                              int tiles_x, int tiles_y, int unit, float4* A4) {
@@ -568,7 +590,11 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
   constexpr int AX = kTX4 + 2 * H, AY = kTY4 + 2 * H;
   constexpr int Q = kJ4 / 4;
   const int ntiles = tiles_x * tiles_y;
-  const int chunk = unit / ntiles, tile = unit % ntiles;
+  const int gsz = stream4_group(P.nv);
+  const int per_group = ntiles * gsz;
+  const int cg = unit / per_group, rem = unit - (unit / per_group) * per_group;
+  const int tile = rem / gsz, chunk = cg * gsz + (rem - (rem / gsz) * gsz);
+  if (chunk * kJ4 >= P.nv) return;  // padding unit of the last group
   const int ix0 = (tile % tiles_x) * kTX4, iy0 = (tile / tiles_x) * kTY4;
   const int j0 = chunk * kJ4;
   const int nx = P.nx, ny = P.ny, nv = P.nv;
@@ -690,11 +716,11 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
 template <int ORDER>
 __global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const float* __restrict__ hin,
                                                                 float* __restrict__ hout, int tiles_x,
-                                                                int tiles_y, int nchunks, int per_xcd) {
+                                                                int tiles_y, int nunits, int per_xcd) {
   __shared__ Stream4LDS<ORDER> L;
   // XCD-aware order: contiguous (chunk, tile) ranges per XCD
   const int unit = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (unit >= tiles_x * tiles_y * nchunks) return;
+  if (unit >= nunits) return;
   stream4_unit<ORDER>(P, hin, hout, tiles_x, tiles_y, unit, L.a);
 }
 
