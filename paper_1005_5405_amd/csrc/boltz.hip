@@ -121,9 +121,11 @@ size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof
 // fixed-point accumulators for every node when they fit next to the h tile
 // and tables, else for half of the nodes per pass, else FP32; the block size
 // gives about 1024 resident threads per CU.  block[0]: pairs drawn in the
-// kernel; block[1]: pairs read from the shared table.  The split mode keeps
-// 8192 / block nodes per thread in registers between its passes, and uses
-// 512 threads.
+// kernel; block[1]: pairs read from the shared table, which runs faster with
+// 512 threads (and unrolled node loops) than with 1024 when only one
+// workgroup fits per CU (346 vs 354 us on the 64x64 cavity).  The split mode
+// keeps 8192 / block nodes per thread in registers between its passes, and
+// uses 512 threads.
 bool pick_collide(int nv, int ns, int& mode, int (&blocks)[2]) {
   int block = 256;
   if (CollideLDS::bytes(nv, ns, ACC_FIXED, true) + collide_static_lds(1024) <= kLdsBytes) mode = ACC_FIXED;
@@ -137,7 +139,7 @@ bool pick_collide(int nv, int ns, int& mode, int (&blocks)[2]) {
   else if (2 * (dyn + collide_static_lds(512)) <= kLdsBytes || mode == ACC_SPLIT) block = 512;
   else block = 1024;
   blocks[0] = block;
-  blocks[1] = block;
+  blocks[1] = block == 1024 ? 512 : block;
   // tuning override: BOLTZ_COLLIDE_BLOCK = 256 | 512 | 1024 (both variants)
   if (const char* e = std::getenv("BOLTZ_COLLIDE_BLOCK")) {
     const int b = std::atoi(e);

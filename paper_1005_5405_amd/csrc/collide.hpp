@@ -444,9 +444,11 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 //   M = M0 + eps sum_j w_j h^c_j psi_j psi_j^T  (M0 = sum w psi psi^T),
 //   r = -eps sum_j w_j psi_j (h^c_j - h^s_j),  psi = (1, v, |v|^2),
 // from the z moments S_p = sum_z omega_z h^c v_z^p (p <= 4) and
-// R_p = sum_z omega_z (h^c - h^s) v_z^p (p <= 2) of the row.  acc[0..15)
-// are the sums of h^c psi_k psi_l (packed k <= l), acc[15..20) those of
-// (h^c - h^s) psi_k, per thread.
+// R_p = sum_z omega_z (h^c - h^s) v_z^p (p <= 2) of the row, accumulated
+// with one FMA per moment and node.  (Cutting the rows into chunks so that
+// more threads share them was measured slower: the strided chunk reads add
+// LDS conflicts.)  acc[0..15) are the sums of h^c psi_k psi_l (packed
+// k <= l), acc[15..20) those of (h^c - h^s) psi_k, per thread.
 template <int BLOCK, int NU>
 __device__ __forceinline__ void correction_sums(const TablesLDS& T, const float* hs, const float* hc_t, int n0,
                                                 int n1, int n2, double (&acc)[20]) {
@@ -466,22 +468,17 @@ __device__ __forceinline__ void correction_sums(const TablesLDS& T, const float*
 #pragma unroll NU
     for (int jz = 0; jz < n2; ++jz) {
       const double hc = (double)hcr[jz], oz = omz[jz], z = vz[jz];
-      double u = oz * hc;
+      const double z2 = z * z, z3 = z2 * z, z4 = z2 * z2;
+      const double u = oz * hc;
       S0 += u;
-      u *= z;
-      S1 += u;
-      u *= z;
-      S2 += u;
-      u *= z;
-      S3 += u;
-      u *= z;
-      S4 += u;
-      double d = oz * (hc - (double)hsr[jz]);
+      S1 = fma(u, z, S1);
+      S2 = fma(u, z2, S2);
+      S3 = fma(u, z3, S3);
+      S4 = fma(u, z4, S4);
+      const double d = oz * (hc - (double)hsr[jz]);
       R0 += d;
-      d *= z;
-      R1 += d;
-      d *= z;
-      R2 += d;
+      R1 = fma(d, z, R1);
+      R2 = fma(d, z2, R2);
     }
     const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
     const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
