@@ -65,6 +65,8 @@ struct boltz_ctx {
   double* gpart = nullptr;      // per-face wall-parameter partials [nfaces][2]
   uint2* tidx = nullptr;        // ngroups * n_pairs pair indices (G != 1)
   float4* tcoef = nullptr;      // ngroups * n_pairs pair coefficients
+  uint2* sidx = nullptr;        // the sampler's output (ACC_SPLIT: sorted into tidx, tcoef)
+  float4* scoef = nullptr;
   std::string err;
 };
 
@@ -378,6 +380,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t o_gpart = off; off = align256(off + (size_t)nfaces * 2 * 8);
   const size_t o_tidx = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(uint2));
   const size_t o_tcoef = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(float4));
+  const size_t nsort = (cmode == ACC_SPLIT) ? (size_t)ngroups * (size_t)p->n_pairs : 0;
+  const size_t o_sidx = off; off = align256(off + nsort * sizeof(uint2));
+  const size_t o_scoef = off; off = align256(off + nsort * sizeof(float4));
   const bool with_adj = (p->flags & BOLTZ_WITH_ADJOINT) != 0;
   const size_t nodes = (size_t)c->ncells * (size_t)c->nv;
   const size_t o_adj_hs = off; off = align256(off + (with_adj ? nodes * 4 : 0));
@@ -451,6 +456,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->ngroups = ngroups;
   c->tidx = ngroups ? reinterpret_cast<uint2*>(base + o_tidx) : nullptr;
   c->tcoef = ngroups ? reinterpret_cast<float4*>(base + o_tcoef) : nullptr;
+  c->sidx = nsort ? reinterpret_cast<uint2*>(base + o_sidx) : c->tidx;
+  c->scoef = nsort ? reinterpret_cast<float4*>(base + o_scoef) : c->tcoef;
   c->lnw = reinterpret_cast<double*>(base + o_lnw);
   c->gpart = reinterpret_cast<double*>(base + o_gpart);
   c->adj_hs = with_adj ? reinterpret_cast<float*>(base + o_adj_hs) : nullptr;
@@ -608,13 +615,17 @@ static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* h
   }
 }
 
-// Shared-sample mode: the pair records of every group for this step.
+// Shared-sample mode: the pair records of every group for this step
+// (ACC_SPLIT: then sorted by the velocity half of their targets).
 static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st) {
   if (c->ngroups > 0 && c->p.n_pairs > 0) {
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     const dim3 grid((unsigned)((c->p.n_pairs + 255) / 256), (unsigned)c->ngroups);
-    hipLaunchKernelGGL(sample_kernel, grid, dim3(256), TablesLDS::bytes(nsum, true), st, c->P, s32, c->tidx,
-                       c->tcoef);
+    hipLaunchKernelGGL(sample_kernel, grid, dim3(256), TablesLDS::bytes(nsum, true), st, c->P, s32, c->sidx,
+                       c->scoef);
+    if (c->sidx != c->tidx)
+      hipLaunchKernelGGL(split_sort_kernel, dim3((unsigned)c->ngroups), dim3(kSortBlock), 0, st, c->sidx, c->scoef,
+                         c->tidx, c->tcoef, (int64_t)c->p.n_pairs, (unsigned)CollideLDS::half(c->nv));
   }
 }
 
@@ -913,8 +924,10 @@ struct boltz_batch {
   void* dmem = nullptr;
   size_t dbytes = 0;
   BatchCav* cavs = nullptr;
-  int* start[4] = {nullptr, nullptr, nullptr, nullptr};  // x faces (all faces, order 1), y faces, stream units, sample blocks
-  int total[4] = {0, 0, 0, 0};
+  // first unit of each problem in the batched launches: x faces (all faces
+  // for order 1), y faces, stream units, sample blocks, sort workgroups
+  int* start[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int total[5] = {0, 0, 0, 0, 0};
   int2* items = nullptr;
   int nitems = 0;
   uint32_t* step_dev = nullptr;
@@ -987,8 +1000,8 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
   }
   // ---- descriptors, launch ranges, work items
   std::vector<BatchCav> cavs(count);
-  std::vector<int> st[4];
-  for (int k = 0; k < 4; ++k) st[k].assign(count + 1, 0);
+  std::vector<int> st[5];
+  for (int k = 0; k < 5; ++k) st[k].assign(count + 1, 0);
   std::vector<double> cost(count);
   int64_t off = 0;
   size_t lds_max = 0, slds_max = 0;
@@ -1000,6 +1013,8 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     C.hoff = off;
     C.tidx = c->tidx;
     C.tcoef = c->tcoef;
+    C.sidx = c->sidx;
+    C.scoef = c->scoef;
     C.mode = c->collide_mode;
     b->hoff.push_back(off);
     off += c->ncells * (int64_t)c->nv;
@@ -1010,9 +1025,10 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     const int nf1 = (cavity && b->order == 2) ? 2 * nx : 0;
     const int64_t units = stream4_units(nx, ny, c->nv);
     const int64_t sblocks = (c->ngroups > 0 && c->p.n_pairs > 0) ? c->ngroups * ((c->p.n_pairs + 255) / 256) : 0;
-    const int64_t nxt[4] = {(int64_t)st[0][i] + nf0, (int64_t)st[1][i] + nf1, (int64_t)st[2][i] + units,
-                            (int64_t)st[3][i] + sblocks};
-    for (int k = 0; k < 4; ++k) {
+    const int64_t sorts = (c->sidx != c->tidx) ? c->ngroups : 0;
+    const int64_t nxt[5] = {(int64_t)st[0][i] + nf0, (int64_t)st[1][i] + nf1, (int64_t)st[2][i] + units,
+                            (int64_t)st[3][i] + sblocks, (int64_t)st[4][i] + sorts};
+    for (int k = 0; k < 5; ++k) {
       if (nxt[k] >= ((int64_t)1 << 31) / 8) {
         boltz_batch_destroy(b);
         return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batch too large for one launch per phase");
@@ -1030,7 +1046,7 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     b->pair_cells += c->ncells * c->p.n_pairs;
   }
   b->nodes = off;
-  for (int k = 0; k < 4; ++k) b->total[k] = st[k][count];
+  for (int k = 0; k < 5; ++k) b->total[k] = st[k][count];
   std::vector<int2> items;
   for (int i = 0; i < count; ++i)
     for (int64_t cell = 0; cell < b->ctx[i]->ncells; ++cell) items.push_back(make_int2(i, (int)cell));
@@ -1041,8 +1057,8 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
   // ---- one device allocation
   size_t o = 0;
   const size_t o_cavs = o; o = align256(o + sizeof(BatchCav) * count);
-  size_t o_st[4];
-  for (int k = 0; k < 4; ++k) { o_st[k] = o; o = align256(o + sizeof(int) * (count + 1)); }
+  size_t o_st[5];
+  for (int k = 0; k < 5; ++k) { o_st[k] = o; o = align256(o + sizeof(int) * (count + 1)); }
   const size_t o_items = o; o = align256(o + sizeof(int2) * items.size());
   const size_t o_step = o; o = align256(o + 4);
   hipError_t e = hipMalloc(&b->dmem, o);
@@ -1053,11 +1069,11 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
   b->dbytes = o;
   unsigned char* base = static_cast<unsigned char*>(b->dmem);
   b->cavs = reinterpret_cast<BatchCav*>(base + o_cavs);
-  for (int k = 0; k < 4; ++k) b->start[k] = reinterpret_cast<int*>(base + o_st[k]);
+  for (int k = 0; k < 5; ++k) b->start[k] = reinterpret_cast<int*>(base + o_st[k]);
   b->items = reinterpret_cast<int2*>(base + o_items);
   b->step_dev = reinterpret_cast<uint32_t*>(base + o_step);
   e = hipMemcpy(b->cavs, cavs.data(), sizeof(BatchCav) * count, hipMemcpyHostToDevice);
-  for (int k = 0; k < 4 && e == hipSuccess; ++k)
+  for (int k = 0; k < 5 && e == hipSuccess; ++k)
     e = hipMemcpy(b->start[k], st[k].data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->step_dev, 0, 4);
@@ -1166,6 +1182,9 @@ int boltz_batch_step(boltz_batch* b, const float* h_in, float* h_out, const bolt
   if (b->total[3] > 0)
     hipLaunchKernelGGL(sample_batch_kernel, dim3(b->total[3]), dim3(256), b->sample_lds, st, b->cavs, b->start[3],
                        b->count, b->step_dev);
+  if (b->total[4] > 0)
+    hipLaunchKernelGGL(split_sort_batch_kernel, dim3(b->total[4]), dim3(kSortBlock), 0, st, b->cavs, b->start[4],
+                       b->count);
   const int t = block_index(b->block);
   const dim3 grid((unsigned)b->grid[t]);
   switch (b->block) {

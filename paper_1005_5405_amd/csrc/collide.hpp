@@ -223,6 +223,55 @@ __global__ __launch_bounds__(256) void sample_kernel(Params P, uint32_t step, ui
   sample_record(P, T, step, blockIdx.y, i, tidx, tcoef);
 }
 
+// Pattern of a shared-sample record for the split accumulation: bit k is
+// set when its k-th target (a*, b*, a, b) lies in the upper half of the
+// velocity index.
+__device__ __forceinline__ unsigned split_pattern(uint2 id, unsigned h2) {
+  return ((id.y & 0xFFFFu) >= h2 ? 1u : 0u) | ((id.y >> 16) >= h2 ? 2u : 0u) | ((id.x & 0xFFFFu) >= h2 ? 4u : 0u) |
+         ((id.x >> 16) >= h2 ? 8u : 0u);
+}
+
+// Counting sort of the N_t records of one sample group by split_pattern
+// (one workgroup per group), from (sidx, scoef) into (tidx, tcoef): the
+// wavefronts of the collision then see records of one pattern, so each of
+// the two passes skips the adds (and records) whose targets all lie in the
+// other half.  The order within a pattern is that of the atomic cursors,
+// which the fixed-point sums do not depend on.
+constexpr int kSortBlock = 1024;
+
+__device__ __forceinline__ void split_sort_group(const uint2* __restrict__ sidx, const float4* __restrict__ scoef,
+                                                 uint2* __restrict__ tidx, float4* __restrict__ tcoef, int64_t nt,
+                                                 unsigned h2) {
+  __shared__ unsigned cnt[16];
+  if (threadIdx.x < 16) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int64_t m = threadIdx.x; m < nt; m += blockDim.x) atomicAdd(&cnt[split_pattern(sidx[m], h2)], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned run = 0;
+    for (int k = 0; k < 16; ++k) {
+      const unsigned c = cnt[k];
+      cnt[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int64_t m = threadIdx.x; m < nt; m += blockDim.x) {
+    const uint2 id = sidx[m];
+    const unsigned pos = atomicAdd(&cnt[split_pattern(id, h2)], 1u);
+    tidx[pos] = id;
+    tcoef[pos] = scoef[m];
+  }
+}
+
+__global__ __launch_bounds__(kSortBlock) void split_sort_kernel(const uint2* __restrict__ sidx,
+                                                                const float4* __restrict__ scoef,
+                                                                uint2* __restrict__ tidx, float4* __restrict__ tcoef,
+                                                                int64_t nt, unsigned h2) {
+  const int64_t g = blockIdx.x;
+  split_sort_group(sidx + g * nt, scoef + g * nt, tidx + g * nt, tcoef + g * nt, nt, h2);
+}
+
 // The records of every shared-sample problem of a batch in one launch:
 // start[c] = first block of problem c, which has ceil(N_t / 256) blocks per
 // group; the step number is read from the device.
@@ -243,7 +292,20 @@ __global__ __launch_bounds__(256) void sample_batch_kernel(const BatchCav* __res
   __syncthreads();
   const int64_t i = (int64_t)(local - (int)group * nb) * 256 + threadIdx.x;
   if (i >= P.n_pairs) return;
-  sample_record(P, T, *step_dev, group, i, C.tidx, C.tcoef);
+  sample_record(P, T, *step_dev, group, i, C.sidx, C.scoef);
+}
+
+// The split-pattern sort of every ACC_SPLIT shared-sample problem of a
+// batch: start[c] = first workgroup of problem c, one per sample group.
+__global__ __launch_bounds__(kSortBlock) void split_sort_batch_kernel(const BatchCav* __restrict__ cavs,
+                                                                      const int* __restrict__ start, int count) {
+  const int u = blockIdx.x;
+  if (u >= start[count]) return;
+  const int c = find_cav(start, count, u);
+  const BatchCav& C = cavs[c];
+  const int64_t nt = C.P.n_pairs, g = u - start[c];
+  split_sort_group(C.sidx + g * nt, C.scoef + g * nt, C.tidx + g * nt, C.tcoef + g * nt, nt,
+                   (unsigned)((C.P.nv + 1) / 2));
 }
 
 // ------------------------------------------------------------------- S5 --
@@ -359,17 +421,41 @@ template <int MODE>
 __device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, int lo, unsigned n, int a, int b,
                                         int as, int bs, double kas, double kbs, double ka, double kb, float g) {
   if (MODE == ACC_SPLIT) {
+    // each add is skipped by the whole wavefront when none of its lanes has
+    // that target in range (the shared records are sorted by target half)
     const double gd = (double)g;
-    if ((unsigned)(as - lo) < n) lds_add_hybrid(acc64, accf, as - lo, kas, gd);
-    if ((unsigned)(bs - lo) < n) lds_add_hybrid(acc64, accf, bs - lo, kbs, gd);
-    if ((unsigned)(a - lo) < n) lds_add_hybrid(acc64, accf, a - lo, -ka, gd);
-    if ((unsigned)(b - lo) < n) lds_add_hybrid(acc64, accf, b - lo, -kb, gd);
+    const bool ias = (unsigned)(as - lo) < n, ibs = (unsigned)(bs - lo) < n;
+    const bool ia = (unsigned)(a - lo) < n, ib = (unsigned)(b - lo) < n;
+    if (__any(ias)) {
+      if (ias) lds_add_hybrid(acc64, accf, as - lo, kas, gd);
+    }
+    if (__any(ibs)) {
+      if (ibs) lds_add_hybrid(acc64, accf, bs - lo, kbs, gd);
+    }
+    if (__any(ia)) {
+      if (ia) lds_add_hybrid(acc64, accf, a - lo, -ka, gd);
+    }
+    if (__any(ib)) {
+      if (ib) lds_add_hybrid(acc64, accf, b - lo, -kb, gd);
+    }
   } else if (MODE == ACC_FIXED) {
+    // the four values are formed first; when every lane has them all in the
+    // fixed-point window (all but about 2% of the wavefronts) the adds run
+    // without a branch per target
     const double gd = (double)g;
-    lds_add_hybrid(acc64, accf, as, kas, gd);
-    lds_add_hybrid(acc64, accf, bs, kbs, gd);
-    lds_add_hybrid(acc64, accf, a, -ka, gd);
-    lds_add_hybrid(acc64, accf, b, -kb, gd);
+    const long long d0 = fixed_of(kas, gd), d1 = fixed_of(kbs, gd), d2 = fixed_of(-ka, gd), d3 = fixed_of(-kb, gd);
+    const bool fast = in_fixed_window(d0) & in_fixed_window(d1) & in_fixed_window(d2) & in_fixed_window(d3);
+    if (__all(fast)) {
+      __hip_atomic_fetch_add(&acc64[as], (unsigned long long)d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&acc64[bs], (unsigned long long)d1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&acc64[a], (unsigned long long)d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&acc64[b], (unsigned long long)d3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      lds_add_fixed_or(acc64, accf, as, d0, kas, gd);
+      lds_add_fixed_or(acc64, accf, bs, d1, kbs, gd);
+      lds_add_fixed_or(acc64, accf, a, d2, -ka, gd);
+      lds_add_fixed_or(acc64, accf, b, d3, -kb, gd);
+    }
   } else {
     float* acc = accf;
     lds_add(&acc[as], (float)kas * g);
@@ -408,8 +494,21 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
       float ha[PU], hb[PU];
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
-        ha[u] = hs[id[u].x & 0xFFFFu];
-        hb[u] = hs[id[u].x >> 16];
+        if (MODE == ACC_SPLIT) {
+          // a record with no target in this half adds nothing: its gathers
+          // are skipped when that holds for the whole wavefront
+          const unsigned a = id[u].x & 0xFFFFu, b = id[u].x >> 16, as = id[u].y & 0xFFFFu, bs = id[u].y >> 16;
+          const bool live = ((a - (unsigned)lo) < n) | ((b - (unsigned)lo) < n) | ((as - (unsigned)lo) < n) |
+                            ((bs - (unsigned)lo) < n);
+          ha[u] = hb[u] = 0.0f;
+          if (__any(live)) {
+            ha[u] = hs[a];
+            hb[u] = hs[b];
+          }
+        } else {
+          ha[u] = hs[id[u].x & 0xFFFFu];
+          hb[u] = hs[id[u].x >> 16];
+        }
       }
 #pragma unroll
       for (int u = 0; u < PU; ++u) {

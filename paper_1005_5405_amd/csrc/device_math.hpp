@@ -159,6 +159,27 @@ __device__ __forceinline__ void lds_add_hybrid(unsigned long long* acc, float* o
   }
 }
 
+// Fixed-point value of k g (units of 2^-32, see lds_add_hybrid) and whether it
+// lies in the fixed-point window.
+__device__ __forceinline__ long long fixed_of(double k, double g) {
+  return __double_as_longlong(fma(k, g, kFixMagic)) - __double_as_longlong(kFixMagic);
+}
+
+__device__ __forceinline__ bool in_fixed_window(long long d) {
+  return (unsigned)((int)(d >> 32) + (1 << 18)) < (1u << 19);
+}
+
+// A contribution whose fixed-point value d was computed by fixed_of: the
+// 64-bit accumulator when d is in the window, else the FP32 array.
+__device__ __forceinline__ void lds_add_fixed_or(unsigned long long* acc, float* ovf, int j, long long d, double k,
+                                                 double g) {
+  if (in_fixed_window(d)) {
+    __hip_atomic_fetch_add(&acc[j], (unsigned long long)d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    lds_add(&ovf[j], (float)(k * g));
+  }
+}
+
 // Per-thread walk over j = j0, j0 + step, ... of the velocity index with the
 // components (jx, jy, jz) updated by carries instead of integer divisions
 // (step < n1 * n2 * n0 arbitrary; each carry is at most one).

@@ -64,6 +64,8 @@ struct BatchCav {
   int64_t hoff;    // first element of the problem's h in the batch buffers
   uint2* tidx;     // shared-sample records (G != 1), else null
   float4* tcoef;
+  uint2* sidx;     // where the sampler writes them (ACC_SPLIT: before the
+  float4* scoef;   // sort by target half; else tidx, tcoef)
   int mode;        // accumulation of the collide increments (ACC_*)
   int pad;
 };
