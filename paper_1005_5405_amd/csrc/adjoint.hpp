@@ -63,8 +63,20 @@ __device__ __forceinline__ void gain_loss_adj(const Params& P, const TablesLDS& 
         const int as = (int)(id[u].y & 0xFFFFu), bs = (int)(id[u].y >> 16);
         const double lg = fma((double)kk[u].x, (double)lI[as], (double)kk[u].y * (double)lI[bs]) -
                           fma((double)kk[u].z, (double)lI[a], (double)kk[u].w * (double)lI[b]);
-        if (lg != 0.0) {
-          const double ha = (double)hs[a], hb = (double)hs[b];
+        const double ha = (double)hs[a], hb = (double)hs[b];
+        if (FIXED) {
+          // both values first; straight-line adds when the whole wavefront
+          // has them in the fixed-point window (a discarded sample adds 0)
+          const double ks = lg * inv_s, fa = fma(eps, hb, 1.0), fb = fma(eps, ha, 1.0);
+          const long long da = fixed_of(ks, fa), db = fixed_of(ks, fb);
+          if (__all(in_fixed_window(da) & in_fixed_window(db))) {
+            __hip_atomic_fetch_add(&acc[a], (unsigned long long)da, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&acc[b], (unsigned long long)db, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          } else {
+            lds_add_fixed_or(acc, ovf, a, da, ks, fa);
+            lds_add_fixed_or(acc, ovf, b, db, ks, fb);
+          }
+        } else if (lg != 0.0) {
           adj_add<FIXED>(ls, acc, ovf, a, lg, inv_s, fma(eps, hb, 1.0));
           adj_add<FIXED>(ls, acc, ovf, b, lg, inv_s, fma(eps, ha, 1.0));
         }
