@@ -47,9 +47,9 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 # kernels), each scaled by what the counter reads for a device copy of the
 # 131 MB state (bench.py --calibrate); valid only for the kernel sources whose
 # SHA-256 is recorded (profiles/collide_counters_cavity64.md).
-TRAFFIC = {"sha256": "ffd72e8031ba45570014b0e4394d6a26f54b70a8a39fd0a4d1f3dcf21173af26",
-           "fetch_kib": 66398.9 + 105.0, "write_kib": 128000.0 + 468.8,
-           "fetch_scale": 128000.0 / 64018.1, "write_scale": 1.0}
+TRAFFIC = {"sha256": "3fcdf5f7ab01b0ad56a13bb9f7d0f191631d0cbd37f0a869bb2fb353ade800a1",
+           "fetch_kib": 66449.1 + 106.0, "write_kib": 128000.0 + 468.8,
+           "fetch_scale": 128000.0 / 64017.9, "write_scale": 1.0}
 KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
 
 
