@@ -47,18 +47,22 @@ __device__ __forceinline__ void gain_loss_adj(const Params& P, const TablesLDS& 
     constexpr int PU = 4;
     const uint2* ri = tidx + (int64_t)group * nt;
     const float4* rk = tcoef + (int64_t)group * nt;
-    for (uint32_t m0 = tid; m0 < nt; m0 += PU * BLOCK) {
+    // one pass: PU records per thread; in the masked (last) pass slots past
+    // the end of the table load and add nothing
+    auto pass = [&](uint32_t m0, const bool masked) {
       uint2 id[PU];
       float4 kk[PU];
+      bool ok[PU];
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
         const uint32_t m = m0 + u * BLOCK;
-        // past the end: a record with zero coefficients (no contribution)
-        id[u] = m < nt ? ri[m] : make_uint2(0u, 0u);
-        kk[u] = m < nt ? rk[m] : make_float4(0.f, 0.f, 0.f, 0.f);
+        ok[u] = !masked || m < nt;
+        id[u] = ok[u] ? ri[m] : make_uint2(0u, 0u);
+        kk[u] = ok[u] ? rk[m] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
+        if (!ok[u]) continue;
         const int a = (int)(id[u].x & 0xFFFFu), b = (int)(id[u].x >> 16);
         const int as = (int)(id[u].y & 0xFFFFu), bs = (int)(id[u].y >> 16);
         const double lg = fma((double)kk[u].x, (double)lI[as], (double)kk[u].y * (double)lI[bs]) -
@@ -81,7 +85,10 @@ __device__ __forceinline__ void gain_loss_adj(const Params& P, const TablesLDS& 
           adj_add<FIXED>(ls, acc, ovf, b, lg, inv_s, fma(eps, ha, 1.0));
         }
       }
-    }
+    };
+    uint32_t m0 = tid;
+    for (; m0 + (PU - 1) * BLOCK < nt; m0 += PU * BLOCK) pass(m0, false);
+    if (m0 < nt) pass(m0, true);
   } else {
     for (uint32_t m = tid; m < nt; m += BLOCK) {
       const Pair p = sample_pair(P, T, group, step, m, nullptr);
@@ -185,8 +192,8 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
     if (correct) {
       __syncthreads();
       double acc[20];
-      correction_sums<BLOCK, 1>(T, hs, accf, n0, n1, n2, acc);
-      block_sum20_lds(acc, red, tot);
+      correction_sums<BLOCK>(T, P.zmom, hs, accf, n0, n1, n2, acc);
+      block_sum20_lds<BLOCK>(acc, red, tot);
       double zs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       NodeWalk walk(tid, BLOCK, n1, n2);
       for (int j = tid; j < nv; j += BLOCK, walk.next()) {
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
         zs[3] += c * u;
         zs[4] += ((a * a + b * b) + c * c) * u;
       }
-      block_sum<5>(zs, red);
+      block_sum<5, BLOCK>(zs, red);
       if (tid < 64) {
         // wavefront 0: M x = r and M y = z, then x . psi and y . psi per axis
         double M[15], r[5], z[5], x[5], y[5];

@@ -123,11 +123,10 @@ size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof
 // fixed-point accumulators for every node when they fit next to the h tile
 // and tables, else for half of the nodes per pass, else FP32; the block size
 // gives about 1024 resident threads per CU.  block[0]: pairs drawn in the
-// kernel; block[1]: pairs read from the shared table, which runs faster with
-// 512 threads (and unrolled node loops) than with 1024 when only one
-// workgroup fits per CU (346 vs 354 us on the 64x64 cavity).  The split mode
-// keeps 8192 / block nodes per thread in registers between its passes, and
-// uses 512 threads.
+// kernel; block[1]: pairs read from the shared table (1024 threads: 304 us
+// per collision on the 64x64 cavity against 309 us with 512).  The split
+// mode keeps 8192 / block nodes per thread in registers between its
+// passes, and uses 512 threads.
 bool pick_collide(int nv, int ns, int& mode, int (&blocks)[2]) {
   int block = 256;
   if (CollideLDS::bytes(nv, ns, ACC_FIXED, true) + collide_static_lds(1024) <= kLdsBytes) mode = ACC_FIXED;
@@ -140,8 +139,7 @@ bool pick_collide(int nv, int ns, int& mode, int (&blocks)[2]) {
   if (4 * (dyn + collide_static_lds(256)) <= kLdsBytes) block = 256;
   else if (2 * (dyn + collide_static_lds(512)) <= kLdsBytes || mode == ACC_SPLIT) block = 512;
   else block = 1024;
-  blocks[0] = block;
-  blocks[1] = block == 1024 ? 512 : block;
+  blocks[0] = blocks[1] = block;
   // tuning override: BOLTZ_COLLIDE_BLOCK = 256 | 512 | 1024 (both variants)
   if (const char* e = std::getenv("BOLTZ_COLLIDE_BLOCK")) {
     const int b = std::atoi(e);
@@ -321,6 +319,13 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   std::vector<float4> nqtab(3 * kMaxAxis, make_float4(0.f, 0.f, 0.f, 0.f));
   std::vector<uint8_t> icdf(3 * kFieldSize, 0);
   std::vector<float> cour(2 * kMaxAxis, 0.f), cour2(2 * kMaxAxis, 0.f);
+  // omega_z v_z^p (p = 0..4) per z node, eight doubles a node
+  std::vector<double> zmom((size_t)8 * c->n[2], 0.0);
+  for (int i = 0; i < c->n[2]; ++i) {
+    const double z = c->v[2][i], z2 = z * z;
+    const double pw[5] = {1.0, z, z2, z2 * z, z2 * z2};
+    for (int q = 0; q < 5; ++q) zmom[(size_t)8 * i + q] = c->om[2][i] * pw[q];
+  }
   for (int k = 0; k < 3; ++k) {
     const int n = c->n[k];
     for (int i = 0; i < n; ++i) {
@@ -366,6 +371,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t o_nq = off; off = align256(off + nqtab.size() * 16);
   const size_t o_icdf = off; off = align256(off + icdf.size());
   const size_t o_m0 = off; off = align256(off + m0.size() * 8);
+  const size_t o_zmom = off; off = align256(off + zmom.size() * 8);
   const size_t o_cour = off; off = align256(off + cour.size() * 4);
   const size_t o_cour2 = off; off = align256(off + cour2.size() * 4);
   const size_t o_nw = off; off = align256(off + (size_t)nfaces * 8);
@@ -399,6 +405,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       {o_v, vtab.data(), vtab.size() * 8}, {o_om, omtab.data(), omtab.size() * 8},
       {o_rw, rwtab.data(), rwtab.size() * 8}, {o_nq, nqtab.data(), nqtab.size() * 16},
       {o_icdf, icdf.data(), icdf.size()}, {o_m0, m0.data(), m0.size() * 8},
+      {o_zmom, zmom.data(), zmom.size() * 8},
       {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4}};
   for (const Cp& cp : cps) {
     e = hipMemcpy(base + cp.o, cp.src, cp.n, hipMemcpyHostToDevice);
@@ -443,6 +450,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.nqtab = reinterpret_cast<const float4*>(base + o_nq);
   P.icdf = reinterpret_cast<const uint8_t*>(base + o_icdf);
   P.m0 = reinterpret_cast<const double*>(base + o_m0);
+  P.zmom = reinterpret_cast<const double*>(base + o_zmom);
   P.cour = reinterpret_cast<const float*>(base + o_cour);
   P.cour2 = reinterpret_cast<const float*>(base + o_cour2);
   P.nw = reinterpret_cast<double*>(base + o_nw);

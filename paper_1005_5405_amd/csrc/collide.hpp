@@ -392,11 +392,14 @@ constexpr int split_regs() { return 8192 / BLOCK; }
 constexpr int kPrefetch = 4;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 struct Prefetch {
   f32x4 r0, r1, r2, r3;
   // every lane loads (indices clamped into the tile) so the registers are
   // always defined and the loads stay in flight until the next tile store
+  // (loads under a branch each wait for the previous one: the compiler
+  // cannot tell that the registers' earlier loads have retired)
   __device__ __forceinline__ void load(const float* src, int i, int stride, int n) {
     const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
     r0 = s4[min(i, n - 1)];
@@ -482,14 +485,19 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
     constexpr int PU = 4;
     const uint2* ri = tidx + (int64_t)group * nt;
     const float4* rk = tcoef + (int64_t)group * nt;
-    uint32_t m = tid;
-    for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) {
+    // one pass: PU records per thread, loads and gathers in flight together;
+    // in the masked (last) pass slots past the end of the table load and
+    // add nothing
+    auto pass = [&](uint32_t m, const bool masked) {
       uint2 id[PU];
       float4 kk[PU];
+      bool ok[PU];
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
-        id[u] = ri[m + u * BLOCK];
-        kk[u] = rk[m + u * BLOCK];
+        const uint32_t mu = m + u * BLOCK;
+        ok[u] = !masked || mu < nt;
+        id[u] = ok[u] ? ri[mu] : make_uint2(0u, 0u);
+        kk[u] = ok[u] ? rk[mu] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
       float ha[PU], hb[PU];
 #pragma unroll
@@ -513,19 +521,14 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
         const float g = (ha[u] + hb[u]) + (epsf * ha[u]) * hb[u];
-        scatter<MODE>(accf, acc64, lo, n, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
-                       (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
+        if (ok[u])
+          scatter<MODE>(accf, acc64, lo, n, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16),
+                        (int)(id[u].y & 0xFFFFu), (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
       }
-    }
-    for (; m < nt; m += BLOCK) {
-      const uint2 i0 = ri[m];
-      const float4 k0 = rk[m];
-      const int a0 = (int)(i0.x & 0xFFFFu), b0 = (int)(i0.x >> 16);
-      const float ha0 = hs[a0], hb0 = hs[b0];
-      const float g0 = (ha0 + hb0) + (epsf * ha0) * hb0;
-      scatter<MODE>(accf, acc64, lo, n, a0, b0, (int)(i0.y & 0xFFFFu), (int)(i0.y >> 16), k0.x, k0.y, k0.z, k0.w,
-                    g0);
-    }
+    };
+    uint32_t m = tid;
+    for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) pass(m, false);
+    if (m < nt) pass(m, true);
   } else {
     for (uint32_t m = tid; m < nt; m += BLOCK) {
       const Pair p = sample_pair(P, T, group, step, m, nullptr);
@@ -543,41 +546,54 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 //   M = M0 + eps sum_j w_j h^c_j psi_j psi_j^T  (M0 = sum w psi psi^T),
 //   r = -eps sum_j w_j psi_j (h^c_j - h^s_j),  psi = (1, v, |v|^2),
 // from the z moments S_p = sum_z omega_z h^c v_z^p (p <= 4) and
-// R_p = sum_z omega_z (h^c - h^s) v_z^p (p <= 2) of the row, accumulated
-// with one FMA per moment and node.  (Cutting the rows into chunks so that
-// more threads share them was measured slower: the strided chunk reads add
-// LDS conflicts.)  acc[0..15) are the sums of h^c psi_k psi_l (packed
-// k <= l), acc[15..20) those of (h^c - h^s) psi_k, per thread.
-template <int BLOCK, int NU>
-__device__ __forceinline__ void correction_sums(const TablesLDS& T, const float* hs, const float* hc_t, int n0,
-                                                int n1, int n2, double (&acc)[20]) {
+// R_p = sum_z omega_z (h^c - h^s) v_z^p (p <= 2) of the row, one FMA per
+// moment and node with the factors omega_z v_z^p of the table zmom.  All
+// threads visit the same z node at the same time, so the factors are read
+// through the constant address space into scalar registers; a row is read
+// four nodes at a time when nv_z is a multiple of 4 (rows 16-byte aligned,
+// no bank conflicts between neighbouring rows).  acc[0..15) are the sums
+// of h^c psi_k psi_l (packed k <= l), acc[15..20) those of
+// (h^c - h^s) psi_k, per thread.
+typedef __attribute__((address_space(4))) const double const_f64;
+
+template <int BLOCK>
+__device__ __forceinline__ void correction_sums(const TablesLDS& T, const double* zmom, const float* hs,
+                                                const float* hc_t, int n0, int n1, int n2, double (&acc)[20]) {
   const double* vx = T.v;
   const double* vy = T.v + n0;
-  const double* vz = T.v + n0 + n1;
   const double* omx = T.om;
   const double* omy = T.om + n0;
-  const double* omz = T.om + n0 + n1;
+  const const_f64* zc = (const const_f64*)zmom;
+  const bool vec = (n2 & 3) == 0;
 #pragma unroll
   for (int i = 0; i < 20; ++i) acc[i] = 0.0;
   for (int row = threadIdx.x; row < n0 * n1; row += BLOCK) {
     const int jx = row / n1, jy = row - (row / n1) * n1;
-    const float* hcr = hc_t + row * n2;
-    const float* hsr = hs + row * n2;
     double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
-#pragma unroll NU
-    for (int jz = 0; jz < n2; ++jz) {
-      const double hc = (double)hcr[jz], oz = omz[jz], z = vz[jz];
-      const double z2 = z * z, z3 = z2 * z, z4 = z2 * z2;
-      const double u = oz * hc;
-      S0 += u;
-      S1 = fma(u, z, S1);
-      S2 = fma(u, z2, S2);
-      S3 = fma(u, z3, S3);
-      S4 = fma(u, z4, S4);
-      const double d = oz * (hc - (double)hsr[jz]);
-      R0 += d;
-      R1 = fma(d, z, R1);
-      R2 = fma(d, z2, R2);
+    auto node = [&](int jz, float hcf, float hsf) {
+      const const_f64* z = zc + 8 * jz;
+      const double hc = (double)hcf, d = hc - (double)hsf;
+      S0 = fma(z[0], hc, S0);
+      S1 = fma(z[1], hc, S1);
+      S2 = fma(z[2], hc, S2);
+      S3 = fma(z[3], hc, S3);
+      S4 = fma(z[4], hc, S4);
+      R0 = fma(z[0], d, R0);
+      R1 = fma(z[1], d, R1);
+      R2 = fma(z[2], d, R2);
+    };
+    if (vec) {
+      const f32x4* hcr = reinterpret_cast<const f32x4*>(hc_t + row * n2);
+      const f32x4* hsr = reinterpret_cast<const f32x4*>(hs + row * n2);
+      for (int q = 0; q < (n2 >> 2); ++q) {
+        const f32x4 c4 = hcr[q], s4 = hsr[q];
+        node(4 * q, c4.x, s4.x);
+        node(4 * q + 1, c4.y, s4.y);
+        node(4 * q + 2, c4.z, s4.z);
+        node(4 * q + 3, c4.w, s4.w);
+      }
+    } else {
+      for (int jz = 0; jz < n2; ++jz) node(jz, hc_t[row * n2 + jz], hs[row * n2 + jz]);
     }
     const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
     const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
@@ -609,15 +625,18 @@ __device__ __forceinline__ void correction_sums(const TablesLDS& T, const float*
 // One cell after its h^s tile is in LDS and the accumulators are cleared
 // (and a barrier passed): S3 + S4 pair pass, h^c, S5 correction, one
 // coalesced store of h^{n+1} to dst.  next() is called once the pair pass is
-// over (the persistent kernel requests the next tile there); defect: the
-// cell's five values or null.  Ends with a barrier, so the LDS can be
+// over (the persistent kernel requests the next tile there); early() is
+// called by every thread while wavefront 0 solves for the correction (the
+// others right away), after the last reads of h^s and of the 64-bit
+// accumulators (the persistent kernel stages the next cell there); defect:
+// the cell's five values or null.  Ends with a barrier, so the LDS can be
 // refilled.
-template <int BLOCK, bool TABLE, int MODE, class Next>
+template <int BLOCK, bool TABLE, int MODE, class Next, class Early>
 __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T, float* hs, float* accf,
-                                             unsigned long long* acc64, double* red, double* tot, uint32_t group,
+                                             unsigned long long* acc64, double* red, uint32_t group,
                                              uint32_t step, uint32_t flags, float* dst, double* defect,
                                              const uint2* __restrict__ tidx, const float4* __restrict__ tcoef,
-                                             Next&& next) {
+                                             Next&& next, Early&& early) {
   const int tid = threadIdx.x;
   const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const double* vx = T.v;
@@ -630,6 +649,9 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
   // 256 VGPRs below 1024 threads per workgroup, 128 at 1024)
   constexpr int NU = BLOCK <= 512 ? 4 : 1;
   const bool correct = !(flags & 1u);
+  // node phases four nodes at a time: rows of whole z quadruples and an
+  // output tile on a 16-byte boundary
+  const bool vec4 = ((n2 & 3) == 0) && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
   const double eps = P.eps;
   // ---- S3 + S4: Jacobi gain/loss, every sample reads the post-stream h
   if (MODE == ACC_SPLIT) {
@@ -672,29 +694,66 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
     gain_loss<BLOCK, TABLE, MODE>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
     __syncthreads();
     next();
-    // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator
+    // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator;
+    // the 64-bit accumulators are left cleared for the next cell
+    auto hc_of = [&](float hsj, float a, unsigned long long q) {
+      double dh = (double)a;
+      if (MODE == ACC_FIXED) dh += from_fixed(q);
+      return (float)((double)hsj + dh);
+    };
+    if (vec4) {
+      // four nodes per thread and access
+      f32x4* a4 = reinterpret_cast<f32x4*>(accf);
+      const f32x4* s4 = reinterpret_cast<const f32x4*>(hs);
+      u64x2* q2 = reinterpret_cast<u64x2*>(acc64);
 #pragma unroll NU
-    for (int j = tid; j < nv; j += BLOCK) {
-      const float hsj = hs[j];
-      double dh = (double)accf[j];
-      if (MODE == ACC_FIXED) dh += from_fixed(acc64[j]);
-      accf[j] = (float)((double)hsj + dh);
+      for (int i = tid; i < (nv >> 2); i += BLOCK) {
+        const f32x4 hv = s4[i];
+        f32x4 av = a4[i];
+        u64x2 q0 = {0ull, 0ull}, q1 = {0ull, 0ull};
+        if (MODE == ACC_FIXED) {
+          q0 = q2[2 * i];
+          q1 = q2[2 * i + 1];
+          q2[2 * i] = u64x2{0ull, 0ull};
+          q2[2 * i + 1] = u64x2{0ull, 0ull};
+        }
+        av.x = hc_of(hv.x, av.x, q0.x);
+        av.y = hc_of(hv.y, av.y, q0.y);
+        av.z = hc_of(hv.z, av.z, q1.x);
+        av.w = hc_of(hv.w, av.w, q1.y);
+        a4[i] = av;
+      }
+    } else {
+#pragma unroll NU
+      for (int j = tid; j < nv; j += BLOCK) {
+        unsigned long long q = 0ull;
+        if (MODE == ACC_FIXED) {
+          q = acc64[j];
+          acc64[j] = 0ull;
+        }
+        accf[j] = hc_of(hs[j], accf[j], q);
+      }
     }
   }
   if (correct) {
     __syncthreads();
     // (2) FP64 sums of M and r, block-reduced
     double acc[20];
-    correction_sums<BLOCK, NU>(T, hs, accf, n0, n1, n2, acc);
-    block_sum20_lds(acc, red, tot);
+    correction_sums<BLOCK>(T, P.zmom, hs, accf, n0, n1, n2, acc);
+    // wavefronts past the last velocity row hold zeros and stay out
+    const int rows = n0 * n1;
+    const double t = block_sum20_w0<BLOCK>(acc, red, rows >= BLOCK ? BLOCK / 64 : (rows + 63) / 64);
+    // M0 through the constant address space (scalar loads): the other
+    // wavefronts may be filling the LDS for the next cell meanwhile
+    const const_f64* m0c = (const const_f64*)P.m0;
     if (tid < 64) {
       // wavefront 0 solves M x = r and tabulates x . psi per axis:
       // x1 v_x + x4 v_x^2, x2 v_y + x4 v_y^2, x0 + x3 v_z + x4 v_z^2
       double M[15], r[5], x[5];
 #pragma unroll
-      for (int k = 0; k < 15; ++k) M[k] = T.m0[k] + eps * tot[k];
+      for (int k = 0; k < 15; ++k) M[k] = m0c[k] + eps * lane_value(t, k);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) r[k] = -eps * tot[15 + k];
+      for (int k = 0; k < 5; ++k) r[k] = -eps * lane_value(t, 15 + k);
       if (!solve5(M, r, x)) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) x[k] = 0.0;
@@ -706,40 +765,68 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
                          : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
       }
     }
+    early();
     __syncthreads();
   }
   // ---- (3) h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
-  double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   bool finite = true;
-  NodeWalk nw2(tid, BLOCK, n1, n2);
-#pragma unroll NU
-  for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
-    const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
-    const double hc = (double)accf[j];
-    float out = (float)hc;
+  auto out_of = [&](double hc, double xpsi) { return (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc); };
+  if (vec4 && !defect) {
+    // four nodes (one z quadruple of a row) per thread and access
+    const f32x4* a4 = reinterpret_cast<const f32x4*>(accf);
+    f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+    NodeWalk nw4(4 * tid, 4 * BLOCK, n1, n2);
     if (correct) {
-      const double xpsi = (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz];
-      out = (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc);
+#pragma unroll NU
+      for (int i = tid; i < (nv >> 2); i += BLOCK, nw4.next()) {
+        const f32x4 c = a4[i];
+        const double xa = T.xt[nw4.jx] + T.xt[n0 + nw4.jy];
+        const double* xz = T.xt + n0 + n1 + nw4.jz;
+        f32x4 o;
+        o.x = out_of((double)c.x, xa + xz[0]);
+        o.y = out_of((double)c.y, xa + xz[1]);
+        o.z = out_of((double)c.z, xa + xz[2]);
+        o.w = out_of((double)c.w, xa + xz[3]);
+        finite = finite && isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w);
+        d4[i] = o;
+      }
+    } else {
+#pragma unroll NU
+      for (int i = tid; i < (nv >> 2); i += BLOCK) {
+        const f32x4 c = a4[i];
+        finite = finite && isfinite(c.x) && isfinite(c.y) && isfinite(c.z) && isfinite(c.w);
+        d4[i] = c;
+      }
     }
-    finite = finite && isfinite(out);
-    dst[j] = out;
+  } else {
+    double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    NodeWalk nw2(tid, BLOCK, n1, n2);
+#pragma unroll NU
+    for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
+      const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
+      const double hc = (double)accf[j];
+      float out = (float)hc;
+      if (correct) out = out_of(hc, (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz]);
+      finite = finite && isfinite(out);
+      dst[j] = out;
+      if (defect) {
+        const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+        const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
+        const double w = (omx[jx] * omy[jy]) * omz[jz];
+        const double diff = eps * ((double)out - (double)hs[j]) * w;
+        dsum[0] += diff;
+        dsum[1] += v1 * diff;
+        dsum[2] += v2 * diff;
+        dsum[3] += v3 * diff;
+        dsum[4] += vv * diff;
+      }
+    }
     if (defect) {
-      const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
-      const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
-      const double w = (omx[jx] * omy[jy]) * omz[jz];
-      const double diff = eps * ((double)out - (double)hs[j]) * w;
-      dsum[0] += diff;
-      dsum[1] += v1 * diff;
-      dsum[2] += v2 * diff;
-      dsum[3] += v3 * diff;
-      dsum[4] += vv * diff;
+      block_sum<5>(dsum, red);
+      if (tid < 5) defect[tid] = dsum[tid];
     }
   }
   if (!finite) atomicOr(P.status, 2u);
-  if (defect) {
-    block_sum<5>(dsum, red);
-    if (tid < 5) defect[tid] = dsum[tid];
-  }
   __syncthreads();
 }
 
@@ -755,7 +842,6 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
                                                         const float4* __restrict__ tcoef) {
   extern __shared__ __align__(16) unsigned char dsm[];
   __shared__ double red[20 * (BLOCK / 64)];
-  __shared__ double tot[20];
   const int nv = P.nv;
   const int64_t ncells = (int64_t)P.nx * P.ny;
   const int tid = threadIdx.x;
@@ -766,34 +852,57 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   TablesLDS T;
   load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, MODE), !TABLE, T);
   const int nv4 = nv >> 2;
-  const bool vec = ((nv & 3) == 0) && nv4 <= kPrefetch * BLOCK;
+  const bool vec = ((nv & 3) == 0) && nv4 <= kPrefetch * BLOCK && ((reinterpret_cast<uintptr_t>(hs_g) & 15) == 0);
   Prefetch pre;
+  // byte ranges of the LDS cleared per cell: the FP32 array (h^c until the
+  // store) and, with ACC_SPLIT, its accumulators; the 64-bit accumulators
+  // of ACC_FIXED after the FP32 array are cleared once here, then by the
+  // h^c pass of every cell as it reads them
+  const size_t t0 = CollideLDS::tile(nv), t1 = MODE == ACC_SPLIT ? t0 + CollideLDS::acc(nv, MODE) : 2 * t0,
+               t2 = t0 + CollideLDS::acc(nv, MODE);
+  auto clear = [&](size_t from, size_t to) {
+    uint4* z = reinterpret_cast<uint4*>(dsm + from);
+    const int nz = (int)((to - from) / 16);
+    for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
+  };
+  if (t2 > t1) clear(t1, t2);
+  // staged: the next cell's tile was written while wavefront 0 solved for
+  // the correction of this cell (h^s is no longer read then, unless the
+  // defect is asked for)
+  bool staged = false;
   int64_t cell = blockIdx.x;
   if (vec && cell < ncells) pre.load(hs_g + cell * nv, tid, BLOCK, nv4);
   for (; cell < ncells; cell += gridDim.x) {
     // ---- h^s tile in, accumulators cleared
-    if (vec) {
-      pre.store(hs, tid, BLOCK, nv4);
-    } else {
-      const float* src = hs_g + cell * nv;
-      for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
+    if (!staged) {
+      if (vec) {
+        pre.store(hs, tid, BLOCK, nv4);
+      } else {
+        const float* src = hs_g + cell * nv;
+        for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
+      }
     }
-    {
-      uint4* z = reinterpret_cast<uint4*>(accf);
-      const int nz = (int)(CollideLDS::acc(nv, MODE) / 16);
-      for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
-    }
+    clear(t0, t1);
     __syncthreads();
     const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
+    const int64_t next = cell + gridDim.x;
+    staged = false;
     // The next cell's tile is requested once the pair pass is over:
     // vector-memory waits retire in issue order, so loads issued before the
     // pair loop would stall its first record loads; the node phases wait on
     // no vector load.
-    collide_body<BLOCK, TABLE, MODE>(P, T, hs, accf, acc64, red, tot, group, step, flags, hout_g + cell * nv,
-                                      defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
-                                        const int64_t next = cell + gridDim.x;
-                                        if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
-                                      });
+    collide_body<BLOCK, TABLE, MODE>(
+        P, T, hs, accf, acc64, red, group, step, flags, hout_g + cell * nv, defect ? defect + cell * 5 : nullptr,
+        tidx, tcoef,
+        [&]() {
+          if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
+        },
+        [&]() {
+          if (MODE != ACC_SPLIT && vec && !defect && next < ncells) {
+            pre.store(hs, tid, BLOCK, nv4);
+            staged = true;
+          }
+        });
   }
 }
 
@@ -812,7 +921,6 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
                                                               const uint32_t* __restrict__ step_dev) {
   extern __shared__ __align__(16) unsigned char dsm[];
   __shared__ double red[20 * (BLOCK / 64)];
-  __shared__ double tot[20];
   const int tid = threadIdx.x;
   const uint32_t step = *step_dev;
   int prev = -1;
@@ -851,7 +959,7 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
     float* dst = hout + C.hoff + cell * nv;
     auto none = []() {};
 #define BOLTZ_BODY(TB, MD)                                                                                      \
-  collide_body<BLOCK, TB, MD>(P, T, hs, accf, acc64, red, tot, group, step, 0u, dst, nullptr, C.tidx, C.tcoef, none)
+  collide_body<BLOCK, TB, MD>(P, T, hs, accf, acc64, red, group, step, 0u, dst, nullptr, C.tidx, C.tcoef, none, none)
     if (table) {
       if (mode == ACC_FIXED) BOLTZ_BODY(true, ACC_FIXED);
       else if (mode == ACC_SPLIT) BOLTZ_BODY(true, ACC_SPLIT);

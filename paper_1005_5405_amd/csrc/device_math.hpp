@@ -108,8 +108,11 @@ constexpr double kFixMagic = 1572864.0;               // 1.5 * 2^20
 constexpr double kFixLimit = 262144.0;                // 2^18
 constexpr double kFixScale = 2.3283064365386963e-10;  // 2^-32
 
+// Value of a 64-bit fixed-point sum: hi + lo 2^-32 of its signed high and
+// unsigned low words with the single rounding of the FMA, which is the
+// correctly rounded (double)(int64) v times 2^-32.
 __device__ __forceinline__ double from_fixed(unsigned long long v) {
-  return (double)(long long)v * kFixScale;
+  return fma((double)(unsigned)v, kFixScale, (double)(int)(v >> 32));
 }
 
 // ------------------------------------------------------- LDS float add --
@@ -212,11 +215,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum of N values per thread over the whole block (blockDim.x a multiple of
-// 64); every thread receives the totals.  red: LDS scratch of
-// N * (blockDim.x / 64) doubles.  Deterministic order.
-template <int N>
+// 64; BLOCK, when given, is blockDim.x known at compile time); every thread
+// receives the totals.  red: LDS scratch of N * (blockDim.x / 64) doubles.
+// Deterministic order.
+template <int N, int BLOCK = 0>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = BLOCK ? BLOCK / 64 : (int)(blockDim.x >> 6);
 #pragma unroll
   for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
   if (lane == 0) {
@@ -227,56 +231,115 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double s = 0.0;
+#pragma unroll 2
     for (int w = 0; w < nw; ++w) s += red[i * nw + w];
     v[i] = s;
   }
   __syncthreads();
 }
 
+// ----------------------------------------- 20-value block reduction --
+// Lane exchanges of gfx950 without the LDS: v_permlane32_swap and
+// v_permlane16_swap (swap two registers' halves between lanes l and l ^ 32,
+// resp. l ^ 16), and DPP reads of lane l ^ 15 (row_mirror), l ^ 7
+// (row_half_mirror), l ^ 2 and l ^ 1 (quad permutations).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppMirror = 0x140, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+
+// Halving step with a lane swap: lanes with (lane & OFF) == 0 end with
+// lo + partner's lo, the others with hi + partner's hi (OFF = 32 or 16).
+template <int OFF>
+__device__ __forceinline__ double swap_sum(double lo, double hi) {
+  const unsigned a0 = (unsigned)__double2loint(lo), a1 = (unsigned)__double2hiint(lo);
+  const unsigned b0 = (unsigned)__double2loint(hi), b1 = (unsigned)__double2hiint(hi);
+  if (OFF == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(a0, b0, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(a1, b1, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(a0, b0, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(a1, b1, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  }
+}
+
 // Halving step of a multi-value wavefront reduction: v[0..N) becomes
-// v[0..H), H = (N + 1) / 2, where lanes with (lane & OFF) == 0 keep the sums
-// of the lower half (v[i] + partner's v[i]) and the others those of the upper
-// half (v[H + i], zero-padded when N is odd).
-template <int N, int OFF>
-__device__ __forceinline__ void fold_half(double* v, bool upper) {
+// v[0..H), H = (N + 1) / 2; lanes without bit OFF keep the sums of the lower
+// half (v[i] + partner's v[i]), the others those of the upper half
+// (v[H + i], zero-padded when N is odd).  The partner differs in bit OFF
+// (and in lower bits only, for the DPP partners).
+template <int N, int OFF, int CTRL>
+__device__ __forceinline__ void fold_half(double* v, int lane) {
   constexpr int H = (N + 1) / 2;
+  const bool upper = lane & OFF;
 #pragma unroll
   for (int i = 0; i < H; ++i) {
     const double lo = v[i];
     const double hi = (H + i < N) ? v[H + i] : 0.0;
-    const double send = upper ? lo : hi;
-    const double keep = upper ? hi : lo;
-    v[i] = keep + __shfl_xor(send, OFF, 64);
+    if (OFF >= 16) {
+      v[i] = swap_sum<OFF>(lo, hi);
+    } else {
+      const double send = upper ? lo : hi;
+      const double keep = upper ? hi : lo;
+      v[i] = keep + dpp_f64<CTRL>(send);
+    }
   }
 }
 
-// Sum of 20 values per thread over the whole block into tot[0..20) in LDS
-// (blockDim.x a multiple of 64).  Within a wavefront the values are halved
-// at every exchange (offsets 32, 16, 8, 4, 2, then a plain pairwise sum),
-// 22 exchanges instead of 120; lane l then holds value
-// 10 b5 + 5 b4 + 3 b3 + 2 b2 + b1 of its bits b_k (or a zero pad).  The
-// wavefront sums are added in wavefront order.  Deterministic order.
-// red: LDS scratch of 20 * (blockDim.x / 64) doubles.  v is consumed.
-__device__ __forceinline__ void block_sum20_lds(double (&v)[20], double* red, double* tot) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  fold_half<20, 32>(v, lane & 32);
-  fold_half<10, 16>(v, lane & 16);
-  fold_half<5, 8>(v, lane & 8);
-  fold_half<3, 4>(v, lane & 4);
-  fold_half<2, 2>(v, lane & 2);
-  const double s = v[0] + __shfl_xor(v[0], 1, 64);
-  const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1,
-            b1 = (lane >> 1) & 1;
-  // positions within the last group of five: b3 b2 b1 -> 0,1,2,pad,3,4,pad,pad
-  const int pos = 3 * b3 + 2 * b2 + b1;
-  const bool valid = ((lane & 1) == 0) && (b3 ? (b2 == 0) : (pos < 3));
-  if (valid) red[(10 * b5 + 5 * b4 + pos) * nw + wid] = s;
-  __syncthreads();
-  if (threadIdx.x < 20) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += red[threadIdx.x * nw + w];
-    tot[threadIdx.x] = t;
+// Sum of 20 values per thread over a block of BLOCK threads (a multiple of
+// 64).  Within a wavefront the values are halved at every exchange (lane
+// bits 5, 4, 3, 2, 1, then a plain pairwise sum), 22 exchanges instead of
+// 120; lane l then holds value 10 b5 + 5 b4 + 3 b3 + 2 b2 + b1 of its bits
+// b_k (or a zero pad).  The wavefront sums are added in wavefront order;
+// on return lane k < 20 of wavefront 0 holds total k (the value returned;
+// other lanes: unspecified).  Deterministic order.  Only the first nwd
+// wavefronts take part (the values of the others must be zero).  red: LDS
+// scratch of 20 * (BLOCK / 64) doubles.  v is consumed.  Ends without a
+// barrier after the reads of red: the caller synchronises before red is
+// written again.
+template <int BLOCK>
+__device__ __forceinline__ double block_sum20_w0(double (&v)[20], double* red, int nwd = BLOCK / 64) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = BLOCK / 64;
+  if (wid < nwd) {
+    fold_half<20, 32, 0>(v, lane);
+    fold_half<10, 16, 0>(v, lane);
+    fold_half<5, 8, kDppMirror>(v, lane);
+    fold_half<3, 4, kDppHalfMirror>(v, lane);
+    fold_half<2, 2, kDppXor2>(v, lane);
+    const double s = v[0] + dpp_f64<kDppXor1>(v[0]);
+    const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1,
+              b1 = (lane >> 1) & 1;
+    // positions within the last group of five: b3 b2 b1 -> 0,1,2,pad,3,4,pad,pad
+    const int pos = 3 * b3 + 2 * b2 + b1;
+    const bool valid = ((lane & 1) == 0) && (b3 ? (b2 == 0) : (pos < 3));
+    if (valid) red[(10 * b5 + 5 * b4 + pos) * nw + wid] = s;
   }
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x < 20) {
+#pragma unroll 4
+    for (int w = 0; w < nwd; ++w) t += red[threadIdx.x * nw + w];
+  }
+  return t;
+}
+
+// Value of lane k of a wavefront (k uniform), in every lane.
+__device__ __forceinline__ double lane_value(double t, int k) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(t), k),
+                          __builtin_amdgcn_readlane(__double2loint(t), k));
+}
+
+// block_sum20_w0 with the totals stored to tot[0..20) in LDS for the whole
+// block (ends with a barrier).
+template <int BLOCK>
+__device__ __forceinline__ void block_sum20_lds(double (&v)[20], double* red, double* tot) {
+  const double t = block_sum20_w0<BLOCK>(v, red);
+  if (threadIdx.x < 20) tot[threadIdx.x] = t;
   __syncthreads();
 }
 

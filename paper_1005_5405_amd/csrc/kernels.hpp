@@ -51,6 +51,7 @@ struct Params {
   double* ratio_b;        // [nx][nv] Phi_w / Phi0 of every bottom face
   const double* tau_b;    // [nx] T_w / T0 of every bottom face
   const double* m0;       // [15] sum_j w_j psi_k psi_l, psi = (1, v, |v|^2), packed k <= l
+  const double* zmom;     // [nv_z][8] omega_z v_z^p for p = 0..4 (then zeros)
   double* dpart;          // [nx] lid shear partial sums
   double* wconst;         // [4][2] per wall: A_w, D_w of the face densities
   double* wconst_b;       // [nx][2] A, D of every bottom face
