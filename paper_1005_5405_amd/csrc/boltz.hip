@@ -123,8 +123,8 @@ size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof
 // fixed-point accumulators for every node when they fit next to the h tile
 // and tables, else for half of the nodes per pass, else FP32; the block size
 // gives about 1024 resident threads per CU.  block[0]: pairs drawn in the
-// kernel; block[1]: pairs read from the shared table (1024 threads: 304 us
-// per collision on the 64x64 cavity against 309 us with 512).  The split
+// kernel; block[1]: pairs read from the shared table (1024 threads: 289 us
+// per collision on the 64x64 cavity against 311 us with 512).  The split
 // mode keeps 8192 / block nodes per thread in registers between its
 // passes, and uses 512 threads.
 bool pick_collide(int nv, int ns, int& mode, int (&blocks)[2]) {

@@ -388,31 +388,31 @@ struct CollideLDS {
 template <int BLOCK>
 constexpr int split_regs() { return 8192 / BLOCK; }
 
-// float4 registers per thread holding the next cell's h^s tile
-constexpr int kPrefetch = 4;
+// float4 registers per thread holding the next cell's h^s tile: 4, or 2
+// with 1024 threads (enough for 8192 nodes)
+template <int BLOCK>
+constexpr int prefetch_regs() { return BLOCK >= 1024 ? 2 : 4; }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
+template <int NR>
 struct Prefetch {
-  f32x4 r0, r1, r2, r3;
+  f32x4 r[NR];
   // every lane loads (indices clamped into the tile) so the registers are
   // always defined and the loads stay in flight until the next tile store
   // (loads under a branch each wait for the previous one: the compiler
   // cannot tell that the registers' earlier loads have retired)
   __device__ __forceinline__ void load(const float* src, int i, int stride, int n) {
     const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
-    r0 = s4[min(i, n - 1)];
-    r1 = s4[min(i + stride, n - 1)];
-    r2 = s4[min(i + 2 * stride, n - 1)];
-    r3 = s4[min(i + 3 * stride, n - 1)];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) r[k] = s4[min(i + k * stride, n - 1)];
   }
   __device__ __forceinline__ void store(float* dst, int i, int stride, int n) const {
     f32x4* d4 = reinterpret_cast<f32x4*>(dst);
-    if (i < n) d4[i] = r0;
-    if (i + stride < n) d4[i + stride] = r1;
-    if (i + 2 * stride < n) d4[i + 2 * stride] = r2;
-    if (i + 3 * stride < n) d4[i + 3 * stride] = r3;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (i + k * stride < n) d4[i + k * stride] = r[k];
   }
 };
 
@@ -852,8 +852,9 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   TablesLDS T;
   load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::acc(nv, MODE), !TABLE, T);
   const int nv4 = nv >> 2;
-  const bool vec = ((nv & 3) == 0) && nv4 <= kPrefetch * BLOCK && ((reinterpret_cast<uintptr_t>(hs_g) & 15) == 0);
-  Prefetch pre;
+  constexpr int NR = prefetch_regs<BLOCK>();
+  const bool vec = ((nv & 3) == 0) && nv4 <= NR * BLOCK && ((reinterpret_cast<uintptr_t>(hs_g) & 15) == 0);
+  Prefetch<NR> pre;
   // byte ranges of the LDS cleared per cell: the FP32 array (h^c until the
   // store) and, with ACC_SPLIT, its accumulators; the 64-bit accumulators
   // of ACC_FIXED after the FP32 array are cleared once here, then by the
