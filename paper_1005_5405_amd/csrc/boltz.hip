@@ -550,21 +550,35 @@ static int ensure_ratio(boltz_ctx* c, const WallArgs& W, const boltz_walls* wall
   return BOLTZ_OK;
 }
 
+// Shared pair records that can be drawn in the first face launch: a table
+// written directly by the sampler (no split-mode sort after it).
+static bool samples_with_walls(const boltz_ctx* c) {
+  return c->ngroups > 0 && c->p.n_pairs > 0 && c->sidx == c->tidx;
+}
+
+// The face densities; with sample_step >= 0 (and samples_with_walls) the
+// records of that step are drawn in the first face launch.
 static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const boltz_walls* walls,
-                        hipStream_t st) {
+                        hipStream_t st, int64_t sample_step = -1) {
   const int rc = ensure_ratio(c, W, walls, st);
   if (rc != BOLTZ_OK) return rc;
   auto launch = [&](auto kern, int nface) {
     const int per_xcd = (nface + 7) / 8;
     hipLaunchKernelGGL(kern, dim3(8 * per_xcd), dim3(kWallBlock), 0, st, c->P, h, nface, per_xcd);
   };
-  if (c->p.order == 2) {
-    // x faces first; the y faces read their densities for the x-swept rows
-    launch(wall_kernel<0>, 2 * c->p.ny);
-    launch(wall_kernel<1>, 2 * c->p.nx);
+  const int nface0 = c->p.order == 2 ? 2 * c->p.ny : 2 * (c->p.nx + c->p.ny);
+  if (sample_step >= 0 && samples_with_walls(c)) {
+    const int per_xcd = (nface0 + 7) / 8;
+    const int nb = (int)((c->p.n_pairs + kWallBlock - 1) / kWallBlock);
+    const int nsum = c->n[0] + c->n[1] + c->n[2];
+    hipLaunchKernelGGL(wall_sample_kernel<0>, dim3((unsigned)(8 * per_xcd + nb * c->ngroups)), dim3(kWallBlock),
+                       TablesLDS::bytes(nsum, true), st, c->P, h, nface0, per_xcd, nb, (uint32_t)sample_step,
+                       c->tidx, c->tcoef);
   } else {
-    launch(wall_kernel<0>, 2 * (c->p.nx + c->p.ny));
+    launch(wall_kernel<0>, nface0);
   }
+  // order 2: the y faces read the x-face densities for the x-swept rows
+  if (c->p.order == 2) launch(wall_kernel<1>, 2 * c->p.nx);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "wall_kernel launch");
 }
@@ -638,10 +652,10 @@ static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st) {
 }
 
 static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
-                          double* defect, hipStream_t st) {
+                          double* defect, hipStream_t st, bool drawn = false) {
   const uint32_t s32 = (uint32_t)step;
   const bool table = c->ngroups > 0;
-  launch_samples(c, s32, st);
+  if (!drawn) launch_samples(c, s32, st);
   switch (c->collide_block[table ? 1 : 0]) {
     case 256: launch_collide_b<256>(c, table, hs, hout, s32, flags, defect, st); break;
     case 512: launch_collide_b<512>(c, table, hs, hout, s32, flags, defect, st); break;
@@ -657,18 +671,25 @@ static bool overlap(const void* a, const void* b, size_t n) {
   return x < y + n && y < x + n;
 }
 
-int boltz_stream(boltz_ctx* c, const float* h_in, float* h_out, const boltz_walls* walls, void* stream) {
+// boltz_stream; with sample_step >= 0 the shared records of that step are
+// drawn with the face densities when possible (*drawn tells).
+static int stream_step(boltz_ctx* c, const float* h_in, float* h_out, const boltz_walls* walls, hipStream_t st,
+                       int64_t sample_step, bool* drawn) {
   if (!c) return BOLTZ_EINVAL;
   if (!h_in || !h_out) return fail(c, BOLTZ_EINVAL, "boltz_stream: null buffer");
   const size_t bytes = (size_t)c->ncells * c->nv * sizeof(float);
   if (overlap(h_in, h_out, bytes)) return fail(c, BOLTZ_EINVAL, "boltz_stream: h_in and h_out overlap");
   const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
   if (cavity && !walls_ok(walls, c->p.nx)) return fail(c, BOLTZ_EINVAL, "boltz_stream: cavity needs valid walls");
-  hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = BOLTZ_OK;
-  if (cavity) rc = launch_walls(c, h_in, make_walls(walls), walls, st);
+  if (cavity) rc = launch_walls(c, h_in, make_walls(walls), walls, st, sample_step);
+  if (drawn) *drawn = cavity && sample_step >= 0 && samples_with_walls(c);
   if (rc == BOLTZ_OK) rc = launch_stream(c, h_in, h_out, st);
   return rc;
+}
+
+int boltz_stream(boltz_ctx* c, const float* h_in, float* h_out, const boltz_walls* walls, void* stream) {
+  return stream_step(c, h_in, h_out, walls, static_cast<hipStream_t>(stream), -1, nullptr);
 }
 
 int boltz_collide(boltz_ctx* c, const float* h_s, float* h_out, int64_t step, uint32_t flags, double* defect,
@@ -684,9 +705,11 @@ int boltz_collide(boltz_ctx* c, const float* h_s, float* h_out, int64_t step, ui
 
 int boltz_step(boltz_ctx* c, const float* h_in, float* h_out, const boltz_walls* walls, int64_t step,
                void* stream) {
-  const int rc = boltz_stream(c, h_in, h_out, walls, stream);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bool drawn = false;
+  const int rc = stream_step(c, h_in, h_out, walls, st, step, &drawn);
   if (rc != BOLTZ_OK) return rc;
-  return launch_collide(c, h_out, h_out, step, 0u, nullptr, static_cast<hipStream_t>(stream));
+  return launch_collide(c, h_out, h_out, step, 0u, nullptr, st, drawn);
 }
 
 int boltz_moments(boltz_ctx* c, const float* h, const boltz_walls* walls, double* mom, double* lid_shear,

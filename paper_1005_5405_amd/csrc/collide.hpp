@@ -974,4 +974,34 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
   }
 }
 
+// ------------------------------------------------ faces with samples --
+// wall_kernel<PHASE> in blocks [0, 8 per_xcd) and, in the blocks after
+// them, the shared pair records of the step (sample_kernel's work with
+// kWallBlock-thread blocks; nb blocks per sample group): the records do not
+// depend on h, so they are drawn while the face reductions (one workgroup
+// per face) leave most of the GPU idle.  Dynamic LDS: the sampler tables.
+template <int PHASE>
+__global__ __launch_bounds__(kWallBlock) void wall_sample_kernel(Params P, const float* __restrict__ h, int nface,
+                                                                 int per_xcd, int nb, uint32_t step,
+                                                                 uint2* __restrict__ tidx,
+                                                                 float4* __restrict__ tcoef) {
+  const int nwb = 8 * per_xcd;
+  if ((int)blockIdx.x < nwb) {
+    __shared__ double red[kWallBlock / 64];
+    int f = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (f >= nface) return;
+    if (PHASE == 1) f += 2 * P.ny;
+    wall_face<PHASE>(P, h, f, red);
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char dsm[];
+  TablesLDS T;
+  load_tables(P, dsm, true, T);
+  __syncthreads();
+  const int b = (int)blockIdx.x - nwb, group = b / nb;
+  const int64_t i = (int64_t)(b - group * nb) * kWallBlock + threadIdx.x;
+  if (i >= P.n_pairs) return;
+  sample_record(P, T, step, (uint32_t)group, i, tidx, tcoef);
+}
+
 }  // namespace boltz
