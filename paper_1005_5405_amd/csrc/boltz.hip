@@ -569,7 +569,7 @@ static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const b
   const int nface0 = c->p.order == 2 ? 2 * c->p.ny : 2 * (c->p.nx + c->p.ny);
   if (sample_step >= 0 && samples_with_walls(c)) {
     const int per_xcd = (nface0 + 7) / 8;
-    const int nb = (int)((c->p.n_pairs + kWallBlock - 1) / kWallBlock);
+    const int nb = (int)((c->p.n_pairs + kSampleBlock - 1) / kSampleBlock);
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     hipLaunchKernelGGL(wall_sample_kernel<0>, dim3((unsigned)(8 * per_xcd + nb * c->ngroups)), dim3(kWallBlock),
                        TablesLDS::bytes(nsum, true), st, c->P, h, nface0, per_xcd, nb, (uint32_t)sample_step,
@@ -642,9 +642,9 @@ static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* h
 static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st) {
   if (c->ngroups > 0 && c->p.n_pairs > 0) {
     const int nsum = c->n[0] + c->n[1] + c->n[2];
-    const dim3 grid((unsigned)((c->p.n_pairs + 255) / 256), (unsigned)c->ngroups);
-    hipLaunchKernelGGL(sample_kernel, grid, dim3(256), TablesLDS::bytes(nsum, true), st, c->P, s32, c->sidx,
-                       c->scoef);
+    const dim3 grid((unsigned)((c->p.n_pairs + kSampleBlock - 1) / kSampleBlock), (unsigned)c->ngroups);
+    hipLaunchKernelGGL(sample_kernel, grid, dim3(kSampleBlock), TablesLDS::bytes(nsum, true), st, c->P, s32, c->sidx,
+                       c->scoef, c->sidx == c->tidx ? 1 : 0);
     if (c->sidx != c->tidx)
       hipLaunchKernelGGL(split_sort_kernel, dim3((unsigned)c->ngroups), dim3(kSortBlock), 0, st, c->sidx, c->scoef,
                          c->tidx, c->tcoef, (int64_t)c->p.n_pairs, (unsigned)CollideLDS::half(c->nv));
@@ -1055,7 +1055,8 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     const int nf0 = !cavity ? 0 : (b->order == 2 ? 2 * ny : 2 * (nx + ny));
     const int nf1 = (cavity && b->order == 2) ? 2 * nx : 0;
     const int64_t units = stream4_units(nx, ny, c->nv);
-    const int64_t sblocks = (c->ngroups > 0 && c->p.n_pairs > 0) ? c->ngroups * ((c->p.n_pairs + 255) / 256) : 0;
+    const int64_t sblocks =
+        (c->ngroups > 0 && c->p.n_pairs > 0) ? c->ngroups * ((c->p.n_pairs + kSampleBlock - 1) / kSampleBlock) : 0;
     const int64_t sorts = (c->sidx != c->tidx) ? c->ngroups : 0;
     const int64_t nxt[5] = {(int64_t)st[0][i] + nf0, (int64_t)st[1][i] + nf1, (int64_t)st[2][i] + units,
                             (int64_t)st[3][i] + sblocks, (int64_t)st[4][i] + sorts};
@@ -1211,8 +1212,8 @@ int boltz_batch_step(boltz_batch* b, const float* h_in, float* h_out, const bolt
                          b->count, h_in, h_out, px);
   }
   if (b->total[3] > 0)
-    hipLaunchKernelGGL(sample_batch_kernel, dim3(b->total[3]), dim3(256), b->sample_lds, st, b->cavs, b->start[3],
-                       b->count, b->step_dev);
+    hipLaunchKernelGGL(sample_batch_kernel, dim3(b->total[3]), dim3(kSampleBlock), b->sample_lds, st, b->cavs,
+                       b->start[3], b->count, b->step_dev);
   if (b->total[4] > 0)
     hipLaunchKernelGGL(split_sort_batch_kernel, dim3(b->total[4]), dim3(kSortBlock), 0, st, b->cavs, b->start[4],
                        b->count);

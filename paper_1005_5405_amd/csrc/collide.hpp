@@ -201,26 +201,119 @@ __global__ __launch_bounds__(256) void debug_pairs_kernel(Params P, int64_t cell
 // once per step into two arrays, idx = {a | b << 16, a* | b* << 16} and
 // coef = {q/w_a*, q/w_b*, q/w_a, q/w_b} in FP32; a discarded pair is stored
 // with a* = a, b* = b and zero coefficients.
-__device__ __forceinline__ void sample_record(const Params& P, const TablesLDS& T, uint32_t step, uint32_t group,
-                                              int64_t i, uint2* __restrict__ tidx, float4* __restrict__ tcoef) {
-  const int64_t nt = P.n_pairs;
+__device__ __forceinline__ void sample_pair_record(const Params& P, const TablesLDS& T, uint32_t step,
+                                                   uint32_t group, int64_t i, uint2& id, float4& coef) {
   const Pair p = sample_pair(P, T, group, step, (uint32_t)i, nullptr);
-  uint2 id;
   id.x = (uint32_t)p.a | ((uint32_t)p.b << 16);
   id.y = p.as >= 0 ? ((uint32_t)p.as | ((uint32_t)p.bs << 16)) : id.x;
-  tidx[(int64_t)group * nt + i] = id;
-  tcoef[(int64_t)group * nt + i] = make_float4((float)p.kas, (float)p.kbs, (float)p.ka, (float)p.kb);
+  coef = make_float4((float)p.kas, (float)p.kbs, (float)p.ka, (float)p.kb);
 }
 
-__global__ __launch_bounds__(256) void sample_kernel(Params P, uint32_t step, uint2* __restrict__ tidx,
-                                                     float4* __restrict__ tcoef) {
+// Records are drawn by blocks of kSampleBlock threads, one record each.
+// The collision hands record m to lane m % 64 of a wavefront, and the sum
+// over the records does not depend on their order; so each full block of
+// 1024 records is stored dealt to lanes: the records whose first node a has
+// a % 64 == k fill lane k of the block's 16 wavefronts in record order, and
+// the ones beyond 16 fill the lanes left empty, in record order (key k, then
+// wavefront).  The 64 gathers of h^s[a] and the 64 adds at a of one
+// wavefront then mostly fall into distinct LDS banks.  All threads of the
+// block call this (valid: the thread holds a record; n_blk: the block's
+// record count; deal: permute, else store in place).  sh: 1280 words of LDS.
+constexpr int kSampleBlock = 1024;
+
+__device__ __forceinline__ void store_records(uint2 id, float4 coef, bool valid, int n_blk, bool deal,
+                                              uint2* __restrict__ tidx, float4* __restrict__ tcoef,
+                                              unsigned* sh) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (!deal || n_blk < kSampleBlock) {
+    if (valid) {
+      tidx[tid] = id;
+      tcoef[tid] = coef;
+    }
+    return;
+  }
+  constexpr int NW = kSampleBlock / 64, CAP = NW;
+  unsigned* cnt = sh;              // [NW][64] per-wavefront key counts, then their prefixes
+  unsigned* tot = sh + NW * 64;    // [64] records per key
+  unsigned* overp = tot + 64;      // [64] exclusive prefix of max(0, tot - CAP)
+  unsigned* defp = overp + 64;     // [64] exclusive prefix of max(0, CAP - tot)
+  const int key = (int)(id.x & 63u);
+  // rank among the wavefront's records with the same key (record order)
+  unsigned rin = 0;
+  for (int k = 0; k < 64; ++k) {
+    const unsigned long long m = __ballot(key == k);
+    if (key == k) rin = (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+    if (lane == k) cnt[w * 64 + k] = (unsigned)__popcll(m);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    unsigned run = 0;
+    for (int v = 0; v < NW; ++v) {
+      const unsigned c = cnt[v * 64 + tid];
+      cnt[v * 64 + tid] = run;
+      run += c;
+    }
+    tot[tid] = run;
+    // exclusive prefixes over the keys of the overflow and of the free lanes
+    unsigned ov = run > CAP ? run - CAP : 0u, df = run < CAP ? CAP - run : 0u;
+    unsigned sov = ov, sdf = df;
+    for (int d = 1; d < 64; d <<= 1) {
+      const unsigned a = __shfl_up(sov, d, 64), b = __shfl_up(sdf, d, 64);
+      if (lane >= d) {
+        sov += a;
+        sdf += b;
+      }
+    }
+    overp[tid] = sov - ov;
+    defp[tid] = sdf - df;
+  }
+  __syncthreads();
+  const unsigned rho = cnt[w * 64 + key] + rin;
+  int slot;
+  if (rho < (unsigned)CAP) {
+    slot = 64 * (int)rho + key;
+  } else {
+    // the L-th record past its key's lanes takes the L-th free lane
+    const unsigned L = overp[key] + (rho - CAP);
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (defp[mid] <= L) lo = mid;
+      else hi = mid - 1;
+    }
+    // the last key with defp <= L: keys without free lanes repeat the
+    // next key's prefix, so it is the key whose free lanes hold L
+    slot = 64 * (int)(tot[lo] + (L - defp[lo])) + lo;
+  }
+  tidx[slot] = id;
+  tcoef[slot] = coef;
+}
+
+// One block of kSampleBlock records of a sample group, from record base:
+// drawn (one per thread), then stored through store_records.
+__device__ __forceinline__ void sample_block(const Params& P, const TablesLDS& T, uint32_t step, uint32_t group,
+                                             int64_t base, bool deal, uint2* __restrict__ tidx,
+                                             float4* __restrict__ tcoef, unsigned* sh) {
+  const int64_t nt = P.n_pairs;
+  const int n_blk = (int)(nt - base < kSampleBlock ? nt - base : kSampleBlock);
+  const bool valid = (int)threadIdx.x < n_blk;
+  uint2 id = make_uint2(0u, 0u);
+  float4 coef = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (valid) sample_pair_record(P, T, step, group, base + threadIdx.x, id, coef);
+  store_records(id, coef, valid, n_blk, deal, tidx + (int64_t)group * nt + base, tcoef + (int64_t)group * nt + base,
+                sh);
+}
+
+// Grid: (ceil(N_t / kSampleBlock), groups).  deal: no sort follows (the
+// records go straight to the collision), so they are dealt to lanes.
+__global__ __launch_bounds__(kSampleBlock) void sample_kernel(Params P, uint32_t step, uint2* __restrict__ tidx,
+                                                              float4* __restrict__ tcoef, int deal) {
   extern __shared__ __align__(16) unsigned char dsm[];
+  __shared__ unsigned sh[1280];
   TablesLDS T;
   load_tables(P, dsm, true, T);
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.n_pairs) return;
-  sample_record(P, T, step, blockIdx.y, i, tidx, tcoef);
+  sample_block(P, T, step, blockIdx.y, (int64_t)blockIdx.x * kSampleBlock, deal != 0, tidx, tcoef, sh);
 }
 
 // Pattern of a shared-sample record for the split accumulation: bit k is
@@ -275,24 +368,24 @@ __global__ __launch_bounds__(kSortBlock) void split_sort_kernel(const uint2* __r
 // The records of every shared-sample problem of a batch in one launch:
 // start[c] = first block of problem c, which has ceil(N_t / 256) blocks per
 // group; the step number is read from the device.
-__global__ __launch_bounds__(256) void sample_batch_kernel(const BatchCav* __restrict__ cavs,
-                                                           const int* __restrict__ start, int count,
-                                                           const uint32_t* __restrict__ step_dev) {
+__global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const BatchCav* __restrict__ cavs,
+                                                                    const int* __restrict__ start, int count,
+                                                                    const uint32_t* __restrict__ step_dev) {
   extern __shared__ __align__(16) unsigned char dsm[];
+  __shared__ unsigned sh[1280];
   const int u = blockIdx.x;
   if (u >= start[count]) return;
   const int c = find_cav(start, count, u);
   const BatchCav& C = cavs[c];
   const Params& P = C.P;
-  const int nb = (int)((P.n_pairs + 255) / 256);
+  const int nb = (int)((P.n_pairs + kSampleBlock - 1) / kSampleBlock);
   const int local = u - start[c];
   const uint32_t group = (uint32_t)(local / nb);
   TablesLDS T;
   load_tables(P, dsm, true, T);
   __syncthreads();
-  const int64_t i = (int64_t)(local - (int)group * nb) * 256 + threadIdx.x;
-  if (i >= P.n_pairs) return;
-  sample_record(P, T, *step_dev, group, i, C.sidx, C.scoef);
+  sample_block(P, T, *step_dev, group, (int64_t)(local - (int)group * nb) * kSampleBlock, C.sidx == C.tidx, C.sidx,
+               C.scoef, sh);
 }
 
 // The split-pattern sort of every ACC_SPLIT shared-sample problem of a
@@ -976,10 +1069,12 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
 
 // ------------------------------------------------ faces with samples --
 // wall_kernel<PHASE> in blocks [0, 8 per_xcd) and, in the blocks after
-// them, the shared pair records of the step (sample_kernel's work with
-// kWallBlock-thread blocks; nb blocks per sample group): the records do not
+// them, the shared pair records of the step (sample_kernel's work, dealt to
+// lanes; nb blocks per sample group): the records do not
 // depend on h, so they are drawn while the face reductions (one workgroup
 // per face) leave most of the GPU idle.  Dynamic LDS: the sampler tables.
+static_assert(kWallBlock == kSampleBlock, "one block shape for faces and samples");
+
 template <int PHASE>
 __global__ __launch_bounds__(kWallBlock) void wall_sample_kernel(Params P, const float* __restrict__ h, int nface,
                                                                  int per_xcd, int nb, uint32_t step,
@@ -995,13 +1090,12 @@ __global__ __launch_bounds__(kWallBlock) void wall_sample_kernel(Params P, const
     return;
   }
   extern __shared__ __align__(16) unsigned char dsm[];
+  __shared__ unsigned sh[1280];
   TablesLDS T;
   load_tables(P, dsm, true, T);
   __syncthreads();
   const int b = (int)blockIdx.x - nwb, group = b / nb;
-  const int64_t i = (int64_t)(b - group * nb) * kWallBlock + threadIdx.x;
-  if (i >= P.n_pairs) return;
-  sample_record(P, T, step, (uint32_t)group, i, tidx, tcoef);
+  sample_block(P, T, step, (uint32_t)group, (int64_t)(b - group * nb) * kSampleBlock, true, tidx, tcoef, sh);
 }
 
 }  // namespace boltz
