@@ -47,9 +47,9 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 # kernels), each scaled by what the counter reads for a device copy of the
 # 131 MB state (bench.py --calibrate); valid only for the kernel sources whose
 # SHA-256 is recorded (profiles/collide_counters_cavity64.md).
-TRAFFIC = {"sha256": "3fcdf5f7ab01b0ad56a13bb9f7d0f191631d0cbd37f0a869bb2fb353ade800a1",
-           "fetch_kib": 66449.1 + 106.0, "write_kib": 128000.0 + 468.8,
-           "fetch_scale": 128000.0 / 64017.9, "write_scale": 1.0}
+TRAFFIC = {"sha256": "d14145b9c0d7c225d4aca7534bf9bf49ce16af2f830b471150aad56fb6769777",
+           "fetch_kib": 66456.2 + 106.0, "write_kib": 128000.0 + 468.8,
+           "fetch_scale": 128000.0 / 64025.4, "write_scale": 1.0}
 KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
 
 
@@ -105,7 +105,7 @@ def cpu_baseline(preset, seconds_budget: float):
 def run(pkg, torch, preset, steps: int, warmup: int):
     """Warm up, then time `steps` whole steps (boltz_step, the entry point of
     the hot path: streaming, then collision, with the step's shared pair
-    records drawn in the first face launch).  A second pass of `steps`
+    records drawn in the last face launch).  A second pass of `steps`
     steps over the same workload calls the two halves (boltz_stream,
     boltz_collide) separately with HIP events on the launch stream between
     them: the kernel-group durations (events between launches add ~10 us

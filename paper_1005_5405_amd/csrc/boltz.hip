@@ -550,14 +550,14 @@ static int ensure_ratio(boltz_ctx* c, const WallArgs& W, const boltz_walls* wall
   return BOLTZ_OK;
 }
 
-// Shared pair records that can be drawn in the first face launch: a table
+// Shared pair records that can be drawn in the last face launch: a table
 // written directly by the sampler (no split-mode sort after it).
 static bool samples_with_walls(const boltz_ctx* c) {
   return c->ngroups > 0 && c->p.n_pairs > 0 && c->sidx == c->tidx;
 }
 
 // The face densities; with sample_step >= 0 (and samples_with_walls) the
-// records of that step are drawn in the first face launch.
+// records of that step are drawn in the last face launch.
 static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const boltz_walls* walls,
                         hipStream_t st, int64_t sample_step = -1) {
   const int rc = ensure_ratio(c, W, walls, st);
@@ -566,19 +566,28 @@ static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const b
     const int per_xcd = (nface + 7) / 8;
     hipLaunchKernelGGL(kern, dim3(8 * per_xcd), dim3(kWallBlock), 0, st, c->P, h, nface, per_xcd);
   };
-  const int nface0 = c->p.order == 2 ? 2 * c->p.ny : 2 * (c->p.nx + c->p.ny);
-  if (sample_step >= 0 && samples_with_walls(c)) {
-    const int per_xcd = (nface0 + 7) / 8;
+  // order 2: x faces first, then the y faces, which read the x-face
+  // densities for their x-swept rows; the pair records go with the last
+  // (and, for order 2, longer) launch
+  const bool with_samples = sample_step >= 0 && samples_with_walls(c);
+  auto launch_last = [&](auto kern, auto kern_s, int nface) {
+    if (!with_samples) {
+      launch(kern, nface);
+      return;
+    }
+    const int per_xcd = (nface + 7) / 8;
     const int nb = (int)((c->p.n_pairs + kSampleBlock - 1) / kSampleBlock);
     const int nsum = c->n[0] + c->n[1] + c->n[2];
-    hipLaunchKernelGGL(wall_sample_kernel<0>, dim3((unsigned)(8 * per_xcd + nb * c->ngroups)), dim3(kWallBlock),
-                       TablesLDS::bytes(nsum, true), st, c->P, h, nface0, per_xcd, nb, (uint32_t)sample_step,
+    hipLaunchKernelGGL(kern_s, dim3((unsigned)(8 * per_xcd + nb * c->ngroups)), dim3(kWallBlock),
+                       TablesLDS::bytes(nsum, true), st, c->P, h, nface, per_xcd, nb, (uint32_t)sample_step,
                        c->tidx, c->tcoef);
+  };
+  if (c->p.order == 2) {
+    launch(wall_kernel<0>, 2 * c->p.ny);
+    launch_last(wall_kernel<1>, wall_sample_kernel<1>, 2 * c->p.nx);
   } else {
-    launch(wall_kernel<0>, nface0);
+    launch_last(wall_kernel<0>, wall_sample_kernel<0>, 2 * (c->p.nx + c->p.ny));
   }
-  // order 2: the y faces read the x-face densities for the x-swept rows
-  if (c->p.order == 2) launch(wall_kernel<1>, 2 * c->p.nx);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "wall_kernel launch");
 }

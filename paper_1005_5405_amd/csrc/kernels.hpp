@@ -255,11 +255,27 @@ __global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, Wa
   }
 }
 
+// Outgoing nodes of a face along its normal axis: the indices i0 .. i1 - 1
+// of the (increasing) velocity table with sgn v < 0.
+__device__ __forceinline__ void outgoing_range(const double* v, int n, int sgn, int& i0, int& i1) {
+  // first index with v >= 0 (sgn = 1: the outgoing ones precede it) or with
+  // v > 0 (sgn = -1: the outgoing ones start there)
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sgn > 0 ? (v[mid] < 0.0) : (v[mid] <= 0.0)) lo = mid + 1;
+    else hi = mid;
+  }
+  if (sgn > 0) { i0 = 0; i1 = lo; }
+  else { i0 = lo; i1 = n; }
+}
+
 // B of one face: sum over the outgoing nodes of |v_n| w_j hhat_j (hhat as in
-// face_density), over j = j0, j0 + step, ... below nv, U nodes per pass
-// with every load of a pass issued before it is used.  A y face of order 2
-// away from the corner columns reads the three cells of each x sweep
-// directly (no ghost value is needed there).
+// face_density).  The outgoing nodes (a range of the normal axis) are
+// numbered t = 0, 1, ... in velocity order; this thread takes t = j0, j0 +
+// step, ..., U nodes per pass with every load of a pass issued before it
+// is used.  A y face of order 2 away from the corner columns reads the three
+// cells of each x sweep directly (no ghost value is needed there).
 template <int U>
 __device__ double face_b(const Params& P, const float* h, int wall, int pos, int order,
                          double nwl0, double nwl1, double nwr0, double nwr1, int j0, int step) {
@@ -278,16 +294,26 @@ __device__ double face_b(const Params& P, const float* h, int wall, int pos, int
   const bool corner = ysw && (pos < 2 || pos >= nx - 2);
   const float* ca = h + cell_off(P, ax_, ay_);
   const float* cb = h + cell_off(P, bx_, by_);
+  int i0, i1;
+  outgoing_range(P.vtab + (nax ? kMaxAxis : 0), P.n[nax], sgn, i0, i1);
+  // the outgoing nodes as a (c0, c1, n2) box: c0 = x nodes, c1 = y nodes
+  const int c0 = nax ? P.n[0] : i1 - i0, c1 = nax ? i1 - i0 : n1;
+  const int nt = c0 * c1 * n2;
   double b = 0.0;
-  NodeWalk walk(j0, step, n1, n2);
-  for (int jb = j0; jb < nv; jb += U * step) {
-    int jxs[U], jys[U], jzs[U];
+  if (nt <= 0) return b;
+  NodeWalk walk(j0, step, c1, n2);
+  for (int tb = j0; tb < nt; tb += U * step) {
+    int jxs[U], jys[U], jzs[U], js[U];
     float a0[U], a1[U], a2[U], b0[U], b1[U], b2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      jxs[u] = walk.jx; jys[u] = walk.jy; jzs[u] = walk.jz;
+      const bool in = tb + u * step < nt;
+      jxs[u] = in ? walk.jx + (nax ? 0 : i0) : 0;
+      jys[u] = in ? walk.jy + (nax ? i0 : 0) : 0;
+      jzs[u] = in ? walk.jz : 0;
       walk.next();
-      const int j = (jb + u * step < nv) ? jb + u * step : j0;
+      const int j = (jxs[u] * n1 + jys[u]) * n2 + jzs[u];
+      js[u] = j;
       a0[u] = ca[j];
       b0[u] = (order == 2) ? cb[j] : 0.0f;
       a1[u] = a2[u] = b1[u] = b2[u] = 0.0f;
@@ -301,11 +327,9 @@ __device__ double face_b(const Params& P, const float* h, int wall, int pos, int
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = jb + u * step;
-      if (j >= nv) continue;
-      const int jx = jxs[u], jy = jys[u], jz = jzs[u];
+      if (tb + u * step >= nt) continue;
+      const int j = js[u], jx = jxs[u], jy = jys[u], jz = jzs[u];
       const double vn = nax ? P.vtab[kMaxAxis + jy] : P.vtab[jx];
-      if (!(sgn * vn < 0.0)) continue;
       const double an = fabs(vn);
       const double aw = an * ((P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz]);
       double ha = a0[u], hb = b0[u];
