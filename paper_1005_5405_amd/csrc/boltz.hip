@@ -427,6 +427,14 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     P.n[k] = c->n[k];
     P.a[k] = c->a[k];
     P.inv_cell[k] = c->inv_cell[k];
+    // sign ranges of the (increasing) node velocities of axis k
+    int neg = 0, pos = 0;
+    for (int i = 0; i < c->n[k]; ++i) {
+      if (c->v[k][i] < 0.0) neg = i + 1;
+      if (c->v[k][i] <= 0.0) pos = i + 1;
+    }
+    P.vneg[k] = neg;
+    P.vpos[k] = pos;
   }
   P.order = p->order;
   P.bc = p->bc;

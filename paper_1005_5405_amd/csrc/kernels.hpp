@@ -32,6 +32,7 @@ enum { WALL_LEFT = 0, WALL_RIGHT = 1, WALL_BOTTOM = 2, WALL_TOP = 3 };
 struct Params {
   int nx, ny, nv;
   int n[3];
+  int vneg[3], vpos[3];   // per axis: nodes 0 .. vneg - 1 move with v < 0, vpos .. n - 1 with v > 0
   int order, bc;
   int64_t n_pairs, sample_group;
   uint32_t key0, key1, cavity, mix16;
@@ -255,21 +256,6 @@ __global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, Wa
   }
 }
 
-// Outgoing nodes of a face along its normal axis: the indices i0 .. i1 - 1
-// of the (increasing) velocity table with sgn v < 0.
-__device__ __forceinline__ void outgoing_range(const double* v, int n, int sgn, int& i0, int& i1) {
-  // first index with v >= 0 (sgn = 1: the outgoing ones precede it) or with
-  // v > 0 (sgn = -1: the outgoing ones start there)
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (sgn > 0 ? (v[mid] < 0.0) : (v[mid] <= 0.0)) lo = mid + 1;
-    else hi = mid;
-  }
-  if (sgn > 0) { i0 = 0; i1 = lo; }
-  else { i0 = lo; i1 = n; }
-}
-
 // B of one face: sum over the outgoing nodes of |v_n| w_j hhat_j (hhat as in
 // face_density).  The outgoing nodes (a range of the normal axis) are
 // numbered t = 0, 1, ... in velocity order; this thread takes t = j0, j0 +
@@ -294,8 +280,9 @@ __device__ double face_b(const Params& P, const float* h, int wall, int pos, int
   const bool corner = ysw && (pos < 2 || pos >= nx - 2);
   const float* ca = h + cell_off(P, ax_, ay_);
   const float* cb = h + cell_off(P, bx_, by_);
-  int i0, i1;
-  outgoing_range(P.vtab + (nax ? kMaxAxis : 0), P.n[nax], sgn, i0, i1);
+  // outgoing along the normal: v < 0 at the left / bottom wall, v > 0 at
+  // the right / top wall
+  const int i0 = sgn > 0 ? 0 : P.vpos[nax], i1 = sgn > 0 ? P.vneg[nax] : P.n[nax];
   // the outgoing nodes as a (c0, c1, n2) box: c0 = x nodes, c1 = y nodes
   const int c0 = nax ? P.n[0] : i1 - i0, c1 = nax ? i1 - i0 : n1;
   const int nt = c0 * c1 * n2;
@@ -318,8 +305,7 @@ __device__ double face_b(const Params& P, const float* h, int wall, int pos, int
       b0[u] = (order == 2) ? cb[j] : 0.0f;
       a1[u] = a2[u] = b1[u] = b2[u] = 0.0f;
       if (ysw && !corner) {
-        const double vx = P.vtab[jxs[u]];
-        const int sx = vx > 0.0 ? 1 : (vx < 0.0 ? -1 : 0);
+        const int sx = jxs[u] < P.vneg[0] ? -1 : (jxs[u] >= P.vpos[0] ? 1 : 0);
         const int64_t o1 = -(int64_t)sx * nv;
         a1[u] = ca[j + o1]; a2[u] = ca[j + 2 * o1];
         b1[u] = cb[j + o1]; b2[u] = cb[j + 2 * o1];
@@ -337,7 +323,7 @@ __device__ double face_b(const Params& P, const float* h, int wall, int pos, int
         if (corner) {
           ha = xswept_value(P, h, ax_, ay_, j, jx, jy, jz, nwl0, nwr0);
           hb = xswept_value(P, h, bx_, by_, j, jx, jy, jz, nwl1, nwr1);
-        } else if (P.vtab[jx] != 0.0) {
+        } else if (jx < P.vneg[0] || jx >= P.vpos[0]) {
           const float Cx = P.cour[jx], Cx2 = P.cour2[jx];
           ha = bw_update(a0[u], a1[u], a2[u], Cx, Cx2);
           hb = bw_update(b0[u], b1[u], b2[u], Cx, Cx2);
