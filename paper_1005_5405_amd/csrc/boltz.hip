@@ -741,7 +741,7 @@ int boltz_moments(boltz_ctx* c, const float* h, const boltz_walls* walls, double
     const int rc = ensure_ratio(c, W, walls, st);
     if (rc != BOLTZ_OK) return rc;
   }
-  hipLaunchKernelGGL(moments_kernel, dim3((unsigned)c->ncells), dim3(256), 0, st, c->P, W, h, mom,
+  hipLaunchKernelGGL(moments_kernel, dim3((unsigned)c->ncells), dim3(kMomentsBlock), 0, st, c->P, W, h, mom,
                      lid_shear ? 1 : 0);
   if (lid_shear) hipLaunchKernelGGL(lid_reduce_kernel, dim3(1), dim3(64), 0, st, c->P, lid_shear);
   const hipError_t e = hipGetLastError();

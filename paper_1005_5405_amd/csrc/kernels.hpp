@@ -760,34 +760,77 @@ __global__ __launch_bounds__(kStream4Block) void stream4_batch_kernel(const Batc
 namespace boltz {
 
 // ------------------------------------------------------------------- S6 --
-__global__ __launch_bounds__(256) void moments_kernel(Params P, WallArgs W, const float* __restrict__ h,
-                                                      double* __restrict__ mom, int want_lid) {
-  __shared__ double red[11 * 4];
-  const int nv = P.nv, n1 = P.n[1], n2 = P.n[2];
-  const int64_t cell = blockIdx.x;
+// One workgroup per cell.  The 11 sums w h {1, v, |v|^2, v_i v_k} come from
+// z moments Z_p = sum_z omega_z v_z^p h (p <= 2) of each velocity row (one
+// row per thread, the factors omega_z v_z^p from the table zmom through
+// scalar loads, rows read four nodes at a time when nv_z % 4 == 0), then
+// the row's terms: W = omega_x omega_y, a = v_x, b = v_y.
+constexpr int kMomentsBlock = 512;
+
+__global__ __launch_bounds__(kMomentsBlock) void moments_kernel(Params P, WallArgs W, const float* __restrict__ h,
+                                                                double* __restrict__ mom, int want_lid) {
+  __shared__ double red[20 * (kMomentsBlock / 64)];
+  const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  // the top row first: its workgroups also sum the lid face (longer), so
+  // they start before the others rather than trail them
+  const int64_t ncells = (int64_t)P.nx * P.ny;
+  const int64_t cell = ((int64_t)blockIdx.x + (int64_t)(P.ny - 1) * P.nx) % ncells;
   const float* src = h + cell * nv;
+  const const_f64* zc = (const const_f64*)P.zmom;
+  const bool vec = (n2 & 3) == 0 && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
   double s[11];
 #pragma unroll
   for (int i = 0; i < 11; ++i) s[i] = 0.0;
-  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
-    int jx, jy, jz;
-    node_decode(j, n1, n2, jx, jy, jz);
-    const double v1 = P.vtab[jx], v2 = P.vtab[kMaxAxis + jy], v3 = P.vtab[2 * kMaxAxis + jz];
-    const double w = (P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz];
-    const double wh = w * (double)src[j];
-    s[0] += wh;
-    s[1] += wh * v1;
-    s[2] += wh * v2;
-    s[3] += wh * v3;
-    s[4] += wh * ((v1 * v1 + v2 * v2) + v3 * v3);
-    s[5] += wh * v1 * v1;
-    s[6] += wh * v1 * v2;
-    s[7] += wh * v1 * v3;
-    s[8] += wh * v2 * v2;
-    s[9] += wh * v2 * v3;
-    s[10] += wh * v3 * v3;
+  for (int row = threadIdx.x; row < n0 * n1; row += kMomentsBlock) {
+    const int jx = row / n1, jy = row - (row / n1) * n1;
+    double Z0 = 0.0, Z1 = 0.0, Z2 = 0.0;
+    auto node = [&](int jz, float hv) {
+      const const_f64* z = zc + 8 * jz;
+      const double x = (double)hv;
+      Z0 = fma(z[0], x, Z0);
+      Z1 = fma(z[1], x, Z1);
+      Z2 = fma(z[2], x, Z2);
+    };
+    if (vec) {
+      const f32x4* r4 = reinterpret_cast<const f32x4*>(src + row * n2);
+      for (int q = 0; q < (n2 >> 2); ++q) {
+        const f32x4 v = r4[q];
+        node(4 * q, v.x);
+        node(4 * q + 1, v.y);
+        node(4 * q + 2, v.z);
+        node(4 * q + 3, v.w);
+      }
+    } else {
+      for (int jz = 0; jz < n2; ++jz) node(jz, src[row * n2 + jz]);
+    }
+    const double Wr = P.omtab[jx] * P.omtab[kMaxAxis + jy], a = P.vtab[jx], b = P.vtab[kMaxAxis + jy];
+    const double T0 = Wr * Z0, T1 = Wr * Z1;
+    s[0] += T0;
+    s[1] += a * T0;
+    s[2] += b * T0;
+    s[3] += T1;
+    s[5] += (a * a) * T0;
+    s[6] += (a * b) * T0;
+    s[7] += a * T1;
+    s[8] += (b * b) * T0;
+    s[9] += b * T1;
+    s[10] += Wr * Z2;
   }
-  block_sum<11>(s, red);
+  s[4] = (s[5] + s[8]) + s[10];
+  {
+    // block sums through the 20-value wavefront fold (lanes 0..10 of
+    // wavefront 0 receive the totals), then broadcast in wavefront 0
+    double v[20];
+#pragma unroll
+    for (int i = 0; i < 20; ++i) v[i] = i < 11 ? s[i] : 0.0;
+    const int rows = n0 * n1;
+    const int nwd = rows >= kMomentsBlock ? kMomentsBlock / 64 : (rows + 63) / 64;
+    const double t = block_sum20_w0<kMomentsBlock>(v, red, nwd);
+    if (threadIdx.x < 64) {
+#pragma unroll
+      for (int i = 0; i < 11; ++i) s[i] = lane_value(t, i);
+    }
+  }
   if (threadIdx.x == 0) {
     // V0 units: n = 1 + eps rho, u = U/n, theta = ((2/3)E - rho)/n - (2/3) eps |u|^2,
     // Pi_ij = 2 P_ij - 2 eps n u_i u_j
@@ -808,17 +851,20 @@ __global__ __launch_bounds__(256) void moments_kernel(Params P, WallArgs W, cons
   if (want_lid && iy == P.ny - 1) {
     // lid face: gas-side values of this top cell for v_y > 0, wall emission
     // with the first-order face density for v_y < 0
+    __syncthreads();  // red is reused
     const double nwt = face_density(P, h, WALL_TOP, ix, 1, 0, 0, 0, 0, red);
+    // Phi_w / Phi0 of the lid from its table (built for these walls; the
+    // same values wall_ratio gives)
+    const double* R = ratio_row(P, WALL_TOP, ix);
     double pxy[1] = {0.0};
     for (int j = threadIdx.x; j < nv; j += blockDim.x) {
       int jx, jy, jz;
       node_decode(j, n1, n2, jx, jy, jz);
-      const double v1 = P.vtab[jx], v2 = P.vtab[kMaxAxis + jy], v3 = P.vtab[2 * kMaxAxis + jz];
+      const double v1 = P.vtab[jx], v2 = P.vtab[kMaxAxis + jy];
       const double w = (P.omtab[jx] * P.omtab[kMaxAxis + jy]) * P.omtab[2 * kMaxAxis + jz];
       double hh = 0.0;
       if (v2 > 0.0) hh = (double)src[j];
-      else if (v2 < 0.0)
-        hh = (nwt * wall_ratio(v1, v2, v3, W.lid_u, W.tau[WALL_TOP], W.tfac[WALL_TOP]) - 1.0) * P.inv_eps;
+      else if (v2 < 0.0) hh = (nwt * R[j] - 1.0) * P.inv_eps;
       pxy[0] += w * v1 * v2 * hh;
     }
     block_sum<1>(pxy, red);
