@@ -47,9 +47,9 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 # kernels), each scaled by what the counter reads for a device copy of the
 # 131 MB state (bench.py --calibrate); valid only for the kernel sources whose
 # SHA-256 is recorded (profiles/collide_counters_cavity64.md).
-TRAFFIC = {"sha256": "d14145b9c0d7c225d4aca7534bf9bf49ce16af2f830b471150aad56fb6769777",
-           "fetch_kib": 66456.2 + 106.0, "write_kib": 128000.0 + 468.8,
-           "fetch_scale": 128000.0 / 64025.4, "write_scale": 1.0}
+TRAFFIC = {"sha256": "c5a670f36aef292e0dfde33b828d2f5e3efd16ba7cd85b7949960f7c4ba61fb3",
+           "fetch_kib": 66418.8 + 120.5, "write_kib": 128000.0 + 468.8,
+           "fetch_scale": 128000.0 / 64018.3, "write_scale": 1.0}
 KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
 
 
