@@ -299,3 +299,37 @@ def test_full_size_sampled_parity(lib, oracle_mod, torch_mod, which):
         assert d.max() <= 1e-5 * np.abs(ref_c[k]).max(), (which, cells[k])
         assert (d * w).max() <= 1e-5 * (np.abs(ref_c[k]) * w).max(), (which, cells[k])
     assert g.read_status() == 0
+
+
+# Shared-sample steps through boltz_step: the pair records are drawn in the
+# last face launch and every full block of 1024 records is stored dealt to
+# lanes (a permutation, so the collision equals the oracle's); N_t = 2348 has
+# two full blocks and a partial one.  Order 2 draws them with the y faces,
+# order 1 with its single face launch; grids with v = 0 nodes included.
+@pytest.mark.parametrize("case", [
+    dict(order=2, nx=10, ny=9, nv=(12, 12, 12), vmax=4.5),
+    dict(order=1, nx=7, ny=11, nv=(8, 8, 8), vmax=3.5),
+    dict(order=2, nx=9, ny=6, nv=(7, 5, 8), vmax=(3.0, 2.5, 3.5)),
+])
+def test_shared_sample_step_parity(lib, oracle_mod, torch_mod, case):
+    from paper_1005_5405_amd import inputs
+
+    kw = dict(case, delta=10.0, eps=0.1, n_pairs=2348, sample_group=0, mix16=4)
+    _say("shared-sample step", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    h = inputs.random_field(o.shape, seed=17, scale=0.3).astype(np.float32).astype(np.float64)
+    walls_o, walls_g = oracle_mod.Walls(**WALLS), lib.Walls(**WALLS)
+    for step in (3, 4):
+        ref = o.step(h, walls_o, step)
+        hout = g.empty()
+        g.step(_dev(torch_mod, h), hout, walls_g, step)
+        torch_mod.cuda.synchronize()
+        rel, wrel = _errs(o, _host(hout), ref)
+        assert rel <= 1e-5 and wrel <= 1e-5, (step, rel, wrel)
+        # the two halves called separately (records drawn by sample_kernel) agree
+        hs, h2 = g.empty(), g.empty()
+        g.stream(_dev(torch_mod, h), hs, walls_g)
+        g.collide(hs, h2, step)
+        torch_mod.cuda.synchronize()
+        assert torch_mod.equal(h2, hout), step
+    assert g.read_status() == 0
