@@ -79,7 +79,7 @@ typedef struct boltz_problem {
   int64_t n_pairs;       /* N_t of Eq. monteCarloInt, pairs per cell per step*/
   int64_t sample_group;  /* G: cells cell/G share a pair stream; 0 = all.    */
                          /* G != 1: the pairs of every group are drawn once */
-                         /* per step into a context table (16 B per pair)   */
+                         /* per step into a context table (24 B per pair)   */
   uint64_t seed;         /* Philox4x32-10 key (low word, high word)          */
   uint32_t cavity_id;    /* fourth Philox counter word                       */
   uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT        */

@@ -366,8 +366,8 @@ __global__ __launch_bounds__(kSortBlock) void split_sort_kernel(const uint2* __r
 }
 
 // The records of every shared-sample problem of a batch in one launch:
-// start[c] = first block of problem c, which has ceil(N_t / 256) blocks per
-// group; the step number is read from the device.
+// start[c] = first block of problem c, which has ceil(N_t / kSampleBlock)
+// blocks per group; the step number is read from the device.
 __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const BatchCav* __restrict__ cavs,
                                                                     const int* __restrict__ start, int count,
                                                                     const uint32_t* __restrict__ step_dev) {
