@@ -861,18 +861,20 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
     early();
     __syncthreads();
   }
-  // ---- (3) h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store
+  // ---- (3) h^{n+1} = h^c + F^c (x . psi) / eps, one coalesced store; the
+  // FP32 array is left cleared for the next cell
   bool finite = true;
   auto out_of = [&](double hc, double xpsi) { return (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc); };
   if (vec4 && !defect) {
     // four nodes (one z quadruple of a row) per thread and access
-    const f32x4* a4 = reinterpret_cast<const f32x4*>(accf);
+    f32x4* a4 = reinterpret_cast<f32x4*>(accf);
     f32x4* d4 = reinterpret_cast<f32x4*>(dst);
     NodeWalk nw4(4 * tid, 4 * BLOCK, n1, n2);
     if (correct) {
 #pragma unroll NU
       for (int i = tid; i < (nv >> 2); i += BLOCK, nw4.next()) {
         const f32x4 c = a4[i];
+        a4[i] = f32x4{0.f, 0.f, 0.f, 0.f};
         const double xa = T.xt[nw4.jx] + T.xt[n0 + nw4.jy];
         const double* xz = T.xt + n0 + n1 + nw4.jz;
         f32x4 o;
@@ -887,6 +889,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
 #pragma unroll NU
       for (int i = tid; i < (nv >> 2); i += BLOCK) {
         const f32x4 c = a4[i];
+        a4[i] = f32x4{0.f, 0.f, 0.f, 0.f};
         finite = finite && isfinite(c.x) && isfinite(c.y) && isfinite(c.z) && isfinite(c.w);
         d4[i] = c;
       }
@@ -898,6 +901,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
     for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
       const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
       const double hc = (double)accf[j];
+      accf[j] = 0.0f;
       float out = (float)hc;
       if (correct) out = out_of(hc, (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz]);
       finite = finite && isfinite(out);
@@ -968,6 +972,8 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   if (vec && cell < ncells) pre.load(hs_g + cell * nv, tid, BLOCK, nv4);
   for (; cell < ncells; cell += gridDim.x) {
     // ---- h^s tile in, accumulators cleared
+    // a staged cell finds its tile in place and the FP32 array and the
+    // 64-bit accumulators cleared by the previous cell's passes
     if (!staged) {
       if (vec) {
         pre.store(hs, tid, BLOCK, nv4);
@@ -975,9 +981,9 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
         const float* src = hs_g + cell * nv;
         for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
       }
+      clear(t0, t1);
+      __syncthreads();
     }
-    clear(t0, t1);
-    __syncthreads();
     const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
     const int64_t next = cell + gridDim.x;
     staged = false;
