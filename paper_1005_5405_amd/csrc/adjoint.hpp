@@ -174,7 +174,14 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
   for (int64_t cell = blockIdx.x; cell < ncells; cell += gridDim.x) {
     const float* src = hs_g + cell * nv;
     const double* lo = lo_g + cell * nv;
-    for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
+    if ((nv & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      float4* d4 = reinterpret_cast<float4*>(hs);
+#pragma unroll 4
+      for (int j = tid; j < (nv >> 2); j += BLOCK) d4[j] = s4[j];
+    } else {
+      for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
+    }
     {
       uint4* z = reinterpret_cast<uint4*>(accf);
       const int nz = (int)(CollideLDS::acc(nv, ACC_FIXED) / 16);
@@ -196,6 +203,8 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
       block_sum20_lds<BLOCK>(acc, red, tot);
       double zs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       NodeWalk walk(tid, BLOCK, n1, n2);
+      // (unrolled: the global loads of lo of several nodes in flight together)
+#pragma unroll 4
       for (int j = tid; j < nv; j += BLOCK, walk.next()) {
         const double u = lo[j] * fma(eps, (double)accf[j], 1.0);
         const double a = vx[walk.jx], b = vy[walk.jy], c = vz[walk.jz];
@@ -236,6 +245,7 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
     {
       double mx = 0.0;
       NodeWalk walk(tid, BLOCK, n1, n2);
+#pragma unroll 4
       for (int j = tid; j < nv; j += BLOCK, walk.next()) {
         double lI;
         const double lhc = lam_hc(lo[j], walk.jx, walk.jy, walk.jz, lI);
@@ -271,6 +281,7 @@ __global__ __launch_bounds__(BLOCK) void collide_adj_kernel(Params P, const floa
     double* dst = ls_g + cell * nv;
     {
       NodeWalk walk(tid, BLOCK, n1, n2);
+#pragma unroll 4
       for (int j = tid; j < nv; j += BLOCK, walk.next()) {
         double v;
         if (FIXED) {
