@@ -519,18 +519,22 @@ __global__ __launch_bounds__(kOrder1AdjBlock) void order1_adj_kernel(Params P, c
 // top walls, one entry per bottom face.  faces: 1 = x faces, 2 = y faces.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(Params P, const double* __restrict__ gpart,
                                                           double* __restrict__ grad, int faces) {
-  const int nx = P.nx, ny = P.ny, t = threadIdx.x;
-  if (t < 4) {
+  const int nx = P.nx, ny = P.ny, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // wavefront w sums the face partials of wall parameter w, all loads of a
+  // lane issued together, then a wavefront tree sum
+  {
+    const bool on = (w == 0 || w == 3) ? (faces & 2) != 0 : (faces & 1) != 0;
+    const int n = (w == 0 || w == 3) ? nx : ny;
     double s = 0.0;
-    if (t == 0 && (faces & 2))
-      for (int i = 0; i < nx; ++i) s += gpart[2 * (2 * ny + nx + i)];
-    if (t == 1 && (faces & 1))
-      for (int i = 0; i < ny; ++i) s += gpart[2 * i + 1];
-    if (t == 2 && (faces & 1))
-      for (int i = 0; i < ny; ++i) s += gpart[2 * (ny + i) + 1];
-    if (t == 3 && (faces & 2))
-      for (int i = 0; i < nx; ++i) s += gpart[2 * (2 * ny + nx + i) + 1];
-    grad[t] += s;
+    if (on) {
+      for (int i = lane; i < n; i += 64) {
+        const int k = w == 0 ? 2 * (2 * ny + nx + i) : (w == 1 ? 2 * i + 1 : (w == 2 ? 2 * (ny + i) + 1
+                                                                                   : 2 * (2 * ny + nx + i) + 1));
+        s += gpart[k];
+      }
+    }
+    s = wave_sum(s);
+    if (lane == 0) grad[w] += s;
   }
   if (faces & 2)
     for (int i = t; i < nx; i += blockDim.x) grad[4 + i] += gpart[2 * (2 * ny + i) + 1];
@@ -543,10 +547,14 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(Params P, const double
 // workgroup per top face adds its part to lam (top cells, v_y > 0 nodes)
 // and writes the face's partials gpart[2 ix] (lid velocity) and
 // gpart[2 ix + 1] (lid temperature).
-__global__ __launch_bounds__(256) void lid_adj_kernel(Params P, WallArgs W, const float* __restrict__ h,
-                                                      double weight, double* __restrict__ lam,
-                                                      double* __restrict__ gpart) {
-  __shared__ double red[5 * 4];
+// One workgroup of kLidAdjBlock threads per top face (the three node loops
+// are latency bound: more threads per face, fewer nodes per thread).
+constexpr int kLidAdjBlock = 1024;
+
+__global__ __launch_bounds__(kLidAdjBlock) void lid_adj_kernel(Params P, WallArgs W, const float* __restrict__ h,
+                                                               double weight, double* __restrict__ lam,
+                                                               double* __restrict__ gpart) {
+  __shared__ double red[5 * (kLidAdjBlock / 64)];
   const int ix = blockIdx.x;
   const int nv = P.nv, n1 = P.n[1], n2 = P.n[2];
   const double nwt = face_density(P, h, WALL_TOP, ix, 1, 0, 0, 0, 0, red);

@@ -898,7 +898,8 @@ int boltz_lid_shear_adjoint(boltz_ctx* c, const float* h, const boltz_walls* wal
   const WallArgs W = make_walls(walls);
   const int rc = ensure_ratio(c, W, walls, st);
   if (rc != BOLTZ_OK) return rc;
-  hipLaunchKernelGGL(lid_adj_kernel, dim3((unsigned)c->p.nx), dim3(256), 0, st, c->P, W, h, weight, lam, c->gpart);
+  hipLaunchKernelGGL(lid_adj_kernel, dim3((unsigned)c->p.nx), dim3(kLidAdjBlock), 0, st, c->P, W, h, weight, lam,
+                     c->gpart);
   if (grad_walls) hipLaunchKernelGGL(lid_grad_kernel, dim3(1), dim3(64), 0, st, c->P, c->gpart, grad_walls);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "lid shear adjoint launch");
