@@ -47,9 +47,9 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 # kernels), each scaled by what the counter reads for a device copy of the
 # 131 MB state (bench.py --calibrate); valid only for the kernel sources whose
 # SHA-256 is recorded (profiles/collide_counters_cavity64.md).
-TRAFFIC = {"sha256": "c5a670f36aef292e0dfde33b828d2f5e3efd16ba7cd85b7949960f7c4ba61fb3",
-           "fetch_kib": 66418.8 + 120.5, "write_kib": 128000.0 + 468.8,
-           "fetch_scale": 128000.0 / 64018.3, "write_scale": 1.0}
+TRAFFIC = {"sha256": "8a5911f2771dadc3725ed51f540275b7de852e8031af9f1d17f1adfa74a8c72d",
+           "fetch_kib": 66437.0 + 113.0, "write_kib": 128000.0 + 468.8,
+           "fetch_scale": 128000.0 / 64024.6, "write_scale": 1.0}
 KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
 
 
