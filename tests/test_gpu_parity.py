@@ -205,12 +205,15 @@ def test_non_spd_correction_is_reported(lib, oracle_mod, torch_mod):
     assert g.read_status() == 0
 
 
-@pytest.mark.parametrize("order", [2, 1])
-def test_moments_and_lid_shear_parity(lib, oracle_mod, torch_mod, order):
+# moments: rows read four nodes at a time (nv_z % 4 == 0) or one by one,
+# fewer or more velocity rows than the 512 threads of a workgroup
+@pytest.mark.parametrize("order,nv,vmax", [(2, 12, 4.5), (1, 12, 4.5), (2, (7, 5, 9), (3.0, 2.5, 3.5)),
+                                           (2, (24, 24, 8), (5.0, 5.0, 3.0))])
+def test_moments_and_lid_shear_parity(lib, oracle_mod, torch_mod, order, nv, vmax):
     from paper_1005_5405_amd import inputs
 
-    _say("moments", order)
-    g, o = _pair(lib, oracle_mod, nx=12, ny=10, nv=12, vmax=4.5, delta=10.0, eps=0.1, n_pairs=100, order=order)
+    _say("moments", order, nv)
+    g, o = _pair(lib, oracle_mod, nx=12, ny=10, nv=nv, vmax=vmax, delta=10.0, eps=0.1, n_pairs=100, order=order)
     h = inputs.random_field(o.shape, seed=3, scale=0.5).astype(np.float32).astype(np.float64)
     mom_ref, D_ref = o.moments(h, oracle_mod.Walls(**WALLS), lid_shear=True)
     mom = torch_mod.zeros(o.nx * o.ny * 11, dtype=torch_mod.float64, device="cuda")
