@@ -134,6 +134,10 @@ COLLIDE_CASES = [
     dict(nx=4, ny=4, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=2000, sample_group=0),
     dict(nx=5, ny=3, nv=(20, 20, 20), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, sample_group=4, mix16=4),
     dict(nx=4, ny=4, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=0),
+    # shared records: whole 1024-record blocks only (every record dealt to lanes), and fewer
+    # records than one block (none dealt)
+    dict(nx=3, ny=3, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=2048, sample_group=0, mix16=4),
+    dict(nx=3, ny=3, nv=(20, 20, 20), vmax=5.0, delta=20.0, eps=0.1, n_pairs=700, sample_group=0),
     # two passes over the pairs, half of the nodes each (grids too large for one pass)
     dict(nx=3, ny=2, nv=(24, 24, 24), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, sample_group=0, mix16=4),
     dict(nx=2, ny=2, nv=(25, 25, 23), vmax=5.0, delta=10.0, eps=0.1, n_pairs=20000, sample_group=0, mix16=4),
