@@ -402,7 +402,7 @@ def main():
             "lds_atomic_lane_ops_per_clk_per_cu": atom_rate,
             "note": "8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision "
                     "launch group; the pair loop is bound by LDS integer atomics (4 per pair and cell), "
-                    "whose measured gfx950 rate is ~5.4 lane-ops/clk/CU"}
+                    "whose measured gfx950 rate for random addresses is ~4.4 lane-ops/clk/CU (64-bit)"}
     stream_gbs = BYTES_PER_NODE_KERNEL * nodes / r["t_stream"] / 1e9
     stream_k = {"kernel": "wallconst_kernel (when the walls change) + wall_kernel x2 + stream4_kernel", "bound": "hbm",
                 "avg_ms": r["t_stream"] * 1e3, "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
