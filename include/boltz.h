@@ -84,7 +84,10 @@ typedef struct boltz_problem {
   uint32_t cavity_id;    /* fourth Philox counter word                       */
   uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT        */
   uint32_t mix16;        /* uniform share beta = mix16/16 of the node-pair   */
-                         /* law (0..16; 0 = the paper's sampling from Phi0)  */
+                         /* law, 0..16.  0 = nodes from the 12-bit discrete  */
+                         /* Maxwellian alone: accepted only on grids where   */
+                         /* that law gives every node a positive probability */
+                         /* (else EINVAL: tail nodes would never be drawn)   */
 } boltz_problem;
 
 /* Wall state for one call (Sec. 2, Eq. bcMax; Sec. 5.1). */
@@ -113,7 +116,8 @@ typedef struct boltz_ctx boltz_ctx;
  * device.  EINVAL: out-of-range sizes, a dt above the Courant limit of the
  * streaming scheme (unless BOLTZ_ALLOW_UNSTABLE), n_pairs >= 2^31.
  * EINVAL also for shared samples (G != 1) with more than 65535 groups or
- * velocity nodes.  EUNSUPPORTED: a velocity grid whose two per-cell FP32
+ * velocity nodes, and for mix16 = 0 on a grid where the Maxwellian node law
+ * leaves a node unreachable (checked before any device call).  EUNSUPPORTED: a velocity grid whose two per-cell FP32
  * tiles exceed the 160 KB local data share.  ENOMEM / EHIP: device
  * allocation failed. */
 int boltz_create(const boltz_problem* problem, boltz_ctx** out);

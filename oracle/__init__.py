@@ -146,7 +146,7 @@ class Oracle:
     """One problem set-up of the oracle (FP64, host memory)."""
 
     def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2,
-                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=0):
+                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4):
         L = _load()
         nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
         vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))

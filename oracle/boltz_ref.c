@@ -172,6 +172,23 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
       c->punif[k][i] = ldexp((double)(hi_u - lo_u), -FIELD_BITS);
     }
   }
+  /* Eq. coll8Dim read as an importance-sampling estimate is unbiased only if
+   * every node the integrand reaches has a positive probability of being
+   * drawn.  The Maxwellian law on 12-bit fields gives probability zero to
+   * the far-tail nodes of wide grids (T_{i+1} = T_i); without the uniform
+   * component those nodes would never be drawn and their loss terms would
+   * be dropped, so the pure Maxwellian law (mix16 = 0) is refused there. */
+  if (p->mix16 == 0) {
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < c->n[k]; ++i)
+        if (!(c->pphi[k][i] > 0.0)) {
+          boltz_ref_destroy(c);
+          set_err(g_create_err,
+                  "mix16 = 0: the Maxwellian node law gives probability zero to tail nodes of this "
+                  "velocity grid (biased estimate); use mix16 > 0");
+          return BOLTZ_REF_EINVAL;
+        }
+  }
   c->beta = p->mix16 / 16.0;
   c->ncells = p->nx * p->ny;
   c->dx = 1.0 / p->nx;

@@ -56,7 +56,9 @@ typedef struct boltz_ref_problem {
   uint64_t seed;         /* Philox key                                      */
   uint32_t cavity_id;    /* fourth Philox counter word                      */
   uint32_t flags;        /* BOLTZ_REF_ALLOW_UNSTABLE                        */
-  uint32_t mix16;        /* uniform share of the pair law, in 1/16 (0..16)  */
+  uint32_t mix16;        /* uniform share of the pair law, in 1/16 (0..16); */
+                         /* 0 only on grids where every node has a positive */
+                         /* Maxwellian-law probability (else EINVAL)        */
 } boltz_ref_problem;
 
 typedef struct boltz_ref_walls {

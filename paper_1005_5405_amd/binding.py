@@ -166,7 +166,7 @@ def _stream(stream):
 
 
 def _problem(nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2, bc=BC_CAVITY, sample_group=1,
-             seed=1, cavity_id=0, flags=0, mix16=0) -> _Problem:
+             seed=1, cavity_id=0, flags=0, mix16=4) -> _Problem:
     nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
     vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
     return _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax), float(delta),
@@ -178,7 +178,7 @@ class Boltz:
     """One problem on the current HIP device (a boltz_ctx)."""
 
     def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2, bc=BC_CAVITY,
-                 sample_group=1, seed=1, cavity_id=0, flags=0, mix16=0, _borrowed=None):
+                 sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4, _borrowed=None):
         L = load_library()
         if _borrowed is None:
             p = _problem(nx, ny, nv, vmax, delta, eps, n_pairs, cfl, dt, order, bc, sample_group, seed, cavity_id,

@@ -284,6 +284,19 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       c->punif[k][i] = std::ldexp((double)(hi_u - lo_u), -kFieldBits);
     }
   }
+  // Eq. coll8Dim as an importance-sampling estimate is unbiased only if
+  // every node the integrand reaches can be drawn: the Maxwellian law on
+  // 12-bit fields gives probability zero to the far-tail nodes of wide grids,
+  // so without the uniform component (mix16 = 0) it is refused there.
+  if (p->mix16 == 0)
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < c->n[k]; ++i)
+        if (!(c->pphi[k][i] > 0.0)) {
+          delete c;
+          return fail(nullptr, BOLTZ_EINVAL,
+                      "boltz_create: mix16 = 0: the Maxwellian node law gives probability zero to tail nodes "
+                      "of this velocity grid (biased estimate); use mix16 > 0");
+        }
   {
     // W = (Om_x Om_y) Om_z, the discrete mass of Phi0
     double Om[3];

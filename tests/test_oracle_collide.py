@@ -22,7 +22,7 @@ def _axis(n, a):
     return v, om, dv
 
 
-def _enumerate_mean_dN(n, a, h, eps, dt, delta, M):
+def _enumerate_mean_dN(n, a, h, eps, dt, delta, M, parts=False):
     """E[Delta N_j] over the sampling law, written independently of the oracle.
 
     On a uniform grid the post-collision cell of v_a + d is a + floor(d/dv + 1/2)
@@ -43,6 +43,7 @@ def _enumerate_mean_dN(n, a, h, eps, dt, delta, M):
     kx, ky = s * np.cos(2 * np.pi * u7.ravel()), s * np.sin(2 * np.pi * u7.ravel())
     kk = np.stack([kx, ky, kz], 1)
     E = np.zeros(n**3)
+    Eg = np.zeros(n**3)
     rng_off = np.arange(-(n - 1), n)
     for rx in rng_off:
         for ry in rng_off:
@@ -74,8 +75,14 @@ def _enumerate_mean_dN(n, a, h, eps, dt, delta, M):
                 ibs = (Bs[..., 0] * n + Bs[..., 1]) * n + Bs[..., 2]
                 np.add.at(E, ias[kept], contrib[kept])
                 np.add.at(E, ibs[kept], contrib[kept])
+                np.add.at(Eg, ias[kept], contrib[kept])
+                np.add.at(Eg, ibs[kept], contrib[kept])
                 np.add.at(E, np.broadcast_to(ia, kept.shape)[kept], -contrib[kept])
                 np.add.at(E, np.broadcast_to(ib, kept.shape)[kept], -contrib[kept])
+    if parts:
+        # (gain, loss): the expected increments at a*, b* and (as positive
+        # numbers) the expected decrements at a, b
+        return dt * K * W * W * Eg, dt * K * W * W * (Eg - E)
     return dt * K * W * W * E
 
 
@@ -130,6 +137,64 @@ def test_mc_mean_matches_enumeration_6cubed(oracle_mod, kind, mix16):
         h2 = _h_test(n, a, "nonequilibrium", eps)
         E2 = _enumerate_mean_dN(n, a, h2 * np.abs(h).max() / np.abs(h2).max(), eps, o.dt, delta, M=64)
         assert np.abs(E).sum() < 0.35 * np.abs(E2).sum()
+
+
+def test_mc_mean_matches_enumeration_per_node_8cubed(oracle_mod):
+    """Every node of an 8^3 grid on [-4, 4], whose 12-bit Maxwellian law gives
+    the two outer nodes of each axis probability zero, with the mixture law
+    (a quarter uniform) that reaches them all.  Gain and loss parts are
+    compared separately, node by node, in units of h (E/w): the loss at a
+    node comes from the draws of that node and is well sampled everywhere;
+    the gain at the edge nodes comes mostly from rare, large events (bulk
+    pairs landing there) whose batch sums are strongly skewed, so there the
+    5-sigma bound is widened by the first Cornish-Fisher term of the sample
+    mean's skewness (skew / sqrt(batches)).  The oracle's
+    own scatter (collide's Delta N) is the gain minus the loss of its
+    sampled pairs."""
+    n, a, eps, delta, nt, nb = 8, 4.0, 0.5, 1.0, 20000, 1200
+    v, _, _ = _axis(n, a)
+    V = np.stack(np.meshgrid(v, v, v, indexing="ij"), -1).reshape(-1, 3)
+    h = 0.8 * np.sin(0.7 * V[:, 0] + 0.3) * np.cos(0.5 * V[:, 1]) + 0.5 * np.cos(0.6 * V[:, 2] - 0.2) \
+        + 0.3 * np.tanh(V[:, 0] * V[:, 1] / 4)
+    with pytest.raises(ValueError, match="mix16 = 0"):
+        oracle_mod.Oracle(1, 1, n, a, delta, eps, nt, bc=oracle_mod.BC_PERIODIC, mix16=0)
+    o = oracle_mod.Oracle(1, 1, n, a, delta, eps, nt, bc=oracle_mod.BC_PERIODIC, mix16=4)
+    w = o.node_weights()
+    G = np.zeros((nb, n**3))
+    L = np.zeros((nb, n**3))
+    for st in range(nb):
+        idx, q = o.debug_pairs(0, st, 0, nt)
+        kept = idx[:, 2] >= 0
+        ia, ib, isa, isb, qk = idx[kept, 0], idx[kept, 1], idx[kept, 2], idx[kept, 3], q[kept]
+        c = qk * (h[ia] + h[ib] + eps * h[ia] * h[ib])
+        G[st] = np.bincount(isa, c, n**3) + np.bincount(isb, c, n**3)
+        L[st] = np.bincount(ia, c, n**3) + np.bincount(ib, c, n**3)
+        if st == 0:
+            _, dN, _ = o.collide(h.reshape(1, 1, -1), st, correction=False, want_dN=True)
+            scale = (np.abs(G[0]) + np.abs(L[0])).max()
+            assert np.abs(dN.ravel() - (G[0] - L[0])).max() <= 1e-12 * scale
+    Eg, El = _enumerate_mean_dN(n, a, h, eps, o.dt, delta, M=256, parts=True)
+    Eg2, El2 = _enumerate_mean_dN(n, a, h, eps, o.dt, delta, M=128, parts=True)
+    for S, E, E2 in ((L, El, El2), (G, Eg, Eg2)):
+        mean, se = S.mean(0), S.std(0, ddof=1) / np.sqrt(nb)
+        # the quadrature has converged below the Monte Carlo error
+        assert np.max(np.abs(E - E2) / se) < 1.0
+    # loss: every node, in h units
+    mean, se = L.mean(0) / w, L.std(0, ddof=1) / np.sqrt(nb) / w
+    z = (mean - El / w) / se
+    assert np.all(np.abs(El) > 0)
+    assert np.max(np.abs(z)) < 5.0, np.max(np.abs(z))
+    assert 0.6 < float((z**2).mean()) < 1.6
+    # gain: every node, 5 sigma plus the Cornish-Fisher skewness term
+    # (z^2 - 1) gamma / 6 of the sample mean (gamma = skew / sqrt(batches))
+    mean, se = G.mean(0) / w, G.std(0, ddof=1) / np.sqrt(nb) / w
+    d = G - G.mean(0)
+    skew = (d**3).mean(0) / np.maximum((d**2).mean(0), 1e-300) ** 1.5
+    z = (mean - Eg / w) / se
+    bound = 5.0 + (25.0 - 1.0) / 6.0 * np.abs(skew) / np.sqrt(nb)
+    assert np.all(np.abs(z) < bound), np.max(np.abs(z) - bound)
+    sym = np.abs(skew) < 2.0
+    assert np.max(np.abs(z[sym])) < 5.0 and 0.6 < float((z[sym] ** 2).mean()) < 1.6
 
 
 def test_raw_increments_conserve_mass_per_pair(oracle_mod):

@@ -117,7 +117,7 @@ def test_inverse_cdf_intervals_are_left_closed(oracle_mod):
 
 def test_sampled_nodes_follow_law(oracle_mod):
     n, a = 8, 3.0
-    o = oracle_mod.Oracle(2, 2, n, a, 1.0, 0.1, 1, bc=oracle_mod.BC_PERIODIC)
+    o = oracle_mod.Oracle(2, 2, n, a, 1.0, 0.1, 1, bc=oracle_mod.BC_PERIODIC, mix16=0)
     N = 200000
     idx, _ = o.debug_pairs(0, 3, 0, N)
     T = np.concatenate([[0], o.thresholds[0].astype(np.float64), [2.0**12]])
@@ -154,10 +154,11 @@ def _laws(o, k):
     return pm, pu
 
 
-@pytest.mark.parametrize("mix16", [0, 4, 8, 16])
-def test_mixture_law_marginals(oracle_mod, mix16):
+# mix16 = 0 only on a grid where the Maxwellian law reaches every node
+@pytest.mark.parametrize("a,mix16", [(3.0, 0), (4.0, 4), (4.0, 8), (4.0, 16)])
+def test_mixture_law_marginals(oracle_mod, a, mix16):
     n = 10
-    o = oracle_mod.Oracle(2, 2, n, 4.0, 1.0, 0.1, 1, bc=oracle_mod.BC_PERIODIC, mix16=mix16)
+    o = oracle_mod.Oracle(2, 2, n, a, 1.0, 0.1, 1, bc=oracle_mod.BC_PERIODIC, mix16=mix16)
     N = 200000
     idx, _, wd = o.debug_pairs(1, 9, 0, N, words=True)
     beta = mix16 / 16.0
@@ -174,26 +175,70 @@ def test_mixture_law_marginals(oracle_mod, mix16):
             assert ((cnt[m] - e[m]) ** 2 / e[m]).sum() / m.sum() < 3.0
 
 
-@pytest.mark.parametrize("mix16", [0, 4])
-def test_mixture_weight_is_w_over_p(oracle_mod, mix16):
-    o = oracle_mod.Oracle(2, 2, (9, 8, 7), (4.0, 3.5, 3.0), 2.0, 0.1, 50, bc=oracle_mod.BC_PERIODIC,
-                          mix16=mix16)
-    idx, q, vel = o.debug_pairs(2, 4, 0, 20000, velocities=True)
-    kept = idx[:, 2] >= 0
-    n = o.nv3
-    laws = [_laws(o, k) for k in range(3)]
+def _total_collision_weight(n, a, M):
+    """sum over ordered node pairs (a, b) of w_a w_b times the direction
+    average of |v_r . k| over the kept directions (both post-collision cells
+    inside the box), by a midpoint rule in (u6, u7); written independently of
+    the oracle.  On a uniform grid the post-collision cell of v_a + d is
+    a + floor(d / dv + 1/2) per axis, so for an offset r = b - a and a
+    direction k the kept first nodes form a box, one interval per axis, and
+    the sum of w_a w_b over it is a product of per-axis interval sums."""
+    dv = 2 * a / n
+    v = (np.arange(n) + 0.5 - n / 2) * dv
+    om = dv * np.exp(-v * v) / np.sqrt(np.pi)
+    u = (np.arange(M) + 0.5) / M
+    u6, u7 = np.meshgrid(u, u, indexing="ij")
+    kz = (2 * u6 - 1).ravel()
+    s = np.sqrt(1 - kz * kz)
+    kk = np.stack([s * np.cos(2 * np.pi * u7.ravel()), s * np.sin(2 * np.pi * u7.ravel()), kz], 1)
+    # prefix[r][i] = sum_{A < i} om_A om_{A + r} over A with A, A + r on the grid
+    prefix = {}
+    for r in range(-(n - 1), n):
+        t = np.array([om[A] * om[A + r] if 0 <= A + r < n else 0.0 for A in range(n)])
+        prefix[r] = np.concatenate([[0.0], np.cumsum(t)])
+    total = 0.0
+    for r in np.stack(np.meshgrid(*[np.arange(-(n - 1), n)] * 3, indexing="ij"), -1).reshape(-1, 3):
+        alpha = dv * (kk @ r)
+        d = alpha[:, None] * kk / dv
+        oa, ob = np.floor(d + 0.5).astype(np.int64), np.floor(-d + 0.5).astype(np.int64)
+        prod = np.abs(alpha)
+        for i in range(3):
+            lo = np.maximum.reduce([np.zeros_like(oa[:, i]), -oa[:, i], -r[i] - ob[:, i],
+                                    np.full_like(oa[:, i], -r[i])])
+            hi = np.minimum.reduce([np.full_like(oa[:, i], n - 1), n - 1 - oa[:, i], n - 1 - r[i] - ob[:, i],
+                                    np.full_like(oa[:, i], n - 1 - r[i])])
+            ok = lo <= hi
+            P = prefix[int(r[i])]
+            prod = prod * np.where(ok, P[np.clip(hi, 0, n - 1) + 1] - P[np.clip(lo, 0, n - 1)], 0.0)
+        total += float(prod.mean())
+    return total
 
-    def ratio(j):
-        i3 = [j // (n[1] * n[2]), (j // n[2]) % n[1], j % n[2]]
-        w = np.prod([o.omega[k][i3[k]] for k in range(3)], axis=0)
-        pm = np.prod([laws[k][0][i3[k]] for k in range(3)], axis=0)
-        pu = np.prod([laws[k][1][i3[k]] for k in range(3)], axis=0)
-        beta = mix16 / 16.0
-        return w / ((1 - beta) * pm + beta * pu)
 
-    alpha = np.sqrt(((vel[:, 2] - vel[:, 0]) ** 2).sum(1))
-    expect = o.dt * o.K * alpha / 50 * ratio(idx[:, 0]) * ratio(idx[:, 1])
-    np.testing.assert_allclose(q[kept], expect[kept], rtol=1e-12, atol=1e-13 * q.max())
+# Unbiasedness of the importance weights of Eq. coll8Dim: whatever law the
+# nodes are drawn from, the mean weight q N_t / (dt K) of a sample is the
+# discrete collision integral of g = 1, i.e. the enumerated total above.  A
+# law that can never draw some node (the 12-bit Maxwellian law alone on a
+# wide grid) would miss that node's share and fail this; it is refused.
+@pytest.mark.parametrize("a,mix16", [(3.0, 0), (3.0, 4), (4.0, 4), (4.0, 16)])
+def test_mean_weight_equals_enumerated_collision_integral(oracle_mod, a, mix16):
+    n, N = 6, 400000
+    o = oracle_mod.Oracle(1, 1, n, a, 2.0, 0.1, N, bc=oracle_mod.BC_PERIODIC, mix16=mix16)
+    _, q = o.debug_pairs(0, 5, 0, N)
+    x = q * N / (o.dt * o.K)
+    se = x.std(ddof=1) / np.sqrt(N)
+    T = _total_collision_weight(n, a, 128)
+    # the quadrature has converged well below the Monte Carlo error
+    assert abs(_total_collision_weight(n, a, 64) - T) < 0.25 * se
+    assert abs(x.mean() - T) < 4.5 * se, (x.mean(), T, se)
+
+
+def test_maxwellian_law_alone_is_refused_where_it_misses_nodes(oracle_mod):
+    # 8 cells on [-4, 4]: the 12-bit Maxwellian law leaves the two outer nodes
+    # of each axis at probability zero
+    with pytest.raises(ValueError, match="mix16 = 0"):
+        oracle_mod.Oracle(1, 1, 8, 4.0, 1.0, 0.1, 100, bc=oracle_mod.BC_PERIODIC, mix16=0)
+    T = oracle_mod.Oracle(1, 1, 8, 4.0, 1.0, 0.1, 100, bc=oracle_mod.BC_PERIODIC, mix16=4).thresholds[0]
+    assert np.any(np.diff(np.concatenate([[0], T.astype(np.int64), [4096]])) == 0)
 
 
 def test_pair_kinematics_conserve_momentum_energy(oracle_mod):
