@@ -1,21 +1,25 @@
 #!/usr/bin/env python
 """Throughput of one time-split Boltzmann step (stream + collide) on one MI355X.
 
-Workload (default): the 64x64-cell driven cavity with a 20^3 velocity grid on
-[-5, 5], Kn = 0.05, lid velocity 0.1, 20000 Monte Carlo pairs per cell per
-step, CFL 0.5, second-order streaming, FP32 h with FP64 moment/correction sums.
-The state starts at rest (h = 0) and evolves through the warm-up steps, so the
-timed steps act on a developing cavity flow; all data stay resident in HBM.
+Workload (default): the largest single-GPU configuration, the 200x200-cell
+driven cavity with a 24^3 velocity grid on [-5, 5], Kn = 0.01, lid velocity
+0.05 sin(0.5 t), 50000 Monte Carlo pairs per cell per step, CFL 0.5,
+second-order streaming, FP32 h (2.2 GB per state) with FP64 moment and
+correction sums.  The state starts at rest (h = 0) and evolves through the
+warm-up steps, so the timed steps act on a developing cavity flow; all data
+stay resident in HBM.
 
 Sample sharing: the headline run draws one set of N_t pairs per step that
 every cell evaluates with its own h (sample group G = 0, the sharing of the
-paper's Sec. 3); the variant with an independent Philox stream per cell
-(G = 1) is timed in the same process and reported beside it.
+paper's Sec. 3).  Beside it: the 64x64 cavity (20^3, 20000 pairs) with shared
+samples, with an independent Philox stream per cell (G = 1) and with
+first-order streaming; the full-length runs (200x200 for 2000 steps with the
+lid shear every 10 steps, 64x64 for 1000 steps); the reverse mode; the batch.
 
-One step = boltz_stream (wall densities + streaming kernels) followed by
-boltz_collide in place (pair table + collision kernel): exactly what
-boltz_step enqueues, with HIP events recorded between the two calls on the
-launch stream to time each kernel group.
+One step = boltz_step (wall densities with the step's pair records drawn in
+the last face launch, streaming, collision in place).  A second pass over the
+same workload calls boltz_stream and boltz_collide with HIP events recorded
+between them on the launch stream, to time each kernel group.
 
 Prints one JSON line: node-updates/s (value), pairs/s, the HBM roofline of the
 dominant kernel group, and the FP64 CPU oracle's throughput on a bounded
@@ -45,11 +49,14 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 # HBM traffic of the collision launch group measured with rocprofv3 counters
 # (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, summed over the group's
 # kernels), each scaled by what the counter reads for a device copy of the
-# 131 MB state (bench.py --calibrate); valid only for the kernel sources whose
-# SHA-256 is recorded (profiles/collide_counters_cavity64.md).
-TRAFFIC = {"sha256": "7ed1a883756f02f6916d0e3229c0949d38f19b98a378371c3bb8888b550d7563",
-           "fetch_kib": 66425.6 + 113.0, "write_kib": 128000.0 + 468.8,
-           "fetch_scale": 128000.0 / 64018.4, "write_scale": 1.0}
+# state (bench.py --calibrate), per workload (cells, velocity grid, G); valid
+# only for the kernel sources whose SHA-256 is recorded (the collide_counters
+# summaries under profiles/).
+TRAFFIC = {}
+# VALU instructions (wave64) per dispatch of the per-cell-sample (G = 1)
+# collision kernel of the 64x64 cavity, rocprofv3 --pmc SQ_INSTS_VALU; valid
+# for the recorded kernel-source SHA-256.
+VALU_G1 = {"sha256": "", "valu_insts_per_dispatch": None}
 KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
 
 
@@ -63,43 +70,132 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    t = TRAFFIC
-    if not t["sha256"] or t["sha256"] != kernel_sources_sha256():
+def _workload_key(kw) -> str:
+    nv = kw["nv"] if isinstance(kw["nv"], int) else kw["nv"][0]
+    return "%dx%d_%d_G%d" % (kw["nx"], kw["ny"], nv, kw["sample_group"])
+
+
+def measured_traffic(kw):
+    t = TRAFFIC.get(_workload_key(kw))
+    if not t or t["sha256"] != kernel_sources_sha256():
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
+def alu_roofline(v):
+    """Vector-instruction issue roofline of the G = 1 collision: every lane
+    draws its own pairs (Philox, FP64 geometry, weights), so the kernel is
+    bound by VALU issue, not HBM.  Peak: one wave64 VALU instruction per clock
+    per CU (four 16-lane SIMDs, four cycles each), 256 CUs at 2.4 GHz =
+    3.93e13 lane-instructions/s (the FP32/FP64 vector FMA peaks of 157.3 and
+    78.6 TFLOP/s count the same 64 lanes per clock and CU)."""
+    peak = N_CU * CLOCK_HZ * 64
+    insts = VALU_G1["valu_insts_per_dispatch"]
+    ok = insts is not None and VALU_G1["sha256"] == kernel_sources_sha256()
+    achieved = insts * 64 / v["t_collide"] if ok else None
+    return {"bound": "alu", "unit": "lane-instructions/s", "peak": peak, "achieved": achieved,
+            "frac": achieved / peak if ok else None,
+            "valu_insts_per_dispatch": insts if ok else None,
+            "note": "SQ_INSTS_VALU x 64 lanes over the HIP-event average of the launch"}
 
 
 def _json_line(d):
     print(json.dumps(d), flush=True)
 
 
-def cpu_baseline(preset, seconds_budget: float):
-    """FP64 oracle on the host cores: full steps of the same workload."""
+def _oracle_steps(oracle, preset, ny, threads, seconds_budget, max_steps=50):
+    """Full steps of the FP64 oracle on an nx x ny slab of the preset's cavity
+    from rest; returns (steps, seconds, threads used, problem)."""
     import numpy as np
 
-    import oracle
-
-    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
     oracle.set_threads(threads)
-    used = oracle.get_threads()
-    kw = preset.problem()
+    kw = preset.problem(ny=ny)
     o = oracle.Oracle(**kw)
-    walls = oracle.Walls(lid_u=preset.lid(0.0))
     h = np.zeros(o.shape)
     steps, t0 = 0, time.perf_counter()
     while True:
+        walls = oracle.Walls(lid_u=preset.lid(steps * o.dt))
         h = o.step(h, walls, steps)
         steps += 1
-        if time.perf_counter() - t0 >= seconds_budget or steps >= 200:
+        if time.perf_counter() - t0 >= seconds_budget or steps >= max_steps:
             break
-    dt = time.perf_counter() - t0
-    ncells, nv = o.nx * o.ny, o.nv
-    return {"value": ncells * nv * steps / dt, "unit": "node-updates/s", "cores": used, "kind": "oracle",
-            "sample": "%d full step(s) of the same %dx%d-cell, %d-node, %d-pair, G=%d workload from rest, "
-                      "FP64, OpenMP over cells, %.1f s" % (steps, o.nx, o.ny, nv, kw["n_pairs"],
-                                                           kw["sample_group"], dt),
-            "pairs_per_s": ncells * kw["n_pairs"] * steps / dt}
+    return steps, time.perf_counter() - t0, oracle.get_threads(), o, kw
+
+
+def cpu_baseline(preset, seconds_budget: float):
+    """FP64 oracle on the host cores, full steps (walls, streaming, collision
+    with its correction) of a slab of the same cavity: the preset's nx, its
+    velocity grid, pair count, Knudsen number and time step (dt is set by
+    the x spacing, which the slab keeps), fewer rows.  The cost per node and
+    per cell does not depend on the row count.  Threads: OMP_NUM_THREADS
+    (the host share of one GPU), and one thread (the paper's speed-up
+    definition, Sec. 5.2)."""
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    # rows so that one multi-threaded step is about a second of work (the
+    # oracle draws and scatters ~1e7 pairs per second and thread)
+    rows = max(2, min(preset.ny, int(round(threads * 1e7 / (preset.nx * preset.n_pairs)))))
+    steps, dt, used, o, kw = _oracle_steps(oracle, preset, rows, threads, seconds_budget)
+    nodes = o.nx * o.ny * o.nv
+    out = {"value": nodes * steps / dt, "unit": "node-updates/s", "cores": used, "kind": "oracle",
+           "nproc": os.cpu_count(),
+           "sample": "%d full step(s) from rest of a %dx%d-cell slab of the %s workload (same velocity grid, "
+                     "%d pairs/cell, G=%d, dt), FP64, OpenMP over cells on %d threads, %.1f s"
+                     % (steps, o.nx, o.ny, preset.name, kw["n_pairs"], kw["sample_group"], used, dt),
+           "pairs_per_s": o.nx * o.ny * kw["n_pairs"] * steps / dt}
+    s1, d1, u1, o1, _ = _oracle_steps(oracle, preset, 2, 1, max(2.0, seconds_budget / 3), max_steps=20)
+    n1 = o1.nx * o1.ny * o1.nv
+    out["single_thread"] = {"value": n1 * s1 / d1, "unit": "node-updates/s", "cores": u1,
+                            "sample": "%d full step(s) of a %dx%d-cell slab, one thread, %.1f s"
+                                      % (s1, o1.nx, o1.ny, d1),
+                            "pairs_per_s": o1.nx * o1.ny * kw["n_pairs"] * s1 / d1}
+    oracle.set_threads(threads)
+    return out
+
+
+def run_full_length(pkg, torch, preset, sample_group: int):
+    """The preset's whole run from rest (its step count, the oscillating lid
+    evaluated at the start of every step), with the lid shear D sampled every
+    `moments_every` steps (every 10th step at least) on the device; returns the
+    D(t) trace, the status word and the wall time."""
+    kw = preset.problem(sample_group=sample_group)
+    g = pkg.Boltz(**kw)
+    every = preset.moments_every or 10
+    nsamp = preset.steps // every
+    a, b = g.empty(0.0), g.empty()
+    mom = torch.empty(g.ncells * 11, dtype=torch.float64, device="cuda")
+    D = torch.zeros(nsamp, dtype=torch.float64, device="cuda")
+    walls = pkg.Walls(lid_u=preset.lid(0.0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    for n in range(preset.steps):
+        walls.lid_u = preset.lid(n * g.dt)
+        g.step(a, b, walls, n)
+        a, b = b, a
+        if (n + 1) % every == 0 and k < nsamp:
+            walls.lid_u = preset.lid((n + 1) * g.dt)
+            g.moments(a, mom, walls, D[k:k + 1])
+            k += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = g.read_status()
+    finite = bool(torch.isfinite(a).all().item())
+    Dh = D.cpu().numpy()
+    t = [(i + 1) * every * g.dt for i in range(nsamp)]
+    lid = [preset.lid(x) for x in t]
+    del a, b, mom
+    torch.cuda.empty_cache()
+    return {"workload": preset.name, "sample_group": sample_group, "steps": preset.steps,
+            "moments_every": every, "wall_s": wall, "ms_per_step": wall / preset.steps * 1e3,
+            "value": g.ncells * g.nv * preset.steps / wall, "status": status, "finite": finite,
+            "D_trace": {"t": [round(x, 6) for x in t[:: max(1, nsamp // 50)]],
+                        "D": [float("%.6g" % x) for x in Dh[:: max(1, nsamp // 50)]],
+                        "lid_u": [float("%.6g" % x) for x in lid[:: max(1, nsamp // 50)]],
+                        "samples": nsamp, "stride_shown": max(1, nsamp // 50),
+                        "min": float(Dh.min()), "max": float(Dh.max()), "last": float(Dh[-1]),
+                        "mean_last_quarter": float(Dh[3 * nsamp // 4:].mean())}}
 
 
 def run(pkg, torch, preset, steps: int, warmup: int):
@@ -338,16 +434,51 @@ def run_batch(pkg, torch, count: int, steps: int, warmup: int):
     return out
 
 
+def _roofline(r, kw, g):
+    """HBM roofline of the collision launch group (sample + collision
+    kernels), 8 B/node per launch over its HIP-event average."""
+    nodes, t_c = r["nodes"], r["t_collide"]
+    coll_gbs = BYTES_PER_NODE_KERNEL * nodes / t_c / 1e9
+    pair_cells = g.ncells * g.n_pairs
+    return {"kernel": "collide_kernel + sample_kernel" if kw["sample_group"] != 1 else "collide_kernel",
+            "bound": "hbm", "achieved": coll_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": coll_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kw), "avg_ms": t_c * 1e3,
+            "algorithmic_bytes_per_launch": BYTES_PER_NODE_KERNEL * nodes,
+            "pair_cells_per_s_in_kernel": pair_cells / t_c,
+            "lds_atomic_lane_ops_per_clk_per_cu": LDS_ATOMICS_PER_PAIR * pair_cells / t_c / (N_CU * CLOCK_HZ),
+            "note": "8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision "
+                    "launch group; its pair loop (2 LDS gathers + 4 LDS integer atomic adds per pair and "
+                    "cell), not HBM, sets its time"}
+
+
+def _stream_kernels(r):
+    stream_gbs = BYTES_PER_NODE_KERNEL * r["nodes"] / r["t_stream"] / 1e9
+    return {"kernel": "wall_kernel x2 (+ wallconst_kernel when the walls change) + stream4_kernel", "bound": "hbm",
+            "avg_ms": r["t_stream"] * 1e3, "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": stream_gbs / HBM_PEAK_GBS}
+
+
+def _summary(r, kw, g, steps):
+    return {"value": r["value"], "unit": "node-updates/s", "ms_per_step": r["ms_per_step"],
+            "pairs_per_s": r["pairs_per_s"], "pairs_per_s_meaning": "pair-cell evaluations (cells x N_t per step)",
+            "hbm_frac_step": 2 * BYTES_PER_NODE_KERNEL * r["nodes"] / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "collide": _roofline(r, kw, g), "stream": _stream_kernels(r), "steps": steps,
+            "config": {"cells": [g.nx, g.ny], "velocity_grid": list(g.nv3), "pairs_per_cell": g.n_pairs,
+                       "sample_group": kw["sample_group"], "order": g.order, "mix16": kw["mix16"]}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="cavity64")
+    ap.add_argument("--config", default="cavity200")
     ap.add_argument("--sample-group", type=int, default=0, help="cells sharing a pair stream (0 = all)")
     ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--variant", choices=["auto", "skip"], default="auto",
-                    help="also time the per-cell sample streams (G = 1)")
+                    help="also time the 64x64 cavity (shared samples, per-cell samples G = 1, order 1)")
+    ap.add_argument("--full", choices=["auto", "skip"], default="auto",
+                    help="also run the full-length 200x200 (2000 steps, D(t)) and 64x64 (1000 steps) runs")
     ap.add_argument("--adjoint", choices=["auto", "skip"], default="auto",
                     help="also time the reverse mode (step adjoint, windowed lid-shear gradient)")
     ap.add_argument("--window", type=int, default=200, help="steps of the windowed gradient")
@@ -386,54 +517,56 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print("[bench] calibration copy: %d bytes" % (4 * n0), flush=True)
+        del src, dst
     r = run(pkg, torch, preset, args.steps, args.warmup)
     g, kw, nodes = r["g"], r["kw"], r["nodes"]
     K = args.steps
     hbm_step = 2 * BYTES_PER_NODE_KERNEL * nodes / (r["wall_s"] / K) / 1e9
-    # dominant kernel group: the collision (pair table + collision kernel)
-    t_c = r["t_collide"]
-    coll_gbs = BYTES_PER_NODE_KERNEL * nodes / t_c / 1e9
-    pair_cells = g.ncells * g.n_pairs
-    atom_rate = LDS_ATOMICS_PER_PAIR * pair_cells / t_c / (N_CU * CLOCK_HZ)
-    roof = {"kernel": "collide_kernel + sample_kernel" if kw["sample_group"] != 1 else "collide_kernel",
-            "bound": "hbm", "achieved": coll_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": coll_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(), "avg_ms": t_c * 1e3,
-            "algorithmic_bytes_per_launch": BYTES_PER_NODE_KERNEL * nodes,
-            "lds_atomic_lane_ops_per_clk_per_cu": atom_rate,
-            "note": "8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision "
-                    "launch group; the pair loop is bound by LDS integer atomics (4 per pair and cell), "
-                    "whose measured gfx950 rate for random addresses is ~4.4 lane-ops/clk/CU (64-bit)"}
-    stream_gbs = BYTES_PER_NODE_KERNEL * nodes / r["t_stream"] / 1e9
-    stream_k = {"kernel": "wallconst_kernel (when the walls change) + wall_kernel x2 + stream4_kernel", "bound": "hbm",
-                "avg_ms": r["t_stream"] * 1e3, "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": stream_gbs / HBM_PEAK_GBS}
     line = {"metric": METRIC, "value": r["value"], "unit": "node-updates/s", "n_gpus": 1, "steps": K,
             "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": preset.name, "cells": [g.nx, g.ny], "velocity_grid": list(g.nv3),
-                       "pairs_per_cell": g.n_pairs, "sample_group": kw["sample_group"], "order": g.order,
-                       "kn": preset.kn, "lid_u": preset.lid_u, "cfl": preset.cfl, "mix16": kw["mix16"],
-                       "parallelism": "single GPU"},
-            "pairs_per_s": r["pairs_per_s"], "hbm_frac_step": hbm_step / HBM_PEAK_GBS,
+                       "velocity_box": [-preset.vmax, preset.vmax], "pairs_per_cell": g.n_pairs,
+                       "sample_group": kw["sample_group"], "order": g.order, "kn": preset.kn,
+                       "lid_u": ("%g sin(%g t)" % (preset.lid_u, preset.lid_omega)) if preset.lid_omega > 0
+                       else preset.lid_u, "cfl": preset.cfl, "mix16": kw["mix16"], "parallelism": "single GPU"},
+            "pairs_per_s": r["pairs_per_s"],
+            "pairs_per_s_meaning": "pair-cell evaluations (cells x N_t per step); with G = 0 every cell "
+                                   "evaluates the same N_t drawn pairs",
+            "hbm_frac_step": hbm_step / HBM_PEAK_GBS,
             "event_ms_per_step": (r["t_stream"] + r["t_collide"]) * 1e3,
             "kernel_timing": "second pass of the same steps: boltz_stream and boltz_collide called separately "
                              "with HIP events between them on the launch stream",
-            "roofline": roof, "kernels": {"stream": stream_k}}
-    if args.variant == "auto" and kw["sample_group"] != 1:
-        print("[bench] variant: per-cell sample streams (G=1)", flush=True)
-        v = run(pkg, torch, preset.with_(sample_group=1), max(10, K // 4), max(3, args.warmup // 4))
-        line["variants"] = {"per_cell_samples_G1": {
-            "value": v["value"], "ms_per_step": v["ms_per_step"], "pairs_per_s": v["pairs_per_s"],
-            "collide_ms": v["t_collide"] * 1e3, "stream_ms": v["t_stream"] * 1e3,
-            "steps": max(10, K // 4)}}
+            "roofline": _roofline(r, kw, g), "kernels": {"stream": _stream_kernels(r)}}
+    del r, g
+    torch.cuda.empty_cache()
+    variants = line.setdefault("variants", {})
+    if args.variant == "auto":
+        c64 = pkg.PRESETS["cavity64"]
+        ks, ws = max(20, K // 2), max(5, args.warmup // 2)
+        for name, pre in (("cavity64_G0", c64.with_(sample_group=0)), ("cavity64_G1", c64.with_(sample_group=1)),
+                          ("cavity64_G0_order1", c64.with_(sample_group=0, order=1))):
+            print("[bench] variant: %s" % name, flush=True)
+            v = run(pkg, torch, pre, ks, ws)
+            variants[name] = _summary(v, v["kw"], v["g"], ks)
+            if name == "cavity64_G1":
+                variants[name]["collide"]["alu_roofline"] = alu_roofline(v)
+            del v
+            torch.cuda.empty_cache()
+    if args.full == "auto":
+        full = variants.setdefault("full_length", {})
+        for key in ("cavity200", "cavity64"):
+            pre = pkg.PRESETS[key]
+            print("[bench] full-length run: %s, %d steps" % (key, pre.steps), flush=True)
+            full[key] = run_full_length(pkg, torch, pre, 0)
     if args.adjoint == "auto":
         print("[bench] variant: reverse mode (%d-step window)" % args.window, flush=True)
-        line.setdefault("variants", {})["adjoint"] = run_adjoint(
-            pkg, torch, preset, max(10, K // 4), max(3, args.warmup // 4), args.window, 20)
+        pre = pkg.PRESETS["cavity64"].with_(sample_group=0)
+        variants["adjoint"] = run_adjoint(pkg, torch, pre, max(10, K // 4), max(3, args.warmup // 4), args.window,
+                                          20)
     if args.batch == "auto":
         print("[bench] variant: batch of %d cavities" % args.batch_count, flush=True)
-        line.setdefault("variants", {})["batch"] = run_batch(pkg, torch, args.batch_count, max(4, K // 10),
-                                                             max(1, args.warmup // 10))
+        variants["batch"] = run_batch(pkg, torch, args.batch_count, max(4, K // 10), max(1, args.warmup // 10))
     if args.cpu_baseline == "auto":
         print("[bench] CPU oracle baseline ...", flush=True)
         line["cpu_baseline"] = cpu_baseline(preset, args.cpu_seconds)

@@ -386,7 +386,7 @@ def test_window_gradient_matches_oracle_chain(lib, oracle_mod, torch_mod):
 def _c3(lib, oracle_mod=None):
     from paper_1005_5405_amd import CAVITY_64
 
-    kw = CAVITY_64.problem()
+    kw = CAVITY_64.problem(sample_group=0)
     g = lib.Boltz(**dict(kw, flags=lib.WITH_ADJOINT))
     o = oracle_mod.Oracle(**kw) if oracle_mod is not None else None
     theta0 = np.concatenate([[CAVITY_64.lid_u, 1.0, 1.0, 1.0], _profile(g.nx)])

@@ -274,7 +274,7 @@ def test_cavity_step_parity_1_and_100_steps(lib, oracle_mod, torch_mod):
 
 @pytest.mark.parametrize("which", ["cavity64", "cavity200"])
 def test_full_size_sampled_parity(lib, oracle_mod, torch_mod, which):
-    """Full-size grids in the launch configuration the benchmark times:
+    """Full-size grids with the presets' per-cell sample streams (G = 1):
     streaming checked on every node for the 64x64 cavity, collision on sampled
     cells that the oracle computes one by one (both sizes)."""
     from paper_1005_5405_amd import PRESETS, inputs
@@ -311,6 +311,63 @@ def test_full_size_sampled_parity(lib, oracle_mod, torch_mod, which):
         assert d.max() <= 1e-5 * np.abs(ref_c[k]).max(), (which, cells[k])
         assert (d * w).max() <= 1e-5 * (np.abs(ref_c[k]) * w).max(), (which, cells[k])
     assert g.read_status() == 0
+
+
+@pytest.mark.parametrize("which", ["cavity64", "cavity200"])
+def test_headline_step_parity_full_size(lib, oracle_mod, torch_mod, which):
+    """The launch configuration the benchmark times, at full size: boltz_step
+    with one shared set of N_t pair records per step (G = 0), drawn in the
+    last face launch and dealt to lanes, then the persistent collision with
+    many cells per workgroup (each after the first staged while the previous
+    one is corrected).  Sampled cells, chosen across several workgroups'
+    cell lists, against the oracle's collision of the same post-stream values
+    (the GPU streaming itself is checked on every node of the 64x64 cavity by
+    test_full_size_sampled_parity).  boltz_collide without a defect buffer
+    (the staged path) on the same post-stream state gives the same cells."""
+    from paper_1005_5405_amd import PRESETS, inputs
+
+    pre = PRESETS[which]
+    kw = pre.problem(sample_group=0)
+    _say("headline step", which, kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    step = 9
+    lid = pre.lid(step * g.dt) if pre.lid_omega > 0 else pre.lid_u
+    lid = lid if abs(lid) > 1e-3 else 0.05
+    walls_o, walls_g = oracle_mod.Walls(lid_u=lid, tau_bottom=1.02), lib.Walls(lid_u=lid, tau_bottom=1.02)
+    h32 = inputs.random_field((o.ny, o.nx, 1), seed=4, scale=0.3).astype(np.float32)
+    prof = inputs.velocity_polynomial(o.node_velocities(), seed=5, scale=0.1).astype(np.float32)
+    hin = (torch_mod.from_numpy(h32).cuda() * torch_mod.from_numpy(prof).cuda().view(1, 1, -1)).contiguous()
+    del h32
+    hout = g.empty()
+    g.step(hin, hout, walls_g, step)
+    hs = g.empty()
+    g.stream(hin, hs, walls_g)
+    del hin
+    h2 = g.empty()
+    g.collide(hs, h2, step)
+    torch_mod.cuda.synchronize()
+    assert g.read_status() == 0
+    ncell = o.nx * o.ny
+    rng = np.random.default_rng(11)
+    # first cells of workgroups, cells staged after them, the corners
+    cells = np.unique(np.concatenate([[0, 1, 255, 256, 257, 511, 512, 1023, 1024, o.nx - 1,
+                                       (o.ny - 1) * o.nx, ncell - 2, ncell - 1],
+                                      rng.integers(0, ncell, 7)]))
+    cells = cells[cells < ncell]
+    idx = torch_mod.from_numpy(cells).cuda()
+    hs_c = hs.view(-1, o.nv)[idx].cpu().numpy().astype(np.float64)
+    got_c = hout.view(-1, o.nv)[idx].cpu().numpy().astype(np.float64)
+    got2_c = h2.view(-1, o.nv)[idx].cpu().numpy().astype(np.float64)
+    ref_c = o.collide_cells(hs_c, step, cells)
+    w = o.node_weights()
+    for k in range(len(cells)):
+        for got in (got_c[k], got2_c[k]):
+            d = np.abs(got - ref_c[k])
+            assert d.max() <= 1e-5 * np.abs(ref_c[k]).max(), (which, cells[k])
+            assert (d * w).max() <= 1e-5 * (np.abs(ref_c[k]) * w).max(), (which, cells[k])
+    # the whole state: the step and the separately called halves agree (the
+    # same records; fixed-point sums do not depend on their order)
+    assert torch_mod.allclose(hout, h2, rtol=1e-6, atol=1e-6 * hout.abs().max().item())
 
 
 # Shared-sample steps through boltz_step: the pair records are drawn in the

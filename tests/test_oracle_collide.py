@@ -86,7 +86,7 @@ def _enumerate_mean_dN(n, a, h, eps, dt, delta, M, parts=False):
     return dt * K * W * W * E
 
 
-def _mc_dN(oracle_mod, n, a, h, eps, delta, nt, nsteps, mix16=0):
+def _mc_dN(oracle_mod, n, a, h, eps, delta, nt, nsteps, mix16=4):
     o = oracle_mod.Oracle(1, 1, n, a, delta, eps, nt, bc=oracle_mod.BC_PERIODIC, mix16=mix16)
     samples = []
     for st in range(nsteps):
