@@ -155,6 +155,20 @@ int boltz_stream(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_wa
 int boltz_collide(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, uint32_t flags,
                   double* defect, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * collision as boltz_collide, same arguments and results, except that the
+ * shared-sample pair records of the step (sample_group != 1) are kept in a
+ * file-scope device array of the library instead of the context: 16 MiB per
+ * device, i.e. about 699 000 records per step (half that with velocity grids
+ * whose collision sorts the records), held until the process ends.  EINVAL
+ * beyond that size.  The call allocates nothing and frees nothing.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (any context, any stream) race and must be serialised by the caller.
+ * With per-cell samples (sample_group == 1) it uses no scratch. */
+int boltz_collide_noalloc(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, uint32_t flags,
+                          double* defect, void* stream);
+
 /* S6: per-cell moments (Sec. 2, Eqs. densita..sforzi, re-derived in units
  * of V0): mom[cell*11 + k] = rho, u_x, u_y, u_z, theta, Pi_xx, Pi_xy, Pi_xz,
  * Pi_yy, Pi_yz, Pi_zz (FP64 device buffer).  lid_shear: NULL or one FP64

@@ -60,7 +60,7 @@ EXPORTS = ("boltz_create", "boltz_destroy", "boltz_query", "boltz_last_error", "
            "boltz_step_adjoint", "boltz_lid_shear_adjoint", "boltz_debug_pairs", "boltz_axis_thresholds",
            "boltz_read_status", "boltz_batch_create", "boltz_batch_destroy", "boltz_batch_query",
            "boltz_batch_last_error", "boltz_batch_offsets", "boltz_batch_problem", "boltz_batch_set_step",
-           "boltz_batch_step", "boltz_batch_tune", "boltz_batch_set_block")
+           "boltz_batch_step", "boltz_batch_tune", "boltz_batch_set_block", "boltz_collide_noalloc")
 
 _lib = None
 
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     L.boltz_last_error.restype = ctypes.c_char_p
     L.boltz_stream.argtypes = [P, V, V, W, V]
     L.boltz_collide.argtypes = [P, V, V, I64, U32, V, V]
+    L.boltz_collide_noalloc.argtypes = [P, V, V, I64, U32, V, V]
     L.boltz_moments.argtypes = [P, V, W, V, V, V]
     L.boltz_step.argtypes = [P, V, V, W, I64, V]
     L.boltz_stream_adjoint.argtypes = [P, V, V, V, V, W, V]
@@ -245,6 +246,18 @@ class Boltz:
                                        _ptr(h_out, self.numel, torch.float32, "h_out"), int(step), flags,
                                        _ptr(defect, self.ncells * 5, torch.float64, "defect", True),
                                        _stream(stream)), "boltz_collide")
+
+    def collide_noalloc(self, h_s, h_out, step, correction=True, defect=None, stream=None):
+        """boltz_collide with the shared-sample records in the library's
+        static device scratch (no allocation; calls on one GPU must not
+        overlap)."""
+        import torch
+
+        flags = 0 if correction else NO_CORRECTION
+        self._check(_lib.boltz_collide_noalloc(self._ctx, _ptr(h_s, self.numel, torch.float32, "h_s"),
+                                               _ptr(h_out, self.numel, torch.float32, "h_out"), int(step), flags,
+                                               _ptr(defect, self.ncells * 5, torch.float64, "defect", True),
+                                               _stream(stream)), "boltz_collide_noalloc")
 
     def moments(self, h, mom, walls=None, lid_shear=None, stream=None):
         import torch

@@ -67,7 +67,26 @@ struct boltz_ctx {
   float4* tcoef = nullptr;      // ngroups * n_pairs pair coefficients
   uint2* sidx = nullptr;        // the sampler's output (ACC_SPLIT: sorted into tidx, tcoef)
   float4* scoef = nullptr;
+  unsigned char* scratch = nullptr;  // this device's copy of the static record scratch
   std::string err;
+};
+
+// Record scratch of boltz_collide_noalloc (see include/boltz.h): the shared
+// pair records of one step, which that entry point keeps here instead of in
+// the context.  One copy per device, held until the process ends; host code
+// uses the address hipGetSymbolAddress returns for the current device (kept in
+// every context created on it), never the array's name.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Where a collision reads its shared records: tidx, tcoef (what the kernel
+// reads) and sidx, scoef (what the sampler writes; the same arrays unless
+// the split layout sorts them).
+struct RecordTables {
+  uint2* tidx;
+  float4* tcoef;
+  uint2* sidx;
+  float4* scoef;
 };
 
 namespace {
@@ -494,6 +513,12 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->collide_block[0] = cblock[0];
   c->collide_block[1] = cblock[1];
   c->collide_mode = cmode;
+  // this device's address of the static record scratch (boltz_collide_noalloc)
+  {
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) == hipSuccess) c->scratch = static_cast<unsigned char*>(sp);
+    else (void)hipGetLastError();
+  }
   int ncu = 0;
   hipError_t ea = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
@@ -556,15 +581,34 @@ int boltz_axis_thresholds(const boltz_ctx* c, int axis, uint64_t* out) {
 
 // Rebuild the wall tables (Phi_w / Phi0 and the flux constants A, D) when the
 // wall state differs from the one they were built for.
+// The lid velocity and the side and top temperatures reach the kernel by
+// value; the bottom faces' temperatures (a host array) are copied only when
+// they change, and then only outside a stream capture (a captured copy would
+// read host memory that no longer exists when the graph is replayed).
 static int ensure_ratio(boltz_ctx* c, const WallArgs& W, const boltz_walls* walls, hipStream_t st) {
   std::vector<double> taub = bottom_taus(walls, c->p.nx);
-  if (c->ratio_valid && std::memcmp(&c->ratio_walls, &W, sizeof(WallArgs)) == 0 && taub == c->ratio_taub)
-    return BOLTZ_OK;
-  // from pageable host memory: staged before the call returns
-  hipError_t e = hipMemcpyAsync(const_cast<double*>(c->P.tau_b), taub.data(), taub.size() * sizeof(double),
-                                hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(c, e, "wall temperatures");
-  hipLaunchKernelGGL(wallconst_kernel, dim3(3 + c->p.nx), dim3(kWallConstBlock), 0, st, c->P, W);
+  const bool same_b = c->ratio_valid && taub == c->ratio_taub;
+  const bool same_w = c->ratio_valid && std::memcmp(&c->ratio_walls, &W, sizeof(WallArgs)) == 0;
+  if (same_b && same_w) return BOLTZ_OK;
+  int first = 0, count = 3 + c->p.nx;
+  if (same_b) {
+    // side walls (blocks 0, 1) and lid (block 2); the bottom tables stand
+    const WallArgs& o = c->ratio_walls;
+    const bool sides = o.tau[0] != W.tau[0] || o.tau[1] != W.tau[1];
+    first = sides ? 0 : 2;
+    count = sides ? 3 : 1;
+  } else {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(c, BOLTZ_EINVAL,
+                  "bottom-wall temperatures changed during a stream capture: make one call with the new walls "
+                  "before capturing");
+    // from pageable host memory: staged before the call returns
+    hipError_t e = hipMemcpyAsync(const_cast<double*>(c->P.tau_b), taub.data(), taub.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(c, e, "wall temperatures");
+  }
+  hipLaunchKernelGGL(wallconst_kernel, dim3(count), dim3(kWallConstBlock), 0, st, c->P, W, first);
   c->ratio_walls = W;
   c->ratio_taub = taub;
   c->ratio_valid = true;
@@ -643,56 +687,66 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream_kernel launch");
 }
 
+static RecordTables own_tables(const boltz_ctx* c) { return RecordTables{c->tidx, c->tcoef, c->sidx, c->scoef}; }
+
 extern "C++" template <int B, int M>
 static void launch_collide_m(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
-                             double* defect, hipStream_t st) {
+                             double* defect, hipStream_t st, const RecordTables& R) {
   const int t = table ? 1 : 0;
   const dim3 grid((unsigned)c->collide_grid[t]);
   const size_t lds = c->collide_lds[t];
   if (table)
     hipLaunchKernelGGL((collide_kernel<B, true, M>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
-                       c->tidx, c->tcoef);
+                       R.tidx, R.tcoef);
   else
     hipLaunchKernelGGL((collide_kernel<B, false, M>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
-                       c->tidx, c->tcoef);
+                       R.tidx, R.tcoef);
 }
 
 extern "C++" template <int B>
 static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
-                             double* defect, hipStream_t st) {
+                             double* defect, hipStream_t st, const RecordTables& R) {
   switch (c->collide_mode) {
-    case ACC_FIXED: launch_collide_m<B, ACC_FIXED>(c, table, hs, hout, s32, flags, defect, st); break;
-    case ACC_SPLIT: launch_collide_m<B, ACC_SPLIT>(c, table, hs, hout, s32, flags, defect, st); break;
-    default: launch_collide_m<B, ACC_CAS>(c, table, hs, hout, s32, flags, defect, st); break;
+    case ACC_FIXED: launch_collide_m<B, ACC_FIXED>(c, table, hs, hout, s32, flags, defect, st, R); break;
+    case ACC_SPLIT: launch_collide_m<B, ACC_SPLIT>(c, table, hs, hout, s32, flags, defect, st, R); break;
+    default: launch_collide_m<B, ACC_CAS>(c, table, hs, hout, s32, flags, defect, st, R); break;
   }
 }
 
 // Shared-sample mode: the pair records of every group for this step
 // (ACC_SPLIT: then sorted by the velocity half of their targets).
-static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st) {
+static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st, const RecordTables& R) {
   if (c->ngroups > 0 && c->p.n_pairs > 0) {
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     const dim3 grid((unsigned)((c->p.n_pairs + kSampleBlock - 1) / kSampleBlock), (unsigned)c->ngroups);
-    hipLaunchKernelGGL(sample_kernel, grid, dim3(kSampleBlock), TablesLDS::bytes(nsum, true), st, c->P, s32, c->sidx,
-                       c->scoef, c->sidx == c->tidx ? 1 : 0);
-    if (c->sidx != c->tidx)
-      hipLaunchKernelGGL(split_sort_kernel, dim3((unsigned)c->ngroups), dim3(kSortBlock), 0, st, c->sidx, c->scoef,
-                         c->tidx, c->tcoef, (int64_t)c->p.n_pairs, (unsigned)CollideLDS::half(c->nv));
+    hipLaunchKernelGGL(sample_kernel, grid, dim3(kSampleBlock), TablesLDS::bytes(nsum, true), st, c->P, s32, R.sidx,
+                       R.scoef, R.sidx == R.tidx ? 1 : 0);
+    if (R.sidx != R.tidx)
+      hipLaunchKernelGGL(split_sort_kernel, dim3((unsigned)c->ngroups), dim3(kSortBlock), 0, st, R.sidx, R.scoef,
+                         R.tidx, R.tcoef, (int64_t)c->p.n_pairs, (unsigned)CollideLDS::half(c->nv));
   }
+}
+
+static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st) { launch_samples(c, s32, st, own_tables(c)); }
+
+// The collision with the records in R (drawn: already written this step).
+static int launch_collide_r(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
+                            double* defect, hipStream_t st, bool drawn, const RecordTables& R) {
+  const uint32_t s32 = (uint32_t)step;
+  const bool table = c->ngroups > 0;
+  if (!drawn) launch_samples(c, s32, st, R);
+  switch (c->collide_block[table ? 1 : 0]) {
+    case 256: launch_collide_b<256>(c, table, hs, hout, s32, flags, defect, st, R); break;
+    case 512: launch_collide_b<512>(c, table, hs, hout, s32, flags, defect, st, R); break;
+    default: launch_collide_b<1024>(c, table, hs, hout, s32, flags, defect, st, R); break;
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "collide_kernel launch");
 }
 
 static int launch_collide(boltz_ctx* c, const float* hs, float* hout, int64_t step, uint32_t flags,
                           double* defect, hipStream_t st, bool drawn = false) {
-  const uint32_t s32 = (uint32_t)step;
-  const bool table = c->ngroups > 0;
-  if (!drawn) launch_samples(c, s32, st);
-  switch (c->collide_block[table ? 1 : 0]) {
-    case 256: launch_collide_b<256>(c, table, hs, hout, s32, flags, defect, st); break;
-    case 512: launch_collide_b<512>(c, table, hs, hout, s32, flags, defect, st); break;
-    default: launch_collide_b<1024>(c, table, hs, hout, s32, flags, defect, st); break;
-  }
-  const hipError_t e = hipGetLastError();
-  return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "collide_kernel launch");
+  return launch_collide_r(c, hs, hout, step, flags, defect, st, drawn, own_tables(c));
 }
 
 static bool overlap(const void* a, const void* b, size_t n) {
@@ -731,6 +785,42 @@ int boltz_collide(boltz_ctx* c, const float* h_s, float* h_out, int64_t step, ui
     return fail(c, BOLTZ_EINVAL, "boltz_collide: h_s and h_out partially overlap");
   if (flags & ~(uint32_t)BOLTZ_NO_CORRECTION) return fail(c, BOLTZ_EINVAL, "boltz_collide: unknown flag");
   return launch_collide(c, h_s, h_out, step, flags, defect, static_cast<hipStream_t>(stream));
+}
+
+int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t step, uint32_t flags,
+                          double* defect, void* stream) {
+  if (!c) return BOLTZ_EINVAL;
+  if (!h_s || !h_out) return fail(c, BOLTZ_EINVAL, "boltz_collide_noalloc: null buffer");
+  const size_t bytes = (size_t)c->ncells * c->nv * sizeof(float);
+  if (h_s != h_out && overlap(h_s, h_out, bytes))
+    return fail(c, BOLTZ_EINVAL, "boltz_collide_noalloc: h_s and h_out partially overlap");
+  if (flags & ~(uint32_t)BOLTZ_NO_CORRECTION) return fail(c, BOLTZ_EINVAL, "boltz_collide_noalloc: unknown flag");
+  RecordTables R{nullptr, nullptr, nullptr, nullptr};
+  if (c->ngroups > 0 && c->p.n_pairs > 0) {
+    if (!c->scratch) return fail(c, BOLTZ_EHIP, "boltz_collide_noalloc: no device address of the record scratch");
+    // one table: n index pairs (256-byte aligned), then n coefficient sets;
+    // the split layout needs a second one for the sampler's unsorted output
+    const size_t n = (size_t)c->ngroups * (size_t)c->p.n_pairs;
+    const bool split = c->sidx != c->tidx;
+    const size_t one = align256(n * sizeof(uint2)) + n * sizeof(float4);
+    const size_t need = split ? align256(one) + one : one;
+    if (need > kScratchBytes)
+      return fail(c, BOLTZ_EINVAL,
+                  "boltz_collide_noalloc: " + std::to_string(need) + " bytes of shared-sample records exceed the " +
+                      std::to_string(kScratchBytes) + "-byte scratch (about " +
+                      std::to_string(kScratchBytes / ((split ? 2 : 1) * 24)) + " records per step at most)");
+    unsigned char* p = c->scratch;
+    R.tidx = reinterpret_cast<uint2*>(p);
+    R.tcoef = reinterpret_cast<float4*>(p + align256(n * sizeof(uint2)));
+    R.sidx = R.tidx;
+    R.scoef = R.tcoef;
+    if (split) {
+      unsigned char* q = p + align256(one);
+      R.sidx = reinterpret_cast<uint2*>(q);
+      R.scoef = reinterpret_cast<float4*>(q + align256(n * sizeof(uint2)));
+    }
+  }
+  return launch_collide_r(c, h_s, h_out, step, flags, defect, static_cast<hipStream_t>(stream), false, R);
 }
 
 int boltz_step(boltz_ctx* c, const float* h_in, float* h_out, const boltz_walls* walls, int64_t step,

@@ -218,9 +218,11 @@ __device__ double face_density(const Params& P, const float* h, int wall, int po
 // wall state changes.
 constexpr int kWallConstBlock = 1024;
 
-__global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, WallArgs W) {
+// Blocks first, first + 1, ... of the full set (0 left, 1 right, 2 top, 3 +
+// i bottom face i): a change of the lid alone rebuilds block 2 only.
+__global__ __launch_bounds__(kWallConstBlock) void wallconst_kernel(Params P, WallArgs W, int first) {
   __shared__ double red[2 * (kWallConstBlock / 64)];
-  const int b = blockIdx.x;
+  const int b = (int)blockIdx.x + first;
   const int wall = b == 0 ? WALL_LEFT : (b == 1 ? WALL_RIGHT : (b == 2 ? WALL_TOP : WALL_BOTTOM));
   const int pos = b < 3 ? 0 : b - 3;
   const int nv = P.nv, n1 = P.n[1], n2 = P.n[2];
