@@ -45,6 +45,8 @@ struct boltz_ctx {
   // grid of the fused-sampler [0] and shared-table [1] variants
   int collide_block[2] = {256, 256};
   int collide_mode = ACC_FIXED;  // accumulation of the increments (ACC_*)
+  int batch_mode = ACC_FIXED;    // ... in batches (no ACC_HYBRID there)
+  int hyb_lo[2] = {0, 0}, hyb_n[2] = {0, 0};  // ACC_HYBRID inner nodes per variant
   size_t collide_lds[2] = {0, 0};
   int64_t collide_grid[2] = {0, 0};
   int64_t ngroups = 0;          // sample groups (shared-sample mode)
@@ -135,8 +137,26 @@ std::vector<double> bottom_taus(const boltz_walls* w, int nx) {
 
 constexpr size_t kLdsBytes = 160 * 1024;
 
-// static LDS of the collide kernel (block reduction scratch) per block size
-size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof(double) + 64; }
+// static LDS of the collide kernel (block reduction scratch and flags) per
+// block size
+size_t collide_static_lds(int block) { return 20 * (size_t)(block / 64) * sizeof(double) + 96; }
+
+// ACC_HYBRID for grids whose 64-bit layout does not fit: the most x-slabs
+// (centred; at least half of them) whose 64-bit accumulators fit next to the
+// h^s tile, the FP32 accumulators of the other slabs and the tables, with
+// 1024 threads.  lo, nin: first inner node and inner node count.
+bool pick_hybrid(const int (&n)[3], int ns, bool sampler, int& lo, int& nin) {
+  const int slab = n[1] * n[2], nv = n[0] * slab;
+  for (int S = n[0]; S >= (n[0] + 1) / 2 && S >= 1; --S) {
+    const int nn = S * slab;
+    if (CollideLDS::hyb_bytes(nv, nn, ns, sampler) + collide_static_lds(1024) <= kLdsBytes) {
+      lo = ((n[0] - S) / 2) * slab;
+      nin = nn;
+      return true;
+    }
+  }
+  return false;
+}
 
 // Accumulation mode and block sizes of the collide kernel: 64-bit
 // fixed-point accumulators for every node when they fit next to the h tile
@@ -205,6 +225,7 @@ const void* collide_fn(int block, bool table, int mode) {
   BOLTZ_COLLIDE_FN(256, ACC_CAS)
   BOLTZ_COLLIDE_FN(512, ACC_CAS)
   BOLTZ_COLLIDE_FN(1024, ACC_CAS)
+  BOLTZ_COLLIDE_FN(1024, ACC_HYBRID)
 #undef BOLTZ_COLLIDE_FN
   return nullptr;
 }
@@ -251,6 +272,15 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   if (nvt > (1 << 20) || !pick_collide((int)nvt, nsum, cmode, cblock))
     return fail(nullptr, BOLTZ_EUNSUPPORTED,
                 "boltz_create: the per-cell h and increment tiles of this velocity grid exceed the 160 KB LDS");
+  // a single problem whose grid is too large for the 64-bit layout collides
+  // in one pass with ACC_HYBRID; batches keep the classic layouts
+  const int bmode = cmode;
+  int hlo[2] = {0, 0}, hn[2] = {0, 0};
+  if (cmode != ACC_FIXED && nvt <= 65535 &&
+      pick_hybrid(p->nv, nsum, true, hlo[0], hn[0]) && pick_hybrid(p->nv, nsum, false, hlo[1], hn[1])) {
+    cmode = ACC_HYBRID;
+    cblock[0] = cblock[1] = 1024;
+  }
   if ((int64_t)p->nx * p->ny * nvt >= ((int64_t)1 << 40))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: phase-space grid too large");
   const int64_t ncells_ = (int64_t)p->nx * p->ny;
@@ -418,7 +448,17 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t o_gpart = off; off = align256(off + (size_t)nfaces * 2 * 8);
   const size_t o_tidx = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(uint2));
   const size_t o_tcoef = off; off = align256(off + (size_t)ngroups * (size_t)p->n_pairs * sizeof(float4));
-  const size_t nsort = (cmode == ACC_SPLIT) ? (size_t)ngroups * (size_t)p->n_pairs : 0;
+  const size_t nsort = (bmode == ACC_SPLIT) ? (size_t)ngroups * (size_t)p->n_pairs : 0;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess || ncu < 1) ncu = 256;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu < 1) ncu = 256;
+  }
+  // ACC_HYBRID: one global row per persistent workgroup (at most one per CU)
+  const int64_t hyb_rows = (cmode == ACC_HYBRID) ? 2 * (int64_t)ncu : 0;
+  const size_t o_hyb = off; off = align256(off + (size_t)hyb_rows * (size_t)nvt * 4);
   const size_t o_sidx = off; off = align256(off + nsort * sizeof(uint2));
   const size_t o_scoef = off; off = align256(off + nsort * sizeof(float4));
   const bool with_adj = (p->flags & BOLTZ_WITH_ADJOINT) != 0;
@@ -447,6 +487,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     }
   }
   e = hipMemset(base + o_nw, 0, o_status + 4 - o_nw);
+  if (e == hipSuccess && hyb_rows) e = hipMemset(base + o_hyb, 0, (size_t)hyb_rows * (size_t)nvt * 4);
   if (e != hipSuccess) {
     boltz_destroy(c);
     return fail(nullptr, BOLTZ_EHIP, std::string("boltz_create: hipMemset: ") + hipGetErrorString(e));
@@ -501,6 +542,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.dpart = reinterpret_cast<double*>(base + o_dpart);
   P.wconst = reinterpret_cast<double*>(base + o_wconst);
   P.status = reinterpret_cast<uint32_t*>(base + o_status);
+  P.hyb_lo = hlo[1];
+  P.hyb_n = hn[1];
+  P.hyb_ovf = hyb_rows ? reinterpret_cast<float*>(base + o_hyb) : nullptr;
   c->ngroups = ngroups;
   c->tidx = ngroups ? reinterpret_cast<uint2*>(base + o_tidx) : nullptr;
   c->tcoef = ngroups ? reinterpret_cast<float4*>(base + o_tcoef) : nullptr;
@@ -513,23 +557,32 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->collide_block[0] = cblock[0];
   c->collide_block[1] = cblock[1];
   c->collide_mode = cmode;
+  c->batch_mode = bmode;
+  for (int t = 0; t < 2; ++t) {
+    c->hyb_lo[t] = hlo[t];
+    c->hyb_n[t] = hn[t];
+  }
   // this device's address of the static record scratch (boltz_collide_noalloc)
   {
     void* sp = nullptr;
     if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) == hipSuccess) c->scratch = static_cast<unsigned char*>(sp);
     else (void)hipGetLastError();
   }
-  int ncu = 0;
   hipError_t ea = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
     const void* fn = collide_fn(cblock[t], t == 1, cmode);
-    c->collide_lds[t] = CollideLDS::bytes(c->nv, nsum, cmode, t == 0);
-    ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->collide_lds[t]);
+    c->collide_lds[t] = cmode == ACC_HYBRID ? CollideLDS::hyb_bytes(c->nv, hn[t], nsum, t == 0)
+                                            : CollideLDS::bytes(c->nv, nsum, cmode, t == 0);
+    // the attribute is per kernel, shared by every context: the largest
+    // dynamic size the block size allows
+    ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(kLdsBytes - collide_static_lds(cblock[t])));
     int per_cu = 0;
     if (ea == hipSuccess)
       ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cblock[t], c->collide_lds[t]);
     if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
-    const int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
+    int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
+    if (cmode == ACC_HYBRID) cap = std::min<int64_t>(cap, hyb_rows);
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
   }
   c->adj_supported = ea == hipSuccess && pick_adjoint(c->nv, nsum, c->adj_block, c->adj_fixed);
@@ -618,7 +671,7 @@ static int ensure_ratio(boltz_ctx* c, const WallArgs& W, const boltz_walls* wall
 // Shared pair records that can be drawn in the last face launch: a table
 // written directly by the sampler (no split-mode sort after it).
 static bool samples_with_walls(const boltz_ctx* c) {
-  return c->ngroups > 0 && c->p.n_pairs > 0 && c->sidx == c->tidx;
+  return c->ngroups > 0 && c->p.n_pairs > 0 && c->collide_mode != ACC_SPLIT;
 }
 
 // The face densities; with sample_step >= 0 (and samples_with_walls) the
@@ -687,7 +740,10 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
   return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "stream_kernel launch");
 }
 
-static RecordTables own_tables(const boltz_ctx* c) { return RecordTables{c->tidx, c->tcoef, c->sidx, c->scoef}; }
+static RecordTables own_tables(const boltz_ctx* c) {
+  const bool split = c->collide_mode == ACC_SPLIT;
+  return RecordTables{c->tidx, c->tcoef, split ? c->sidx : c->tidx, split ? c->scoef : c->tcoef};
+}
 
 extern "C++" template <int B, int M>
 static void launch_collide_m(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
@@ -695,11 +751,14 @@ static void launch_collide_m(boltz_ctx* c, bool table, const float* hs, float* h
   const int t = table ? 1 : 0;
   const dim3 grid((unsigned)c->collide_grid[t]);
   const size_t lds = c->collide_lds[t];
+  Params P = c->P;
+  P.hyb_lo = c->hyb_lo[t];
+  P.hyb_n = c->hyb_n[t];
   if (table)
-    hipLaunchKernelGGL((collide_kernel<B, true, M>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
+    hipLaunchKernelGGL((collide_kernel<B, true, M>), grid, dim3(B), lds, st, P, hs, hout, s32, flags, defect,
                        R.tidx, R.tcoef);
   else
-    hipLaunchKernelGGL((collide_kernel<B, false, M>), grid, dim3(B), lds, st, c->P, hs, hout, s32, flags, defect,
+    hipLaunchKernelGGL((collide_kernel<B, false, M>), grid, dim3(B), lds, st, P, hs, hout, s32, flags, defect,
                        R.tidx, R.tcoef);
 }
 
@@ -707,6 +766,9 @@ extern "C++" template <int B>
 static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* hout, uint32_t s32, uint32_t flags,
                              double* defect, hipStream_t st, const RecordTables& R) {
   switch (c->collide_mode) {
+    case ACC_HYBRID:
+      if (B == 1024) launch_collide_m<1024, ACC_HYBRID>(c, table, hs, hout, s32, flags, defect, st, R);
+      break;
     case ACC_FIXED: launch_collide_m<B, ACC_FIXED>(c, table, hs, hout, s32, flags, defect, st, R); break;
     case ACC_SPLIT: launch_collide_m<B, ACC_SPLIT>(c, table, hs, hout, s32, flags, defect, st, R); break;
     default: launch_collide_m<B, ACC_CAS>(c, table, hs, hout, s32, flags, defect, st, R); break;
@@ -801,7 +863,7 @@ int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t 
     // one table: n index pairs (256-byte aligned), then n coefficient sets;
     // the split layout needs a second one for the sampler's unsorted output
     const size_t n = (size_t)c->ngroups * (size_t)c->p.n_pairs;
-    const bool split = c->sidx != c->tidx;
+    const bool split = c->collide_mode == ACC_SPLIT;
     const size_t one = align256(n * sizeof(uint2)) + n * sizeof(float4);
     const size_t need = split ? align256(one) + one : one;
     if (need > kScratchBytes)
@@ -1167,7 +1229,7 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     C.tcoef = c->tcoef;
     C.sidx = c->sidx;
     C.scoef = c->scoef;
-    C.mode = c->collide_mode;
+    C.mode = c->batch_mode;
     b->hoff.push_back(off);
     off += c->ncells * (int64_t)c->nv;
     const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
@@ -1190,11 +1252,11 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     }
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     const bool table = c->ngroups > 0;
-    lds_max = std::max(lds_max, CollideLDS::bytes(c->nv, nsum, c->collide_mode, !table));
+    lds_max = std::max(lds_max, CollideLDS::bytes(c->nv, nsum, c->batch_mode, !table));
     if (table) slds_max = std::max(slds_max, TablesLDS::bytes(nsum, true));
     // relative cost of one cell: pair loop (drawn pairs cost more) plus the node phases
     cost[i] = (double)c->p.n_pairs * (table ? 1.0 : 3.0) *
-                  (c->collide_mode == ACC_FIXED ? 1.0 : (c->collide_mode == ACC_SPLIT ? 1.3 : 4.0)) +
+                  (c->batch_mode == ACC_FIXED ? 1.0 : (c->batch_mode == ACC_SPLIT ? 1.3 : 4.0)) +
               40.0 * c->nv;
     b->pair_cells += c->ncells * c->p.n_pairs;
   }

@@ -469,7 +469,12 @@ __device__ __forceinline__ bool solve5(const double* S, const double* r, double*
 //              twice, each pass keeping the increments of one half of the
 //              velocity index (10 B/node; grids too large for ACC_FIXED)
 //   ACC_CAS    FP32 compare-and-swap for every node (8 B/node)
-enum : int { ACC_CAS = 0, ACC_FIXED = 1, ACC_SPLIT = 2 };
+//   ACC_HYBRID one pass for grids too large for ACC_FIXED: 64-bit fixed point
+//              for the inner x-slabs of the velocity grid, FP32
+//              compare-and-swap for the outer slabs (rarely reached), next to
+//              the full h^s tile; h^c is not stored but formed again from
+//              h^s and the accumulators where it is read
+enum : int { ACC_CAS = 0, ACC_FIXED = 1, ACC_SPLIT = 2, ACC_HYBRID = 3 };
 
 // Dynamic LDS of the collide kernel: the h^s tile (FP32), the accumulators,
 // then the tables.  The region after the tile holds h^c after the pair pass
@@ -486,7 +491,67 @@ struct CollideLDS {
   static __host__ __device__ size_t bytes(int nv, int ns, int mode, bool sampler) {
     return tile(nv) + acc(nv, mode) + TablesLDS::bytes(ns, sampler);
   }
+  // ACC_HYBRID with nin inner nodes: 64-bit accumulators, then the FP32 ones
+  static __host__ __device__ size_t hyb64(int nin) { return ((size_t)nin * 8 + 15) & ~(size_t)15; }
+  static __host__ __device__ size_t hyb_acc(int nv, int nin) {
+    return hyb64(nin) + (((size_t)(nv - nin) * 4 + 15) & ~(size_t)15);
+  }
+  static __host__ __device__ size_t hyb_bytes(int nv, int nin, int ns, bool sampler) {
+    return tile(nv) + hyb_acc(nv, nin) + TablesLDS::bytes(ns, sampler);
+  }
 };
+
+// Accumulators of ACC_HYBRID: nodes lo .. lo + n - 1 in in[node - lo]
+// (64-bit fixed point), the others in out[slot] (FP32; slot = node below
+// lo, node - n above); ovf: the workgroup's global row for terms beyond the
+// 64-bit range, with flag (LDS) raised when it is used.
+struct Hyb {
+  unsigned long long* in;
+  float* out;
+  int lo;
+  unsigned n;
+  float* ovf;
+  unsigned* flag;
+  __device__ __forceinline__ bool inner(int j) const { return (unsigned)(j - lo) < n; }
+  __device__ __forceinline__ int slot(int j) const { return j < lo ? j : j - (int)n; }
+};
+
+// A term whose fast form failed (outside the 64-bit window, or an outer node).
+__device__ __forceinline__ void hyb_slow(const Hyb& H, int j, double k, double g) {
+  const double x = k * g;
+  if (H.inner(j)) {
+    unsigned long long v;
+    if (fixed_exact(x, v)) {
+      __hip_atomic_fetch_add(&H.in[j - H.lo], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      atomicAdd(&H.ovf[j], (float)x);
+      *H.flag = 1u;
+    }
+  } else {
+    lds_add(&H.out[H.slot(j)], (float)x);
+  }
+}
+
+// The four terms of a sample: the 64-bit adds run predicated per lane for
+// inner targets inside the fast window; the few others (outer slabs, far
+// tails) take hyb_slow.
+__device__ __forceinline__ void scatter_hybrid(const Hyb& H, int a, int b, int as, int bs, double kas, double kbs,
+                                               double ka, double kb, float g) {
+  const double gd = (double)g;
+  const long long d0 = fixed_of(kas, gd), d1 = fixed_of(kbs, gd), d2 = fixed_of(-ka, gd), d3 = fixed_of(-kb, gd);
+  const bool f0 = H.inner(as) && in_fixed_window(d0), f1 = H.inner(bs) && in_fixed_window(d1);
+  const bool f2 = H.inner(a) && in_fixed_window(d2), f3 = H.inner(b) && in_fixed_window(d3);
+  if (f0) __hip_atomic_fetch_add(&H.in[as - H.lo], (unsigned long long)d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (f1) __hip_atomic_fetch_add(&H.in[bs - H.lo], (unsigned long long)d1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (f2) __hip_atomic_fetch_add(&H.in[a - H.lo], (unsigned long long)d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (f3) __hip_atomic_fetch_add(&H.in[b - H.lo], (unsigned long long)d3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (__any(!(f0 && f1 && f2 && f3))) {
+    if (!f0) hyb_slow(H, as, kas, gd);
+    if (!f1) hyb_slow(H, bs, kbs, gd);
+    if (!f2) hyb_slow(H, a, -ka, gd);
+    if (!f3) hyb_slow(H, b, -kb, gd);
+  }
+}
 
 // nodes per thread of one ACC_SPLIT half kept in registers between passes
 template <int BLOCK>
@@ -494,8 +559,8 @@ constexpr int split_regs() { return 8192 / BLOCK; }
 
 // float4 registers per thread holding the next cell's h^s tile: 4, or 2
 // with 1024 threads (enough for 8192 nodes)
-template <int BLOCK>
-constexpr int prefetch_regs() { return BLOCK >= 1024 ? 2 : 4; }
+template <int BLOCK, int MODE = ACC_FIXED>
+constexpr int prefetch_regs() { return (BLOCK >= 1024 && MODE != ACC_HYBRID) ? 2 : 4; }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
@@ -581,7 +646,7 @@ template <int BLOCK, bool TABLE, int MODE>
 __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, const float* hs, float* accf,
                                           unsigned long long* acc64, uint32_t group, uint32_t step,
                                           const uint2* __restrict__ tidx, const float4* __restrict__ tcoef,
-                                          int lo = 0, unsigned n = 0) {
+                                          int lo = 0, unsigned n = 0, const Hyb* H = nullptr) {
   const int tid = threadIdx.x;
   const float epsf = (float)P.eps;
   const uint32_t nt = (uint32_t)P.n_pairs;
@@ -625,9 +690,14 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
         const float g = (ha[u] + hb[u]) + (epsf * ha[u]) * hb[u];
-        if (ok[u])
+        if (MODE == ACC_HYBRID) {
+          if (ok[u])
+            scatter_hybrid(*H, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
+                           (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
+        } else if (ok[u]) {
           scatter<MODE>(accf, acc64, lo, n, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16),
                         (int)(id[u].y & 0xFFFFu), (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
+        }
       }
     };
     uint32_t m = tid;
@@ -639,7 +709,8 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
       if (p.as >= 0) {
         const float ha = hs[p.a], hb = hs[p.b];
         const float g = (ha + hb) + (epsf * ha) * hb;
-        scatter<MODE>(accf, acc64, lo, n, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+        if (MODE == ACC_HYBRID) scatter_hybrid(*H, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+        else scatter<MODE>(accf, acc64, lo, n, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
       }
     }
   }
@@ -724,6 +795,232 @@ __device__ __forceinline__ void correction_sums(const TablesLDS& T, const double
     acc[18] += Q1;
     acc[19] += c2 * Q0 + Q2;
   }
+}
+
+// ---------------------------------------------------- ACC_HYBRID cells --
+// Increment of h at node j from its accumulator (and the workgroup's global
+// row when the cell used it).
+__device__ __forceinline__ double hyb_dh(const Hyb& H, int j, bool flagged) {
+  double dh = H.inner(j) ? from_fixed(H.in[j - H.lo]) : (double)H.out[H.slot(j)];
+  if (flagged) dh += (double)H.ovf[j];
+  return dh;
+}
+
+// correction_sums with h^c formed from h^s and the accumulators (rows are
+// whole x-slab members, so a row is inner or outer as a whole).
+template <int BLOCK>
+__device__ __forceinline__ void correction_sums_hybrid(const TablesLDS& T, const double* zmom, const float* hs,
+                                                       const Hyb& H, bool flagged, int n0, int n1, int n2,
+                                                       double (&acc)[20]) {
+  const double* vx = T.v;
+  const double* vy = T.v + n0;
+  const double* omx = T.om;
+  const double* omy = T.om + n0;
+  const const_f64* zc = (const const_f64*)zmom;
+  const bool vec = (n2 & 3) == 0 && !flagged;
+#pragma unroll
+  for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+  for (int row = threadIdx.x; row < n0 * n1; row += BLOCK) {
+    const int jx = row / n1, jy = row - (row / n1) * n1;
+    const int j0 = row * n2;
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
+    auto node = [&](int jz, float hsf, double dh) {
+      const const_f64* z = zc + 8 * jz;
+      const float hcf = (float)((double)hsf + dh);
+      const double hc = (double)hcf, d = hc - (double)hsf;
+      S0 = fma(z[0], hc, S0);
+      S1 = fma(z[1], hc, S1);
+      S2 = fma(z[2], hc, S2);
+      S3 = fma(z[3], hc, S3);
+      S4 = fma(z[4], hc, S4);
+      R0 = fma(z[0], d, R0);
+      R1 = fma(z[1], d, R1);
+      R2 = fma(z[2], d, R2);
+    };
+    if (vec) {
+      const f32x4* hsr = reinterpret_cast<const f32x4*>(hs + j0);
+      if (H.inner(j0)) {
+        const u64x2* q = reinterpret_cast<const u64x2*>(H.in + (j0 - H.lo));
+        for (int c = 0; c < (n2 >> 2); ++c) {
+          const f32x4 s4 = hsr[c];
+          const u64x2 qa = q[2 * c], qb = q[2 * c + 1];
+          node(4 * c, s4.x, from_fixed(qa.x));
+          node(4 * c + 1, s4.y, from_fixed(qa.y));
+          node(4 * c + 2, s4.z, from_fixed(qb.x));
+          node(4 * c + 3, s4.w, from_fixed(qb.y));
+        }
+      } else {
+        const f32x4* o = reinterpret_cast<const f32x4*>(H.out + H.slot(j0));
+        for (int c = 0; c < (n2 >> 2); ++c) {
+          const f32x4 s4 = hsr[c], o4 = o[c];
+          node(4 * c, s4.x, (double)o4.x);
+          node(4 * c + 1, s4.y, (double)o4.y);
+          node(4 * c + 2, s4.z, (double)o4.z);
+          node(4 * c + 3, s4.w, (double)o4.w);
+        }
+      }
+    } else {
+      for (int jz = 0; jz < n2; ++jz) node(jz, hs[j0 + jz], hyb_dh(H, j0 + jz, flagged));
+    }
+    const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
+    const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
+    const double E0 = c2 * T0 + T2;
+    acc[0] += T0;
+    acc[1] += a * T0;
+    acc[2] += b * T0;
+    acc[3] += T1;
+    acc[4] += E0;
+    acc[5] += (a * a) * T0;
+    acc[6] += (a * b) * T0;
+    acc[7] += a * T1;
+    acc[8] += a * E0;
+    acc[9] += (b * b) * T0;
+    acc[10] += b * T1;
+    acc[11] += b * E0;
+    acc[12] += T2;
+    acc[13] += c2 * T1 + T3;
+    acc[14] += (c2 * c2) * T0 + 2.0 * c2 * T2 + T4;
+    const double Q0 = W * R0, Q1 = W * R1, Q2 = W * R2;
+    acc[15] += Q0;
+    acc[16] += a * Q0;
+    acc[17] += b * Q0;
+    acc[18] += Q1;
+    acc[19] += c2 * Q0 + Q2;
+  }
+}
+
+// One cell in the ACC_HYBRID layout (h^s tile in LDS, accumulators cleared,
+// a barrier passed): S3 + S4 pair pass, S5 sums and solve with h^c formed
+// from h^s and the accumulators, then the store pass, which forms h^c once
+// more, applies the correction, writes h^{n+1} and clears the accumulators
+// (and the global row when used).  next(): after the pair pass.  Ends with
+// a barrier.
+template <int BLOCK, bool TABLE, class Next>
+__device__ __forceinline__ void collide_body_hybrid(const Params& P, const TablesLDS& T, float* hs, const Hyb& H,
+                                                    double* red, uint32_t group, uint32_t step, uint32_t flags,
+                                                    float* dst, double* defect, const uint2* __restrict__ tidx,
+                                                    const float4* __restrict__ tcoef, Next&& next) {
+  const int tid = threadIdx.x;
+  const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const bool correct = !(flags & 1u);
+  const bool vec4 = ((n2 & 3) == 0) && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
+  const double eps = P.eps;
+  gain_loss<BLOCK, TABLE, ACC_HYBRID>(P, T, hs, nullptr, nullptr, group, step, tidx, tcoef, 0, 0u, &H);
+  __syncthreads();
+  next();
+  const bool flagged = *H.flag != 0u;
+  if (correct) {
+    double acc[20];
+    correction_sums_hybrid<BLOCK>(T, P.zmom, hs, H, flagged, n0, n1, n2, acc);
+    const int rows = n0 * n1;
+    const double t = block_sum20_w0<BLOCK>(acc, red, rows >= BLOCK ? BLOCK / 64 : (rows + 63) / 64);
+    const const_f64* m0c = (const const_f64*)P.m0;
+    if (tid < 64) {
+      double M[15], r[5], x[5];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) M[k] = m0c[k] + eps * lane_value(t, k);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) r[k] = -eps * lane_value(t, 15 + k);
+      if (!solve5(M, r, x)) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[k] = 0.0;
+        if (tid == 0) atomicOr(P.status, 1u);
+      }
+      for (int i = tid; i < n0 + n1 + n2; i += 64) {
+        const double v = T.v[i];
+        T.xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
+                         : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
+      }
+    }
+    __syncthreads();
+  }
+  // ---- h^{n+1} = h^c + F^c (x . psi) / eps, h^c formed again; the
+  // accumulators (and the global row) are left cleared for the next cell
+  bool finite = true;
+  auto out_of = [&](double hc, double xpsi) { return (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc); };
+  if (vec4 && !defect && !flagged) {
+    f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+    const f32x4* s4 = reinterpret_cast<const f32x4*>(hs);
+    NodeWalk nw4(4 * tid, 4 * BLOCK, n1, n2);
+#pragma unroll 1
+    for (int i = tid; i < (nv >> 2); i += BLOCK, nw4.next()) {
+      const int j = 4 * i;
+      const f32x4 hv = s4[i];
+      double dh[4];
+      if (H.inner(j)) {
+        u64x2* q = reinterpret_cast<u64x2*>(H.in + (j - H.lo));
+        const u64x2 qa = q[0], qb = q[1];
+        q[0] = u64x2{0ull, 0ull};
+        q[1] = u64x2{0ull, 0ull};
+        dh[0] = from_fixed(qa.x);
+        dh[1] = from_fixed(qa.y);
+        dh[2] = from_fixed(qb.x);
+        dh[3] = from_fixed(qb.y);
+      } else {
+        f32x4* o = reinterpret_cast<f32x4*>(H.out + H.slot(j));
+        const f32x4 ov = o[0];
+        o[0] = f32x4{0.f, 0.f, 0.f, 0.f};
+        dh[0] = ov.x;
+        dh[1] = ov.y;
+        dh[2] = ov.z;
+        dh[3] = ov.w;
+      }
+      const float c0 = (float)((double)hv.x + dh[0]), c1 = (float)((double)hv.y + dh[1]);
+      const float c2 = (float)((double)hv.z + dh[2]), c3 = (float)((double)hv.w + dh[3]);
+      f32x4 o;
+      if (correct) {
+        const double xa = T.xt[nw4.jx] + T.xt[n0 + nw4.jy];
+        const double* xz = T.xt + n0 + n1 + nw4.jz;
+        o.x = out_of((double)c0, xa + xz[0]);
+        o.y = out_of((double)c1, xa + xz[1]);
+        o.z = out_of((double)c2, xa + xz[2]);
+        o.w = out_of((double)c3, xa + xz[3]);
+      } else {
+        o = f32x4{c0, c1, c2, c3};
+      }
+      finite = finite && isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w);
+      d4[i] = o;
+    }
+  } else {
+    const double* vx = T.v;
+    const double* vy = T.v + n0;
+    const double* vz = T.v + n0 + n1;
+    const double* omx = T.om;
+    const double* omy = T.om + n0;
+    const double* omz = T.om + n0 + n1;
+    double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    NodeWalk nw2(tid, BLOCK, n1, n2);
+#pragma unroll 1
+    for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
+      const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
+      const float hsj = hs[j];
+      const double hc = (double)(float)((double)hsj + hyb_dh(H, j, flagged));
+      if (H.inner(j)) H.in[j - H.lo] = 0ull;
+      else H.out[H.slot(j)] = 0.0f;
+      if (flagged) H.ovf[j] = 0.0f;
+      float out = (float)hc;
+      if (correct) out = out_of(hc, (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz]);
+      finite = finite && isfinite(out);
+      dst[j] = out;
+      if (defect) {
+        const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+        const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
+        const double w = (omx[jx] * omy[jy]) * omz[jz];
+        const double diff = eps * ((double)out - (double)hsj) * w;
+        dsum[0] += diff;
+        dsum[1] += v1 * diff;
+        dsum[2] += v2 * diff;
+        dsum[3] += v3 * diff;
+        dsum[4] += vv * diff;
+      }
+    }
+    if (defect) {
+      block_sum<5>(dsum, red);
+      if (tid < 5) defect[tid] = dsum[tid];
+    }
+  }
+  if (!finite) atomicOr(P.status, 2u);
+  __syncthreads();
 }
 
 // One cell after its h^s tile is in LDS and the accumulators are cleared
@@ -954,6 +1251,52 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
   const int64_t ncells = (int64_t)P.nx * P.ny;
   const int tid = threadIdx.x;
   float* hs = reinterpret_cast<float*>(dsm);
+  if constexpr (MODE == ACC_HYBRID) {
+    // tile, 64-bit accumulators of the inner slabs, FP32 ones of the outer
+    // slabs, tables; no h^c array, so the next tile goes in at the start of
+    // each cell (from the registers it was loaded into during the previous
+    // cell's node phases)
+    __shared__ unsigned hflag[2];
+    const int nin = P.hyb_n;
+    Hyb H;
+    H.in = reinterpret_cast<unsigned long long*>(dsm + CollideLDS::tile(nv));
+    H.out = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv) + CollideLDS::hyb64(nin));
+    H.lo = P.hyb_lo;
+    H.n = (unsigned)nin;
+    H.ovf = P.hyb_ovf + (int64_t)blockIdx.x * nv;
+    TablesLDS T;
+    load_tables(P, dsm + CollideLDS::tile(nv) + CollideLDS::hyb_acc(nv, nin), !TABLE, T);
+    {
+      uint4* z = reinterpret_cast<uint4*>(dsm + CollideLDS::tile(nv));
+      const int nz = (int)(CollideLDS::hyb_acc(nv, nin) / 16);
+      for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (tid < 2) hflag[tid] = 0u;
+    }
+    const int nv4 = nv >> 2;
+    constexpr int NR = prefetch_regs<BLOCK, MODE>();
+    const bool vec = ((nv & 3) == 0) && nv4 <= NR * BLOCK && ((reinterpret_cast<uintptr_t>(hs_g) & 15) == 0);
+    Prefetch<NR> pre;
+    int64_t cell = blockIdx.x;
+    if (vec && cell < ncells) pre.load(hs_g + cell * nv, tid, BLOCK, nv4);
+    for (int k = 0; cell < ncells; cell += gridDim.x, ++k) {
+      if (vec) {
+        pre.store(hs, tid, BLOCK, nv4);
+      } else {
+        const float* src = hs_g + cell * nv;
+        for (int j = tid; j < nv; j += BLOCK) hs[j] = src[j];
+      }
+      H.flag = &hflag[k & 1];
+      if (tid == 0) hflag[(k + 1) & 1] = 0u;
+      __syncthreads();
+      const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
+      const int64_t next = cell + gridDim.x;
+      collide_body_hybrid<BLOCK, TABLE>(P, T, hs, H, red, group, step, flags, hout_g + cell * nv,
+                                        defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
+                                          if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
+                                        });
+    }
+    return;
+  }
   float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
   unsigned long long* acc64 =
       reinterpret_cast<unsigned long long*>(dsm + (MODE == ACC_SPLIT ? 1 : 2) * CollideLDS::tile(nv));

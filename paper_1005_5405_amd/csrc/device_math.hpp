@@ -183,6 +183,21 @@ __device__ __forceinline__ void lds_add_fixed_or(unsigned long long* acc, float*
   }
 }
 
+// round(x 2^32) as a 64-bit two's complement integer for |x| < 2^26, the
+// range the magic-number form (|x| < 2^18) does not reach: t = rint(x 2^32)
+// is an integer below 2^58, its high word floor(t 2^-32) and low word
+// t - 2^32 floor(t 2^-32) are exact in FP64.  false (nothing written) beyond
+// that range or for a non-finite x.
+constexpr double kFixWide = 67108864.0;  // 2^26
+__device__ __forceinline__ bool fixed_exact(double x, unsigned long long& v) {
+  if (!(fabs(x) < kFixWide)) return false;
+  const double t = rint(x * 4294967296.0);
+  const double hi = floor(t * kFixScale);
+  const double lo = fma(-hi, 4294967296.0, t);
+  v = ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+  return true;
+}
+
 // Per-thread walk over j = j0, j0 + step, ... of the velocity index with the
 // components (jx, jy, jz) updated by carries instead of integer divisions
 // (step < n1 * n2 * n0 arbitrary; each carry is at most one).

@@ -57,6 +57,12 @@ struct Params {
   double* wconst;         // [4][2] per wall: A_w, D_w of the face densities
   double* wconst_b;       // [nx][2] A, D of every bottom face
   uint32_t* status;       // device status bits
+  // ACC_HYBRID collisions: nodes hyb_lo .. hyb_lo + hyb_n - 1 (whole
+  // x-slabs) take 64-bit accumulators, the others FP32; hyb_ovf: one row of
+  // nv FP32 values per persistent workgroup for the rare terms beyond the
+  // 64-bit range (zero between uses)
+  int hyb_lo, hyb_n;
+  float* hyb_ovf;
 };
 
 // One problem of a batch: its constants and tables, the offset of its state
