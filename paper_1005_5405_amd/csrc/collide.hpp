@@ -470,8 +470,8 @@ __device__ __forceinline__ bool solve5(const double* S, const double* r, double*
 //              velocity index (10 B/node; grids too large for ACC_FIXED)
 //   ACC_CAS    FP32 compare-and-swap for every node (8 B/node)
 //   ACC_HYBRID one pass for grids too large for ACC_FIXED: 64-bit fixed point
-//              for the inner x-slabs of the velocity grid, FP32
-//              compare-and-swap for the outer slabs (rarely reached), next to
+//              for the inner x-slabs of the velocity grid, FP32 (the LDS
+//              float atomic) for the outer slabs (rarely reached), next to
 //              the full h^s tile; h^c is not stored but formed again from
 //              h^s and the accumulators where it is read
 enum : int { ACC_CAS = 0, ACC_FIXED = 1, ACC_SPLIT = 2, ACC_HYBRID = 3 };
@@ -516,40 +516,44 @@ struct Hyb {
   __device__ __forceinline__ int slot(int j) const { return j < lo ? j : j - (int)n; }
 };
 
-// A term whose fast form failed (outside the 64-bit window, or an outer node).
-__device__ __forceinline__ void hyb_slow(const Hyb& H, int j, double k, double g) {
+// An inner term outside the fast 64-bit window (far tails): the exact 64-bit
+// conversion, or beyond its range (or non-finite) the workgroup's global row.
+__device__ __forceinline__ void hyb_wide(const Hyb& H, int j, double k, double g) {
   const double x = k * g;
-  if (H.inner(j)) {
-    unsigned long long v;
-    if (fixed_exact(x, v)) {
-      __hip_atomic_fetch_add(&H.in[j - H.lo], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else {
-      atomicAdd(&H.ovf[j], (float)x);
-      *H.flag = 1u;
-    }
+  unsigned long long v;
+  if (fixed_exact(x, v)) {
+    __hip_atomic_fetch_add(&H.in[j - H.lo], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
-    lds_add(&H.out[H.slot(j)], (float)x);
+    atomicAdd(&H.ovf[j], (float)x);
+    *H.flag = 1u;
   }
 }
 
-// The four terms of a sample: the 64-bit adds run predicated per lane for
-// inner targets inside the fast window; the few others (outer slabs, far
-// tails) take hyb_slow.
+// One term of a sample: a 64-bit add for an inner target inside the fast
+// window, an FP32 add (the LDS's own float atomic, cheap for the few lanes
+// that take it) for an outer target; both run predicated per lane, without
+// a branch.  Returns whether the term needs hyb_wide.
+__device__ __forceinline__ bool hyb_term(const Hyb& H, int j, double k, double g) {
+  const long long d = fixed_of(k, g);
+  const bool in = H.inner(j);
+  const bool fast = in && in_fixed_window(d);
+  if (fast) __hip_atomic_fetch_add(&H.in[j - H.lo], (unsigned long long)d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (!in) atomicAdd(&H.out[H.slot(j)], (float)(k * g));
+  return in && !fast;
+}
+
+// The four terms of a sample (the rare wide inner terms after a wavefront
+// test).
 __device__ __forceinline__ void scatter_hybrid(const Hyb& H, int a, int b, int as, int bs, double kas, double kbs,
                                                double ka, double kb, float g) {
   const double gd = (double)g;
-  const long long d0 = fixed_of(kas, gd), d1 = fixed_of(kbs, gd), d2 = fixed_of(-ka, gd), d3 = fixed_of(-kb, gd);
-  const bool f0 = H.inner(as) && in_fixed_window(d0), f1 = H.inner(bs) && in_fixed_window(d1);
-  const bool f2 = H.inner(a) && in_fixed_window(d2), f3 = H.inner(b) && in_fixed_window(d3);
-  if (f0) __hip_atomic_fetch_add(&H.in[as - H.lo], (unsigned long long)d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  if (f1) __hip_atomic_fetch_add(&H.in[bs - H.lo], (unsigned long long)d1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  if (f2) __hip_atomic_fetch_add(&H.in[a - H.lo], (unsigned long long)d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  if (f3) __hip_atomic_fetch_add(&H.in[b - H.lo], (unsigned long long)d3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  if (__any(!(f0 && f1 && f2 && f3))) {
-    if (!f0) hyb_slow(H, as, kas, gd);
-    if (!f1) hyb_slow(H, bs, kbs, gd);
-    if (!f2) hyb_slow(H, a, -ka, gd);
-    if (!f3) hyb_slow(H, b, -kb, gd);
+  const bool w0 = hyb_term(H, as, kas, gd), w1 = hyb_term(H, bs, kbs, gd);
+  const bool w2 = hyb_term(H, a, -ka, gd), w3 = hyb_term(H, b, -kb, gd);
+  if (__any(w0 || w1 || w2 || w3)) {
+    if (w0) hyb_wide(H, as, kas, gd);
+    if (w1) hyb_wide(H, bs, kbs, gd);
+    if (w2) hyb_wide(H, a, -ka, gd);
+    if (w3) hyb_wide(H, b, -kb, gd);
   }
 }
 
