@@ -19,7 +19,8 @@
  *
  * Layout of every distribution buffer: FP32, cell-major,
  *   h[cell * nv + j],  cell = iy * nx + ix,  j = (jx * nv_y + jy) * nv_z + jz,
- * velocity node of axis k: v_i = (2 i + 1 - nv_k) * vmax_k / nv_k.
+ * velocity node of axis k: v_i = (2 i + 1 - nv_k) * vmax_k / nv_k (uniform
+ * cells), or the centre of the i-th stretched cell (boltz_problem.rv).
  *
  * Conventions of every call below:
  *   - Buffers named h*, mom, defect, lid_shear are DEVICE pointers owned by
@@ -88,6 +89,11 @@ typedef struct boltz_problem {
                          /* Maxwellian alone: accepted only on grids where   */
                          /* that law gives every node a positive probability */
                          /* (else EINVAL: tail nodes would never be drawn)   */
+  double rv;             /* velocity cells: 0 or 1 uniform; 0 < rv < 1      */
+                         /* stretched in the progression ratio rv, the      */
+                         /* smallest at the origin (Sec. 5.1): on each half */
+                         /* axis the i-th cell from the origin is w0 rv^-i  */
+                         /* long; needs even nv[k] (else EINVAL)            */
 } boltz_problem;
 
 /* Wall state for one call (Sec. 2, Eq. bcMax; Sec. 5.1). */

@@ -47,7 +47,7 @@ class _Problem(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("dt", ctypes.c_double), ("order", ctypes.c_int32),
                 ("bc", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("sample_group", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("cavity_id", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("mix16", ctypes.c_uint32)]
+                ("mix16", ctypes.c_uint32), ("rv", ctypes.c_double)]
 
 
 class _Walls(ctypes.Structure):
@@ -74,6 +74,7 @@ def _load():
         L.boltz_ref_set_threads.argtypes = [ctypes.c_int]
         L.boltz_ref_get_threads.restype = ctypes.c_int
         L.boltz_ref_axis.argtypes = [P, ctypes.c_int, V, V, V]
+        L.boltz_ref_axis_edges.argtypes = [P, ctypes.c_int, V]
         L.boltz_ref_axis_draw.argtypes = [P, ctypes.c_int, U32]
         L.boltz_ref_philox4x32_10.argtypes = [V, V, V]
         L.boltz_ref_cos_sin_2pi.argtypes = [D, ctypes.POINTER(D), ctypes.POINTER(D)]
@@ -146,13 +147,14 @@ class Oracle:
     """One problem set-up of the oracle (FP64, host memory)."""
 
     def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2,
-                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4):
+                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0):
         L = _load()
         nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
         vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
         p = _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax),
                      float(delta), float(eps), float(cfl), float(dt), int(order), int(bc),
-                     int(n_pairs), int(sample_group), int(seed), int(cavity_id), int(flags), int(mix16))
+                     int(n_pairs), int(sample_group), int(seed), int(cavity_id), int(flags), int(mix16),
+                     float(rv))
         ctx = ctypes.c_void_p()
         rc = L.boltz_ref_create(ctypes.byref(p), ctypes.byref(ctx))
         if rc != 0:
@@ -168,7 +170,11 @@ class Oracle:
         self.v = []
         self.omega = []
         self.thresholds = []
+        self.edges = []
         for k in range(3):
+            e = np.zeros(nv[k] + 1)
+            L.boltz_ref_axis_edges(ctx, k, e.ctypes.data)
+            self.edges.append(e)
             v = np.zeros(nv[k])
             om = np.zeros(nv[k])
             thr = np.zeros(max(nv[k] - 1, 1), dtype=np.uint64)

@@ -40,6 +40,8 @@ struct boltz_ref_ctx {
   int nv, ncells;
   double dvel[3];
   double inv_cell[3]; /* n / (2 a): maps x + a to a cell coordinate */
+  int stretched;      /* cells in geometric progression (Sec. 5.1)        */
+  double* edge[3];    /* stretched grids: cell edges e_0 = -a .. e_n = a    */
   double* v[3];
   double* om[3];
   double Om[3];
@@ -88,6 +90,7 @@ void boltz_ref_destroy(boltz_ref_ctx* c) {
     free(c->T[k]);
     free(c->pphi[k]);
     free(c->punif[k]);
+    free(c->edge[k]);
   }
   free(c);
 }
@@ -114,6 +117,14 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
       p->n_pairs >= (int64_t)1 << 31 || p->sample_group < 0 || p->mix16 > 16 ||
       (!(p->dt > 0.0) && !(p->cfl > 0.0))) {
     set_err(g_create_err, "invalid scalar parameter");
+    return BOLTZ_REF_EINVAL;
+  }
+  /* rv: 0 or 1 = uniform velocity cells; 0 < rv < 1 = cells stretched in
+   * the progression ratio rv, smallest at the origin (Sec. 5.1), which needs
+   * an even cell count per axis */
+  const int stretched = (p->rv != 0.0 && p->rv != 1.0);
+  if (stretched && (!(p->rv > 0.0 && p->rv < 1.0) || (p->nv[0] & 1) || (p->nv[1] & 1) || (p->nv[2] & 1))) {
+    set_err(g_create_err, "stretched velocity grid needs 0 < rv < 1 and an even cell count per axis");
     return BOLTZ_REF_EINVAL;
   }
   boltz_ref_ctx* c = (boltz_ref_ctx*)calloc(1, sizeof(*c));
@@ -145,12 +156,58 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
     c->dvel[k] = (2.0 * a) / n;
     c->inv_cell[k] = (double)n / (2.0 * a);
     double om_sum = 0.0;
-    for (int i = 0; i < n; ++i) {
-      double vi = ((double)(2 * i + 1 - n) * a) / n;
-      c->v[k][i] = vi;
-      /* per-axis midpoint weight of Phi0: omega = dv exp(-v^2)/sqrt(pi) */
-      c->om[k][i] = (c->dvel[k] * exp(-(vi * vi))) * INV_SQRT_PI;
-      om_sum += c->om[k][i];
+    if (!stretched) {
+      for (int i = 0; i < n; ++i) {
+        double vi = ((double)(2 * i + 1 - n) * a) / n;
+        c->v[k][i] = vi;
+        /* per-axis midpoint weight of Phi0: omega = dv exp(-v^2)/sqrt(pi) */
+        c->om[k][i] = (c->dvel[k] * exp(-(vi * vi))) * INV_SQRT_PI;
+        om_sum += c->om[k][i];
+      }
+    } else {
+      /* Sec. 5.1: cell lengths stretched in the progression ratio rv, the
+       * smallest at the origin: on each half axis the i-th cell from the
+       * origin is w0 rv^-i long, i = 0 .. m-1 (m = n/2), and the lengths add
+       * up to a; the outermost edge is set to a exactly.  Nodes at the cell
+       * centres, the negative half the exact mirror of the positive one. */
+      const int m = n / 2;
+      double* e = (double*)malloc(sizeof(double) * (n + 1));
+      double* E = (double*)malloc(sizeof(double) * (m + 1));
+      c->edge[k] = e;
+      if (!e || !E) {
+        free(E);
+        boltz_ref_destroy(c);
+        set_err(g_create_err, "out of memory");
+        return BOLTZ_REF_ENOMEM;
+      }
+      double sum = 0.0, t = 1.0;
+      for (int i = 0; i < m; ++i) {
+        sum += t;
+        t /= p->rv;
+      }
+      const double w0 = a / sum;
+      E[0] = 0.0;
+      t = 1.0;
+      for (int i = 0; i < m; ++i) {
+        E[i + 1] = E[i] + w0 * t;
+        t /= p->rv;
+      }
+      E[m] = a;
+      for (int i = 0; i <= m; ++i) {
+        e[m + i] = E[i];
+        e[m - i] = -E[i];
+      }
+      for (int i = 0; i < m; ++i) {
+        const double vi = 0.5 * (E[i] + E[i + 1]);
+        c->v[k][m + i] = vi;
+        c->v[k][m - 1 - i] = -vi;
+      }
+      free(E);
+      for (int i = 0; i < n; ++i) {
+        const double vi = c->v[k][i];
+        c->om[k][i] = ((e[i + 1] - e[i]) * exp(-(vi * vi))) * INV_SQRT_PI;
+        om_sum += c->om[k][i];
+      }
     }
     c->Om[k] = om_sum;
     /* cumulative thresholds of the per-axis node law, on 12-bit fields */
@@ -189,6 +246,7 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
           return BOLTZ_REF_EINVAL;
         }
   }
+  c->stretched = stretched;
   c->beta = p->mix16 / 16.0;
   c->ncells = p->nx * p->ny;
   c->dx = 1.0 / p->nx;
@@ -228,6 +286,14 @@ int boltz_ref_info(const boltz_ref_ctx* c, double* out) {
   out[BOLTZ_REF_INFO_DY] = c->dy;
   out[BOLTZ_REF_INFO_NCELLS] = c->ncells;
   out[BOLTZ_REF_INFO_NV] = c->nv;
+  return BOLTZ_REF_OK;
+}
+
+int boltz_ref_axis_edges(const boltz_ref_ctx* c, int axis, double* edges) {
+  if (!c || axis < 0 || axis > 2 || !edges) return BOLTZ_REF_EINVAL;
+  const int n = c->n[axis];
+  for (int i = 0; i <= n; ++i)
+    edges[i] = c->stretched ? c->edge[axis][i] : -c->a[axis] + i * c->dvel[axis];
   return BOLTZ_REF_OK;
 }
 
@@ -355,8 +421,20 @@ int boltz_ref_axis_draw(const boltz_ref_ctx* c, int axis, uint32_t f) {
   return axis_draw(c, axis, f);
 }
 
-/* Cell of a velocity component, or -1 outside the box. */
+/* Cell of a velocity component, or -1 outside the box: uniform cells by
+ * floor((x + a) n / 2a); stretched cells by counting the interior edges at
+ * or below x (a component on an edge belongs to the upper cell, as with the
+ * floor), outside when x < e_0 or x >= e_n. */
 static int axis_cell(const boltz_ref_ctx* c, int k, double x) {
+  if (c->stretched) {
+    const double* e = c->edge[k];
+    const int n = c->n[k];
+    if (!(x >= e[0] && x < e[n])) return -1;
+    int cnt = 0;
+    for (int i = 1; i < n; ++i)
+      if (x >= e[i]) cnt++;
+    return cnt;
+  }
   double t = floor((x + c->a[k]) * c->inv_cell[k]);
   if (!(t >= 0.0 && t < (double)c->n[k])) return -1;
   return (int)t;

@@ -59,6 +59,9 @@ typedef struct boltz_ref_problem {
   uint32_t mix16;        /* uniform share of the pair law, in 1/16 (0..16); */
                          /* 0 only on grids where every node has a positive */
                          /* Maxwellian-law probability (else EINVAL)        */
+  double rv;             /* 0 or 1: uniform velocity cells; 0 < rv < 1:     */
+                         /* cells stretched in the progression ratio rv,    */
+                         /* smallest at the origin (Sec. 5.1; even counts)  */
 } boltz_ref_problem;
 
 typedef struct boltz_ref_walls {
@@ -88,6 +91,10 @@ int boltz_ref_get_threads(void);
  * thresholds T_1..T_{n-1} of the node law on 12-bit fields (T in [0, 4096]). */
 int boltz_ref_axis(const boltz_ref_ctx* ctx, int axis, double* v, double* omega,
                    uint64_t* thresholds /* n-1 entries */);
+
+/* Cell edges of one axis (n + 1 values from -a to a): uniform cells, or
+ * the stretched cells of Sec. 5.1. */
+int boltz_ref_axis_edges(const boltz_ref_ctx* ctx, int axis, double* edges);
 
 /* Inverse CDF of the per-axis node law on a 12-bit field f:
  * #{i in [1, n) : f >= T_i} (-1 for f >= 4096). */

@@ -30,7 +30,7 @@ struct boltz_ctx {
   boltz_problem p{};
   int n[3]{};
   double a[3]{}, dvel[3]{}, inv_cell[3]{};
-  std::vector<double> v[3], om[3];
+  std::vector<double> v[3], om[3], edge[3];
   std::vector<uint64_t> T[3];
   std::vector<double> pphi[3], punif[3];
   double dx = 0, dy = 0, dt = 0, K = 0, W = 0, qfac = 0;
@@ -265,6 +265,10 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       (!(p->dt > 0.0) && !(p->cfl > 0.0)) ||
       (p->flags & ~(uint32_t)(BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT)))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: invalid scalar parameter");
+  const bool stretched = p->rv != 0.0 && p->rv != 1.0;
+  if (stretched && (!(p->rv > 0.0 && p->rv < 1.0) || (p->nv[0] & 1) || (p->nv[1] & 1) || (p->nv[2] & 1)))
+    return fail(nullptr, BOLTZ_EINVAL,
+                "boltz_create: a stretched velocity grid needs 0 < rv < 1 and an even cell count per axis");
   const int64_t nvt = (int64_t)p->nv[0] * p->nv[1] * p->nv[2];
   const int nsum = p->nv[0] + p->nv[1] + p->nv[2];
   int cmode = ACC_FIXED;
@@ -306,13 +310,50 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     c->inv_cell[k] = (double)n / (2.0 * a);
     c->v[k].resize(n);
     c->om[k].resize(n);
+    c->edge[k].resize(n + 1);
     c->T[k].assign(n, 0);
     double osum = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double vi = ((double)(2 * i + 1 - n) * a) / n;
-      c->v[k][i] = vi;
-      c->om[k][i] = (c->dvel[k] * std::exp(-(vi * vi))) * kInvSqrtPi;
-      osum += c->om[k][i];
+    if (!stretched) {
+      for (int i = 0; i < n; ++i) {
+        const double vi = ((double)(2 * i + 1 - n) * a) / n;
+        c->v[k][i] = vi;
+        c->om[k][i] = (c->dvel[k] * std::exp(-(vi * vi))) * kInvSqrtPi;
+        osum += c->om[k][i];
+      }
+      for (int i = 0; i <= n; ++i) c->edge[k][i] = -a + i * c->dvel[k];
+    } else {
+      // Sec. 5.1: the i-th cell from the origin on each half axis is
+      // w0 rv^-i long (the smallest at the origin, lengths adding up to a,
+      // outermost edge a exactly); nodes at the cell centres, the negative
+      // half the mirror image of the positive one
+      const int m = n / 2;
+      double sum = 0.0, t = 1.0;
+      for (int i = 0; i < m; ++i) {
+        sum += t;
+        t /= p->rv;
+      }
+      const double w0 = a / sum;
+      std::vector<double> E(m + 1, 0.0);
+      t = 1.0;
+      for (int i = 0; i < m; ++i) {
+        E[i + 1] = E[i] + w0 * t;
+        t /= p->rv;
+      }
+      E[m] = a;
+      for (int i = 0; i <= m; ++i) {
+        c->edge[k][m + i] = E[i];
+        c->edge[k][m - i] = -E[i];
+      }
+      for (int i = 0; i < m; ++i) {
+        const double vi = 0.5 * (E[i] + E[i + 1]);
+        c->v[k][m + i] = vi;
+        c->v[k][m - 1 - i] = -vi;
+      }
+      for (int i = 0; i < n; ++i) {
+        const double vi = c->v[k][i];
+        c->om[k][i] = ((c->edge[k][i + 1] - c->edge[k][i]) * std::exp(-(vi * vi))) * kInvSqrtPi;
+        osum += c->om[k][i];
+      }
     }
     // node law of one axis on a 12-bit field f: node i for f in
     // [T_i, T_{i+1}), T_i = round(2^12 sum_{l<i} omega_l / sum omega)
@@ -378,6 +419,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
 
   // ---- host images of the device tables
   std::vector<double> vtab(3 * kMaxAxis, 0.0), omtab(3 * kMaxAxis, 0.0), rwtab(3 * kMaxAxis, 0.0);
+  std::vector<double> edgetab(3 * (kMaxAxis + 1), 0.0);
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i <= c->n[k]; ++i) edgetab[k * (kMaxAxis + 1) + i] = c->edge[k][i];
   std::vector<float4> nqtab(3 * kMaxAxis, make_float4(0.f, 0.f, 0.f, 0.f));
   std::vector<uint8_t> icdf(3 * kFieldSize, 0);
   std::vector<float> cour(2 * kMaxAxis, 0.f), cour2(2 * kMaxAxis, 0.f);
@@ -428,6 +472,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const int nfaces = 2 * (p->nx + p->ny);
   size_t off = 0;
   const size_t o_v = off; off = align256(off + vtab.size() * 8);
+  const size_t o_edge = off; off = align256(off + edgetab.size() * 8);
   const size_t o_om = off; off = align256(off + omtab.size() * 8);
   const size_t o_rw = off; off = align256(off + rwtab.size() * 8);
   const size_t o_nq = off; off = align256(off + nqtab.size() * 16);
@@ -474,7 +519,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->dbytes = off;
   unsigned char* base = static_cast<unsigned char*>(c->dmem);
   struct Cp { size_t o; const void* src; size_t n; } cps[] = {
-      {o_v, vtab.data(), vtab.size() * 8}, {o_om, omtab.data(), omtab.size() * 8},
+      {o_v, vtab.data(), vtab.size() * 8}, {o_edge, edgetab.data(), edgetab.size() * 8},
+      {o_om, omtab.data(), omtab.size() * 8},
       {o_rw, rwtab.data(), rwtab.size() * 8}, {o_nq, nqtab.data(), nqtab.size() * 16},
       {o_icdf, icdf.data(), icdf.size()}, {o_m0, m0.data(), m0.size() * 8},
       {o_zmom, zmom.data(), zmom.size() * 8},
@@ -526,6 +572,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.qfac = c->qfac;
 
   P.vtab = reinterpret_cast<const double*>(base + o_v);
+  P.stretched = stretched ? 1 : 0;
+  P.edgetab = reinterpret_cast<const double*>(base + o_edge);
   P.omtab = reinterpret_cast<const double*>(base + o_om);
   P.rwtab = reinterpret_cast<const double*>(base + o_rw);
   P.nqtab = reinterpret_cast<const float4*>(base + o_nq);

@@ -20,10 +20,12 @@ struct TablesLDS {
   float4* nq;     // {omega, p_phi, p_unif, 0}, FP32
   double* rw;     // 1 / omega, FP64
   uint8_t* icdf;  // [3 * kFieldSize] Maxwellian inverse CDF on 12-bit fields
+  double* edge;   // [ns + 3] cell edges per axis (n + 1 each), for the search
+                  // of post-collision cells on stretched grids
 
   static __host__ __device__ size_t bytes(int ns, bool sampler) {
     size_t b = 24 * (size_t)ns + 16 * sizeof(double);
-    if (sampler) b += 24 * (size_t)ns + 3 * (size_t)kFieldSize;
+    if (sampler) b += 32 * (size_t)ns + 24 + 3 * (size_t)kFieldSize;
     return b;
   }
 };
@@ -37,7 +39,8 @@ __device__ __forceinline__ void load_tables(const Params& P, unsigned char* base
   T.m0 = T.xt + ns;
   T.nq = reinterpret_cast<float4*>(T.m0 + 16);
   T.rw = reinterpret_cast<double*>(T.nq + ns);
-  T.icdf = reinterpret_cast<uint8_t*>(T.rw + ns);
+  T.edge = T.rw + ns;
+  T.icdf = reinterpret_cast<uint8_t*>(T.edge + ns + 3);
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
     const int k = i < n0 ? 0 : (i < n0 + n1 ? 1 : 2);
     const int o = k * kMaxAxis + i - (k == 0 ? 0 : (k == 1 ? n0 : n0 + n1));
@@ -46,6 +49,14 @@ __device__ __forceinline__ void load_tables(const Params& P, unsigned char* base
     if (sampler) {
       T.nq[i] = P.nqtab[o];
       T.rw[i] = P.rwtab[o];
+    }
+  }
+  if (sampler) {
+    // n + 1 edges per axis, axis k at offset n0 + ... + n_{k-1} + k
+    for (int i = threadIdx.x; i < ns + 3; i += blockDim.x) {
+      const int k = i < n0 + 1 ? 0 : (i < n0 + n1 + 2 ? 1 : 2);
+      const int o = i - (k == 0 ? 0 : (k == 1 ? n0 + 1 : n0 + n1 + 2));
+      T.edge[i] = P.edgetab[k * (kMaxAxis + 1) + o];
     }
   }
   if (threadIdx.x < 15) T.m0[threadIdx.x] = P.m0[threadIdx.x];
@@ -75,6 +86,21 @@ __device__ __forceinline__ NodeWeight node_weight(const TablesLDS& T, float beta
   o.r = w * s;
   o.s = s;
   return o;
+}
+
+// Cell of x among n stretched cells with edges e[0] = -a < ... < e[n] = a:
+// the largest i with e[i] <= x (an x on an edge belongs to the upper cell),
+// -1 outside [e[0], e[n]).  Binary search, the same number of steps in
+// every lane.
+__device__ __forceinline__ int edge_search(const double* e, int n, double x) {
+  int lo = 0, hi = n;  // e[lo] <= x < e[hi] while inside
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    const bool up = x >= e[mid];
+    lo = up ? mid : lo;
+    hi = up ? hi : mid;
+  }
+  return (x >= e[0] && x < e[n]) ? lo : -1;
 }
 
 // One Monte Carlo collision sample.  The four coefficients are the weight q
@@ -135,15 +161,34 @@ __device__ __forceinline__ Pair sample_pair(const Params& P, const TablesLDS& T,
   const double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
   const double alpha = (vrx * kx + vry * ky) + vrz * kz;
   const double ddx = alpha * kx, ddy = alpha * ky, ddz = alpha * kz;
-  const double tsx = floor((vax + ddx + P.a[0]) * P.inv_cell[0]);
-  const double tsy = floor((vay + ddy + P.a[1]) * P.inv_cell[1]);
-  const double tsz = floor((vaz + ddz + P.a[2]) * P.inv_cell[2]);
-  const double ttx = floor((vbx - ddx + P.a[0]) * P.inv_cell[0]);
-  const double tty = floor((vby - ddy + P.a[1]) * P.inv_cell[1]);
-  const double ttz = floor((vbz - ddz + P.a[2]) * P.inv_cell[2]);
-  // inside the box iff 0 <= floor < n per component (the integer conversion
-  // saturates, so far-out values fail the unsigned test as well)
-  const int sx = (int)tsx, sy = (int)tsy, sz = (int)tsz, tx = (int)ttx, ty = (int)tty, tz = (int)ttz;
+  int sx, sy, sz, tx, ty, tz;
+  if (P.stretched) {
+    // stretched cells (Sec. 5.1): binary search over the edges
+    const double* ex = T.edge;
+    const double* ey = T.edge + n0 + 1;
+    const double* ez = T.edge + n0 + n1 + 2;
+    sx = edge_search(ex, n0, vax + ddx);
+    sy = edge_search(ey, n1, vay + ddy);
+    sz = edge_search(ez, n2, vaz + ddz);
+    tx = edge_search(ex, n0, vbx - ddx);
+    ty = edge_search(ey, n1, vby - ddy);
+    tz = edge_search(ez, n2, vbz - ddz);
+  } else {
+    const double tsx = floor((vax + ddx + P.a[0]) * P.inv_cell[0]);
+    const double tsy = floor((vay + ddy + P.a[1]) * P.inv_cell[1]);
+    const double tsz = floor((vaz + ddz + P.a[2]) * P.inv_cell[2]);
+    const double ttx = floor((vbx - ddx + P.a[0]) * P.inv_cell[0]);
+    const double tty = floor((vby - ddy + P.a[1]) * P.inv_cell[1]);
+    const double ttz = floor((vbz - ddz + P.a[2]) * P.inv_cell[2]);
+    // inside the box iff 0 <= floor < n per component (the integer
+    // conversion saturates, so far-out values fail the unsigned test as well)
+    sx = (int)tsx;
+    sy = (int)tsy;
+    sz = (int)tsz;
+    tx = (int)ttx;
+    ty = (int)tty;
+    tz = (int)ttz;
+  }
   const bool kept = ((unsigned)sx < (unsigned)n0) & ((unsigned)sy < (unsigned)n1) & ((unsigned)sz < (unsigned)n2) &
                     ((unsigned)tx < (unsigned)n0) & ((unsigned)ty < (unsigned)n1) & ((unsigned)tz < (unsigned)n2);
   Pair p;

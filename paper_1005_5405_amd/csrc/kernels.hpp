@@ -63,6 +63,9 @@ struct Params {
   // 64-bit range (zero between uses)
   int hyb_lo, hyb_n;
   float* hyb_ovf;
+  // stretched velocity cells (Sec. 5.1): post-collision cells by search
+  int stretched;
+  const double* edgetab;  // [3][kMaxAxis + 1] cell edges -a .. a per axis
 };
 
 // One problem of a batch: its constants and tables, the offset of its state

@@ -402,3 +402,53 @@ def test_shared_sample_step_parity(lib, oracle_mod, torch_mod, case):
         torch_mod.cuda.synchronize()
         assert torch_mod.equal(h2, hout), step
     assert g.read_status() == 0
+
+
+# Stretched velocity cells (Sec. 5.1, the paper's own discretisation: 20^3 on
+# [-3, 3] in the ratio 0.945; 18^3 in 0.970): node tables, samples (the
+# post-collision cells found by a binary search over the edges on the GPU, by
+# counting edges in the oracle), collision and whole steps.
+@pytest.mark.parametrize("nv,rv,G", [(20, 0.945, 1), (20, 0.945, 0), (18, 0.97, 0), ((20, 18, 20), 0.945, 1)])
+def test_stretched_grid_parity(lib, oracle_mod, torch_mod, nv, rv, G):
+    from paper_1005_5405_amd import inputs
+
+    kw = dict(nx=7, ny=6, nv=nv, vmax=3.0, delta=1.0, eps=0.05, n_pairs=6144, sample_group=G, rv=rv)
+    _say("stretched", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    for k in range(3):
+        np.testing.assert_array_equal(g.axis_thresholds(k), o.thresholds[k])
+    assert g.dt == o.dt and g.K == o.K and g.W == o.W and g.qfac == o.qfac
+    for cell, step in [(0, 0), (37, 12345)]:
+        gi, gq, gw = g.debug_pairs(cell, step, 0, 6144, words=True)
+        oi, oq, ow = o.debug_pairs(cell, step, 0, 6144, words=True)
+        np.testing.assert_array_equal(gw, ow)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_allclose(gq, oq, rtol=2e-6, atol=1e-12 * oq.max())
+    h = inputs.random_field(o.shape, seed=21, scale=0.3).astype(np.float32).astype(np.float64)
+    walls_o, walls_g = oracle_mod.Walls(**WALLS), lib.Walls(**WALLS)
+    # stream, collide, step against the oracle
+    ref_s = o.stream(h, walls_o)
+    hs = g.empty()
+    g.stream(_dev(torch_mod, h), hs, walls_g)
+    ref_c = o.collide(_host(hs), 3)
+    hc = g.empty()
+    g.collide(hs, hc, 3)
+    ref = o.step(h, walls_o, 3)
+    hout = g.empty()
+    g.step(_dev(torch_mod, h), hout, walls_g, 3)
+    torch_mod.cuda.synchronize()
+    for got, r in ((_host(hs), ref_s), (_host(hc), ref_c), (_host(hout), ref)):
+        rel, wrel = _errs(o, got, r)
+        assert rel <= 1e-5 and wrel <= 1e-5, (rel, wrel)
+    # 20 steps from rest of the driven cavity with the paper's lid velocity
+    href = np.zeros(o.shape)
+    a, b = g.empty(0.0), g.empty()
+    wo, wg = oracle_mod.Walls(lid_u=0.01), lib.Walls(lid_u=0.01)
+    for n in range(20):
+        href = o.step(href, wo, n)
+        g.step(a, b, wg, n)
+        a, b = b, a
+    torch_mod.cuda.synchronize()
+    rel, wrel = _errs(o, _host(a), href)
+    assert rel <= 1e-4 and wrel <= 1e-4, (rel, wrel)
+    assert g.read_status() == 0

@@ -48,15 +48,17 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
            dict(n_pairs=2**31), dict(dt=1.0), dict(vmax=(0.0, 1.0, 1.0)), dict(sample_group=-1),
            dict(mix16=17), dict(flags=4),
            # the 12-bit Maxwellian law alone cannot draw the outer nodes of 8 cells on [-4, 4]
-           dict(mix16=0, vmax=(4.0, 4.0, 4.0)), dict(mix16=0, nv=(20, 20, 20), vmax=(5.0, 5.0, 5.0))]
+           dict(mix16=0, vmax=(4.0, 4.0, 4.0)), dict(mix16=0, nv=(20, 20, 20), vmax=(5.0, 5.0, 5.0)),
+           # stretched velocity cells need 0 < rv < 1 and even counts
+           dict(rv=1.5), dict(rv=-0.2), dict(rv=0.9, nv=(8, 7, 8))]
     base = dict(nx=8, ny=8, nv=(8, 8, 8), vmax=(3.0, 3.0, 3.0), delta=1.0, eps=0.1, cfl=0.5, dt=0.0, order=2,
-                bc=0, n_pairs=100, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4)
+                bc=0, n_pairs=100, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0)
     for over in bad:
         kw = dict(base, **over)
         p = binding._Problem(kw["nx"], kw["ny"], (ctypes.c_int32 * 3)(*kw["nv"]),
                              (ctypes.c_double * 3)(*kw["vmax"]), kw["delta"], kw["eps"], kw["cfl"], kw["dt"],
                              kw["order"], kw["bc"], kw["n_pairs"], kw["sample_group"], kw["seed"],
-                             kw["cavity_id"], kw["flags"], kw["mix16"])
+                             kw["cavity_id"], kw["flags"], kw["mix16"], kw["rv"])
         rc = L.boltz_create(ctypes.byref(p), ctypes.byref(ctx))
         assert rc == binding.EINVAL, (over, rc)
         if over.get("mix16") == 0:
