@@ -113,7 +113,24 @@ typedef struct boltz_info {
   double W;              /* discrete mass of Phi0 on the velocity grid       */
   double qfac;           /* dt K / N_t                                       */
   int64_t device_bytes;  /* device memory held by the context                */
+  int32_t collide_layout;   /* LDS layout of the collision (BOLTZ_LAYOUT_*) */
+  int32_t collide_block;    /* its threads per workgroup (shared samples)   */
+  int32_t collide_lds_nodes; /* nodes of the h tile held in LDS             */
+  int32_t reserved;
 } boltz_info;
+
+/* LDS layouts of the collision kernel (boltz_info.collide_layout): where the
+ * per-cell increments of Eq. monteCarloInt are accumulated.
+ *   FIXED   64-bit fixed point for every node next to the full h tile
+ *   SPLIT   the same for one half of the nodes per pass over the pairs
+ *   CAS     FP32 compare-and-swap
+ *   HYBRID  64-bit fixed point for the central x-slabs, FP32 for the rest
+ *   PART    64-bit fixed point for every node, the h tile of the central
+ *           x-slabs in LDS and the outer slabs read from global memory
+ * The environment variable BOLTZ_COLLIDE_LAYOUT=hybrid, read by
+ * boltz_create, selects HYBRID over PART where both fit. */
+enum { BOLTZ_LAYOUT_CAS = 0, BOLTZ_LAYOUT_FIXED = 1, BOLTZ_LAYOUT_SPLIT = 2, BOLTZ_LAYOUT_HYBRID = 3,
+       BOLTZ_LAYOUT_PART = 4 };
 
 typedef struct boltz_ctx boltz_ctx;
 

@@ -52,7 +52,13 @@ class _BatchInfo(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("ncells", ctypes.c_int64), ("nv", ctypes.c_int64), ("dt", ctypes.c_double),
                 ("K", ctypes.c_double), ("W", ctypes.c_double), ("qfac", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("collide_layout", ctypes.c_int32),
+                ("collide_block", ctypes.c_int32), ("collide_lds_nodes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+# LDS layouts of the collision kernel (boltz_info.collide_layout)
+LAYOUTS = {0: "cas", 1: "fixed", 2: "split", 3: "hybrid", 4: "part"}
 
 
 EXPORTS = ("boltz_create", "boltz_destroy", "boltz_query", "boltz_last_error", "boltz_stream",
@@ -202,6 +208,9 @@ class Boltz:
         self.shape = (self.ny, self.nx, self.nv)
         self.dt, self.K, self.W, self.qfac = info.dt, info.K, info.W, info.qfac
         self.device_bytes = int(info.device_bytes)
+        self.collide_layout = LAYOUTS.get(int(info.collide_layout), str(info.collide_layout))
+        self.collide_block = int(info.collide_block)
+        self.collide_lds_nodes = int(info.collide_lds_nodes)
         self.n_pairs, self.order, self.bc, self.eps = int(n_pairs), int(order), int(bc), float(eps)
         self.mix16 = int(mix16)
 

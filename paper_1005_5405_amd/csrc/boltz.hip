@@ -45,8 +45,8 @@ struct boltz_ctx {
   // grid of the fused-sampler [0] and shared-table [1] variants
   int collide_block[2] = {256, 256};
   int collide_mode = ACC_FIXED;  // accumulation of the increments (ACC_*)
-  int batch_mode = ACC_FIXED;    // ... in batches (no ACC_HYBRID there)
-  int hyb_lo[2] = {0, 0}, hyb_n[2] = {0, 0};  // ACC_HYBRID inner nodes per variant
+  int batch_mode = ACC_FIXED;    // ... in batches (no ACC_HYBRID or ACC_PART there)
+  int hyb_lo[2] = {0, 0}, hyb_n[2] = {0, 0};  // ACC_HYBRID / ACC_PART inner nodes per variant
   size_t collide_lds[2] = {0, 0};
   int64_t collide_grid[2] = {0, 0};
   int64_t ngroups = 0;          // sample groups (shared-sample mode)
@@ -158,6 +158,22 @@ bool pick_hybrid(const int (&n)[3], int ns, bool sampler, int& lo, int& nin) {
   return false;
 }
 
+// ACC_PART for grids whose 64-bit layout does not fit: the most x-slabs
+// (centred; at least half of them) whose FP32 h^s tile fits after the
+// 64-bit accumulators of every node and the tables, with 1024 threads.
+bool pick_part(const int (&n)[3], int ns, bool sampler, int& lo, int& nin) {
+  const int slab = n[1] * n[2], nv = n[0] * slab;
+  for (int S = n[0]; S >= (n[0] + 1) / 2 && S >= 1; --S) {
+    const int nn = S * slab;
+    if (CollideLDS::part_bytes(nv, nn, ns, sampler) + collide_static_lds(1024) <= kLdsBytes) {
+      lo = ((n[0] - S) / 2) * slab;
+      nin = nn;
+      return true;
+    }
+  }
+  return false;
+}
+
 // Accumulation mode and block sizes of the collide kernel: 64-bit
 // fixed-point accumulators for every node when they fit next to the h tile
 // and tables, else for half of the nodes per pass, else FP32; the block size
@@ -226,6 +242,7 @@ const void* collide_fn(int block, bool table, int mode) {
   BOLTZ_COLLIDE_FN(512, ACC_CAS)
   BOLTZ_COLLIDE_FN(1024, ACC_CAS)
   BOLTZ_COLLIDE_FN(1024, ACC_HYBRID)
+  BOLTZ_COLLIDE_FN(1024, ACC_PART)
 #undef BOLTZ_COLLIDE_FN
   return nullptr;
 }
@@ -277,13 +294,20 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     return fail(nullptr, BOLTZ_EUNSUPPORTED,
                 "boltz_create: the per-cell h and increment tiles of this velocity grid exceed the 160 KB LDS");
   // a single problem whose grid is too large for the 64-bit layout collides
-  // in one pass with ACC_HYBRID; batches keep the classic layouts
+  // in one pass with ACC_PART, else ACC_HYBRID; batches keep the classic
+  // layouts
   const int bmode = cmode;
   int hlo[2] = {0, 0}, hn[2] = {0, 0};
-  if (cmode != ACC_FIXED && nvt <= 65535 &&
-      pick_hybrid(p->nv, nsum, true, hlo[0], hn[0]) && pick_hybrid(p->nv, nsum, false, hlo[1], hn[1])) {
-    cmode = ACC_HYBRID;
-    cblock[0] = cblock[1] = 1024;
+  if (cmode != ACC_FIXED && nvt <= 65535) {
+    const char* lay = std::getenv("BOLTZ_COLLIDE_LAYOUT");
+    const bool no_part = lay && std::strcmp(lay, "hybrid") == 0;
+    if (!no_part && pick_part(p->nv, nsum, true, hlo[0], hn[0]) && pick_part(p->nv, nsum, false, hlo[1], hn[1])) {
+      cmode = ACC_PART;
+      cblock[0] = cblock[1] = 1024;
+    } else if (pick_hybrid(p->nv, nsum, true, hlo[0], hn[0]) && pick_hybrid(p->nv, nsum, false, hlo[1], hn[1])) {
+      cmode = ACC_HYBRID;
+      cblock[0] = cblock[1] = 1024;
+    }
   }
   if ((int64_t)p->nx * p->ny * nvt >= ((int64_t)1 << 40))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: phase-space grid too large");
@@ -501,8 +525,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (ncu < 1) ncu = 256;
   }
-  // ACC_HYBRID: one global row per persistent workgroup (at most one per CU)
-  const int64_t hyb_rows = (cmode == ACC_HYBRID) ? 2 * (int64_t)ncu : 0;
+  // ACC_HYBRID, ACC_PART: one global row per persistent workgroup (at most two per CU)
+  const int64_t hyb_rows = (cmode == ACC_HYBRID || cmode == ACC_PART) ? 2 * (int64_t)ncu : 0;
   const size_t o_hyb = off; off = align256(off + (size_t)hyb_rows * (size_t)nvt * 4);
   const size_t o_sidx = off; off = align256(off + nsort * sizeof(uint2));
   const size_t o_scoef = off; off = align256(off + nsort * sizeof(float4));
@@ -620,6 +644,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
     const void* fn = collide_fn(cblock[t], t == 1, cmode);
     c->collide_lds[t] = cmode == ACC_HYBRID ? CollideLDS::hyb_bytes(c->nv, hn[t], nsum, t == 0)
+                        : cmode == ACC_PART ? CollideLDS::part_bytes(c->nv, hn[t], nsum, t == 0)
                                             : CollideLDS::bytes(c->nv, nsum, cmode, t == 0);
     // the attribute is per kernel, shared by every context: the largest
     // dynamic size the block size allows
@@ -630,7 +655,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cblock[t], c->collide_lds[t]);
     if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
     int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
-    if (cmode == ACC_HYBRID) cap = std::min<int64_t>(cap, hyb_rows);
+    if (hyb_rows) cap = std::min<int64_t>(cap, hyb_rows);
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
   }
   c->adj_supported = ea == hipSuccess && pick_adjoint(c->nv, nsum, c->adj_block, c->adj_fixed);
@@ -671,6 +696,11 @@ int boltz_query(const boltz_ctx* c, boltz_info* out) {
   out->W = c->W;
   out->qfac = c->qfac;
   out->device_bytes = (int64_t)c->dbytes;
+  out->collide_layout = c->collide_mode;
+  out->collide_block = c->collide_block[1];
+  out->collide_lds_nodes = (c->collide_mode == ACC_HYBRID || c->collide_mode == ACC_PART) ? c->hyb_n[1]
+                           : (c->collide_mode == ACC_SPLIT ? (int)((c->nv + 1) / 2) : (int)c->nv);
+  out->reserved = 0;
   return BOLTZ_OK;
 }
 
@@ -816,6 +846,9 @@ static void launch_collide_b(boltz_ctx* c, bool table, const float* hs, float* h
   switch (c->collide_mode) {
     case ACC_HYBRID:
       if (B == 1024) launch_collide_m<1024, ACC_HYBRID>(c, table, hs, hout, s32, flags, defect, st, R);
+      break;
+    case ACC_PART:
+      if (B == 1024) launch_collide_m<1024, ACC_PART>(c, table, hs, hout, s32, flags, defect, st, R);
       break;
     case ACC_FIXED: launch_collide_m<B, ACC_FIXED>(c, table, hs, hout, s32, flags, defect, st, R); break;
     case ACC_SPLIT: launch_collide_m<B, ACC_SPLIT>(c, table, hs, hout, s32, flags, defect, st, R); break;

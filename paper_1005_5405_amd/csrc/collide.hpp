@@ -519,7 +519,13 @@ __device__ __forceinline__ bool solve5(const double* S, const double* r, double*
 //              float atomic) for the outer slabs (rarely reached), next to
 //              the full h^s tile; h^c is not stored but formed again from
 //              h^s and the accumulators where it is read
-enum : int { ACC_CAS = 0, ACC_FIXED = 1, ACC_SPLIT = 2, ACC_HYBRID = 3 };
+//   ACC_PART   one pass with 64-bit fixed point for every node (grids too
+//              large for ACC_FIXED): the h^s tile of the central x-slabs
+//              sits in LDS after the accumulators, the outer slabs' h^s is
+//              read from the cell's row in global memory (gathers of the
+//              few samples that reach them, rows in the node phases); h^c
+//              is formed again where it is read (12 B/node or less)
+enum : int { ACC_CAS = 0, ACC_FIXED = 1, ACC_SPLIT = 2, ACC_HYBRID = 3, ACC_PART = 4 };
 
 // Dynamic LDS of the collide kernel: the h^s tile (FP32), the accumulators,
 // then the tables.  The region after the tile holds h^c after the pair pass
@@ -543,6 +549,12 @@ struct CollideLDS {
   }
   static __host__ __device__ size_t hyb_bytes(int nv, int nin, int ns, bool sampler) {
     return tile(nv) + hyb_acc(nv, nin) + TablesLDS::bytes(ns, sampler);
+  }
+  // ACC_PART with nin nodes in the LDS tile: 64-bit accumulators of every
+  // node, the tile, the tables
+  static __host__ __device__ size_t part64(int nv) { return ((size_t)nv * 8 + 15) & ~(size_t)15; }
+  static __host__ __device__ size_t part_bytes(int nv, int nin, int ns, bool sampler) {
+    return part64(nv) + tile(nin) + TablesLDS::bytes(ns, sampler);
   }
 };
 
@@ -602,14 +614,69 @@ __device__ __forceinline__ void scatter_hybrid(const Hyb& H, int a, int b, int a
   }
 }
 
+// ACC_PART state of one cell: accumulators acc[node]; h^s of nodes lo ..
+// lo + n - 1 in tile[node - lo] (LDS), of the others in hg[node] (the
+// cell's row in global memory); ovf, flag: the workgroup's global row for
+// terms beyond the 64-bit range, as in ACC_HYBRID.
+struct Part {
+  unsigned long long* acc;
+  float* tile;
+  const float* hg;
+  int lo;
+  unsigned n;
+  float* ovf;
+  unsigned* flag;
+  __device__ __forceinline__ bool inner(int j) const { return (unsigned)(j - lo) < n; }
+};
+
+// A term outside the fast window: the exact 64-bit conversion, or beyond its
+// range (or non-finite) the workgroup's global row.
+__device__ __forceinline__ void part_wide(const Part& Q, int j, double k, double g) {
+  const double x = k * g;
+  unsigned long long v;
+  if (fixed_exact(x, v)) {
+    __hip_atomic_fetch_add(&Q.acc[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    atomicAdd(&Q.ovf[j], (float)x);
+    *Q.flag = 1u;
+  }
+}
+
+// The four terms of a sample, 64-bit adds at every target; the wide terms
+// (far tails) after a wavefront test.
+__device__ __forceinline__ void scatter_part(const Part& Q, int a, int b, int as, int bs, double kas, double kbs,
+                                             double ka, double kb, float g) {
+  const double gd = (double)g;
+  const long long d0 = fixed_of(kas, gd), d1 = fixed_of(kbs, gd), d2 = fixed_of(-ka, gd), d3 = fixed_of(-kb, gd);
+  const bool f0 = in_fixed_window(d0), f1 = in_fixed_window(d1), f2 = in_fixed_window(d2), f3 = in_fixed_window(d3);
+  if (__all(f0 & f1 & f2 & f3)) {
+    __hip_atomic_fetch_add(&Q.acc[as], (unsigned long long)d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&Q.acc[bs], (unsigned long long)d1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&Q.acc[a], (unsigned long long)d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&Q.acc[b], (unsigned long long)d3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    if (f0) __hip_atomic_fetch_add(&Q.acc[as], (unsigned long long)d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else part_wide(Q, as, kas, gd);
+    if (f1) __hip_atomic_fetch_add(&Q.acc[bs], (unsigned long long)d1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else part_wide(Q, bs, kbs, gd);
+    if (f2) __hip_atomic_fetch_add(&Q.acc[a], (unsigned long long)d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else part_wide(Q, a, -ka, gd);
+    if (f3) __hip_atomic_fetch_add(&Q.acc[b], (unsigned long long)d3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else part_wide(Q, b, -kb, gd);
+  }
+}
+
 // nodes per thread of one ACC_SPLIT half kept in registers between passes
 template <int BLOCK>
 constexpr int split_regs() { return 8192 / BLOCK; }
 
-// float4 registers per thread holding the next cell's h^s tile: 4, or 2
-// with 1024 threads (enough for 8192 nodes)
+// float4 registers per thread holding the next cell's h^s tile: 4, or with
+// 1024 threads 2 (enough for 8192 nodes), 4 for the full 24^3 tile of
+// ACC_HYBRID, 3 for the 20 inner slabs of ACC_PART at 24^3
 template <int BLOCK, int MODE = ACC_FIXED>
-constexpr int prefetch_regs() { return (BLOCK >= 1024 && MODE != ACC_HYBRID) ? 2 : 4; }
+constexpr int prefetch_regs() {
+  return BLOCK < 1024 ? 4 : (MODE == ACC_HYBRID ? 4 : (MODE == ACC_PART ? 3 : 2));
+}
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
@@ -760,6 +827,71 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
         const float g = (ha + hb) + (epsf * ha) * hb;
         if (MODE == ACC_HYBRID) scatter_hybrid(*H, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
         else scatter<MODE>(accf, acc64, lo, n, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+      }
+    }
+  }
+}
+
+// S3 + S4 in the ACC_PART layout: gain_loss with h^s of a sample's nodes
+// from the LDS tile, or for the outer slabs from the cell's row in global
+// memory (a load for the few lanes that need it, issued after every LDS
+// gather of the pass).
+template <int BLOCK, bool TABLE>
+__device__ __forceinline__ void gain_loss_part(const Params& P, const TablesLDS& T, const Part& Q, uint32_t group,
+                                               uint32_t step, const uint2* __restrict__ tidx,
+                                               const float4* __restrict__ tcoef) {
+  const int tid = threadIdx.x;
+  const float epsf = (float)P.eps;
+  const uint32_t nt = (uint32_t)P.n_pairs;
+  if (TABLE) {
+    constexpr int PU = 4;
+    const uint2* ri = tidx + (int64_t)group * nt;
+    const float4* rk = tcoef + (int64_t)group * nt;
+    auto pass = [&](uint32_t m, const bool masked) {
+      uint2 id[PU];
+      float4 kk[PU];
+      bool ok[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const uint32_t mu = m + u * BLOCK;
+        ok[u] = !masked || mu < nt;
+        id[u] = ok[u] ? ri[mu] : make_uint2(0u, 0u);
+        kk[u] = ok[u] ? rk[mu] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      float ha[PU], hb[PU];
+      bool ia[PU], ib[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int a = (int)(id[u].x & 0xFFFFu), b = (int)(id[u].x >> 16);
+        ia[u] = Q.inner(a);
+        ib[u] = Q.inner(b);
+        ha[u] = Q.tile[ia[u] ? a - Q.lo : 0];
+        hb[u] = Q.tile[ib[u] ? b - Q.lo : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        if (!ia[u]) ha[u] = Q.hg[id[u].x & 0xFFFFu];
+        if (!ib[u]) hb[u] = Q.hg[id[u].x >> 16];
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const float g = (ha[u] + hb[u]) + (epsf * ha[u]) * hb[u];
+        if (ok[u])
+          scatter_part(Q, (int)(id[u].x & 0xFFFFu), (int)(id[u].x >> 16), (int)(id[u].y & 0xFFFFu),
+                       (int)(id[u].y >> 16), kk[u].x, kk[u].y, kk[u].z, kk[u].w, g);
+      }
+    };
+    uint32_t m = tid;
+    for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) pass(m, false);
+    if (m < nt) pass(m, true);
+  } else {
+    for (uint32_t m = tid; m < nt; m += BLOCK) {
+      const Pair p = sample_pair(P, T, group, step, m, nullptr);
+      if (p.as >= 0) {
+        const float ha = Q.inner(p.a) ? Q.tile[p.a - Q.lo] : Q.hg[p.a];
+        const float hb = Q.inner(p.b) ? Q.tile[p.b - Q.lo] : Q.hg[p.b];
+        const float g = (ha + hb) + (epsf * ha) * hb;
+        scatter_part(Q, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
       }
     }
   }
@@ -1072,6 +1204,210 @@ __device__ __forceinline__ void collide_body_hybrid(const Params& P, const Table
   __syncthreads();
 }
 
+// ---------------------------------------------------- ACC_PART cells --
+// correction_sums with h^c formed from h^s (LDS tile or global row) and the
+// 64-bit accumulators (rows are whole x-slab members, so a row's h^s comes
+// from one place).
+template <int BLOCK>
+__device__ __forceinline__ void correction_sums_part(const TablesLDS& T, const double* zmom, const Part& Q,
+                                                     bool flagged, bool vec, int n0, int n1, int n2,
+                                                     double (&acc)[20]) {
+  const double* vx = T.v;
+  const double* vy = T.v + n0;
+  const double* omx = T.om;
+  const double* omy = T.om + n0;
+  const const_f64* zc = (const const_f64*)zmom;
+#pragma unroll
+  for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+  for (int row = threadIdx.x; row < n0 * n1; row += BLOCK) {
+    const int jx = row / n1, jy = row - (row / n1) * n1;
+    const int j0 = row * n2;
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
+    auto node = [&](int jz, float hsf, double dh) {
+      const const_f64* z = zc + 8 * jz;
+      const float hcf = (float)((double)hsf + dh);
+      const double hc = (double)hcf, d = hc - (double)hsf;
+      S0 = fma(z[0], hc, S0);
+      S1 = fma(z[1], hc, S1);
+      S2 = fma(z[2], hc, S2);
+      S3 = fma(z[3], hc, S3);
+      S4 = fma(z[4], hc, S4);
+      R0 = fma(z[0], d, R0);
+      R1 = fma(z[1], d, R1);
+      R2 = fma(z[2], d, R2);
+    };
+    const u64x2* q = reinterpret_cast<const u64x2*>(Q.acc + j0);
+    auto row4 = [&](const f32x4* hsr) {
+      for (int c = 0; c < (n2 >> 2); ++c) {
+        const f32x4 s4 = hsr[c];
+        const u64x2 qa = q[2 * c], qb = q[2 * c + 1];
+        node(4 * c, s4.x, from_fixed(qa.x));
+        node(4 * c + 1, s4.y, from_fixed(qa.y));
+        node(4 * c + 2, s4.z, from_fixed(qb.x));
+        node(4 * c + 3, s4.w, from_fixed(qb.y));
+      }
+    };
+    const bool in = Q.inner(j0);
+    if (vec && !flagged) {
+      if (in) row4(reinterpret_cast<const f32x4*>(Q.tile + (j0 - Q.lo)));
+      else row4(reinterpret_cast<const f32x4*>(Q.hg + j0));
+    } else {
+      for (int jz = 0; jz < n2; ++jz) {
+        const int j = j0 + jz;
+        double dh = from_fixed(Q.acc[j]);
+        if (flagged) dh += (double)Q.ovf[j];
+        node(jz, in ? Q.tile[j - Q.lo] : Q.hg[j], dh);
+      }
+    }
+    const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
+    const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
+    const double E0 = c2 * T0 + T2;
+    acc[0] += T0;
+    acc[1] += a * T0;
+    acc[2] += b * T0;
+    acc[3] += T1;
+    acc[4] += E0;
+    acc[5] += (a * a) * T0;
+    acc[6] += (a * b) * T0;
+    acc[7] += a * T1;
+    acc[8] += a * E0;
+    acc[9] += (b * b) * T0;
+    acc[10] += b * T1;
+    acc[11] += b * E0;
+    acc[12] += T2;
+    acc[13] += c2 * T1 + T3;
+    acc[14] += (c2 * c2) * T0 + 2.0 * c2 * T2 + T4;
+    const double Q0 = W * R0, Q1 = W * R1, Q2 = W * R2;
+    acc[15] += Q0;
+    acc[16] += a * Q0;
+    acc[17] += b * Q0;
+    acc[18] += Q1;
+    acc[19] += c2 * Q0 + Q2;
+  }
+}
+
+// One cell in the ACC_PART layout (inner h^s tile in LDS, Q.hg the cell's
+// row, accumulators cleared, a barrier passed): as collide_body_hybrid.
+// vec: rows of whole z quadruples and a 16-byte aligned global row.
+template <int BLOCK, bool TABLE, class Next>
+__device__ __forceinline__ void collide_body_part(const Params& P, const TablesLDS& T, const Part& Q, double* red,
+                                                  bool vec, uint32_t group, uint32_t step, uint32_t flags,
+                                                  float* dst, double* defect, const uint2* __restrict__ tidx,
+                                                  const float4* __restrict__ tcoef, Next&& next) {
+  const int tid = threadIdx.x;
+  const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const bool correct = !(flags & 1u);
+  const bool vec4 = vec && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
+  const double eps = P.eps;
+  gain_loss_part<BLOCK, TABLE>(P, T, Q, group, step, tidx, tcoef);
+  __syncthreads();
+  next();
+  const bool flagged = *Q.flag != 0u;
+  if (correct) {
+    double acc[20];
+    correction_sums_part<BLOCK>(T, P.zmom, Q, flagged, vec, n0, n1, n2, acc);
+    const int rows = n0 * n1;
+    const double t = block_sum20_w0<BLOCK>(acc, red, rows >= BLOCK ? BLOCK / 64 : (rows + 63) / 64);
+    const const_f64* m0c = (const const_f64*)P.m0;
+    if (tid < 64) {
+      double M[15], r[5], x[5];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) M[k] = m0c[k] + eps * lane_value(t, k);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) r[k] = -eps * lane_value(t, 15 + k);
+      if (!solve5(M, r, x)) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[k] = 0.0;
+        if (tid == 0) atomicOr(P.status, 1u);
+      }
+      for (int i = tid; i < n0 + n1 + n2; i += 64) {
+        const double v = T.v[i];
+        T.xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
+                         : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
+      }
+    }
+    __syncthreads();
+  }
+  // ---- h^{n+1} = h^c + F^c (x . psi) / eps, h^c formed again; the
+  // accumulators (and the global row) are left cleared for the next cell.
+  // Each thread reads a node's h^s before it writes that node's output, so
+  // h_s may be the output array.
+  bool finite = true;
+  auto out_of = [&](double hc, double xpsi) { return (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc); };
+  if (vec4 && !defect && !flagged) {
+    f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+    const f32x4* t4 = reinterpret_cast<const f32x4*>(Q.tile);
+    const f32x4* g4 = reinterpret_cast<const f32x4*>(Q.hg);
+    NodeWalk nw4(4 * tid, 4 * BLOCK, n1, n2);
+#pragma unroll 1
+    for (int i = tid; i < (nv >> 2); i += BLOCK, nw4.next()) {
+      const int j = 4 * i;
+      const f32x4 hv = Q.inner(j) ? t4[(j - Q.lo) >> 2] : g4[i];
+      u64x2* q = reinterpret_cast<u64x2*>(Q.acc + j);
+      const u64x2 qa = q[0], qb = q[1];
+      q[0] = u64x2{0ull, 0ull};
+      q[1] = u64x2{0ull, 0ull};
+      const float c0 = (float)((double)hv.x + from_fixed(qa.x)), c1 = (float)((double)hv.y + from_fixed(qa.y));
+      const float c2 = (float)((double)hv.z + from_fixed(qb.x)), c3 = (float)((double)hv.w + from_fixed(qb.y));
+      f32x4 o;
+      if (correct) {
+        const double xa = T.xt[nw4.jx] + T.xt[n0 + nw4.jy];
+        const double* xz = T.xt + n0 + n1 + nw4.jz;
+        o.x = out_of((double)c0, xa + xz[0]);
+        o.y = out_of((double)c1, xa + xz[1]);
+        o.z = out_of((double)c2, xa + xz[2]);
+        o.w = out_of((double)c3, xa + xz[3]);
+      } else {
+        o = f32x4{c0, c1, c2, c3};
+      }
+      finite = finite && isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w);
+      d4[i] = o;
+    }
+  } else {
+    const double* vx = T.v;
+    const double* vy = T.v + n0;
+    const double* vz = T.v + n0 + n1;
+    const double* omx = T.om;
+    const double* omy = T.om + n0;
+    const double* omz = T.om + n0 + n1;
+    double dsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    NodeWalk nw2(tid, BLOCK, n1, n2);
+#pragma unroll 1
+    for (int j = tid; j < nv; j += BLOCK, nw2.next()) {
+      const int jx = nw2.jx, jy = nw2.jy, jz = nw2.jz;
+      const float hsj = Q.inner(j) ? Q.tile[j - Q.lo] : Q.hg[j];
+      double dh = from_fixed(Q.acc[j]);
+      Q.acc[j] = 0ull;
+      if (flagged) {
+        dh += (double)Q.ovf[j];
+        Q.ovf[j] = 0.0f;
+      }
+      const double hc = (double)(float)((double)hsj + dh);
+      float out = (float)hc;
+      if (correct) out = out_of(hc, (T.xt[jx] + T.xt[n0 + jy]) + T.xt[n0 + n1 + jz]);
+      finite = finite && isfinite(out);
+      dst[j] = out;
+      if (defect) {
+        const double v1 = vx[jx], v2 = vy[jy], v3 = vz[jz];
+        const double vv = fma(v1, v1, fma(v2, v2, v3 * v3));
+        const double w = (omx[jx] * omy[jy]) * omz[jz];
+        const double diff = eps * ((double)out - (double)hsj) * w;
+        dsum[0] += diff;
+        dsum[1] += v1 * diff;
+        dsum[2] += v2 * diff;
+        dsum[3] += v3 * diff;
+        dsum[4] += vv * diff;
+      }
+    }
+    if (defect) {
+      block_sum<5>(dsum, red);
+      if (tid < 5) defect[tid] = dsum[tid];
+    }
+  }
+  if (!finite) atomicOr(P.status, 2u);
+  __syncthreads();
+}
+
 // One cell after its h^s tile is in LDS and the accumulators are cleared
 // (and a barrier passed): S3 + S4 pair pass, h^c, S5 correction, one
 // coalesced store of h^{n+1} to dst.  next() is called once the pair pass is
@@ -1343,6 +1679,54 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
                                         defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
                                           if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
                                         });
+    }
+    return;
+  }
+  if constexpr (MODE == ACC_PART) {
+    // accumulators of every node, the inner tile, tables; the next cell's
+    // inner tile waits in registers during the node phases
+    __shared__ unsigned pflag[2];
+    const int nin = P.hyb_n;
+    Part Q;
+    Q.acc = reinterpret_cast<unsigned long long*>(dsm);
+    Q.tile = reinterpret_cast<float*>(dsm + CollideLDS::part64(nv));
+    Q.lo = P.hyb_lo;
+    Q.n = (unsigned)nin;
+    Q.ovf = P.hyb_ovf + (int64_t)blockIdx.x * nv;
+    TablesLDS T;
+    load_tables(P, dsm + CollideLDS::part64(nv) + CollideLDS::tile(nin), !TABLE, T);
+    {
+      uint4* z = reinterpret_cast<uint4*>(dsm);
+      const int nz = (int)(CollideLDS::part64(nv) / 16);
+      for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (tid < 2) pflag[tid] = 0u;
+    }
+    // whole z quadruples (then lo and nin are multiples of 4 as well) and
+    // a 16-byte aligned input
+    const bool vec = ((P.n[2] & 3) == 0) && ((reinterpret_cast<uintptr_t>(hs_g) & 15) == 0);
+    const int nin4 = nin >> 2;
+    constexpr int NR = prefetch_regs<BLOCK, MODE>();
+    const bool pvec = vec && nin4 <= NR * BLOCK;
+    Prefetch<NR> pre;
+    int64_t cell = blockIdx.x;
+    if (pvec && cell < ncells) pre.load(hs_g + cell * nv + Q.lo, tid, BLOCK, nin4);
+    for (int k = 0; cell < ncells; cell += gridDim.x, ++k) {
+      if (pvec) {
+        pre.store(Q.tile, tid, BLOCK, nin4);
+      } else {
+        const float* src = hs_g + cell * nv + Q.lo;
+        for (int j = tid; j < nin; j += BLOCK) Q.tile[j] = src[j];
+      }
+      Q.hg = hs_g + cell * nv;
+      Q.flag = &pflag[k & 1];
+      if (tid == 0) pflag[(k + 1) & 1] = 0u;
+      __syncthreads();
+      const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
+      const int64_t next = cell + gridDim.x;
+      collide_body_part<BLOCK, TABLE>(P, T, Q, red, vec, group, step, flags, hout_g + cell * nv,
+                                      defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
+                                        if (pvec && next < ncells) pre.load(hs_g + next * nv + Q.lo, tid, BLOCK, nin4);
+                                      });
     }
     return;
   }

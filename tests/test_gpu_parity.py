@@ -136,6 +136,8 @@ COLLIDE_CASES = [
     dict(nx=2, ny=2, nv=(24, 24, 24), vmax=5.0, delta=100.0, eps=0.05, n_pairs=50000, mix16=4),
     dict(nx=3, ny=2, nv=(5, 7, 3), vmax=(3.0, 3.5, 2.0), delta=2.0, eps=0.3, n_pairs=3000),  # nv % 4 != 0
     dict(nx=2, ny=2, nv=(26, 26, 26), vmax=5.0, delta=1.0, eps=0.1, n_pairs=5000, mix16=16),  # largest LDS tile
+    # 22 of 25 x-slabs of h in LDS, the others gathered from global memory; nv_z % 4 != 0
+    dict(nx=3, ny=2, nv=(25, 24, 23), vmax=5.0, delta=50.0, eps=0.05, n_pairs=30000, mix16=4),
     dict(nx=4, ny=4, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=2000, sample_group=0),
     dict(nx=5, ny=3, nv=(20, 20, 20), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, sample_group=4, mix16=4),
     dict(nx=4, ny=4, nv=(12, 12, 12), vmax=4.5, delta=10.0, eps=0.1, n_pairs=0),
@@ -185,6 +187,34 @@ def test_collide_parity(lib, oracle_mod, torch_mod, case, correction):
         # conservation up to FP32 storage of h
         assert np.all(np.abs(d_dev) <= 1e-6 * scale)
     assert g.read_status() == 0
+
+
+@pytest.mark.parametrize("layout", ["part", "hybrid"])
+def test_collide_layouts_24cubed(lib, oracle_mod, torch_mod, layout, monkeypatch):
+    """The one-pass layouts of grids too large for 64-bit accumulators next
+    to the full tile (24^3): the partial-tile layout (chosen by default) and
+    the hybrid one (FP32 accumulators on the outer slabs), each against the
+    oracle, with shared samples over several cells per workgroup and with
+    per-cell samples."""
+    from paper_1005_5405_amd import inputs
+
+    if layout == "hybrid":
+        monkeypatch.setenv("BOLTZ_COLLIDE_LAYOUT", "hybrid")
+    for G in (0, 1):
+        kw = dict(nx=6, ny=5, nv=24, vmax=5.0, delta=100.0, eps=0.05, n_pairs=20000, mix16=4, bc=1,
+                  sample_group=G)
+        _say("layout", layout, kw)
+        g, o = _pair(lib, oracle_mod, **kw)
+        assert g.collide_layout == layout and g.collide_block == 1024
+        assert 24 * 24 * 12 <= g.collide_lds_nodes < 24**3
+        h = inputs.random_field(o.shape, seed=31 + G, scale=0.3).astype(np.float32).astype(np.float64)
+        ref = o.collide(h, 5)
+        hs, hout = _dev(torch_mod, h), g.empty()
+        g.collide(hs, hout, 5)
+        torch_mod.cuda.synchronize()
+        rel, wrel = _errs(o, _host(hout), ref)
+        assert rel <= 1e-5 and wrel <= 1e-5, (rel, wrel)
+        assert g.read_status() == 0
 
 
 def test_equilibrium_is_bitwise_fixed_point(lib, oracle_mod, torch_mod):
