@@ -687,11 +687,13 @@ struct Prefetch {
   // every lane loads (indices clamped into the tile) so the registers are
   // always defined and the loads stay in flight until the next tile store
   // (loads under a branch each wait for the previous one: the compiler
-  // cannot tell that the registers' earlier loads have retired)
+  // cannot tell that the registers' earlier loads have retired).  The
+  // loads, like the stores of h^{n+1}, are non-temporal: each tile is read
+  // once, and the shared pair records, read by every cell, stay in L2.
   __device__ __forceinline__ void load(const float* src, int i, int stride, int n) {
     const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
 #pragma unroll
-    for (int k = 0; k < NR; ++k) r[k] = s4[min(i + k * stride, n - 1)];
+    for (int k = 0; k < NR; ++k) r[k] = __builtin_nontemporal_load(&s4[min(i + k * stride, n - 1)]);
   }
   __device__ __forceinline__ void store(float* dst, int i, int stride, int n) const {
     f32x4* d4 = reinterpret_cast<f32x4*>(dst);
@@ -1160,7 +1162,7 @@ __device__ __forceinline__ void collide_body_hybrid(const Params& P, const Table
         o = f32x4{c0, c1, c2, c3};
       }
       finite = finite && isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w);
-      d4[i] = o;
+      __builtin_nontemporal_store(o, &d4[i]);
     }
   } else {
     const double* vx = T.v;
@@ -1361,7 +1363,7 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
         o = f32x4{c0, c1, c2, c3};
       }
       finite = finite && isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w);
-      d4[i] = o;
+      __builtin_nontemporal_store(o, &d4[i]);
     }
   } else {
     const double* vx = T.v;
@@ -1576,7 +1578,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
         o.z = out_of((double)c.z, xa + xz[2]);
         o.w = out_of((double)c.w, xa + xz[3]);
         finite = finite && isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w);
-        d4[i] = o;
+        __builtin_nontemporal_store(o, &d4[i]);
       }
     } else {
 #pragma unroll NU
@@ -1584,7 +1586,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
         const f32x4 c = a4[i];
         a4[i] = f32x4{0.f, 0.f, 0.f, 0.f};
         finite = finite && isfinite(c.x) && isfinite(c.y) && isfinite(c.z) && isfinite(c.w);
-        d4[i] = c;
+        __builtin_nontemporal_store(c, &d4[i]);
       }
     }
   } else {

@@ -93,6 +93,14 @@ __device__ __forceinline__ float bw_update(float h0, float h1, float h2, float C
   return h0 - C * (h0 - h1) - c2 * ((h0 - 2.0f * h1) + h2);
 }
 
+// A 16-byte store that does not keep its line in L2 (outputs read by the
+// next launch only): the halo rows and shared tables that are read again
+// stay cached.
+__device__ __forceinline__ void nt_store4(float* p, float4 v) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  __builtin_nontemporal_store(f4v{v.x, v.y, v.z, v.w}, reinterpret_cast<f4v*>(p));
+}
+
 // ------------------------------------------------ fixed-point LDS sums --
 // Increments of h are accumulated as signed 64-bit integers in units of
 // 2^-32 with the integer LDS atomic add, which on gfx950 runs an order of

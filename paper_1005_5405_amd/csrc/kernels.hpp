@@ -715,7 +715,7 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
       const float4 h0 = hx[r + 2];
       const float4 out = (sy == 0) ? h0
                          : (sy > 0 ? bw4(h0, hx[r + 1], hx[r], Cy, Cy2) : bw4(h0, hx[r + 3], hx[r + 4], Cy, Cy2));
-      *reinterpret_cast<float4*>(dst + cell_off(P, ix, iy)) = out;
+      nt_store4(dst + cell_off(P, ix, iy), out);
     }
   } else {
     float* dst = hout + jq;
@@ -732,7 +732,7 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
       out.y = h0.y + Cx * (hxn.y - h0.y) + Cy * (hyn.y - h0.y);
       out.z = h0.z + Cx * (hxn.z - h0.z) + Cy * (hyn.z - h0.z);
       out.w = h0.w + Cx * (hxn.w - h0.w) + Cy * (hyn.w - h0.w);
-      *reinterpret_cast<float4*>(dst + cell_off(P, ix, iy)) = out;
+      nt_store4(dst + cell_off(P, ix, iy), out);
     }
   }
 }
