@@ -837,12 +837,12 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 // S3 + S4 in the ACC_PART layout: gain_loss with h^s of a sample's nodes
 // from the LDS tile, or for the outer slabs from the cell's row in global
 // memory (a load for the few lanes that need it, issued after every LDS
-// gather of the pass).
+// gather of the pass).  BLOCK threads take part, tid = 0 .. BLOCK - 1 (a
+// multiple of 64, so shared record m stays with lane m mod 64).
 template <int BLOCK, bool TABLE>
 __device__ __forceinline__ void gain_loss_part(const Params& P, const TablesLDS& T, const Part& Q, uint32_t group,
                                                uint32_t step, const uint2* __restrict__ tidx,
-                                               const float4* __restrict__ tcoef) {
-  const int tid = threadIdx.x;
+                                               const float4* __restrict__ tcoef, int tid) {
   const float epsf = (float)P.eps;
   const uint32_t nt = (uint32_t)P.n_pairs;
   if (TABLE) {
@@ -914,6 +914,19 @@ __device__ __forceinline__ void gain_loss_part(const Params& P, const TablesLDS&
 // (h^c - h^s) psi_k, per thread.
 typedef __attribute__((address_space(4))) const double const_f64;
 
+// The factors omega_z v_z^p (p <= 4) of four consecutive z nodes, loaded
+// together before any is used: the sums then wait once per quadruple for
+// the scalar loads, not once per node.
+struct ZQuad {
+  double f[4][5];
+  __device__ __forceinline__ void load(const const_f64* zc, int jz) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int p = 0; p < 5; ++p) f[k][p] = zc[8 * (jz + k) + p];
+  }
+};
+
 template <int BLOCK>
 __device__ __forceinline__ void correction_sums(const TablesLDS& T, const double* zmom, const float* hs,
                                                 const float* hc_t, int n0, int n1, int n2, double (&acc)[20]) {
@@ -944,11 +957,22 @@ __device__ __forceinline__ void correction_sums(const TablesLDS& T, const double
       const f32x4* hcr = reinterpret_cast<const f32x4*>(hc_t + row * n2);
       const f32x4* hsr = reinterpret_cast<const f32x4*>(hs + row * n2);
       for (int q = 0; q < (n2 >> 2); ++q) {
+        ZQuad zq;
+        zq.load(zc, 4 * q);
         const f32x4 c4 = hcr[q], s4 = hsr[q];
-        node(4 * q, c4.x, s4.x);
-        node(4 * q + 1, c4.y, s4.y);
-        node(4 * q + 2, c4.z, s4.z);
-        node(4 * q + 3, c4.w, s4.w);
+        const float hcq[4] = {c4.x, c4.y, c4.z, c4.w}, hsq[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double hc = (double)hcq[k], d = hc - (double)hsq[k];
+          S0 = fma(zq.f[k][0], hc, S0);
+          S1 = fma(zq.f[k][1], hc, S1);
+          S2 = fma(zq.f[k][2], hc, S2);
+          S3 = fma(zq.f[k][3], hc, S3);
+          S4 = fma(zq.f[k][4], hc, S4);
+          R0 = fma(zq.f[k][0], d, R0);
+          R1 = fma(zq.f[k][1], d, R1);
+          R2 = fma(zq.f[k][2], d, R2);
+        }
       }
     } else {
       for (int jz = 0; jz < n2; ++jz) node(jz, hc_t[row * n2 + jz], hs[row * n2 + jz]);
@@ -1241,12 +1265,25 @@ __device__ __forceinline__ void correction_sums_part(const TablesLDS& T, const d
     const u64x2* q = reinterpret_cast<const u64x2*>(Q.acc + j0);
     auto row4 = [&](const f32x4* hsr) {
       for (int c = 0; c < (n2 >> 2); ++c) {
+        ZQuad zq;
+        zq.load(zc, 4 * c);
         const f32x4 s4 = hsr[c];
         const u64x2 qa = q[2 * c], qb = q[2 * c + 1];
-        node(4 * c, s4.x, from_fixed(qa.x));
-        node(4 * c + 1, s4.y, from_fixed(qa.y));
-        node(4 * c + 2, s4.z, from_fixed(qb.x));
-        node(4 * c + 3, s4.w, from_fixed(qb.y));
+        const float hsq[4] = {s4.x, s4.y, s4.z, s4.w};
+        const double dhq[4] = {from_fixed(qa.x), from_fixed(qa.y), from_fixed(qb.x), from_fixed(qb.y)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float hcf = (float)((double)hsq[k] + dhq[k]);
+          const double hc = (double)hcf, d = hc - (double)hsq[k];
+          S0 = fma(zq.f[k][0], hc, S0);
+          S1 = fma(zq.f[k][1], hc, S1);
+          S2 = fma(zq.f[k][2], hc, S2);
+          S3 = fma(zq.f[k][3], hc, S3);
+          S4 = fma(zq.f[k][4], hc, S4);
+          R0 = fma(zq.f[k][0], d, R0);
+          R1 = fma(zq.f[k][1], d, R1);
+          R2 = fma(zq.f[k][2], d, R2);
+        }
       }
     };
     const bool in = Q.inner(j0);
@@ -1301,7 +1338,7 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
   const bool correct = !(flags & 1u);
   const bool vec4 = vec && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
   const double eps = P.eps;
-  gain_loss_part<BLOCK, TABLE>(P, T, Q, group, step, tidx, tcoef);
+  gain_loss_part<BLOCK, TABLE>(P, T, Q, group, step, tidx, tcoef, tid);
   __syncthreads();
   next();
   const bool flagged = *Q.flag != 0u;

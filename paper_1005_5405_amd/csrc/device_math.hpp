@@ -325,16 +325,24 @@ __device__ __forceinline__ void fold_half(double* v, int lane) {
 // scratch of 20 * (BLOCK / 64) doubles.  v is consumed.  Ends without a
 // barrier after the reads of red: the caller synchronises before red is
 // written again.
+// The wavefront part: returns, in lane 32 b5 + 16 b4 + 8 b3 + 4 b2 + 2 b1
+// with k = 10 b5 + 5 b4 + 3 b3 + 2 b2 + b1 (b3 = 1 only with b2 = 0), the
+// wavefront's sum of value k (other lanes: partial sums or pads).  v is
+// consumed.
+__device__ __forceinline__ double wave_fold20(double (&v)[20], int lane) {
+  fold_half<20, 32, 0>(v, lane);
+  fold_half<10, 16, 0>(v, lane);
+  fold_half<5, 8, kDppMirror>(v, lane);
+  fold_half<3, 4, kDppHalfMirror>(v, lane);
+  fold_half<2, 2, kDppXor2>(v, lane);
+  return v[0] + dpp_f64<kDppXor1>(v[0]);
+}
+
 template <int BLOCK>
 __device__ __forceinline__ double block_sum20_w0(double (&v)[20], double* red, int nwd = BLOCK / 64) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = BLOCK / 64;
   if (wid < nwd) {
-    fold_half<20, 32, 0>(v, lane);
-    fold_half<10, 16, 0>(v, lane);
-    fold_half<5, 8, kDppMirror>(v, lane);
-    fold_half<3, 4, kDppHalfMirror>(v, lane);
-    fold_half<2, 2, kDppXor2>(v, lane);
-    const double s = v[0] + dpp_f64<kDppXor1>(v[0]);
+    const double s = wave_fold20(v, lane);
     const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1,
               b1 = (lane >> 1) & 1;
     // positions within the last group of five: b3 b2 b1 -> 0,1,2,pad,3,4,pad,pad

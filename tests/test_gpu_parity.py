@@ -194,14 +194,14 @@ def test_collide_layouts_24cubed(lib, oracle_mod, torch_mod, layout, monkeypatch
     """The one-pass layouts of grids too large for 64-bit accumulators next
     to the full tile (24^3): the partial-tile layout (chosen by default) and
     the hybrid one (FP32 accumulators on the outer slabs), each against the
-    oracle, with shared samples over several cells per workgroup and with
-    per-cell samples."""
+    oracle, with shared samples over several cells per workgroup (320 cells,
+    more than workgroups) and with per-cell samples."""
     from paper_1005_5405_amd import inputs
 
     if layout == "hybrid":
         monkeypatch.setenv("BOLTZ_COLLIDE_LAYOUT", "hybrid")
     for G in (0, 1):
-        kw = dict(nx=6, ny=5, nv=24, vmax=5.0, delta=100.0, eps=0.05, n_pairs=20000, mix16=4, bc=1,
+        kw = dict(nx=16, ny=20, nv=24, vmax=5.0, delta=100.0, eps=0.05, n_pairs=20000, mix16=4, bc=1,
                   sample_group=G)
         _say("layout", layout, kw)
         g, o = _pair(lib, oracle_mod, **kw)
