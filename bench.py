@@ -421,8 +421,15 @@ def run_batch(pkg, torch, count: int, steps: int, warmup: int):
     out = {"workload": "%d cavities, N in 32..128, 16^3/20^3/24^3 velocities, Kn log-uniform [0.01, 1], lid "
                        "U[0.05, 0.3], 5000..30000 pairs/cell, G = 0 (numpy default_rng(0))" % count,
            "cavities": count, "velocity_grids": classes, "nodes": b.nodes, "pair_cells": b.pair_cells,
-           "state_bytes": 4 * b.nodes, "create_s": t_create, "collide_block": b.collide_block,
-           "tune_ms_per_step": {str(k): v for k, v in tune_ms.items()},
+           "state_bytes": 4 * b.nodes, "create_s": t_create,
+           "tuned": {"ms_per_step_before": tune_ms["before"], "ms_per_step_after": tune_ms["after"],
+                     "stream_tile": list(b.stream_tile),
+                     "classes": [{"velocity_grid": list(c["nv"]), "problems": c["problems"], "cells": c["cells"],
+                                  "collide_block": c["collide_block"], "pairs_per_lane": c["pairs_per_lane"],
+                                  "workgroups": c["grid"], "cells_per_workgroup": c["cells_per_group"],
+                                  "collide_ms": c["ms"]} for c in b.classes()],
+                     "not_tuned": "the sample group G (part of each problem: it decides which samples a cell "
+                                  "uses)"},
            "eager": {"steps": steps, "ms_per_step": ms_eager, "value": b.nodes / (ms_eager * 1e-3),
                      "pairs_per_s": b.pair_cells / (ms_eager * 1e-3), "wall_s": wall_eager},
            "graph": {"steps": 2 * reps, "ms_per_step": ms_graph, "value": b.nodes / (ms_graph * 1e-3),

@@ -263,11 +263,33 @@ typedef struct boltz_batch boltz_batch;
 
 typedef struct boltz_batch_info {
   int32_t count;         /* problems                                         */
-  int32_t collide_block; /* threads per workgroup of the batched collision   */
+  int32_t collide_block; /* threads per workgroup of the collision of the
+                            class with the most pair-cells                   */
   int64_t nodes;         /* phase-space nodes of the whole batch             */
   int64_t pair_cells;    /* sum over problems of cells * n_pairs             */
   int64_t device_bytes;  /* device memory held by the batch                  */
+  int32_t classes;       /* classes (problems with one velocity grid)        */
+  int32_t stream_tile[2]; /* cells per stream workgroup in x and y           */
+  int32_t reserved;
 } boltz_batch_info;
+
+/* A class of a batch: its problems with one velocity grid.  Each class's
+ * cells are one collision launch per step with settings of their own. */
+typedef struct boltz_batch_class {
+  int32_t nv[3];          /* the class's velocity grid                       */
+  int32_t problems;       /* problems in it                                  */
+  int64_t cells;          /* their cells                                     */
+  int64_t pair_cells;     /* sum of cells * n_pairs                          */
+  int32_t collide_block;  /* threads per workgroup                           */
+  int32_t pairs_per_lane; /* shared pair records per thread in flight (2, 4) */
+  int32_t spread;         /* workgroups: 0 one per resident slot, 1 two per
+                             slot, 2 one per cell                            */
+  int32_t grid;           /* the resulting workgroups of the launch          */
+  int32_t cells_per_group; /* cells per workgroup, rounded up               */
+  int32_t reserved;
+  double ms;              /* ms per launch measured by boltz_batch_tune at
+                             these settings (0 before tuning)                */
+} boltz_batch_class;
 
 /* Create a batch of `count` (1..4096) problems on the current device; each
  * problem is validated as by boltz_create (its error message names it).
@@ -300,17 +322,32 @@ int boltz_batch_set_step(boltz_batch* batch, int64_t step, void* stream);
 int boltz_batch_step(boltz_batch* batch, const float* h_in, float* h_out, const boltz_walls* walls,
                      void* stream);
 
-/* Tuning: time `steps` steps (h_a <-> h_b, both overwritten; the step
- * counter advances) for every collision block size that fits the batch's
- * LDS (256, 512, 1024 threads), keep the fastest; ms_out (host, 3 values or
- * NULL) receives each size's milliseconds per step (untouched if it does
- * not fit).  Synchronises `stream`. */
+/* Tuning (h_a and h_b are working buffers, both overwritten; the step
+ * counter advances).  First the stream tile shape (16 x 8 or 32 x 4 cells),
+ * by `steps` whole steps each; then, for every class, every collision
+ * setting whose LDS fits (block size 256, 512, 1024 threads x 2 or 4 shared
+ * records per thread in flight x the three workgroup spreads), by `steps`
+ * launches of the class's collision alone; the fastest of each is kept.
+ * The sample group G is part of each problem (it decides which samples a
+ * cell uses) and is not tuned.  ms_out (host, 2 values or NULL): ms per
+ * whole step before and after.  Synchronises `stream`. */
 int boltz_batch_tune(boltz_batch* batch, float* h_a, float* h_b, const boltz_walls* walls, int steps,
                      void* stream, double* ms_out);
 
-/* Use a given collision block size (256, 512 or 1024; EINVAL if its LDS does
- * not fit). */
+/* Use a given collision block size (256, 512 or 1024) for every class whose
+ * layout allows it (the partial-tile layout of 24^3-class grids runs 1024
+ * threads only); EINVAL if no class can. */
 int boltz_batch_set_block(boltz_batch* batch, int block);
+
+/* Settings of class `index` (0 .. classes - 1; EINVAL beyond) into *out. */
+int boltz_batch_class_info(const boltz_batch* batch, int index, boltz_batch_class* out);
+
+/* Set one class's collision (block 256/512/1024 where its LDS fits,
+ * pairs_per_lane 2 or 4, spread 0..2; EINVAL otherwise). */
+int boltz_batch_set_class(boltz_batch* batch, int index, int block, int pairs_per_lane, int spread);
+
+/* Stream tile shape: (16, 8) or (32, 4) cells per workgroup; EINVAL else. */
+int boltz_batch_set_stream_tile(boltz_batch* batch, int tx, int ty);
 
 /* Test hook: the pairs the collision kernel draws for (cell, step) and pair
  * indices m0 .. m0+count-1, computed on the device by the kernel's own

@@ -46,7 +46,15 @@ class _Walls(ctypes.Structure):
 
 class _BatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("collide_block", ctypes.c_int32), ("nodes", ctypes.c_int64),
-                ("pair_cells", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("pair_cells", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("classes", ctypes.c_int32),
+                ("stream_tile", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32)]
+
+
+class _BatchClass(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int32 * 3), ("problems", ctypes.c_int32), ("cells", ctypes.c_int64),
+                ("pair_cells", ctypes.c_int64), ("collide_block", ctypes.c_int32),
+                ("pairs_per_lane", ctypes.c_int32), ("spread", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("cells_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -66,7 +74,8 @@ EXPORTS = ("boltz_create", "boltz_destroy", "boltz_query", "boltz_last_error", "
            "boltz_step_adjoint", "boltz_lid_shear_adjoint", "boltz_debug_pairs", "boltz_axis_thresholds",
            "boltz_read_status", "boltz_batch_create", "boltz_batch_destroy", "boltz_batch_query",
            "boltz_batch_last_error", "boltz_batch_offsets", "boltz_batch_problem", "boltz_batch_set_step",
-           "boltz_batch_step", "boltz_batch_tune", "boltz_batch_set_block", "boltz_collide_noalloc")
+           "boltz_batch_step", "boltz_batch_tune", "boltz_batch_set_block", "boltz_collide_noalloc",
+           "boltz_batch_class_info", "boltz_batch_set_class", "boltz_batch_set_stream_tile")
 
 _lib = None
 
@@ -115,6 +124,9 @@ def load_library(path: str = LIB_PATH):
     L.boltz_batch_step.argtypes = [P, V, V, W, V]
     L.boltz_batch_tune.argtypes = [P, V, V, W, ctypes.c_int, V, V]
     L.boltz_batch_set_block.argtypes = [P, ctypes.c_int]
+    L.boltz_batch_class_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(_BatchClass)]
+    L.boltz_batch_set_class.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.boltz_batch_set_stream_tile.argtypes = [P, ctypes.c_int, ctypes.c_int]
     for name in EXPORTS:
         if name not in ("boltz_last_error", "boltz_destroy", "boltz_batch_last_error", "boltz_batch_destroy",
                         "boltz_batch_problem"):
@@ -384,6 +396,7 @@ class Batch:
         _lib.boltz_batch_query(self._b, ctypes.byref(info))
         self.nodes, self.pair_cells = int(info.nodes), int(info.pair_cells)
         self.collide_block, self.device_bytes = int(info.collide_block), int(info.device_bytes)
+        self.nclasses, self.stream_tile = int(info.classes), (int(info.stream_tile[0]), int(info.stream_tile[1]))
 
     def close(self):
         if getattr(self, "_b", None) is not None and _lib is not None:
@@ -432,18 +445,41 @@ class Batch:
                                           _stream(stream)), "boltz_batch_step")
 
     def tune(self, h_a, h_b, walls=None, steps=2, stream=None):
-        """Time every collision block size that fits and keep the fastest;
-        returns {block: ms per step}.  Overwrites h_a, h_b and advances the
-        step counter."""
+        """Tune the stream tile shape, then each class's collision settings
+        (block size, records per lane, workgroup spread); returns
+        {"before": ms, "after": ms} per whole step.  Overwrites h_a, h_b and
+        advances the step counter."""
         import torch
 
-        ms = np.zeros(3)
+        ms = np.zeros(2)
         self._check(_lib.boltz_batch_tune(self._b, _ptr(h_a, self.nodes, torch.float32, "h_a"),
                                           _ptr(h_b, self.nodes, torch.float32, "h_b"), self._walls(walls),
                                           int(steps), _stream(stream), ms.ctypes.data), "boltz_batch_tune")
         self._refresh()
-        return {b: float(m) for b, m in zip((256, 512, 1024), ms) if m > 0}
+        return {"before": float(ms[0]), "after": float(ms[1])}
 
     def set_block(self, block):
         self._check(_lib.boltz_batch_set_block(self._b, int(block)), "boltz_batch_set_block")
+        self._refresh()
+
+    def classes(self):
+        """Settings of every class (problems with one velocity grid)."""
+        out = []
+        for k in range(self.nclasses):
+            c = _BatchClass()
+            self._check(_lib.boltz_batch_class_info(self._b, k, ctypes.byref(c)), "boltz_batch_class_info")
+            out.append({"nv": tuple(int(x) for x in c.nv), "problems": int(c.problems), "cells": int(c.cells),
+                        "pair_cells": int(c.pair_cells), "collide_block": int(c.collide_block),
+                        "pairs_per_lane": int(c.pairs_per_lane), "spread": int(c.spread), "grid": int(c.grid),
+                        "cells_per_group": int(c.cells_per_group), "ms": float(c.ms)})
+        return out
+
+    def set_class(self, index, block, pairs_per_lane=4, spread=0):
+        self._check(_lib.boltz_batch_set_class(self._b, int(index), int(block), int(pairs_per_lane), int(spread)),
+                    "boltz_batch_set_class")
+        self._refresh()
+
+    def set_stream_tile(self, tx, ty):
+        self._check(_lib.boltz_batch_set_stream_tile(self._b, int(tx), int(ty)), "boltz_batch_set_stream_tile")
+        self._refresh()
         self._refresh()

@@ -1201,10 +1201,36 @@ __global__ void advance_step_kernel(uint32_t* step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1u;
 }
 
-const void* collide_batch_fn(int block) {
-  if (block == 256) return (const void*)collide_batch_kernel<256>;
-  if (block == 512) return (const void*)collide_batch_kernel<512>;
-  return (const void*)collide_batch_kernel<1024>;
+const void* collide_batch_fn(int block, int pu) {
+  if (block == 256) return pu == 2 ? (const void*)collide_batch_kernel<256, 2> : (const void*)collide_batch_kernel<256, 4>;
+  if (block == 512) return pu == 2 ? (const void*)collide_batch_kernel<512, 2> : (const void*)collide_batch_kernel<512, 4>;
+  return pu == 2 ? (const void*)collide_batch_kernel<1024, 2> : (const void*)collide_batch_kernel<1024, 4>;
+}
+
+// A class of a batch: its problems with one velocity grid.  The class's
+// cells (items item0 .. item0 + nitems - 1, by decreasing cost) are one
+// collide launch with settings of its own: block size, shared records per
+// thread in flight (pu) and workgroups (spread 0: one per resident slot,
+// 1: two per slot, 2: one per cell).
+struct BatchClass {
+  int nv3[3] = {0, 0, 0};
+  int problems = 0;
+  int64_t cells = 0, pair_cells = 0;
+  int item0 = 0, nitems = 0;
+  size_t lds = 0;
+  bool ok[3] = {false, false, false};  // 256, 512, 1024 threads fit
+  int64_t cap[3] = {0, 0, 0};          // resident workgroups (all CUs)
+  int block = 512, pu = 4, spread = 0;
+  bool part = false;                   // ACC_PART: 1024 threads, spread 0 or 1 (the global rows)
+  double ms = 0.0;                     // ms per launch measured by the tuner
+};
+
+int block_index(int block) { return block == 256 ? 0 : (block == 512 ? 1 : 2); }
+
+int64_t class_grid(const BatchClass& k) {
+  const int64_t cap = k.cap[block_index(k.block)];
+  const int64_t g = k.spread == 0 ? cap : (k.spread == 1 ? 2 * cap : (int64_t)k.nitems);
+  return std::max<int64_t>(1, std::min<int64_t>(g, k.nitems));
 }
 
 }  // namespace
@@ -1225,14 +1251,15 @@ struct boltz_batch {
   int total[5] = {0, 0, 0, 0, 0};
   int2* items = nullptr;
   int nitems = 0;
+  std::vector<BatchClass> cls;
+  // stream work units per problem for the 32 x 4 tile shape (start[2], total[2]: 16 x 8)
+  int* start_b = nullptr;
+  int total_b = 0;
+  int stile = 0;  // stream tile shape in use: 0 = 16 x 8, 1 = 32 x 4
   uint32_t* step_dev = nullptr;
   int64_t nodes = 0;
   int64_t pair_cells = 0;
-  size_t collide_lds = 0;
   size_t sample_lds = 0;
-  int block = 512;                // collide block size in use
-  bool block_ok[3] = {false, false, false};  // 256, 512, 1024 fit
-  int64_t grid[3] = {0, 0, 0};
   std::string err;
 };
 
@@ -1245,7 +1272,22 @@ int bfail(boltz_batch* b, int code, const std::string& msg) {
   return code;
 }
 
-int block_index(int block) { return block == 256 ? 0 : (block == 512 ? 1 : 2); }
+// Launch one class's collision, hin -> hout (the batched step: in place).
+void launch_class(const boltz_batch* b, const BatchClass& k, const float* hin, float* hout, hipStream_t st) {
+  const dim3 grid((unsigned)class_grid(k));
+  const int2* it = b->items + k.item0;
+#define BOLTZ_CLASS_LAUNCH(B, U)                                                                              \
+  hipLaunchKernelGGL((collide_batch_kernel<B, U>), grid, dim3(B), k.lds, st, b->cavs, it, k.nitems, hin, hout,   \
+                     b->step_dev)
+  if (k.block == 256) {
+    if (k.pu == 2) BOLTZ_CLASS_LAUNCH(256, 2); else BOLTZ_CLASS_LAUNCH(256, 4);
+  } else if (k.block == 512) {
+    if (k.pu == 2) BOLTZ_CLASS_LAUNCH(512, 2); else BOLTZ_CLASS_LAUNCH(512, 4);
+  } else {
+    if (k.pu == 2) BOLTZ_CLASS_LAUNCH(1024, 2); else BOLTZ_CLASS_LAUNCH(1024, 4);
+  }
+#undef BOLTZ_CLASS_LAUNCH
+}
 
 }  // namespace
 
@@ -1295,11 +1337,12 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
   }
   // ---- descriptors, launch ranges, work items
   std::vector<BatchCav> cavs(count);
-  std::vector<int> st[5];
+  std::vector<int> st[5], stb(count + 1, 0);
   for (int k = 0; k < 5; ++k) st[k].assign(count + 1, 0);
   std::vector<double> cost(count);
+  std::vector<int> cls_of(count);
   int64_t off = 0;
-  size_t lds_max = 0, slds_max = 0;
+  size_t slds_max = 0;
   for (int i = 0; i < count; ++i) {
     const boltz_ctx* c = b->ctx[i];
     BatchCav& C = cavs[i];
@@ -1308,9 +1351,15 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     C.hoff = off;
     C.tidx = c->tidx;
     C.tcoef = c->tcoef;
-    C.sidx = c->sidx;
-    C.scoef = c->scoef;
-    C.mode = c->batch_mode;
+    // a problem whose single-problem collision uses the partial-tile layout
+    // keeps it (its records unsorted); the others take the batch layouts
+    const bool part = c->collide_mode == ACC_PART;
+    const int tv = c->ngroups > 0 ? 1 : 0;
+    C.P.hyb_lo = c->hyb_lo[tv];
+    C.P.hyb_n = c->hyb_n[tv];
+    C.sidx = part ? c->tidx : c->sidx;
+    C.scoef = part ? c->tcoef : c->scoef;
+    C.mode = part ? ACC_PART : c->batch_mode;
     b->hoff.push_back(off);
     off += c->ncells * (int64_t)c->nv;
     const bool cavity = c->p.bc == BOLTZ_BC_CAVITY;
@@ -1319,9 +1368,15 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     const int nf0 = !cavity ? 0 : (b->order == 2 ? 2 * ny : 2 * (nx + ny));
     const int nf1 = (cavity && b->order == 2) ? 2 * nx : 0;
     const int64_t units = stream4_units(nx, ny, c->nv);
+    const int64_t units_b = stream4_units(nx, ny, c->nv, kTX4b, kTY4b);
+    if ((int64_t)stb[i] + units_b >= ((int64_t)1 << 31) / 8) {
+      boltz_batch_destroy(b);
+      return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batch too large for one launch per phase");
+    }
+    stb[i + 1] = stb[i] + (int)units_b;
     const int64_t sblocks =
         (c->ngroups > 0 && c->p.n_pairs > 0) ? c->ngroups * ((c->p.n_pairs + kSampleBlock - 1) / kSampleBlock) : 0;
-    const int64_t sorts = (c->sidx != c->tidx) ? c->ngroups : 0;
+    const int64_t sorts = (!part && c->sidx != c->tidx) ? c->ngroups : 0;
     const int64_t nxt[5] = {(int64_t)st[0][i] + nf0, (int64_t)st[1][i] + nf1, (int64_t)st[2][i] + units,
                             (int64_t)st[3][i] + sblocks, (int64_t)st[4][i] + sorts};
     for (int k = 0; k < 5; ++k) {
@@ -1333,28 +1388,52 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     }
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     const bool table = c->ngroups > 0;
-    lds_max = std::max(lds_max, CollideLDS::bytes(c->nv, nsum, c->batch_mode, !table));
+    // class: the problems with this velocity grid
+    int k = 0;
+    while (k < (int)b->cls.size() && !(b->cls[k].nv3[0] == c->n[0] && b->cls[k].nv3[1] == c->n[1] &&
+                                       b->cls[k].nv3[2] == c->n[2]))
+      ++k;
+    if (k == (int)b->cls.size()) {
+      b->cls.emplace_back();
+      for (int a = 0; a < 3; ++a) b->cls[k].nv3[a] = c->n[a];
+    }
+    BatchClass& K = b->cls[k];
+    cls_of[i] = k;
+    K.problems += 1;
+    K.cells += c->ncells;
+    K.pair_cells += c->ncells * c->p.n_pairs;
+    K.part = part;
+    K.lds = std::max(K.lds, part ? CollideLDS::part_bytes(c->nv, c->hyb_n[tv], nsum, !table)
+                                 : CollideLDS::bytes(c->nv, nsum, c->batch_mode, !table));
     if (table) slds_max = std::max(slds_max, TablesLDS::bytes(nsum, true));
     // relative cost of one cell: pair loop (drawn pairs cost more) plus the node phases
     cost[i] = (double)c->p.n_pairs * (table ? 1.0 : 3.0) *
-                  (c->batch_mode == ACC_FIXED ? 1.0 : (c->batch_mode == ACC_SPLIT ? 1.3 : 4.0)) +
+                  ((part || c->batch_mode == ACC_FIXED) ? 1.0 : (c->batch_mode == ACC_SPLIT ? 1.3 : 4.0)) +
               40.0 * c->nv;
     b->pair_cells += c->ncells * c->p.n_pairs;
   }
   b->nodes = off;
   for (int k = 0; k < 5; ++k) b->total[k] = st[k][count];
+  b->total_b = stb[count];
+  // work items grouped by class, by decreasing cost within a class
   std::vector<int2> items;
   for (int i = 0; i < count; ++i)
     for (int64_t cell = 0; cell < b->ctx[i]->ncells; ++cell) items.push_back(make_int2(i, (int)cell));
-  std::stable_sort(items.begin(), items.end(), [&](const int2& x, const int2& y) { return cost[x.x] > cost[y.x]; });
+  std::stable_sort(items.begin(), items.end(), [&](const int2& x, const int2& y) {
+    return cls_of[x.x] != cls_of[y.x] ? cls_of[x.x] < cls_of[y.x] : cost[x.x] > cost[y.x];
+  });
   b->nitems = (int)items.size();
-  b->collide_lds = lds_max;
+  for (size_t m = 0; m < items.size(); ++m) {
+    BatchClass& K = b->cls[cls_of[items[m].x]];
+    if (K.nitems++ == 0) K.item0 = (int)m;
+  }
   b->sample_lds = slds_max;
   // ---- one device allocation
   size_t o = 0;
   const size_t o_cavs = o; o = align256(o + sizeof(BatchCav) * count);
   size_t o_st[5];
   for (int k = 0; k < 5; ++k) { o_st[k] = o; o = align256(o + sizeof(int) * (count + 1)); }
+  const size_t o_stb = o; o = align256(o + sizeof(int) * (count + 1));
   const size_t o_items = o; o = align256(o + sizeof(int2) * items.size());
   const size_t o_step = o; o = align256(o + 4);
   hipError_t e = hipMalloc(&b->dmem, o);
@@ -1366,11 +1445,13 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
   unsigned char* base = static_cast<unsigned char*>(b->dmem);
   b->cavs = reinterpret_cast<BatchCav*>(base + o_cavs);
   for (int k = 0; k < 5; ++k) b->start[k] = reinterpret_cast<int*>(base + o_st[k]);
+  b->start_b = reinterpret_cast<int*>(base + o_stb);
   b->items = reinterpret_cast<int2*>(base + o_items);
   b->step_dev = reinterpret_cast<uint32_t*>(base + o_step);
   e = hipMemcpy(b->cavs, cavs.data(), sizeof(BatchCav) * count, hipMemcpyHostToDevice);
   for (int k = 0; k < 5 && e == hipSuccess; ++k)
     e = hipMemcpy(b->start[k], st[k].data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->start_b, stb.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->step_dev, 0, 4);
   // ---- collide launch set-up for each block size whose LDS fits
@@ -1380,29 +1461,34 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
     e = hipFuncSetAttribute((const void*)sample_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)slds_max);
   const int blocks[3] = {256, 512, 1024};
-  for (int t = 0; t < 3 && e == hipSuccess; ++t) {
-    if (lds_max + collide_static_lds(blocks[t]) > kLdsBytes) continue;
-    const void* fn = collide_batch_fn(blocks[t]);
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
-    int per_cu = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, blocks[t], lds_max);
-    if (e != hipSuccess || per_cu < 1) {
-      (void)hipGetLastError();
-      e = hipSuccess;
-      continue;
+  for (int t = 0; t < 3 && e == hipSuccess; ++t)
+    for (int pu = 2; pu <= 4 && e == hipSuccess; pu += 2)
+      e = hipFuncSetAttribute(collide_batch_fn(blocks[t], pu), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kLdsBytes - collide_static_lds(blocks[t])));
+  for (BatchClass& K : b->cls) {
+    for (int t = 0; t < 3 && e == hipSuccess; ++t) {
+      if (K.lds + collide_static_lds(blocks[t]) > kLdsBytes || (K.part && blocks[t] != 1024)) continue;
+      int per_cu = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, collide_batch_fn(blocks[t], 4), blocks[t], K.lds);
+      if (e != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        e = hipSuccess;
+        continue;
+      }
+      K.ok[t] = true;
+      K.cap[t] = (int64_t)per_cu * (ncu < 1 ? 1 : ncu);
+      // the partial-tile layout's global rows: two per CU, one per workgroup
+      if (K.part) K.cap[t] = std::min<int64_t>(K.cap[t], ncu < 1 ? 1 : ncu);
     }
-    b->block_ok[t] = true;
-    const int64_t cap = (int64_t)per_cu * (ncu < 1 ? 1 : ncu);
-    b->grid[t] = b->nitems < cap ? b->nitems : cap;
+    K.block = K.ok[1] ? 512 : (K.ok[0] ? 256 : 1024);
+    if (e == hipSuccess && !K.ok[block_index(K.block)]) {
+      boltz_batch_destroy(b);
+      return bfail(nullptr, BOLTZ_EUNSUPPORTED, "boltz_batch_create: no collide block size fits a class's LDS");
+    }
   }
   if (e != hipSuccess) {
     boltz_batch_destroy(b);
     return bfail(nullptr, BOLTZ_EHIP, std::string("boltz_batch_create: ") + hipGetErrorString(e));
-  }
-  b->block = b->block_ok[1] ? 512 : (b->block_ok[0] ? 256 : 1024);
-  if (!b->block_ok[block_index(b->block)]) {
-    boltz_batch_destroy(b);
-    return bfail(nullptr, BOLTZ_EUNSUPPORTED, "boltz_batch_create: no collide block size fits the batch's LDS");
   }
   *out = b;
   return BOLTZ_OK;
@@ -1413,7 +1499,15 @@ int boltz_batch_query(const boltz_batch* b, boltz_batch_info* out) {
   out->count = b->count;
   out->nodes = b->nodes;
   out->pair_cells = b->pair_cells;
-  out->collide_block = b->block;
+  // the block size of the class with the most pair-cells
+  const BatchClass* big = nullptr;
+  for (const BatchClass& K : b->cls)
+    if (!big || K.pair_cells > big->pair_cells) big = &K;
+  out->collide_block = big ? big->block : 0;
+  out->classes = (int32_t)b->cls.size();
+  out->stream_tile[0] = b->stile == 0 ? kTX4 : kTX4b;
+  out->stream_tile[1] = b->stile == 0 ? kTY4 : kTY4b;
+  out->reserved = 0;
   int64_t bytes = (int64_t)b->dbytes;
   for (const boltz_ctx* c : b->ctx) bytes += (int64_t)c->dbytes;
   out->device_bytes = bytes;
@@ -1466,14 +1560,22 @@ int boltz_batch_step(boltz_batch* b, const float* h_in, float* h_out, const bolt
     hipLaunchKernelGGL(wall_batch_kernel<1>, dim3(8 * px), dim3(kWallBlock), 0, st, b->cavs, b->start[1], b->count,
                        h_in, px);
   }
-  {
+  if (b->stile == 0) {
     const int px = ranged(b->total[2]);
     if (b->order == 2)
-      hipLaunchKernelGGL(stream4_batch_kernel<2>, dim3(8 * px), dim3(kStream4Block), 0, st, b->cavs, b->start[2],
-                         b->count, h_in, h_out, px);
+      hipLaunchKernelGGL((stream4_batch_kernel<2, kTX4, kTY4>), dim3(8 * px), dim3(kTX4 * (kJ4 / 4)), 0, st, b->cavs,
+                         b->start[2], b->count, h_in, h_out, px);
     else
-      hipLaunchKernelGGL(stream4_batch_kernel<1>, dim3(8 * px), dim3(kStream4Block), 0, st, b->cavs, b->start[2],
-                         b->count, h_in, h_out, px);
+      hipLaunchKernelGGL((stream4_batch_kernel<1, kTX4, kTY4>), dim3(8 * px), dim3(kTX4 * (kJ4 / 4)), 0, st, b->cavs,
+                         b->start[2], b->count, h_in, h_out, px);
+  } else {
+    const int px = ranged(b->total_b);
+    if (b->order == 2)
+      hipLaunchKernelGGL((stream4_batch_kernel<2, kTX4b, kTY4b>), dim3(8 * px), dim3(kTX4b * (kJ4 / 4)), 0, st,
+                         b->cavs, b->start_b, b->count, h_in, h_out, px);
+    else
+      hipLaunchKernelGGL((stream4_batch_kernel<1, kTX4b, kTY4b>), dim3(8 * px), dim3(kTX4b * (kJ4 / 4)), 0, st,
+                         b->cavs, b->start_b, b->count, h_in, h_out, px);
   }
   if (b->total[3] > 0)
     hipLaunchKernelGGL(sample_batch_kernel, dim3(b->total[3]), dim3(kSampleBlock), b->sample_lds, st, b->cavs,
@@ -1481,22 +1583,7 @@ int boltz_batch_step(boltz_batch* b, const float* h_in, float* h_out, const bolt
   if (b->total[4] > 0)
     hipLaunchKernelGGL(split_sort_batch_kernel, dim3(b->total[4]), dim3(kSortBlock), 0, st, b->cavs, b->start[4],
                        b->count);
-  const int t = block_index(b->block);
-  const dim3 grid((unsigned)b->grid[t]);
-  switch (b->block) {
-    case 256:
-      hipLaunchKernelGGL(collide_batch_kernel<256>, grid, dim3(256), b->collide_lds, st, b->cavs, b->items, b->nitems,
-                         h_out, h_out, b->step_dev);
-      break;
-    case 512:
-      hipLaunchKernelGGL(collide_batch_kernel<512>, grid, dim3(512), b->collide_lds, st, b->cavs, b->items, b->nitems,
-                         h_out, h_out, b->step_dev);
-      break;
-    default:
-      hipLaunchKernelGGL(collide_batch_kernel<1024>, grid, dim3(1024), b->collide_lds, st, b->cavs, b->items,
-                         b->nitems, h_out, h_out, b->step_dev);
-      break;
-  }
+  for (const BatchClass& K : b->cls) launch_class(b, K, h_out, h_out, st);
   hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, b->step_dev);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BOLTZ_OK : bfail(b, BOLTZ_EHIP, std::string("boltz_batch_step: ") + hipGetErrorString(e));
@@ -1504,9 +1591,54 @@ int boltz_batch_step(boltz_batch* b, const float* h_in, float* h_out, const bolt
 
 int boltz_batch_set_block(boltz_batch* b, int block) {
   if (!b) return BOLTZ_EINVAL;
-  if ((block != 256 && block != 512 && block != 1024) || !b->block_ok[block_index(block)])
-    return bfail(b, BOLTZ_EINVAL, "boltz_batch_set_block: block size not available for this batch");
-  b->block = block;
+  if (block != 256 && block != 512 && block != 1024)
+    return bfail(b, BOLTZ_EINVAL, "boltz_batch_set_block: block size must be 256, 512 or 1024");
+  bool any = false;
+  for (const BatchClass& K : b->cls) any = any || K.ok[block_index(block)];
+  if (!any) return bfail(b, BOLTZ_EINVAL, "boltz_batch_set_block: block size not available for any class");
+  for (BatchClass& K : b->cls)
+    if (K.ok[block_index(block)]) K.block = block;
+  return BOLTZ_OK;
+}
+
+int boltz_batch_class_info(const boltz_batch* b, int index, boltz_batch_class* out) {
+  if (!b || !out || index < 0 || index >= (int)b->cls.size()) return BOLTZ_EINVAL;
+  const BatchClass& K = b->cls[index];
+  for (int a = 0; a < 3; ++a) out->nv[a] = K.nv3[a];
+  out->problems = K.problems;
+  out->cells = K.cells;
+  out->pair_cells = K.pair_cells;
+  out->collide_block = K.block;
+  out->pairs_per_lane = K.pu;
+  out->spread = K.spread;
+  out->grid = class_grid(K);
+  out->cells_per_group = (K.nitems + out->grid - 1) / out->grid;
+  out->ms = K.ms;
+  return BOLTZ_OK;
+}
+
+int boltz_batch_set_class(boltz_batch* b, int index, int block, int pairs_per_lane, int spread) {
+  if (!b) return BOLTZ_EINVAL;
+  if (index < 0 || index >= (int)b->cls.size())
+    return bfail(b, BOLTZ_EINVAL, "boltz_batch_set_class: no such class");
+  BatchClass& K = b->cls[index];
+  if ((block != 256 && block != 512 && block != 1024) || !K.ok[block_index(block)])
+    return bfail(b, BOLTZ_EINVAL, "boltz_batch_set_class: block size not available for this class");
+  if ((pairs_per_lane != 2 && pairs_per_lane != 4) || spread < 0 || spread > (K.part ? 1 : 2))
+    return bfail(b, BOLTZ_EINVAL,
+                 "boltz_batch_set_class: pairs_per_lane must be 2 or 4 and spread 0, 1 or 2 (0 or 1 for the "
+                 "partial-tile layout)");
+  K.block = block;
+  K.pu = pairs_per_lane;
+  K.spread = spread;
+  return BOLTZ_OK;
+}
+
+int boltz_batch_set_stream_tile(boltz_batch* b, int tx, int ty) {
+  if (!b) return BOLTZ_EINVAL;
+  if (tx == kTX4 && ty == kTY4) b->stile = 0;
+  else if (tx == kTX4b && ty == kTY4b) b->stile = 1;
+  else return bfail(b, BOLTZ_EINVAL, "boltz_batch_set_stream_tile: tiles are 16 x 8 or 32 x 4 cells");
   return BOLTZ_OK;
 }
 
@@ -1519,36 +1651,83 @@ int boltz_batch_tune(boltz_batch* b, float* h_a, float* h_b, const boltz_walls* 
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he != hipSuccess) return bfail(b, BOLTZ_EHIP, std::string("boltz_batch_tune: ") + hipGetErrorString(he));
-  const int blocks[3] = {256, 512, 1024};
-  int best = b->block;
-  float best_ms = 0.f;
   int rc = BOLTZ_OK;
-  for (int t = 0; t < 3 && rc == BOLTZ_OK; ++t) {
-    if (!b->block_ok[t]) continue;
-    b->block = blocks[t];
-    rc = boltz_batch_step(b, h_a, h_b, walls, stream);  // warm-up
-    if (rc != BOLTZ_OK) break;
+  // milliseconds per call of f over `steps` calls after one warm-up call
+  auto timed = [&](auto&& f, double& ms) {
+    rc = f(0);
+    if (rc != BOLTZ_OK) return false;
     (void)hipEventRecord(e0, st);
-    for (int k = 0; k < steps && rc == BOLTZ_OK; ++k)
-      rc = boltz_batch_step(b, (k & 1) ? h_a : h_b, (k & 1) ? h_b : h_a, walls, stream);
+    for (int k = 0; k < steps && rc == BOLTZ_OK; ++k) rc = f(k + 1);
     (void)hipEventRecord(e1, st);
     he = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    float t = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
     if (he != hipSuccess) {
       rc = bfail(b, BOLTZ_EHIP, std::string("boltz_batch_tune: ") + hipGetErrorString(he));
-      break;
+      return false;
     }
-    ms /= steps;
-    if (ms_out) ms_out[t] = ms;
-    if (best_ms == 0.f || ms < best_ms) {
+    ms = (double)t / steps;
+    return rc == BOLTZ_OK;
+  };
+  auto whole = [&](int k) { return boltz_batch_step(b, (k & 1) ? h_a : h_b, (k & 1) ? h_b : h_a, walls, stream); };
+  double before = 0.0, after = 0.0;
+  // 1. the stream tile shape, by whole steps
+  bool ok = timed(whole, before);
+  double best_ms = before;
+  const int tile0 = b->stile;
+  int best_tile = tile0;
+  for (int t = 0; t < 2 && ok; ++t) {
+    if (t == tile0) continue;
+    b->stile = t;
+    double ms = 0.0;
+    ok = timed(whole, ms);
+    if (ok && ms < best_ms) {
       best_ms = ms;
-      best = blocks[t];
+      best_tile = t;
     }
   }
+  b->stile = best_tile;
+  // 2. per class: block size x records per lane x workgroups, by the
+  // class's collision launch alone (h_b -> h_a, the same input every time)
+  const int blocks[3] = {256, 512, 1024};
+  for (BatchClass& K : b->cls) {
+    if (!ok) break;
+    const BatchClass keep = K;
+    BatchClass best = K;
+    best.ms = 0.0;
+    for (int t = 0; t < 3 && ok; ++t) {
+      if (!K.ok[t]) continue;
+      for (int pu = 2; pu <= 4 && ok; pu += 2)
+        for (int sp = 0; sp < 3 && ok; ++sp) {
+          K = keep;
+          K.block = blocks[t];
+          K.pu = pu;
+          K.spread = sp;
+          if (K.part && sp == 2) continue;
+          double ms = 0.0;
+          ok = timed(
+              [&](int) {
+                launch_class(b, K, h_b, h_a, st);
+                const hipError_t le = hipGetLastError();
+                return le == hipSuccess ? BOLTZ_OK
+                                        : bfail(b, BOLTZ_EHIP, std::string("boltz_batch_tune: ") + hipGetErrorString(le));
+              },
+              ms);
+          if (ok && (best.ms == 0.0 || ms < best.ms)) {
+            best = K;
+            best.ms = ms;
+          }
+        }
+    }
+    K = ok ? best : keep;
+  }
+  if (ok) ok = timed(whole, after);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->block = best;
+  if (ms_out && ok) {
+    ms_out[0] = before;
+    ms_out[1] = after;
+  }
   return rc;
 }
 

@@ -760,7 +760,7 @@ __device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, 
 // the accumulators.  TABLE: the pairs are the records of sample_kernel for
 // the cell's group, four per thread and pass so that their loads and
 // gathers are in flight together; else they are drawn here.
-template <int BLOCK, bool TABLE, int MODE>
+template <int BLOCK, bool TABLE, int MODE, int PU = 4>
 __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, const float* hs, float* accf,
                                           unsigned long long* acc64, uint32_t group, uint32_t step,
                                           const uint2* __restrict__ tidx, const float4* __restrict__ tcoef,
@@ -769,7 +769,6 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
   const float epsf = (float)P.eps;
   const uint32_t nt = (uint32_t)P.n_pairs;
   if (TABLE) {
-    constexpr int PU = 4;
     const uint2* ri = tidx + (int64_t)group * nt;
     const float4* rk = tcoef + (int64_t)group * nt;
     // one pass: PU records per thread, loads and gathers in flight together;
@@ -839,14 +838,13 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 // memory (a load for the few lanes that need it, issued after every LDS
 // gather of the pass).  BLOCK threads take part, tid = 0 .. BLOCK - 1 (a
 // multiple of 64, so shared record m stays with lane m mod 64).
-template <int BLOCK, bool TABLE>
+template <int BLOCK, bool TABLE, int PU = 4>
 __device__ __forceinline__ void gain_loss_part(const Params& P, const TablesLDS& T, const Part& Q, uint32_t group,
                                                uint32_t step, const uint2* __restrict__ tidx,
                                                const float4* __restrict__ tcoef, int tid) {
   const float epsf = (float)P.eps;
   const uint32_t nt = (uint32_t)P.n_pairs;
   if (TABLE) {
-    constexpr int PU = 4;
     const uint2* ri = tidx + (int64_t)group * nt;
     const float4* rk = tcoef + (int64_t)group * nt;
     auto pass = [&](uint32_t m, const bool masked) {
@@ -1328,7 +1326,7 @@ __device__ __forceinline__ void correction_sums_part(const TablesLDS& T, const d
 // One cell in the ACC_PART layout (inner h^s tile in LDS, Q.hg the cell's
 // row, accumulators cleared, a barrier passed): as collide_body_hybrid.
 // vec: rows of whole z quadruples and a 16-byte aligned global row.
-template <int BLOCK, bool TABLE, class Next>
+template <int BLOCK, bool TABLE, class Next, int PU = 4>
 __device__ __forceinline__ void collide_body_part(const Params& P, const TablesLDS& T, const Part& Q, double* red,
                                                   bool vec, uint32_t group, uint32_t step, uint32_t flags,
                                                   float* dst, double* defect, const uint2* __restrict__ tidx,
@@ -1338,7 +1336,7 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
   const bool correct = !(flags & 1u);
   const bool vec4 = vec && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
   const double eps = P.eps;
-  gain_loss_part<BLOCK, TABLE>(P, T, Q, group, step, tidx, tcoef, tid);
+  gain_loss_part<BLOCK, TABLE, PU>(P, T, Q, group, step, tidx, tcoef, tid);
   __syncthreads();
   next();
   const bool flagged = *Q.flag != 0u;
@@ -1456,7 +1454,7 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
 // accumulators (the persistent kernel stages the next cell there); defect:
 // the cell's five values or null.  Ends with a barrier, so the LDS can be
 // refilled.
-template <int BLOCK, bool TABLE, int MODE, class Next, class Early>
+template <int BLOCK, bool TABLE, int MODE, int PU = 4, class Next, class Early>
 __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T, float* hs, float* accf,
                                              unsigned long long* acc64, double* red, uint32_t group,
                                              uint32_t step, uint32_t flags, float* dst, double* defect,
@@ -1495,7 +1493,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
         for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();
       }
-      gain_loss<BLOCK, TABLE, ACC_SPLIT>(P, T, hs, ovf, acc64, group, step, tidx, tcoef, lo, (unsigned)n);
+      gain_loss<BLOCK, TABLE, ACC_SPLIT, PU>(P, T, hs, ovf, acc64, group, step, tidx, tcoef, lo, (unsigned)n);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < R; ++k) {
@@ -1516,7 +1514,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
     }
     __syncthreads();
   } else {
-    gain_loss<BLOCK, TABLE, MODE>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
+    gain_loss<BLOCK, TABLE, MODE, PU>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
     __syncthreads();
     next();
     // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator;
@@ -1839,14 +1837,17 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
 // problem's tables are reloaded into LDS when it changes from one item to
 // the next.  The dynamic LDS is that of the largest problem; each problem
 // uses its own layout (accumulation mode, drawn or shared
-// samples).  The step number is read from the device (graph replays).
-template <int BLOCK>
+// samples).  The step number is read from the device (graph replays).  PU:
+// shared records per thread in flight in the pair loop.  A launch covers the
+// items of one class of problems (one velocity grid).
+template <int BLOCK, int PU>
 __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __restrict__ cavs,
                                                               const int2* __restrict__ items, int nitems,
                                                               const float* hin, float* hout,
                                                               const uint32_t* __restrict__ step_dev) {
   extern __shared__ __align__(16) unsigned char dsm[];
   __shared__ double red[20 * (BLOCK / 64)];
+  __shared__ unsigned pflag;
   const int tid = threadIdx.x;
   const uint32_t step = *step_dev;
   int prev = -1;
@@ -1858,6 +1859,50 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
     const int nv = P.nv;
     const int mode = C.mode;
     const bool table = P.sample_group != 1;
+    if constexpr (BLOCK == 1024) {
+      if (mode == ACC_PART) {
+        // the partial-tile layout (grids of one class share it); the
+        // launch has at most one workgroup per row of P.hyb_ovf
+        Part Q;
+        Q.acc = reinterpret_cast<unsigned long long*>(dsm);
+        Q.tile = reinterpret_cast<float*>(dsm + CollideLDS::part64(nv));
+        Q.lo = P.hyb_lo;
+        Q.n = (unsigned)P.hyb_n;
+        Q.ovf = P.hyb_ovf + (int64_t)blockIdx.x * nv;
+        Q.flag = &pflag;
+        if (it.x != prev) {
+          load_tables(P, dsm + CollideLDS::part64(nv) + CollideLDS::tile(P.hyb_n), !table, T);
+          prev = it.x;
+        }
+        const int64_t cell = it.y;
+        Q.hg = hin + C.hoff + cell * nv;
+        const bool vec = ((P.n[2] & 3) == 0) && ((reinterpret_cast<uintptr_t>(Q.hg) & 15) == 0);
+        if (vec) {
+          const float4* s4 = reinterpret_cast<const float4*>(Q.hg + Q.lo);
+          float4* d4 = reinterpret_cast<float4*>(Q.tile);
+          for (int j = tid; j < (P.hyb_n >> 2); j += BLOCK) d4[j] = s4[j];
+        } else {
+          for (int j = tid; j < P.hyb_n; j += BLOCK) Q.tile[j] = Q.hg[Q.lo + j];
+        }
+        {
+          uint4* z = reinterpret_cast<uint4*>(dsm);
+          const int nz = (int)(CollideLDS::part64(nv) / 16);
+          for (int k = tid; k < nz; k += BLOCK) z[k] = make_uint4(0u, 0u, 0u, 0u);
+          if (tid == 0) pflag = 0u;
+        }
+        __syncthreads();
+        const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
+        float* dst = hout + C.hoff + cell * nv;
+        auto none = []() {};
+        if (table)
+          collide_body_part<BLOCK, true, decltype(none)&, PU>(P, T, Q, red, vec, group, step, 0u, dst, nullptr, C.tidx,
+                                                             C.tcoef, none);
+        else
+          collide_body_part<BLOCK, false, decltype(none)&, PU>(P, T, Q, red, vec, group, step, 0u, dst, nullptr,
+                                                              C.tidx, C.tcoef, none);
+        continue;
+      }
+    }
     float* hs = reinterpret_cast<float*>(dsm);
     float* accf = reinterpret_cast<float*>(dsm + CollideLDS::tile(nv));
     unsigned long long* acc64 =
@@ -1885,7 +1930,8 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
     float* dst = hout + C.hoff + cell * nv;
     auto none = []() {};
 #define BOLTZ_BODY(TB, MD)                                                                                      \
-  collide_body<BLOCK, TB, MD>(P, T, hs, accf, acc64, red, group, step, 0u, dst, nullptr, C.tidx, C.tcoef, none, none)
+  collide_body<BLOCK, TB, MD, PU>(P, T, hs, accf, acc64, red, group, step, 0u, dst, nullptr, C.tidx, C.tcoef, none, \
+                                  none)
     if (table) {
       if (mode == ACC_FIXED) BOLTZ_BODY(true, ACC_FIXED);
       else if (mode == ACC_SPLIT) BOLTZ_BODY(true, ACC_SPLIT);

@@ -564,8 +564,11 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
 // column.  The raw block with its upwind halo is staged in LDS; each thread
 // then x-sweeps the rows of its column into registers and applies the y
 // sweep from that register window (order 2), or the unsplit first-order
-// stencil (order 1).  Same arithmetic per element as stream_kernel.
+// stencil (order 1).  Same arithmetic per element as stream_kernel.  The
+// tile shape TX x TY is a template parameter (16 x 8 for single problems;
+// batches also offer 32 x 4, chosen by boltz_batch_tune); TX * 8 threads.
 constexpr int kTX4 = 16, kTY4 = 8, kJ4 = 32, kStream4Block = kTX4 * (kJ4 / 4);
+constexpr int kTX4b = 32, kTY4b = 4;
 // Consecutive velocity chunks of one tile that are adjacent work units (at
 // most kChunkGroup, at most the problem's chunk count): each cell is then
 // read in runs of up to 2 KB rather than 128 B, about 10% faster on the
@@ -579,8 +582,8 @@ __host__ __device__ inline int stream4_group(int nv) {
 
 // work units of one problem: tiles x velocity chunks, rounded up to whole
 // chunk groups
-__host__ __device__ inline int64_t stream4_units(int nx, int ny, int nv) {
-  const int64_t tiles = (int64_t)((nx + kTX4 - 1) / kTX4) * ((ny + kTY4 - 1) / kTY4);
+__host__ __device__ inline int64_t stream4_units(int nx, int ny, int nv, int tx = kTX4, int ty = kTY4) {
+  const int64_t tiles = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
   const int cg = stream4_group(nv);
   const int64_t groups = ((nv + kJ4 - 1) / kJ4 + cg - 1) / cg;
   return tiles * groups * cg;
@@ -596,9 +599,9 @@ __device__ __forceinline__ float4 bw4(float4 h0, float4 h1, float4 h2, float C, 
                      bw_update(h0.z, h1.z, h2.z, C, c2), bw_update(h0.w, h1.w, h2.w, C, c2));
 }
 
-template <int ORDER>
+template <int ORDER, int TX = kTX4, int TY = kTY4>
 struct Stream4LDS {
-  static constexpr int AX = kTX4 + 2 * ORDER, AY = kTY4 + 2 * ORDER, Q = kJ4 / 4;
+  static constexpr int AX = TX + 2 * ORDER, AY = TY + 2 * ORDER, Q = kJ4 / 4;
   float4 a[AY * AX * Q];
 };
 
@@ -607,11 +610,12 @@ struct Stream4LDS {
 // run chunk-group-major over the tiles, so that neighbouring tiles (which
 // share halos) follow each other; within a group, stream4_group(nv)
 // consecutive chunks of one tile.
-template <int ORDER>
+template <int ORDER, int TX = kTX4, int TY = kTY4>
 __device__ __forceinline__ void stream4_unit(const Params& P, const float* __restrict__ hin, float* __restrict__ hout,
                                              int tiles_x, int tiles_y, int unit, float4* A4) {
   constexpr int H = ORDER;
-  constexpr int AX = kTX4 + 2 * H, AY = kTY4 + 2 * H;
+  constexpr int AX = TX + 2 * H, AY = TY + 2 * H;
+  constexpr int NT = TX * (kJ4 / 4);
   constexpr int Q = kJ4 / 4;
   const int ntiles = tiles_x * tiles_y;
   const int gsz = stream4_group(P.nv);
@@ -619,7 +623,7 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
   const int cg = unit / per_group, rem = unit - (unit / per_group) * per_group;
   const int tile = rem / gsz, chunk = cg * gsz + (rem - (rem / gsz) * gsz);
   if (chunk * kJ4 >= P.nv) return;  // padding unit of the last group
-  const int ix0 = (tile % tiles_x) * kTX4, iy0 = (tile / tiles_x) * kTY4;
+  const int ix0 = (tile % tiles_x) * TX, iy0 = (tile / tiles_x) * TY;
   const int j0 = chunk * kJ4;
   const int nx = P.nx, ny = P.ny, nv = P.nv;
   const int n1 = P.n[1], n2 = P.n[2];
@@ -638,7 +642,7 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
   // All loads of a thread are issued before its LDS stores (fixed trip
   // count), so their latencies overlap.
   {
-    constexpr int kRows = kStream4Block / Q;                 // cells per pass
+    constexpr int kRows = NT / Q;                            // cells per pass
     constexpr int kIter = (AY * AX + kRows - 1) / kRows;     // passes
     const int q = threadIdx.x % Q;
     const int jq = j0 + 4 * q;
@@ -688,7 +692,7 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
   __syncthreads();
   if (!ok) return;
   if (ORDER == 2) {
-    // x-swept rows iy0 - 2 .. iy0 + kTY4 + 1 of this column (only the rows
+    // x-swept rows iy0 - 2 .. iy0 + TY + 1 of this column (only the rows
     // on the upwind side in y are formed)
     float4 hx[AY];
     const int xc = c + 2;
@@ -709,7 +713,7 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
     }
     float* dst = hout + jq;
 #pragma unroll
-    for (int r = 0; r < kTY4; ++r) {
+    for (int r = 0; r < TY; ++r) {
       const int iy = iy0 + r;
       if (iy >= ny) break;
       const float4 h0 = hx[r + 2];
@@ -720,7 +724,7 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
   } else {
     float* dst = hout + jq;
 #pragma unroll
-    for (int r = 0; r < kTY4; ++r) {
+    for (int r = 0; r < TY; ++r) {
       const int iy = iy0 + r;
       if (iy >= ny) break;
       const float4* ctr = &A4[((r + 1) * AX + c + 1) * Q + q];
@@ -750,18 +754,18 @@ __global__ __launch_bounds__(kStream4Block) void stream4_kernel(Params P, const 
 
 // Every problem of a batch in one launch (start: first unit of each problem;
 // all problems have n_z % 4 == 0 and the same order).
-template <int ORDER>
-__global__ __launch_bounds__(kStream4Block) void stream4_batch_kernel(const BatchCav* __restrict__ cavs,
-                                                                      const int* __restrict__ start, int count,
-                                                                      const float* __restrict__ hin,
-                                                                      float* __restrict__ hout, int per_xcd) {
-  __shared__ Stream4LDS<ORDER> L;
+template <int ORDER, int TX, int TY>
+__global__ __launch_bounds__(TX * (kJ4 / 4)) void stream4_batch_kernel(const BatchCav* __restrict__ cavs,
+                                                                       const int* __restrict__ start, int count,
+                                                                       const float* __restrict__ hin,
+                                                                       float* __restrict__ hout, int per_xcd) {
+  __shared__ Stream4LDS<ORDER, TX, TY> L;
   const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (u >= start[count]) return;
   const int c = find_cav(start, count, u);
   const Params& P = cavs[c].P;
-  const int tiles_x = (P.nx + kTX4 - 1) / kTX4, tiles_y = (P.ny + kTY4 - 1) / kTY4;
-  stream4_unit<ORDER>(P, hin + cavs[c].hoff, hout + cavs[c].hoff, tiles_x, tiles_y, u - start[c], L.a);
+  const int tiles_x = (P.nx + TX - 1) / TX, tiles_y = (P.ny + TY - 1) / TY;
+  stream4_unit<ORDER, TX, TY>(P, hin + cavs[c].hoff, hout + cavs[c].hoff, tiles_x, tiles_y, u - start[c], L.a);
 }
 
 }  // namespace boltz

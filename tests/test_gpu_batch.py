@@ -131,6 +131,44 @@ def test_batch_matches_single_problems(lib, torch_mod):
         assert (d - f).abs().max().item() <= 1e-6 * f.abs().max().item(), blk
 
 
+def test_batch_class_settings_and_stream_tiles(lib, torch_mod):
+    """Records per lane, workgroup spread and the stream tile shape change no
+    arithmetic: every setting reproduces the default one bit for bit (the
+    compare-and-swap layout to 1e-6); all classes at one block size."""
+    _say("batch class settings")
+    batch = lib.Batch(PROBLEMS)
+    walls = [_walls(lib, i, p["nx"]) for i, p in enumerate(PROBLEMS)]
+
+    def run():
+        a = _fill(torch_mod, batch, 51)
+        b = batch.empty()
+        batch.set_step(9)
+        for k in range(2):
+            batch.step(a, b, walls)
+            a, b = b, a
+        torch_mod.cuda.synchronize()
+        return a
+
+    batch.set_block(512)
+    batch.set_stream_tile(16, 8)
+    ref = run()
+    cls = batch.classes()
+    for tile, pu, spread in (((32, 4), 4, 0), ((16, 8), 2, 1), ((32, 4), 2, 2), ((16, 8), 4, 2)):
+        batch.set_stream_tile(*tile)
+        for k, c in enumerate(cls):
+            # the partial-tile layout (24^3 here) runs 1024 threads and at most two workgroups per CU
+            part = c["collide_block"] == 1024
+            batch.set_class(k, c["collide_block"], pu, min(spread, 1) if part else spread)
+        assert batch.stream_tile == tile
+        got = run()
+        for i in range(batch.count):
+            g, r = batch.view(got, i), batch.view(ref, i)
+            if _fixed_layout(PROBLEMS[i]):
+                assert torch_mod.equal(g, r), (tile, pu, spread, i)
+            else:
+                assert (g - r).abs().max().item() <= 1e-6 * r.abs().max().item(), (tile, pu, spread, i)
+
+
 def test_batch_problem_matches_oracle(lib, oracle_mod, torch_mod):
     _say("batch problem vs oracle")
     batch = lib.Batch(PROBLEMS)
@@ -197,15 +235,47 @@ def test_batch_graph_replays_match_eager_steps(lib, torch_mod):
         assert torch_mod.equal(tmp, ga)
 
 
-def test_batch_tune_and_validation(lib, torch_mod):
+def test_batch_tune_and_validation(lib, oracle_mod, torch_mod):
     _say("batch tune")
     batch = lib.Batch(PROBLEMS)
     walls = [_walls(lib, i, p["nx"]) for i, p in enumerate(PROBLEMS)]
     a = _fill(torch_mod, batch, 41)
     b = batch.empty()
     ms = batch.tune(a, b, walls, steps=2)
-    assert ms and all(v > 0 for v in ms.values())
-    assert batch.collide_block in ms and ms[batch.collide_block] == min(ms.values())
+    assert ms["before"] > 0 and ms["after"] > 0
+    # the tuned settings: one class per velocity grid, each within its options
+    cls = batch.classes()
+    grids = {tuple(p["nv"]) for p in PROBLEMS}
+    assert len(cls) == len(grids) == batch.nclasses and {c["nv"] for c in cls} == grids
+    assert sum(c["cells"] for c in cls) == sum(p["nx"] * p["ny"] for p in PROBLEMS)
+    for c in cls:
+        assert c["collide_block"] in (256, 512, 1024) and c["pairs_per_lane"] in (2, 4) and 0 <= c["spread"] <= 2
+        assert c["grid"] >= 1 and c["cells_per_group"] == -(-c["cells"] // c["grid"]) and c["ms"] > 0
+    assert batch.stream_tile in ((16, 8), (32, 4))
+    # a tuned step against the oracle
+    a = _fill(torch_mod, batch, 43)
+    batch.set_step(5)
+    batch.step(a, b, walls)
+    torch_mod.cuda.synchronize()
+    o = oracle_mod.Oracle(**PROBLEMS[0])
+    w = walls[0]
+    wo = oracle_mod.Walls(lid_u=w.lid_u, tau_left=w.tau_left, tau_right=w.tau_right, tau_bottom=w.tau_bottom,
+                          tau_top=w.tau_top)
+    ref = o.step(batch.view(a, 0).cpu().numpy().astype(np.float64), wo, 5)
+    got = batch.view(b, 0).cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    part = [k for k, c in enumerate(cls) if c["nv"] == (24, 24, 24)]
+    assert part and cls[part[0]]["collide_block"] == 1024 and cls[part[0]]["spread"] <= 1
+    with pytest.raises(lib.BoltzError):
+        batch.set_class(part[0], 512)
+    with pytest.raises(lib.BoltzError):
+        batch.set_class(part[0], 1024, spread=2)
+    with pytest.raises(lib.BoltzError):
+        batch.set_class(0, 512, pairs_per_lane=3)
+    with pytest.raises(lib.BoltzError):
+        batch.set_class(99, 512)
+    with pytest.raises(lib.BoltzError):
+        batch.set_stream_tile(8, 8)
     with pytest.raises(lib.BoltzError):
         batch.set_block(128)
     with pytest.raises(lib.BoltzError):
