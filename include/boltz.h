@@ -59,8 +59,13 @@ enum { BOLTZ_BC_CAVITY = 0, BOLTZ_BC_PERIODIC = 1 };
 
 /* boltz_problem.flags */
 enum { BOLTZ_ALLOW_UNSTABLE = 1u,    /* accept a dt above the Courant limit  */
-       BOLTZ_WITH_ADJOINT = 2u };    /* also allocate the scratch of         */
+       BOLTZ_WITH_ADJOINT = 2u,      /* also allocate the scratch of         */
                                      /* boltz_step_adjoint                   */
+       BOLTZ_CONTINUOUS_PAIRS = 4u };/* draw v, v1 of every pair from the    */
+                                     /* continuous Maxwellian (Box-Muller)   */
+                                     /* and bin them to cells (Sec. 4's      */
+                                     /* sampling kernel) instead of the node */
+                                     /* law; see boltz_collide               */
 /* boltz_collide flags */
 enum { BOLTZ_NO_CORRECTION = 1u };   /* skip S5 (raw Monte Carlo update)     */
 /* device status bits (boltz_read_status) */
@@ -83,7 +88,8 @@ typedef struct boltz_problem {
                          /* per step into a context table (24 B per pair)   */
   uint64_t seed;         /* Philox4x32-10 key (low word, high word)          */
   uint32_t cavity_id;    /* fourth Philox counter word                       */
-  uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT        */
+  uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT |
+                            BOLTZ_CONTINUOUS_PAIRS                           */
   uint32_t mix16;        /* uniform share beta = mix16/16 of the node-pair   */
                          /* law, 0..16.  0 = nodes from the 12-bit discrete  */
                          /* Maxwellian alone: accepted only on grids where   */
@@ -172,6 +178,12 @@ int boltz_stream(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_wa
  * increments of Eq. monteCarloInt are applied in Jacobi form
  * (Eq. collision_step), then the correction of Eq. rinorm_a restores the
  * post-stream mass, momentum and energy (FP64 sums and 5x5 solve).
+ * With BOLTZ_CONTINUOUS_PAIRS (problem flag) the pairs follow the sampling
+ * kernel of Sec. 4 instead: v and v1 from the continuous Maxwellian by the
+ * Box-Muller method (two Philox blocks, counters (m, group, step, cavity)
+ * and (m, group | 2^31, step, cavity)), h taken in the cells that contain
+ * them, weight dt K |v_r . k| / N_t; a pair with any velocity outside the
+ * box is discarded (it still counts in N_t).
  * h_s may equal h_out (in place); otherwise they must not overlap.
  * flags: BOLTZ_NO_CORRECTION.  defect: NULL or ncells*5 FP64 device buffer
  * receiving sum_j w_j psi_k (F_out - F_s) of the stored FP32 values. */

@@ -26,6 +26,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 BC_CAVITY = 0
 BC_PERIODIC = 1
 ALLOW_UNSTABLE = 1
+CONTINUOUS = 4  # pair velocities from the continuous Maxwellian (Box-Muller), binned to cells
 NO_CORRECTION = 1
 
 
@@ -78,6 +79,8 @@ def _load():
         L.boltz_ref_axis_draw.argtypes = [P, ctypes.c_int, U32]
         L.boltz_ref_philox4x32_10.argtypes = [V, V, V]
         L.boltz_ref_cos_sin_2pi.argtypes = [D, ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.boltz_ref_neg_ln.argtypes = [D]
+        L.boltz_ref_neg_ln.restype = D
         L.boltz_ref_debug_pairs.argtypes = [P, I64, I64, I64, I64, V, V, V, V]
         L.boltz_ref_wall_density.argtypes = [P, V, ctypes.POINTER(_Walls), V]
         L.boltz_ref_stream.argtypes = [P, V, V, ctypes.POINTER(_Walls)]
@@ -107,6 +110,11 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     _load().boltz_ref_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
     return out
+
+
+def neg_ln(u: float) -> float:
+    """-ln u of the continuous sampler (u in (0, 1])."""
+    return float(_load().boltz_ref_neg_ln(float(u)))
 
 
 def cos_sin_2pi(u: float):

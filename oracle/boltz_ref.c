@@ -235,7 +235,7 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
    * the far-tail nodes of wide grids (T_{i+1} = T_i); without the uniform
    * component those nodes would never be drawn and their loss terms would
    * be dropped, so the pure Maxwellian law (mix16 = 0) is refused there. */
-  if (p->mix16 == 0) {
+  if (p->mix16 == 0 && !(p->flags & BOLTZ_REF_CONTINUOUS)) {
     for (int k = 0; k < 3; ++k)
       for (int i = 0; i < c->n[k]; ++i)
         if (!(c->pphi[k][i] > 0.0)) {
@@ -392,6 +392,33 @@ void boltz_ref_cos_sin_2pi(double u, double* cs, double* sn) {
   }
 }
 
+/* ------------------------------------------------------------ -ln u -- */
+
+/* -ln u, u in (0, 1]: u = 2^e m with m in [sqrt(1/2), sqrt(2)) (exact, from
+ * the bits), ln m = ln(1 + t) with t = m - 1 (exact) by its alternating
+ * series t - t^2/2 + ... to 40 terms (|t|^40 / 40 < 2e-17), Horner from the
+ * last term; -ln u = -(e ln 2 + ln m). */
+static const double kLn2 = 0.6931471805599453094172321;
+double boltz_ref_neg_ln(double u) {
+  uint64_t bits;
+  memcpy(&bits, &u, sizeof(bits));
+  int e = (int)((bits >> 52) & 0x7FF) - 1023;
+  uint64_t mb = (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+  double m;
+  memcpy(&m, &mb, sizeof(m));
+  if (m > 1.4142135623730951) {
+    m = m * 0.5;
+    e += 1;
+  }
+  double t = m - 1.0;
+  double p = 0.0;
+  for (int n = 40; n >= 1; --n) {
+    const double cn = ((n & 1) ? 1.0 : -1.0) / (double)n;
+    p = cn + t * p;
+  }
+  return -((double)e * kLn2 + t * p);
+}
+
 /* --------------------------------------------------------- pair sample -- */
 
 typedef struct {
@@ -464,8 +491,15 @@ static double node_ratio(const boltz_ref_ctx* c, int i, int j, int k) {
  * importance-sampling estimate of Eq. coll8Dim for the mixture density
  * p~ = (1 - beta) p_Maxwell + beta p_uniform.  Pairs whose post-collision
  * velocity leaves the box are discarded (they still count in N_t). */
+static void sample_pair_continuous(const boltz_ref_ctx* c, uint32_t group, uint32_t step, uint32_t m,
+                                   pair_t* out);
+
 static void sample_pair(const boltz_ref_ctx* c, uint32_t group, uint32_t step, uint32_t m,
                         pair_t* out) {
+  if (c->p.flags & BOLTZ_REF_CONTINUOUS) {
+    sample_pair_continuous(c, group, step, m, out);
+    return;
+  }
   const uint32_t key[2] = {(uint32_t)c->p.seed, (uint32_t)(c->p.seed >> 32)};
   const uint32_t ctr[4] = {m, group, step, c->p.cavity_id};
   uint32_t* r = out->r;
@@ -505,6 +539,69 @@ static void sample_pair(const boltz_ref_ctx* c, uint32_t group, uint32_t step, u
     out->bs = node_of(c, tx, ty, tz);
     out->q = ((c->qfac * fabs(alpha)) * node_ratio(c, ia[0], ia[1], ia[2])) *
              node_ratio(c, ib[0], ib[1], ib[2]);
+  } else {
+    out->as = -1;
+    out->bs = -1;
+    out->q = 0.0;
+  }
+}
+
+/* The continuous variant (problem flag BOLTZ_REF_CONTINUOUS; the sampling
+ * kernel of Sec. 4 as printed): v and v1 are drawn from the Maxwellian Phi0
+ * (each component normal with variance 1/2) by the Box-Muller method, k as
+ * above, and every velocity is binned to the cell that contains it.  Two
+ * Philox4x32-10 blocks per sample: A with counter (m, group, step, cavity),
+ * B with (m, group | 2^31, step, cavity).  With U(w) = (w + 1) 2^-32 (in
+ * (0, 1]) for radii and U'(w) = (w + 1/2) 2^-32 for angles:
+ *   (v_x, v_y) = sqrt(-ln U(A0)) (cos, sin)(2 pi U'(A1)),
+ *   (v_z, v1_x) from (A2, A3), (v1_y, v1_z) from (B0, B1),
+ *   k_z = 2 U'(B2) - 1, azimuth 2 pi U'(B3).
+ * h is taken in the cells a = cell(v), b = cell(v1); the weight is
+ * q = dt K |v_r.k| / N_t (Phi0 is the sampling density itself).  A pair
+ * with any of the four velocities outside the box is discarded (it counts
+ * in N_t); a and b are then -1 when v or v1 is outside. */
+static void sample_pair_continuous(const boltz_ref_ctx* c, uint32_t group, uint32_t step, uint32_t m,
+                                   pair_t* out) {
+  const uint32_t key[2] = {(uint32_t)c->p.seed, (uint32_t)(c->p.seed >> 32)};
+  const uint32_t ca[4] = {m, group, step, c->p.cavity_id};
+  const uint32_t cb[4] = {m, group | 0x80000000u, step, c->p.cavity_id};
+  uint32_t A[4], B[4];
+  boltz_ref_philox4x32_10(ca, key, A);
+  boltz_ref_philox4x32_10(cb, key, B);
+  memcpy(out->r, A, sizeof(A));
+  double nrm[6];
+  const uint32_t rad[3] = {A[0], A[2], B[0]}, ang[3] = {A[1], A[3], B[1]};
+  for (int i = 0; i < 3; ++i) {
+    const double r = sqrt(boltz_ref_neg_ln(((double)rad[i] + 1.0) * 0x1p-32));
+    double cs, sn;
+    boltz_ref_cos_sin_2pi(((double)ang[i] + 0.5) * 0x1p-32, &cs, &sn);
+    nrm[2 * i] = r * cs;
+    nrm[2 * i + 1] = r * sn;
+  }
+  const double vax = nrm[0], vay = nrm[1], vaz = nrm[2], vbx = nrm[3], vby = nrm[4], vbz = nrm[5];
+  const double kz = 2.0 * (((double)B[2] + 0.5) * 0x1p-32) - 1.0;
+  const double s = sqrt((1.0 - kz) * (1.0 + kz));
+  double cp, sp;
+  boltz_ref_cos_sin_2pi(((double)B[3] + 0.5) * 0x1p-32, &cp, &sp);
+  const double kx = s * cp, ky = s * sp;
+  const double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
+  const double alpha = (vrx * kx + vry * ky) + vrz * kz;
+  const double ddx = alpha * kx, ddy = alpha * ky, ddz = alpha * kz;
+  const int ax = axis_cell(c, 0, vax), ay = axis_cell(c, 1, vay), az = axis_cell(c, 2, vaz);
+  const int bx = axis_cell(c, 0, vbx), by = axis_cell(c, 1, vby), bz = axis_cell(c, 2, vbz);
+  const int sx = axis_cell(c, 0, vax + ddx), sy = axis_cell(c, 1, vay + ddy), sz = axis_cell(c, 2, vaz + ddz);
+  const int tx = axis_cell(c, 0, vbx - ddx), ty = axis_cell(c, 1, vby - ddy), tz = axis_cell(c, 2, vbz - ddz);
+  const double vel[12] = {vax, vay, vaz, vbx, vby, vbz, vax + ddx, vay + ddy, vaz + ddz,
+                          vbx - ddx, vby - ddy, vbz - ddz};
+  memcpy(out->vel, vel, sizeof(vel));
+  const int in_a = ax >= 0 && ay >= 0 && az >= 0, in_b = bx >= 0 && by >= 0 && bz >= 0;
+  out->a = in_a ? node_of(c, ax, ay, az) : -1;
+  out->b = in_b ? node_of(c, bx, by, bz) : -1;
+  out->kept = in_a && in_b && sx >= 0 && sy >= 0 && sz >= 0 && tx >= 0 && ty >= 0 && tz >= 0;
+  if (out->kept) {
+    out->as = node_of(c, sx, sy, sz);
+    out->bs = node_of(c, tx, ty, tz);
+    out->q = c->qfac * fabs(alpha);
   } else {
     out->as = -1;
     out->bs = -1;

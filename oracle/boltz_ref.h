@@ -37,7 +37,10 @@ enum {
 enum { BOLTZ_REF_BC_CAVITY = 0, BOLTZ_REF_BC_PERIODIC = 1 };
 
 /* problem flags */
-enum { BOLTZ_REF_ALLOW_UNSTABLE = 1u };
+/* BOLTZ_REF_CONTINUOUS: the pre-collision velocities are drawn from the
+ * continuous Maxwellian by the Box-Muller method and binned to their cells
+ * (the sampling kernel of Sec. 4), instead of the node law. */
+enum { BOLTZ_REF_ALLOW_UNSTABLE = 1u, BOLTZ_REF_CONTINUOUS = 4u };
 /* collide flags */
 enum { BOLTZ_REF_NO_CORRECTION = 1u };
 
@@ -55,7 +58,7 @@ typedef struct boltz_ref_problem {
   int64_t sample_group;  /* G: cells sharing one pair stream (0 = all)      */
   uint64_t seed;         /* Philox key                                      */
   uint32_t cavity_id;    /* fourth Philox counter word                      */
-  uint32_t flags;        /* BOLTZ_REF_ALLOW_UNSTABLE                        */
+  uint32_t flags;        /* BOLTZ_REF_ALLOW_UNSTABLE | BOLTZ_REF_CONTINUOUS */
   uint32_t mix16;        /* uniform share of the pair law, in 1/16 (0..16); */
                          /* 0 only on grids where every node has a positive */
                          /* Maxwellian-law probability (else EINVAL)        */
@@ -107,6 +110,11 @@ void boltz_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint3
 /* cos(2 pi u), sin(2 pi u) by the octant reduction + Taylor polynomials that
  * define the direction map of the pair sampler. */
 void boltz_ref_cos_sin_2pi(double u, double* c, double* s);
+
+/* -ln u for u in (0, 1], from the binary exponent and a 40-term series of
+ * ln(1 + t), |t| <= sqrt(2) - 1, in a fixed order of IEEE adds and
+ * multiplies. */
+double boltz_ref_neg_ln(double u);
 
 /* Pair sampler for (cell, step, m0 .. m0+count-1): node indices
  * (a, b, a*, b*) with -1 for a*, b* when the pair is discarded, the weight q

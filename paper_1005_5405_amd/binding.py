@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libboltz.so")
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BC_CAVITY, BC_PERIODIC = 0, 1
 ALLOW_UNSTABLE, WITH_ADJOINT = 1, 2
+CONTINUOUS_PAIRS = 4  # pair velocities from the continuous Maxwellian (Box-Muller), binned to cells
 NO_CORRECTION = 1
 STATUS_NOT_SPD, STATUS_NONFINITE = 1, 2
 

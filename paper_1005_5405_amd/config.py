@@ -33,6 +33,7 @@ class Preset:
     lid_omega: float = 0.0       # lid_u * sin(lid_omega * t) when > 0
     moments_every: int = 0
     rv: float = 0.0              # velocity cells stretched in this ratio (0: uniform)
+    continuous: bool = False     # pairs from the continuous Maxwellian (Box-Muller), binned to cells
 
     @property
     def delta(self) -> float:
@@ -42,6 +43,8 @@ class Preset:
         kw = dict(nx=self.nx, ny=self.ny, nv=self.nv, vmax=self.vmax, delta=self.delta, eps=self.eps,
                   n_pairs=self.n_pairs, cfl=self.cfl, order=self.order, seed=self.seed,
                   sample_group=self.sample_group, mix16=self.mix16, rv=self.rv)
+        if self.continuous:
+            kw["flags"] = 4  # BOLTZ_CONTINUOUS_PAIRS
         kw.update(over)
         return kw
 
@@ -68,7 +71,8 @@ CAVITY_200 = Preset("cavity 200x200, 24^3 velocities, Kn 0.01, 50000 pairs/cell,
 # The paper's own benchmark discretisation (Sec. 5.1): delta = 1, 160x160
 # cells (N_r = 25600), 20^3 velocity cells on [-3, 3] stretched in the ratio
 # 0.945, N_t = 6144, lid velocity 0.01, CFL 0.5
-CAVITY_PAPER = Preset("cavity 160x160, 20^3 velocities stretched 0.945 on [-3, 3], delta 1, 6144 pairs/cell",
-                      160, 160, 20, 3.0, 1.0, 0.01, 0.01, 6144, 1000, rv=0.945)
+CAVITY_PAPER = Preset("cavity 160x160, 20^3 velocities stretched 0.945 on [-3, 3], delta 1, 6144 pairs/cell "
+                      "from the continuous Maxwellian (Box-Muller)",
+                      160, 160, 20, 3.0, 1.0, 0.01, 0.01, 6144, 1000, rv=0.945, continuous=True)
 
 PRESETS = {"cavity16": CAVITY_16, "cavity64": CAVITY_64, "cavity200": CAVITY_200, "paper160": CAVITY_PAPER}

@@ -280,7 +280,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       (p->bc != BOLTZ_BC_CAVITY && p->bc != BOLTZ_BC_PERIODIC) || p->n_pairs < 0 ||
       p->n_pairs >= ((int64_t)1 << 31) || p->sample_group < 0 || p->mix16 > 16 ||
       (!(p->dt > 0.0) && !(p->cfl > 0.0)) ||
-      (p->flags & ~(uint32_t)(BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT)))
+      (p->flags & ~(uint32_t)(BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT | BOLTZ_CONTINUOUS_PAIRS)))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: invalid scalar parameter");
   const bool stretched = p->rv != 0.0 && p->rv != 1.0;
   if (stretched && (!(p->rv > 0.0 && p->rv < 1.0) || (p->nv[0] & 1) || (p->nv[1] & 1) || (p->nv[2] & 1)))
@@ -401,8 +401,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   // Eq. coll8Dim as an importance-sampling estimate is unbiased only if
   // every node the integrand reaches can be drawn: the Maxwellian law on
   // 12-bit fields gives probability zero to the far-tail nodes of wide grids,
-  // so without the uniform component (mix16 = 0) it is refused there.
-  if (p->mix16 == 0)
+  // so without the uniform component (mix16 = 0) it is refused there (the
+  // continuous sampler does not use the node law).
+  if (p->mix16 == 0 && !(p->flags & BOLTZ_CONTINUOUS_PAIRS))
     for (int k = 0; k < 3; ++k)
       for (int i = 0; i < c->n[k]; ++i)
         if (!(c->pphi[k][i] > 0.0)) {
@@ -597,6 +598,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
 
   P.vtab = reinterpret_cast<const double*>(base + o_v);
   P.stretched = stretched ? 1 : 0;
+  P.continuous = (p->flags & BOLTZ_CONTINUOUS_PAIRS) ? 1 : 0;
   P.edgetab = reinterpret_cast<const double*>(base + o_edge);
   P.omtab = reinterpret_cast<const double*>(base + o_om);
   P.rwtab = reinterpret_cast<const double*>(base + o_rw);

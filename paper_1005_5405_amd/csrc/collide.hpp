@@ -121,8 +121,12 @@ struct Pair {
 // is below mix16; k_z = 2 (r3 + 1/2) 2^-32 - 1, azimuth 2 pi (phi + 1/2) 2^-16;
 // v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a;
 // post-collision cells floor((x + a) n / 2a), discard outside the box.
+__device__ Pair sample_pair_continuous(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
+                                       uint32_t m, u32x4* words);
+
 __device__ __forceinline__ Pair sample_pair(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
                                             uint32_t m, u32x4* words) {
+  if (P.continuous) return sample_pair_continuous(P, T, group, step, m, words);
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const u32x4 c = {m, group, step, P.cavity};
   uint32_t k0 = P.key0, k1 = P.key1;
@@ -216,6 +220,85 @@ __device__ __forceinline__ Pair sample_pair(const Params& P, const TablesLDS& T,
   return p;
 }
 
+// Cell of velocity component x on axis k (n cells), -1 outside the box: the
+// floor of the uniform grid or the edge search of stretched cells.
+__device__ __forceinline__ int velocity_cell(const Params& P, const TablesLDS& T, int k, int n, double x) {
+  if (P.stretched) {
+    const double* e = T.edge + (k == 0 ? 0 : (k == 1 ? P.n[0] + 1 : P.n[0] + P.n[1] + 2));
+    return edge_search(e, n, x);
+  }
+  const int t = (int)floor((x + P.a[k]) * P.inv_cell[k]);
+  return (unsigned)t < (unsigned)n ? t : -1;
+}
+
+// The continuous variant (problem flag BOLTZ_CONTINUOUS_PAIRS; the sampling
+// kernel of Sec. 4): v and v1 from the Maxwellian Phi0 (components normal
+// with variance 1/2) by the Box-Muller method, k as in sample_pair, every
+// velocity binned to its cell.  Two Philox blocks: A with counter
+// (m, group, step, cavity), B with (m, group | 2^31, step, cavity); radii
+// sqrt(-ln((w + 1) 2^-32)), angles 2 pi (w + 1/2) 2^-32:
+//   (v_x, v_y) from (A0, A1), (v_z, v1_x) from (A2, A3), (v1_y, v1_z) from
+//   (B0, B1), k_z = 2 (B2 + 1/2) 2^-32 - 1, azimuth 2 pi (B3 + 1/2) 2^-32.
+// Weight q = dt K |v_r . k| / N_t (Phi0 is the sampling density); a pair
+// with any velocity outside the box is discarded, a and b then -1 when v or
+// v1 is outside.  words: block A.
+__device__ Pair sample_pair_continuous(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
+                                       uint32_t m, u32x4* words) {
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  uint32_t k0 = P.key0, k1 = P.key1;
+  asm volatile("" : "+s"(k0), "+s"(k1));
+  const u32x4 A = philox4x32_10(u32x4{m, group, step, P.cavity}, k0, k1);
+  const u32x4 B = philox4x32_10(u32x4{m, group | 0x80000000u, step, P.cavity}, k0, k1);
+  if (words) words[0] = A;
+  double nv[6];
+  const uint32_t rad[3] = {A.x, A.z, B.x}, ang[3] = {A.y, A.w, B.y};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double r = sqrt(neg_ln_unit(((double)rad[i] + 1.0) * 0x1p-32));
+    double cs, sn;
+    cos_sin_2pi(((double)ang[i] + 0.5) * 0x1p-32, cs, sn);
+    nv[2 * i] = r * cs;
+    nv[2 * i + 1] = r * sn;
+  }
+  const double vax = nv[0], vay = nv[1], vaz = nv[2], vbx = nv[3], vby = nv[4], vbz = nv[5];
+  const double kz = 2.0 * (((double)B.z + 0.5) * 0x1p-32) - 1.0;
+  const double s = sqrt((1.0 - kz) * (1.0 + kz));
+  double cp, sp;
+  cos_sin_2pi(((double)B.w + 0.5) * 0x1p-32, cp, sp);
+  const double kx = s * cp, ky = s * sp;
+  const double vrx = vbx - vax, vry = vby - vay, vrz = vbz - vaz;
+  const double alpha = (vrx * kx + vry * ky) + vrz * kz;
+  const double ddx = alpha * kx, ddy = alpha * ky, ddz = alpha * kz;
+  const int ax = velocity_cell(P, T, 0, n0, vax), ay = velocity_cell(P, T, 1, n1, vay),
+            az = velocity_cell(P, T, 2, n2, vaz);
+  const int bx = velocity_cell(P, T, 0, n0, vbx), by = velocity_cell(P, T, 1, n1, vby),
+            bz = velocity_cell(P, T, 2, n2, vbz);
+  const int sx = velocity_cell(P, T, 0, n0, vax + ddx), sy = velocity_cell(P, T, 1, n1, vay + ddy),
+            sz = velocity_cell(P, T, 2, n2, vaz + ddz);
+  const int tx = velocity_cell(P, T, 0, n0, vbx - ddx), ty = velocity_cell(P, T, 1, n1, vby - ddy),
+            tz = velocity_cell(P, T, 2, n2, vbz - ddz);
+  const bool in_a = (ax >= 0) & (ay >= 0) & (az >= 0), in_b = (bx >= 0) & (by >= 0) & (bz >= 0);
+  const bool kept = in_a & in_b & (sx >= 0) & (sy >= 0) & (sz >= 0) & (tx >= 0) & (ty >= 0) & (tz >= 0);
+  Pair p;
+  p.a = in_a ? (ax * n1 + ay) * n2 + az : -1;
+  p.b = in_b ? (bx * n1 + by) * n2 + bz : -1;
+  if (kept) {
+    p.as = (sx * n1 + sy) * n2 + sz;
+    p.bs = (tx * n1 + ty) * n2 + tz;
+    p.q = P.qfac * fabs(alpha);
+    p.ka = p.q * ((T.rw[ax] * T.rw[n0 + ay]) * T.rw[n0 + n1 + az]);
+    p.kb = p.q * ((T.rw[bx] * T.rw[n0 + by]) * T.rw[n0 + n1 + bz]);
+    p.kas = p.q * ((T.rw[sx] * T.rw[n0 + sy]) * T.rw[n0 + n1 + sz]);
+    p.kbs = p.q * ((T.rw[tx] * T.rw[n0 + ty]) * T.rw[n0 + n1 + tz]);
+  } else {
+    p.as = -1;
+    p.bs = -1;
+    p.q = 0.0;
+    p.kas = p.kbs = p.ka = p.kb = 0.0;
+  }
+  return p;
+}
+
 // Test hook kernel: the pairs of (cell, step, m0 + i) from the same sampler.
 __global__ __launch_bounds__(256) void debug_pairs_kernel(Params P, int64_t cell, uint32_t step, int64_t m0,
                                                           int64_t count, int32_t* idx4, double* q,
@@ -249,7 +332,10 @@ __global__ __launch_bounds__(256) void debug_pairs_kernel(Params P, int64_t cell
 __device__ __forceinline__ void sample_pair_record(const Params& P, const TablesLDS& T, uint32_t step,
                                                    uint32_t group, int64_t i, uint2& id, float4& coef) {
   const Pair p = sample_pair(P, T, group, step, (uint32_t)i, nullptr);
-  id.x = (uint32_t)p.a | ((uint32_t)p.b << 16);
+  // a discarded continuous pair may have no cell for v or v1: node 0 then
+  // (its coefficients are zero)
+  const uint32_t a = p.a < 0 ? 0u : (uint32_t)p.a, b = p.b < 0 ? 0u : (uint32_t)p.b;
+  id.x = a | (b << 16);
   id.y = p.as >= 0 ? ((uint32_t)p.as | ((uint32_t)p.bs << 16)) : id.x;
   coef = make_float4((float)p.kas, (float)p.kbs, (float)p.ka, (float)p.kb);
 }

@@ -93,6 +93,26 @@ __device__ __forceinline__ float bw_update(float h0, float h1, float h2, float C
   return h0 - C * (h0 - h1) - c2 * ((h0 - 2.0f * h1) + h2);
 }
 
+// -ln u for u in (0, 1] (the radii of the Box-Muller pairs): u = 2^e m with
+// m in [sqrt(1/2), sqrt(2)) taken from the bits, ln m = ln(1 + t), t = m - 1
+// (exact), by its alternating series to 40 terms (|t|^40 / 40 < 2e-17) in
+// Horner form from the last term, with coefficients folded at compile time;
+// IEEE adds and multiplies only, so the host reproduces every bit.
+__device__ __forceinline__ double neg_ln_unit(double u) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(u);
+  int e = (int)((bits >> 52) & 0x7FFull) - 1023;
+  double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+  if (m > 1.4142135623730951) {
+    m = m * 0.5;
+    e += 1;
+  }
+  const double t = m - 1.0;
+  double p = 0.0;
+#pragma unroll
+  for (int n = 40; n >= 1; --n) p = ((n & 1) ? 1.0 : -1.0) / (double)n + t * p;
+  return -((double)e * 0.6931471805599453094172321 + t * p);
+}
+
 // A 16-byte store that does not keep its line in L2 (outputs read by the
 // next launch only): the halo rows and shared tables that are read again
 // stay cached.

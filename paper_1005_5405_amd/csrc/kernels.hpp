@@ -65,6 +65,8 @@ struct Params {
   float* hyb_ovf;
   // stretched velocity cells (Sec. 5.1): post-collision cells by search
   int stretched;
+  // pairs from the continuous Maxwellian (Box-Muller), binned to cells
+  int continuous;
   const double* edgetab;  // [3][kMaxAxis + 1] cell edges -a .. a per axis
 };
 

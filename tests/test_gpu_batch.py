@@ -50,6 +50,8 @@ PROBLEMS = [
     dict(nx=6, ny=6, nv=(8, 8, 4), vmax=3.0, delta=20.0, eps=0.1, n_pairs=0, sample_group=0),
     dict(nx=9, ny=8, nv=(8, 8, 8), vmax=3.5, delta=5.0, eps=0.1, n_pairs=1000, sample_group=0, bc=1),
     dict(nx=3, ny=2, nv=(24, 24, 24), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, sample_group=0, mix16=4),
+    # pairs from the continuous Maxwellian (Box-Muller), binned to cells
+    dict(nx=7, ny=5, nv=(8, 8, 8), vmax=3.0, delta=5.0, eps=0.1, n_pairs=2000, sample_group=0, flags=4),
 ]
 
 
@@ -178,7 +180,7 @@ def test_batch_problem_matches_oracle(lib, oracle_mod, torch_mod):
     batch.set_step(4)
     batch.step(a, b, walls)
     torch_mod.cuda.synchronize()
-    for i in (0, 2, 4):
+    for i in (0, 2, 4, 6):
         p = PROBLEMS[i]
         o = oracle_mod.Oracle(**p)
         w = walls[i]

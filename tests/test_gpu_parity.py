@@ -482,3 +482,56 @@ def test_stretched_grid_parity(lib, oracle_mod, torch_mod, nv, rv, G):
     rel, wrel = _errs(o, _host(a), href)
     assert rel <= 1e-4 and wrel <= 1e-4, (rel, wrel)
     assert g.read_status() == 0
+
+
+# Continuous pairs (problem flag CONTINUOUS_PAIRS, the sampling kernel of
+# Sec. 4 as printed: v, v1 from the Maxwellian by Box-Muller, binned to their
+# cells): the same pairs bit for bit (cells of all four velocities, -1 for a
+# velocity outside the box, the first Philox block), weights to FP32, and
+# collision and step parity.
+CONT_GRIDS = [dict(nv=12, vmax=4.5), dict(nv=(7, 5, 9), vmax=(3.0, 2.5, 3.5)), dict(nv=20, vmax=3.0, rv=0.945),
+              dict(nv=(20, 18, 20), vmax=3.0, rv=0.97)]
+
+
+@pytest.mark.parametrize("grid", range(len(CONT_GRIDS)))
+def test_continuous_pairs_bit_exact(lib, oracle_mod, torch_mod, grid):
+    kw = dict(nx=5, ny=4, delta=1.0, eps=0.05, n_pairs=6144, sample_group=0, flags=lib.CONTINUOUS_PAIRS,
+              **CONT_GRIDS[grid])
+    _say("continuous pairs", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    for cell, step, m0, count in [(0, 0, 0, 6144), (3, 777, 100000, 20000)]:
+        gi, gq, gw = g.debug_pairs(cell, step, m0, count, words=True)
+        oi, oq, ow = o.debug_pairs(cell, step, m0, count, words=True)
+        np.testing.assert_array_equal(gw, ow)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_allclose(gq, oq, rtol=2e-6, atol=1e-12 * oq.max())
+        assert 0.3 < (oi[:, 2] >= 0).mean() <= 1.0
+
+
+@pytest.mark.parametrize("G", [0, 1])
+def test_continuous_collide_and_step_parity(lib, oracle_mod, torch_mod, G):
+    from paper_1005_5405_amd import inputs
+
+    kw = dict(nx=6, ny=5, nv=20, vmax=3.0, rv=0.945, delta=1.0, eps=0.05, n_pairs=6144, sample_group=G,
+              flags=lib.CONTINUOUS_PAIRS)
+    _say("continuous collide", kw)
+    g, o = _pair(lib, oracle_mod, **kw)
+    h = inputs.random_field(o.shape, seed=61 + G, scale=0.3).astype(np.float32).astype(np.float64)
+    ref = o.collide(h, 11)
+    hs, hout = _dev(torch_mod, h), g.empty()
+    g.collide(hs, hout, 11)
+    torch_mod.cuda.synchronize()
+    rel, wrel = _errs(o, _host(hout), ref)
+    assert rel <= 1e-5 and wrel <= 1e-5, (rel, wrel)
+    # 20 steps of the driven cavity from rest
+    href = np.zeros(o.shape)
+    a, b = g.empty(0.0), g.empty()
+    wo, wg = oracle_mod.Walls(lid_u=0.01), lib.Walls(lid_u=0.01)
+    for n in range(20):
+        href = o.step(href, wo, n)
+        g.step(a, b, wg, n)
+        a, b = b, a
+    torch_mod.cuda.synchronize()
+    rel, wrel = _errs(o, _host(a), href)
+    assert rel <= 1e-4 and wrel <= 1e-4, (rel, wrel)
+    assert g.read_status() == 0

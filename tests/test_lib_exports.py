@@ -46,7 +46,7 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
     assert "null" in L.boltz_last_error(None).decode()
     bad = [dict(nx=1), dict(nv=(0, 4, 4)), dict(nv=(256, 4, 4)), dict(eps=0.0), dict(order=3),
            dict(n_pairs=2**31), dict(dt=1.0), dict(vmax=(0.0, 1.0, 1.0)), dict(sample_group=-1),
-           dict(mix16=17), dict(flags=4),
+           dict(mix16=17), dict(flags=8),
            # the 12-bit Maxwellian law alone cannot draw the outer nodes of 8 cells on [-4, 4]
            dict(mix16=0, vmax=(4.0, 4.0, 4.0)), dict(mix16=0, nv=(20, 20, 20), vmax=(5.0, 5.0, 5.0)),
            # stretched velocity cells need 0 < rv < 1 and even counts
