@@ -46,6 +46,9 @@ BYTES_PER_NODE_KERNEL = 8
 # h_a and h_b and four 64-bit integer atomic adds (Eq. monteCarloInt).
 LDS_READS_PER_PAIR, LDS_ATOMICS_PER_PAIR = 2, 4
 N_CU, CLOCK_HZ = 256, 2.4e9
+# The paper's stream+collide rate on its own workload (GTX 260), derived from its printed streaming and
+# collision flop rates and its flop counts per node and per cell-step; context only.
+PAPER_NODE_UPDATES_PER_S = 1.0e9
 # HBM traffic of the collision launch group measured with rocprofv3 counters
 # (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, summed over the group's
 # kernels), each scaled by what the counter reads for a device copy of the
@@ -510,7 +513,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr, flush=True)
         sys.exit(2)
 
@@ -567,6 +570,22 @@ def main():
                 variants[name]["collide"]["alu_roofline"] = alu_roofline(v)
             del v
             torch.cuda.empty_cache()
+        # the paper's own discretisation and workload (Sec. 5.1): 160 x 160 cells, 20^3 velocities stretched
+        # 0.945 on [-3, 3], delta 1, 6144 pairs from the continuous Maxwellian shared by all cells
+        pre = pkg.PRESETS["paper160"].with_(sample_group=0)
+        print("[bench] variant: paper160_G0", flush=True)
+        v = run(pkg, torch, pre, ks, ws)
+        summ = _summary(v, v["kw"], v["g"], ks)
+        summ["config"].update({"velocity_box": [-pre.vmax, pre.vmax], "rv": pre.rv, "continuous_pairs": True,
+                               "kn": pre.kn, "lid_u": pre.lid_u})
+        summ["paper_context"] = {
+            "node_updates_per_s": PAPER_NODE_UPDATES_PER_S, "ratio": v["value"] / PAPER_NODE_UPDATES_PER_S,
+            "source": "Sec. 5 figures for this workload: streaming ~30 GFLOP/s at 11 flop/node and collision "
+                      "~140 GFLOP/s at 713 728 flop per cell-step combined, on a GeForce GTX 260 (192 cores, "
+                      "111.9 GB/s, FP32 storage); context, not a target"}
+        variants["paper160_G0"] = summ
+        del v
+        torch.cuda.empty_cache()
     if args.full == "auto":
         full = variants.setdefault("full_length", {})
         for key in ("cavity200", "cavity64"):

@@ -52,7 +52,7 @@ typedef enum boltz_status {
   BOLTZ_ENOMEM = -2,       /* device allocation failed                       */
   BOLTZ_EHIP = -3,         /* a HIP runtime call failed                      */
   BOLTZ_ENUMERIC = -4,     /* numerical failure reported by the device       */
-  BOLTZ_EUNSUPPORTED = -5  /* valid request this build does not implement   */
+  BOLTZ_EUNSUPPORTED = -5  /* valid request the library does not implement  */
 } boltz_status;
 
 enum { BOLTZ_BC_CAVITY = 0, BOLTZ_BC_PERIODIC = 1 };

@@ -1,6 +1,6 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
 
-Bars (the benchmark spec tolerances): node indices and Philox words bit-exact; h
+Bars: node indices and Philox words bit-exact; h
 within a relative 1e-5 per step and 1e-4 after 100 steps, measured as
 max|h_gpu - h_ref| / max|h_ref|; the same bar on the Maxwellian-weighted
 error max_j w_j |dh_j| / max_j w_j |h_ref,j|, which is not dominated by the

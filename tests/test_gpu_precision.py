@@ -7,7 +7,7 @@ samples for N steps, each side on its own state; then the moments of
 Sec. 2 (Eqs. densita..sforzi, re-derived in units of V0) and the lid shear D
 of Sec. 5.2 are compared.  Per moment the printed figure is
 max over cells |m_gpu - m_ref| / max over cells |m_ref| (D: |D_gpu - D_ref| /
-|D_ref|), bounded by the benchmark spec's tolerance after N steps.
+|D_ref|), bounded by the tolerance of the step parity tests after 100 steps.
 """
 import sys
 
@@ -67,6 +67,6 @@ def test_moment_errors_fp32_vs_fp64(name):
     row = "  ".join("%s %.2e" % (nm, e) for nm, e in zip(NAMES, err))
     print("[precision] %s after %d steps: %s  D %.2e (D = %.6f)" % (name, case["steps"], row, errD, D_ref),
           flush=True)
-    # the benchmark spec's bound on the state after many steps (1e-4), moment by moment
+    # the bound of the step parity tests after 100 steps (1e-4), moment by moment
     assert np.all(err <= 1e-4), dict(zip(NAMES, err))
     assert errD <= 1e-4, errD

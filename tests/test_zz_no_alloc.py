@@ -8,7 +8,7 @@ boltz_collide of the same problem, whose records live in its context: the
 same records and kernels, and fixed-point sums that do not depend on the
 order of the lanes (the FP32 array of rare far-tail terms aside), so the
 results agree to 1e-6 of the state's largest value, and both match the
-oracle at the benchmark spec's tolerance.
+oracle at the tolerance of the parity tests.
 """
 import sys
 
