@@ -228,10 +228,13 @@ const void* collide_adj_fn(int block, bool table, bool fixed) {
   return nullptr;
 }
 
-const void* collide_fn(int block, bool table, int mode) {
+// table: shared records; else pairs drawn in the kernel by the node law or,
+// with cont, from the continuous Maxwellian
+const void* collide_fn(int block, bool table, int mode, bool cont = false) {
 #define BOLTZ_COLLIDE_FN(B, M)                                                                                 \
   if (block == B && mode == M)                                                                                 \
-    return table ? (const void*)collide_kernel<B, true, M> : (const void*)collide_kernel<B, false, M>;
+    return table ? (const void*)collide_kernel<B, true, M>                                                     \
+                 : (cont ? (const void*)collide_kernel<B, false, M, 2> : (const void*)collide_kernel<B, false, M, 1>);
   BOLTZ_COLLIDE_FN(256, ACC_FIXED)
   BOLTZ_COLLIDE_FN(512, ACC_FIXED)
   BOLTZ_COLLIDE_FN(1024, ACC_FIXED)
@@ -644,7 +647,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   }
   hipError_t ea = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
-    const void* fn = collide_fn(cblock[t], t == 1, cmode);
+    const void* fn = collide_fn(cblock[t], t == 1, cmode, (p->flags & BOLTZ_CONTINUOUS_PAIRS) != 0);
     c->collide_lds[t] = cmode == ACC_HYBRID ? CollideLDS::hyb_bytes(c->nv, hn[t], nsum, t == 0)
                         : cmode == ACC_PART ? CollideLDS::part_bytes(c->nv, hn[t], nsum, t == 0)
                                             : CollideLDS::bytes(c->nv, nsum, cmode, t == 0);
@@ -837,8 +840,11 @@ static void launch_collide_m(boltz_ctx* c, bool table, const float* hs, float* h
   if (table)
     hipLaunchKernelGGL((collide_kernel<B, true, M>), grid, dim3(B), lds, st, P, hs, hout, s32, flags, defect,
                        R.tidx, R.tcoef);
+  else if (P.continuous)
+    hipLaunchKernelGGL((collide_kernel<B, false, M, 2>), grid, dim3(B), lds, st, P, hs, hout, s32, flags, defect,
+                       R.tidx, R.tcoef);
   else
-    hipLaunchKernelGGL((collide_kernel<B, false, M>), grid, dim3(B), lds, st, P, hs, hout, s32, flags, defect,
+    hipLaunchKernelGGL((collide_kernel<B, false, M, 1>), grid, dim3(B), lds, st, P, hs, hout, s32, flags, defect,
                        R.tidx, R.tcoef);
 }
 

@@ -121,12 +121,11 @@ struct Pair {
 // is below mix16; k_z = 2 (r3 + 1/2) 2^-32 - 1, azimuth 2 pi (phi + 1/2) 2^-16;
 // v* = v_a + (v_r.k) k, v1* = v_b - (v_r.k) k with v_r = v_b - v_a;
 // post-collision cells floor((x + a) n / 2a), discard outside the box.
-__device__ Pair sample_pair_continuous(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
-                                       uint32_t m, u32x4* words);
+__device__ __forceinline__ Pair sample_pair_continuous(const Params& P, const TablesLDS& T, uint32_t group,
+                                                       uint32_t step, uint32_t m, u32x4* words);
 
-__device__ __forceinline__ Pair sample_pair(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
-                                            uint32_t m, u32x4* words) {
-  if (P.continuous) return sample_pair_continuous(P, T, group, step, m, words);
+__device__ __forceinline__ Pair sample_pair_node(const Params& P, const TablesLDS& T, uint32_t group,
+                                                 uint32_t step, uint32_t m, u32x4* words) {
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const u32x4 c = {m, group, step, P.cavity};
   uint32_t k0 = P.key0, k1 = P.key1;
@@ -242,8 +241,8 @@ __device__ __forceinline__ int velocity_cell(const Params& P, const TablesLDS& T
 // Weight q = dt K |v_r . k| / N_t (Phi0 is the sampling density); a pair
 // with any velocity outside the box is discarded, a and b then -1 when v or
 // v1 is outside.  words: block A.
-__device__ Pair sample_pair_continuous(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
-                                       uint32_t m, u32x4* words) {
+__device__ __forceinline__ Pair sample_pair_continuous(const Params& P, const TablesLDS& T, uint32_t group,
+                                                       uint32_t step, uint32_t m, u32x4* words) {
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   uint32_t k0 = P.key0, k1 = P.key1;
   asm volatile("" : "+s"(k0), "+s"(k1));
@@ -297,6 +296,15 @@ __device__ Pair sample_pair_continuous(const Params& P, const TablesLDS& T, uint
     p.kas = p.kbs = p.ka = p.kb = 0.0;
   }
   return p;
+}
+
+// The sampler of the problem: the node law, or continuous pairs.  Loops
+// that draw pairs per cell choose once, outside the loop (each loop is then
+// compiled with one sampler's registers).
+__device__ __forceinline__ Pair sample_pair(const Params& P, const TablesLDS& T, uint32_t group, uint32_t step,
+                                            uint32_t m, u32x4* words) {
+  return P.continuous ? sample_pair_continuous(P, T, group, step, m, words)
+                      : sample_pair_node(P, T, group, step, m, words);
 }
 
 // Test hook kernel: the pairs of (cell, step, m0 + i) from the same sampler.
@@ -846,7 +854,9 @@ __device__ __forceinline__ void scatter(float* accf, unsigned long long* acc64, 
 // the accumulators.  TABLE: the pairs are the records of sample_kernel for
 // the cell's group, four per thread and pass so that their loads and
 // gathers are in flight together; else they are drawn here.
-template <int BLOCK, bool TABLE, int MODE, int PU = 4>
+// DRAW (pairs drawn here, not TABLE): 1 the node law, 2 continuous pairs,
+// 0 whichever the problem asks for (chosen once, outside the loop).
+template <int BLOCK, bool TABLE, int MODE, int PU = 4, int DRAW = 0>
 __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, const float* hs, float* accf,
                                           unsigned long long* acc64, uint32_t group, uint32_t step,
                                           const uint2* __restrict__ tidx, const float4* __restrict__ tcoef,
@@ -907,15 +917,21 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
     for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) pass(m, false);
     if (m < nt) pass(m, true);
   } else {
-    for (uint32_t m = tid; m < nt; m += BLOCK) {
-      const Pair p = sample_pair(P, T, group, step, m, nullptr);
-      if (p.as >= 0) {
-        const float ha = hs[p.a], hb = hs[p.b];
-        const float g = (ha + hb) + (epsf * ha) * hb;
-        if (MODE == ACC_HYBRID) scatter_hybrid(*H, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
-        else scatter<MODE>(accf, acc64, lo, n, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+    auto draw = [&](auto&& sampler) {
+      for (uint32_t m = tid; m < nt; m += BLOCK) {
+        const Pair p = sampler(P, T, group, step, m, nullptr);
+        if (p.as >= 0) {
+          const float ha = hs[p.a], hb = hs[p.b];
+          const float g = (ha + hb) + (epsf * ha) * hb;
+          if (MODE == ACC_HYBRID) scatter_hybrid(*H, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+          else scatter<MODE>(accf, acc64, lo, n, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+        }
       }
-    }
+    };
+    if constexpr (DRAW == 1) draw(sample_pair_node);
+    else if constexpr (DRAW == 2) draw(sample_pair_continuous);
+    else if (P.continuous) draw(sample_pair_continuous);
+    else draw(sample_pair_node);
   }
 }
 
@@ -924,7 +940,7 @@ __device__ __forceinline__ void gain_loss(const Params& P, const TablesLDS& T, c
 // memory (a load for the few lanes that need it, issued after every LDS
 // gather of the pass).  BLOCK threads take part, tid = 0 .. BLOCK - 1 (a
 // multiple of 64, so shared record m stays with lane m mod 64).
-template <int BLOCK, bool TABLE, int PU = 4>
+template <int BLOCK, bool TABLE, int PU = 4, int DRAW = 0>
 __device__ __forceinline__ void gain_loss_part(const Params& P, const TablesLDS& T, const Part& Q, uint32_t group,
                                                uint32_t step, const uint2* __restrict__ tidx,
                                                const float4* __restrict__ tcoef, int tid) {
@@ -971,15 +987,21 @@ __device__ __forceinline__ void gain_loss_part(const Params& P, const TablesLDS&
     for (; m + (PU - 1) * BLOCK < nt; m += PU * BLOCK) pass(m, false);
     if (m < nt) pass(m, true);
   } else {
-    for (uint32_t m = tid; m < nt; m += BLOCK) {
-      const Pair p = sample_pair(P, T, group, step, m, nullptr);
-      if (p.as >= 0) {
-        const float ha = Q.inner(p.a) ? Q.tile[p.a - Q.lo] : Q.hg[p.a];
-        const float hb = Q.inner(p.b) ? Q.tile[p.b - Q.lo] : Q.hg[p.b];
-        const float g = (ha + hb) + (epsf * ha) * hb;
-        scatter_part(Q, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+    auto draw = [&](auto&& sampler) {
+      for (uint32_t m = tid; m < nt; m += BLOCK) {
+        const Pair p = sampler(P, T, group, step, m, nullptr);
+        if (p.as >= 0) {
+          const float ha = Q.inner(p.a) ? Q.tile[p.a - Q.lo] : Q.hg[p.a];
+          const float hb = Q.inner(p.b) ? Q.tile[p.b - Q.lo] : Q.hg[p.b];
+          const float g = (ha + hb) + (epsf * ha) * hb;
+          scatter_part(Q, p.a, p.b, p.as, p.bs, p.kas, p.kbs, p.ka, p.kb, g);
+        }
       }
-    }
+    };
+    if constexpr (DRAW == 1) draw(sample_pair_node);
+    else if constexpr (DRAW == 2) draw(sample_pair_continuous);
+    else if (P.continuous) draw(sample_pair_continuous);
+    else draw(sample_pair_node);
   }
 }
 
@@ -1186,7 +1208,7 @@ __device__ __forceinline__ void correction_sums_hybrid(const TablesLDS& T, const
 // more, applies the correction, writes h^{n+1} and clears the accumulators
 // (and the global row when used).  next(): after the pair pass.  Ends with
 // a barrier.
-template <int BLOCK, bool TABLE, class Next>
+template <int BLOCK, bool TABLE, int DRAW = 0, class Next>
 __device__ __forceinline__ void collide_body_hybrid(const Params& P, const TablesLDS& T, float* hs, const Hyb& H,
                                                     double* red, uint32_t group, uint32_t step, uint32_t flags,
                                                     float* dst, double* defect, const uint2* __restrict__ tidx,
@@ -1196,7 +1218,7 @@ __device__ __forceinline__ void collide_body_hybrid(const Params& P, const Table
   const bool correct = !(flags & 1u);
   const bool vec4 = ((n2 & 3) == 0) && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
   const double eps = P.eps;
-  gain_loss<BLOCK, TABLE, ACC_HYBRID>(P, T, hs, nullptr, nullptr, group, step, tidx, tcoef, 0, 0u, &H);
+  gain_loss<BLOCK, TABLE, ACC_HYBRID, 4, DRAW>(P, T, hs, nullptr, nullptr, group, step, tidx, tcoef, 0, 0u, &H);
   __syncthreads();
   next();
   const bool flagged = *H.flag != 0u;
@@ -1412,7 +1434,7 @@ __device__ __forceinline__ void correction_sums_part(const TablesLDS& T, const d
 // One cell in the ACC_PART layout (inner h^s tile in LDS, Q.hg the cell's
 // row, accumulators cleared, a barrier passed): as collide_body_hybrid.
 // vec: rows of whole z quadruples and a 16-byte aligned global row.
-template <int BLOCK, bool TABLE, class Next, int PU = 4>
+template <int BLOCK, bool TABLE, class Next, int PU = 4, int DRAW = 0>
 __device__ __forceinline__ void collide_body_part(const Params& P, const TablesLDS& T, const Part& Q, double* red,
                                                   bool vec, uint32_t group, uint32_t step, uint32_t flags,
                                                   float* dst, double* defect, const uint2* __restrict__ tidx,
@@ -1422,7 +1444,7 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
   const bool correct = !(flags & 1u);
   const bool vec4 = vec && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
   const double eps = P.eps;
-  gain_loss_part<BLOCK, TABLE, PU>(P, T, Q, group, step, tidx, tcoef, tid);
+  gain_loss_part<BLOCK, TABLE, PU, DRAW>(P, T, Q, group, step, tidx, tcoef, tid);
   __syncthreads();
   next();
   const bool flagged = *Q.flag != 0u;
@@ -1540,7 +1562,7 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
 // accumulators (the persistent kernel stages the next cell there); defect:
 // the cell's five values or null.  Ends with a barrier, so the LDS can be
 // refilled.
-template <int BLOCK, bool TABLE, int MODE, int PU = 4, class Next, class Early>
+template <int BLOCK, bool TABLE, int MODE, int PU = 4, int DRAW = 0, class Next, class Early>
 __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T, float* hs, float* accf,
                                              unsigned long long* acc64, double* red, uint32_t group,
                                              uint32_t step, uint32_t flags, float* dst, double* defect,
@@ -1579,7 +1601,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
         for (int i = tid; i < nz; i += BLOCK) z[i] = make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();
       }
-      gain_loss<BLOCK, TABLE, ACC_SPLIT, PU>(P, T, hs, ovf, acc64, group, step, tidx, tcoef, lo, (unsigned)n);
+      gain_loss<BLOCK, TABLE, ACC_SPLIT, PU, DRAW>(P, T, hs, ovf, acc64, group, step, tidx, tcoef, lo, (unsigned)n);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < R; ++k) {
@@ -1600,7 +1622,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
     }
     __syncthreads();
   } else {
-    gain_loss<BLOCK, TABLE, MODE, PU>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
+    gain_loss<BLOCK, TABLE, MODE, PU, DRAW>(P, T, hs, accf, acc64, group, step, tidx, tcoef);
     __syncthreads();
     next();
     // ---- S5 (1): h^c = h^s + increment, stored over the FP32 accumulator;
@@ -1748,7 +1770,7 @@ __device__ __forceinline__ void collide_body(const Params& P, const TablesLDS& T
 // phases of the current one run.  TABLE: the pairs come from the records of
 // sample_kernel (cells of one group share them).  MODE: accumulation of the
 // increments (ACC_FIXED, ACC_SPLIT, ACC_CAS).  h_s may equal h_out.
-template <int BLOCK, bool TABLE, int MODE>
+template <int BLOCK, bool TABLE, int MODE, int DRAW = 1>
 __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* hs_g, float* hout_g, uint32_t step,
                                                         uint32_t flags, double* __restrict__ defect,
                                                         const uint2* __restrict__ tidx,
@@ -1798,7 +1820,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
       __syncthreads();
       const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
       const int64_t next = cell + gridDim.x;
-      collide_body_hybrid<BLOCK, TABLE>(P, T, hs, H, red, group, step, flags, hout_g + cell * nv,
+      collide_body_hybrid<BLOCK, TABLE, DRAW>(P, T, hs, H, red, group, step, flags, hout_g + cell * nv,
                                         defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
                                           if (vec && next < ncells) pre.load(hs_g + next * nv, tid, BLOCK, nv4);
                                         });
@@ -1846,10 +1868,12 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
       __syncthreads();
       const uint32_t group = (P.sample_group == 0) ? 0u : (uint32_t)(cell / P.sample_group);
       const int64_t next = cell + gridDim.x;
-      collide_body_part<BLOCK, TABLE>(P, T, Q, red, vec, group, step, flags, hout_g + cell * nv,
-                                      defect ? defect + cell * 5 : nullptr, tidx, tcoef, [&]() {
-                                        if (pvec && next < ncells) pre.load(hs_g + next * nv + Q.lo, tid, BLOCK, nin4);
-                                      });
+      auto next_part = [&]() {
+        if (pvec && next < ncells) pre.load(hs_g + next * nv + Q.lo, tid, BLOCK, nin4);
+      };
+      collide_body_part<BLOCK, TABLE, decltype(next_part)&, 4, DRAW>(
+          P, T, Q, red, vec, group, step, flags, hout_g + cell * nv, defect ? defect + cell * 5 : nullptr, tidx,
+          tcoef, next_part);
     }
     return;
   }
@@ -1901,7 +1925,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(Params P, const float* h
     // vector-memory waits retire in issue order, so loads issued before the
     // pair loop would stall its first record loads; the node phases wait on
     // no vector load.
-    collide_body<BLOCK, TABLE, MODE>(
+    collide_body<BLOCK, TABLE, MODE, 4, DRAW>(
         P, T, hs, accf, acc64, red, group, step, flags, hout_g + cell * nv, defect ? defect + cell * 5 : nullptr,
         tidx, tcoef,
         [&]() {
