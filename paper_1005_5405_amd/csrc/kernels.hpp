@@ -591,6 +591,15 @@ __host__ __device__ inline int64_t stream4_units(int nx, int ny, int nv, int tx 
   return tiles * groups * cg;
 }
 
+// a / b for 0 <= a < 2^24, 0 < b < 2^12: the float quotient is within one
+// of the truth, then corrected.
+__device__ __forceinline__ int div_small(int a, int b) {
+  int t = (int)((float)a * __frcp_rn((float)b));
+  t -= (t * b > a) ? 1 : 0;
+  t += ((t + 1) * b <= a) ? 1 : 0;
+  return t;
+}
+
 __device__ __forceinline__ float4 ghost4(double nwv, const double* R, double inv_eps) {
   return make_float4(ghost_value(nwv, R[0], inv_eps), ghost_value(nwv, R[1], inv_eps),
                      ghost_value(nwv, R[2], inv_eps), ghost_value(nwv, R[3], inv_eps));
@@ -648,6 +657,10 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
     constexpr int kIter = (AY * AX + kRows - 1) / kRows;     // passes
     const int q = threadIdx.x % Q;
     const int jq = j0 + 4 * q;
+    // the block's corner cell (ix0 - H, iy0 - H) at this thread's velocity
+    // (an address only: corner cells outside the cavity are never read)
+    const int row_stride = nx * nv;
+    const float* corner = hin + ((int64_t)(iy0 - H) * nx + (ix0 - H)) * nv + jq;
     float4 v[kIter];
 #pragma unroll
     for (int it = 0; it < kIter; ++it) {
@@ -658,9 +671,12 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
       if (r < r_lo || r >= r_hi || c < c_lo || c >= c_hi || jq >= nv) continue;
       const int iy = iy0 - H + r, ix = ix0 - H + c;
       const bool inY = iy >= 0 && iy < ny, inX = ix >= 0 && ix < nx;
-      if (periodic || (inX && inY)) {
-        const int64_t base = cell_off(P, periodic ? wrapi(ix, nx) : ix, periodic ? wrapi(iy, ny) : iy);
+      if (periodic) {
+        const int64_t base = cell_off(P, wrapi(ix, nx), wrapi(iy, ny));
         v[it] = *reinterpret_cast<const float4*>(hin + base + jq);
+      } else if (inX && inY) {
+        // 32-bit offset from the tile's corner (r, c >= 0, within 12 rows)
+        v[it] = *reinterpret_cast<const float4*>(corner + (r * row_stride + c * nv));
       } else if (inY || (ORDER == 1 && inX)) {
         int wall;
         double nwv;
@@ -684,8 +700,14 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
   const int jq = j0 + 4 * q;
   const int ix = ix0 + c;
   const bool ok = jq < nv && ix < nx;
-  int jx = 0, jy = 0, jz = 0;
-  if (jq < nv) node_decode(jq, n1, n2, jx, jy, jz);
+  // velocity row (jx, jy) of this thread's quadruple, by a float reciprocal
+  // (exact after one correction for the node counts here, < 2^24)
+  int jx = 0, jy = 0;
+  if (jq < nv) {
+    const int row = div_small(jq, n2);
+    jx = div_small(row, n1);
+    jy = row - jx * n1;
+  }
   const double vx = P.vtab[jx], vy = P.vtab[kMaxAxis + jy];
   const int sx = vx > 0.0 ? 1 : (vx < 0.0 ? -1 : 0);
   const int sy = vy > 0.0 ? 1 : (vy < 0.0 ? -1 : 0);
@@ -719,8 +741,10 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
       const int iy = iy0 + r;
       if (iy >= ny) break;
       const float4 h0 = hx[r + 2];
-      const float4 out = (sy == 0) ? h0
-                         : (sy > 0 ? bw4(h0, hx[r + 1], hx[r], Cy, Cy2) : bw4(h0, hx[r + 3], hx[r + 4], Cy, Cy2));
+      // the upwind neighbours are selected first (the sign of v_y varies
+      // across the lanes of a wavefront), then one update is evaluated
+      const float4 h1 = sy > 0 ? hx[r + 1] : hx[r + 3], h2 = sy > 0 ? hx[r] : hx[r + 4];
+      const float4 out = (sy == 0) ? h0 : bw4(h0, h1, h2, Cy, Cy2);
       nt_store4(dst + cell_off(P, ix, iy), out);
     }
   } else {
