@@ -27,6 +27,7 @@ BC_CAVITY = 0
 BC_PERIODIC = 1
 ALLOW_UNSTABLE = 1
 CONTINUOUS = 4  # pair velocities from the continuous Maxwellian (Box-Muller), binned to cells
+SEQUENTIAL = 8  # collision updates h in place, sample after sample (Alg. 3)
 NO_CORRECTION = 1
 
 

@@ -10,6 +10,7 @@
  *   Sec. 3  Eq. streaming2D                            first-order upwind streaming
  *   Sec. 3  Eqs. coll8Dim, monteCarloInt               MC collision integral
  *   Sec. 3  Eq. collision_step                         explicit (Jacobi) update
+ *   Alg. 3                                             in-place sequential update (option)
  *   Sec. 3  Eqs. rinorm_a, correzione                  conservation correction
  *   Sec. 5.1                                           units, driven cavity, CFL
  * The readings taken where the paper is silent or garbled are listed in the
@@ -321,6 +322,12 @@ static int node_of(const boltz_ref_ctx* c, int jx, int jy, int jz) {
 
 static double node_w(const boltz_ref_ctx* c, int jx, int jy, int jz) {
   return (c->om[0][jx] * c->om[1][jy]) * c->om[2][jz];
+}
+
+static double node_w_flat(const boltz_ref_ctx* c, int j) {
+  int jx, jy, jz;
+  node_idx(c, j, &jx, &jy, &jz);
+  return node_w(c, jx, jy, jz);
 }
 
 /* ------------------------------------------------------------- Philox -- */
@@ -935,25 +942,44 @@ static int collide_cell(const boltz_ref_ctx* c, int64_t cell, int64_t step, uint
   int status = BOLTZ_REF_OK;
   memset(dn, 0, sizeof(double) * nv);
   uint32_t g = group_of(c, cell);
-  /* Eq. monteCarloInt evaluated at the post-stream h (Eq. collision_step):
-   * every sample reads the same h (Jacobi form). */
-  for (int64_t m = 0; m < nt; ++m) {
-    pair_t pr;
-    sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
-    if (!pr.kept) continue;
-    double ha = hs[pr.a], hb = hs[pr.b];
-    double gg = (ha + hb) + (eps * ha) * hb;
-    double qg = pr.q * gg;
-    dn[pr.as] += qg;
-    dn[pr.bs] += qg;
-    dn[pr.a] -= qg;
-    dn[pr.b] -= qg;
-  }
-  /* Eq. collision_step: h^c_j = h^s_j + Delta N_j / (dV_j Phi0_j) */
-  for (int j = 0; j < nv; ++j) {
-    int jx, jy, jz;
-    node_idx(c, j, &jx, &jy, &jz);
-    hc[j] = hs[j] + dn[j] / node_w(c, jx, jy, jz);
+  if (c->p.flags & BOLTZ_REF_SEQUENTIAL) {
+    /* Alg. 3: the samples update h in place in the order m = 0, 1, ...;
+     * each reads the current h at its nodes a and b, then adds its four
+     * increments, at a*, b*, a and b in this order, each to the current
+     * value (where two of the nodes coincide both increments land). */
+    memcpy(hc, hs, sizeof(double) * nv);
+    for (int64_t m = 0; m < nt; ++m) {
+      pair_t pr;
+      sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
+      if (!pr.kept) continue;
+      double ha = hc[pr.a], hb = hc[pr.b];
+      double gg = (ha + hb) + (eps * ha) * hb;
+      double qg = pr.q * gg;
+      hc[pr.as] += qg / node_w_flat(c, pr.as);
+      hc[pr.bs] += qg / node_w_flat(c, pr.bs);
+      hc[pr.a] -= qg / node_w_flat(c, pr.a);
+      hc[pr.b] -= qg / node_w_flat(c, pr.b);
+    }
+    /* the change of the number of particles per node, as in the Jacobi
+     * form: Delta N_j = dV_j Phi0_j (h^c_j - h^s_j) */
+    for (int j = 0; j < nv; ++j) dn[j] = node_w_flat(c, j) * (hc[j] - hs[j]);
+  } else {
+    /* Eq. monteCarloInt evaluated at the post-stream h (Eq. collision_step):
+     * every sample reads the same h (Jacobi form). */
+    for (int64_t m = 0; m < nt; ++m) {
+      pair_t pr;
+      sample_pair(c, g, (uint32_t)step, (uint32_t)m, &pr);
+      if (!pr.kept) continue;
+      double ha = hs[pr.a], hb = hs[pr.b];
+      double gg = (ha + hb) + (eps * ha) * hb;
+      double qg = pr.q * gg;
+      dn[pr.as] += qg;
+      dn[pr.bs] += qg;
+      dn[pr.a] -= qg;
+      dn[pr.b] -= qg;
+    }
+    /* Eq. collision_step: h^c_j = h^s_j + Delta N_j / (dV_j Phi0_j) */
+    for (int j = 0; j < nv; ++j) hc[j] = hs[j] + dn[j] / node_w_flat(c, j);
   }
   if (flags & BOLTZ_REF_NO_CORRECTION) {
     memcpy(ho, hc, sizeof(double) * nv);
@@ -1475,6 +1501,8 @@ static void collide_cell_adj(const boltz_ref_ctx* c, int64_t cell, int64_t step,
 int boltz_ref_collide_adjoint(const boltz_ref_ctx* c, const double* h_s, const double* lam_out,
                               double* lam_s, int64_t step, uint32_t flags) {
   if (!c || !h_s || !lam_out || !lam_s) return BOLTZ_REF_EINVAL;
+  /* the adjoint follows the Jacobi form of Eq. collision_step only */
+  if (c->p.flags & BOLTZ_REF_SEQUENTIAL) return BOLTZ_REF_EINVAL;
   const int nv = c->nv;
 #pragma omp parallel
   {
@@ -1495,6 +1523,7 @@ int boltz_ref_collide_adjoint(const boltz_ref_ctx* c, const double* h_s, const d
 int boltz_ref_step_adjoint(const boltz_ref_ctx* c, const double* h_in, const double* lam_out,
                            double* lam_in, double* grad, const boltz_ref_walls* walls, int64_t step) {
   if (!c || !h_in || !lam_out || !lam_in || lam_out == lam_in) return BOLTZ_REF_EINVAL;
+  if (c->p.flags & BOLTZ_REF_SEQUENTIAL) return BOLTZ_REF_EINVAL;
   const size_t n = (size_t)c->ncells * c->nv;
   double* hs = (double*)malloc(sizeof(double) * n);
   double* lam_s = (double*)malloc(sizeof(double) * n);

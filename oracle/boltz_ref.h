@@ -39,8 +39,11 @@ enum { BOLTZ_REF_BC_CAVITY = 0, BOLTZ_REF_BC_PERIODIC = 1 };
 /* problem flags */
 /* BOLTZ_REF_CONTINUOUS: the pre-collision velocities are drawn from the
  * continuous Maxwellian by the Box-Muller method and binned to their cells
- * (the sampling kernel of Sec. 4), instead of the node law. */
-enum { BOLTZ_REF_ALLOW_UNSTABLE = 1u, BOLTZ_REF_CONTINUOUS = 4u };
+ * (the sampling kernel of Sec. 4), instead of the node law.
+ * BOLTZ_REF_SEQUENTIAL: the collision updates h in place, sample after
+ * sample (Alg. 3), instead of evaluating every sample at the post-stream h
+ * (Eq. collision_step). */
+enum { BOLTZ_REF_ALLOW_UNSTABLE = 1u, BOLTZ_REF_CONTINUOUS = 4u, BOLTZ_REF_SEQUENTIAL = 8u };
 /* collide flags */
 enum { BOLTZ_REF_NO_CORRECTION = 1u };
 
@@ -59,6 +62,7 @@ typedef struct boltz_ref_problem {
   uint64_t seed;         /* Philox key                                      */
   uint32_t cavity_id;    /* fourth Philox counter word                      */
   uint32_t flags;        /* BOLTZ_REF_ALLOW_UNSTABLE | BOLTZ_REF_CONTINUOUS */
+                         /* | BOLTZ_REF_SEQUENTIAL                          */
   uint32_t mix16;        /* uniform share of the pair law, in 1/16 (0..16); */
                          /* 0 only on grids where every node has a positive */
                          /* Maxwellian-law probability (else EINVAL)        */
