@@ -67,7 +67,7 @@ TRAFFIC = {
 # collision kernel of the 64x64 cavity, rocprofv3 --pmc SQ_INSTS_VALU; valid
 # for the recorded kernel-source SHA-256.
 VALU_G1 = {"sha256": "f0b03e3eea724cf9600936d72b9c2231ba81870e37e8d201562ce216f7ded512", "valu_insts_per_dispatch": 4.98797e8}
-KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp")
+KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp", "sequential.hpp")
 
 
 def kernel_sources_sha256() -> str:
@@ -82,7 +82,7 @@ def kernel_sources_sha256() -> str:
 
 def _workload_key(kw) -> str:
     nv = kw["nv"] if isinstance(kw["nv"], int) else kw["nv"][0]
-    return "%dx%d_%d_G%d" % (kw["nx"], kw["ny"], nv, kw["sample_group"])
+    return "%dx%d_%d_G%d%s" % (kw["nx"], kw["ny"], nv, kw["sample_group"], "_seq" if kw.get("flags", 0) & 8 else "")
 
 
 def measured_traffic(kw):
@@ -457,15 +457,23 @@ def _roofline(r, kw, g):
     nodes, t_c = r["nodes"], r["t_collide"]
     coll_gbs = BYTES_PER_NODE_KERNEL * nodes / t_c / 1e9
     pair_cells = g.ncells * g.n_pairs
-    return {"kernel": "collide_kernel + sample_kernel" if kw["sample_group"] != 1 else "collide_kernel",
+    seq = bool(kw.get("flags", 0) & 8)
+    kernel = ("sample_kernel + seq_level_kernel + seq_collide_kernel" if seq
+              else "collide_kernel + sample_kernel" if kw["sample_group"] != 1 else "collide_kernel")
+    note = ("8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision launch group; "
+            "its in-place pair loop (4 LDS reads and 4 LDS writes per record, one level of the shared records "
+            "at a time, latency-bound at one wavefront per cell), not HBM, sets its time" if seq else
+            "8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision "
+            "launch group; its pair loop (2 LDS gathers + 4 LDS integer atomic adds per pair and "
+            "cell), not HBM, sets its time")
+    return {"kernel": kernel,
             "bound": "hbm", "achieved": coll_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": coll_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kw), "avg_ms": t_c * 1e3,
             "algorithmic_bytes_per_launch": BYTES_PER_NODE_KERNEL * nodes,
             "pair_cells_per_s_in_kernel": pair_cells / t_c,
-            "lds_atomic_lane_ops_per_clk_per_cu": LDS_ATOMICS_PER_PAIR * pair_cells / t_c / (N_CU * CLOCK_HZ),
-            "note": "8 B/node (FP32 h read + write) per launch over the HIP-event average of the collision "
-                    "launch group; its pair loop (2 LDS gathers + 4 LDS integer atomic adds per pair and "
-                    "cell), not HBM, sets its time"}
+            "lds_atomic_lane_ops_per_clk_per_cu": (None if seq else
+                                                   LDS_ATOMICS_PER_PAIR * pair_cells / t_c / (N_CU * CLOCK_HZ)),
+            "note": note}
 
 
 def _stream_kernels(r):
@@ -492,6 +500,8 @@ def main():
     ap.add_argument("--config", default="cavity200")
     ap.add_argument("--sample-group", type=int, default=0, help="cells sharing a pair stream (0 = all)")
     ap.add_argument("--order", type=int, default=None)
+    ap.add_argument("--sequential", action="store_true",
+                    help="the in-place sequential collision of Alg. 3 instead of the Jacobi form")
     ap.add_argument("--variant", choices=["auto", "skip"], default="auto",
                     help="also time the 64x64 cavity (shared samples, per-cell samples G = 1, order 1)")
     ap.add_argument("--full", choices=["auto", "skip"], default="auto",
@@ -524,6 +534,8 @@ def main():
     over = {"sample_group": args.sample_group}
     if args.order is not None:
         over["order"] = args.order
+    if args.sequential:
+        over["sequential"] = True
     preset = pkg.PRESETS[args.config].with_(**over)
     print("[bench] %s: G=%d, warm-up %d + %d timed steps" % (args.config, args.sample_group, args.warmup,
                                                            args.steps), flush=True)
@@ -546,7 +558,8 @@ def main():
                        "velocity_box": [-preset.vmax, preset.vmax], "pairs_per_cell": g.n_pairs,
                        "sample_group": kw["sample_group"], "order": g.order, "kn": preset.kn,
                        "lid_u": ("%g sin(%g t)" % (preset.lid_u, preset.lid_omega)) if preset.lid_omega > 0
-                       else preset.lid_u, "cfl": preset.cfl, "mix16": kw["mix16"], "parallelism": "single GPU"},
+                       else preset.lid_u, "cfl": preset.cfl, "mix16": kw["mix16"], "parallelism": "single GPU",
+                       "sequential_update": bool(args.sequential)},
             "pairs_per_s": r["pairs_per_s"],
             "pairs_per_s_meaning": "pair-cell evaluations (cells x N_t per step); with G = 0 every cell "
                                    "evaluates the same N_t drawn pairs",
@@ -586,6 +599,15 @@ def main():
         variants["paper160_G0"] = summ
         del v
         torch.cuda.empty_cache()
+        # the in-place sequential collision of Alg. 3 on the same two workloads
+        for name, pre in (("cavity64_G0_sequential", c64.with_(sample_group=0, sequential=True)),
+                          ("paper160_G0_sequential", pkg.PRESETS["paper160"].with_(sample_group=0, sequential=True))):
+            print("[bench] variant: %s" % name, flush=True)
+            v = run(pkg, torch, pre, ks, ws)
+            variants[name] = _summary(v, v["kw"], v["g"], ks)
+            variants[name]["config"]["sequential_update"] = True
+            del v
+            torch.cuda.empty_cache()
     if args.full == "auto":
         full = variants.setdefault("full_length", {})
         for key in ("cavity200", "cavity64"):

@@ -61,11 +61,14 @@ enum { BOLTZ_BC_CAVITY = 0, BOLTZ_BC_PERIODIC = 1 };
 enum { BOLTZ_ALLOW_UNSTABLE = 1u,    /* accept a dt above the Courant limit  */
        BOLTZ_WITH_ADJOINT = 2u,      /* also allocate the scratch of         */
                                      /* boltz_step_adjoint                   */
-       BOLTZ_CONTINUOUS_PAIRS = 4u };/* draw v, v1 of every pair from the    */
+       BOLTZ_CONTINUOUS_PAIRS = 4u,  /* draw v, v1 of every pair from the    */
                                      /* continuous Maxwellian (Box-Muller)   */
                                      /* and bin them to cells (Sec. 4's      */
                                      /* sampling kernel) instead of the node */
                                      /* law; see boltz_collide               */
+       BOLTZ_SEQUENTIAL_UPDATE = 8u };/* collide in place, sample after      */
+                                     /* sample (Alg. 3), instead of the      */
+                                     /* Jacobi form; see boltz_collide       */
 /* boltz_collide flags */
 enum { BOLTZ_NO_CORRECTION = 1u };   /* skip S5 (raw Monte Carlo update)     */
 /* device status bits (boltz_read_status) */
@@ -89,7 +92,7 @@ typedef struct boltz_problem {
   uint64_t seed;         /* Philox4x32-10 key (low word, high word)          */
   uint32_t cavity_id;    /* fourth Philox counter word                       */
   uint32_t flags;        /* BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT |
-                            BOLTZ_CONTINUOUS_PAIRS                           */
+                            BOLTZ_CONTINUOUS_PAIRS | BOLTZ_SEQUENTIAL_UPDATE */
   uint32_t mix16;        /* uniform share beta = mix16/16 of the node-pair   */
                          /* law, 0..16.  0 = nodes from the 12-bit discrete  */
                          /* Maxwellian alone: accepted only on grids where   */
@@ -133,10 +136,12 @@ typedef struct boltz_info {
  *   HYBRID  64-bit fixed point for the central x-slabs, FP32 for the rest
  *   PART    64-bit fixed point for every node, the h tile of the central
  *           x-slabs in LDS and the outer slabs read from global memory
+ *   SEQUENTIAL  BOLTZ_SEQUENTIAL_UPDATE: the FP32 h tile updated in place,
+ *           one wavefront per cell
  * The environment variable BOLTZ_COLLIDE_LAYOUT=hybrid, read by
  * boltz_create, selects HYBRID over PART where both fit. */
 enum { BOLTZ_LAYOUT_CAS = 0, BOLTZ_LAYOUT_FIXED = 1, BOLTZ_LAYOUT_SPLIT = 2, BOLTZ_LAYOUT_HYBRID = 3,
-       BOLTZ_LAYOUT_PART = 4 };
+       BOLTZ_LAYOUT_PART = 4, BOLTZ_LAYOUT_SEQUENTIAL = 5 };
 
 typedef struct boltz_ctx boltz_ctx;
 
@@ -184,6 +189,14 @@ int boltz_stream(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_wa
  * and (m, group | 2^31, step, cavity)), h taken in the cells that contain
  * them, weight dt K |v_r . k| / N_t; a pair with any velocity outside the
  * box is discarded (it still counts in N_t).
+ * With BOLTZ_SEQUENTIAL_UPDATE (problem flag; shared samples only, i.e.
+ * sample_group != 1, else boltz_create returns EINVAL) the samples update h
+ * in place in the order m = 0, 1, ... as in Alg. 3: each reads the current
+ * h at a and b and adds its four increments before the next one is read
+ * (where two of its nodes coincide, both increments land).  The cell's h is
+ * kept in FP32 during the loop (the paper's precision), the correction
+ * restores the moments of h_s as above.  Results do not depend on the
+ * launch (the order of every node's updates is the sample order).
  * h_s may equal h_out (in place); otherwise they must not overlap.
  * flags: BOLTZ_NO_CORRECTION.  defect: NULL or ncells*5 FP64 device buffer
  * receiving sum_j w_j psi_k (F_out - F_s) of the stored FP32 values. */
@@ -200,6 +213,8 @@ int boltz_collide(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, 
  * beyond that size.  The call allocates nothing and frees nothing.  Every
  * call on one GPU shares that GPU's array: calls that overlap on one GPU
  * (any context, any stream) race and must be serialised by the caller.
+ * With BOLTZ_SEQUENTIAL_UPDATE the array also holds one level byte per
+ * record and one int per 64 records (about 25 B per record in all).
  * With per-cell samples (sample_group == 1) it uses no scratch. */
 int boltz_collide_noalloc(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, uint32_t flags,
                           double* defect, void* stream);

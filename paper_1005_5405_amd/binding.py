@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BC_CAVITY, BC_PERIODIC = 0, 1
 ALLOW_UNSTABLE, WITH_ADJOINT = 1, 2
 CONTINUOUS_PAIRS = 4  # pair velocities from the continuous Maxwellian (Box-Muller), binned to cells
+SEQUENTIAL_UPDATE = 8  # collision in place, sample after sample (Alg. 3); shared samples only
 NO_CORRECTION = 1
 STATUS_NOT_SPD, STATUS_NONFINITE = 1, 2
 
@@ -67,7 +68,7 @@ class _Info(ctypes.Structure):
 
 
 # LDS layouts of the collision kernel (boltz_info.collide_layout)
-LAYOUTS = {0: "cas", 1: "fixed", 2: "split", 3: "hybrid", 4: "part"}
+LAYOUTS = {0: "cas", 1: "fixed", 2: "split", 3: "hybrid", 4: "part", 5: "sequential"}
 
 
 EXPORTS = ("boltz_create", "boltz_destroy", "boltz_query", "boltz_last_error", "boltz_stream",

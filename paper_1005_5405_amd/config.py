@@ -34,6 +34,7 @@ class Preset:
     moments_every: int = 0
     rv: float = 0.0              # velocity cells stretched in this ratio (0: uniform)
     continuous: bool = False     # pairs from the continuous Maxwellian (Box-Muller), binned to cells
+    sequential: bool = False     # collision in place, sample after sample (Alg. 3)
 
     @property
     def delta(self) -> float:
@@ -43,8 +44,9 @@ class Preset:
         kw = dict(nx=self.nx, ny=self.ny, nv=self.nv, vmax=self.vmax, delta=self.delta, eps=self.eps,
                   n_pairs=self.n_pairs, cfl=self.cfl, order=self.order, seed=self.seed,
                   sample_group=self.sample_group, mix16=self.mix16, rv=self.rv)
-        if self.continuous:
-            kw["flags"] = 4  # BOLTZ_CONTINUOUS_PAIRS
+        flags = (4 if self.continuous else 0) | (8 if self.sequential else 0)
+        if flags:
+            kw["flags"] = flags  # BOLTZ_CONTINUOUS_PAIRS | BOLTZ_SEQUENTIAL_UPDATE
         kw.update(over)
         return kw
 

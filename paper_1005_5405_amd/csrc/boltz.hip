@@ -14,6 +14,7 @@
 #include "boltz.h"
 #include "adjoint.hpp"
 #include "kernels.hpp"
+#include "sequential.hpp"
 
 using namespace boltz;
 
@@ -70,6 +71,14 @@ struct boltz_ctx {
   uint2* sidx = nullptr;        // the sampler's output (ACC_SPLIT: sorted into tidx, tcoef)
   float4* scoef = nullptr;
   unsigned char* scratch = nullptr;  // this device's copy of the static record scratch
+  // in-place sequential collision (BOLTZ_SEQUENTIAL_UPDATE): level of every
+  // shared record, largest level of every group of 64 records, node
+  // velocities and weights of the three axes (FP64), dynamic LDS
+  bool seq = false;
+  uint8_t* tlev = nullptr;
+  int* tgmax = nullptr;
+  double* vom = nullptr;
+  size_t seq_lds = 0;
   std::string err;
 };
 
@@ -89,6 +98,8 @@ struct RecordTables {
   float4* tcoef;
   uint2* sidx;
   float4* scoef;
+  uint8_t* lev = nullptr;  // sequential collision: record levels and group maxima
+  int* gmax = nullptr;
 };
 
 namespace {
@@ -283,8 +294,18 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       (p->bc != BOLTZ_BC_CAVITY && p->bc != BOLTZ_BC_PERIODIC) || p->n_pairs < 0 ||
       p->n_pairs >= ((int64_t)1 << 31) || p->sample_group < 0 || p->mix16 > 16 ||
       (!(p->dt > 0.0) && !(p->cfl > 0.0)) ||
-      (p->flags & ~(uint32_t)(BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT | BOLTZ_CONTINUOUS_PAIRS)))
+      (p->flags & ~(uint32_t)(BOLTZ_ALLOW_UNSTABLE | BOLTZ_WITH_ADJOINT | BOLTZ_CONTINUOUS_PAIRS |
+                              BOLTZ_SEQUENTIAL_UPDATE)))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: invalid scalar parameter");
+  const bool seq = (p->flags & BOLTZ_SEQUENTIAL_UPDATE) != 0;
+  if (seq && p->sample_group == 1)
+    return fail(nullptr, BOLTZ_EINVAL,
+                "boltz_create: the sequential update needs shared samples (sample_group 0 or >= 2): its "
+                "record order is worked out once per sample group and step");
+  if (seq && (p->flags & BOLTZ_WITH_ADJOINT))
+    return fail(nullptr, BOLTZ_EINVAL, "boltz_create: the adjoint follows the Jacobi collision only");
+  if (seq && (int64_t)p->nx * p->ny > 0x7fffffffLL)
+    return fail(nullptr, BOLTZ_EINVAL, "boltz_create: the sequential collision takes at most 2^31 - 1 cells");
   const bool stretched = p->rv != 0.0 && p->rv != 1.0;
   if (stretched && (!(p->rv > 0.0 && p->rv < 1.0) || (p->nv[0] & 1) || (p->nv[1] & 1) || (p->nv[2] & 1)))
     return fail(nullptr, BOLTZ_EINVAL,
@@ -293,12 +314,17 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const int nsum = p->nv[0] + p->nv[1] + p->nv[2];
   int cmode = ACC_FIXED;
   int cblock[2] = {256, 256};
-  if (nvt > (1 << 20) || !pick_collide((int)nvt, nsum, cmode, cblock))
+  if (nvt > (1 << 20) || (!pick_collide((int)nvt, nsum, cmode, cblock) && !seq))
     return fail(nullptr, BOLTZ_EUNSUPPORTED,
                 "boltz_create: the per-cell h and increment tiles of this velocity grid exceed the 160 KB LDS");
   // a single problem whose grid is too large for the 64-bit layout collides
   // in one pass with ACC_PART, else ACC_HYBRID; batches keep the classic
-  // layouts
+  // layouts.  The sequential collision has a kernel of its own (the Jacobi
+  // set-up below is skipped).
+  if (seq) {
+    cmode = ACC_FIXED;
+    cblock[0] = cblock[1] = 256;
+  }
   const int bmode = cmode;
   int hlo[2] = {0, 0}, hn[2] = {0, 0};
   if (cmode != ACC_FIXED && nvt <= 65535) {
@@ -320,6 +346,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   if (ngroups > 65535 || nvt > 65535)
     return fail(nullptr, BOLTZ_EINVAL,
                 "boltz_create: shared-sample mode needs at most 65535 groups and 65535 velocity nodes");
+  if (seq && SeqLDS::bytes((int)nvt, nsum) > kLdsBytes)
+    return fail(nullptr, BOLTZ_EUNSUPPORTED,
+                "boltz_create: the h tile of the sequential collision exceeds the 160 KB LDS");
 
   boltz_ctx* c = new (std::nothrow) boltz_ctx;
   if (!c) return fail(nullptr, BOLTZ_ENOMEM, "boltz_create: out of host memory");
@@ -538,6 +567,20 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t nodes = (size_t)c->ncells * (size_t)c->nv;
   const size_t o_adj_hs = off; off = align256(off + (with_adj ? nodes * 4 : 0));
   const size_t o_adj_lam = off; off = align256(off + (with_adj ? nodes * 8 : 0));
+  const size_t nrec = seq ? (size_t)ngroups * (size_t)p->n_pairs : 0;
+  const size_t ngr64 = seq ? (size_t)ngroups * (size_t)((p->n_pairs + kSeqGroup - 1) / kSeqGroup) : 0;
+  const size_t o_tlev = off; off = align256(off + nrec);
+  const size_t o_tgmax = off; off = align256(off + ngr64 * 4);
+  std::vector<double> vom(2 * (size_t)nsum, 0.0);
+  {
+    size_t i = 0;
+    for (int k = 0; k < 3; ++k)
+      for (int j = 0; j < c->n[k]; ++j, ++i) {
+        vom[i] = c->v[k][j];
+        vom[nsum + i] = c->om[k][j];
+      }
+  }
+  const size_t o_vom = off; off = align256(off + vom.size() * 8);
   (void)hipGetDevice(&c->device);
   hipError_t e = hipMalloc(&c->dmem, off);
   if (e != hipSuccess) {
@@ -552,7 +595,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       {o_rw, rwtab.data(), rwtab.size() * 8}, {o_nq, nqtab.data(), nqtab.size() * 16},
       {o_icdf, icdf.data(), icdf.size()}, {o_m0, m0.data(), m0.size() * 8},
       {o_zmom, zmom.data(), zmom.size() * 8},
-      {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4}};
+      {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4},
+      {o_vom, vom.data(), vom.size() * 8}};
   for (const Cp& cp : cps) {
     e = hipMemcpy(base + cp.o, cp.src, cp.n, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -631,6 +675,11 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->gpart = reinterpret_cast<double*>(base + o_gpart);
   c->adj_hs = with_adj ? reinterpret_cast<float*>(base + o_adj_hs) : nullptr;
   c->adj_lam = with_adj ? reinterpret_cast<double*>(base + o_adj_lam) : nullptr;
+  c->seq = seq;
+  c->tlev = seq ? reinterpret_cast<uint8_t*>(base + o_tlev) : nullptr;
+  c->tgmax = seq ? reinterpret_cast<int*>(base + o_tgmax) : nullptr;
+  c->vom = reinterpret_cast<double*>(base + o_vom);
+  c->seq_lds = SeqLDS::bytes(c->nv, nsum);
   c->collide_block[0] = cblock[0];
   c->collide_block[1] = cblock[1];
   c->collide_mode = cmode;
@@ -646,7 +695,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     else (void)hipGetLastError();
   }
   hipError_t ea = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-  for (int t = 0; t < 2 && ea == hipSuccess; ++t) {
+  for (int t = 0; t < 2 && ea == hipSuccess && !seq; ++t) {
     const void* fn = collide_fn(cblock[t], t == 1, cmode, (p->flags & BOLTZ_CONTINUOUS_PAIRS) != 0);
     c->collide_lds[t] = cmode == ACC_HYBRID ? CollideLDS::hyb_bytes(c->nv, hn[t], nsum, t == 0)
                         : cmode == ACC_PART ? CollideLDS::part_bytes(c->nv, hn[t], nsum, t == 0)
@@ -663,7 +712,15 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     if (hyb_rows) cap = std::min<int64_t>(cap, hyb_rows);
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
   }
-  c->adj_supported = ea == hipSuccess && pick_adjoint(c->nv, nsum, c->adj_block, c->adj_fixed);
+  if (ea == hipSuccess && seq) {
+    ea = hipFuncSetAttribute((const void*)seq_collide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kLdsBytes);
+    int per_cu = 0;
+    if (ea == hipSuccess)
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)seq_collide_kernel, 64, c->seq_lds);
+    if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
+  }
+  c->adj_supported = ea == hipSuccess && !seq && pick_adjoint(c->nv, nsum, c->adj_block, c->adj_fixed);
   for (int t = 0; t < 2 && ea == hipSuccess && c->adj_supported; ++t) {
     // the fixed-point layout when the runtime accepts its LDS size, else FP64 sums
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -701,9 +758,10 @@ int boltz_query(const boltz_ctx* c, boltz_info* out) {
   out->W = c->W;
   out->qfac = c->qfac;
   out->device_bytes = (int64_t)c->dbytes;
-  out->collide_layout = c->collide_mode;
-  out->collide_block = c->collide_block[1];
-  out->collide_lds_nodes = (c->collide_mode == ACC_HYBRID || c->collide_mode == ACC_PART) ? c->hyb_n[1]
+  out->collide_layout = c->seq ? BOLTZ_LAYOUT_SEQUENTIAL : c->collide_mode;
+  out->collide_block = c->seq ? 64 : c->collide_block[1];
+  out->collide_lds_nodes = c->seq ? (int)c->nv
+                           : (c->collide_mode == ACC_HYBRID || c->collide_mode == ACC_PART) ? c->hyb_n[1]
                            : (c->collide_mode == ACC_SPLIT ? (int)((c->nv + 1) / 2) : (int)c->nv);
   out->reserved = 0;
   return BOLTZ_OK;
@@ -781,7 +839,7 @@ static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const b
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     hipLaunchKernelGGL(kern_s, dim3((unsigned)(8 * per_xcd + nb * c->ngroups)), dim3(kWallBlock),
                        TablesLDS::bytes(nsum, true), st, c->P, h, nface, per_xcd, nb, (uint32_t)sample_step,
-                       c->tidx, c->tcoef);
+                       c->tidx, c->tcoef, c->seq ? 0 : 1);
   };
   if (c->p.order == 2) {
     launch(wall_kernel<0>, 2 * c->p.ny);
@@ -825,7 +883,8 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
 
 static RecordTables own_tables(const boltz_ctx* c) {
   const bool split = c->collide_mode == ACC_SPLIT;
-  return RecordTables{c->tidx, c->tcoef, split ? c->sidx : c->tidx, split ? c->scoef : c->tcoef};
+  return RecordTables{c->tidx, c->tcoef, split ? c->sidx : c->tidx, split ? c->scoef : c->tcoef, c->tlev,
+                      c->tgmax};
 }
 
 extern "C++" template <int B, int M>
@@ -870,8 +929,10 @@ static void launch_samples(boltz_ctx* c, uint32_t s32, hipStream_t st, const Rec
   if (c->ngroups > 0 && c->p.n_pairs > 0) {
     const int nsum = c->n[0] + c->n[1] + c->n[2];
     const dim3 grid((unsigned)((c->p.n_pairs + kSampleBlock - 1) / kSampleBlock), (unsigned)c->ngroups);
+    // records in sample order for the sequential collision, else dealt to
+    // lanes where no sort follows
     hipLaunchKernelGGL(sample_kernel, grid, dim3(kSampleBlock), TablesLDS::bytes(nsum, true), st, c->P, s32, R.sidx,
-                       R.scoef, R.sidx == R.tidx ? 1 : 0);
+                       R.scoef, (R.sidx == R.tidx && !c->seq) ? 1 : 0);
     if (R.sidx != R.tidx)
       hipLaunchKernelGGL(split_sort_kernel, dim3((unsigned)c->ngroups), dim3(kSortBlock), 0, st, R.sidx, R.scoef,
                          R.tidx, R.tcoef, (int64_t)c->p.n_pairs, (unsigned)CollideLDS::half(c->nv));
@@ -886,6 +947,18 @@ static int launch_collide_r(boltz_ctx* c, const float* hs, float* hout, int64_t 
   const uint32_t s32 = (uint32_t)step;
   const bool table = c->ngroups > 0;
   if (!drawn) launch_samples(c, s32, st, R);
+  if (c->seq) {
+    // Alg. 3: the record levels of every sample group, then one wavefront
+    // per cell
+    const int64_t ngr = (c->p.n_pairs + kSeqGroup - 1) / kSeqGroup;
+    if (ngr > 0)
+      hipLaunchKernelGGL(seq_level_kernel, dim3((unsigned)ngr, (unsigned)c->ngroups), dim3(64), 0, st, R.tidx,
+                         R.tcoef, (int64_t)c->p.n_pairs, R.lev, R.gmax);
+    hipLaunchKernelGGL(seq_collide_kernel, dim3((unsigned)c->ncells), dim3(64), c->seq_lds, st, c->P, c->vom, hs,
+                       hout, flags, defect, R.tidx, R.tcoef, R.lev, R.gmax);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "seq_collide_kernel launch");
+  }
   switch (c->collide_block[table ? 1 : 0]) {
     case 256: launch_collide_b<256>(c, table, hs, hout, s32, flags, defect, st, R); break;
     case 512: launch_collide_b<512>(c, table, hs, hout, s32, flags, defect, st, R); break;
@@ -954,7 +1027,10 @@ int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t 
     const size_t n = (size_t)c->ngroups * (size_t)c->p.n_pairs;
     const bool split = c->collide_mode == ACC_SPLIT;
     const size_t one = align256(n * sizeof(uint2)) + n * sizeof(float4);
-    const size_t need = split ? align256(one) + one : one;
+    // the sequential collision also keeps a level per record and the
+    // largest level of every group of 64 records
+    const size_t ngr64 = (size_t)c->ngroups * (size_t)((c->p.n_pairs + kSeqGroup - 1) / kSeqGroup);
+    const size_t need = split ? align256(one) + one : (c->seq ? align256(one) + align256(n) + ngr64 * 4 : one);
     if (need > kScratchBytes)
       return fail(c, BOLTZ_EINVAL,
                   "boltz_collide_noalloc: " + std::to_string(need) + " bytes of shared-sample records exceed the " +
@@ -969,6 +1045,10 @@ int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t 
       unsigned char* q = p + align256(one);
       R.sidx = reinterpret_cast<uint2*>(q);
       R.scoef = reinterpret_cast<float4*>(q + align256(n * sizeof(uint2)));
+    }
+    if (c->seq) {
+      R.lev = p + align256(one);
+      R.gmax = reinterpret_cast<int*>(p + align256(one) + align256(n));
     }
   }
   return launch_collide_r(c, h_s, h_out, step, flags, defect, static_cast<hipStream_t>(stream), false, R);
@@ -1327,6 +1407,8 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
       return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batched streaming needs nv[2] % 4 == 0");
     if ((int64_t)problems[i].nx * problems[i].ny >= ((int64_t)1 << 31))
       return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: too many cells in one problem");
+    if (problems[i].flags & BOLTZ_SEQUENTIAL_UPDATE)
+      return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batches take the Jacobi collision only");
   }
   boltz_batch* b = new (std::nothrow) boltz_batch;
   if (!b) return bfail(nullptr, BOLTZ_ENOMEM, "boltz_batch_create: out of host memory");

@@ -2058,7 +2058,7 @@ __global__ __launch_bounds__(BLOCK) void collide_batch_kernel(const BatchCav* __
 // ------------------------------------------------ faces with samples --
 // wall_kernel<PHASE> in blocks [0, 8 per_xcd) and, in the blocks after
 // them, the shared pair records of the step (sample_kernel's work, dealt to
-// lanes; nb blocks per sample group): the records do not
+// lanes unless deal = 0; nb blocks per sample group): the records do not
 // depend on h, so they are drawn while the face reductions (one workgroup
 // per face) leave most of the GPU idle.  Dynamic LDS: the sampler tables.
 static_assert(kWallBlock == kSampleBlock, "one block shape for faces and samples");
@@ -2067,7 +2067,7 @@ template <int PHASE>
 __global__ __launch_bounds__(kWallBlock) void wall_sample_kernel(Params P, const float* __restrict__ h, int nface,
                                                                  int per_xcd, int nb, uint32_t step,
                                                                  uint2* __restrict__ tidx,
-                                                                 float4* __restrict__ tcoef) {
+                                                                 float4* __restrict__ tcoef, int deal) {
   const int nwb = 8 * per_xcd;
   if ((int)blockIdx.x < nwb) {
     __shared__ double red[kWallBlock / 64];
@@ -2083,7 +2083,7 @@ __global__ __launch_bounds__(kWallBlock) void wall_sample_kernel(Params P, const
   load_tables(P, dsm, true, T);
   __syncthreads();
   const int b = (int)blockIdx.x - nwb, group = b / nb;
-  sample_block(P, T, step, (uint32_t)group, (int64_t)(b - group * nb) * kSampleBlock, true, tidx, tcoef, sh);
+  sample_block(P, T, step, (uint32_t)group, (int64_t)(b - group * nb) * kSampleBlock, deal != 0, tidx, tcoef, sh);
 }
 
 }  // namespace boltz

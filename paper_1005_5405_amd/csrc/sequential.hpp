@@ -1,0 +1,302 @@
+// sequential.hpp -- the in-place sequential collision of Alg. 3 on gfx950.
+//
+// In Alg. 3 the samples of a cell update its h one after another: sample m
+// reads the current h at its nodes a and b, forms g, and changes h at a*,
+// b*, a and b before sample m + 1 reads anything.  (Eq. collision_step, the
+// Jacobi form the other collision kernels implement, evaluates every sample
+// at the post-stream h.)  Shared-sample mode only: the N_t records of a
+// sample group are read by every cell of the group, so the order
+// constraints between them are worked out once per step.
+//
+//   seq_level_kernel    groups of 64 consecutive records, one wavefront
+//                       each: the level of a record is 1 + the largest level
+//                       among the earlier records of its group that share a
+//                       node with it.  Records of one level share no node,
+//                       so they can be applied together; applying the levels
+//                       of a group in order, and the groups in order, gives
+//                       every node its updates in record order, hence the
+//                       result of the sequential loop.  The kernel also
+//                       merges the four coefficients of a record where its
+//                       nodes coincide (each slot then carries the sum over
+//                       the slots of its node, signed: gain at a*, b*, loss
+//                       at a, b), so the collision writes whole values.
+//   seq_collide_kernel  one wavefront per cell, the cell's h in LDS (FP32,
+//                       4 B per node, five cells per CU on a 20^3 grid):
+//                       moments of h^s, the groups and levels in order, then
+//                       the conservation correction (S5) and the store.
+#pragma once
+
+namespace boltz {
+
+constexpr int kSeqGroup = 64;  // records per level group (one per lane)
+
+// Dynamic LDS of seq_collide_kernel: the h tile (FP32), then the per-axis
+// parts of x . psi of the correction (FP64).
+struct SeqLDS {
+  static __host__ __device__ size_t tile(int nv) { return ((size_t)nv * 4 + 15) & ~(size_t)15; }
+  static __host__ __device__ size_t bytes(int nv, int ns) { return tile(nv) + (size_t)ns * 8; }
+};
+
+// Grid: (ceil(N_t / 64), sample groups); 64 threads.  A record's nodes are
+// a = id.x & 0xFFFF, b = id.x >> 16, a* = id.y & 0xFFFF, b* = id.y >> 16 and
+// its coefficients {q/w_a*, q/w_b*, q/w_a, q/w_b} (all zero: a discarded
+// pair, which takes level 0 and changes nothing).  Writes lev[m] (0..64),
+// gmax[group of 64] and the merged signed coefficients over tcoef.
+__global__ __launch_bounds__(64) void seq_level_kernel(const uint2* __restrict__ tidx, float4* __restrict__ tcoef,
+                                                       int64_t nt, uint8_t* __restrict__ lev, int* __restrict__ gmax) {
+  const int lane = threadIdx.x;
+  const int64_t ngr = (nt + kSeqGroup - 1) / kSeqGroup;
+  const int64_t tab = blockIdx.y;
+  const int64_t m = (int64_t)blockIdx.x * kSeqGroup + lane;
+  const bool in = m < nt;
+  uint2 id = make_uint2(0u, 0u);
+  float4 k = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (in) {
+    id = tidx[tab * nt + m];
+    k = tcoef[tab * nt + m];
+  }
+  const bool act = in && (k.x != 0.f || k.y != 0.f || k.z != 0.f || k.w != 0.f);
+  // slots in coefficient order: a*, b*, a, b
+  const unsigned n0 = id.y & 0xFFFFu, n1 = id.y >> 16, n2 = id.x & 0xFFFFu, n3 = id.x >> 16;
+  // records of lower lanes sharing a node: bit (lane - d) for distance d
+  unsigned long long conf = 0ull;
+  for (int d = 1; d < kSeqGroup; ++d) {
+    const unsigned ox = (unsigned)__shfl_up((int)id.x, d, 64), oy = (unsigned)__shfl_up((int)id.y, d, 64);
+    const int oact = __shfl_up(act ? 1 : 0, d, 64);
+    const unsigned o0 = oy & 0xFFFFu, o1 = oy >> 16, o2 = ox & 0xFFFFu, o3 = ox >> 16;
+    const bool hit = n0 == o0 || n0 == o1 || n0 == o2 || n0 == o3 || n1 == o0 || n1 == o1 || n1 == o2 ||
+                     n1 == o3 || n2 == o0 || n2 == o1 || n2 == o2 || n2 == o3 || n3 == o0 || n3 == o1 ||
+                     n3 == o2 || n3 == o3;
+    if (lane >= d && act && oact && hit) conf |= 1ull << (lane - d);
+  }
+  // levels in lane order: lane j's level is final once the lanes below it
+  // have been taken into account
+  int level = act ? 1 : 0;
+  for (int j = 0; j < kSeqGroup - 1; ++j) {
+    const int lj = __builtin_amdgcn_readlane(level, j);
+    if ((conf >> j) & 1ull) level = max(level, lj + 1);
+  }
+  int top = level;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
+  if (in) {
+    lev[tab * nt + m] = (uint8_t)level;
+    // every slot carries the signed sum over the slots of its node, summed
+    // in slot order (equal for all slots of one node)
+    const float s[4] = {k.x, k.y, -k.z, -k.w};
+    const unsigned nn[4] = {n0, n1, n2, n3};
+    float c[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float v = 0.0f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (nn[u] == nn[t]) v += s[u];
+      c[t] = v;
+    }
+    tcoef[tab * nt + m] = make_float4(c[0], c[1], c[2], c[3]);
+  }
+  if (lane == 0) gmax[tab * ngr + blockIdx.x] = top;
+}
+
+// Lane holding value k (0..19) after wave_fold20.
+__host__ __device__ constexpr int fold20_lane(int k) {
+  return 32 * (k / 10) + 16 * ((k % 10) / 5) +
+         ((k % 5) < 3 ? 4 * ((k % 5) / 2) + 2 * ((k % 5) % 2) : 8 + 2 * ((k % 5) - 3));
+}
+
+// Sums over the cell of w_j psi_k(j) h_j, psi = (1, v_x, v_y, v_z, |v|^2),
+// by velocity rows (jx, jy): per row the z sums with the factors
+// omega_z v_z^p, then the row weight omega_x omega_y.  Per lane; h in LDS.
+__device__ __forceinline__ void seq_moments(const double* vx, const double* vy, const double* omx,
+                                            const double* omy, const double* zmom, const float* h, int n0, int n1,
+                                            int n2, double (&s)[5]) {
+  typedef __attribute__((address_space(4))) const double cf64;
+  const cf64* zc = (const cf64*)zmom;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) s[i] = 0.0;
+  for (int row = threadIdx.x; row < n0 * n1; row += 64) {
+    const int jx = row / n1, jy = row - (row / n1) * n1;
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+    for (int jz = 0; jz < n2; ++jz) {
+      const double v = (double)h[row * n2 + jz];
+      S0 = fma(zc[8 * jz], v, S0);
+      S1 = fma(zc[8 * jz + 1], v, S1);
+      S2 = fma(zc[8 * jz + 2], v, S2);
+    }
+    const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy];
+    const double T0 = W * S0;
+    s[0] += T0;
+    s[1] += a * T0;
+    s[2] += b * T0;
+    s[3] += W * S1;
+    s[4] += (a * a + b * b) * T0 + W * S2;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) s[i] = wave_sum(s[i]);
+}
+
+// Grid: one workgroup of 64 threads per cell.  vom: node velocities of the
+// three axes, then their weights omega (n0 + n1 + n2 each, FP64).  Records
+// of the cell's sample group as left by seq_level_kernel.
+__global__ __launch_bounds__(64) void seq_collide_kernel(Params P, const double* __restrict__ vom,
+                                                         const float* __restrict__ hs_all, float* __restrict__ hout_all,
+                                                         uint32_t flags, double* __restrict__ defect,
+                                                         const uint2* __restrict__ tidx,
+                                                         const float4* __restrict__ tcoef,
+                                                         const uint8_t* __restrict__ lev, const int* __restrict__ gmax) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int lane = threadIdx.x;
+  const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2], ns = n0 + n1 + n2;
+  const int64_t cell = blockIdx.x;
+  float* tile = reinterpret_cast<float*>(dsm);
+  double* xt = reinterpret_cast<double*>(dsm + SeqLDS::tile(nv));
+  const float* hs = hs_all + cell * (int64_t)nv;
+  float* dst = hout_all + cell * (int64_t)nv;
+  const double* vx = vom;
+  const double* vy = vom + n0;
+  const double* vz = vom + n0 + n1;
+  const double* omx = vom + ns;
+  const double* omy = vom + ns + n0;
+  const double* omz = vom + ns + n0 + n1;
+  const double eps = P.eps;
+  const bool vec4 = ((nv & 3) == 0) && ((reinterpret_cast<uintptr_t>(hs) & 15) == 0) &&
+                    ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
+  // ---- h^s into LDS (read once), and its moments: the targets of S5
+  if (vec4) {
+    const f32x4* s4 = reinterpret_cast<const f32x4*>(hs);
+    f32x4* t4 = reinterpret_cast<f32x4*>(tile);
+    for (int i = lane; i < (nv >> 2); i += 64) t4[i] = __builtin_nontemporal_load(&s4[i]);
+  } else {
+    for (int j = lane; j < nv; j += 64) tile[j] = hs[j];
+  }
+  __syncthreads();
+  double ms[5];
+  seq_moments(vx, vy, omx, omy, P.zmom, tile, n0, n1, n2, ms);
+  // ---- S3 + S4: the records in order, one level of a group at a time
+  const int64_t nt = P.n_pairs, ngr = (nt + kSeqGroup - 1) / kSeqGroup;
+  const int64_t tab = P.sample_group == 0 ? 0 : cell / P.sample_group;
+  const uint2* T = tidx + tab * nt;
+  const float4* C = tcoef + tab * nt;
+  const uint8_t* L = lev + tab * nt;
+  const int* GM = gmax + tab * ngr;
+  const float epsf = (float)eps;
+  uint2 nid = make_uint2(0u, 0u);
+  float4 nco = make_float4(0.f, 0.f, 0.f, 0.f);
+  int nlv = 0, ntop = 0;
+  auto load = [&](int64_t g) {
+    const int64_t m = g * kSeqGroup + lane;
+    nlv = 0;
+    if (m < nt) {
+      nid = T[m];
+      nco = C[m];
+      nlv = L[m];
+    }
+    ntop = GM[g];
+  };
+  if (ngr > 0) load(0);
+  for (int64_t g = 0; g < ngr; ++g) {
+    const uint2 id = nid;
+    const float4 co = nco;
+    const int lv = nlv;
+    const int top = __builtin_amdgcn_readfirstlane(ntop);
+    if (g + 1 < ngr) load(g + 1);
+    const int ia = (int)(id.x & 0xFFFFu), ib = (int)(id.x >> 16);
+    const int ias = (int)(id.y & 0xFFFFu), ibs = (int)(id.y >> 16);
+    for (int k = 1; k <= top; ++k) {
+      if (lv == k) {
+        // the four current values, then the four new ones: slots of one
+        // node read the same value and carry the same merged coefficient
+        const float va = tile[ia], vb = tile[ib], vas = tile[ias], vbs = tile[ibs];
+        const float gg = (va + vb) + (epsf * va) * vb;
+        tile[ias] = fmaf(co.x, gg, vas);
+        tile[ibs] = fmaf(co.y, gg, vbs);
+        tile[ia] = fmaf(co.z, gg, va);
+        tile[ib] = fmaf(co.w, gg, vb);
+      }
+    }
+  }
+  __syncthreads();
+  // ---- S5: M x = r with M_kl = sum w F^c psi_k psi_l and r = eps (moments
+  // of h^s - moments of h^c), the moments of h^c being row 0 of the sums
+  const bool correct = !(flags & 1u);
+  if (correct) {
+    TablesLDS Tb;
+    Tb.v = const_cast<double*>(vom);
+    Tb.om = const_cast<double*>(vom + ns);
+    Tb.xt = xt;
+    double acc[20];
+    correction_sums<64>(Tb, P.zmom, tile, tile, n0, n1, n2, acc);
+    const double t = wave_fold20(acc, lane);
+    const const_f64* m0c = (const const_f64*)P.m0;
+    double M[15], r[5], x[5];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) M[k] = m0c[k] + eps * lane_value(t, fold20_lane(k));
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r[k] = eps * (ms[k] - lane_value(t, fold20_lane(k)));
+    if (!solve5(M, r, x)) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) x[k] = 0.0;
+      if (lane == 0) atomicOr(P.status, 1u);
+    }
+    for (int i = lane; i < ns; i += 64) {
+      const double v = vom[i];
+      xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
+                     : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
+    }
+    __syncthreads();
+  }
+  // ---- h^{n+1} = h^c + F^c (x . psi) / eps; moments of the output for the
+  // defect
+  bool finite = true;
+  auto out_of = [&](double hc, double xpsi) { return (float)fma(fma(eps, hc, 1.0) * xpsi, P.inv_eps, hc); };
+  if (vec4 && !defect) {
+    const f32x4* a4 = reinterpret_cast<const f32x4*>(tile);
+    f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+    NodeWalk nw4(4 * lane, 4 * 64, n1, n2);
+    for (int i = lane; i < (nv >> 2); i += 64, nw4.next()) {
+      const f32x4 c = a4[i];
+      f32x4 o = c;
+      if (correct) {
+        const double xa = xt[nw4.jx] + xt[n0 + nw4.jy];
+        const double* xz = xt + n0 + n1 + nw4.jz;
+        o.x = out_of((double)c.x, xa + xz[0]);
+        o.y = out_of((double)c.y, xa + xz[1]);
+        o.z = out_of((double)c.z, xa + xz[2]);
+        o.w = out_of((double)c.w, xa + xz[3]);
+      }
+      finite = finite && isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w);
+      __builtin_nontemporal_store(o, &d4[i]);
+    }
+  } else {
+    for (int j = lane; j < nv; j += 64) {
+      const double hc = (double)tile[j];
+      float out = (float)hc;
+      if (correct) {
+        const int jz = j % n2, jy = (j / n2) % n1, jx = j / (n2 * n1);
+        out = out_of(hc, (xt[jx] + xt[n0 + jy]) + xt[n0 + n1 + jz]);
+      }
+      finite = finite && isfinite(out);
+      dst[j] = out;
+      tile[j] = out;
+    }
+    if (defect) {
+      // the output's moments against those of h^s, times eps
+      __syncthreads();
+      double mo[5];
+      seq_moments(vx, vy, omx, omy, P.zmom, tile, n0, n1, n2, mo);
+      if (lane < 5) {
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+          if (lane == k) d = eps * (mo[k] - ms[k]);
+        defect[cell * 5 + lane] = d;
+      }
+    }
+  }
+  (void)vz;
+  (void)omz;
+  if (!finite) atomicOr(P.status, 2u);
+}
+
+}  // namespace boltz

@@ -46,7 +46,9 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
     assert "null" in L.boltz_last_error(None).decode()
     bad = [dict(nx=1), dict(nv=(0, 4, 4)), dict(nv=(256, 4, 4)), dict(eps=0.0), dict(order=3),
            dict(n_pairs=2**31), dict(dt=1.0), dict(vmax=(0.0, 1.0, 1.0)), dict(sample_group=-1),
-           dict(mix16=17), dict(flags=8),
+           dict(mix16=17), dict(flags=16),
+           # the sequential update needs shared samples and has no adjoint
+           dict(flags=8, sample_group=1), dict(flags=8 | 2, sample_group=0),
            # the 12-bit Maxwellian law alone cannot draw the outer nodes of 8 cells on [-4, 4]
            dict(mix16=0, vmax=(4.0, 4.0, 4.0)), dict(mix16=0, nv=(20, 20, 20), vmax=(5.0, 5.0, 5.0)),
            # stretched velocity cells need 0 < rv < 1 and even counts
@@ -92,6 +94,9 @@ def test_batch_arguments_are_rejected_before_any_device_call():
     assert "order" in L.boltz_batch_last_error(None).decode()
     assert L.boltz_batch_create((binding._Problem * 2)(p, r), 2, ctypes.byref(b)) == binding.EINVAL
     assert "nv[2]" in L.boltz_batch_last_error(None).decode()
+    s = binding._problem(nx=8, ny=8, nv=8, vmax=3.0, delta=1.0, eps=0.1, n_pairs=10, sample_group=0, flags=8)
+    assert L.boltz_batch_create((binding._Problem * 2)(p, s), 2, ctypes.byref(b)) == binding.EINVAL
+    assert "Jacobi" in L.boltz_batch_last_error(None).decode()
     assert L.boltz_batch_step(None, None, None, None, None) == binding.EINVAL
     assert L.boltz_batch_query(None, None) == binding.EINVAL
     assert L.boltz_batch_problem(None, 0) is None
