@@ -125,7 +125,7 @@ typedef struct boltz_info {
   int32_t collide_layout;   /* LDS layout of the collision (BOLTZ_LAYOUT_*) */
   int32_t collide_block;    /* its threads per workgroup (shared samples)   */
   int32_t collide_lds_nodes; /* nodes of the h tile held in LDS             */
-  int32_t reserved;
+  int32_t collide_per_cu;   /* its workgroups resident per CU (occupancy)  */
 } boltz_info;
 
 /* LDS layouts of the collision kernel (boltz_info.collide_layout): where the
@@ -213,8 +213,8 @@ int boltz_collide(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, 
  * beyond that size.  The call allocates nothing and frees nothing.  Every
  * call on one GPU shares that GPU's array: calls that overlap on one GPU
  * (any context, any stream) race and must be serialised by the caller.
- * With BOLTZ_SEQUENTIAL_UPDATE the array also holds one level byte per
- * record and one int per 64 records (about 25 B per record in all).
+ * With BOLTZ_SEQUENTIAL_UPDATE the array also holds two bytes of level
+ * schedule per record (26 B per record in all).
  * With per-cell samples (sample_group == 1) it uses no scratch. */
 int boltz_collide_noalloc(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, uint32_t flags,
                           double* defect, void* stream);

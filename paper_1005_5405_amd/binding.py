@@ -64,7 +64,7 @@ class _Info(ctypes.Structure):
                 ("K", ctypes.c_double), ("W", ctypes.c_double), ("qfac", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("collide_layout", ctypes.c_int32),
                 ("collide_block", ctypes.c_int32), ("collide_lds_nodes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("collide_per_cu", ctypes.c_int32)]
 
 
 # LDS layouts of the collision kernel (boltz_info.collide_layout)
@@ -225,6 +225,7 @@ class Boltz:
         self.collide_layout = LAYOUTS.get(int(info.collide_layout), str(info.collide_layout))
         self.collide_block = int(info.collide_block)
         self.collide_lds_nodes = int(info.collide_lds_nodes)
+        self.collide_per_cu = int(info.collide_per_cu)
         self.n_pairs, self.order, self.bc, self.eps = int(n_pairs), int(order), int(bc), float(eps)
         self.mix16 = int(mix16)
 

@@ -72,13 +72,13 @@ struct boltz_ctx {
   float4* scoef = nullptr;
   unsigned char* scratch = nullptr;  // this device's copy of the static record scratch
   // in-place sequential collision (BOLTZ_SEQUENTIAL_UPDATE): level of every
-  // shared record, largest level of every group of 64 records, node
-  // velocities and weights of the three axes (FP64), dynamic LDS
+  // shared record, node velocities and weights of the three axes (FP64),
+  // dynamic LDS
   bool seq = false;
-  uint8_t* tlev = nullptr;
-  int* tgmax = nullptr;
+  uint16_t* tlev = nullptr;
   double* vom = nullptr;
   size_t seq_lds = 0;
+  int collide_per_cu[2] = {0, 0};  // resident workgroups per CU of the two collide variants
   std::string err;
 };
 
@@ -98,8 +98,7 @@ struct RecordTables {
   float4* tcoef;
   uint2* sidx;
   float4* scoef;
-  uint8_t* lev = nullptr;  // sequential collision: record levels and group maxima
-  int* gmax = nullptr;
+  uint16_t* lev = nullptr;  // sequential collision: record levels
 };
 
 namespace {
@@ -568,9 +567,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t o_adj_hs = off; off = align256(off + (with_adj ? nodes * 4 : 0));
   const size_t o_adj_lam = off; off = align256(off + (with_adj ? nodes * 8 : 0));
   const size_t nrec = seq ? (size_t)ngroups * (size_t)p->n_pairs : 0;
-  const size_t ngr64 = seq ? (size_t)ngroups * (size_t)((p->n_pairs + kSeqGroup - 1) / kSeqGroup) : 0;
-  const size_t o_tlev = off; off = align256(off + nrec);
-  const size_t o_tgmax = off; off = align256(off + ngr64 * 4);
+  const size_t o_tlev = off; off = align256(off + nrec * 2);
   std::vector<double> vom(2 * (size_t)nsum, 0.0);
   {
     size_t i = 0;
@@ -676,8 +673,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->adj_hs = with_adj ? reinterpret_cast<float*>(base + o_adj_hs) : nullptr;
   c->adj_lam = with_adj ? reinterpret_cast<double*>(base + o_adj_lam) : nullptr;
   c->seq = seq;
-  c->tlev = seq ? reinterpret_cast<uint8_t*>(base + o_tlev) : nullptr;
-  c->tgmax = seq ? reinterpret_cast<int*>(base + o_tgmax) : nullptr;
+  c->tlev = seq ? reinterpret_cast<uint16_t*>(base + o_tlev) : nullptr;
   c->vom = reinterpret_cast<double*>(base + o_vom);
   c->seq_lds = SeqLDS::bytes(c->nv, nsum);
   c->collide_block[0] = cblock[0];
@@ -708,6 +704,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     if (ea == hipSuccess)
       ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, cblock[t], c->collide_lds[t]);
     if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
+    c->collide_per_cu[t] = per_cu;
     int64_t cap = (int64_t)(per_cu < 1 ? 1 : per_cu) * (ncu < 1 ? 1 : ncu);
     if (hyb_rows) cap = std::min<int64_t>(cap, hyb_rows);
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
@@ -717,8 +714,10 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
                              (int)kLdsBytes);
     int per_cu = 0;
     if (ea == hipSuccess)
-      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)seq_collide_kernel, 64, c->seq_lds);
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)seq_collide_kernel, kSeqBlock,
+                                                         c->seq_lds);
     if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
+    c->collide_per_cu[0] = c->collide_per_cu[1] = per_cu;
   }
   c->adj_supported = ea == hipSuccess && !seq && pick_adjoint(c->nv, nsum, c->adj_block, c->adj_fixed);
   for (int t = 0; t < 2 && ea == hipSuccess && c->adj_supported; ++t) {
@@ -763,7 +762,7 @@ int boltz_query(const boltz_ctx* c, boltz_info* out) {
   out->collide_lds_nodes = c->seq ? (int)c->nv
                            : (c->collide_mode == ACC_HYBRID || c->collide_mode == ACC_PART) ? c->hyb_n[1]
                            : (c->collide_mode == ACC_SPLIT ? (int)((c->nv + 1) / 2) : (int)c->nv);
-  out->reserved = 0;
+  out->collide_per_cu = c->collide_per_cu[1];
   return BOLTZ_OK;
 }
 
@@ -883,8 +882,7 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
 
 static RecordTables own_tables(const boltz_ctx* c) {
   const bool split = c->collide_mode == ACC_SPLIT;
-  return RecordTables{c->tidx, c->tcoef, split ? c->sidx : c->tidx, split ? c->scoef : c->tcoef, c->tlev,
-                      c->tgmax};
+  return RecordTables{c->tidx, c->tcoef, split ? c->sidx : c->tidx, split ? c->scoef : c->tcoef, c->tlev};
 }
 
 extern "C++" template <int B, int M>
@@ -953,9 +951,9 @@ static int launch_collide_r(boltz_ctx* c, const float* hs, float* hout, int64_t 
     const int64_t ngr = (c->p.n_pairs + kSeqGroup - 1) / kSeqGroup;
     if (ngr > 0)
       hipLaunchKernelGGL(seq_level_kernel, dim3((unsigned)ngr, (unsigned)c->ngroups), dim3(64), 0, st, R.tidx,
-                         R.tcoef, (int64_t)c->p.n_pairs, R.lev, R.gmax);
-    hipLaunchKernelGGL(seq_collide_kernel, dim3((unsigned)c->ncells), dim3(64), c->seq_lds, st, c->P, c->vom, hs,
-                       hout, flags, defect, R.tidx, R.tcoef, R.lev, R.gmax);
+                         R.tcoef, (int64_t)c->p.n_pairs, R.lev);
+    hipLaunchKernelGGL(seq_collide_kernel, dim3((unsigned)c->ncells), dim3(kSeqBlock), c->seq_lds, st, c->P, c->vom, hs,
+                       hout, flags, defect, R.tidx, R.tcoef, R.lev);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "seq_collide_kernel launch");
   }
@@ -1027,10 +1025,8 @@ int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t 
     const size_t n = (size_t)c->ngroups * (size_t)c->p.n_pairs;
     const bool split = c->collide_mode == ACC_SPLIT;
     const size_t one = align256(n * sizeof(uint2)) + n * sizeof(float4);
-    // the sequential collision also keeps a level per record and the
-    // largest level of every group of 64 records
-    const size_t ngr64 = (size_t)c->ngroups * (size_t)((c->p.n_pairs + kSeqGroup - 1) / kSeqGroup);
-    const size_t need = split ? align256(one) + one : (c->seq ? align256(one) + align256(n) + ngr64 * 4 : one);
+    // the sequential collision also keeps a level per record
+    const size_t need = split ? align256(one) + one : (c->seq ? align256(one) + 2 * n : one);
     if (need > kScratchBytes)
       return fail(c, BOLTZ_EINVAL,
                   "boltz_collide_noalloc: " + std::to_string(need) + " bytes of shared-sample records exceed the " +
@@ -1046,10 +1042,7 @@ int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t 
       R.sidx = reinterpret_cast<uint2*>(q);
       R.scoef = reinterpret_cast<float4*>(q + align256(n * sizeof(uint2)));
     }
-    if (c->seq) {
-      R.lev = p + align256(one);
-      R.gmax = reinterpret_cast<int*>(p + align256(one) + align256(n));
-    }
+    if (c->seq) R.lev = reinterpret_cast<uint16_t*>(p + align256(one));
   }
   return launch_collide_r(c, h_s, h_out, step, flags, defect, static_cast<hipStream_t>(stream), false, R);
 }

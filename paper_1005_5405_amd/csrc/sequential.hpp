@@ -20,32 +20,42 @@
 //                       nodes coincide (each slot then carries the sum over
 //                       the slots of its node, signed: gain at a*, b*, loss
 //                       at a, b), so the collision writes whole values.
-//   seq_collide_kernel  one wavefront per cell, the cell's h in LDS (FP32,
+//   seq_collide_kernel  one workgroup per cell, the cell's h in LDS (FP32,
 //                       4 B per node, five cells per CU on a 20^3 grid):
-//                       moments of h^s, the groups and levels in order, then
-//                       the conservation correction (S5) and the store.
+//                       moments of h^s, the groups and levels in order (one
+//                       wavefront), then the conservation correction (S5) and
+//                       the store.
 #pragma once
 
 namespace boltz {
 
 constexpr int kSeqGroup = 64;  // records per level group (one per lane)
+constexpr int kSeqAhead = 8;   // groups of records loaded ahead of the one applied
 
-// Dynamic LDS of seq_collide_kernel: the h tile (FP32), then the per-axis
-// parts of x . psi of the correction (FP64).
+constexpr int kSeqBlock = 256;  // threads per cell: the node phases use all, the pair loop one wavefront
+
+// Dynamic LDS of seq_collide_kernel: the h tile (FP32), one spare word per
+// lane, then the per-axis parts of x . psi of the correction (FP64); the
+// block reductions (at most 20 doubles per wavefront) use the region after
+// the tile before x . psi is written.
 struct SeqLDS {
+  static constexpr size_t kSpare = 64 * 4;
   static __host__ __device__ size_t tile(int nv) { return ((size_t)nv * 4 + 15) & ~(size_t)15; }
-  static __host__ __device__ size_t bytes(int nv, int ns) { return tile(nv) + (size_t)ns * 8; }
+  static __host__ __device__ size_t bytes(int nv, int ns) {
+    const size_t tail = kSpare + (size_t)ns * 8, red = (size_t)20 * (kSeqBlock / 64) * 8;
+    return tile(nv) + (tail > red ? tail : red);
+  }
 };
 
 // Grid: (ceil(N_t / 64), sample groups); 64 threads.  A record's nodes are
 // a = id.x & 0xFFFF, b = id.x >> 16, a* = id.y & 0xFFFF, b* = id.y >> 16 and
 // its coefficients {q/w_a*, q/w_b*, q/w_a, q/w_b} (all zero: a discarded
-// pair, which takes level 0 and changes nothing).  Writes lev[m] (0..64),
-// gmax[group of 64] and the merged signed coefficients over tcoef.
+// pair, which takes level 0 and changes nothing).  Writes lev[m] = level
+// (0..64) | (the group's largest level << 8) and the merged signed
+// coefficients over tcoef.
 __global__ __launch_bounds__(64) void seq_level_kernel(const uint2* __restrict__ tidx, float4* __restrict__ tcoef,
-                                                       int64_t nt, uint8_t* __restrict__ lev, int* __restrict__ gmax) {
+                                                       int64_t nt, uint16_t* __restrict__ lev) {
   const int lane = threadIdx.x;
-  const int64_t ngr = (nt + kSeqGroup - 1) / kSeqGroup;
   const int64_t tab = blockIdx.y;
   const int64_t m = (int64_t)blockIdx.x * kSeqGroup + lane;
   const bool in = m < nt;
@@ -80,7 +90,7 @@ __global__ __launch_bounds__(64) void seq_level_kernel(const uint2* __restrict__
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
   if (in) {
-    lev[tab * nt + m] = (uint8_t)level;
+    lev[tab * nt + m] = (uint16_t)(level | (top << 8));
     // every slot carries the signed sum over the slots of its node, summed
     // in slot order (equal for all slots of one node)
     const float s[4] = {k.x, k.y, -k.z, -k.w};
@@ -96,29 +106,39 @@ __global__ __launch_bounds__(64) void seq_level_kernel(const uint2* __restrict__
     }
     tcoef[tab * nt + m] = make_float4(c[0], c[1], c[2], c[3]);
   }
-  if (lane == 0) gmax[tab * ngr + blockIdx.x] = top;
-}
-
-// Lane holding value k (0..19) after wave_fold20.
-__host__ __device__ constexpr int fold20_lane(int k) {
-  return 32 * (k / 10) + 16 * ((k % 10) / 5) +
-         ((k % 5) < 3 ? 4 * ((k % 5) / 2) + 2 * ((k % 5) % 2) : 8 + 2 * ((k % 5) - 3));
 }
 
 // Sums over the cell of w_j psi_k(j) h_j, psi = (1, v_x, v_y, v_z, |v|^2),
 // by velocity rows (jx, jy): per row the z sums with the factors
-// omega_z v_z^p, then the row weight omega_x omega_y.  Per lane; h in LDS.
+// omega_z v_z^p (four z nodes per scalar load batch), then the row weight
+// omega_x omega_y.  Block-reduced over kSeqBlock threads (red: 5 * kSeqBlock
+// / 64 doubles of LDS; ends with a barrier); h in LDS.
 __device__ __forceinline__ void seq_moments(const double* vx, const double* vy, const double* omx,
                                             const double* omy, const double* zmom, const float* h, int n0, int n1,
-                                            int n2, double (&s)[5]) {
+                                            int n2, double* red, double (&s)[5]) {
   typedef __attribute__((address_space(4))) const double cf64;
   const cf64* zc = (const cf64*)zmom;
 #pragma unroll
   for (int i = 0; i < 5; ++i) s[i] = 0.0;
-  for (int row = threadIdx.x; row < n0 * n1; row += 64) {
+  for (int row = threadIdx.x; row < n0 * n1; row += kSeqBlock) {
     const int jx = row / n1, jy = row - (row / n1) * n1;
     double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-    for (int jz = 0; jz < n2; ++jz) {
+    int jz = 0;
+    for (; jz + 4 <= n2; jz += 4) {
+      double z[4][3];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) z[k][p] = zc[8 * (jz + k) + p];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = (double)h[row * n2 + jz + k];
+        S0 = fma(z[k][0], v, S0);
+        S1 = fma(z[k][1], v, S1);
+        S2 = fma(z[k][2], v, S2);
+      }
+    }
+    for (; jz < n2; ++jz) {
       const double v = (double)h[row * n2 + jz];
       S0 = fma(zc[8 * jz], v, S0);
       S1 = fma(zc[8 * jz + 1], v, S1);
@@ -132,25 +152,28 @@ __device__ __forceinline__ void seq_moments(const double* vx, const double* vy, 
     s[3] += W * S1;
     s[4] += (a * a + b * b) * T0 + W * S2;
   }
-#pragma unroll
-  for (int i = 0; i < 5; ++i) s[i] = wave_sum(s[i]);
+  block_sum<5, kSeqBlock>(s, red);
 }
 
-// Grid: one workgroup of 64 threads per cell.  vom: node velocities of the
-// three axes, then their weights omega (n0 + n1 + n2 each, FP64).  Records
-// of the cell's sample group as left by seq_level_kernel.
-__global__ __launch_bounds__(64) void seq_collide_kernel(Params P, const double* __restrict__ vom,
-                                                         const float* __restrict__ hs_all, float* __restrict__ hout_all,
-                                                         uint32_t flags, double* __restrict__ defect,
-                                                         const uint2* __restrict__ tidx,
-                                                         const float4* __restrict__ tcoef,
-                                                         const uint8_t* __restrict__ lev, const int* __restrict__ gmax) {
+// Grid: one workgroup of kSeqBlock threads per cell.  vom: node velocities
+// of the three axes, then their weights omega (n0 + n1 + n2 each, FP64).
+// Records of the cell's sample group as left by seq_level_kernel.  The node
+// phases use the whole workgroup; the pair loop, a chain of dependent LDS
+// accesses, runs on wavefront 0 while the others wait at a barrier.
+__global__ __launch_bounds__(kSeqBlock) void seq_collide_kernel(
+    Params P, const double* __restrict__ vom, const float* __restrict__ hs_all, float* __restrict__ hout_all,
+    uint32_t flags, double* __restrict__ defect, const uint2* __restrict__ tidx, const float4* __restrict__ tcoef,
+    const uint16_t* __restrict__ lev) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int nv = P.nv, n0 = P.n[0], n1 = P.n[1], n2 = P.n[2], ns = n0 + n1 + n2;
   const int64_t cell = blockIdx.x;
   float* tile = reinterpret_cast<float*>(dsm);
-  double* xt = reinterpret_cast<double*>(dsm + SeqLDS::tile(nv));
+  // after the tile: one spare word per lane (the accesses of the lanes
+  // without a record in a level), then x . psi per axis; the block sums use
+  // the same region before x . psi is written
+  double* red = reinterpret_cast<double*>(dsm + SeqLDS::tile(nv));
+  double* xt = reinterpret_cast<double*>(dsm + SeqLDS::tile(nv) + SeqLDS::kSpare);
   const float* hs = hs_all + cell * (int64_t)nv;
   float* dst = hout_all + cell * (int64_t)nv;
   const double* vx = vom;
@@ -166,53 +189,76 @@ __global__ __launch_bounds__(64) void seq_collide_kernel(Params P, const double*
   if (vec4) {
     const f32x4* s4 = reinterpret_cast<const f32x4*>(hs);
     f32x4* t4 = reinterpret_cast<f32x4*>(tile);
-    for (int i = lane; i < (nv >> 2); i += 64) t4[i] = __builtin_nontemporal_load(&s4[i]);
+    for (int i = tid; i < (nv >> 2); i += kSeqBlock) t4[i] = __builtin_nontemporal_load(&s4[i]);
   } else {
-    for (int j = lane; j < nv; j += 64) tile[j] = hs[j];
+    for (int j = tid; j < nv; j += kSeqBlock) tile[j] = hs[j];
   }
   __syncthreads();
   double ms[5];
-  seq_moments(vx, vy, omx, omy, P.zmom, tile, n0, n1, n2, ms);
+  seq_moments(vx, vy, omx, omy, P.zmom, tile, n0, n1, n2, red, ms);
   // ---- S3 + S4: the records in order, one level of a group at a time
-  const int64_t nt = P.n_pairs, ngr = (nt + kSeqGroup - 1) / kSeqGroup;
-  const int64_t tab = P.sample_group == 0 ? 0 : cell / P.sample_group;
-  const uint2* T = tidx + tab * nt;
-  const float4* C = tcoef + tab * nt;
-  const uint8_t* L = lev + tab * nt;
-  const int* GM = gmax + tab * ngr;
-  const float epsf = (float)eps;
-  uint2 nid = make_uint2(0u, 0u);
-  float4 nco = make_float4(0.f, 0.f, 0.f, 0.f);
-  int nlv = 0, ntop = 0;
-  auto load = [&](int64_t g) {
-    const int64_t m = g * kSeqGroup + lane;
-    nlv = 0;
-    if (m < nt) {
-      nid = T[m];
-      nco = C[m];
-      nlv = L[m];
+  if (tid < 64) {
+    const int64_t nt = P.n_pairs, ngr = (nt + kSeqGroup - 1) / kSeqGroup;
+    const int64_t tab = P.sample_group == 0 ? 0 : cell / P.sample_group;
+    const uint2* T = tidx + tab * nt;
+    const float4* C = tcoef + tab * nt;
+    const uint16_t* L = lev + tab * nt;
+    const float epsf = (float)eps;
+    const int spare = (int)(SeqLDS::tile(nv) / 4) + lane;
+    // the records of the next kSeqAhead groups are in flight in registers
+    // (a group's levels take less time than a load from L2).  The loads are
+    // unconditional (indices clamped into the table) and their values are
+    // not touched before the group is applied, so each group waits only
+    // for its own records.
+    uint2 qid[kSeqAhead];
+    float4 qco[kSeqAhead];
+    unsigned qlt[kSeqAhead];
+    bool qok[kSeqAhead];
+    auto fetch = [&](int64_t g, int s) {
+      const int64_t gc = g < ngr ? g : ngr - 1;
+      const int64_t m = gc * kSeqGroup + lane;
+      const int64_t mc = m < nt ? m : nt - 1;
+      qid[s] = T[mc];
+      qco[s] = C[mc];
+      qlt[s] = L[mc];
+      qok[s] = m < nt;
+    };
+    if (ngr > 0) {
+#pragma unroll
+      for (int s = 0; s < kSeqAhead; ++s) fetch(s, s);
     }
-    ntop = GM[g];
-  };
-  if (ngr > 0) load(0);
-  for (int64_t g = 0; g < ngr; ++g) {
-    const uint2 id = nid;
-    const float4 co = nco;
-    const int lv = nlv;
-    const int top = __builtin_amdgcn_readfirstlane(ntop);
-    if (g + 1 < ngr) load(g + 1);
-    const int ia = (int)(id.x & 0xFFFFu), ib = (int)(id.x >> 16);
-    const int ias = (int)(id.y & 0xFFFFu), ibs = (int)(id.y >> 16);
-    for (int k = 1; k <= top; ++k) {
-      if (lv == k) {
-        // the four current values, then the four new ones: slots of one
-        // node read the same value and carry the same merged coefficient
-        const float va = tile[ia], vb = tile[ib], vas = tile[ias], vbs = tile[ibs];
-        const float gg = (va + vb) + (epsf * va) * vb;
-        tile[ias] = fmaf(co.x, gg, vas);
-        tile[ibs] = fmaf(co.y, gg, vbs);
-        tile[ia] = fmaf(co.z, gg, va);
-        tile[ib] = fmaf(co.w, gg, vb);
+    for (int64_t g0 = 0; g0 < ngr; g0 += kSeqAhead) {
+#pragma unroll
+      for (int s = 0; s < kSeqAhead; ++s) {
+        const int64_t g = g0 + s;
+        const uint2 id = qid[s];
+        const float4 co = qco[s];
+        const unsigned lt = qlt[s];
+        const bool ok = qok[s];
+        fetch(g + kSeqAhead, s);
+        if (g < ngr) {
+          // level of the lane's record and the group's last level (lane 0
+          // always holds a record of the group)
+          const int lv = ok ? (int)(lt & 0xFFu) : 0;
+          const int top = __builtin_amdgcn_readfirstlane((int)(lt >> 8));
+          const int ia = (int)(id.x & 0xFFFFu), ib = (int)(id.x >> 16);
+          const int ias = (int)(id.y & 0xFFFFu), ibs = (int)(id.y >> 16);
+          for (int k = 1; k <= top; ++k) {
+            // every lane reads and writes four words; a lane whose record
+            // is not of this level uses its spare word for all four
+            const bool on = lv == k;
+            const int pa = on ? ia : spare, pb = on ? ib : spare;
+            const int pas = on ? ias : spare, pbs = on ? ibs : spare;
+            // the four current values, then the four new ones: slots of one
+            // node read the same value and carry the same merged coefficient
+            const float va = tile[pa], vb = tile[pb], vas = tile[pas], vbs = tile[pbs];
+            const float gg = (va + vb) + (epsf * va) * vb;
+            tile[pas] = fmaf(co.x, gg, vas);
+            tile[pbs] = fmaf(co.y, gg, vbs);
+            tile[pa] = fmaf(co.z, gg, va);
+            tile[pb] = fmaf(co.w, gg, vb);
+          }
+        }
       }
     }
   }
@@ -226,23 +272,28 @@ __global__ __launch_bounds__(64) void seq_collide_kernel(Params P, const double*
     Tb.om = const_cast<double*>(vom + ns);
     Tb.xt = xt;
     double acc[20];
-    correction_sums<64>(Tb, P.zmom, tile, tile, n0, n1, n2, acc);
-    const double t = wave_fold20(acc, lane);
-    const const_f64* m0c = (const const_f64*)P.m0;
-    double M[15], r[5], x[5];
+    correction_sums<kSeqBlock>(Tb, P.zmom, tile, tile, n0, n1, n2, acc);
+    const int rows = n0 * n1;
+    const double t = block_sum20_w0<kSeqBlock>(acc, red, rows >= kSeqBlock ? kSeqBlock / 64 : (rows + 63) / 64);
+    if (tid < 64) {
+      // wavefront 0: thread k < 20 holds total k; it has read red before
+      // x . psi overwrites the region
+      const const_f64* m0c = (const const_f64*)P.m0;
+      double M[15], r[5], x[5];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) M[k] = m0c[k] + eps * lane_value(t, fold20_lane(k));
+      for (int k = 0; k < 15; ++k) M[k] = m0c[k] + eps * lane_value(t, k);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) r[k] = eps * (ms[k] - lane_value(t, fold20_lane(k)));
-    if (!solve5(M, r, x)) {
+      for (int k = 0; k < 5; ++k) r[k] = eps * (ms[k] - lane_value(t, k));
+      if (!solve5(M, r, x)) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) x[k] = 0.0;
-      if (lane == 0) atomicOr(P.status, 1u);
-    }
-    for (int i = lane; i < ns; i += 64) {
-      const double v = vom[i];
-      xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
-                     : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
+        for (int k = 0; k < 5; ++k) x[k] = 0.0;
+        if (tid == 0) atomicOr(P.status, 1u);
+      }
+      for (int i = tid; i < ns; i += 64) {
+        const double v = vom[i];
+        xt[i] = i < n0 ? x[1] * v + x[4] * (v * v)
+                       : (i < n0 + n1 ? x[2] * v + x[4] * (v * v) : x[0] + x[3] * v + x[4] * (v * v));
+      }
     }
     __syncthreads();
   }
@@ -253,8 +304,8 @@ __global__ __launch_bounds__(64) void seq_collide_kernel(Params P, const double*
   if (vec4 && !defect) {
     const f32x4* a4 = reinterpret_cast<const f32x4*>(tile);
     f32x4* d4 = reinterpret_cast<f32x4*>(dst);
-    NodeWalk nw4(4 * lane, 4 * 64, n1, n2);
-    for (int i = lane; i < (nv >> 2); i += 64, nw4.next()) {
+    NodeWalk nw4(4 * tid, 4 * kSeqBlock, n1, n2);
+    for (int i = tid; i < (nv >> 2); i += kSeqBlock, nw4.next()) {
       const f32x4 c = a4[i];
       f32x4 o = c;
       if (correct) {
@@ -269,28 +320,27 @@ __global__ __launch_bounds__(64) void seq_collide_kernel(Params P, const double*
       __builtin_nontemporal_store(o, &d4[i]);
     }
   } else {
-    for (int j = lane; j < nv; j += 64) {
+    NodeWalk nw1(tid, kSeqBlock, n1, n2);
+    for (int j = tid; j < nv; j += kSeqBlock, nw1.next()) {
       const double hc = (double)tile[j];
       float out = (float)hc;
-      if (correct) {
-        const int jz = j % n2, jy = (j / n2) % n1, jx = j / (n2 * n1);
-        out = out_of(hc, (xt[jx] + xt[n0 + jy]) + xt[n0 + n1 + jz]);
-      }
+      if (correct) out = out_of(hc, (xt[nw1.jx] + xt[n0 + nw1.jy]) + xt[n0 + n1 + nw1.jz]);
       finite = finite && isfinite(out);
       dst[j] = out;
       tile[j] = out;
     }
     if (defect) {
-      // the output's moments against those of h^s, times eps
+      // the output's moments against those of h^s, times eps (red is free:
+      // x . psi has been used)
       __syncthreads();
       double mo[5];
-      seq_moments(vx, vy, omx, omy, P.zmom, tile, n0, n1, n2, mo);
-      if (lane < 5) {
+      seq_moments(vx, vy, omx, omy, P.zmom, tile, n0, n1, n2, red, mo);
+      if (tid < 5) {
         double d = 0.0;
 #pragma unroll
         for (int k = 0; k < 5; ++k)
-          if (lane == k) d = eps * (mo[k] - ms[k]);
-        defect[cell * 5 + lane] = d;
+          if (tid == k) d = eps * (mo[k] - ms[k]);
+        defect[cell * 5 + tid] = d;
       }
     }
   }
