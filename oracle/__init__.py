@@ -49,7 +49,8 @@ class _Problem(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("dt", ctypes.c_double), ("order", ctypes.c_int32),
                 ("bc", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("sample_group", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("cavity_id", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("mix16", ctypes.c_uint32), ("rv", ctypes.c_double)]
+                ("mix16", ctypes.c_uint32), ("rv", ctypes.c_double), ("rx", ctypes.c_double),
+                ("ry", ctypes.c_double)]
 
 
 class _Walls(ctypes.Structure):
@@ -77,6 +78,7 @@ def _load():
         L.boltz_ref_get_threads.restype = ctypes.c_int
         L.boltz_ref_axis.argtypes = [P, ctypes.c_int, V, V, V]
         L.boltz_ref_axis_edges.argtypes = [P, ctypes.c_int, V]
+        L.boltz_ref_cell_widths.argtypes = [P, ctypes.c_int, V]
         L.boltz_ref_axis_draw.argtypes = [P, ctypes.c_int, U32]
         L.boltz_ref_philox4x32_10.argtypes = [V, V, V]
         L.boltz_ref_cos_sin_2pi.argtypes = [D, ctypes.POINTER(D), ctypes.POINTER(D)]
@@ -156,14 +158,14 @@ class Oracle:
     """One problem set-up of the oracle (FP64, host memory)."""
 
     def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2,
-                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0):
+                 bc=BC_CAVITY, sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0, rx=0.0, ry=0.0):
         L = _load()
         nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
         vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
         p = _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax),
                      float(delta), float(eps), float(cfl), float(dt), int(order), int(bc),
                      int(n_pairs), int(sample_group), int(seed), int(cavity_id), int(flags), int(mix16),
-                     float(rv))
+                     float(rv), float(rx), float(ry))
         ctx = ctypes.c_void_p()
         rc = L.boltz_ref_create(ctypes.byref(p), ctypes.byref(ctx))
         if rc != 0:
@@ -176,6 +178,10 @@ class Oracle:
         info = np.zeros(8)
         L.boltz_ref_info(ctx, info.ctypes.data)
         self.dt, self.K, self.W, self.qfac, self.dx, self.dy = (float(x) for x in info[:6])
+        # spatial cell widths along x and y (Sec. 5.1 stretching, else 1/n)
+        self.wx, self.wy = np.zeros(self.nx), np.zeros(self.ny)
+        L.boltz_ref_cell_widths(ctx, 0, self.wx.ctypes.data)
+        L.boltz_ref_cell_widths(ctx, 1, self.wy.ctypes.data)
         self.v = []
         self.omega = []
         self.thresholds = []

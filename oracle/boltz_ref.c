@@ -48,6 +48,9 @@ struct boltz_ref_ctx {
   double Om[3];
   uint64_t* T[3]; /* T[k][i] = T_i for i in [1, n); T[k][0] = 0 */
   double* pphi[3];  /* realised per-axis Maxwellian law (T_{i+1} - T_i) 2^-12 */
+  int sstretched;   /* spatial cells in geometric progression (Sec. 5.1) */
+  double* wx;       /* widths of the nx spatial cells along x            */
+  double* wy;       /* ... and of the ny cells along y                   */
   double* punif[3]; /* realised per-axis uniform law of floor(f n / 2^12)     */
   double beta;      /* weight of the uniform component, mix16 / 16           */
   double dx, dy, dt, K, W, qfac;
@@ -93,6 +96,8 @@ void boltz_ref_destroy(boltz_ref_ctx* c) {
     free(c->punif[k]);
     free(c->edge[k]);
   }
+  free(c->wx);
+  free(c->wy);
   free(c);
 }
 
@@ -126,6 +131,14 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
   const int stretched = (p->rv != 0.0 && p->rv != 1.0);
   if (stretched && (!(p->rv > 0.0 && p->rv < 1.0) || (p->nv[0] & 1) || (p->nv[1] & 1) || (p->nv[2] & 1))) {
     set_err(g_create_err, "stretched velocity grid needs 0 < rv < 1 and an even cell count per axis");
+    return BOLTZ_REF_EINVAL;
+  }
+  /* rx, ry: 0 or 1 = uniform spatial cells; 0 < r < 1 = stretched (Sec.
+   * 5.1), with the first-order scheme of Eq. streaming2D only */
+  const int sx_str = (p->rx != 0.0 && p->rx != 1.0), sy_str = (p->ry != 0.0 && p->ry != 1.0);
+  if ((sx_str && !(p->rx > 0.0 && p->rx < 1.0)) || (sy_str && !(p->ry > 0.0 && p->ry < 1.0)) ||
+      ((sx_str || sy_str) && p->order != 1)) {
+    set_err(g_create_err, "stretched spatial cells need 0 < rx, ry < 1 and first-order streaming");
     return BOLTZ_REF_EINVAL;
   }
   boltz_ref_ctx* c = (boltz_ref_ctx*)calloc(1, sizeof(*c));
@@ -252,15 +265,45 @@ int boltz_ref_create(const boltz_ref_problem* p, boltz_ref_ctx** out) {
   c->ncells = p->nx * p->ny;
   c->dx = 1.0 / p->nx;
   c->dy = 1.0 / p->ny;
+  /* Sec. 5.1: spatial cell lengths in geometric progression.  Along x the
+   * cell at distance d (in cells) from the nearer side wall is w0 rx^-d long,
+   * along y the cell d cells below the lid w0 ry^-d; the lengths add up to
+   * the cavity side 1.  Uniform cells: all 1/n. */
+  c->sstretched = sx_str || sy_str;
+  c->wx = (double*)malloc(sizeof(double) * p->nx);
+  c->wy = (double*)malloc(sizeof(double) * p->ny);
+  {
+    double sum = 0.0;
+    for (int i = 0; i < p->nx; ++i) {
+      int d = i < p->nx - 1 - i ? i : p->nx - 1 - i;
+      c->wx[i] = sx_str ? pow(p->rx, -d) : 1.0;
+      sum += c->wx[i];
+    }
+    for (int i = 0; i < p->nx; ++i) c->wx[i] /= sum;
+    sum = 0.0;
+    for (int i = 0; i < p->ny; ++i) {
+      c->wy[i] = sy_str ? pow(p->ry, -(p->ny - 1 - i)) : 1.0;
+      sum += c->wy[i];
+    }
+    for (int i = 0; i < p->ny; ++i) c->wy[i] /= sum;
+  }
+  double mwx = c->wx[0], mwy = c->wy[0];
+  for (int i = 0; i < p->nx; ++i) mwx = c->wx[i] < mwx ? c->wx[i] : mwx;
+  for (int i = 0; i < p->ny; ++i) mwy = c->wy[i] < mwy ? c->wy[i] : mwy;
+  if (!c->sstretched) {
+    mwx = c->dx;
+    mwy = c->dy;
+  }
   double vmx = fabs(c->v[0][0]), vmy = fabs(c->v[1][0]);
   if (p->dt > 0.0) {
     c->dt = p->dt;
   } else {
-    /* Sec. 5.1: the largest Courant number over nodes and axes equals cfl */
-    double rx = vmx / c->dx, ry = vmy / c->dy;
+    /* Sec. 5.1: the largest Courant number over nodes, cells and axes
+     * equals cfl */
+    double rx = vmx / mwx, ry = vmy / mwy;
     c->dt = p->cfl / (rx > ry ? rx : ry);
   }
-  double cx = vmx * c->dt / c->dx, cy = vmy * c->dt / c->dy;
+  double cx = vmx * c->dt / mwx, cy = vmy * c->dt / mwy;
   int stable = (p->order == 1) ? (cx + cy <= 1.0 + 1e-12) : (cx <= 1.0 + 1e-12 && cy <= 1.0 + 1e-12);
   if (!stable && !(p->flags & BOLTZ_REF_ALLOW_UNSTABLE)) {
     boltz_ref_destroy(c);
@@ -287,6 +330,13 @@ int boltz_ref_info(const boltz_ref_ctx* c, double* out) {
   out[BOLTZ_REF_INFO_DY] = c->dy;
   out[BOLTZ_REF_INFO_NCELLS] = c->ncells;
   out[BOLTZ_REF_INFO_NV] = c->nv;
+  return BOLTZ_REF_OK;
+}
+
+int boltz_ref_cell_widths(const boltz_ref_ctx* c, int axis, double* widths) {
+  if (!c || axis < 0 || axis > 1 || !widths) return BOLTZ_REF_EINVAL;
+  const int n = axis == 0 ? c->p.nx : c->p.ny;
+  for (int i = 0; i < n; ++i) widths[i] = axis == 0 ? c->wx[i] : c->wy[i];
   return BOLTZ_REF_OK;
 }
 
@@ -814,7 +864,10 @@ static void stream_order1(const boltz_ref_ctx* c, const double* h, double* hs, c
       node_idx(c, j, &jx, &jy, &jz);
       double vx = c->v[0][jx], vy = c->v[1][jy];
       double h0 = h[(size_t)cell * nv + j];
-      double Cx = fabs(vx) * c->dt / c->dx, Cy = fabs(vy) * c->dt / c->dy;
+      /* Courant numbers of this cell: its own lengths (the upwind
+       * finite-volume form, conservative on stretched cells) */
+      double Cx = fabs(vx) * c->dt / (c->sstretched ? c->wx[ix] : c->dx);
+      double Cy = fabs(vy) * c->dt / (c->sstretched ? c->wy[iy] : c->dy);
       double hxn = h0, hyn = h0;
       if (vx != 0.0) {
         int i = ix - (vx > 0.0 ? 1 : -1);
@@ -1135,9 +1188,11 @@ int boltz_ref_moments(const boltz_ref_ctx* c, const double* h, const boltz_ref_w
                                : (vy < 0.0 ? ghost_value(c, WALL_TOP, ix, nw, j, walls) : 0.0);
         pxy += node_w(c, jx, jy, jz) * vx * vy * hh;
       }
-      total += 2.0 * pxy;
+      /* stretched cells: the faces weighted by their lengths (the mean
+       * over the lid) */
+      total += c->sstretched ? c->wx[ix] * (2.0 * pxy) : 2.0 * pxy;
     }
-    *lid_shear = -total / nx;
+    *lid_shear = c->sstretched ? -total : -total / nx;
   }
   return BOLTZ_REF_OK;
 }
@@ -1365,6 +1420,8 @@ static void order1_adj(const boltz_ref_ctx* c, const double* lam_out, double* la
 int boltz_ref_stream_adjoint(const boltz_ref_ctx* c, const double* h_in, const double* lam_out,
                              double* lam_in, double* grad, const boltz_ref_walls* walls) {
   if (!c || !h_in || !lam_out || !lam_in) return BOLTZ_REF_EINVAL;
+  /* the adjoint follows uniform spatial cells only */
+  if (c->sstretched) return BOLTZ_REF_EINVAL;
   const int cavity = (c->p.bc == BOLTZ_REF_BC_CAVITY);
   if (cavity && !walls) return BOLTZ_REF_EINVAL;
   const int nx = c->p.nx, ny = c->p.ny;
@@ -1523,6 +1580,8 @@ int boltz_ref_collide_adjoint(const boltz_ref_ctx* c, const double* h_s, const d
 int boltz_ref_step_adjoint(const boltz_ref_ctx* c, const double* h_in, const double* lam_out,
                            double* lam_in, double* grad, const boltz_ref_walls* walls, int64_t step) {
   if (!c || !h_in || !lam_out || !lam_in || lam_out == lam_in) return BOLTZ_REF_EINVAL;
+  /* the adjoint follows uniform spatial cells only */
+  if (c->sstretched) return BOLTZ_REF_EINVAL;
   if (c->p.flags & BOLTZ_REF_SEQUENTIAL) return BOLTZ_REF_EINVAL;
   const size_t n = (size_t)c->ncells * c->nv;
   double* hs = (double*)malloc(sizeof(double) * n);
@@ -1543,6 +1602,8 @@ int boltz_ref_step_adjoint(const boltz_ref_ctx* c, const double* h_in, const dou
 int boltz_ref_lid_shear_adjoint(const boltz_ref_ctx* c, const double* h, const boltz_ref_walls* walls,
                                 double weight, double* lam, double* grad) {
   if (!c || !h || !walls || !lam || c->p.bc != BOLTZ_REF_BC_CAVITY) return BOLTZ_REF_EINVAL;
+  /* the adjoint follows uniform spatial cells only */
+  if (c->sstretched) return BOLTZ_REF_EINVAL;
   const int nx = c->p.nx, ny = c->p.ny, nv = c->nv;
   /* D = -(1/nx) sum_ix 2 sum_j w_j v_x v_y hhat_j (see boltz_ref_moments) */
   for (int ix = 0; ix < nx; ++ix) {

@@ -69,6 +69,10 @@ typedef struct boltz_ref_problem {
   double rv;             /* 0 or 1: uniform velocity cells; 0 < rv < 1:     */
                          /* cells stretched in the progression ratio rv,    */
                          /* smallest at the origin (Sec. 5.1; even counts)  */
+  double rx, ry;         /* 0 or 1: uniform spatial cells; 0 < r < 1:       */
+                         /* cells stretched in the progression ratio r,     */
+                         /* smallest at the side walls (x) and at the lid   */
+                         /* (y) (Sec. 5.1); first-order streaming only      */
 } boltz_ref_problem;
 
 typedef struct boltz_ref_walls {
@@ -101,6 +105,8 @@ int boltz_ref_axis(const boltz_ref_ctx* ctx, int axis, double* v, double* omega,
 
 /* Cell edges of one axis (n + 1 values from -a to a): uniform cells, or
  * the stretched cells of Sec. 5.1. */
+/* Widths of the nx (axis 0) or ny (axis 1) spatial cells. */
+int boltz_ref_cell_widths(const boltz_ref_ctx* ctx, int axis, double* widths);
 int boltz_ref_axis_edges(const boltz_ref_ctx* ctx, int axis, double* edges);
 
 /* Inverse CDF of the per-axis node law on a 12-bit field f:
