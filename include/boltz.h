@@ -103,6 +103,16 @@ typedef struct boltz_problem {
                          /* smallest at the origin (Sec. 5.1): on each half */
                          /* axis the i-th cell from the origin is w0 rv^-i  */
                          /* long; needs even nv[k] (else EINVAL)            */
+  double rx, ry;         /* spatial cells: 0 or 1 uniform; 0 < r < 1        */
+                         /* stretched in the progression ratio r (Sec. 5.1):*/
+                         /* along x the cell d cells from the nearer side   */
+                         /* wall is w0 rx^-d long, along y the cell d cells */
+                         /* below the lid w0 ry^-d (lengths adding up to 1);*/
+                         /* streams at order 1 with each cell's own lengths */
+                         /* in its Courant numbers, the time step from the  */
+                         /* smallest cells, the lid shear D weighted by the */
+                         /* face lengths.  Needs order 1; no adjoint and no */
+                         /* batches (EINVAL)                                 */
 } boltz_problem;
 
 /* Wall state for one call (Sec. 2, Eq. bcMax; Sec. 5.1). */

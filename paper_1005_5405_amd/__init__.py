@@ -6,4 +6,4 @@ include/boltz.h); :mod:`.binding` marshals torch device tensors into it.
 """
 from .binding import (BC_CAVITY, BC_PERIODIC, CONTINUOUS_PAIRS, GRAD_NAMES, SEQUENTIAL_UPDATE, WITH_ADJOINT, Batch, Boltz, BoltzError,  # noqa: F401
                       Walls, load_library)
-from .config import CAVITY_16, CAVITY_64, CAVITY_200, CAVITY_PAPER, PRESETS, Preset  # noqa: F401
+from .config import CAVITY_16, CAVITY_64, CAVITY_200, CAVITY_PAPER, CAVITY_PAPER_LITERAL, PRESETS, Preset  # noqa: F401

@@ -38,7 +38,8 @@ class _Problem(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("dt", ctypes.c_double), ("order", ctypes.c_int32),
                 ("bc", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("sample_group", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("cavity_id", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("mix16", ctypes.c_uint32), ("rv", ctypes.c_double)]
+                ("mix16", ctypes.c_uint32), ("rv", ctypes.c_double), ("rx", ctypes.c_double),
+                ("ry", ctypes.c_double)]
 
 
 class _Walls(ctypes.Structure):
@@ -187,23 +188,23 @@ def _stream(stream):
 
 
 def _problem(nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2, bc=BC_CAVITY, sample_group=1,
-             seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0) -> _Problem:
+             seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0, rx=0.0, ry=0.0) -> _Problem:
     nv = tuple(int(x) for x in (nv if np.ndim(nv) else (nv, nv, nv)))
     vmax = tuple(float(x) for x in (vmax if np.ndim(vmax) else (vmax, vmax, vmax)))
     return _Problem(int(nx), int(ny), (ctypes.c_int32 * 3)(*nv), (ctypes.c_double * 3)(*vmax), float(delta),
                     float(eps), float(cfl), float(dt), int(order), int(bc), int(n_pairs), int(sample_group),
-                    int(seed), int(cavity_id), int(flags), int(mix16), float(rv))
+                    int(seed), int(cavity_id), int(flags), int(mix16), float(rv), float(rx), float(ry))
 
 
 class Boltz:
     """One problem on the current HIP device (a boltz_ctx)."""
 
     def __init__(self, nx, ny, nv, vmax, delta, eps, n_pairs, cfl=0.5, dt=0.0, order=2, bc=BC_CAVITY,
-                 sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0, _borrowed=None):
+                 sample_group=1, seed=1, cavity_id=0, flags=0, mix16=4, rv=0.0, rx=0.0, ry=0.0, _borrowed=None):
         L = load_library()
         if _borrowed is None:
             p = _problem(nx, ny, nv, vmax, delta, eps, n_pairs, cfl, dt, order, bc, sample_group, seed, cavity_id,
-                         flags, mix16, rv)
+                         flags, mix16, rv, rx, ry)
             ctx = ctypes.c_void_p()
             rc = L.boltz_create(ctypes.byref(p), ctypes.byref(ctx))
             if rc != OK:

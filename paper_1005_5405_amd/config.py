@@ -35,6 +35,8 @@ class Preset:
     rv: float = 0.0              # velocity cells stretched in this ratio (0: uniform)
     continuous: bool = False     # pairs from the continuous Maxwellian (Box-Muller), binned to cells
     sequential: bool = False     # collision in place, sample after sample (Alg. 3)
+    rx: float = 0.0              # spatial cells stretched in these ratios (0: uniform; order 1)
+    ry: float = 0.0
 
     @property
     def delta(self) -> float:
@@ -43,7 +45,7 @@ class Preset:
     def problem(self, **over) -> dict:
         kw = dict(nx=self.nx, ny=self.ny, nv=self.nv, vmax=self.vmax, delta=self.delta, eps=self.eps,
                   n_pairs=self.n_pairs, cfl=self.cfl, order=self.order, seed=self.seed,
-                  sample_group=self.sample_group, mix16=self.mix16, rv=self.rv)
+                  sample_group=self.sample_group, mix16=self.mix16, rv=self.rv, rx=self.rx, ry=self.ry)
         flags = (4 if self.continuous else 0) | (8 if self.sequential else 0)
         if flags:
             kw["flags"] = flags  # BOLTZ_CONTINUOUS_PAIRS | BOLTZ_SEQUENTIAL_UPDATE
@@ -77,4 +79,14 @@ CAVITY_PAPER = Preset("cavity 160x160, 20^3 velocities stretched 0.945 on [-3, 3
                       "from the continuous Maxwellian (Box-Muller)",
                       160, 160, 20, 3.0, 1.0, 0.01, 0.01, 6144, 1000, rv=0.945, continuous=True)
 
-PRESETS = {"cavity16": CAVITY_16, "cavity64": CAVITY_64, "cavity200": CAVITY_200, "paper160": CAVITY_PAPER}
+# The same with every paper-literal option (Sec. 3, 4, 5.1): first-order
+# streaming (Eq. streaming2D) on spatial cells stretched 0.996 (x) and 0.998
+# (y), smallest at the side walls and the lid, and the in-place sequential
+# collision of Alg. 3
+CAVITY_PAPER_LITERAL = CAVITY_PAPER.with_(
+    name="cavity 160x160, spatial cells stretched 0.996 / 0.998, first-order streaming, 20^3 velocities stretched "
+         "0.945 on [-3, 3], delta 1, 6144 pairs/cell from the continuous Maxwellian, in-place sequential collision",
+    order=1, rx=0.996, ry=0.998, sequential=True, sample_group=0)
+
+PRESETS = {"cavity16": CAVITY_16, "cavity64": CAVITY_64, "cavity200": CAVITY_200, "paper160": CAVITY_PAPER,
+           "paper160_literal": CAVITY_PAPER_LITERAL}

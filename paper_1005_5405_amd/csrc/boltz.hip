@@ -38,6 +38,9 @@ struct boltz_ctx {
   int nv = 0;
   int64_t ncells = 0;
   int device = 0;
+  // spatial cell widths (Sec. 5.1 stretching, else 1/n) and whether stretched
+  std::vector<double> wx, wy;
+  bool sstretched = false;
   // device memory (one allocation)
   void* dmem = nullptr;
   size_t dbytes = 0;
@@ -303,6 +306,13 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
                 "record order is worked out once per sample group and step");
   if (seq && (p->flags & BOLTZ_WITH_ADJOINT))
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: the adjoint follows the Jacobi collision only");
+  const bool sx_str = p->rx != 0.0 && p->rx != 1.0, sy_str = p->ry != 0.0 && p->ry != 1.0;
+  if ((sx_str && !(p->rx > 0.0 && p->rx < 1.0)) || (sy_str && !(p->ry > 0.0 && p->ry < 1.0)) ||
+      ((sx_str || sy_str) && p->order != 1))
+    return fail(nullptr, BOLTZ_EINVAL,
+                "boltz_create: stretched spatial cells need 0 < rx, ry < 1 and first-order streaming");
+  if ((sx_str || sy_str) && (p->flags & BOLTZ_WITH_ADJOINT))
+    return fail(nullptr, BOLTZ_EINVAL, "boltz_create: the adjoint follows uniform spatial cells only");
   if (seq && (int64_t)p->nx * p->ny > 0x7fffffffLL)
     return fail(nullptr, BOLTZ_EINVAL, "boltz_create: the sequential collision takes at most 2^31 - 1 cells");
   const bool stretched = p->rv != 0.0 && p->rv != 1.0;
@@ -455,14 +465,38 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   }
   c->dx = 1.0 / p->nx;
   c->dy = 1.0 / p->ny;
+  // Sec. 5.1: spatial cell lengths in geometric progression, the cell d
+  // cells from the nearer side wall w0 rx^-d long (x), the cell d cells
+  // below the lid w0 ry^-d (y), adding up to the cavity side 1
+  c->sstretched = sx_str || sy_str;
+  c->wx.assign(p->nx, 1.0);
+  c->wy.assign(p->ny, 1.0);
+  {
+    double sum = 0.0;
+    for (int i = 0; i < p->nx; ++i) {
+      const int d = std::min(i, p->nx - 1 - i);
+      if (sx_str) c->wx[i] = std::pow(p->rx, -d);
+      sum += c->wx[i];
+    }
+    for (double& w : c->wx) w /= sum;
+    sum = 0.0;
+    for (int i = 0; i < p->ny; ++i) {
+      if (sy_str) c->wy[i] = std::pow(p->ry, -(p->ny - 1 - i));
+      sum += c->wy[i];
+    }
+    for (double& w : c->wy) w /= sum;
+  }
+  const double mwx = c->sstretched ? *std::min_element(c->wx.begin(), c->wx.end()) : c->dx;
+  const double mwy = c->sstretched ? *std::min_element(c->wy.begin(), c->wy.end()) : c->dy;
   const double vmx = std::fabs(c->v[0][0]), vmy = std::fabs(c->v[1][0]);
   if (p->dt > 0.0) {
     c->dt = p->dt;
   } else {
-    const double rx = vmx / c->dx, ry = vmy / c->dy;
+    // the largest Courant number over nodes, cells and axes equals cfl
+    const double rx = vmx / mwx, ry = vmy / mwy;
     c->dt = p->cfl / (rx > ry ? rx : ry);
   }
-  const double cx = vmx * c->dt / c->dx, cy = vmy * c->dt / c->dy;
+  const double cx = vmx * c->dt / mwx, cy = vmy * c->dt / mwy;
   const bool stable = (p->order == 1) ? (cx + cy <= 1.0 + 1e-12) : (cx <= 1.0 + 1e-12 && cy <= 1.0 + 1e-12);
   if (!stable && !(p->flags & BOLTZ_ALLOW_UNSTABLE)) {
     delete c;
@@ -578,6 +612,14 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       }
   }
   const size_t o_vom = off; off = align256(off + vom.size() * 8);
+  // stretched spatial cells: x widths, 1 / x widths, 1 / y widths
+  std::vector<double> swid;
+  if (c->sstretched) {
+    for (double w : c->wx) swid.push_back(w);
+    for (double w : c->wx) swid.push_back(1.0 / w);
+    for (double w : c->wy) swid.push_back(1.0 / w);
+  }
+  const size_t o_swid = off; off = align256(off + swid.size() * 8);
   (void)hipGetDevice(&c->device);
   hipError_t e = hipMalloc(&c->dmem, off);
   if (e != hipSuccess) {
@@ -593,7 +635,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
       {o_icdf, icdf.data(), icdf.size()}, {o_m0, m0.data(), m0.size() * 8},
       {o_zmom, zmom.data(), zmom.size() * 8},
       {o_cour, cour.data(), cour.size() * 4}, {o_cour2, cour2.data(), cour2.size() * 4},
-      {o_vom, vom.data(), vom.size() * 8}};
+      {o_vom, vom.data(), vom.size() * 8}, {o_swid, swid.data(), swid.size() * 8}};
   for (const Cp& cp : cps) {
     e = hipMemcpy(base + cp.o, cp.src, cp.n, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -643,6 +685,9 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   P.vtab = reinterpret_cast<const double*>(base + o_v);
   P.stretched = stretched ? 1 : 0;
   P.continuous = (p->flags & BOLTZ_CONTINUOUS_PAIRS) ? 1 : 0;
+  P.wx = c->sstretched ? reinterpret_cast<const double*>(base + o_swid) : nullptr;
+  P.inv_wx = c->sstretched ? P.wx + p->nx : nullptr;
+  P.inv_wy = c->sstretched ? P.wx + 2 * p->nx : nullptr;
   P.edgetab = reinterpret_cast<const double*>(base + o_edge);
   P.omtab = reinterpret_cast<const double*>(base + o_om);
   P.rwtab = reinterpret_cast<const double*>(base + o_rw);
@@ -851,7 +896,15 @@ static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const b
 }
 
 static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_t st) {
-  if (c->n[2] % 4 == 0) {
+  if (c->sstretched) {
+    // stretched spatial cells (order 1): each cell's Courant numbers
+    const int tiles_x = (c->p.nx + kTX - 1) / kTX, tiles_y = (c->p.ny + kTY - 1) / kTY;
+    const int nchunks = (c->nv + kJ - 1) / kJ;
+    const long long total = (long long)tiles_x * tiles_y * nchunks;
+    const int per_xcd = (int)((total + 7) / 8);
+    hipLaunchKernelGGL((stream_kernel<1, true>), dim3((unsigned)(8 * (long long)per_xcd)), dim3(kStreamBlock), 0, st,
+                       c->P, hin, hout, tiles_x, tiles_y, nchunks, per_xcd);
+  } else if (c->n[2] % 4 == 0) {
     // velocity groups of four share (jx, jy): vector kernel
     const int tiles_x = (c->p.nx + kTX4 - 1) / kTX4, tiles_y = (c->p.ny + kTY4 - 1) / kTY4;
     const long long total = stream4_units(c->p.nx, c->p.ny, c->nv);
@@ -1402,6 +1455,8 @@ int boltz_batch_create(const boltz_problem* problems, int count, boltz_batch** o
       return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: too many cells in one problem");
     if (problems[i].flags & BOLTZ_SEQUENTIAL_UPDATE)
       return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batches take the Jacobi collision only");
+    if ((problems[i].rx != 0.0 && problems[i].rx != 1.0) || (problems[i].ry != 0.0 && problems[i].ry != 1.0))
+      return bfail(nullptr, BOLTZ_EINVAL, "boltz_batch_create: batches take uniform spatial cells only");
   }
   boltz_batch* b = new (std::nothrow) boltz_batch;
   if (!b) return bfail(nullptr, BOLTZ_ENOMEM, "boltz_batch_create: out of host memory");

@@ -67,6 +67,11 @@ struct Params {
   int stretched;
   // pairs from the continuous Maxwellian (Box-Muller), binned to cells
   int continuous;
+  // stretched spatial cells (Sec. 5.1; first-order streaming): widths of
+  // the x cells and reciprocal widths along x and y, else null
+  const double* wx;
+  const double* inv_wx;
+  const double* inv_wy;
   const double* edgetab;  // [3][kMaxAxis + 1] cell edges -a .. a per axis
 };
 
@@ -432,10 +437,13 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 // of the chunk decide).  Cells outside the cavity take the re-emitted value
 // of the wall they lie beyond.  Order 2: the x sweep of every tile row
 // (y-halo rows included) goes to a second LDS buffer, then the y sweep.
-template <int ORDER>
+// STRETCH (order 1 only): Courant numbers of each cell from its own
+// lengths, |v| dt / dx_i and |v| dt / dy_j (stretched spatial cells).
+template <int ORDER, bool STRETCH = false>
 __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const float* __restrict__ hin,
                                                               float* __restrict__ hout, int tiles_x,
                                                               int tiles_y, int nchunks, int per_xcd) {
+  static_assert(!STRETCH || ORDER == 1, "stretched spatial cells stream at first order");
   constexpr int H = ORDER;
   constexpr int AX = kTX + 2 * H, AY = kTY + 2 * H;
   constexpr int Q = kJ / 4;  // float4 per cell and chunk
@@ -554,7 +562,12 @@ __global__ __launch_bounds__(kStreamBlock) void stream_kernel(Params P, const fl
       const float h0 = ctr[0];
       const float hxn = (sx == 0) ? h0 : ctr[-sx * kJ];
       const float hyn = (sy == 0) ? h0 : ctr[-sy * AX * kJ];
-      hout[cell_off(P, ix, iy) + j] = h0 + Cx * (hxn - h0) + Cy * (hyn - h0);
+      float cx = Cx, cy = Cy;
+      if (STRETCH) {
+        cx = (float)(fabs(vx) * P.dt * P.inv_wx[ix]);
+        cy = (float)(fabs(vy) * P.dt * P.inv_wy[iy]);
+      }
+      hout[cell_off(P, ix, iy) + j] = h0 + cx * (hxn - h0) + cy * (hyn - h0);
     }
   }
 }
@@ -916,8 +929,14 @@ __global__ __launch_bounds__(kMomentsBlock) void moments_kernel(Params P, WallAr
 __global__ void lid_reduce_kernel(Params P, double* __restrict__ out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double t = 0.0;
-    for (int i = 0; i < P.nx; ++i) t += P.dpart[i];
-    *out = -t / P.nx;
+    if (P.wx) {
+      // stretched cells: the faces weighted by their lengths
+      for (int i = 0; i < P.nx; ++i) t += P.wx[i] * P.dpart[i];
+      *out = -t;
+    } else {
+      for (int i = 0; i < P.nx; ++i) t += P.dpart[i];
+      *out = -t / P.nx;
+    }
   }
 }
 

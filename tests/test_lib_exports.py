@@ -49,6 +49,8 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
            dict(mix16=17), dict(flags=16),
            # the sequential update needs shared samples and has no adjoint
            dict(flags=8, sample_group=1), dict(flags=8 | 2, sample_group=0),
+           # stretched spatial cells: 0 < r < 1, first-order streaming, no adjoint
+           dict(rx=0.9, order=2), dict(ry=1.5, order=1), dict(rx=-0.1, order=1), dict(rx=0.9, order=1, flags=2),
            # the 12-bit Maxwellian law alone cannot draw the outer nodes of 8 cells on [-4, 4]
            dict(mix16=0, vmax=(4.0, 4.0, 4.0)), dict(mix16=0, nv=(20, 20, 20), vmax=(5.0, 5.0, 5.0)),
            # stretched velocity cells need 0 < rv < 1 and even counts
@@ -60,7 +62,8 @@ def test_null_and_invalid_arguments_are_rejected_before_any_device_call():
         p = binding._Problem(kw["nx"], kw["ny"], (ctypes.c_int32 * 3)(*kw["nv"]),
                              (ctypes.c_double * 3)(*kw["vmax"]), kw["delta"], kw["eps"], kw["cfl"], kw["dt"],
                              kw["order"], kw["bc"], kw["n_pairs"], kw["sample_group"], kw["seed"],
-                             kw["cavity_id"], kw["flags"], kw["mix16"], kw["rv"])
+                             kw["cavity_id"], kw["flags"], kw["mix16"], kw["rv"], kw.get("rx", 0.0),
+                             kw.get("ry", 0.0))
         rc = L.boltz_create(ctypes.byref(p), ctypes.byref(ctx))
         assert rc == binding.EINVAL, (over, rc)
         if over.get("mix16") == 0:
@@ -97,6 +100,10 @@ def test_batch_arguments_are_rejected_before_any_device_call():
     s = binding._problem(nx=8, ny=8, nv=8, vmax=3.0, delta=1.0, eps=0.1, n_pairs=10, sample_group=0, flags=8)
     assert L.boltz_batch_create((binding._Problem * 2)(p, s), 2, ctypes.byref(b)) == binding.EINVAL
     assert "Jacobi" in L.boltz_batch_last_error(None).decode()
+    q1 = binding._problem(nx=8, ny=8, nv=8, vmax=3.0, delta=1.0, eps=0.1, n_pairs=10, order=1)
+    t1 = binding._problem(nx=8, ny=8, nv=8, vmax=3.0, delta=1.0, eps=0.1, n_pairs=10, order=1, rx=0.9, ry=0.9)
+    assert L.boltz_batch_create((binding._Problem * 2)(q1, t1), 2, ctypes.byref(b)) == binding.EINVAL
+    assert "uniform spatial" in L.boltz_batch_last_error(None).decode()
     assert L.boltz_batch_step(None, None, None, None, None) == binding.EINVAL
     assert L.boltz_batch_query(None, None) == binding.EINVAL
     assert L.boltz_batch_problem(None, 0) is None
