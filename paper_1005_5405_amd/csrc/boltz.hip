@@ -896,8 +896,9 @@ static int launch_walls(boltz_ctx* c, const float* h, const WallArgs& W, const b
 }
 
 static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_t st) {
-  if (c->sstretched) {
-    // stretched spatial cells (order 1): each cell's Courant numbers
+  if (c->sstretched && c->n[2] % 4 != 0) {
+    // stretched spatial cells (order 1): each cell's Courant numbers (the
+    // vector kernel below takes them too)
     const int tiles_x = (c->p.nx + kTX - 1) / kTX, tiles_y = (c->p.ny + kTY - 1) / kTY;
     const int nchunks = (c->nv + kJ - 1) / kJ;
     const long long total = (long long)tiles_x * tiles_y * nchunks;

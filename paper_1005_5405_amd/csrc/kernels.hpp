@@ -762,19 +762,25 @@ __device__ __forceinline__ void stream4_unit(const Params& P, const float* __res
     }
   } else {
     float* dst = hout + jq;
+    // stretched spatial cells: the Courant numbers of each cell from its
+    // own lengths
+    const bool str = P.inv_wx != nullptr;
+    const float cx = str ? (float)(fabs(vx) * P.dt * P.inv_wx[ix]) : Cx;
+    const double avy = fabs(vy) * P.dt;
 #pragma unroll
     for (int r = 0; r < TY; ++r) {
       const int iy = iy0 + r;
       if (iy >= ny) break;
+      const float cy = str ? (float)(avy * P.inv_wy[iy]) : Cy;
       const float4* ctr = &A4[((r + 1) * AX + c + 1) * Q + q];
       const float4 h0 = ctr[0];
       const float4 hxn = (sx == 0) ? h0 : ctr[-sx * Q];
       const float4 hyn = (sy == 0) ? h0 : ctr[-sy * AX * Q];
       float4 out;
-      out.x = h0.x + Cx * (hxn.x - h0.x) + Cy * (hyn.x - h0.x);
-      out.y = h0.y + Cx * (hxn.y - h0.y) + Cy * (hyn.y - h0.y);
-      out.z = h0.z + Cx * (hxn.z - h0.z) + Cy * (hyn.z - h0.z);
-      out.w = h0.w + Cx * (hxn.w - h0.w) + Cy * (hyn.w - h0.w);
+      out.x = h0.x + cx * (hxn.x - h0.x) + cy * (hyn.x - h0.x);
+      out.y = h0.y + cx * (hxn.y - h0.y) + cy * (hyn.y - h0.y);
+      out.z = h0.z + cx * (hxn.z - h0.z) + cy * (hyn.z - h0.z);
+      out.w = h0.w + cx * (hxn.w - h0.w) + cy * (hyn.w - h0.w);
       nt_store4(dst + cell_off(P, ix, iy), out);
     }
   }
