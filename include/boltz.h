@@ -223,8 +223,8 @@ int boltz_collide(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, 
  * beyond that size.  The call allocates nothing and frees nothing.  Every
  * call on one GPU shares that GPU's array: calls that overlap on one GPU
  * (any context, any stream) race and must be serialised by the caller.
- * With BOLTZ_SEQUENTIAL_UPDATE the array also holds two bytes of level
- * schedule per record (26 B per record in all).
+ * With BOLTZ_SEQUENTIAL_UPDATE the array also holds the step schedule of
+ * the records (12 B per record, 36 B per record in all).
  * With per-cell samples (sample_group == 1) it uses no scratch. */
 int boltz_collide_noalloc(boltz_ctx* ctx, const float* h_s, float* h_out, int64_t step, uint32_t flags,
                           double* defect, void* stream);

@@ -78,7 +78,8 @@ struct boltz_ctx {
   // shared record, node velocities and weights of the three axes (FP64),
   // dynamic LDS
   bool seq = false;
-  uint16_t* tlev = nullptr;
+  unsigned char* sched = nullptr;  // SeqSched of every sample group, or the levels (groups schedule)
+  int seq_sched = 1;               // 1: steps of up to 64 records of one level; 0: groups of 64
   double* vom = nullptr;
   size_t seq_lds = 0;
   int collide_per_cu[2] = {0, 0};  // resident workgroups per CU of the two collide variants
@@ -101,7 +102,7 @@ struct RecordTables {
   float4* tcoef;
   uint2* sidx;
   float4* scoef;
-  uint16_t* lev = nullptr;  // sequential collision: record levels
+  unsigned char* sched = nullptr;  // sequential collision: the step schedule (SeqSched)
 };
 
 namespace {
@@ -600,8 +601,8 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   const size_t nodes = (size_t)c->ncells * (size_t)c->nv;
   const size_t o_adj_hs = off; off = align256(off + (with_adj ? nodes * 4 : 0));
   const size_t o_adj_lam = off; off = align256(off + (with_adj ? nodes * 8 : 0));
-  const size_t nrec = seq ? (size_t)ngroups * (size_t)p->n_pairs : 0;
-  const size_t o_tlev = off; off = align256(off + nrec * 2);
+  const int64_t ngr_seq = (p->n_pairs + kSeqGroup - 1) / kSeqGroup;
+  const size_t o_sched = off; off = align256(off + (seq ? SeqSched::bytes(ngr_seq, ngroups) : 0));
   std::vector<double> vom(2 * (size_t)nsum, 0.0);
   {
     size_t i = 0;
@@ -718,7 +719,7 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
   c->adj_hs = with_adj ? reinterpret_cast<float*>(base + o_adj_hs) : nullptr;
   c->adj_lam = with_adj ? reinterpret_cast<double*>(base + o_adj_lam) : nullptr;
   c->seq = seq;
-  c->tlev = seq ? reinterpret_cast<uint16_t*>(base + o_tlev) : nullptr;
+  c->sched = seq ? base + o_sched : nullptr;
   c->vom = reinterpret_cast<double*>(base + o_vom);
   c->seq_lds = SeqLDS::bytes(c->nv, nsum);
   c->collide_block[0] = cblock[0];
@@ -755,12 +756,19 @@ int boltz_create(const boltz_problem* p, boltz_ctx** out) {
     c->collide_grid[t] = c->ncells < cap ? c->ncells : cap;
   }
   if (ea == hipSuccess && seq) {
-    ea = hipFuncSetAttribute((const void*)seq_collide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)kLdsBytes);
+    // the steps schedule where chains of dependent records are long against
+    // the groups of 64 (few pairs per velocity node), else the groups; the
+    // environment variable BOLTZ_SEQ_SCHEDULE=steps|groups overrides
+    c->seq_sched = (double)p->n_pairs < 1.5 * (double)c->nv ? 1 : 0;
+    if (const char* e = std::getenv("BOLTZ_SEQ_SCHEDULE")) {
+      if (std::strcmp(e, "steps") == 0) c->seq_sched = 1;
+      if (std::strcmp(e, "groups") == 0) c->seq_sched = 0;
+    }
+    const void* fn = c->seq_sched == 1 ? (const void*)seq_collide_kernel<1> : (const void*)seq_collide_kernel<0>;
+    ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
     int per_cu = 0;
     if (ea == hipSuccess)
-      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)seq_collide_kernel, kSeqBlock,
-                                                         c->seq_lds);
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSeqBlock, c->seq_lds);
     if (ea == hipSuccess && per_cu < 1) ea = hipErrorInvalidConfiguration;
     c->collide_per_cu[0] = c->collide_per_cu[1] = per_cu;
   }
@@ -936,7 +944,7 @@ static int launch_stream(boltz_ctx* c, const float* hin, float* hout, hipStream_
 
 static RecordTables own_tables(const boltz_ctx* c) {
   const bool split = c->collide_mode == ACC_SPLIT;
-  return RecordTables{c->tidx, c->tcoef, split ? c->sidx : c->tidx, split ? c->scoef : c->tcoef, c->tlev};
+  return RecordTables{c->tidx, c->tcoef, split ? c->sidx : c->tidx, split ? c->scoef : c->tcoef, c->sched};
 }
 
 extern "C++" template <int B, int M>
@@ -1003,11 +1011,28 @@ static int launch_collide_r(boltz_ctx* c, const float* hs, float* hout, int64_t 
     // Alg. 3: the record levels of every sample group, then one wavefront
     // per cell
     const int64_t ngr = (c->p.n_pairs + kSeqGroup - 1) / kSeqGroup;
-    if (ngr > 0)
-      hipLaunchKernelGGL(seq_level_kernel, dim3((unsigned)ngr, (unsigned)c->ngroups), dim3(64), 0, st, R.tidx,
-                         R.tcoef, (int64_t)c->p.n_pairs, R.lev);
-    hipLaunchKernelGGL(seq_collide_kernel, dim3((unsigned)c->ncells), dim3(kSeqBlock), c->seq_lds, st, c->P, c->vom, hs,
-                       hout, flags, defect, R.tidx, R.tcoef, R.lev);
+    const SeqSched S = SeqSched::carve(R.sched, ngr, c->ngroups);
+    // the groups schedule keeps one level word per record at the start of
+    // the same region
+    uint16_t* lev = reinterpret_cast<uint16_t*>(R.sched);
+    const dim3 grid((unsigned)c->ncells), block(kSeqBlock);
+    if (c->seq_sched == 1) {
+      if (ngr > 0) {
+        hipLaunchKernelGGL(seq_level_kernel, dim3((unsigned)ngr, (unsigned)c->ngroups), dim3(kSeqGroup), 0, st,
+                           R.tidx, R.tcoef, (int64_t)c->p.n_pairs, S);
+        hipLaunchKernelGGL(seq_steps_kernel, dim3((unsigned)c->ngroups), dim3(kSeqGroup), 0, st,
+                           (int64_t)c->p.n_pairs, S);
+      }
+      hipLaunchKernelGGL(seq_collide_kernel<1>, grid, block, c->seq_lds, st, c->P, c->vom, hs, hout, flags, defect,
+                         R.tidx, R.tcoef, S, lev);
+    } else {
+      const int64_t ngr64 = (c->p.n_pairs + kSeqGroup64 - 1) / kSeqGroup64;
+      if (ngr64 > 0)
+        hipLaunchKernelGGL(seq_level64_kernel, dim3((unsigned)ngr64, (unsigned)c->ngroups), dim3(64), 0, st, R.tidx,
+                           R.tcoef, (int64_t)c->p.n_pairs, lev);
+      hipLaunchKernelGGL(seq_collide_kernel<0>, grid, block, c->seq_lds, st, c->P, c->vom, hs, hout, flags, defect,
+                         R.tidx, R.tcoef, S, lev);
+    }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? BOLTZ_OK : hip_fail(c, e, "seq_collide_kernel launch");
   }
@@ -1079,8 +1104,9 @@ int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t 
     const size_t n = (size_t)c->ngroups * (size_t)c->p.n_pairs;
     const bool split = c->collide_mode == ACC_SPLIT;
     const size_t one = align256(n * sizeof(uint2)) + n * sizeof(float4);
-    // the sequential collision also keeps a level per record
-    const size_t need = split ? align256(one) + one : (c->seq ? align256(one) + 2 * n : one);
+    // the sequential collision also keeps its step schedule
+    const size_t nsch = c->seq ? SeqSched::bytes((c->p.n_pairs + kSeqGroup - 1) / kSeqGroup, c->ngroups) : 0;
+    const size_t need = split ? align256(one) + one : (c->seq ? align256(one) + nsch : one);
     if (need > kScratchBytes)
       return fail(c, BOLTZ_EINVAL,
                   "boltz_collide_noalloc: " + std::to_string(need) + " bytes of shared-sample records exceed the " +
@@ -1096,7 +1122,7 @@ int boltz_collide_noalloc(boltz_ctx* c, const float* h_s, float* h_out, int64_t 
       R.sidx = reinterpret_cast<uint2*>(q);
       R.scoef = reinterpret_cast<float4*>(q + align256(n * sizeof(uint2)));
     }
-    if (c->seq) R.lev = reinterpret_cast<uint16_t*>(p + align256(one));
+    if (c->seq) R.sched = p + align256(one);
   }
   return launch_collide_r(c, h_s, h_out, step, flags, defect, static_cast<hipStream_t>(stream), false, R);
 }

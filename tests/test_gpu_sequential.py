@@ -5,7 +5,10 @@ C ABI.
 The GPU keeps each cell's h in FP32 while the samples update it one after
 another (the oracle in FP64); a level schedule of the shared records lets a
 wavefront apply the records that share no node together, in an order that
-gives every node its updates in sample order.  Bars as for the Jacobi
+gives every node its updates in sample order.  Both schedules (steps of one
+level across groups of 1024 records, or levels within groups of 64 kept in
+registers; the library picks one per problem, BOLTZ_SEQ_SCHEDULE forces it)
+are tested.  Bars as for the Jacobi
 collision: max|dh| / max|h_ref| and its Maxwellian-weighted form within
 1e-5.  Results are bit-identical from call to call and between the
 context's and the static scratch's records.
@@ -83,12 +86,18 @@ CASES = [
 ]
 
 
+@pytest.fixture(params=["steps", "groups"])
+def schedule(request, monkeypatch):
+    monkeypatch.setenv("BOLTZ_SEQ_SCHEDULE", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("case", range(len(CASES)))
 @pytest.mark.parametrize("correction", [True, False])
-def test_sequential_collide_parity(lib, oracle_mod, torch_mod, case, correction):
+def test_sequential_collide_parity(lib, oracle_mod, torch_mod, case, correction, schedule):
     kw = dict(CASES[case], bc=1)
     kw["flags"] = kw.get("flags", 0) | SEQ
-    _say("sequential collide", kw, "correction", correction)
+    _say("sequential collide", kw, "correction", correction, "schedule", schedule)
     g, o = lib.Boltz(**kw), oracle_mod.Oracle(**kw)
     assert g.collide_layout == "sequential"
     h = _state(o, 300 + case)
@@ -147,7 +156,7 @@ def test_sequential_differs_from_jacobi(lib, oracle_mod, torch_mod):
     assert wrel_jac > 100 * wrel_seq and wrel_jac > 1e-4, (wrel_jac, wrel_seq)
 
 
-def test_sequential_step_parity(lib, oracle_mod, torch_mod):
+def test_sequential_step_parity(lib, oracle_mod, torch_mod, schedule):
     """boltz_step (walls, streaming, the records drawn in the face launch in
     sample order, levels, collision) against the oracle's step, 3 steps of
     the 16x16 cavity with a moving lid."""
@@ -169,7 +178,7 @@ def test_sequential_step_parity(lib, oracle_mod, torch_mod):
     assert g.read_status() == 0
 
 
-def test_sequential_full_size_sampled_cells(lib, oracle_mod, torch_mod):
+def test_sequential_full_size_sampled_cells(lib, oracle_mod, torch_mod, schedule):
     """The 64x64 cavity (20^3, 20000 shared pairs) at full size in the launch
     the benchmark's sequential variant times (boltz_step): sampled cells of
     the GPU's collision against the oracle's collision of the same cells,
@@ -201,7 +210,7 @@ def test_sequential_full_size_sampled_cells(lib, oracle_mod, torch_mod):
     assert (d * w).max() <= 1e-5 * (np.abs(ref) * w).max()
 
 
-def test_sequential_noalloc_equals_context_records(lib, torch_mod):
+def test_sequential_noalloc_equals_context_records(lib, torch_mod, schedule):
     kw = dict(nx=10, ny=8, nv=(20, 20, 20), vmax=5.0, delta=20.0, eps=0.1, n_pairs=20000, sample_group=0, mix16=4,
               bc=1, flags=SEQ)
     g = lib.Boltz(**kw)
