@@ -206,7 +206,10 @@ int boltz_stream(boltz_ctx* ctx, const float* h_in, float* h_out, const boltz_wa
  * (where two of its nodes coincide, both increments land).  The cell's h is
  * kept in FP32 during the loop (the paper's precision), the correction
  * restores the moments of h_s as above.  Results do not depend on the
- * launch (the order of every node's updates is the sample order).
+ * launch (the order of every node's updates is the sample order).  The
+ * samples that share no node are applied together; which of two schedules
+ * groups them is chosen per problem at boltz_create (the environment
+ * variable BOLTZ_SEQ_SCHEDULE=steps|groups, read there, overrides it).
  * h_s may equal h_out (in place); otherwise they must not overlap.
  * flags: BOLTZ_NO_CORRECTION.  defect: NULL or ncells*5 FP64 device buffer
  * receiving sum_j w_j psi_k (F_out - F_s) of the stored FP32 values. */
