@@ -46,6 +46,11 @@ BYTES_PER_NODE_KERNEL = 8
 # h_a and h_b and four 64-bit integer atomic adds (Eq. monteCarloInt).
 LDS_READS_PER_PAIR, LDS_ATOMICS_PER_PAIR = 2, 4
 N_CU, CLOCK_HZ = 256, 2.4e9
+# Random-address LDS rates on the MI355X, lane-operations per clock and CU,
+# measured by a standalone probe with every CU busy: ds_read_b32 (512 threads
+# per workgroup) and ds_add_u64 (1024 threads per workgroup).  They bound the
+# collision's pair loop: the time its LDS operations take at these rates.
+LDS_READ_RATE, LDS_ADD64_RATE = 9.4, 4.43
 # The paper's stream+collide rate on its own workload (GTX 260), derived from its printed streaming and
 # collision flop rates and its flop counts per node and per cell-step; context only.
 PAPER_NODE_UPDATES_PER_S = 1.0e9
@@ -473,7 +478,23 @@ def _roofline(r, kw, g):
             "pair_cells_per_s_in_kernel": pair_cells / t_c,
             "lds_atomic_lane_ops_per_clk_per_cu": (None if seq else
                                                    LDS_ATOMICS_PER_PAIR * pair_cells / t_c / (N_CU * CLOCK_HZ)),
+            # per-cell streams (G = 1) draw their pairs in the kernel: vector
+            # issue, not the LDS, bounds that pair loop (the ALU roofline)
+            "lds_pair_loop": None if (seq or kw["sample_group"] == 1) else _lds_pair_bound(pair_cells, t_c),
             "note": note}
+
+
+def _lds_pair_bound(pair_cells, t_c):
+    """Time the collision's pair loop needs at the probe's random-address LDS
+    rates (2 gathers + 4 64-bit adds per pair and cell), against the launch
+    group's measured average (which also holds the node phases, the tile
+    traffic and the sampler)."""
+    clk_per_pair = LDS_READS_PER_PAIR / LDS_READ_RATE + LDS_ATOMICS_PER_PAIR / LDS_ADD64_RATE
+    bound = pair_cells * clk_per_pair / (N_CU * CLOCK_HZ)
+    return {"bound_ms": bound * 1e3, "frac": bound / t_c, "clk_per_pair_per_cu": clk_per_pair,
+            "rates_lane_ops_per_clk_per_cu": {"ds_read_b32": LDS_READ_RATE, "ds_add_u64": LDS_ADD64_RATE},
+            "note": "LDS-op time of the pair loop at the rates of a standalone random-address probe, "
+                    "divided by the HIP-event average of the whole collision launch group"}
 
 
 def _stream_kernels(r):
