@@ -1339,11 +1339,18 @@ __device__ __forceinline__ void collide_body_hybrid(const Params& P, const Table
 // ---------------------------------------------------- ACC_PART cells --
 // correction_sums with h^c formed from h^s (LDS tile or global row) and the
 // 64-bit accumulators (rows are whole x-slab members, so a row's h^s comes
-// from one place).
+// from one place).  With whole z quadruples and no overflow row, wavefronts
+// take units of work: 64 inner rows (whole rows from the tile), or 64 outer
+// rows times one pair of z quadruples (from global memory, both loads in
+// flight together, where one thread per outer row would wait for n2/4 loads
+// one after another).  The quadruples of a unit are the same for all its
+// lanes, so their z factors are scalar loads.  The row terms are linear in a
+// row's z sums, so every unit adds its own part.  Returns the number of
+// threads that hold sums (a multiple of 64, or n0 * n1).
 template <int BLOCK>
-__device__ __forceinline__ void correction_sums_part(const TablesLDS& T, const double* zmom, const Part& Q,
-                                                     bool flagged, bool vec, int n0, int n1, int n2,
-                                                     double (&acc)[20]) {
+__device__ __forceinline__ int correction_sums_part(const TablesLDS& T, const double* zmom, const Part& Q,
+                                                    bool flagged, bool vec, int n0, int n1, int n2,
+                                                    double (&acc)[20]) {
   const double* vx = T.v;
   const double* vy = T.v + n0;
   const double* omx = T.om;
@@ -1351,59 +1358,9 @@ __device__ __forceinline__ void correction_sums_part(const TablesLDS& T, const d
   const const_f64* zc = (const const_f64*)zmom;
 #pragma unroll
   for (int i = 0; i < 20; ++i) acc[i] = 0.0;
-  for (int row = threadIdx.x; row < n0 * n1; row += BLOCK) {
-    const int jx = row / n1, jy = row - (row / n1) * n1;
-    const int j0 = row * n2;
-    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
-    auto node = [&](int jz, float hsf, double dh) {
-      const const_f64* z = zc + 8 * jz;
-      const float hcf = (float)((double)hsf + dh);
-      const double hc = (double)hcf, d = hc - (double)hsf;
-      S0 = fma(z[0], hc, S0);
-      S1 = fma(z[1], hc, S1);
-      S2 = fma(z[2], hc, S2);
-      S3 = fma(z[3], hc, S3);
-      S4 = fma(z[4], hc, S4);
-      R0 = fma(z[0], d, R0);
-      R1 = fma(z[1], d, R1);
-      R2 = fma(z[2], d, R2);
-    };
-    const u64x2* q = reinterpret_cast<const u64x2*>(Q.acc + j0);
-    auto row4 = [&](const f32x4* hsr) {
-      for (int c = 0; c < (n2 >> 2); ++c) {
-        ZQuad zq;
-        zq.load(zc, 4 * c);
-        const f32x4 s4 = hsr[c];
-        const u64x2 qa = q[2 * c], qb = q[2 * c + 1];
-        const float hsq[4] = {s4.x, s4.y, s4.z, s4.w};
-        const double dhq[4] = {from_fixed(qa.x), from_fixed(qa.y), from_fixed(qb.x), from_fixed(qb.y)};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const float hcf = (float)((double)hsq[k] + dhq[k]);
-          const double hc = (double)hcf, d = hc - (double)hsq[k];
-          S0 = fma(zq.f[k][0], hc, S0);
-          S1 = fma(zq.f[k][1], hc, S1);
-          S2 = fma(zq.f[k][2], hc, S2);
-          S3 = fma(zq.f[k][3], hc, S3);
-          S4 = fma(zq.f[k][4], hc, S4);
-          R0 = fma(zq.f[k][0], d, R0);
-          R1 = fma(zq.f[k][1], d, R1);
-          R2 = fma(zq.f[k][2], d, R2);
-        }
-      }
-    };
-    const bool in = Q.inner(j0);
-    if (vec && !flagged) {
-      if (in) row4(reinterpret_cast<const f32x4*>(Q.tile + (j0 - Q.lo)));
-      else row4(reinterpret_cast<const f32x4*>(Q.hg + j0));
-    } else {
-      for (int jz = 0; jz < n2; ++jz) {
-        const int j = j0 + jz;
-        double dh = from_fixed(Q.acc[j]);
-        if (flagged) dh += (double)Q.ovf[j];
-        node(jz, in ? Q.tile[j - Q.lo] : Q.hg[j], dh);
-      }
-    }
+  // the terms of row (jx, jy) from its z sums: S of h^c, R of h^c - h^s
+  auto add_row = [&](int jx, int jy, double S0, double S1, double S2, double S3, double S4, double R0, double R1,
+                     double R2) {
     const double W = omx[jx] * omy[jy], a = vx[jx], b = vy[jy], c2 = a * a + b * b;
     const double T0 = W * S0, T1 = W * S1, T2 = W * S2, T3 = W * S3, T4 = W * S4;
     const double E0 = c2 * T0 + T2;
@@ -1428,7 +1385,92 @@ __device__ __forceinline__ void correction_sums_part(const TablesLDS& T, const d
     acc[17] += b * Q0;
     acc[18] += Q1;
     acc[19] += c2 * Q0 + Q2;
+  };
+  if (vec && !flagged) {
+    const int nq = n2 >> 2;
+    // inner rows r_lo .. r_hi - 1 (the tile holds whole x slabs)
+    const int r_lo = Q.lo / n2, r_hi = (Q.lo + (int)Q.n) / n2;
+    const int n_in = r_hi - r_lo, n_out = n0 * n1 - n_in;
+    const int w_in = (n_in + 63) >> 6, b_out = (n_out + 63) >> 6, g_out = (nq + 1) >> 1;
+    const int units = w_in + g_out * b_out;
+    const int lane = (int)threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const f32x4* t4 = reinterpret_cast<const f32x4*>(Q.tile);
+    const f32x4* g4 = reinterpret_cast<const f32x4*>(Q.hg);
+    for (int un = wid; un < units; un += BLOCK / 64) {
+      double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
+      // quadruple c (uniform) of a row: s4 its h^s, q the row's accumulators
+      auto quad = [&](int c, const f32x4 s4, const u64x2* q) {
+        ZQuad zq;
+        zq.load(zc, 4 * c);
+        const u64x2 qa = q[2 * c], qb = q[2 * c + 1];
+        const float hsq[4] = {s4.x, s4.y, s4.z, s4.w};
+        const double dhq[4] = {from_fixed(qa.x), from_fixed(qa.y), from_fixed(qb.x), from_fixed(qb.y)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float hcf = (float)((double)hsq[k] + dhq[k]);
+          const double hc = (double)hcf, d = hc - (double)hsq[k];
+          S0 = fma(zq.f[k][0], hc, S0);
+          S1 = fma(zq.f[k][1], hc, S1);
+          S2 = fma(zq.f[k][2], hc, S2);
+          S3 = fma(zq.f[k][3], hc, S3);
+          S4 = fma(zq.f[k][4], hc, S4);
+          R0 = fma(zq.f[k][0], d, R0);
+          R1 = fma(zq.f[k][1], d, R1);
+          R2 = fma(zq.f[k][2], d, R2);
+        }
+      };
+      if (un < w_in) {
+        const int i = un * 64 + lane;
+        if (i < n_in) {
+          const int row = r_lo + i;
+          const f32x4* hsr = t4 + ((row * n2 - Q.lo) >> 2);
+          const u64x2* q = reinterpret_cast<const u64x2*>(Q.acc + row * n2);
+          for (int c = 0; c < nq; ++c) quad(c, hsr[c], q);
+          add_row(row / n1, row - (row / n1) * n1, S0, S1, S2, S3, S4, R0, R1, R2);
+        }
+      } else {
+        const int v = un - w_in, g = v / b_out, o = (v - g * b_out) * 64 + lane;
+        const int c0 = 2 * g;
+        const bool two = c0 + 1 < nq;
+        if (o < n_out) {
+          const int row = o < r_lo ? o : r_hi + (o - r_lo);
+          const f32x4* hsr = g4 + ((row * n2) >> 2);
+          const u64x2* q = reinterpret_cast<const u64x2*>(Q.acc + row * n2);
+          const f32x4 sa = hsr[c0], sb = hsr[two ? c0 + 1 : c0];
+          quad(c0, sa, q);
+          if (two) quad(c0 + 1, sb, q);
+          add_row(row / n1, row - (row / n1) * n1, S0, S1, S2, S3, S4, R0, R1, R2);
+        }
+      }
+    }
+    return units * 64;
   }
+  for (int row = threadIdx.x; row < n0 * n1; row += BLOCK) {
+    const int jx = row / n1, jy = row - (row / n1) * n1;
+    const int j0 = row * n2;
+    const bool in = Q.inner(j0);
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
+    for (int jz = 0; jz < n2; ++jz) {
+      const int j = j0 + jz;
+      double dh = from_fixed(Q.acc[j]);
+      if (flagged) dh += (double)Q.ovf[j];
+      const float hsf = in ? Q.tile[j - Q.lo] : Q.hg[j];
+      const const_f64* z = zc + 8 * jz;
+      const float hcf = (float)((double)hsf + dh);
+      const double hc = (double)hcf, d = hc - (double)hsf;
+      S0 = fma(z[0], hc, S0);
+      S1 = fma(z[1], hc, S1);
+      S2 = fma(z[2], hc, S2);
+      S3 = fma(z[3], hc, S3);
+      S4 = fma(z[4], hc, S4);
+      R0 = fma(z[0], d, R0);
+      R1 = fma(z[1], d, R1);
+      R2 = fma(z[2], d, R2);
+    }
+    add_row(jx, jy, S0, S1, S2, S3, S4, R0, R1, R2);
+  }
+  return n0 * n1;
 }
 
 // One cell in the ACC_PART layout (inner h^s tile in LDS, Q.hg the cell's
@@ -1450,9 +1492,8 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
   const bool flagged = *Q.flag != 0u;
   if (correct) {
     double acc[20];
-    correction_sums_part<BLOCK>(T, P.zmom, Q, flagged, vec, n0, n1, n2, acc);
-    const int rows = n0 * n1;
-    const double t = block_sum20_w0<BLOCK>(acc, red, rows >= BLOCK ? BLOCK / 64 : (rows + 63) / 64);
+    const int items = correction_sums_part<BLOCK>(T, P.zmom, Q, flagged, vec, n0, n1, n2, acc);
+    const double t = block_sum20_w0<BLOCK>(acc, red, items >= BLOCK ? BLOCK / 64 : (items + 63) / 64);
     const const_f64* m0c = (const const_f64*)P.m0;
     if (tid < 64) {
       double M[15], r[5], x[5];
