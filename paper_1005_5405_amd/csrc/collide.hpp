@@ -1350,7 +1350,7 @@ __device__ __forceinline__ void collide_body_hybrid(const Params& P, const Table
 template <int BLOCK>
 __device__ __forceinline__ int correction_sums_part(const TablesLDS& T, const double* zmom, const Part& Q,
                                                     bool flagged, bool vec, int n0, int n1, int n2,
-                                                    double (&acc)[20]) {
+                                                    double (&acc)[20], bool keep) {
   const double* vx = T.v;
   const double* vy = T.v + n0;
   const double* omx = T.om;
@@ -1395,20 +1395,23 @@ __device__ __forceinline__ int correction_sums_part(const TablesLDS& T, const do
     const int units = w_in + g_out * b_out;
     const int lane = (int)threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    const f32x4* t4 = reinterpret_cast<const f32x4*>(Q.tile);
     const f32x4* g4 = reinterpret_cast<const f32x4*>(Q.hg);
     for (int un = wid; un < units; un += BLOCK / 64) {
       double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, R0 = 0.0, R1 = 0.0, R2 = 0.0;
-      // quadruple c (uniform) of a row: s4 its h^s, q the row's accumulators
-      auto quad = [&](int c, const f32x4 s4, const u64x2* q) {
+      // quadruple c (uniform) of a row: s4 its h^s, q the row's
+      // accumulators; with hc4, h^c goes back to the tile in place of h^s and
+      // the accumulators are cleared (the store pass then reads h^c there)
+      auto quad = [&](int c, const f32x4 s4, u64x2* q, f32x4* hc4) {
         ZQuad zq;
         zq.load(zc, 4 * c);
         const u64x2 qa = q[2 * c], qb = q[2 * c + 1];
         const float hsq[4] = {s4.x, s4.y, s4.z, s4.w};
         const double dhq[4] = {from_fixed(qa.x), from_fixed(qa.y), from_fixed(qb.x), from_fixed(qb.y)};
+        float hcq[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const float hcf = (float)((double)hsq[k] + dhq[k]);
+          hcq[k] = hcf;
           const double hc = (double)hcf, d = hc - (double)hsq[k];
           S0 = fma(zq.f[k][0], hc, S0);
           S1 = fma(zq.f[k][1], hc, S1);
@@ -1419,14 +1422,19 @@ __device__ __forceinline__ int correction_sums_part(const TablesLDS& T, const do
           R1 = fma(zq.f[k][1], d, R1);
           R2 = fma(zq.f[k][2], d, R2);
         }
+        if (hc4) {
+          hc4[c] = f32x4{hcq[0], hcq[1], hcq[2], hcq[3]};
+          q[2 * c] = u64x2{0ull, 0ull};
+          q[2 * c + 1] = u64x2{0ull, 0ull};
+        }
       };
       if (un < w_in) {
         const int i = un * 64 + lane;
         if (i < n_in) {
           const int row = r_lo + i;
-          const f32x4* hsr = t4 + ((row * n2 - Q.lo) >> 2);
-          const u64x2* q = reinterpret_cast<const u64x2*>(Q.acc + row * n2);
-          for (int c = 0; c < nq; ++c) quad(c, hsr[c], q);
+          f32x4* hsr = reinterpret_cast<f32x4*>(Q.tile) + ((row * n2 - Q.lo) >> 2);
+          u64x2* q = reinterpret_cast<u64x2*>(Q.acc + row * n2);
+          for (int c = 0; c < nq; ++c) quad(c, hsr[c], q, keep ? hsr : nullptr);
           add_row(row / n1, row - (row / n1) * n1, S0, S1, S2, S3, S4, R0, R1, R2);
         }
       } else {
@@ -1436,10 +1444,10 @@ __device__ __forceinline__ int correction_sums_part(const TablesLDS& T, const do
         if (o < n_out) {
           const int row = o < r_lo ? o : r_hi + (o - r_lo);
           const f32x4* hsr = g4 + ((row * n2) >> 2);
-          const u64x2* q = reinterpret_cast<const u64x2*>(Q.acc + row * n2);
+          u64x2* q = reinterpret_cast<u64x2*>(Q.acc + row * n2);
           const f32x4 sa = hsr[c0], sb = hsr[two ? c0 + 1 : c0];
-          quad(c0, sa, q);
-          if (two) quad(c0 + 1, sb, q);
+          quad(c0, sa, q, nullptr);
+          if (two) quad(c0 + 1, sb, q, nullptr);
           add_row(row / n1, row - (row / n1) * n1, S0, S1, S2, S3, S4, R0, R1, R2);
         }
       }
@@ -1490,9 +1498,12 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
   __syncthreads();
   next();
   const bool flagged = *Q.flag != 0u;
+  // the row sums leave h^c of the inner slabs in the tile (and their
+  // accumulators cleared) when the vector store below follows them
+  const bool hc_tile = correct && vec4 && !defect && !flagged;
   if (correct) {
     double acc[20];
-    const int items = correction_sums_part<BLOCK>(T, P.zmom, Q, flagged, vec, n0, n1, n2, acc);
+    const int items = correction_sums_part<BLOCK>(T, P.zmom, Q, flagged, vec, n0, n1, n2, acc, hc_tile);
     const double t = block_sum20_w0<BLOCK>(acc, red, items >= BLOCK ? BLOCK / 64 : (items + 63) / 64);
     const const_f64* m0c = (const const_f64*)P.m0;
     if (tid < 64) {
@@ -1528,13 +1539,25 @@ __device__ __forceinline__ void collide_body_part(const Params& P, const TablesL
 #pragma unroll 1
     for (int i = tid; i < (nv >> 2); i += BLOCK, nw4.next()) {
       const int j = 4 * i;
-      const f32x4 hv = Q.inner(j) ? t4[(j - Q.lo) >> 2] : g4[i];
-      u64x2* q = reinterpret_cast<u64x2*>(Q.acc + j);
-      const u64x2 qa = q[0], qb = q[1];
-      q[0] = u64x2{0ull, 0ull};
-      q[1] = u64x2{0ull, 0ull};
-      const float c0 = (float)((double)hv.x + from_fixed(qa.x)), c1 = (float)((double)hv.y + from_fixed(qa.y));
-      const float c2 = (float)((double)hv.z + from_fixed(qb.x)), c3 = (float)((double)hv.w + from_fixed(qb.y));
+      const bool in = Q.inner(j);
+      const f32x4 hv = in ? t4[(j - Q.lo) >> 2] : g4[i];
+      float c0, c1, c2, c3;
+      if (hc_tile && in) {
+        // h^c, formed by the row sums
+        c0 = hv.x;
+        c1 = hv.y;
+        c2 = hv.z;
+        c3 = hv.w;
+      } else {
+        u64x2* q = reinterpret_cast<u64x2*>(Q.acc + j);
+        const u64x2 qa = q[0], qb = q[1];
+        q[0] = u64x2{0ull, 0ull};
+        q[1] = u64x2{0ull, 0ull};
+        c0 = (float)((double)hv.x + from_fixed(qa.x));
+        c1 = (float)((double)hv.y + from_fixed(qa.y));
+        c2 = (float)((double)hv.z + from_fixed(qb.x));
+        c3 = (float)((double)hv.w + from_fixed(qb.y));
+      }
       f32x4 o;
       if (correct) {
         const double xa = T.xt[nw4.jx] + T.xt[n0 + nw4.jy];
