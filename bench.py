@@ -62,16 +62,16 @@ PAPER_NODE_UPDATES_PER_S = 1.0e9
 # summaries under profiles/).
 TRAFFIC = {
     # sample_kernel + collide_kernel<1024, true, ACC_PART>
-    "200x200_24_G0": {"sha256": "200fba0e007ef872bdb13d89876f0ff16e577488b6b91efa6b34add448387db2", "fetch_kib": 143.0 + 1085859.1, "fetch_scale": 1.99993,
-                      "write_kib": 1171.88 + 2164096.6, "write_scale": 1.0},
+    "200x200_24_G0": {"sha256": "57597daa49de834632e57087beab4a53a322094cd1cfaa93aee33ff37e69ee7d", "fetch_kib": 143.0 + 1085867.5, "fetch_scale": 1.99993,
+                      "write_kib": 1171.88 + 2164097.5, "write_scale": 1.0},
     # sample_kernel + collide_kernel<1024, true, ACC_FIXED>
-    "64x64_20_G0": {"sha256": "200fba0e007ef872bdb13d89876f0ff16e577488b6b91efa6b34add448387db2", "fetch_kib": 143.0 + 66042.5, "fetch_scale": 1.99943,
+    "64x64_20_G0": {"sha256": "57597daa49de834632e57087beab4a53a322094cd1cfaa93aee33ff37e69ee7d", "fetch_kib": 143.0 + 66042.5, "fetch_scale": 1.99943,
                     "write_kib": 468.75 + 128000.0, "write_scale": 1.0},
 }
 # VALU instructions (wave64) per dispatch of the per-cell-sample (G = 1)
 # collision kernel of the 64x64 cavity, rocprofv3 --pmc SQ_INSTS_VALU; valid
 # for the recorded kernel-source SHA-256.
-VALU_G1 = {"sha256": "200fba0e007ef872bdb13d89876f0ff16e577488b6b91efa6b34add448387db2", "valu_insts_per_dispatch": 4.98797e8}
+VALU_G1 = {"sha256": "57597daa49de834632e57087beab4a53a322094cd1cfaa93aee33ff37e69ee7d", "valu_insts_per_dispatch": 4.98797e8}
 KERNEL_SOURCES = ("adjoint.hpp", "boltz.hip", "collide.hpp", "device_math.hpp", "kernels.hpp", "sequential.hpp")
 
 

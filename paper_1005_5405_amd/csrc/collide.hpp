@@ -1345,8 +1345,10 @@ __device__ __forceinline__ void collide_body_hybrid(const Params& P, const Table
 // flight together, where one thread per outer row would wait for n2/4 loads
 // one after another).  The quadruples of a unit are the same for all its
 // lanes, so their z factors are scalar loads.  The row terms are linear in a
-// row's z sums, so every unit adds its own part.  Returns the number of
-// threads that hold sums (a multiple of 64, or n0 * n1).
+// row's z sums, so every unit adds its own part.  keep (the vector store
+// pass follows): the inner units write h^c over h^s in the tile and clear
+// their accumulators.  Returns the number of threads that hold sums (a
+// multiple of 64, or n0 * n1).
 template <int BLOCK>
 __device__ __forceinline__ int correction_sums_part(const TablesLDS& T, const double* zmom, const Part& Q,
                                                     bool flagged, bool vec, int n0, int n1, int n2,
